@@ -1,0 +1,177 @@
+/*
+ * trevr2.h -- C ABI of an MI355X (gfx950) implementation of TREVR2, the
+ * tree-based reverse ray tracer of Wadsley, Baumschlager & Shen (2023,
+ * "TREVR2: Illuminating fast N log2 N radiative transfer", MNRAS).
+ *
+ * Problem solved (Sections 1.2, 2): given gas elements with position, mass
+ * m, density rho, per-band opacity kappa_b (per unit mass) and per-band
+ * luminosity L_b, return for every *active* element i and band b the
+ * element-averaged angle-integrated intensity
+ *     J_ib = integral of I_b over solid angle, averaged over the element,
+ * (the quantity <4 pi J> of eq. intint; L/(4 pi r^2) far from a lone source
+ * in vacuum), computed by tracing N_ray = 12 nside^2 HEALPix beams outward
+ * from each bucket of the radiation tree (Sections 2.3-2.6).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors)
+ *     owned by the caller, unless stated otherwise.  Per-band arrays are
+ *     band-major: element (b, i) at [b * n + i].
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued asynchronously on it; arrays must stay alive
+ *     until that work completes.
+ *   - The library never allocates device memory: the caller passes the tree
+ *     workspace and the scratch buffer, sized with trevr_workspace_bytes.
+ *   - Every call returns a trevr_status and never throws.  Parameter and
+ *     size errors are found on the host before any launch (TREVR_E_INVALID,
+ *     TREVR_E_CAPACITY).  Errors found on the device (non-positive mass or
+ *     density, non-finite input, a buffer too small for the data) raise a
+ *     sticky per-tree flag reported by trevr_check or the next call that
+ *     synchronises (TREVR_E_DATA, TREVR_E_CAPACITY).  HIP runtime failures
+ *     map to TREVR_E_HIP with the text in trevr_last_error().
+ */
+#ifndef TREVR2_H
+#define TREVR2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TREVR_OK = 0,
+  TREVR_E_INVALID = 1,  /* bad parameter, size or NULL pointer            */
+  TREVR_E_CAPACITY = 2, /* workspace or scratch too small                  */
+  TREVR_E_HIP = 3,      /* HIP runtime error (see trevr_last_error)         */
+  TREVR_E_STATE = 4,    /* unknown or destroyed tree handle                 */
+  TREVR_E_DATA = 5      /* invalid input data found on the device          */
+} trevr_status;
+
+/* Option flags (trevr_params.flags). */
+enum {
+  TREVR_THICK_CORR = 1u, /* multiply J by (1 - e^-tau)/tau, tau = kappa rho h
+                            (Section 2.1, eq. taucorr)                       */
+  TREVR_NEAR_FIELD = 2u, /* particle-particle transfer inside the p-p sphere
+                            (Section 2.4); off: r_pp = 0                      */
+  TREVR_BACKGROUND = 4u  /* isotropic background intensity entering at the
+                            root-cube boundary (abstract; Section 4)          */
+};
+
+typedef struct trevr_params {
+  int32_t nside;     /* HEALPix N_side, a power of two in [1, 8]; N_ray = 12 nside^2
+                        (Sections 1.3, 2.5; paper default 2, i.e. 48 rays)          */
+  int32_t leaf_size; /* bucket capacity, >= 1 (Section 2.3; paper default 12)       */
+  int32_t n_bands;   /* B in [1, 8]                                                 */
+  uint32_t flags;    /* TREVR_* flags                                               */
+  double theta;      /* opening parameter theta_rad >= 0 (Section 2.5.2; 0.75)      */
+  double rpp_min;    /* lower bound of the p-p radius (>= 0; 0 = paper's rule)      */
+  double box[4];     /* root cube {lo_x, lo_y, lo_z, L}; L <= 0: bounding cube of
+                        the particles                                              */
+} trevr_params;
+
+/* Work counters of the last compute_J on a tree (see trevr_get_counters). */
+typedef struct trevr_counters {
+  int64_t buckets;          /* buckets with >= 1 active element (walked)        */
+  int64_t cells;            /* cells used whole: accepted cells + opened buckets */
+  int64_t absorber_entries; /* (cell, ray) pairs with a chord beyond r_pp        */
+  int64_t source_entries;   /* far sources placed on a ray                       */
+  int64_t segments;         /* sum over active i of sum over rays of
+                               (1 + absorber entries + source entries)           */
+  int64_t near_pairs;       /* sum over active i of its bucket's p-p set size    */
+  int64_t max_near;         /* largest p-p set of a bucket                       */
+  int64_t nodes;            /* tree nodes                                       */
+} trevr_counters;
+
+typedef struct trevr_tree trevr_tree; /* opaque host handle */
+
+/*
+ * Byte sizes of the two caller-owned device buffers for n elements:
+ *   tree_bytes    -- holds the tree (sorted elements, nodes, per-direction
+ *                    transmission tables; Sections 2.3, 2.6); must outlive
+ *                    the tree handle;
+ *   scratch_bytes -- a default size for compute_J scratch (fixed part plus a
+ *                    budget of 64 p-p entries per element).  compute_J
+ *                    reports TREVR_E_CAPACITY when its p-p lists need more;
+ *                    trevr_scratch_needed then gives the exact size.
+ * Returns TREVR_E_INVALID for bad parameters or n <= 0.
+ */
+trevr_status trevr_workspace_bytes(const trevr_params* p, int64_t n, size_t* tree_bytes,
+                                   size_t* scratch_bytes);
+
+/*
+ * Build the radiation tree (Section 2.3) and its moments (Section 2.6,
+ * Fig. sourcecombine): Morton sort, radix-tree topology with buckets of at
+ * most leaf_size elements, luminosity sums and centres, bucket absorption
+ * sum(kappa m)/sum(m/rho) and per-direction transmission averages.
+ *   x, y, z, m, rho : float [n];  kappa, lum : float [n_bands][n] (device).
+ *   tree_ws         : device buffer of >= tree_bytes, caller-owned.
+ * The inputs are copied (sorted) into tree_ws and may be freed once the
+ * stream work completes.  On success *out receives a new handle that borrows
+ * tree_ws.  Synchronises `stream` a few times (one per tree level).
+ */
+trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, const float* y,
+                              const float* z, const float* m, const float* rho,
+                              const float* kappa, const float* lum, void* tree_ws,
+                              size_t tree_ws_bytes, void* stream, trevr_tree** out);
+
+/*
+ * J for the active elements (Sections 2.1-2.6): per active bucket, the p-p
+ * radius and set, one tree walk assigning accepted cells to HEALPix rays as
+ * absorbers and sources, the ray reduction with projection correction, the
+ * p-p near field, the optional background and thick-element correction.
+ *   active : uint8 [n] (nonzero = active), NULL = all active.
+ *   bg     : float [n_bands] background intensity, used with
+ *            TREVR_BACKGROUND; may be NULL otherwise.
+ *   J      : double [n_bands][n], input order; rows of inactive elements are
+ *            not written.
+ *   scratch: device buffer of scratch_bytes bytes.
+ * Synchronises `stream` once (to size the p-p lists).  Returns
+ * TREVR_E_CAPACITY, writing no J, if scratch is too small.
+ */
+trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* bg, double* J,
+                             void* scratch, size_t scratch_bytes, void* stream);
+
+/* Scratch bytes the last compute_J on this tree needed (0 before any). */
+trevr_status trevr_scratch_needed(const trevr_tree* t, size_t* bytes);
+
+/* Counters of the last compute_J (synchronises the tree's stream). */
+trevr_status trevr_get_counters(trevr_tree* t, trevr_counters* host_out);
+
+/* Synchronise the tree's stream and return its sticky device error. */
+trevr_status trevr_check(trevr_tree* t);
+
+/* Free the host handle (the workspace stays the caller's). */
+trevr_status trevr_tree_destroy(trevr_tree* t);
+
+/* Tree shape: node count, number of stored direction classes, depth and the
+ * root cube {lo_x, lo_y, lo_z, L} (host outputs, any may be NULL). */
+trevr_status trevr_tree_info(const trevr_tree* t, int64_t* num_nodes, int32_t* num_classes,
+                             int32_t* depth, double* root_box);
+
+/*
+ * Copy the tree tables to HOST buffers (any may be NULL), nodes in
+ * depth-first preorder, child 0 (lower half) first:
+ *   perm    int64 [n]        sorted slot -> input index
+ *   ints    int64 [nodes][7] first, count, owned prefix length, split bit
+ *                            (-1 for buckets), child 0, child 1, next (preorder
+ *                            index after the subtree)
+ *   box     double [nodes][6] lo xyz, hi xyz
+ *   cen     double [nodes][3] luminosity centre (box centre when dark)
+ *   Lb      double [nodes][B] luminosity per band;  Lbol double [nodes]
+ *   alpha   float [nodes][classes][B] transmission-averaged absorption
+ *   ray_class int32 [N_ray]  direction class of each HEALPix ray
+ * Synchronises the tree's stream.
+ */
+trevr_status trevr_tree_export(trevr_tree* t, int64_t* perm, int64_t* ints, double* box,
+                               double* cen, double* Lb, double* Lbol, float* alpha,
+                               int32_t* ray_class);
+
+const char* trevr_status_string(trevr_status s);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* trevr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TREVR2_H */

@@ -175,8 +175,11 @@ class OracleTree:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
-            lib().ora_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.ora_free(h)
+            except Exception:
+                pass
             self.h = None
 
     @property

@@ -1,0 +1,240 @@
+"""Python binding of the C ABI in include/trevr2.h (argument marshalling only).
+
+Every step of the computation runs in the HIP library ``libtrevr2.so``; this
+module only passes device pointers of torch tensors and the current HIP
+stream.  There is no fallback: if the library is missing or no GPU is
+present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libtrevr2.so")
+
+# status codes and flags (include/trevr2.h)
+OK, E_INVALID, E_CAPACITY, E_HIP, E_STATE, E_DATA = range(6)
+THICK_CORR, NEAR_FIELD, BACKGROUND = 1, 2, 4
+
+EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
+            "trevr_scratch_needed", "trevr_get_counters", "trevr_check", "trevr_tree_destroy",
+            "trevr_tree_info", "trevr_tree_export", "trevr_status_string", "trevr_last_error")
+
+
+class TrevrError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("n_bands", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("theta", ctypes.c_double), ("rpp_min", ctypes.c_double),
+                ("box", ctypes.c_double * 4)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("buckets", "cells", "absorber_entries", "source_entries", "segments",
+                 "near_pairs", "max_near", "nodes")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtrevr2.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is missing: build it with "
+                               "`python paper_2310_15235_amd/build.py`")
+        L = ctypes.CDLL(SO_PATH)
+        vp, sz, i64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int32
+        L.trevr_workspace_bytes.argtypes = [ctypes.POINTER(Params), i64, ctypes.POINTER(sz),
+                                            ctypes.POINTER(sz)]
+        L.trevr_build_tree.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 8 + [sz, vp,
+                                                                                   ctypes.POINTER(vp)]
+        L.trevr_compute_J.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        L.trevr_scratch_needed.argtypes = [vp, ctypes.POINTER(sz)]
+        L.trevr_get_counters.argtypes = [vp, ctypes.POINTER(Counters)]
+        L.trevr_check.argtypes = [vp]
+        L.trevr_tree_destroy.argtypes = [vp]
+        L.trevr_tree_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32), vp]
+        L.trevr_tree_export.argtypes = [vp] * 9
+        L.trevr_status_string.restype = ctypes.c_char_p
+        L.trevr_status_string.argtypes = [ctypes.c_int]
+        L.trevr_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("trevr_status_string", "trevr_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise TrevrError(status, where, lib().trevr_last_error().decode())
+
+
+def make_params(nside=2, leaf_size=8, n_bands=1, flags=THICK_CORR | NEAR_FIELD, theta=0.75,
+                rpp_min=0.0, box=None) -> Params:
+    p = Params()
+    p.nside, p.leaf_size, p.n_bands, p.flags = int(nside), int(leaf_size), int(n_bands), int(flags)
+    p.theta, p.rpp_min = float(theta), float(rpp_min)
+    b = (0.0, 0.0, 0.0, 0.0) if box is None else box
+    for a in range(4):
+        p.box[a] = float(b[a])
+    return p
+
+
+def workspace_bytes(params: Params, n: int):
+    tb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().trevr_workspace_bytes(ctypes.byref(params), int(n), ctypes.byref(tb),
+                                       ctypes.byref(sb)), "trevr_workspace_bytes")
+    return tb.value, sb.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Tree:
+    """A radiation tree built on the GPU; owns its workspace tensor."""
+
+    def __init__(self, x, y, z, m, rho, kappa, lum, *, nside=2, leaf_size=8, theta=0.75,
+                 flags=THICK_CORR | NEAR_FIELD, rpp_min=0.0, box=None):
+        torch = _torch()
+        n = int(x.shape[0])
+        B = int(kappa.shape[0])
+        self.n, self.B, self.nside = n, B, int(nside)
+        self.params = make_params(nside, leaf_size, B, flags, theta, rpp_min, box)
+        tb, sb = workspace_bytes(self.params, n)
+        self.device = x.device
+        self.ws = torch.empty(tb, dtype=torch.uint8, device=x.device)
+        self._scratch = torch.empty(sb, dtype=torch.uint8, device=x.device)
+        f = torch.float32
+        h = ctypes.c_void_p()
+        _check(lib().trevr_build_tree(ctypes.byref(self.params), n, _dev(x, f), _dev(y, f),
+                                      _dev(z, f), _dev(m, f), _dev(rho, f), _dev(kappa, f),
+                                      _dev(lum, f), ctypes.c_void_p(self.ws.data_ptr()), tb,
+                                      _stream_ptr(), ctypes.byref(h)), "trevr_build_tree")
+        self.handle = h
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda"):
+        torch = _torch()
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
+        flags = (THICK_CORR if scene.thick_corr else 0) | (NEAR_FIELD if scene.near_field else 0) | \
+            (BACKGROUND if scene.background else 0)
+        return cls(t(scene.x), t(scene.y), t(scene.z), t(scene.m), t(scene.rho), t(scene.kappa),
+                   t(scene.lum), nside=scene.nside, leaf_size=scene.leaf_size, theta=scene.theta,
+                   flags=flags, rpp_min=scene.rpp_min, box=scene.box)
+
+    def compute_J(self, active=None, bg=None, out=None):
+        """J [B, n] float64 on the device (rows of inactive elements keep
+        `out`'s values, zeros by default)."""
+        torch = _torch()
+        if out is None:
+            out = torch.zeros((self.B, self.n), dtype=torch.float64, device=self.device)
+        a = None if active is None else _dev(active, torch.uint8)
+        g = None if bg is None else _dev(bg, torch.float32)
+        for _ in range(2):
+            st = lib().trevr_compute_J(self.handle, a, g, _dev(out, torch.float64),
+                                       ctypes.c_void_p(self._scratch.data_ptr()),
+                                       self._scratch.numel(), _stream_ptr())
+            if st != E_CAPACITY:
+                break
+            need = ctypes.c_size_t()
+            _check(lib().trevr_scratch_needed(self.handle, ctypes.byref(need)),
+                   "trevr_scratch_needed")
+            if need.value <= self._scratch.numel():
+                break
+            self._scratch = torch.empty(int(need.value * 1.1) + 4096, dtype=torch.uint8,
+                                        device=self.device)
+        _check(st, "trevr_compute_J")
+        return out
+
+    def check(self):
+        _check(lib().trevr_check(self.handle), "trevr_check")
+
+    def counters(self) -> dict:
+        c = Counters()
+        _check(lib().trevr_get_counters(self.handle, ctypes.byref(c)), "trevr_get_counters")
+        return {k: int(getattr(c, k)) for k, _ in Counters._fields_}
+
+    def info(self):
+        nn, nc, dp = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        box = np.zeros(4)
+        _check(lib().trevr_tree_info(self.handle, ctypes.byref(nn), ctypes.byref(nc),
+                                     ctypes.byref(dp), box.ctypes.data_as(ctypes.c_void_p)),
+               "trevr_tree_info")
+        return dict(num_nodes=nn.value, num_classes=nc.value, depth=dp.value, root_box=box)
+
+    def export(self) -> dict:
+        inf = self.info()
+        nn, C, B = inf["num_nodes"], inf["num_classes"], self.B
+        perm = np.zeros(self.n, np.int64)
+        ints = np.zeros((nn, 7), np.int64)
+        box = np.zeros((nn, 6))
+        cen = np.zeros((nn, 3))
+        Lb = np.zeros((nn, B))
+        Lbol = np.zeros(nn)
+        alpha = np.zeros((nn, C, B), np.float32)
+        rc = np.zeros(12 * self.nside ** 2, np.int32)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().trevr_tree_export(self.handle, p(perm), p(ints), p(box), p(cen), p(Lb),
+                                       p(Lbol), p(alpha), p(rc)), "trevr_tree_export")
+        return dict(perm=perm, first=ints[:, 0], count=ints[:, 1], lown=ints[:, 2],
+                    split=ints[:, 3], child0=ints[:, 4], child1=ints[:, 5], next=ints[:, 6],
+                    lo=box[:, :3], hi=box[:, 3:], cen=cen, Lb=Lb, Lbol=Lbol, alpha=alpha,
+                    ray_class=rc, **inf)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().trevr_tree_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def compute_J(scene, active=None, device="cuda"):
+    """Build the tree of a scene and return (J as numpy [B, n], counters)."""
+    torch = _torch()
+    T = Tree.from_scene(scene, device=device)
+    act = scene.active if active is None else active
+    a = None if act is None else torch.as_tensor(np.ascontiguousarray(act, np.uint8), device=device)
+    bg = None
+    if scene.background and scene.bg is not None:
+        bg = torch.as_tensor(np.ascontiguousarray(scene.bg, np.float32), device=device)
+    J = T.compute_J(a, bg)
+    T.check()
+    out = J.cpu().numpy()
+    cnt = T.counters()
+    T.close()
+    return out, cnt

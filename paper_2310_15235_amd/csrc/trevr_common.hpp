@@ -1,0 +1,199 @@
+// Shared definitions of the MI355X TREVR2 library (device and host side).
+// Method: Wadsley, Baumschlager & Shen (2023), "TREVR2" (MNRAS).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "trevr2.h"
+
+namespace trevr {
+
+constexpr int kMaxBands = 8;
+constexpr int kMaxNside = 8;
+constexpr int kMaxRays = 12 * kMaxNside * kMaxNside;
+constexpr int kKeyBits = 21;           // bits per axis of the Morton key
+constexpr int kMaxLevels = 64;         // prefix lengths 0..63
+constexpr double kPi = 3.14159265358979323846;
+
+// Sticky device error bits.
+enum : uint32_t {
+  ERR_DATA = 1u,         // non-positive or non-finite element data
+  ERR_STACK = 2u,        // walk stack overflow
+  ERR_CUT = 4u,          // cut list of a bucket over capacity
+  ERR_SRC = 8u,          // sources of a ray group over capacity
+};
+
+// Node meta word (nk.w): owned prefix length in bits 0..5, flags above.
+enum : uint32_t {
+  META_LEAF = 1u << 8,
+  META_LUM = 1u << 9,     // bolometric luminosity > 0
+  META_ABS = 1u << 10,    // sum of kappa*m > 0
+};
+
+// Cut list entry: id (node or sorted slot) and a meta word: pixel in bits
+// 0..15 (0xFFFF = no source), kind in bits 16..17, absorbing flag bit 18.
+enum : uint32_t {
+  CUT_NOPIX = 0xFFFFu,
+  CUT_CELL = 0u << 16,        // accepted cell (absorber and/or merged source)
+  CUT_LEAF = 1u << 16,        // opened bucket: absorber only
+  CUT_PART = 2u << 16,        // element source resolved from an opened bucket
+  CUT_KIND_MASK = 3u << 16,
+  CUT_ABS = 1u << 18,
+};
+
+// Counter slots (uint64 on the device).
+enum { CNT_BUCKETS = 0, CNT_CELLS, CNT_ABS, CNT_SRC, CNT_SEG, CNT_NEAR_PAIRS, CNT_MAX_NEAR,
+       CNT_NODES, CNT_MAX_CUT, CNT_MAX_GSRC, CNT_N = 16 };
+
+// Device view of a tree (all pointers into the caller's tree workspace).
+struct DevTree {
+  int64_t n;
+  int32_t B, nside, nray, nclass, leaf_size;
+  uint32_t flags;
+  double theta2, rpp_min, wbeam;
+  int64_t num_nodes;
+  const double* hdr;          // root lo[3], L, quantisation scale
+  // sorted elements
+  const float *x, *y, *z, *m, *rho;
+  const double *h, *lbol;
+  const float *kappa, *lum;   // [B][n]
+  const uint32_t* perm;       // slot -> input index
+  // nodes in preorder
+  const uint4* nk;            // k_x, k_y, k_z, meta
+  const uint2* nlink;         // leaf: (first, count); internal: (child1, split)
+  const uint32_t* next;       // preorder index after the subtree
+  const double4* cen;         // luminosity centre, bolometric luminosity
+  const double* Lb;           // [node][B]
+  const float* alpha;         // [node][nclass][B]
+  const double* ray_n;        // [nray][3]
+  const int32_t* ray_class;   // [nray]
+  uint32_t* err;              // sticky error bits
+  unsigned long long* counters;
+};
+
+// ------------------------------------------------------------ geometry
+// Bits of prefix length l on axis a (x gets the first bit).
+__host__ __device__ inline int nbits_axis(int l, int a) { return (l + 2 - a) / 3; }
+
+// Box of a node from its integer prefix coordinates k and prefix length l.
+__device__ inline void node_box(const double* hdr, uint4 nk, double lo[3], double hi[3]) {
+  const int l = (int)(nk.w & 63u);
+  const uint32_t kk[3] = {nk.x, nk.y, nk.z};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double side = ldexp(hdr[3], -nbits_axis(l, a));
+    lo[a] = hdr[a] + (double)kk[a] * side;
+    hi[a] = hdr[a] + (double)(kk[a] + 1u) * side;
+  }
+}
+
+__device__ inline double dist2_box(const double lo[3], const double hi[3], const double c[3]) {
+  double dd[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    dd[a] = (c[a] < lo[a]) ? lo[a] - c[a] : (c[a] > hi[a] ? c[a] - hi[a] : 0.0);
+  return dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+}
+
+__device__ inline double far2_box(const double lo[3], const double hi[3], const double c[3]) {
+  double e[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = lo[a] - c[a], w = hi[a] - c[a];
+    e[a] = fmax(u * u, w * w);
+  }
+  return e[0] + e[1] + e[2];
+}
+
+__device__ inline double dist2_pt3(double ax, double ay, double az, const double c[3]) {
+  const double d0 = ax - c[0], d1 = ay - c[1], d2 = az - c[2];
+  return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
+// Slab intersection of the ray c + t n with a box.
+__device__ inline bool slab(const double lo[3], const double hi[3], const double c[3],
+                            const double n[3], const double inv[3], double& tin, double& tout) {
+  tin = -INFINITY;
+  tout = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] != 0.0) {
+      const double t1 = (lo[a] - c[a]) * inv[a];
+      const double t2 = (hi[a] - c[a]) * inv[a];
+      tin = fmax(tin, fmin(t1, t2));
+      tout = fmin(tout, fmax(t1, t2));
+    } else if (c[a] < lo[a] || c[a] > hi[a]) {
+      return false;
+    }
+  }
+  return tin < tout;
+}
+
+// HEALPix ring-scheme pixel containing direction v (Gorski et al. 2005).
+__device__ inline int healpix_pixel(int N, double x, double y, double zz) {
+  const double r = sqrt(x * x + y * y + zz * zz);
+  const double z = zz / r;
+  const double za = fabs(z);
+  double phi = atan2(y, x);
+  if (phi < 0.0) phi += 2.0 * kPi;
+  const double tt = phi / (0.5 * kPi);
+  const int ncap = 2 * N * (N - 1);
+  if (za <= 2.0 / 3.0) {
+    const double t1 = N * (0.5 + tt);
+    const double t2 = N * z * 0.75;
+    const long jp = (long)floor(t1 - t2);
+    const long jm = (long)floor(t1 + t2);
+    const long ir = N + 1 + jp - jm;
+    const long kshift = 1 - (ir & 1);
+    long ip = (jp + jm - N + kshift + 1) / 2;
+    ip = ((ip % (4 * N)) + 4 * N) % (4 * N);
+    return (int)(ncap + (ir - 1) * 4 * N + ip);
+  }
+  const double tp = tt - floor(tt);
+  const double tmp = N * sqrt(3.0 * (1.0 - za));
+  const long jp = (long)floor(tp * tmp);
+  const long jm = (long)floor((1.0 - tp) * tmp);
+  const long ir = jp + jm + 1;
+  long ip = (long)floor(tt * ir);
+  ip = ((ip % (4 * ir)) + 4 * ir) % (4 * ir);
+  if (z > 0) return (int)(2 * ir * (ir - 1) + ip);
+  return (int)(12 * N * N - 2 * ir * (ir + 1) + ip);
+}
+
+// ------------------------------------------------------------ wave helpers
+__device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
+__device__ inline int lane_id() { return __lane_id(); }
+__device__ inline int mbcnt(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Exclusive scan of `total` uint32 in place by one workgroup of 1024
+// threads; the grand total goes to *sum_out when given.
+static __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* a, int64_t total,
+                                                          uint32_t* sum_out) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (total + 1023) / 1024;
+  const int64_t b0 = t * per, b1 = (b0 + per < total) ? b0 + per : total;
+  uint32_t s = 0;
+  for (int64_t i = b0; i < b1; ++i) s += a[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = (t >= off) ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = t ? part[t - 1] : 0u;
+  for (int64_t i = b0; i < b1; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  if (t == 1023 && sum_out) *sum_out = part[1023];
+}
+
+}  // namespace trevr

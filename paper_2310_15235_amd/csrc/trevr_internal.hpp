@@ -1,0 +1,100 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "trevr_common.hpp"
+
+namespace trevr {
+
+// Bump allocator over a caller-owned buffer (base == nullptr: size only).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T> T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Mutable device pointers of a tree (same memory the DevTree views).
+struct TreeBufs {
+  double* hdr;
+  uint32_t* bbox_u;           // ordered-uint min/max of x, y, z
+  uint64_t *keys, *keys_alt;
+  uint32_t *vals, *vals_alt, *hist;
+  float *x, *y, *z, *m, *rho, *kappa, *lum;
+  double *h, *lbol;
+  uint32_t* perm;
+  uint32_t *b_first, *b_count, *b_c0, *b_c1, *b_size, *b_pre;
+  int32_t *b_lown, *b_split;
+  uint32_t* alloc;
+  uint4* nk;
+  uint2* nlink;
+  uint32_t* next;
+  double4 *cen, *sl;
+  double *Lb, *kmass, *alpha64;
+  float* alpha32;
+  double* ray_n;
+  int32_t* ray_class;
+  double* geom;               // [64][nclass][3]: log w1, log w12, chord / L
+  uint32_t* err;
+  unsigned long long* counters;
+};
+
+struct SortCfg {
+  static constexpr int kThreads = 256;
+  static constexpr int kItems = 16;
+  static constexpr int kTile = kThreads * kItems;
+};
+
+// Direction tables of an N_side: centres, classes (rays sharing |n_x|,
+// |n_y|, |n_z| see the same transmission averages) and the combine
+// geometry per prefix length and class.
+struct DirTables {
+  int nside = 0, nray = 0, nclass = 0;
+  std::vector<double> ray_n;      // [nray][3]
+  std::vector<int32_t> ray_class; // [nray]
+  std::vector<double> geom;       // [64][nclass][3]
+};
+DirTables make_dir_tables(int nside);
+
+size_t layout_tree(const trevr_params& p, int64_t n, int nclass, void* base, TreeBufs* out);
+
+}  // namespace trevr
+
+struct trevr_tree {
+  uint64_t magic;
+  trevr_params p;
+  int64_t n;
+  int32_t B, nray, nclass, depth;
+  int64_t num_nodes, num_leaves;
+  hipStream_t stream;
+  void* ws;
+  size_t ws_bytes;
+  trevr::TreeBufs buf;
+  trevr::DevTree dev;
+  trevr::DirTables dirs;
+  std::vector<std::pair<uint32_t, uint32_t>> levels;  // BFS index ranges per depth
+  size_t scratch_needed;
+  bool counters_valid;
+};
+
+namespace trevr {
+trevr_status set_error(trevr_status s, const std::string& msg);
+trevr_status hip_check(hipError_t e, const char* what);
+trevr_status build_tree_impl(trevr_tree* t, const float* x, const float* y, const float* z,
+                             const float* m, const float* rho, const float* kappa,
+                             const float* lum);
+trevr_status compute_J_impl(trevr_tree* t, const uint8_t* active, const float* bg, double* J,
+                            void* scratch, size_t scratch_bytes);
+size_t scratch_fixed_bytes(int64_t n);
+}  // namespace trevr
