@@ -81,6 +81,9 @@ typedef struct trevr_counters {
   int64_t near_pairs;       /* sum over active i of its bucket's p-p set size    */
   int64_t max_near;         /* largest p-p set of a bucket                       */
   int64_t nodes;            /* tree nodes                                       */
+  int64_t src_pairs;        /* sum over active i of its bucket's far sources     */
+  int64_t near_src_triples; /* sum over active i of (luminous p-p elements) x
+                               (p-p set size): the p-p source paths tested     */
 } trevr_counters;
 
 typedef struct trevr_tree trevr_tree; /* opaque host handle */
@@ -166,6 +169,22 @@ trevr_status trevr_tree_info(const trevr_tree* t, int64_t* num_nodes, int32_t* n
 trevr_status trevr_tree_export(trevr_tree* t, int64_t* perm, int64_t* ints, double* box,
                                double* cen, double* Lb, double* Lbol, float* alpha,
                                int32_t* ray_class);
+
+/*
+ * Kernel timing (support call, not part of the method): when enabled, each
+ * compute_J records HIP events on its stream around its phases, and
+ * trevr_profile_read adds their elapsed times (synchronising the stream):
+ *   ms[TREVR_PROF_SETUP]  bucket list, p-p radii and p-p lists
+ *   ms[TREVR_PROF_WALK]   tree walks (cut lists)
+ *   ms[TREVR_PROF_REDUCE] far-field ray reduction and final J
+ *   ms[TREVR_PROF_NEAR]   particle-particle transfer
+ * with launches[] the number of timed launches of each.  Totals accumulate
+ * from the last enable; `on` = 0 stops recording.
+ */
+enum { TREVR_PROF_SETUP = 0, TREVR_PROF_WALK = 1, TREVR_PROF_REDUCE = 2, TREVR_PROF_NEAR = 3,
+       TREVR_PROF_SLOTS = 4 };
+trevr_status trevr_profile_enable(trevr_tree* t, int on);
+trevr_status trevr_profile_read(trevr_tree* t, double* ms, int64_t* launches);
 
 const char* trevr_status_string(trevr_status s);
 /* Text of the last error raised on the calling thread ("" if none). */

@@ -28,7 +28,7 @@ NEAR_FIELD = 2
 BACKGROUND = 4
 
 COUNTER_NAMES = ("buckets", "cells", "absorber_entries", "source_entries", "segments",
-                 "near_pairs", "max_near", "nodes")
+                 "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples")
 
 
 def build() -> str:
@@ -232,7 +232,7 @@ class OracleTree:
         if self.scene.background and self.scene.bg is not None:
             bg = _f64(self.scene.bg)
         J = np.zeros((self.B, self.n)) if J_init is None else np.array(J_init, dtype=np.float64)
-        cnt = np.zeros(8, dtype=np.int64)
+        cnt = np.zeros(len(COUNTER_NAMES), dtype=np.int64)
         info = None
         if bucket_info:
             nn = self.num_nodes
@@ -271,7 +271,7 @@ def jvp(scene, tL=None, tkappa=None, trho=None, active=None, nthreads: int = 0,
     tL_, tk_, tr_ = z(tL, (B, n)), z(tkappa, (B, n)), z(trho, (n,))
     J = np.zeros((B, n))
     dJ = np.zeros((B, n))
-    cnt = np.zeros(8, dtype=np.int64)
+    cnt = np.zeros(len(COUNTER_NAMES), dtype=np.int64)
     lib().ora_jvp(ctypes.byref(p), n, *[_ptr(a) for a in arrs], _ptr(act), _ptr(bg), _ptr(tL_),
                   _ptr(tk_), _ptr(tr_), _ptr(J), _ptr(dJ), _ptr(cnt), int(nthreads))
     return J, dJ, dict(zip(COUNTER_NAMES, (int(c) for c in cnt)))

@@ -84,7 +84,8 @@ struct Params {
 };
 enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u };
 
-enum { C_BUCKETS = 0, C_CELLS, C_ABS, C_SRC, C_SEG, C_NEAR_PAIRS, C_MAX_NEAR, C_NODES, C_N };
+enum { C_BUCKETS = 0, C_CELLS, C_ABS, C_SRC, C_SEG, C_NEAR_PAIRS, C_MAX_NEAR, C_NODES,
+       C_SRC_PAIRS, C_NS_TRIPLES, C_N };
 
 // ------------------------------------------------- element physics (2.1-2.4)
 // Finite-element intensity kernel, Section 2.2, eq. (intint): the volume
@@ -884,6 +885,10 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
   cnt[C_SRC] += nsrc;
   cnt[C_SEG] += nact * ((int64_t)K + nabs + nsrc);
   cnt[C_NEAR_PAIRS] += nact * (int64_t)nearv.size();
+  cnt[C_SRC_PAIRS] += nact * nsrc;
+  int64_t nlum = 0;
+  for (int64_t j : nearv) nlum += (val(P.Lbol[j]) > 0.0) ? 1 : 0;
+  cnt[C_NS_TRIPLES] += nact * nlum * (int64_t)nearv.size();
   cnt[C_MAX_NEAR] = std::max<int64_t>(cnt[C_MAX_NEAR], (int64_t)nearv.size());
   if (info) {
     info->rpp = val(r);
@@ -1032,8 +1037,9 @@ void ora_nodes(void* h, int64_t* ints, double* box, double* cen, double* Lb, dou
   if (alpha) std::memcpy(alpha, H->mo.alpha.data(), sizeof(double) * nn * D * B);
 }
 // J [B][n] in input order (rows of inactive particles untouched).
-// counters[8]: buckets, cells, absorber entries, source entries, segments,
-// near pairs, largest near set, nodes.  bucket_info (optional) [nb][6]:
+// counters[10]: buckets, cells, absorber entries, source entries, segments,
+// near pairs, largest near set, nodes, receiver-source pairs, p-p source
+// path tests.  bucket_info (optional) [nb][6]:
 // leaf node, r_pp, near count, cells, absorber entries, source entries.
 int64_t ora_compute_J(void* h, const uint8_t* active, const double* bg, double* J,
                       int64_t* counters, double* bucket_info, int nthreads) {

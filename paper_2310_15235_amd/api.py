@@ -22,7 +22,9 @@ THICK_CORR, NEAR_FIELD, BACKGROUND = 1, 2, 4
 
 EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_scratch_needed", "trevr_get_counters", "trevr_check", "trevr_tree_destroy",
-            "trevr_tree_info", "trevr_tree_export", "trevr_status_string", "trevr_last_error")
+            "trevr_tree_info", "trevr_tree_export", "trevr_profile_enable",
+            "trevr_profile_read", "trevr_status_string", "trevr_last_error")
+PROF_SETUP, PROF_WALK, PROF_REDUCE, PROF_NEAR, PROF_SLOTS = 0, 1, 2, 3, 4
 
 
 class TrevrError(RuntimeError):
@@ -41,7 +43,7 @@ class Params(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("buckets", "cells", "absorber_entries", "source_entries", "segments",
-                 "near_pairs", "max_near", "nodes")]
+                 "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples")]
 
 
 _lib = None
@@ -68,6 +70,8 @@ def lib():
         L.trevr_tree_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                       ctypes.POINTER(i32), vp]
         L.trevr_tree_export.argtypes = [vp] * 9
+        L.trevr_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.trevr_profile_read.argtypes = [vp, vp, vp]
         L.trevr_status_string.restype = ctypes.c_char_p
         L.trevr_status_string.argtypes = [ctypes.c_int]
         L.trevr_last_error.restype = ctypes.c_char_p
@@ -183,6 +187,18 @@ class Tree:
         c = Counters()
         _check(lib().trevr_get_counters(self.handle, ctypes.byref(c)), "trevr_get_counters")
         return {k: int(getattr(c, k)) for k, _ in Counters._fields_}
+
+    def profile(self, on: bool = True):
+        _check(lib().trevr_profile_enable(self.handle, int(on)), "trevr_profile_enable")
+
+    def profile_read(self):
+        ms = np.zeros(PROF_SLOTS)
+        calls = np.zeros(PROF_SLOTS, np.int64)
+        _check(lib().trevr_profile_read(self.handle, ms.ctypes.data_as(ctypes.c_void_p),
+                                        calls.ctypes.data_as(ctypes.c_void_p)),
+               "trevr_profile_read")
+        names = ("setup", "walk", "reduce", "near")
+        return {nm: (float(ms[i]), int(calls[i])) for i, nm in enumerate(names)}
 
     def info(self):
         nn, nc, dp = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()

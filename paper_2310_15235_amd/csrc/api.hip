@@ -53,6 +53,33 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
   return TREVR_OK;
 }
 
+hipEvent_t prof_begin(trevr_tree* t) {
+  if (!t->prof_on || t->ev_used + 2 > t->ev_pool.size()) return nullptr;
+  hipEvent_t e = t->ev_pool[t->ev_used++];
+  if (hipEventRecord(e, t->stream) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_end(trevr_tree* t, int slot, hipEvent_t begin) {
+  if (!begin || t->ev_used + 1 > t->ev_pool.size()) return;
+  hipEvent_t e = t->ev_pool[t->ev_used++];
+  if (hipEventRecord(e, t->stream) != hipSuccess) return;
+  t->ev_pending.push_back({slot, {begin, e}});
+}
+
+// Fold recorded event pairs into the totals (the stream is synchronised).
+static void prof_collect(trevr_tree* t) {
+  for (auto& pe : t->ev_pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      t->prof_ms[pe.first] += ms;
+      t->prof_calls[pe.first] += 1;
+    }
+  }
+  t->ev_pending.clear();
+  t->ev_used = 0;
+}
+
 }  // namespace trevr
 
 using namespace trevr;
@@ -72,6 +99,36 @@ const char* trevr_status_string(trevr_status s) {
 }
 
 const char* trevr_last_error(void) { return g_last_error.c_str(); }
+
+trevr_status trevr_profile_enable(trevr_tree* t, int on) {
+  if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
+  hipError_t he = hipStreamSynchronize(t->stream);
+  if (he != hipSuccess) return hip_check(he, "sync");
+  t->ev_pending.clear();
+  t->ev_used = 0;
+  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { t->prof_ms[i] = 0.0; t->prof_calls[i] = 0; }
+  if (on && t->ev_pool.empty()) {
+    t->ev_pool.resize(512);
+    for (auto& e : t->ev_pool) {
+      he = hipEventCreate(&e);
+      if (he != hipSuccess) return hip_check(he, "hipEventCreate");
+    }
+  }
+  t->prof_on = on != 0;
+  return TREVR_OK;
+}
+
+trevr_status trevr_profile_read(trevr_tree* t, double* ms, int64_t* launches) {
+  if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
+  hipError_t he = hipStreamSynchronize(t->stream);
+  if (he != hipSuccess) return hip_check(he, "sync");
+  prof_collect(t);
+  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) {
+    if (ms) ms[i] = t->prof_ms[i];
+    if (launches) launches[i] = t->prof_calls[i];
+  }
+  return TREVR_OK;
+}
 
 trevr_status trevr_workspace_bytes(const trevr_params* p, int64_t n, size_t* tree_bytes,
                                    size_t* scratch_bytes) {
@@ -106,6 +163,10 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->ws_bytes = tree_ws_bytes;
   T->scratch_needed = 0;
   T->counters_valid = false;
+  T->prof_on = false;
+  T->ev_used = 0;
+  T->host_u32 = nullptr;
+  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }
   const size_t need = layout_tree(*p, n, T->nclass, nullptr, nullptr);
   if (tree_ws_bytes < need) {
     delete T;
@@ -134,7 +195,8 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
     std::lock_guard<std::mutex> g(g_reg_mu);
     g_live.insert(T);
   }
-  rc = build_tree_impl(T, x, y, z, m, rho, kappa, lum);
+  rc = hip_check(hipHostMalloc((void**)&T->host_u32, 4 * sizeof(uint32_t)), "hipHostMalloc");
+  if (rc == TREVR_OK) rc = build_tree_impl(T, x, y, z, m, rho, kappa, lum);
   if (rc != TREVR_OK) {
     trevr_tree_destroy(T);
     return rc;
@@ -195,6 +257,8 @@ trevr_status trevr_get_counters(trevr_tree* t, trevr_counters* o) {
   o->near_pairs = (int64_t)c[CNT_NEAR_PAIRS];
   o->max_near = (int64_t)c[CNT_MAX_NEAR];
   o->nodes = t->num_nodes;
+  o->src_pairs = (int64_t)c[CNT_SRC_PAIRS];
+  o->near_src_triples = (int64_t)c[CNT_NS_TRIPLES];
   return TREVR_OK;
 }
 
@@ -205,6 +269,9 @@ trevr_status trevr_tree_destroy(trevr_tree* t) {
     g_live.erase(t);
   }
   t->magic = 0;
+  (void)hipStreamSynchronize(t->stream);
+  for (auto& e : t->ev_pool) (void)hipEventDestroy(e);
+  if (t->host_u32) (void)hipHostFree(t->host_u32);
   delete t;
   return TREVR_OK;
 }

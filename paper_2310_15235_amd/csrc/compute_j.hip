@@ -4,22 +4,28 @@
 // Per active bucket (a leaf of the radiation tree holding >= 1 active
 // element) the work is split over kernels:
 //   k_active_buckets  list buckets with active members;
-//   k_setup           p-p radius by fixed point and the p-p set size;
-//   k_near_fill       the p-p set (sorted slots) in key order;
+//   k_setup           p-p radius by fixed point (wavefront range queries),
+//                     p-p set size and number of luminous p-p elements;
+//   k_near_fill       the p-p set, luminous elements first;
 //   k_walk            one wavefront walks the tree cooperatively (LDS stack,
 //                     ballot compaction) and writes the bucket's cut: accepted
 //                     cells, opened buckets and resolved element sources, each
 //                     source tagged with its HEALPix pixel;
-//   k_reduce          one wavefront reduces the cut ray by ray: rays are taken
-//                     in groups of 64 with one lane per ray, so each lane owns
-//                     its ray's sources and adds the optical depth of every
-//                     absorbing cell its ray crosses without atomics; then the
-//                     lanes sweep the sources against every receiver,
-//                     accumulating J in FP64.
-// Decisions (opening test, p-p membership, pixel of a source, ray-box
-// intersection) are made in FP64 with the same correctly rounded operation
-// sequence as their definition, so they are reproducible; transcendental
-// physics (exp, the intensity kernel) runs in FP32 with FP64 accumulation.
+//   k_nearfield       256 threads per bucket stage the p-p set through LDS:
+//                     per receiver and ray the p-p optical depth (kept for the
+//                     far field), and the attenuated p-p sources (J starts
+//                     with these);
+//   k_far             one wavefront reduces the cut ray by ray: rays in groups
+//                     of 64 with one lane per ray, so a lane owns its ray's
+//                     sources and adds the optical depth of every absorbing
+//                     cell its ray crosses without atomics; then the lanes
+//                     sweep the sources against every receiver (FP64 sums),
+//                     add the background and apply the thick-element factor.
+// Decisions (opening test, p-p membership, the side of a receiver an element
+// lies on, pixel of a source, ray-box intersection) are made in FP64 with the
+// same correctly rounded operation sequence as their definition, so they are
+// reproducible; transcendental physics (exp, the intensity kernel) runs in
+// FP32 with FP64 accumulation.
 
 #include <algorithm>
 #include <cmath>
@@ -28,11 +34,15 @@
 
 namespace trevr {
 
-constexpr int kRMax = 8;        // receivers per pass
-constexpr int kStackCap = 3072; // walk stack entries
-constexpr int kNearSrcCap = 512;
+constexpr int kRMax = 8;         // receivers per pass
+constexpr int kStackCap = 4096;  // traversal stack entries (LDS)
 constexpr uint32_t kCutCap = 2048;
 constexpr uint32_t kBatch = 16384;
+constexpr int kNT = 256;         // threads of the near-field kernel
+constexpr int kNChunk = 256;     // p-p elements staged per pass
+constexpr int kNPair = 2;        // (receiver, p-p source) pairs per thread per pass
+constexpr int kRayPer = 2;       // rays per thread in the p-p column pass
+constexpr double kR = 0.48860251190291992;   // (3/(4 pi))^(1/2)
 
 __device__ inline void atomic_max_u64(unsigned long long* a, unsigned long long v) {
   atomicMax(a, v);
@@ -60,76 +70,162 @@ __device__ inline void leaf_centre(const DevTree& T, uint32_t leaf, double c[3])
   for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
 }
 
-// Elements strictly within sqrt(r2) of c: count, largest size, and
-// optionally their slots in key order.  Boxes are pruned conservatively
-// (an element may sit an ulp outside its box after quantisation).
-__device__ inline uint32_t near_scan(const DevTree& T, const double c[3], double r2,
-                                     double* hmax, uint32_t* out) {
-  uint32_t cnt = 0;
-  double hm = 0.0;
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline uint32_t wave_sum_u(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+  return v;
+}
+// exclusive prefix sum over the wavefront
+__device__ inline uint32_t wave_excl(uint32_t v, int lane) {
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = (uint32_t)__shfl_up((int)incl, o);
+    if (lane >= o) incl += u;
+  }
+  return incl - v;
+}
+
+// Range query by one wavefront: elements strictly within sqrt(r2) of c.
+// Returns the count; *hmax gets their largest size, *nlum the number that
+// emit.  With `out`, writes their sorted slots: luminous ones from out[0],
+// the others from out[lum_total].  Boxes are pruned conservatively (an
+// element can sit an ulp outside its box after quantisation); membership is
+// the exact test.  The traversal stack lives in `stack` (kStackCap words).
+__device__ uint32_t wave_near(const DevTree& T, const double c[3], double r2, uint32_t* stack,
+                              double* hmax, uint32_t* nlum, uint32_t* out, uint32_t lum_total,
+                              bool* overflow) {
+  const int lane = threadIdx.x & 63;
   const double prune = r2 * (1.0 + 1e-9);
-  int64_t node = 0;
-  while (node < T.num_nodes) {
-    const uint4 nk = T.nk[node];
-    double lo[3], hi[3];
-    node_box(T.hdr, nk, lo, hi);
-    if (dist2_box(lo, hi, c) > prune) {
-      node = T.next[node];
-      continue;
-    }
-    if (nk.w & META_LEAF) {
-      const uint2 lk = T.nlink[node];
-      for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
-        if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
-          if (out) out[cnt] = s;
-          ++cnt;
-          hm = fmax(hm, T.h[s]);
+  uint32_t cnt = 0, lum = 0;
+  double hm = 0.0;
+  int sp = 1;
+  if (lane == 0) stack[0] = 0u;
+  __syncthreads();
+  while (sp > 0) {
+    const int take = min(sp, 64);
+    sp -= take;
+    const bool valid = lane < take;
+    const uint32_t node = valid ? stack[sp + lane] : 0u;
+    __syncthreads();
+    bool push = false;
+    uint32_t mine = 0, mylum = 0;
+    uint2 lk = make_uint2(0, 0);
+    bool isleaf = false;
+    if (valid) {
+      const uint4 nk = T.nk[node];
+      double lo[3], hi[3];
+      node_box(T.hdr, nk, lo, hi);
+      if (!(dist2_box(lo, hi, c) > prune)) {
+        isleaf = (nk.w & META_LEAF) != 0u;
+        lk = T.nlink[node];
+        push = !isleaf;
+        if (isleaf) {
+          for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
+            if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
+              ++mine;
+              hm = fmax(hm, T.h[s]);
+              if (T.lbol[s] > 0.0) ++mylum;
+            }
+          }
         }
       }
     }
-    ++node;
+    if (out) {
+      const uint32_t lbase = lum + wave_excl(mylum, lane);
+      const uint32_t dbase = lum_total + (cnt - lum) + wave_excl(mine - mylum, lane);
+      if (isleaf && mine) {
+        uint32_t a = 0, b = 0;
+        for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
+          if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
+            if (T.lbol[s] > 0.0) out[lbase + a++] = s;
+            else out[dbase + b++] = s;
+          }
+        }
+      }
+    }
+    cnt += wave_sum_u(mine);
+    lum += wave_sum_u(mylum);
+    const uint64_t pm = ballot64(push);
+    const int npush = __popcll(pm);
+    if (sp + 2 * npush > kStackCap) {
+      *overflow = true;
+      break;
+    }
+    if (push) {
+      const int ppos = mbcnt(pm);
+      stack[sp + 2 * ppos] = lk.x;          // child 1
+      stack[sp + 2 * ppos + 1] = node + 1u; // child 0
+    }
+    sp += 2 * npush;
+    __syncthreads();
   }
-  if (hmax) *hmax = hm;
+  if (hmax) *hmax = wave_max(hm);
+  if (nlum) *nlum = lum;
   return cnt;
 }
 
 // p-p radius (Section 2.4): past every bucket member by its size, then grown
-// until no element inside is wider than the beam there (w r).
-__global__ void k_setup(DevTree T, const uint32_t* blist, const uint32_t* nbp, double* brad,
-                        uint32_t* ncnt) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+// until no element inside is wider than the beam there (w r).  One
+// wavefront per bucket.
+__global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
+                                              const uint32_t* nbp, double* brad, uint32_t* ncnt,
+                                              uint32_t* nlumc) {
+  const uint32_t b = blockIdx.x;
   if (b >= *nbp) return;
+  __shared__ uint32_t stack[kStackCap];
+  const int lane = threadIdx.x;
   const uint32_t leaf = blist[b];
   double c[3];
   leaf_centre(T, leaf, c);
   double r = 0.0;
-  uint32_t cnt = 0;
+  uint32_t cnt = 0, nlum = 0;
+  bool overflow = false;
   if (T.flags & TREVR_NEAR_FIELD) {
     r = T.rpp_min;
     const uint2 lk = T.nlink[leaf];
-    for (uint32_t s = lk.x; s < lk.x + lk.y; ++s)
-      r = fmax(r, sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s]);
+    double rm = 0.0;
+    for (uint32_t s = lk.x + lane; s < lk.x + lk.y; s += 64)
+      rm = fmax(rm, sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s]);
+    r = fmax(r, wave_max(rm));
     for (;;) {
       double hm = 0.0;
-      cnt = near_scan(T, c, r * r, &hm, nullptr);
+      cnt = wave_near(T, c, r * r, stack, &hm, &nlum, nullptr, 0, &overflow);
       const double rn = fmax(r, hm / T.wbeam);
-      if (!(rn > r)) break;
+      if (!(rn > r) || overflow) break;
       r = rn;
     }
   }
-  brad[b] = r;
-  ncnt[b] = cnt;
+  if (lane == 0) {
+    brad[b] = r;
+    ncnt[b] = cnt;
+    nlumc[b] = nlum;
+    if (overflow) atomicOr(T.err, ERR_STACK);
+  }
 }
 
-__global__ void k_near_fill(DevTree T, const uint32_t* blist, const uint32_t* nbp,
-                            const double* brad, const uint32_t* noff, uint32_t* nidx) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= *nbp) return;
-  if (!(T.flags & TREVR_NEAR_FIELD)) return;
+__global__ void __launch_bounds__(64) k_near_fill(DevTree T, const uint32_t* blist,
+                                                  const uint32_t* nbp, const double* brad,
+                                                  const uint32_t* noff, const uint32_t* nlumc,
+                                                  uint32_t* nidx) {
+  const uint32_t b = blockIdx.x;
+  if (b >= *nbp || !(T.flags & TREVR_NEAR_FIELD)) return;
+  __shared__ uint32_t stack[kStackCap];
   double c[3];
   leaf_centre(T, blist[b], c);
   const double r = brad[b];
-  near_scan(T, c, r * r, nullptr, nidx + noff[b]);
+  bool overflow = false;
+  wave_near(T, c, r * r, stack, nullptr, nullptr, nidx + noff[b], nlumc[b], &overflow);
 }
 
 // Opening criterion (Section 2.5.2): open if the cell reaches into the p-p
@@ -283,7 +379,7 @@ __device__ inline float fshape(float x) {
     const float at = 0.5f * logf((x + 1.0f) / (x - 1.0f));
     return 1.0f - (x - 1.0f) * (x + 1.0f) * at / x;
   }
-  const float y2 = 1.0f / (x * x);
+  const float y2 = __builtin_amdgcn_rcpf(x * x);
   float s = 2.0f / 483.0f;
   s = __builtin_fmaf(s, y2, 2.0f / 399.0f);
   s = __builtin_fmaf(s, y2, 2.0f / 323.0f);
@@ -298,16 +394,6 @@ __device__ inline float fshape(float x) {
   return s * y2;
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ inline uint32_t wave_sum_u(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
-  return v;
-}
 
 struct RecvInfo {
   double x[3];
@@ -318,17 +404,261 @@ struct RecvInfo {
   uint32_t slot;
 };
 
-// ---------------------------------------------------------- the reduction
-// Sources of one ray group held on chip.
-template <int NB> struct SrcCap { static constexpr int value = NB <= 3 ? 1024 : 512; };
+// ------------------------------------------------------------ near field
+// Particle-particle transfer inside the p-p sphere (Section 2.4).  For each
+// receiver i and ray k: the optical depth of the p-p elements ahead of i on
+// the ray and within their size of the ray line, kappa_l Sigma_l(b) with
+// Sigma_l(b) = 3 m_l/(pi h_l^2) (1 - b/h_l) (written to tpp for the far
+// field).  For each luminous p-p element j (i itself included, at r = 0):
+// L_j K(r_ij, h_i) exp(-tau_ij), tau over the elements closer to j than i is
+// and within their size of the segment i-j; J of i starts with their sum.
+template <int NB>
+__global__ void __launch_bounds__(kNT) k_nearfield(DevTree T, const uint32_t* blist,
+                                                  const uint32_t* noff, const uint32_t* nlumc,
+                                                  const uint32_t* nidx, const uint32_t* roff,
+                                                  uint32_t b0, uint32_t nbuck,
+                                                  const uint8_t* active, float* tpp, double* J) {
+  const uint32_t bucket = b0 + blockIdx.x;
+  if (bucket >= nbuck) return;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  __shared__ double lx[kNChunk], ly[kNChunk], lz[kNChunk], lh2[kNChunk];
+  __shared__ float lsig[kNChunk], linvh[kNChunk];
+  __shared__ float lkap[kNChunk][NB];
+  __shared__ uint32_t lslot[kNChunk];
+  __shared__ RecvInfo recv[kRMax];
+  __shared__ double wred[kNT / 64][kRMax][NB];
+  __shared__ uint32_t nrecv_s;
+
+  const uint32_t leafb = blist[bucket];
+  double c[3];
+  leaf_centre(T, leafb, c);
+  const uint32_t n0 = noff[bucket], nnear = noff[bucket + 1] - n0, nl = nlumc[bucket];
+  const uint32_t* near = nidx + n0;
+  const uint2 lk = T.nlink[leafb];
+  const int nray = T.nray;
+  const int64_t n = T.n;
+  uint32_t rbase = roff[bucket];
+  uint32_t member = lk.x;
+  const uint32_t mend = lk.x + lk.y;
+  uint32_t nact = 0;
+
+  // stage p-p elements [c0, c0 + cl) into LDS
+  auto stage = [&](uint32_t c0, uint32_t cl) {
+    __syncthreads();
+    if ((uint32_t)t < cl) {
+      const uint32_t l = near[c0 + t];
+      const double hl = T.h[l];
+      lx[t] = (double)T.x[l];
+      ly[t] = (double)T.y[l];
+      lz[t] = (double)T.z[l];
+      lh2[t] = hl * hl;
+      lsig[t] = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+      linvh[t] = (float)(1.0 / hl);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) lkap[t][b] = T.kappa[(int64_t)b * n + l];
+      lslot[t] = l;
+    }
+    __syncthreads();
+  };
+
+  for (;;) {
+    __syncthreads();
+    if (t == 0) {  // thread 0 owns the member cursor
+      uint32_t k = 0;
+      while (member < mend && k < (uint32_t)kRMax) {
+        const uint32_t s = member++;
+        if (active == nullptr || active[T.perm[s]]) {
+          RecvInfo ri;
+          ri.x[0] = (double)T.x[s];
+          ri.x[1] = (double)T.y[s];
+          ri.x[2] = (double)T.z[s];
+          ri.h = T.h[s];
+          for (int a = 0; a < 3; ++a) ri.rel[a] = (float)(ri.x[a] - c[a]);
+          ri.inv_rh = (float)(1.0 / (kR * ri.h));
+          ri.kfac = (float)(1.0 / (2.0 * ri.h * ri.h));
+          ri.slot = s;
+          recv[k++] = ri;
+        }
+      }
+      nrecv_s = k;
+    }
+    __syncthreads();
+    const int nrecv = (int)nrecv_s;
+    if (nrecv == 0) break;
+
+    // ---- p-p optical depth per (receiver, ray).  A thread takes one
+    // receiver and kRayPer rays, so the offset to each p-p element and its
+    // length are shared by the rays.  Whether the element lies ahead (proj > 0)
+    // is a discontinuous decision and uses the exact FP64 projection; the
+    // impact-parameter test b < h and the column Sigma(b) are continuous
+    // (Sigma -> 0 at b = h) and use b^2 = |d|^2 - proj^2.
+    const int gpr = (nray + kRayPer - 1) / kRayPer;      // ray groups per receiver
+    const uint32_t P1 = (uint32_t)nrecv * (uint32_t)gpr;
+    for (uint32_t pb = 0; pb < P1; pb += kNT) {
+      const uint32_t p = pb + (uint32_t)t;
+      const bool ok = p < P1;
+      const int i = ok ? (int)(p / gpr) : 0;
+      const int kb = ok ? (int)(p % gpr) * kRayPer : 0;
+      const double xi0 = recv[i].x[0], xi1 = recv[i].x[1], xi2 = recv[i].x[2];
+      const uint32_t si = ok ? recv[i].slot : 0xFFFFFFFFu;
+      double nv[kRayPer][3];
+      bool kok[kRayPer];
+      float tau[kRayPer][NB];
+#pragma unroll
+      for (int q = 0; q < kRayPer; ++q) {
+        kok[q] = ok && kb + q < nray;
+        const int kq = kok[q] ? kb + q : 0;
+        nv[q][0] = T.ray_n[3 * kq];
+        nv[q][1] = T.ray_n[3 * kq + 1];
+        nv[q][2] = T.ray_n[3 * kq + 2];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) tau[q][b] = 0.0f;
+      }
+      for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
+        const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
+        stage(c0, cl);
+        if (!ok) continue;
+        for (uint32_t u = 0; u < cl; ++u) {
+          if (lslot[u] == si) continue;
+          const double d0 = lx[u] - xi0, d1 = ly[u] - xi1, d2 = lz[u] - xi2;
+          const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+          const double h2 = lh2[u];
+#pragma unroll
+          for (int q = 0; q < kRayPer; ++q) {
+            const double proj = d0 * nv[q][0] + d1 * nv[q][1] + d2 * nv[q][2];
+            if (!(proj > 0.0)) continue;
+            const double b2 = dd - proj * proj;
+            if (!(b2 < h2) || !kok[q]) continue;
+            const float bb = sqrtf((float)fmax(b2, 0.0));
+            const float sig = lsig[u] * (1.0f - bb * linvh[u]);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) tau[q][b] += lkap[u][b] * sig;
+          }
+        }
+      }
+      if (ok) {
+#pragma unroll
+        for (int q = 0; q < kRayPer; ++q) {
+          if (!kok[q]) continue;
+          float* o = tpp + ((int64_t)(rbase + i) * nray + kb + q) * NB;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) o[b] = tau[q][b];
+        }
+      }
+    }
+
+    // ---- p-p sources
+    double acc[kRMax][NB];
+#pragma unroll
+    for (int i = 0; i < kRMax; ++i)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[i][b] = 0.0;
+    const uint32_t P2 = (uint32_t)nrecv * nl;
+    for (uint32_t pb = 0; pb < P2; pb += kNT * kNPair) {
+      bool ok[kNPair];
+      int ii[kNPair];
+      uint32_t jj[kNPair], si[kNPair];
+      double xi[kNPair][3], xj[kNPair][3], e[kNPair][3], rij2[kNPair], tau[kNPair][NB];
+#pragma unroll
+      for (int q = 0; q < kNPair; ++q) {
+        const uint32_t p = pb + (uint32_t)t + (uint32_t)(q * kNT);
+        ok[q] = p < P2;
+        ii[q] = ok[q] ? (int)(p / nl) : 0;
+        jj[q] = ok[q] ? near[p % nl] : 0u;
+        si[q] = recv[ii[q]].slot;
+        xj[q][0] = (double)T.x[jj[q]];
+        xj[q][1] = (double)T.y[jj[q]];
+        xj[q][2] = (double)T.z[jj[q]];
+        for (int a = 0; a < 3; ++a) {
+          xi[q][a] = recv[ii[q]].x[a];
+          e[q][a] = xj[q][a] - xi[q][a];
+        }
+        rij2[q] = e[q][0] * e[q][0] + e[q][1] * e[q][1] + e[q][2] * e[q][2];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) tau[q][b] = 0.0;
+      }
+      // Closer to the source than the receiver is (discontinuous: exact
+      // FP64 squared distances); within h of the segment (continuous).
+      double inv2[kNPair];
+#pragma unroll
+      for (int q = 0; q < kNPair; ++q) inv2[q] = (rij2[q] > 0.0) ? 1.0 / rij2[q] : 0.0;
+      for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
+        const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
+        stage(c0, cl);
+        for (uint32_t u = 0; u < cl; ++u) {
+          const double ux = lx[u], uy = ly[u], uz = lz[u], h2 = lh2[u];
+          const uint32_t us = lslot[u];
+#pragma unroll
+          for (int q = 0; q < kNPair; ++q) {
+            if (!ok[q] || us == si[q] || us == jj[q]) continue;
+            const double f0 = ux - xj[q][0], f1 = uy - xj[q][1], f2 = uz - xj[q][2];
+            if (!(f0 * f0 + f1 * f1 + f2 * f2 < rij2[q])) continue;
+            const double w0 = ux - xi[q][0], w1 = uy - xi[q][1], w2 = uz - xi[q][2];
+            double uu = (w0 * e[q][0] + w1 * e[q][1] + w2 * e[q][2]) * inv2[q];
+            uu = fmin(1.0, fmax(0.0, uu));
+            const double g0 = w0 - uu * e[q][0], g1 = w1 - uu * e[q][1], g2 = w2 - uu * e[q][2];
+            const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+            if (!(b2 < h2)) continue;
+            const float bb = sqrtf((float)b2);
+            const float sig = lsig[u] * (1.0f - bb * linvh[u]);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) tau[q][b] += (double)(lkap[u][b] * sig);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kNPair; ++q) {
+        if (!ok[q]) continue;
+        const RecvInfo& ri = recv[ii[q]];
+        const float rij = (float)sqrt(rij2[q]);
+        const float Kv = fshape(rij * ri.inv_rh) * ri.kfac;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double v = (double)T.lum[(int64_t)b * n + jj[q]] * (double)Kv * exp(-tau[q][b]);
+#pragma unroll
+          for (int i2 = 0; i2 < kRMax; ++i2)
+            if (i2 == ii[q]) acc[i2][b] += v;
+        }
+      }
+    }
+    // ---- block reduction; J starts with the p-p sources
+#pragma unroll
+    for (int i = 0; i < kRMax; ++i) {
+      if (i >= nrecv) continue;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const double v = wave_sum(acc[i][b]);
+        if (lane == 0) wred[wv][i][b] = v;
+      }
+    }
+    __syncthreads();
+    if (t < nrecv * NB) {
+      const int i = t / NB, b = t % NB;
+      double v = 0.0;
+      for (int w = 0; w < kNT / 64; ++w) v += wred[w][i][b];
+      J[(int64_t)b * n + T.perm[recv[i].slot]] = v;
+    }
+    rbase += (uint32_t)nrecv;
+    nact += (uint32_t)nrecv;
+  }
+  if (t == 0) {
+    atomicAdd(&T.counters[CNT_NEAR_PAIRS], (unsigned long long)nact * nnear);
+    atomicAdd(&T.counters[CNT_NS_TRIPLES], (unsigned long long)nact * nl * nnear);
+    atomic_max_u64(&T.counters[CNT_MAX_NEAR], (unsigned long long)nnear);
+  }
+}
+
+// ------------------------------------------------------------- far field
+// Sources of one ray group held on chip per window.
+template <int NB> struct SrcCap { static constexpr int value = NB <= 4 ? 512 : 256; };
 
 template <int NB>
-__global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
-                                               const double* brad, const uint32_t* noff,
-                                               const uint32_t* nidx, uint32_t b0,
-                                               uint32_t nbuck, const uint2* cut,
-                                               const uint32_t* bstat, const float* bg,
-                                               double* J, uint8_t const* active) {
+__global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, const double* brad,
+                                            const uint32_t* roff, uint32_t b0, uint32_t nbuck,
+                                            const uint2* cut, const uint32_t* bstat,
+                                            const float* tppg, const float* bg, double* J,
+                                            const uint8_t* active) {
   constexpr int kSrcCap = SrcCap<NB>::value;
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
@@ -344,7 +674,16 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
   __shared__ uint32_t ray_fill[64];
   __shared__ float tpp[kRMax][64][NB];
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nsrc_list[kNearSrcCap];
+  __shared__ uint32_t nrecv_s;
+  __shared__ double a_lo[64][3], a_hi[64][3];
+  __shared__ uint32_t a_node[64], a_pre[64];
+  __shared__ uint64_t a_mask[64];
+  __shared__ float s_sfx[kSrcCap][NB];
+  __shared__ double g_n[64][3], g_inv[64][3];
+  __shared__ float g_nf[64][3];
+  __shared__ double h_t0[64], h_t1[64];
+  __shared__ uint32_t h_node[64], h_cnt[64], h_beg[65];
+  __shared__ uint8_t h_ray[64], h_ord[64];
 
   const uint32_t leafb = blist[bucket];
   const double r = brad[bucket];
@@ -352,22 +691,18 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
   leaf_centre(T, leafb, c);
   const uint32_t ncut = min(bstat[4 * bucket + 0], kCutCap);
   const uint2* mycut = cut + (size_t)blockIdx.x * kCutCap;
-  const uint32_t n0 = noff[bucket], nnear = noff[bucket + 1] - n0;
-  const uint32_t* near = nidx + n0;
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
   const int ngroups = (nray + 63) / 64;
   const int64_t n = T.n;
   const bool use_bg = (T.flags & TREVR_BACKGROUND) && bg != nullptr;
-  constexpr double kR = 0.48860251190291992;   // (3/(4 pi))^(1/2)
 
   uint32_t nabs_total = 0;
   uint32_t nact_total = 0;
+  uint32_t rbase = roff[bucket];
   uint32_t member = lk.x;
   const uint32_t mend = lk.x + lk.y;
-  while (true) {
-    // next chunk of active receivers
-    __shared__ uint32_t nrecv_s;
+  for (;;) {
     if (lane == 0) {
       uint32_t k = 0;
       while (member < mend && k < (uint32_t)kRMax) {
@@ -387,7 +722,6 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
       }
       nrecv_s = k;
     }
-    member = (uint32_t)__shfl((int)member, 0);
     __syncthreads();
     const int nrecv = (int)nrecv_s;
     if (nrecv == 0) break;
@@ -413,35 +747,15 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
           inv[a] = (nv[a] != 0.0) ? 1.0 / nv[a] : 0.0;
         }
         cls = T.ray_class[k];
-      }
-      // ---- p-p optical depth along each ray from each receiver (Section 2.4)
-      if (rlane) {
-        for (int i = 0; i < nrecv; ++i) {
-          const RecvInfo ri = recv[i];
-          double tau[NB];
-#pragma unroll
-          for (int b = 0; b < NB; ++b) tau[b] = 0.0;
-          for (uint32_t q = 0; q < nnear; ++q) {
-            const uint32_t l = near[q];
-            if (l == ri.slot) continue;
-            const double d0 = (double)T.x[l] - ri.x[0];
-            const double d1 = (double)T.y[l] - ri.x[1];
-            const double d2 = (double)T.z[l] - ri.x[2];
-            const double proj = d0 * nv[0] + d1 * nv[1] + d2 * nv[2];
-            if (!(proj > 0.0)) continue;
-            const double cx = d1 * nv[2] - d2 * nv[1];
-            const double cy = d2 * nv[0] - d0 * nv[2];
-            const double cz = d0 * nv[1] - d1 * nv[0];
-            const double bb = sqrt(cx * cx + cy * cy + cz * cz);
-            const double hl = T.h[l];
-            if (!(bb < hl)) continue;
-            const double sig = (3.0 * (double)T.m[l] / (kPi * hl * hl)) * (1.0 - bb / hl);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) tau[b] += (double)T.kappa[(int64_t)b * n + l] * sig;
-          }
-#pragma unroll
-          for (int b = 0; b < NB; ++b) tpp[i][lane][b] = (float)tau[b];
+        for (int a = 0; a < 3; ++a) {
+          g_n[lane][a] = nv[a];
+          g_inv[lane][a] = inv[a];
+          g_nf[lane][a] = (float)nv[a];
         }
+        for (int i = 0; i < nrecv; ++i)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            tpp[i][lane][b] = tppg[((int64_t)(rbase + i) * nray + k) * NB + b];
       }
 
       // Sources of this group are held kSrcCap at a time; a second window
@@ -470,14 +784,14 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
                 p[0] = (double)T.x[ent.x];
                 p[1] = (double)T.y[ent.x];
                 p[2] = (double)T.z[ent.x];
-  #pragma unroll
+#pragma unroll
                 for (int b = 0; b < NB; ++b) Lv[b] = T.lum[(int64_t)b * n + ent.x];
               } else {
                 const double4 cn = T.cen[ent.x];
                 p[0] = cn.x;
                 p[1] = cn.y;
                 p[2] = cn.z;
-  #pragma unroll
+#pragma unroll
                 for (int b = 0; b < NB; ++b) Lv[b] = (float)T.Lb[(int64_t)ent.x * NB + b];
               }
               const double v0 = p[0] - c[0], v1 = p[1] - c[1], v2 = p[2] - c[2];
@@ -490,7 +804,7 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
               s_rel[slot][1] = (float)v1;
               s_rel[slot][2] = (float)v2;
               s_s[slot] = (float)s;
-  #pragma unroll
+#pragma unroll
               for (int b = 0; b < NB; ++b) {
                 s_L[slot][b] = Lv[b];
                 s_tau[slot][b] = 0.0f;
@@ -501,22 +815,17 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
           nsg_all += (uint32_t)__popcll(m);
         }
         const uint32_t nsg = min(nsg_all - skip, (uint32_t)kSrcCap);
-        // ---- bin sources by ray
+        // ---- bin sources by ray, then sort each ray's sources by distance
         ray_fill[lane] = 0u;
         __syncthreads();
         for (uint32_t q = lane; q < nsg; q += 64) atomicAdd(&ray_fill[s_ray[q]], 1u);
         __syncthreads();
         {
-          uint32_t v = ray_fill[lane];
-          uint32_t incl = v;
-  #pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = (uint32_t)__shfl_up((int)incl, o);
-            if (lane >= o) incl += u;
-          }
-          ray_beg[lane] = incl - v;
-          if (lane == 63) ray_beg[64] = incl;
-          ray_fill[lane] = incl - v;
+          const uint32_t v = ray_fill[lane];
+          const uint32_t ex = wave_excl(v, lane);
+          ray_beg[lane] = ex;
+          if (lane == 63) ray_beg[64] = ex + v;
+          ray_fill[lane] = ex;
         }
         __syncthreads();
         for (uint32_t q = lane; q < nsg; q += 64) {
@@ -524,36 +833,181 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
           s_order[pos] = (uint16_t)q;
         }
         __syncthreads();
+        const uint32_t q0 = rlane ? ray_beg[lane] : 0u, q1 = rlane ? ray_beg[lane + 1] : 0u;
+        for (uint32_t a = q0 + 1; a < q1; ++a) {     // insertion sort by s
+          const uint16_t key = s_order[a];
+          const float ks = s_s[key];
+          uint32_t b = a;
+          while (b > q0 && s_s[s_order[b - 1]] > ks) {
+            s_order[b] = s_order[b - 1];
+            --b;
+          }
+          s_order[b] = key;
+        }
+        for (uint32_t q = lane; q < nsg; q += 64)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) s_sfx[q][b] = 0.0f;
+        __syncthreads();
 
-        // ---- cell absorption along each ray (Sections 2.5.1, 2.6)
+        // ---- cell absorption along each ray (Sections 2.5.1, 2.6).
+        // Absorbing cut entries are staged 64 at a time.  A conservative FP32
+        // bounding-sphere test gives each entry its candidate rays; the
+        // (entry, ray) candidates are packed across lanes for the exact FP64
+        // ray-box test; each hit is then applied by the lane owning its ray:
+        // sources on the ray inside the chord get the partial length, the
+        // nearest source beyond it a suffix add (resolved by a prefix sum
+        // over the ray's sources sorted by distance).
         float texl[NB];
-  #pragma unroll
+#pragma unroll
         for (int b = 0; b < NB; ++b) texl[b] = 0.0f;
         uint32_t nabs = 0;
-        const uint32_t q0 = rlane ? ray_beg[lane] : 0u, q1 = rlane ? ray_beg[lane + 1] : 0u;
-        for (uint32_t e = 0; e < ncut; ++e) {
-          const uint2 ent = mycut[e];
-          if (!(ent.y & CUT_ABS)) continue;
-          double lo[3], hi[3];
-          node_box(T.hdr, T.nk[ent.x], lo, hi);
-          double tin, tout;
-          if (rlane && slab(lo, hi, c, nv, inv, tin, tout) && tout > fmax(tin, r)) {
-            const double t0 = fmax(tin, r);
-            ++nabs;
-            const float* al = &T.alpha[((int64_t)ent.x * T.nclass + cls) * NB];
-            float a[NB];
-  #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              a[b] = al[b];
-              texl[b] += a[b] * (float)(tout - t0);
+        for (uint32_t e0 = 0; e0 < ncut; e0 += 64) {
+          const uint32_t e = e0 + lane;
+          bool is = false;
+          uint32_t node = 0;
+          if (e < ncut) {
+            const uint2 ent = mycut[e];
+            is = (ent.y & CUT_ABS) != 0u;
+            node = ent.x;
+          }
+          const uint64_t am = ballot64(is);
+          const int na = __popcll(am);
+          uint64_t mask = 0ull;
+          const int pos = mbcnt(am);
+          if (is) {
+            double lo[3], hi[3];
+            node_box(T.hdr, T.nk[node], lo, hi);
+            float mc[3];
+            float R2 = 0.0f, D2 = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              a_lo[pos][a] = lo[a];
+              a_hi[pos][a] = hi[a];
+              mc[a] = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
+              const float hx = (float)(0.5 * (hi[a] - lo[a]));
+              R2 += hx * hx;
+              D2 += mc[a] * mc[a];
             }
-            for (uint32_t q = q0; q < q1; ++q) {
-              const uint32_t si = s_order[q];
-              const double s = (double)s_s[si];
-              if (!(s > t0)) continue;
-              const float len = (float)(fmin(tout, s) - t0);
-  #pragma unroll
-              for (int b = 0; b < NB; ++b) s_tau[si][b] += a[b] * len;
+            a_node[pos] = node;
+            const float marg = 1e-5f * D2 + 1e-30f;
+            if (D2 - R2 <= marg) {
+              mask = (kn == 64) ? ~0ull : ((1ull << kn) - 1ull);
+            } else {
+              const float thr = D2 - R2 - marg;
+              for (int kq = 0; kq < kn; ++kq) {
+                const float nm = g_nf[kq][0] * mc[0] + g_nf[kq][1] * mc[1] + g_nf[kq][2] * mc[2];
+                if (nm > 0.0f && nm * nm >= thr) mask |= 1ull << kq;
+              }
+            }
+          }
+          const uint32_t cntc = (uint32_t)__popcll(mask);
+          const uint32_t pre = wave_excl(cntc, lane);
+          const uint32_t C = wave_sum_u(cntc);
+          if (is) {
+            a_mask[pos] = mask;
+            a_pre[pos] = pre;
+          }
+          __syncthreads();
+          for (uint32_t g0 = 0; g0 < C; g0 += 64) {
+            const uint32_t gi = g0 + lane;
+            bool hit = false;
+            double t0 = 0.0, t1 = 0.0;
+            uint32_t hnode = 0;
+            int kray = 0;
+            if (gi < C) {
+              int lo_j = 0, hi_j = na - 1;
+              while (lo_j < hi_j) {
+                const int mid = (lo_j + hi_j + 1) >> 1;
+                if (a_pre[mid] <= gi) lo_j = mid; else hi_j = mid - 1;
+              }
+              uint64_t m = a_mask[lo_j];
+              for (uint32_t rr = gi - a_pre[lo_j]; rr > 0; --rr) m &= m - 1ull;
+              kray = __ffsll((long long)m) - 1;
+              const double lo[3] = {a_lo[lo_j][0], a_lo[lo_j][1], a_lo[lo_j][2]};
+              const double hi[3] = {a_hi[lo_j][0], a_hi[lo_j][1], a_hi[lo_j][2]};
+              const double nn[3] = {g_n[kray][0], g_n[kray][1], g_n[kray][2]};
+              const double iv[3] = {g_inv[kray][0], g_inv[kray][1], g_inv[kray][2]};
+              double tin, tout;
+              if (slab(lo, hi, c, nn, iv, tin, tout) && tout > fmax(tin, r)) {
+                hit = true;
+                t0 = fmax(tin, r);
+                t1 = tout;
+                hnode = a_node[lo_j];
+              }
+            }
+            const uint64_t hm = ballot64(hit);
+            h_cnt[lane] = 0u;
+            __syncthreads();
+            if (hit) {
+              const int hp = mbcnt(hm);
+              h_t0[hp] = t0;
+              h_t1[hp] = t1;
+              h_node[hp] = hnode;
+              h_ray[hp] = (uint8_t)kray;
+              atomicAdd(&h_cnt[kray], 1u);
+            }
+            __syncthreads();
+            {
+              const uint32_t v = h_cnt[lane];
+              const uint32_t ex = wave_excl(v, lane);
+              h_beg[lane] = ex;
+              if (lane == 63) h_beg[64] = ex + v;
+              h_cnt[lane] = ex;
+            }
+            __syncthreads();
+            if (hit) {
+              const int hp = mbcnt(hm);
+              h_ord[atomicAdd(&h_cnt[kray], 1u)] = (uint8_t)hp;
+            }
+            __syncthreads();
+            if (rlane) {
+              for (uint32_t hq = h_beg[lane]; hq < h_beg[lane + 1]; ++hq) {
+                const int hi2 = h_ord[hq];
+                const double ht0 = h_t0[hi2], ht1 = h_t1[hi2];
+                const float len = (float)(ht1 - ht0);
+                const float* al = &T.alpha[((int64_t)h_node[hi2] * T.nclass + cls) * NB];
+                float av[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                  av[b] = al[b];
+                  texl[b] += av[b] * len;
+                }
+                ++nabs;
+                // first source beyond t0 (sources sorted by s)
+                uint32_t lo_p = q0, hi_p = q1;
+                while (lo_p < hi_p) {
+                  const uint32_t mid = (lo_p + hi_p) >> 1;
+                  if ((double)s_s[s_order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
+                }
+                uint32_t pq = lo_p;
+                for (; pq < q1; ++pq) {
+                  const uint32_t si = s_order[pq];
+                  const double sq = (double)s_s[si];
+                  if (!(sq < ht1)) break;
+                  const float part = (float)(sq - ht0);
+#pragma unroll
+                  for (int b = 0; b < NB; ++b) s_tau[si][b] += av[b] * part;
+                }
+                if (pq < q1) {
+                  const uint32_t si = s_order[pq];
+#pragma unroll
+                  for (int b = 0; b < NB; ++b) s_sfx[si][b] += av[b] * len;
+                }
+              }
+            }
+            __syncthreads();
+          }
+        }
+        if (rlane) {   // resolve the suffix adds along each ray
+          float run[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) run[b] = 0.0f;
+          for (uint32_t pq = q0; pq < q1; ++pq) {
+            const uint32_t si = s_order[pq];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              run[b] += s_sfx[si][b];
+              s_tau[si][b] += run[b];
             }
           }
         }
@@ -566,16 +1020,16 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
           const float ss = s_s[q];
           const int ray = s_ray[q];
           float tau[NB], Lv[NB];
-  #pragma unroll
+#pragma unroll
           for (int b = 0; b < NB; ++b) { tau[b] = s_tau[q][b]; Lv[b] = s_L[q][b]; }
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < kRMax; ++i) {
             if (i < nrecv) {
               const float dx = sx - recv[i].rel[0], dy = sy - recv[i].rel[1], dz = sz - recv[i].rel[2];
               const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
               const float Kv = fshape(rr * recv[i].inv_rh) * recv[i].kfac;
-              const float ratio = rr / ss;
-  #pragma unroll
+              const float ratio = rr * __builtin_amdgcn_rcpf(ss);
+#pragma unroll
               for (int b = 0; b < NB; ++b) {
                 const float tc = (tau[b] > 0.0f) ? tau[b] * ratio : 0.0f;
                 const float e = __expf(-(tpp[i][ray][b] + tc));
@@ -586,10 +1040,10 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
         }
         // ---- isotropic background along each ray (to the root-cube edge)
         if (use_bg && rlane && skip == 0) {
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < kRMax; ++i)
             if (i < nrecv)
-  #pragma unroll
+#pragma unroll
               for (int b = 0; b < NB; ++b)
                 acc[i][b] += (4.0 * kPi / nray) * (double)bg[b] *
                              (double)__expf(-(tpp[i][lane][b] + texl[b]));
@@ -597,63 +1051,9 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
         __syncthreads();
         if (nsg_all <= skip + (uint32_t)kSrcCap) break;
       }
-      __syncthreads();
     }
 
-    // ---- p-p sources, the receiver itself included (Section 2.4); the
-    // luminous members of the p-p set are taken kNearSrcCap at a time
-    for (uint32_t c0 = 0; c0 < nnear; c0 += (uint32_t)kNearSrcCap) {
-      const uint32_t c1 = min(nnear, c0 + (uint32_t)kNearSrcCap);
-      uint32_t nns = 0;
-      for (uint32_t q0 = c0; q0 < c1; q0 += 64) {
-        const uint32_t q = q0 + lane;
-        const bool is = q < c1 && T.lbol[near[q]] > 0.0;
-        const uint64_t m = ballot64(is);
-        if (is) nsrc_list[nns + (uint32_t)mbcnt(m)] = near[q];
-        nns += (uint32_t)__popcll(m);
-      }
-      __syncthreads();
-      for (uint32_t pq = lane; pq < (uint32_t)nrecv * nns; pq += 64) {
-        const int i = (int)(pq / nns);
-        const uint32_t j = nsrc_list[pq % nns];
-        const RecvInfo ri = recv[i];
-        const double xj0 = (double)T.x[j], xj1 = (double)T.y[j], xj2 = (double)T.z[j];
-        const double e0 = xj0 - ri.x[0], e1 = xj1 - ri.x[1], e2 = xj2 - ri.x[2];
-        const double rij2 = e0 * e0 + e1 * e1 + e2 * e2;
-        double tau[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) tau[b] = 0.0;
-        for (uint32_t q = 0; q < nnear; ++q) {
-          const uint32_t l = near[q];
-          if (l == ri.slot || l == j) continue;
-          const double xl0 = (double)T.x[l], xl1 = (double)T.y[l], xl2 = (double)T.z[l];
-          const double f0 = xl0 - xj0, f1 = xl1 - xj1, f2 = xl2 - xj2;
-          if (!(f0 * f0 + f1 * f1 + f2 * f2 < rij2)) continue;
-          const double w0 = xl0 - ri.x[0], w1 = xl1 - ri.x[1], w2 = xl2 - ri.x[2];
-          double u = (w0 * e0 + w1 * e1 + w2 * e2) / rij2;
-          u = fmin(1.0, fmax(0.0, u));
-          const double g0 = w0 - u * e0, g1 = w1 - u * e1, g2 = w2 - u * e2;
-          const double bb = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
-          const double hl = T.h[l];
-          if (!(bb < hl)) continue;
-          const double sig = (3.0 * (double)T.m[l] / (kPi * hl * hl)) * (1.0 - bb / hl);
-#pragma unroll
-          for (int b = 0; b < NB; ++b) tau[b] += (double)T.kappa[(int64_t)b * n + l] * sig;
-        }
-        const float rij = (float)sqrt(rij2);
-        const float Kv = fshape(rij * ri.inv_rh) * ri.kfac;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const double v = (double)T.lum[(int64_t)b * n + j] * (double)Kv * exp(-tau[b]);
-#pragma unroll
-          for (int ii = 0; ii < kRMax; ++ii)
-            if (ii == i) acc[ii][b] += v;
-        }
-      }
-      __syncthreads();
-    }
-
-    // ---- reduce over lanes, thick-element correction (Section 2.1), store
+    // ---- reduce over lanes, add the p-p part, thick-element correction
 #pragma unroll
     for (int i = 0; i < kRMax; ++i) {
       if (i >= nrecv) continue;
@@ -662,15 +1062,17 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
         const double v = wave_sum(acc[i][b]);
         if (lane == b) {
           const uint32_t s = recv[i].slot;
-          double out = v;
+          const int64_t o = (int64_t)b * n + T.perm[s];
+          double out = J[o] + v;
           if (T.flags & TREVR_THICK_CORR) {
             const double tau = (double)T.kappa[(int64_t)b * n + s] * (double)T.rho[s] * recv[i].h;
             out *= (tau == 0.0) ? 1.0 : -expm1(-tau) / tau;
           }
-          J[(int64_t)b * n + T.perm[s]] = out;
+          J[o] = out;
         }
       }
     }
+    rbase += (uint32_t)nrecv;
     __syncthreads();
   }
 
@@ -682,53 +1084,60 @@ __global__ void __launch_bounds__(64) k_reduce(DevTree T, const uint32_t* blist,
     atomicAdd(&T.counters[CNT_SRC], (unsigned long long)nsrc);
     atomicAdd(&T.counters[CNT_SEG],
               (unsigned long long)nact_total * ((unsigned long long)nray + nabs_total + nsrc));
-    atomicAdd(&T.counters[CNT_NEAR_PAIRS], (unsigned long long)nact_total * nnear);
-    atomic_max_u64(&T.counters[CNT_MAX_NEAR], (unsigned long long)nnear);
+    atomicAdd(&T.counters[CNT_SRC_PAIRS], (unsigned long long)nact_total * nsrc);
   }
 }
 
 // ============================================================ host side
 struct Scratch {
-  uint32_t *blist, *bnact, *ncnt, *bstat, *nb, *near_total;
+  uint32_t *blist, *bnact, *ncnt, *nlumc, *roff, *bstat, *nb;
   double* brad;
   uint2* cut;
   uint32_t* nidx;
+  float* tpp;
   size_t fixed;
 };
 
-static Scratch carve_scratch(void* base, int64_t n, int64_t nleaves) {
+static Scratch carve_scratch(void* base, int64_t nleaves) {
   Carve cv(base);
   Scratch s{};
   const int64_t L = std::max<int64_t>(nleaves, 1);
-  s.nb = cv.take<uint32_t>(4);
-  s.near_total = s.nb + 1;
+  s.nb = cv.take<uint32_t>(4);           // buckets, p-p total, active total
   s.blist = cv.take<uint32_t>(L);
-  s.bnact = cv.take<uint32_t>(L);
+  s.bnact = cv.take<uint32_t>(L + 1);
   s.ncnt = cv.take<uint32_t>(L + 1);
+  s.nlumc = cv.take<uint32_t>(L);
   s.bstat = cv.take<uint32_t>(4 * L);
   s.brad = cv.take<double>(L);
   s.cut = cv.take<uint2>((size_t)std::min<int64_t>(L, kBatch) * kCutCap);
   s.fixed = cv.off + 256;
-  s.nidx = cv.take<uint32_t>(0);
-  (void)n;
   return s;
 }
 
-size_t scratch_fixed_bytes(int64_t n) { return carve_scratch(nullptr, n, n).fixed; }
+size_t scratch_fixed_bytes(int64_t n) { return carve_scratch(nullptr, n).fixed; }
 
 template <int NB>
-static void launch_reduce(const DevTree& D, const Scratch& S, uint32_t b0, uint32_t nb,
-                          uint32_t cnt, const float* bg, double* J, const uint8_t* active,
-                          hipStream_t st) {
-  k_reduce<NB><<<cnt, 64, 0, st>>>(D, S.blist, S.brad, S.ncnt, S.nidx, b0, nb, S.cut, S.bstat,
-                                   bg, J, active);
+static void launch_pair(const DevTree& D, const Scratch& S, uint32_t b0, uint32_t nb, uint32_t cnt,
+                        const float* bg, double* J, const uint8_t* active, hipStream_t st,
+                        trevr_tree* T, trevr_status* rc) {
+  hipEvent_t e0 = prof_begin(T);
+  k_nearfield<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, S.bnact, b0, nb,
+                                       active, S.tpp, J);
+  *rc = hip_check(hipGetLastError(), "k_nearfield");
+  if (*rc != TREVR_OK) return;
+  prof_end(T, TREVR_PROF_NEAR, e0);
+  hipEvent_t e1 = prof_begin(T);
+  k_far<NB><<<cnt, 64, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp, bg,
+                                J, active);
+  *rc = hip_check(hipGetLastError(), "k_far");
+  prof_end(T, TREVR_PROF_REDUCE, e1);
 }
 
 trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* bg, double* J,
                             void* scratch, size_t scratch_bytes) {
   hipStream_t st = T->stream;
   const int64_t nleaves = T->num_leaves;
-  Scratch S = carve_scratch(scratch, T->n, nleaves);
+  Scratch S = carve_scratch(scratch, nleaves);
   if (scratch_bytes < S.fixed) {
     T->scratch_needed = S.fixed;
     return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
@@ -746,44 +1155,53 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   if ((rc = hip_check(hipMemsetAsync(S.ncnt, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) !=
       TREVR_OK)
     return rc;
+  if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) !=
+      TREVR_OK)
+    return rc;
+  hipEvent_t ev_setup = prof_begin(T);
   k_active_buckets<<<(unsigned)((T->num_nodes + 255) / 256), 256, 0, st>>>(D, active, S.blist,
                                                                             S.bnact, S.nb);
   TREVR_LAUNCH_CHECK("k_active_buckets");
-  k_setup<<<(unsigned)((nleaves + 63) / 64), 64, 0, st>>>(D, S.blist, S.nb, S.brad, S.ncnt);
+  k_setup<<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist, S.nb, S.brad, S.ncnt, S.nlumc);
   TREVR_LAUNCH_CHECK("k_setup");
-  k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.near_total);
-  TREVR_LAUNCH_CHECK("k_scan_inplace");
-  uint32_t* hbuf = nullptr;
-  if ((rc = hip_check(hipHostMalloc((void**)&hbuf, 2 * sizeof(uint32_t)), "hipHostMalloc")) != TREVR_OK)
-    return rc;
-  hipError_t e = hipMemcpyAsync(hbuf, S.nb, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.nb + 1);
+  TREVR_LAUNCH_CHECK("k_scan_u32");
+  k_scan_u32<<<1, 1024, 0, st>>>(S.bnact, nleaves + 1, S.nb + 2);
+  TREVR_LAUNCH_CHECK("k_scan_u32");
+  uint32_t* hbuf = T->host_u32;
+  hipError_t e = hipMemcpyAsync(hbuf, S.nb, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  const uint32_t nb = hbuf[0], near_total = hbuf[1];
-  (void)hipHostFree(hbuf);
   if ((rc = hip_check(e, "bucket readback")) != TREVR_OK) return rc;
-  const size_t need = S.fixed + sizeof(uint32_t) * (size_t)near_total + 256;
+  const uint32_t nb = hbuf[0], near_total = hbuf[1], act_total = hbuf[2];
+  const size_t near_off = (S.fixed + 255) & ~(size_t)255;
+  const size_t tpp_off = (near_off + sizeof(uint32_t) * (size_t)near_total + 255) & ~(size_t)255;
+  const size_t need = tpp_off + sizeof(float) * (size_t)act_total * T->nray * T->B + 256;
   T->scratch_needed = need;
   if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
-  S.nidx = (uint32_t*)((char*)scratch + ((S.fixed + 255) & ~(size_t)255));
+  S.nidx = (uint32_t*)((char*)scratch + near_off);
+  S.tpp = (float*)((char*)scratch + tpp_off);
   if (nb > 0) {
-    k_near_fill<<<(unsigned)((nb + 63) / 64), 64, 0, st>>>(D, S.blist, S.nb, S.brad, S.ncnt, S.nidx);
+    k_near_fill<<<nb, 64, 0, st>>>(D, S.blist, S.nb, S.brad, S.ncnt, S.nlumc, S.nidx);
     TREVR_LAUNCH_CHECK("k_near_fill");
   }
+  prof_end(T, TREVR_PROF_SETUP, ev_setup);
   for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
     const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
+    hipEvent_t ev_walk = prof_begin(T);
     k_walk<<<cnt, 64, 0, st>>>(D, S.blist, S.brad, b0, nb, S.cut, S.bstat);
     TREVR_LAUNCH_CHECK("k_walk");
+    prof_end(T, TREVR_PROF_WALK, ev_walk);
     switch (T->B) {
-      case 1: launch_reduce<1>(D, S, b0, nb, cnt, bg, J, active, st); break;
-      case 2: launch_reduce<2>(D, S, b0, nb, cnt, bg, J, active, st); break;
-      case 3: launch_reduce<3>(D, S, b0, nb, cnt, bg, J, active, st); break;
-      case 4: launch_reduce<4>(D, S, b0, nb, cnt, bg, J, active, st); break;
-      case 5: launch_reduce<5>(D, S, b0, nb, cnt, bg, J, active, st); break;
-      case 6: launch_reduce<6>(D, S, b0, nb, cnt, bg, J, active, st); break;
-      case 7: launch_reduce<7>(D, S, b0, nb, cnt, bg, J, active, st); break;
-      default: launch_reduce<8>(D, S, b0, nb, cnt, bg, J, active, st); break;
+      case 1: launch_pair<1>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      case 2: launch_pair<2>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      case 3: launch_pair<3>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      case 4: launch_pair<4>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      case 5: launch_pair<5>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      case 6: launch_pair<6>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      case 7: launch_pair<7>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      default: launch_pair<8>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
     }
-    TREVR_LAUNCH_CHECK("k_reduce");
+    if (rc != TREVR_OK) return rc;
   }
 #undef TREVR_LAUNCH_CHECK
   T->counters_valid = true;

@@ -586,24 +586,19 @@ trevr_status build_tree_impl(trevr_tree* T, const float* x, const float* y, cons
   TREVR_LAUNCH_CHECK("k_root");
   T->levels.clear();
   uint32_t lb = 0, le = 1;
-  uint32_t* host_alloc = nullptr;
-  if ((rc = hip_check(hipHostMalloc((void**)&host_alloc, sizeof(uint32_t)), "hipHostMalloc")) != TREVR_OK)
-    return rc;
+  uint32_t* host_alloc = T->host_u32;
   while (lb < le) {
     T->levels.emplace_back(lb, le);
     k_level<<<grid_for(le - lb, 256), 256, 0, st>>>(tb, lb, le, T->p.leaf_size);
     TREVR_LAUNCH_CHECK("k_level");
     hipError_t e = hipMemcpyAsync(host_alloc, tb.alloc, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if ((rc = hip_check(e, "level readback")) != TREVR_OK) { (void)hipHostFree(host_alloc); return rc; }
+    if ((rc = hip_check(e, "level readback")) != TREVR_OK) return rc;
     lb = le;
     le = *host_alloc;
-    if (T->levels.size() > (size_t)kMaxLevels + 2) {
-      (void)hipHostFree(host_alloc);
+    if (T->levels.size() > (size_t)kMaxLevels + 2)
       return set_error(TREVR_E_DATA, "tree deeper than the key allows");
-    }
   }
-  (void)hipHostFree(host_alloc);
   const uint32_t total = le;
   T->num_nodes = total;
   T->num_leaves = (total + 1) / 2;

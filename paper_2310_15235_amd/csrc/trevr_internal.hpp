@@ -86,6 +86,14 @@ struct trevr_tree {
   std::vector<std::pair<uint32_t, uint32_t>> levels;  // BFS index ranges per depth
   size_t scratch_needed;
   bool counters_valid;
+  uint32_t* host_u32;                       // pinned 4-word readback buffer
+  // kernel timing (trevr_profile_enable)
+  bool prof_on;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double prof_ms[TREVR_PROF_SLOTS];
+  int64_t prof_calls[TREVR_PROF_SLOTS];
 };
 
 namespace trevr {
@@ -97,4 +105,7 @@ trevr_status build_tree_impl(trevr_tree* t, const float* x, const float* y, cons
 trevr_status compute_J_impl(trevr_tree* t, const uint8_t* active, const float* bg, double* J,
                             void* scratch, size_t scratch_bytes);
 size_t scratch_fixed_bytes(int64_t n);
+// Record an event pair around a phase (no-op unless profiling is on).
+hipEvent_t prof_begin(trevr_tree* t);
+void prof_end(trevr_tree* t, int slot, hipEvent_t begin);
 }  // namespace trevr
