@@ -11,10 +11,10 @@
 //                     ballot compaction) and writes the bucket's cut: accepted
 //                     cells, opened buckets and resolved element sources, each
 //                     source tagged with its HEALPix pixel;
-//   k_nearfield       256 threads per bucket stage the p-p set through LDS:
+//   k_pp_rays         256 threads per bucket stage the p-p set through LDS:
 //                     per receiver and ray the p-p optical depth (kept for the
-//                     far field), and the attenuated p-p sources (J starts
-//                     with these);
+//                     far field);
+//   k_pp_src          the attenuated p-p sources (J starts with these);
 //   k_far             one wavefront reduces the cut ray by ray: rays in groups
 //                     of 64 with one lane per ray, so a lane owns its ray's
 //                     sources and adds the optical depth of every absorbing
@@ -37,7 +37,8 @@ namespace trevr {
 constexpr int kRMax = 8;         // receivers per pass
 constexpr int kStackCap = 4096;  // traversal stack entries (LDS)
 constexpr uint32_t kCutCap = 2048;
-constexpr uint32_t kBatch = 16384;
+constexpr uint32_t kBatch = 65536;   // buckets per launch (bounds the cut-list scratch)
+constexpr int kCostBins = 48;
 constexpr int kNT = 256;         // threads of the near-field kernel
 constexpr int kNChunk = 256;     // p-p elements staged per pass
 constexpr int kNPair = 2;        // (receiver, p-p source) pairs per thread per pass
@@ -405,242 +406,320 @@ struct RecvInfo {
 };
 
 // ------------------------------------------------------------ near field
-// Particle-particle transfer inside the p-p sphere (Section 2.4).  For each
-// receiver i and ray k: the optical depth of the p-p elements ahead of i on
-// the ray and within their size of the ray line, kappa_l Sigma_l(b) with
-// Sigma_l(b) = 3 m_l/(pi h_l^2) (1 - b/h_l) (written to tpp for the far
-// field).  For each luminous p-p element j (i itself included, at r = 0):
-// L_j K(r_ij, h_i) exp(-tau_ij), tau over the elements closer to j than i is
-// and within their size of the segment i-j; J of i starts with their sum.
+// Particle-particle transfer inside the p-p sphere (Section 2.4), in two
+// kernels of 256 threads per bucket that stage the p-p set through LDS
+// kNChunk elements at a time.  Elements are culled kSub at a time with FP32
+// boxes (each element's position grown by its own size h, plus a margin),
+// which is conservative: an element can only absorb on a line that passes
+// within h of it.  Threads are mapped receiver-fastest, so the lines of a
+// wavefront are nearly parallel and skip the same boxes.
+constexpr int kSub = 16;
+constexpr int kNSub = kNChunk / kSub;
+
+template <int NB> struct NearTile {
+  double x[kNChunk], y[kNChunk], z[kNChunk], h2[kNChunk];
+  float sig[kNChunk], invh[kNChunk];
+  float kap[kNChunk][NB];
+  uint32_t slot[kNChunk];
+  float blo[kNSub][3], bhi[kNSub][3];
+};
+
 template <int NB>
-__global__ void __launch_bounds__(kNT) k_nearfield(DevTree T, const uint32_t* blist,
-                                                  const uint32_t* noff, const uint32_t* nlumc,
-                                                  const uint32_t* nidx, const uint32_t* roff,
-                                                  uint32_t b0, uint32_t nbuck,
-                                                  const uint8_t* active, float* tpp, double* J) {
+__device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint32_t* near,
+                                  uint32_t c0, uint32_t cl, const double c[3]) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  if ((uint32_t)t < cl) {
+    const uint32_t l = near[c0 + t];
+    const double hl = T.h[l];
+    S.x[t] = (double)T.x[l];
+    S.y[t] = (double)T.y[l];
+    S.z[t] = (double)T.z[l];
+    S.h2[t] = hl * hl;
+    S.sig[t] = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+    S.invh[t] = (float)(1.0 / hl);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) S.kap[t][b] = T.kappa[(int64_t)b * T.n + l];
+    S.slot[t] = l;
+  }
+  __syncthreads();
+  if (t < kNSub) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int u1 = min((int)cl, (t + 1) * kSub);
+    for (int u = t * kSub; u < u1; ++u) {
+      const float h = sqrtf((float)S.h2[u]);
+      const float p[3] = {(float)(S.x[u] - c[0]), (float)(S.y[u] - c[1]), (float)(S.z[u] - c[2])};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float m = h + 1e-5f * (fabsf(p[a]) + h);
+        lo[a] = fminf(lo[a], p[a] - m);
+        hi[a] = fmaxf(hi[a], p[a] + m);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { S.blo[t][a] = lo[a]; S.bhi[t][a] = hi[a]; }
+  }
+  __syncthreads();
+}
+
+// Next chunk of active bucket members (thread 0 keeps the cursor).
+__device__ inline int load_receivers(const DevTree& T, const uint8_t* active, const double c[3],
+                                     uint32_t& member, uint32_t mend, RecvInfo* recv,
+                                     uint32_t* nrecv_s) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t k = 0;
+    while (member < mend && k < (uint32_t)kRMax) {
+      const uint32_t s = member++;
+      if (active == nullptr || active[T.perm[s]]) {
+        RecvInfo ri;
+        ri.x[0] = (double)T.x[s];
+        ri.x[1] = (double)T.y[s];
+        ri.x[2] = (double)T.z[s];
+        ri.h = T.h[s];
+        for (int a = 0; a < 3; ++a) ri.rel[a] = (float)(ri.x[a] - c[a]);
+        ri.inv_rh = (float)(1.0 / (kR * ri.h));
+        ri.kfac = (float)(1.0 / (2.0 * ri.h * ri.h));
+        ri.slot = s;
+        recv[k++] = ri;
+      }
+    }
+    *nrecv_s = k;
+  }
+  __syncthreads();
+  return (int)*nrecv_s;
+}
+
+// FP32 ray-box test on the half line o + t n, t >= 0 (inv = 1/n, +-huge for 0).
+__device__ inline bool ray_meets_box(const float o[3], const float inv[3], const float lo[3],
+                                     const float hi[3]) {
+  float tin = 0.0f, tout = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float t1 = (lo[a] - o[a]) * inv[a], t2 = (hi[a] - o[a]) * inv[a];
+    tin = fmaxf(tin, fminf(t1, t2));
+    tout = fminf(tout, fmaxf(t1, t2));
+  }
+  return tin <= tout;
+}
+
+// For each receiver i and ray k: the optical depth of the p-p elements ahead
+// of i on the ray (exact FP64 projection: a discontinuous decision) whose
+// size h reaches the ray line (b < h, with b^2 = |d|^2 - proj^2: continuous,
+// Sigma -> 0 at b = h): kappa_l Sigma_l(b), Sigma_l(b) = 3 m_l/(pi h_l^2)
+// (1 - b/h_l).  Written to tpp[receiver][ray][band] for the far field.
+template <int NB>
+__global__ void __launch_bounds__(kNT) k_pp_rays(DevTree T, const uint32_t* blist,
+                                                const uint32_t* noff, const uint32_t* nidx,
+                                                const uint32_t* roff, uint32_t b0, uint32_t nbuck,
+                                                const uint8_t* active, float* tpp) {
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
   const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
-  __shared__ double lx[kNChunk], ly[kNChunk], lz[kNChunk], lh2[kNChunk];
-  __shared__ float lsig[kNChunk], linvh[kNChunk];
-  __shared__ float lkap[kNChunk][NB];
-  __shared__ uint32_t lslot[kNChunk];
+  __shared__ NearTile<NB> S;
   __shared__ RecvInfo recv[kRMax];
-  __shared__ double wred[kNT / 64][kRMax][NB];
   __shared__ uint32_t nrecv_s;
+  const uint32_t leafb = blist[bucket];
+  double c[3];
+  leaf_centre(T, leafb, c);
+  const uint32_t n0 = noff[bucket], nnear = noff[bucket + 1] - n0;
+  const uint32_t* near = nidx + n0;
+  const uint2 lk = T.nlink[leafb];
+  const int nray = T.nray;
+  uint32_t rbase = roff[bucket];
+  uint32_t member = lk.x;
+  for (;;) {
+    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    if (nrecv == 0) break;
+    const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
+    const int gpr = (nray + 1) / 2;                 // two rays per thread
+    const uint32_t P = (uint32_t)nrecv * (uint32_t)gpr;
+    const int i = t % nrecv;
+    const RecvInfo& ri = recv[i];
+    for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
+      const uint32_t p = pb + (uint32_t)t;
+      const bool ok = t < stride && p < P;
+      const int kb = ok ? 2 * (int)(p / nrecv) : 0;
+      double nv[2][3];
+      float of[3], inv[2][3];
+      bool kok[2];
+      float tau[2][NB];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        kok[q] = ok && kb + q < nray;
+        const int kq = kok[q] ? kb + q : 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          nv[q][a] = T.ray_n[3 * kq + a];
+          const float nf = (float)nv[q][a];
+          inv[q][a] = (nf != 0.0f) ? 1.0f / nf : 1e30f;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) tau[q][b] = 0.0f;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) of[a] = ri.rel[a];
+      const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
+      const uint32_t si = ri.slot;
+      for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
+        const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
+        stage_near<NB>(S, T, near, c0, cl, c);
+        const int nsub = ((int)cl + kSub - 1) / kSub;
+        for (int sb = 0; sb < nsub; ++sb) {
+          bool need = false;
+          if (ok) {
+            const float blo[3] = {S.blo[sb][0], S.blo[sb][1], S.blo[sb][2]};
+            const float bhi[3] = {S.bhi[sb][0], S.bhi[sb][1], S.bhi[sb][2]};
+            need = (kok[0] && ray_meets_box(of, inv[0], blo, bhi)) ||
+                   (kok[1] && ray_meets_box(of, inv[1], blo, bhi));
+          }
+          if (ballot64(need) == 0ull) continue;
+          if (!need) continue;
+          const int u1 = min((int)cl, (sb + 1) * kSub);
+          for (int u = sb * kSub; u < u1; ++u) {
+            const double d0 = S.x[u] - xi0, d1 = S.y[u] - xi1, d2 = S.z[u] - xi2;
+            const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+            const double h2 = S.h2[u];
+            const bool other = S.slot[u] != si;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const double proj = d0 * nv[q][0] + d1 * nv[q][1] + d2 * nv[q][2];
+              const double b2 = dd - proj * proj;
+              if (proj > 0.0 && b2 < h2 && other && kok[q]) {
+                const float bb = sqrtf((float)fmax(b2, 0.0));
+                const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) tau[q][b] += S.kap[u][b] * sg;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (!kok[q]) continue;
+        float* o = tpp + ((int64_t)(rbase + i) * nray + kb + q) * NB;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) o[b] = tau[q][b];
+      }
+    }
+    rbase += (uint32_t)nrecv;
+  }
+}
 
+// For each receiver i and luminous p-p element j (i itself included, at
+// r = 0): L_j K(r_ij, h_i) exp(-tau_ij), tau over the p-p elements closer to
+// j than i is (exact FP64 squared distances: discontinuous) and within their
+// size of the segment i-j (continuous).  J of i starts with the sum.
+template <int NB>
+__global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist,
+                                               const uint32_t* noff, const uint32_t* nlumc,
+                                               const uint32_t* nidx, uint32_t b0, uint32_t nbuck,
+                                               const uint8_t* active, double* J) {
+  const uint32_t bucket = b0 + blockIdx.x;
+  if (bucket >= nbuck) return;
+  const int t = threadIdx.x;
+  __shared__ NearTile<NB> S;
+  __shared__ RecvInfo recv[kRMax];
+  __shared__ uint32_t nrecv_s;
+  __shared__ double red[kNT][NB];
   const uint32_t leafb = blist[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
   const uint32_t n0 = noff[bucket], nnear = noff[bucket + 1] - n0, nl = nlumc[bucket];
   const uint32_t* near = nidx + n0;
   const uint2 lk = T.nlink[leafb];
-  const int nray = T.nray;
   const int64_t n = T.n;
-  uint32_t rbase = roff[bucket];
   uint32_t member = lk.x;
-  const uint32_t mend = lk.x + lk.y;
   uint32_t nact = 0;
-
-  // stage p-p elements [c0, c0 + cl) into LDS
-  auto stage = [&](uint32_t c0, uint32_t cl) {
-    __syncthreads();
-    if ((uint32_t)t < cl) {
-      const uint32_t l = near[c0 + t];
-      const double hl = T.h[l];
-      lx[t] = (double)T.x[l];
-      ly[t] = (double)T.y[l];
-      lz[t] = (double)T.z[l];
-      lh2[t] = hl * hl;
-      lsig[t] = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-      linvh[t] = (float)(1.0 / hl);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) lkap[t][b] = T.kappa[(int64_t)b * n + l];
-      lslot[t] = l;
-    }
-    __syncthreads();
-  };
-
   for (;;) {
-    __syncthreads();
-    if (t == 0) {  // thread 0 owns the member cursor
-      uint32_t k = 0;
-      while (member < mend && k < (uint32_t)kRMax) {
-        const uint32_t s = member++;
-        if (active == nullptr || active[T.perm[s]]) {
-          RecvInfo ri;
-          ri.x[0] = (double)T.x[s];
-          ri.x[1] = (double)T.y[s];
-          ri.x[2] = (double)T.z[s];
-          ri.h = T.h[s];
-          for (int a = 0; a < 3; ++a) ri.rel[a] = (float)(ri.x[a] - c[a]);
-          ri.inv_rh = (float)(1.0 / (kR * ri.h));
-          ri.kfac = (float)(1.0 / (2.0 * ri.h * ri.h));
-          ri.slot = s;
-          recv[k++] = ri;
-        }
-      }
-      nrecv_s = k;
-    }
-    __syncthreads();
-    const int nrecv = (int)nrecv_s;
+    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
-
-    // ---- p-p optical depth per (receiver, ray).  A thread takes one
-    // receiver and kRayPer rays, so the offset to each p-p element and its
-    // length are shared by the rays.  Whether the element lies ahead (proj > 0)
-    // is a discontinuous decision and uses the exact FP64 projection; the
-    // impact-parameter test b < h and the column Sigma(b) are continuous
-    // (Sigma -> 0 at b = h) and use b^2 = |d|^2 - proj^2.
-    const int gpr = (nray + kRayPer - 1) / kRayPer;      // ray groups per receiver
-    const uint32_t P1 = (uint32_t)nrecv * (uint32_t)gpr;
-    for (uint32_t pb = 0; pb < P1; pb += kNT) {
+    nact += (uint32_t)nrecv;
+    const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
+    const int i = t % nrecv;
+    const RecvInfo& ri = recv[i];
+    const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
+    const uint32_t si = ri.slot;
+    double acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+    const uint32_t P = (uint32_t)nrecv * nl;
+    for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
       const uint32_t p = pb + (uint32_t)t;
-      const bool ok = p < P1;
-      const int i = ok ? (int)(p / gpr) : 0;
-      const int kb = ok ? (int)(p % gpr) * kRayPer : 0;
-      const double xi0 = recv[i].x[0], xi1 = recv[i].x[1], xi2 = recv[i].x[2];
-      const uint32_t si = ok ? recv[i].slot : 0xFFFFFFFFu;
-      double nv[kRayPer][3];
-      bool kok[kRayPer];
-      float tau[kRayPer][NB];
+      const bool ok = t < stride && p < P;
+      const uint32_t j = ok ? near[p / nrecv] : near[0];
+      const double xj0 = (double)T.x[j], xj1 = (double)T.y[j], xj2 = (double)T.z[j];
+      const double e0 = xj0 - xi0, e1 = xj1 - xi1, e2 = xj2 - xi2;
+      const double rij2 = e0 * e0 + e1 * e1 + e2 * e2;
+      const double inv2 = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
+      const float jr[3] = {(float)(xj0 - c[0]), (float)(xj1 - c[1]), (float)(xj2 - c[2])};
+      float smin[3], smax[3];
 #pragma unroll
-      for (int q = 0; q < kRayPer; ++q) {
-        kok[q] = ok && kb + q < nray;
-        const int kq = kok[q] ? kb + q : 0;
-        nv[q][0] = T.ray_n[3 * kq];
-        nv[q][1] = T.ray_n[3 * kq + 1];
-        nv[q][2] = T.ray_n[3 * kq + 2];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) tau[q][b] = 0.0f;
+      for (int a = 0; a < 3; ++a) {
+        smin[a] = fminf(ri.rel[a], jr[a]);
+        smax[a] = fmaxf(ri.rel[a], jr[a]);
       }
+      const float r2f = (float)rij2 * (1.0f + 1e-5f) + 1e-30f;
+      float tau[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) tau[b] = 0.0f;
       for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
         const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
-        stage(c0, cl);
-        if (!ok) continue;
-        for (uint32_t u = 0; u < cl; ++u) {
-          if (lslot[u] == si) continue;
-          const double d0 = lx[u] - xi0, d1 = ly[u] - xi1, d2 = lz[u] - xi2;
-          const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-          const double h2 = lh2[u];
+        stage_near<NB>(S, T, near, c0, cl, c);
+        const int nsub = ((int)cl + kSub - 1) / kSub;
+        for (int sb = 0; sb < nsub; ++sb) {
+          bool need = false;
+          if (ok && rij2 > 0.0) {
+            float dmin2 = 0.0f;
+            bool over = true;
 #pragma unroll
-          for (int q = 0; q < kRayPer; ++q) {
-            const double proj = d0 * nv[q][0] + d1 * nv[q][1] + d2 * nv[q][2];
-            if (!(proj > 0.0)) continue;
-            const double b2 = dd - proj * proj;
-            if (!(b2 < h2) || !kok[q]) continue;
-            const float bb = sqrtf((float)fmax(b2, 0.0));
-            const float sig = lsig[u] * (1.0f - bb * linvh[u]);
+            for (int a = 0; a < 3; ++a) {
+              const float lo = S.blo[sb][a], hi = S.bhi[sb][a];
+              over = over && (smax[a] >= lo) && (smin[a] <= hi);
+              const float dj = fmaxf(fmaxf(lo - jr[a], jr[a] - hi), 0.0f);
+              dmin2 += dj * dj;
+            }
+            need = over && dmin2 < r2f;
+          }
+          if (ballot64(need) == 0ull) continue;
+          if (!need) continue;
+          const int u1 = min((int)cl, (sb + 1) * kSub);
+          for (int u = sb * kSub; u < u1; ++u) {
+            const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
+            const double f0 = ux - xj0, f1 = uy - xj1, f2 = uz - xj2;
+            const double w0 = ux - xi0, w1 = uy - xi1, w2 = uz - xi2;
+            double uu = (w0 * e0 + w1 * e1 + w2 * e2) * inv2;
+            uu = fmin(1.0, fmax(0.0, uu));
+            const double g0 = w0 - uu * e0, g1 = w1 - uu * e1, g2 = w2 - uu * e2;
+            const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+            const uint32_t us = S.slot[u];
+            if ((f0 * f0 + f1 * f1 + f2 * f2 < rij2) && b2 < S.h2[u] && us != si && us != j) {
+              const float bb = sqrtf((float)b2);
+              const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) tau[q][b] += lkap[u][b] * sig;
+              for (int b = 0; b < NB; ++b) tau[b] += S.kap[u][b] * sg;
+            }
           }
         }
       }
       if (ok) {
+        const float Kv = fshape((float)sqrt(rij2) * ri.inv_rh) * ri.kfac;
 #pragma unroll
-        for (int q = 0; q < kRayPer; ++q) {
-          if (!kok[q]) continue;
-          float* o = tpp + ((int64_t)(rbase + i) * nray + kb + q) * NB;
-#pragma unroll
-          for (int b = 0; b < NB; ++b) o[b] = tau[q][b];
-        }
+        for (int b = 0; b < NB; ++b)
+          acc[b] += (double)T.lum[(int64_t)b * n + j] * (double)Kv * exp(-(double)tau[b]);
       }
     }
-
-    // ---- p-p sources
-    double acc[kRMax][NB];
+    // receiver-wise sums in thread order (deterministic)
 #pragma unroll
-    for (int i = 0; i < kRMax; ++i)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[i][b] = 0.0;
-    const uint32_t P2 = (uint32_t)nrecv * nl;
-    for (uint32_t pb = 0; pb < P2; pb += kNT * kNPair) {
-      bool ok[kNPair];
-      int ii[kNPair];
-      uint32_t jj[kNPair], si[kNPair];
-      double xi[kNPair][3], xj[kNPair][3], e[kNPair][3], rij2[kNPair], tau[kNPair][NB];
-#pragma unroll
-      for (int q = 0; q < kNPair; ++q) {
-        const uint32_t p = pb + (uint32_t)t + (uint32_t)(q * kNT);
-        ok[q] = p < P2;
-        ii[q] = ok[q] ? (int)(p / nl) : 0;
-        jj[q] = ok[q] ? near[p % nl] : 0u;
-        si[q] = recv[ii[q]].slot;
-        xj[q][0] = (double)T.x[jj[q]];
-        xj[q][1] = (double)T.y[jj[q]];
-        xj[q][2] = (double)T.z[jj[q]];
-        for (int a = 0; a < 3; ++a) {
-          xi[q][a] = recv[ii[q]].x[a];
-          e[q][a] = xj[q][a] - xi[q][a];
-        }
-        rij2[q] = e[q][0] * e[q][0] + e[q][1] * e[q][1] + e[q][2] * e[q][2];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) tau[q][b] = 0.0;
-      }
-      // Closer to the source than the receiver is (discontinuous: exact
-      // FP64 squared distances); within h of the segment (continuous).
-      double inv2[kNPair];
-#pragma unroll
-      for (int q = 0; q < kNPair; ++q) inv2[q] = (rij2[q] > 0.0) ? 1.0 / rij2[q] : 0.0;
-      for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
-        const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
-        stage(c0, cl);
-        for (uint32_t u = 0; u < cl; ++u) {
-          const double ux = lx[u], uy = ly[u], uz = lz[u], h2 = lh2[u];
-          const uint32_t us = lslot[u];
-#pragma unroll
-          for (int q = 0; q < kNPair; ++q) {
-            if (!ok[q] || us == si[q] || us == jj[q]) continue;
-            const double f0 = ux - xj[q][0], f1 = uy - xj[q][1], f2 = uz - xj[q][2];
-            if (!(f0 * f0 + f1 * f1 + f2 * f2 < rij2[q])) continue;
-            const double w0 = ux - xi[q][0], w1 = uy - xi[q][1], w2 = uz - xi[q][2];
-            double uu = (w0 * e[q][0] + w1 * e[q][1] + w2 * e[q][2]) * inv2[q];
-            uu = fmin(1.0, fmax(0.0, uu));
-            const double g0 = w0 - uu * e[q][0], g1 = w1 - uu * e[q][1], g2 = w2 - uu * e[q][2];
-            const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-            if (!(b2 < h2)) continue;
-            const float bb = sqrtf((float)b2);
-            const float sig = lsig[u] * (1.0f - bb * linvh[u]);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) tau[q][b] += (double)(lkap[u][b] * sig);
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kNPair; ++q) {
-        if (!ok[q]) continue;
-        const RecvInfo& ri = recv[ii[q]];
-        const float rij = (float)sqrt(rij2[q]);
-        const float Kv = fshape(rij * ri.inv_rh) * ri.kfac;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const double v = (double)T.lum[(int64_t)b * n + jj[q]] * (double)Kv * exp(-tau[q][b]);
-#pragma unroll
-          for (int i2 = 0; i2 < kRMax; ++i2)
-            if (i2 == ii[q]) acc[i2][b] += v;
-        }
-      }
-    }
-    // ---- block reduction; J starts with the p-p sources
-#pragma unroll
-    for (int i = 0; i < kRMax; ++i) {
-      if (i >= nrecv) continue;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const double v = wave_sum(acc[i][b]);
-        if (lane == 0) wred[wv][i][b] = v;
-      }
-    }
+    for (int b = 0; b < NB; ++b) red[t][b] = acc[b];
     __syncthreads();
     if (t < nrecv * NB) {
-      const int i = t / NB, b = t % NB;
+      const int ii = t / NB, b = t % NB;
       double v = 0.0;
-      for (int w = 0; w < kNT / 64; ++w) v += wred[w][i][b];
-      J[(int64_t)b * n + T.perm[recv[i].slot]] = v;
+      for (int u = ii; u < stride; u += nrecv) v += red[u][b];
+      J[(int64_t)b * n + T.perm[recv[ii].slot]] = v;
     }
-    rbase += (uint32_t)nrecv;
-    nact += (uint32_t)nrecv;
   }
   if (t == 0) {
     atomicAdd(&T.counters[CNT_NEAR_PAIRS], (unsigned long long)nact * nnear);
@@ -1088,10 +1167,52 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
   }
 }
 
+// ----------------------------------------------------- bucket ordering
+// Buckets are processed heaviest first (a counting sort by the log2 of an
+// estimate of their p-p work), so the slowest buckets start early instead of
+// forming the tail of a launch.  Each bucket's result is independent of its
+// position.
+__global__ void k_cost_bins(const uint32_t* nbp, const uint32_t* bnact, const uint32_t* ncnt,
+                            const uint32_t* nlumc, int nray, uint32_t* bbin, uint32_t* bins) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= *nbp) return;
+  const unsigned long long cost =
+      (unsigned long long)bnact[b] * ((unsigned long long)ncnt[b] * (nray / 2 + nlumc[b]) + 2000ull);
+  const int lg = 63 - __clzll((long long)cost);
+  const uint32_t bin = (uint32_t)max(0, (kCostBins - 1) - min(lg, kCostBins - 1));
+  bbin[b] = bin;
+  atomicAdd(&bins[bin], 1u);
+}
+
+__global__ void k_bins_scan(uint32_t* bins) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int i = 0; i < kCostBins; ++i) {
+    const uint32_t v = bins[i];
+    bins[i] = run;
+    run += v;
+  }
+}
+
+__global__ void k_reorder(const uint32_t* nbp, const uint32_t* bbin, uint32_t* bins,
+                          const uint32_t* blist, const uint32_t* bnact, const uint32_t* ncnt,
+                          const uint32_t* nlumc, const double* brad, uint32_t* blist2,
+                          uint32_t* bnact2, uint32_t* ncnt2, uint32_t* nlumc2, double* brad2) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= *nbp) return;
+  const uint32_t pos = atomicAdd(&bins[bbin[b]], 1u);
+  blist2[pos] = blist[b];
+  bnact2[pos] = bnact[b];
+  ncnt2[pos] = ncnt[b];
+  nlumc2[pos] = nlumc[b];
+  brad2[pos] = brad[b];
+}
+
 // ============================================================ host side
 struct Scratch {
   uint32_t *blist, *bnact, *ncnt, *nlumc, *roff, *bstat, *nb;
-  double* brad;
+  uint32_t *blist2, *bnact2, *ncnt2, *nlumc2, *bbin, *bins;
+  double *brad, *brad2;
   uint2* cut;
   uint32_t* nidx;
   float* tpp;
@@ -1109,6 +1230,13 @@ static Scratch carve_scratch(void* base, int64_t nleaves) {
   s.nlumc = cv.take<uint32_t>(L);
   s.bstat = cv.take<uint32_t>(4 * L);
   s.brad = cv.take<double>(L);
+  s.blist2 = cv.take<uint32_t>(L);
+  s.bnact2 = cv.take<uint32_t>(L + 1);
+  s.ncnt2 = cv.take<uint32_t>(L + 1);
+  s.nlumc2 = cv.take<uint32_t>(L);
+  s.brad2 = cv.take<double>(L);
+  s.bbin = cv.take<uint32_t>(L);
+  s.bins = cv.take<uint32_t>(kCostBins);
   s.cut = cv.take<uint2>((size_t)std::min<int64_t>(L, kBatch) * kCutCap);
   s.fixed = cv.off + 256;
   return s;
@@ -1121,9 +1249,11 @@ static void launch_pair(const DevTree& D, const Scratch& S, uint32_t b0, uint32_
                         const float* bg, double* J, const uint8_t* active, hipStream_t st,
                         trevr_tree* T, trevr_status* rc) {
   hipEvent_t e0 = prof_begin(T);
-  k_nearfield<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, S.bnact, b0, nb,
-                                       active, S.tpp, J);
-  *rc = hip_check(hipGetLastError(), "k_nearfield");
+  k_pp_rays<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nidx, S.bnact, b0, nb, active, S.tpp);
+  *rc = hip_check(hipGetLastError(), "k_pp_rays");
+  if (*rc != TREVR_OK) return;
+  k_pp_src<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, b0, nb, active, J);
+  *rc = hip_check(hipGetLastError(), "k_pp_src");
   if (*rc != TREVR_OK) return;
   prof_end(T, TREVR_PROF_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
@@ -1164,6 +1294,27 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   TREVR_LAUNCH_CHECK("k_active_buckets");
   k_setup<<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist, S.nb, S.brad, S.ncnt, S.nlumc);
   TREVR_LAUNCH_CHECK("k_setup");
+  // heaviest buckets first
+  if ((rc = hip_check(hipMemsetAsync(S.bins, 0, sizeof(uint32_t) * kCostBins, st), "memset")) != TREVR_OK)
+    return rc;
+  if ((rc = hip_check(hipMemsetAsync(S.ncnt2, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
+    return rc;
+  if ((rc = hip_check(hipMemsetAsync(S.bnact2, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
+    return rc;
+  k_cost_bins<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(S.nb, S.bnact, S.ncnt, S.nlumc,
+                                                                 T->nray, S.bbin, S.bins);
+  TREVR_LAUNCH_CHECK("k_cost_bins");
+  k_bins_scan<<<1, 64, 0, st>>>(S.bins);
+  TREVR_LAUNCH_CHECK("k_bins_scan");
+  k_reorder<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(
+      S.nb, S.bbin, S.bins, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.blist2, S.bnact2, S.ncnt2,
+      S.nlumc2, S.brad2);
+  TREVR_LAUNCH_CHECK("k_reorder");
+  std::swap(S.blist, S.blist2);
+  std::swap(S.bnact, S.bnact2);
+  std::swap(S.ncnt, S.ncnt2);
+  std::swap(S.nlumc, S.nlumc2);
+  std::swap(S.brad, S.brad2);
   k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.nb + 1);
   TREVR_LAUNCH_CHECK("k_scan_u32");
   k_scan_u32<<<1, 1024, 0, st>>>(S.bnact, nleaves + 1, S.nb + 2);
