@@ -729,40 +729,68 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
 }
 
 // ------------------------------------------------------------- far field
-// Sources of one ray group held on chip per window.
+// One workgroup of kFT threads per bucket.  Rays are taken in groups of 64;
+// thread k < 64 owns ray k of the group (its sources and their optical
+// depths), so hits update them without atomics.  Sources of a group are held
+// kSrcCap at a time (a second window re-reads the cut; only very source-rich
+// buckets need it).  Receivers are fixed per thread (t mod P2, P2 the power
+// of two >= the receiver count), so each thread keeps one FP64 accumulator
+// per band, reduced per receiver in a fixed order at the end.
+constexpr int kFT = 256;
 template <int NB> struct SrcCap { static constexpr int value = NB <= 4 ? 512 : 256; };
 
+// Block-wide compaction: position of this thread's item among the set ones
+// (in thread order) and the block total.  Uses wcnt[4] in LDS; two barriers.
+__device__ inline uint32_t block_compact(bool pred, uint32_t* wcnt, uint32_t* total) {
+  const int t = threadIdx.x, wv = t >> 6;
+  const uint64_t m = ballot64(pred);
+  if ((t & 63) == 0) wcnt[wv] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kFT / 64; ++w) {
+    if (w < wv) base += wcnt[w];
+    tot += wcnt[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + (uint32_t)mbcnt(m);
+}
+
 template <int NB>
-__global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, const double* brad,
-                                            const uint32_t* roff, uint32_t b0, uint32_t nbuck,
-                                            const uint2* cut, const uint32_t* bstat,
-                                            const float* tppg, const float* bg, double* J,
-                                            const uint8_t* active) {
+__global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, const double* brad,
+                                             const uint32_t* roff, uint32_t b0, uint32_t nbuck,
+                                             const uint2* cut, const uint32_t* bstat,
+                                             const float* tppg, const float* bg, double* J,
+                                             const uint8_t* active) {
   constexpr int kSrcCap = SrcCap<NB>::value;
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
   __shared__ float s_rel[kSrcCap][3];
   __shared__ float s_s[kSrcCap];
   __shared__ float s_tau[kSrcCap][NB];
+  __shared__ float s_sfx[kSrcCap][NB];
   __shared__ float s_L[kSrcCap][NB];
   __shared__ uint8_t s_ray[kSrcCap];
   __shared__ uint16_t s_order[kSrcCap];
-  __shared__ uint32_t ray_beg[65];
-  __shared__ uint32_t ray_fill[64];
+  __shared__ uint32_t ray_beg[65], ray_fill[64];
   __shared__ float tpp[kRMax][64][NB];
+  __shared__ float tex[64][NB];
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nrecv_s;
+  __shared__ uint32_t nrecv_s, wcnt[kFT / 64], abs_count, cand_total;
   __shared__ double a_lo[64][3], a_hi[64][3];
+  __shared__ float a_mc[64][3], a_d2[64], a_r2[64];
   __shared__ uint32_t a_node[64], a_pre[64];
-  __shared__ uint64_t a_mask[64];
-  __shared__ float s_sfx[kSrcCap][NB];
+  __shared__ unsigned long long a_mask[64];
   __shared__ double g_n[64][3], g_inv[64][3];
   __shared__ float g_nf[64][3];
-  __shared__ double h_t0[64], h_t1[64];
-  __shared__ uint32_t h_node[64], h_cnt[64], h_beg[65];
-  __shared__ uint8_t h_ray[64], h_ord[64];
+  __shared__ double h_t0[kFT], h_t1[kFT];
+  __shared__ uint32_t h_node[kFT], h_cnt[64], h_beg[65];
+  __shared__ uint8_t h_ray[kFT];
+  __shared__ uint16_t h_ord[kFT];
+  __shared__ double red[kFT / 64][kRMax][NB];
 
   const uint32_t leafb = blist[bucket];
   const double r = brad[bucket];
@@ -776,74 +804,53 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
   const int64_t n = T.n;
   const bool use_bg = (T.flags & TREVR_BACKGROUND) && bg != nullptr;
 
-  uint32_t nabs_total = 0;
+  if (t == 0) abs_count = 0u;
   uint32_t nact_total = 0;
   uint32_t rbase = roff[bucket];
   uint32_t member = lk.x;
-  const uint32_t mend = lk.x + lk.y;
   for (;;) {
-    if (lane == 0) {
-      uint32_t k = 0;
-      while (member < mend && k < (uint32_t)kRMax) {
-        const uint32_t s = member++;
-        if (active == nullptr || active[T.perm[s]]) {
-          RecvInfo ri;
-          ri.x[0] = (double)T.x[s];
-          ri.x[1] = (double)T.y[s];
-          ri.x[2] = (double)T.z[s];
-          ri.h = T.h[s];
-          for (int a = 0; a < 3; ++a) ri.rel[a] = (float)(ri.x[a] - c[a]);
-          ri.inv_rh = (float)(1.0 / (kR * ri.h));
-          ri.kfac = (float)(1.0 / (2.0 * ri.h * ri.h));
-          ri.slot = s;
-          recv[k++] = ri;
-        }
-      }
-      nrecv_s = k;
-    }
-    __syncthreads();
-    const int nrecv = (int)nrecv_s;
+    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
     const bool first_chunk = nact_total == 0;
     nact_total += (uint32_t)nrecv;
-
-    double acc[kRMax][NB];
+    int P2 = 1;
+    while (P2 < nrecv) P2 <<= 1;
+    const int my_i = t & (P2 - 1);             // this thread's receiver
+    const bool has_i = my_i < nrecv;
+    const int per_round = kFT / P2;
+    const int my_q = t / P2;
+    double acc[NB];
 #pragma unroll
-    for (int i = 0; i < kRMax; ++i)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[i][b] = 0.0;
+    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
 
     for (int g = 0; g < ngroups; ++g) {
       const int k0 = 64 * g;
       const int kn = min(64, nray - k0);
-      const int k = k0 + lane;
-      const bool rlane = lane < kn;
-      double nv[3] = {0.0, 0.0, 1.0}, inv[3] = {0.0, 0.0, 0.0};
+      const bool rt = t < kn;                  // ray-owning thread
       int cls = 0;
-      if (rlane) {
-        for (int a = 0; a < 3; ++a) {
-          nv[a] = T.ray_n[3 * k + a];
-          inv[a] = (nv[a] != 0.0) ? 1.0 / nv[a] : 0.0;
-        }
+      if (rt) {
+        const int k = k0 + t;
         cls = T.ray_class[k];
-        for (int a = 0; a < 3; ++a) {
-          g_n[lane][a] = nv[a];
-          g_inv[lane][a] = inv[a];
-          g_nf[lane][a] = (float)nv[a];
-        }
-        for (int i = 0; i < nrecv; ++i)
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
-            tpp[i][lane][b] = tppg[((int64_t)(rbase + i) * nray + k) * NB + b];
+        for (int a = 0; a < 3; ++a) {
+          const double na = T.ray_n[3 * k + a];
+          g_n[t][a] = na;
+          g_inv[t][a] = (na != 0.0) ? 1.0 / na : 0.0;
+          g_nf[t][a] = (float)na;
+        }
+      }
+      for (int q = t; q < nrecv * kn; q += kFT) {
+        const int i = q / kn, kq = q % kn;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          tpp[i][kq][b] = tppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
       }
 
-      // Sources of this group are held kSrcCap at a time; a second window
-      // re-reads the cut, which only very source-rich buckets need.
       for (uint32_t skip = 0;; skip += (uint32_t)kSrcCap) {
         // ---- sources whose pixel is in this group, window [skip, skip + cap)
         uint32_t nsg_all = 0;
-        for (uint32_t e0 = 0; e0 < ncut; e0 += 64) {
-          const uint32_t e = e0 + lane;
+        for (uint32_t e0 = 0; e0 < ncut; e0 += kFT) {
+          const uint32_t e = e0 + (uint32_t)t;
           bool mine = false;
           uint2 ent = make_uint2(0, 0);
           uint32_t pix = CUT_NOPIX;
@@ -852,67 +859,66 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
             pix = ent.y & 0xFFFFu;
             mine = pix != CUT_NOPIX && (int)pix >= k0 && (int)pix < k0 + kn;
           }
-          const uint64_t m = ballot64(mine);
-          if (mine) {
-            const uint32_t gi = nsg_all + (uint32_t)mbcnt(m);
-            if (gi >= skip && gi < skip + (uint32_t)kSrcCap) {
-              const uint32_t slot = gi - skip;
-              double p[3];
-              float Lv[NB];
-              if ((ent.y & CUT_KIND_MASK) == CUT_PART) {
-                p[0] = (double)T.x[ent.x];
-                p[1] = (double)T.y[ent.x];
-                p[2] = (double)T.z[ent.x];
+          uint32_t tot;
+          const uint32_t gi = nsg_all + block_compact(mine, wcnt, &tot);
+          if (mine && gi >= skip && gi < skip + (uint32_t)kSrcCap) {
+            const uint32_t slot = gi - skip;
+            double p[3];
+            float Lv[NB];
+            if ((ent.y & CUT_KIND_MASK) == CUT_PART) {
+              p[0] = (double)T.x[ent.x];
+              p[1] = (double)T.y[ent.x];
+              p[2] = (double)T.z[ent.x];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) Lv[b] = T.lum[(int64_t)b * n + ent.x];
-              } else {
-                const double4 cn = T.cen[ent.x];
-                p[0] = cn.x;
-                p[1] = cn.y;
-                p[2] = cn.z;
+              for (int b = 0; b < NB; ++b) Lv[b] = T.lum[(int64_t)b * n + ent.x];
+            } else {
+              const double4 cn = T.cen[ent.x];
+              p[0] = cn.x;
+              p[1] = cn.y;
+              p[2] = cn.z;
 #pragma unroll
-                for (int b = 0; b < NB; ++b) Lv[b] = (float)T.Lb[(int64_t)ent.x * NB + b];
-              }
-              const double v0 = p[0] - c[0], v1 = p[1] - c[1], v2 = p[2] - c[2];
-              double s = 0.0;
-              if (!(v0 == 0.0 && v1 == 0.0 && v2 == 0.0)) {
-                const double* nn = &T.ray_n[3 * pix];
-                s = v0 * nn[0] + v1 * nn[1] + v2 * nn[2];
-              }
-              s_rel[slot][0] = (float)v0;
-              s_rel[slot][1] = (float)v1;
-              s_rel[slot][2] = (float)v2;
-              s_s[slot] = (float)s;
-#pragma unroll
-              for (int b = 0; b < NB; ++b) {
-                s_L[slot][b] = Lv[b];
-                s_tau[slot][b] = 0.0f;
-              }
-              s_ray[slot] = (uint8_t)(pix - k0);
+              for (int b = 0; b < NB; ++b) Lv[b] = (float)T.Lb[(int64_t)ent.x * NB + b];
             }
+            const double v0 = p[0] - c[0], v1 = p[1] - c[1], v2 = p[2] - c[2];
+            double sd = 0.0;
+            if (!(v0 == 0.0 && v1 == 0.0 && v2 == 0.0)) {
+              const double* nn = &T.ray_n[3 * pix];
+              sd = v0 * nn[0] + v1 * nn[1] + v2 * nn[2];
+            }
+            s_rel[slot][0] = (float)v0;
+            s_rel[slot][1] = (float)v1;
+            s_rel[slot][2] = (float)v2;
+            s_s[slot] = (float)sd;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              s_L[slot][b] = Lv[b];
+              s_tau[slot][b] = 0.0f;
+              s_sfx[slot][b] = 0.0f;
+            }
+            s_ray[slot] = (uint8_t)(pix - k0);
           }
-          nsg_all += (uint32_t)__popcll(m);
+          nsg_all += tot;
         }
         const uint32_t nsg = min(nsg_all - skip, (uint32_t)kSrcCap);
         // ---- bin sources by ray, then sort each ray's sources by distance
-        ray_fill[lane] = 0u;
+        if (t < 64) ray_fill[t] = 0u;
         __syncthreads();
-        for (uint32_t q = lane; q < nsg; q += 64) atomicAdd(&ray_fill[s_ray[q]], 1u);
+        for (uint32_t q = t; q < nsg; q += kFT) atomicAdd(&ray_fill[s_ray[q]], 1u);
         __syncthreads();
-        {
-          const uint32_t v = ray_fill[lane];
-          const uint32_t ex = wave_excl(v, lane);
-          ray_beg[lane] = ex;
-          if (lane == 63) ray_beg[64] = ex + v;
-          ray_fill[lane] = ex;
+        if (t < 64) {
+          const uint32_t v = ray_fill[t];
+          const uint32_t ex = wave_excl(v, t);
+          ray_beg[t] = ex;
+          if (t == 63) ray_beg[64] = ex + v;
+          ray_fill[t] = ex;
         }
         __syncthreads();
-        for (uint32_t q = lane; q < nsg; q += 64) {
+        for (uint32_t q = t; q < nsg; q += kFT) {
           const uint32_t pos = atomicAdd(&ray_fill[s_ray[q]], 1u);
           s_order[pos] = (uint16_t)q;
         }
         __syncthreads();
-        const uint32_t q0 = rlane ? ray_beg[lane] : 0u, q1 = rlane ? ray_beg[lane + 1] : 0u;
+        const uint32_t q0 = rt ? ray_beg[t] : 0u, q1 = rt ? ray_beg[t + 1] : 0u;
         for (uint32_t a = q0 + 1; a < q1; ++a) {     // insertion sort by s
           const uint16_t key = s_order[a];
           const float ks = s_s[key];
@@ -923,72 +929,85 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
           }
           s_order[b] = key;
         }
-        for (uint32_t q = lane; q < nsg; q += 64)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) s_sfx[q][b] = 0.0f;
-        __syncthreads();
 
         // ---- cell absorption along each ray (Sections 2.5.1, 2.6).
-        // Absorbing cut entries are staged 64 at a time.  A conservative FP32
-        // bounding-sphere test gives each entry its candidate rays; the
-        // (entry, ray) candidates are packed across lanes for the exact FP64
-        // ray-box test; each hit is then applied by the lane owning its ray:
-        // sources on the ray inside the chord get the partial length, the
-        // nearest source beyond it a suffix add (resolved by a prefix sum
-        // over the ray's sources sorted by distance).
+        // Absorbing cut entries are staged 64 at a time; a conservative FP32
+        // bounding-sphere test (rays split over the four wavefronts) gives each
+        // its candidate rays; the (entry, ray) candidates are packed across
+        // the block for the exact FP64 ray-box test; each hit is applied by the
+        // thread owning its ray: sources on the ray inside the chord get the
+        // partial length, the nearest source beyond it a suffix add (resolved
+        // by a prefix sum over the ray's sources sorted by distance).
         float texl[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) texl[b] = 0.0f;
         uint32_t nabs = 0;
         for (uint32_t e0 = 0; e0 < ncut; e0 += 64) {
-          const uint32_t e = e0 + lane;
-          bool is = false;
-          uint32_t node = 0;
-          if (e < ncut) {
-            const uint2 ent = mycut[e];
-            is = (ent.y & CUT_ABS) != 0u;
-            node = ent.x;
-          }
-          const uint64_t am = ballot64(is);
-          const int na = __popcll(am);
-          uint64_t mask = 0ull;
-          const int pos = mbcnt(am);
-          if (is) {
-            double lo[3], hi[3];
-            node_box(T.hdr, T.nk[node], lo, hi);
-            float mc[3];
-            float R2 = 0.0f, D2 = 0.0f;
+          if (t < 64) {
+            const uint32_t e = e0 + (uint32_t)t;
+            bool is = false;
+            uint32_t node = 0;
+            if (e < ncut) {
+              const uint2 ent = mycut[e];
+              is = (ent.y & CUT_ABS) != 0u;
+              node = ent.x;
+            }
+            const uint64_t am = ballot64(is);
+            if (t == 0) wcnt[0] = (uint32_t)__popcll(am);
+            if (is) {
+              const int pos = mbcnt(am);
+              double lo[3], hi[3];
+              node_box(T.hdr, T.nk[node], lo, hi);
+              float R2 = 0.0f, D2 = 0.0f;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              a_lo[pos][a] = lo[a];
-              a_hi[pos][a] = hi[a];
-              mc[a] = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
-              const float hx = (float)(0.5 * (hi[a] - lo[a]));
-              R2 += hx * hx;
-              D2 += mc[a] * mc[a];
-            }
-            a_node[pos] = node;
-            const float marg = 1e-5f * D2 + 1e-30f;
-            if (D2 - R2 <= marg) {
-              mask = (kn == 64) ? ~0ull : ((1ull << kn) - 1ull);
-            } else {
-              const float thr = D2 - R2 - marg;
-              for (int kq = 0; kq < kn; ++kq) {
-                const float nm = g_nf[kq][0] * mc[0] + g_nf[kq][1] * mc[1] + g_nf[kq][2] * mc[2];
-                if (nm > 0.0f && nm * nm >= thr) mask |= 1ull << kq;
+              for (int a = 0; a < 3; ++a) {
+                a_lo[pos][a] = lo[a];
+                a_hi[pos][a] = hi[a];
+                const float m = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
+                const float hx = (float)(0.5 * (hi[a] - lo[a]));
+                a_mc[pos][a] = m;
+                R2 += hx * hx;
+                D2 += m * m;
               }
+              a_node[pos] = node;
+              a_d2[pos] = D2;
+              a_r2[pos] = R2;
+              a_mask[pos] = 0ull;
             }
-          }
-          const uint32_t cntc = (uint32_t)__popcll(mask);
-          const uint32_t pre = wave_excl(cntc, lane);
-          const uint32_t C = wave_sum_u(cntc);
-          if (is) {
-            a_mask[pos] = mask;
-            a_pre[pos] = pre;
           }
           __syncthreads();
-          for (uint32_t g0 = 0; g0 < C; g0 += 64) {
-            const uint32_t gi = g0 + lane;
+          const int na = (int)wcnt[0];
+          {   // candidate rays: entry t%64, rays wv*16 .. wv*16+15
+            const int ej = t & 63;
+            if (ej < na) {
+              const float D2 = a_d2[ej], R2 = a_r2[ej];
+              const float marg = 1e-5f * D2 + 1e-30f;
+              unsigned long long part = 0ull;
+              const int ka = wv * 16, kb = min(kn, ka + 16);
+              if (D2 - R2 <= marg) {
+                for (int kq = ka; kq < kb; ++kq) part |= 1ull << kq;
+              } else {
+                const float thr = D2 - R2 - marg;
+                const float m0 = a_mc[ej][0], m1 = a_mc[ej][1], m2 = a_mc[ej][2];
+                for (int kq = ka; kq < kb; ++kq) {
+                  const float nm = g_nf[kq][0] * m0 + g_nf[kq][1] * m1 + g_nf[kq][2] * m2;
+                  if (nm > 0.0f && nm * nm >= thr) part |= 1ull << kq;
+                }
+              }
+              if (part) atomicOr(&a_mask[ej], part);
+            }
+          }
+          __syncthreads();
+          if (t < 64) {
+            const uint32_t cntc = (t < na) ? (uint32_t)__popcll(a_mask[t]) : 0u;
+            const uint32_t pre = wave_excl(cntc, t);
+            if (t < na) a_pre[t] = pre;
+            if (t == 63) cand_total = pre + cntc;
+          }
+          __syncthreads();
+          const uint32_t C = cand_total;
+          for (uint32_t g0 = 0; g0 < C; g0 += kFT) {
+            const uint32_t gi = g0 + (uint32_t)t;
             bool hit = false;
             double t0 = 0.0, t1 = 0.0;
             uint32_t hnode = 0;
@@ -1014,11 +1033,10 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
                 hnode = a_node[lo_j];
               }
             }
-            const uint64_t hm = ballot64(hit);
-            h_cnt[lane] = 0u;
-            __syncthreads();
+            if (t < 64) h_cnt[t] = 0u;
+            uint32_t nh;
+            const uint32_t hp = block_compact(hit, wcnt, &nh);
             if (hit) {
-              const int hp = mbcnt(hm);
               h_t0[hp] = t0;
               h_t1[hp] = t1;
               h_node[hp] = hnode;
@@ -1026,21 +1044,18 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
               atomicAdd(&h_cnt[kray], 1u);
             }
             __syncthreads();
-            {
-              const uint32_t v = h_cnt[lane];
-              const uint32_t ex = wave_excl(v, lane);
-              h_beg[lane] = ex;
-              if (lane == 63) h_beg[64] = ex + v;
-              h_cnt[lane] = ex;
+            if (t < 64) {
+              const uint32_t v = h_cnt[t];
+              const uint32_t ex = wave_excl(v, t);
+              h_beg[t] = ex;
+              if (t == 63) h_beg[64] = ex + v;
+              h_cnt[t] = ex;
             }
             __syncthreads();
-            if (hit) {
-              const int hp = mbcnt(hm);
-              h_ord[atomicAdd(&h_cnt[kray], 1u)] = (uint8_t)hp;
-            }
+            if (hit) h_ord[atomicAdd(&h_cnt[kray], 1u)] = (uint16_t)hp;
             __syncthreads();
-            if (rlane) {
-              for (uint32_t hq = h_beg[lane]; hq < h_beg[lane + 1]; ++hq) {
+            if (rt) {
+              for (uint32_t hq = h_beg[t]; hq < h_beg[t + 1]; ++hq) {
                 const int hi2 = h_ord[hq];
                 const double ht0 = h_t0[hi2], ht1 = h_t1[hi2];
                 const float len = (float)(ht1 - ht0);
@@ -1052,8 +1067,7 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
                   texl[b] += av[b] * len;
                 }
                 ++nabs;
-                // first source beyond t0 (sources sorted by s)
-                uint32_t lo_p = q0, hi_p = q1;
+                uint32_t lo_p = q0, hi_p = q1;     // first source beyond t0
                 while (lo_p < hi_p) {
                   const uint32_t mid = (lo_p + hi_p) >> 1;
                   if ((double)s_s[s_order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
@@ -1077,7 +1091,7 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
             __syncthreads();
           }
         }
-        if (rlane) {   // resolve the suffix adds along each ray
+        if (rt) {   // resolve the suffix adds along each ray
           float run[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) run[b] = 0.0f;
@@ -1089,74 +1103,73 @@ __global__ void __launch_bounds__(64) k_far(DevTree T, const uint32_t* blist, co
               s_tau[si][b] += run[b];
             }
           }
+#pragma unroll
+          for (int b = 0; b < NB; ++b) tex[t][b] = texl[b];
+          if (skip == 0 && first_chunk) atomicAdd(&abs_count, nabs);
         }
-        if (skip == 0 && first_chunk) nabs_total += wave_sum_u(nabs);
         __syncthreads();
 
         // ---- far sources at every receiver (Section 2.5.1, eq. intint)
-        for (uint32_t q = lane; q < nsg; q += 64) {
-          const float sx = s_rel[q][0], sy = s_rel[q][1], sz = s_rel[q][2];
-          const float ss = s_s[q];
-          const int ray = s_ray[q];
-          float tau[NB], Lv[NB];
+        if (has_i) {
+          const RecvInfo& ri = recv[my_i];
+          for (uint32_t q = (uint32_t)my_q; q < nsg; q += (uint32_t)per_round) {
+            const float dx = s_rel[q][0] - ri.rel[0];
+            const float dy = s_rel[q][1] - ri.rel[1];
+            const float dz = s_rel[q][2] - ri.rel[2];
+            const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
+            const float Kv = fshape(rr * ri.inv_rh) * ri.kfac;
+            const float ratio = rr * __builtin_amdgcn_rcpf(s_s[q]);
+            const int ray = s_ray[q];
 #pragma unroll
-          for (int b = 0; b < NB; ++b) { tau[b] = s_tau[q][b]; Lv[b] = s_L[q][b]; }
-#pragma unroll
-          for (int i = 0; i < kRMax; ++i) {
-            if (i < nrecv) {
-              const float dx = sx - recv[i].rel[0], dy = sy - recv[i].rel[1], dz = sz - recv[i].rel[2];
-              const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
-              const float Kv = fshape(rr * recv[i].inv_rh) * recv[i].kfac;
-              const float ratio = rr * __builtin_amdgcn_rcpf(ss);
-#pragma unroll
-              for (int b = 0; b < NB; ++b) {
-                const float tc = (tau[b] > 0.0f) ? tau[b] * ratio : 0.0f;
-                const float e = __expf(-(tpp[i][ray][b] + tc));
-                acc[i][b] += (double)(Lv[b] * Kv * e);
-              }
+            for (int b = 0; b < NB; ++b) {
+              const float tau = s_tau[q][b];
+              const float tc = (tau > 0.0f) ? tau * ratio : 0.0f;
+              const float e = __expf(-(tpp[my_i][ray][b] + tc));
+              acc[b] += (double)(s_L[q][b] * Kv * e);
             }
           }
-        }
-        // ---- isotropic background along each ray (to the root-cube edge)
-        if (use_bg && rlane && skip == 0) {
-#pragma unroll
-          for (int i = 0; i < kRMax; ++i)
-            if (i < nrecv)
+          // ---- isotropic background along each ray (to the root-cube edge)
+          if (use_bg && skip == 0) {
+            for (int kq = my_q; kq < kn; kq += per_round)
 #pragma unroll
               for (int b = 0; b < NB; ++b)
-                acc[i][b] += (4.0 * kPi / nray) * (double)bg[b] *
-                             (double)__expf(-(tpp[i][lane][b] + texl[b]));
+                acc[b] += (4.0 * kPi / nray) * (double)bg[b] *
+                          (double)__expf(-(tpp[my_i][kq][b] + tex[kq][b]));
+          }
         }
         __syncthreads();
         if (nsg_all <= skip + (uint32_t)kSrcCap) break;
       }
     }
 
-    // ---- reduce over lanes, add the p-p part, thick-element correction
+    // ---- per-receiver sums in a fixed order, add the p-p part, thick factor
 #pragma unroll
-    for (int i = 0; i < kRMax; ++i) {
-      if (i >= nrecv) continue;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const double v = wave_sum(acc[i][b]);
-        if (lane == b) {
-          const uint32_t s = recv[i].slot;
-          const int64_t o = (int64_t)b * n + T.perm[s];
-          double out = J[o] + v;
-          if (T.flags & TREVR_THICK_CORR) {
-            const double tau = (double)T.kappa[(int64_t)b * n + s] * (double)T.rho[s] * recv[i].h;
-            out *= (tau == 0.0) ? 1.0 : -expm1(-tau) / tau;
-          }
-          J[o] = out;
-        }
+    for (int b = 0; b < NB; ++b) {
+      double v = acc[b];
+      for (int o = 32; o >= P2 && o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane < P2 && lane < nrecv) red[wv][lane][b] = v;
+    }
+    __syncthreads();
+    if (t < nrecv * NB) {
+      const int i = t / NB, b = t % NB;
+      double v = 0.0;
+      for (int w = 0; w < kFT / 64; ++w) v += red[w][i][b];
+      const uint32_t sl = recv[i].slot;
+      const int64_t o = (int64_t)b * n + T.perm[sl];
+      double out = J[o] + v;
+      if (T.flags & TREVR_THICK_CORR) {
+        const double tau = (double)T.kappa[(int64_t)b * n + sl] * (double)T.rho[sl] * recv[i].h;
+        out *= (tau == 0.0) ? 1.0 : -expm1(-tau) / tau;
       }
+      J[o] = out;
     }
     rbase += (uint32_t)nrecv;
-    __syncthreads();
   }
 
-  if (lane == 0) {
+  __syncthreads();
+  if (t == 0) {
     const uint32_t nsrc = bstat[4 * bucket + 1], ncells = bstat[4 * bucket + 2];
+    const uint32_t nabs_total = abs_count;
     atomicAdd(&T.counters[CNT_BUCKETS], 1ull);
     atomicAdd(&T.counters[CNT_CELLS], (unsigned long long)ncells);
     atomicAdd(&T.counters[CNT_ABS], (unsigned long long)nabs_total);
@@ -1257,7 +1270,7 @@ static void launch_pair(const DevTree& D, const Scratch& S, uint32_t b0, uint32_
   if (*rc != TREVR_OK) return;
   prof_end(T, TREVR_PROF_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
-  k_far<NB><<<cnt, 64, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp, bg,
+  k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp, bg,
                                 J, active);
   *rc = hip_check(hipGetLastError(), "k_far");
   prof_end(T, TREVR_PROF_REDUCE, e1);
