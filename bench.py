@@ -51,6 +51,21 @@ def far_flops(c: dict, B: int) -> float:
     return c["src_pairs"] * (37 + 6 * B) + c["absorber_entries"] * (20 + 2 * B)
 
 
+def measured_traffic(kernel: str):
+    """HBM-side bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs (profiles/), or None when the kernel source
+    changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_clumpy2e18_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +74,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=0.05,
                     help="fraction of receivers the oracle evaluates for the CPU baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (a kernel of known "
+                         "traffic, for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU (this build has no multi-GPU path)",
@@ -79,6 +97,12 @@ def main():
     flags = api.THICK_CORR | api.NEAR_FIELD
     kw = dict(nside=sc.nside, leaf_size=sc.leaf_size, theta=sc.theta, flags=flags, box=sc.box)
     J = torch.zeros((B, n), dtype=torch.float64, device=dev)
+    if args.calibrate_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         T = api.Tree(x, y, z, m, rho, kappa, lum, **kw)
@@ -134,9 +158,10 @@ def main():
     flops = far_flops(counters, B) if kname == "reduce" else near_flops(counters, nray)
     per_launch = flops / max(red_calls / args.steps, 1)
     achieved = per_launch / (red_ms / max(red_calls, 1) * 1e-3) / 1e12
-    roofline = {"kernel": {"near": "k_nearfield", "reduce": "k_far"}[kname], "bound": "alu", "achieved": achieved,
+    roofline = {"kernel": {"near": "k_pp_rays+k_pp_src", "reduce": "k_far"}[kname], "bound": "alu",
+                "achieved": achieved,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": None,
+                "traffic": measured_traffic("k_far") if kname == "reduce" else None,
                 "launches_per_step": red_calls / args.steps,
                 "avg_launch_ms": red_ms / max(red_calls, 1),
                 "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}}
