@@ -2,10 +2,14 @@
 """Throughput of the TREVR2 hot path on one MI355X, in receiver-ray segments/s.
 
 A step is one pass of the whole path over one scene resident in HBM: build
-the radiation tree (Morton sort, topology, moments, transmission tables) and
-compute J at the active elements.  The segment count (per active element
-and ray: 1 + absorbing cells with a chord beyond r_pp + sources on the ray)
-is the library's counter, equal to the oracle's by test.
+the radiation tree (Morton sort, topology, moments, transmission tables),
+compute J at the active elements, and run the adjoint for a fixed seeded
+dE/dJ (gradients with respect to L, kappa and rho).  The segment count (per
+active element and ray: 1 + absorbing cells with a chord beyond r_pp +
+sources on the ray) is the library's counter, equal to the oracle's by
+test; `value` is segments per step over the step time (build + forward +
+adjoint), and the forward alone and forward + adjoint on a resident tree
+are reported beside it.
 
 Workload: the clumpy medium -- 2^18 elements drawn from a log-normal density
 field (P(k) ~ k^-3, sigma_ln rho = 1.5), 10% sources with log-normal
@@ -49,6 +53,15 @@ def near_flops(c: dict, nray: int) -> float:
 
 def far_flops(c: dict, B: int) -> float:
     return c["src_pairs"] * (37 + 6 * B) + c["absorber_entries"] * (20 + 2 * B)
+
+
+def far_adjoint_flops(c: dict, B: int) -> float:
+    """Arithmetic of the far-field adjoint kernel: per (receiver, source
+    entry) the forward term (37 + 6B) plus its derivatives (intensity-kernel
+    slope 14, dK/dr and dK/dh 6, position 4, 13 per band); per (bucket,
+    absorber entry) two sweeps of the hit arithmetic (2 x (20 + 2B)) and the
+    cell-absorption adjoint (4B)."""
+    return c["src_pairs"] * (61 + 19 * B) + c["absorber_entries"] * (40 + 8 * B)
 
 
 def measured_traffic(kernel: str):
@@ -97,6 +110,10 @@ def main():
     flags = api.THICK_CORR | api.NEAR_FIELD
     kw = dict(nside=sc.nside, leaf_size=sc.leaf_size, theta=sc.theta, flags=flags, box=sc.box)
     J = torch.zeros((B, n), dtype=torch.float64, device=dev)
+    gJ = torch.as_tensor(np.random.default_rng(7).normal(size=(B, n)), device=dev)
+    grads = (torch.empty((B, n), dtype=torch.float64, device=dev),
+             torch.empty((B, n), dtype=torch.float64, device=dev),
+             torch.empty((n,), dtype=torch.float64, device=dev))
     if args.calibrate_copy:
         src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -107,16 +124,13 @@ def main():
     def step():
         T = api.Tree(x, y, z, m, rho, kappa, lum, **kw)
         T.compute_J(active, None, out=J)
+        T.compute_J_backward(gJ, active, None, out=grads)
         return T
 
     # warm-up (also sizes the scratch buffer once)
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         T = step()
         T.check()
-        counters = T.counters()
-        T.close()
-    if args.warmup == 0:
-        T = step()
         counters = T.counters()
         T.close()
     seg = counters["segments"]
@@ -130,9 +144,11 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
 
-    # forward alone on a resident tree, and per-kernel HIP event timing
+    # forward alone and forward + adjoint on a resident tree, with per-phase
+    # HIP event timing recorded by the library on its stream
     T = api.Tree(x, y, z, m, rho, kappa, lum, **kw)
     T.compute_J(active, None, out=J)
+    T.compute_J_backward(gJ, active, None, out=grads)
     T.profile(True)
     torch.cuda.synchronize()
     f0 = time.perf_counter()
@@ -140,9 +156,19 @@ def main():
         T.compute_J(active, None, out=J)
     torch.cuda.synchronize()
     f1 = time.perf_counter()
+    prof_fwd = T.profile_read()
+    T.profile(True)
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    for _ in range(args.steps):
+        T.compute_J(active, None, out=J)
+        T.compute_J_backward(gJ, active, None, out=grads)
+    torch.cuda.synchronize()
+    a1 = time.perf_counter()
     prof = T.profile_read()
     T.check()
     ms_fwd = (f1 - f0) * 1e3 / args.steps
+    ms_fwd_adj = (a1 - a0) * 1e3 / args.steps
     T.close()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -152,19 +178,23 @@ def main():
     ms_build = ev0.elapsed_time(ev1)
     T.close()
 
-    # the dominant kernel by time
-    kname, (red_ms, red_calls) = max(((k, v) for k, v in prof.items() if k in ("near", "reduce")),
-                                     key=lambda kv: kv[1][0])
-    flops = far_flops(counters, B) if kname == "reduce" else near_flops(counters, nray)
+    # the dominant single kernel of a step: the far-field reduction or its
+    # adjoint (the p-p phases are two kernels each and shorter)
+    kname = max(("reduce", "adj_reduce"), key=lambda k: prof[k][0])
+    red_ms, red_calls = prof[kname]
+    flops = far_flops(counters, B) if kname == "reduce" else far_adjoint_flops(counters, B)
     per_launch = flops / max(red_calls / args.steps, 1)
     achieved = per_launch / (red_ms / max(red_calls, 1) * 1e-3) / 1e12
-    roofline = {"kernel": {"near": "k_pp_rays+k_pp_src", "reduce": "k_far"}[kname], "bound": "alu",
+    kernel = {"reduce": "k_far", "adj_reduce": "k_far_bwd"}[kname]
+    roofline = {"kernel": kernel, "bound": "alu",
                 "achieved": achieved,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": measured_traffic("k_far") if kname == "reduce" else None,
+                "traffic": measured_traffic(kernel),
                 "launches_per_step": red_calls / args.steps,
                 "avg_launch_ms": red_ms / max(red_calls, 1),
-                "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}}
+                "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+                "fwd_kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_fwd.items()
+                                           if v[1]}}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -202,7 +232,8 @@ def main():
                                "all active",
                    "n": n, "bands": B, "nside": sc.nside, "active": int(sc.active.sum()),
                    "segments_per_step": seg},
-        "fwd_only": {"value": seg / (ms_fwd * 1e-3), "ms": ms_fwd},
+        "fwd": {"value": seg / (ms_fwd * 1e-3), "ms": ms_fwd},
+        "fwd_adjoint": {"value": seg / (ms_fwd_adj * 1e-3), "ms": ms_fwd_adj},
         "build_ms": ms_build,
         "roofline": roofline,
         "cpu_baseline": cpu,

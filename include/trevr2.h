@@ -135,7 +135,35 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
 trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* bg, double* J,
                              void* scratch, size_t scratch_bytes, void* stream);
 
-/* Scratch bytes the last compute_J on this tree needed (0 before any). */
+/*
+ * Adjoint of trevr_compute_J (reverse-mode derivative; not in the paper,
+ * which defines only the forward map of Sections 2.1-2.6).  Given
+ * gJ = dE/dJ for a scalar objective E of the J that trevr_compute_J returns
+ * with the same active set and bg, writes
+ *   gL     : double [n_bands][n]  dE/dL     (input order, every row written)
+ *   gkappa : double [n_bands][n]  dE/dkappa
+ *   grho   : double [n]           dE/drho   (through h = (m/rho)^(1/3), the
+ *                                 bucket absorption, the columns and the
+ *                                 thick-element factor)
+ * The derivative is that of the piecewise-smooth map with every discrete
+ * decision held at its value: tree, opening tests, pixel of each source,
+ * p-p sets, the element whose size sets each p-p radius, ray-cell hits.
+ * Positions and masses are not differentiated.
+ *   gJ     : double [n_bands][n] (device), rows of inactive elements ignored.
+ * Repeats the forward's setup, walk and p-p columns (the tree is not
+ * changed), synchronises `stream` once, and needs more scratch than
+ * compute_J (accumulators per node, class and band, and a second p-p column
+ * buffer): on TREVR_E_CAPACITY trevr_scratch_needed gives the size.
+ * Partial sums are formed with atomics (FP32 in LDS, FP64 in device memory),
+ * so repeated calls agree to FP32 rounding of those sums, not bit for bit.
+ */
+trevr_status trevr_compute_J_backward(trevr_tree* t, const uint8_t* active, const float* bg,
+                                      const double* gJ, double* gL, double* gkappa,
+                                      double* grho, void* scratch, size_t scratch_bytes,
+                                      void* stream);
+
+/* Scratch bytes the last compute_J or compute_J_backward on this tree needed
+ * (0 before any). */
 trevr_status trevr_scratch_needed(const trevr_tree* t, size_t* bytes);
 
 /* Counters of the last compute_J (synchronises the tree's stream). */
@@ -178,11 +206,17 @@ trevr_status trevr_tree_export(trevr_tree* t, int64_t* perm, int64_t* ints, doub
  *   ms[TREVR_PROF_WALK]   tree walks (cut lists)
  *   ms[TREVR_PROF_REDUCE] far-field ray reduction and final J
  *   ms[TREVR_PROF_NEAR]   particle-particle transfer
- * with launches[] the number of timed launches of each.  Totals accumulate
- * from the last enable; `on` = 0 stops recording.
+ *   ms[TREVR_PROF_ADJ_REDUCE] adjoint of the far-field reduction
+ *   ms[TREVR_PROF_ADJ_NEAR]   adjoint of the particle-particle transfer
+ *   ms[TREVR_PROF_ADJ_TREE]   adjoint of the p-p radii and of the tree
+ *                             moments, gradients to input order
+ * (compute_J_backward also records SETUP, WALK and NEAR for the forward
+ * steps it repeats), with launches[] the number of timed launches of each.
+ * Totals accumulate from the last enable; `on` = 0 stops recording.
  */
 enum { TREVR_PROF_SETUP = 0, TREVR_PROF_WALK = 1, TREVR_PROF_REDUCE = 2, TREVR_PROF_NEAR = 3,
-       TREVR_PROF_SLOTS = 4 };
+       TREVR_PROF_ADJ_REDUCE = 4, TREVR_PROF_ADJ_NEAR = 5, TREVR_PROF_ADJ_TREE = 6,
+       TREVR_PROF_SLOTS = 7 };
 trevr_status trevr_profile_enable(trevr_tree* t, int on);
 trevr_status trevr_profile_read(trevr_tree* t, double* ms, int64_t* launches);
 

@@ -21,10 +21,12 @@ OK, E_INVALID, E_CAPACITY, E_HIP, E_STATE, E_DATA = range(6)
 THICK_CORR, NEAR_FIELD, BACKGROUND = 1, 2, 4
 
 EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
+            "trevr_compute_J_backward",
             "trevr_scratch_needed", "trevr_get_counters", "trevr_check", "trevr_tree_destroy",
             "trevr_tree_info", "trevr_tree_export", "trevr_profile_enable",
             "trevr_profile_read", "trevr_status_string", "trevr_last_error")
-PROF_SETUP, PROF_WALK, PROF_REDUCE, PROF_NEAR, PROF_SLOTS = 0, 1, 2, 3, 4
+PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree")
+PROF_SLOTS = len(PROF_NAMES)
 
 
 class TrevrError(RuntimeError):
@@ -63,6 +65,7 @@ def lib():
         L.trevr_build_tree.argtypes = [ctypes.POINTER(Params), i64] + [vp] * 8 + [sz, vp,
                                                                                    ctypes.POINTER(vp)]
         L.trevr_compute_J.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        L.trevr_compute_J_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.trevr_scratch_needed.argtypes = [vp, ctypes.POINTER(sz)]
         L.trevr_get_counters.argtypes = [vp, ctypes.POINTER(Counters)]
         L.trevr_check.argtypes = [vp]
@@ -164,10 +167,17 @@ class Tree:
             out = torch.zeros((self.B, self.n), dtype=torch.float64, device=self.device)
         a = None if active is None else _dev(active, torch.uint8)
         g = None if bg is None else _dev(bg, torch.float32)
+        self._call_with_scratch(
+            lambda sp, sb: lib().trevr_compute_J(self.handle, a, g, _dev(out, torch.float64), sp,
+                                                 sb, _stream_ptr()), "trevr_compute_J")
+        return out
+
+    def _call_with_scratch(self, fn, where):
+        """Run fn(scratch_ptr, scratch_bytes); on TREVR_E_CAPACITY grow the
+        scratch to the size the library reports and run once more."""
+        torch = _torch()
         for _ in range(2):
-            st = lib().trevr_compute_J(self.handle, a, g, _dev(out, torch.float64),
-                                       ctypes.c_void_p(self._scratch.data_ptr()),
-                                       self._scratch.numel(), _stream_ptr())
+            st = fn(ctypes.c_void_p(self._scratch.data_ptr()), self._scratch.numel())
             if st != E_CAPACITY:
                 break
             need = ctypes.c_size_t()
@@ -177,8 +187,25 @@ class Tree:
                 break
             self._scratch = torch.empty(int(need.value * 1.1) + 4096, dtype=torch.uint8,
                                         device=self.device)
-        _check(st, "trevr_compute_J")
-        return out
+        _check(st, where)
+
+    def compute_J_backward(self, gJ, active=None, bg=None, out=None):
+        """Adjoint of compute_J: (dE/dL [B, n], dE/dkappa [B, n], dE/drho [n])
+        as float64 device tensors, given gJ = dE/dJ [B, n] float64."""
+        torch = _torch()
+        if out is None:
+            out = (torch.empty((self.B, self.n), dtype=torch.float64, device=self.device),
+                   torch.empty((self.B, self.n), dtype=torch.float64, device=self.device),
+                   torch.empty((self.n,), dtype=torch.float64, device=self.device))
+        gL, gk, gr = out
+        a = None if active is None else _dev(active, torch.uint8)
+        g = None if bg is None else _dev(bg, torch.float32)
+        f64 = torch.float64
+        self._call_with_scratch(
+            lambda sp, sb: lib().trevr_compute_J_backward(
+                self.handle, a, g, _dev(gJ, f64), _dev(gL, f64), _dev(gk, f64), _dev(gr, f64),
+                sp, sb, _stream_ptr()), "trevr_compute_J_backward")
+        return gL, gk, gr
 
     def check(self):
         _check(lib().trevr_check(self.handle), "trevr_check")
@@ -197,8 +224,7 @@ class Tree:
         _check(lib().trevr_profile_read(self.handle, ms.ctypes.data_as(ctypes.c_void_p),
                                         calls.ctypes.data_as(ctypes.c_void_p)),
                "trevr_profile_read")
-        names = ("setup", "walk", "reduce", "near")
-        return {nm: (float(ms[i]), int(calls[i])) for i, nm in enumerate(names)}
+        return {nm: (float(ms[i]), int(calls[i])) for i, nm in enumerate(PROF_NAMES)}
 
     def info(self):
         nn, nc, dp = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
@@ -254,3 +280,58 @@ def compute_J(scene, active=None, device="cuda"):
     cnt = T.counters()
     T.close()
     return out, cnt
+
+
+def compute_J_backward(scene, gJ, active=None, device="cuda"):
+    """Build the tree of a scene, run the adjoint of compute_J for
+    gJ = dE/dJ [B, n]; returns numpy (gL [B, n], gkappa [B, n], grho [n])."""
+    torch = _torch()
+    T = Tree.from_scene(scene, device=device)
+    act = scene.active if active is None else active
+    a = None if act is None else torch.as_tensor(np.ascontiguousarray(act, np.uint8), device=device)
+    bg = None
+    if scene.background and scene.bg is not None:
+        bg = torch.as_tensor(np.ascontiguousarray(scene.bg, np.float32), device=device)
+    g = torch.as_tensor(np.ascontiguousarray(gJ, np.float64), device=device)
+    gL, gk, gr = T.compute_J_backward(g, a, bg)
+    T.check()
+    out = (gL.cpu().numpy(), gk.cpu().numpy(), gr.cpu().numpy())
+    T.close()
+    return out
+
+class TrevrJ:
+    """J as a differentiable torch function of (kappa, lum, rho).
+
+    ``TrevrJ.apply(x, y, z, m, rho, kappa, lum, active, bg, opts)`` builds the
+    tree and returns J [B, n] (float64).  The backward pass calls
+    trevr_compute_J_backward on the same tree; positions, masses, the active
+    set and bg get no gradient.  ``opts`` holds the Tree keyword arguments
+    (nside, leaf_size, theta, flags, rpp_min, box)."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, *args):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, x, y, z, m, rho, kappa, lum, active, bg, opts):
+                    T = Tree(x.detach(), y.detach(), z.detach(), m.detach(), rho.detach(),
+                             kappa.detach(), lum.detach(), **opts)
+                    J = T.compute_J(active, bg)
+                    ctx.tree, ctx.active, ctx.bg = T, active, bg
+                    ctx.dtypes = (rho.dtype, kappa.dtype, lum.dtype)
+                    return J
+
+                @staticmethod
+                def backward(ctx, gJ):
+                    gL, gk, gr = ctx.tree.compute_J_backward(gJ.contiguous().to(torch.float64),
+                                                             ctx.active, ctx.bg)
+                    dr, dk, dl = ctx.dtypes
+                    return (None, None, None, None, gr.to(dr), gk.to(dk), gL.to(dl), None, None,
+                            None)
+
+            cls._fn = _F
+        return cls._fn.apply(*args)

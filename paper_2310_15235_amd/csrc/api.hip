@@ -216,6 +216,19 @@ trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* 
   return compute_J_impl(t, active, bg, J, scratch, scratch_bytes);
 }
 
+trevr_status trevr_compute_J_backward(trevr_tree* t, const uint8_t* active, const float* bg,
+                                      const double* gJ, double* gL, double* gkappa,
+                                      double* grho, void* scratch, size_t scratch_bytes,
+                                      void* stream) {
+  if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
+  if (!gJ || !gL || !gkappa || !grho || !scratch)
+    return set_error(TREVR_E_INVALID, "NULL gradient or scratch pointer");
+  if ((t->p.flags & TREVR_BACKGROUND) && !bg)
+    return set_error(TREVR_E_INVALID, "TREVR_BACKGROUND needs bg");
+  t->stream = (hipStream_t)stream;
+  return compute_J_backward_impl(t, active, bg, gJ, gL, gkappa, grho, scratch, scratch_bytes);
+}
+
 trevr_status trevr_scratch_needed(const trevr_tree* t, size_t* bytes) {
   if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
   if (!bytes) return set_error(TREVR_E_INVALID, "NULL output");

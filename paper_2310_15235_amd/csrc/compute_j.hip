@@ -30,24 +30,10 @@
 #include <algorithm>
 #include <cmath>
 
-#include "trevr_internal.hpp"
+#include "path_device.hpp"
+#include "path_host.hpp"
 
 namespace trevr {
-
-constexpr int kRMax = 8;         // receivers per pass
-constexpr int kStackCap = 4096;  // traversal stack entries (LDS)
-constexpr uint32_t kCutCap = 2048;
-constexpr uint32_t kBatch = 65536;   // buckets per launch (bounds the cut-list scratch)
-constexpr int kCostBins = 48;
-constexpr int kNT = 256;         // threads of the near-field kernel
-constexpr int kNChunk = 256;     // p-p elements staged per pass
-constexpr int kNPair = 2;        // (receiver, p-p source) pairs per thread per pass
-constexpr int kRayPer = 2;       // rays per thread in the p-p column pass
-constexpr double kR = 0.48860251190291992;   // (3/(4 pi))^(1/2)
-
-__device__ inline void atomic_max_u64(unsigned long long* a, unsigned long long v) {
-  atomicMax(a, v);
-}
 
 // ------------------------------------------------------ active buckets
 __global__ void k_active_buckets(DevTree T, const uint8_t* active, uint32_t* blist,
@@ -63,117 +49,6 @@ __global__ void k_active_buckets(DevTree T, const uint8_t* active, uint32_t* bli
   const uint32_t b = atomicAdd(nb, 1u);
   blist[b] = (uint32_t)p;
   bnact[b] = cnt;
-}
-
-__device__ inline void leaf_centre(const DevTree& T, uint32_t leaf, double c[3]) {
-  double lo[3], hi[3];
-  node_box(T.hdr, T.nk[leaf], lo, hi);
-  for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
-}
-
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ inline uint32_t wave_sum_u(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
-  return v;
-}
-// exclusive prefix sum over the wavefront
-__device__ inline uint32_t wave_excl(uint32_t v, int lane) {
-  uint32_t incl = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t u = (uint32_t)__shfl_up((int)incl, o);
-    if (lane >= o) incl += u;
-  }
-  return incl - v;
-}
-
-// Range query by one wavefront: elements strictly within sqrt(r2) of c.
-// Returns the count; *hmax gets their largest size, *nlum the number that
-// emit.  With `out`, writes their sorted slots: luminous ones from out[0],
-// the others from out[lum_total].  Boxes are pruned conservatively (an
-// element can sit an ulp outside its box after quantisation); membership is
-// the exact test.  The traversal stack lives in `stack` (kStackCap words).
-__device__ uint32_t wave_near(const DevTree& T, const double c[3], double r2, uint32_t* stack,
-                              double* hmax, uint32_t* nlum, uint32_t* out, uint32_t lum_total,
-                              bool* overflow) {
-  const int lane = threadIdx.x & 63;
-  const double prune = r2 * (1.0 + 1e-9);
-  uint32_t cnt = 0, lum = 0;
-  double hm = 0.0;
-  int sp = 1;
-  if (lane == 0) stack[0] = 0u;
-  __syncthreads();
-  while (sp > 0) {
-    const int take = min(sp, 64);
-    sp -= take;
-    const bool valid = lane < take;
-    const uint32_t node = valid ? stack[sp + lane] : 0u;
-    __syncthreads();
-    bool push = false;
-    uint32_t mine = 0, mylum = 0;
-    uint2 lk = make_uint2(0, 0);
-    bool isleaf = false;
-    if (valid) {
-      const uint4 nk = T.nk[node];
-      double lo[3], hi[3];
-      node_box(T.hdr, nk, lo, hi);
-      if (!(dist2_box(lo, hi, c) > prune)) {
-        isleaf = (nk.w & META_LEAF) != 0u;
-        lk = T.nlink[node];
-        push = !isleaf;
-        if (isleaf) {
-          for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
-            if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
-              ++mine;
-              hm = fmax(hm, T.h[s]);
-              if (T.lbol[s] > 0.0) ++mylum;
-            }
-          }
-        }
-      }
-    }
-    if (out) {
-      const uint32_t lbase = lum + wave_excl(mylum, lane);
-      const uint32_t dbase = lum_total + (cnt - lum) + wave_excl(mine - mylum, lane);
-      if (isleaf && mine) {
-        uint32_t a = 0, b = 0;
-        for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
-          if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
-            if (T.lbol[s] > 0.0) out[lbase + a++] = s;
-            else out[dbase + b++] = s;
-          }
-        }
-      }
-    }
-    cnt += wave_sum_u(mine);
-    lum += wave_sum_u(mylum);
-    const uint64_t pm = ballot64(push);
-    const int npush = __popcll(pm);
-    if (sp + 2 * npush > kStackCap) {
-      *overflow = true;
-      break;
-    }
-    if (push) {
-      const int ppos = mbcnt(pm);
-      stack[sp + 2 * ppos] = lk.x;          // child 1
-      stack[sp + 2 * ppos + 1] = node + 1u; // child 0
-    }
-    sp += 2 * npush;
-    __syncthreads();
-  }
-  if (hmax) *hmax = wave_max(hm);
-  if (nlum) *nlum = lum;
-  return cnt;
 }
 
 // p-p radius (Section 2.4): past every bucket member by its size, then grown
@@ -227,27 +102,6 @@ __global__ void __launch_bounds__(64) k_near_fill(DevTree T, const uint32_t* bli
   const double r = brad[b];
   bool overflow = false;
   wave_near(T, c, r * r, stack, nullptr, nullptr, nidx + noff[b], nlumc[b], &overflow);
-}
-
-// Opening criterion (Section 2.5.2): open if the cell reaches into the p-p
-// sphere or B/d > theta (d to the nearest point of the cell, B from the
-// luminosity centre to the farthest corner), compared as squares.
-__device__ inline bool open_cell(const double lo[3], const double hi[3], const double cn[3],
-                                 const double c[3], double r2, double theta2) {
-  const double d2 = dist2_box(lo, hi, c);
-  double e[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double u = cn[a] - lo[a], w = hi[a] - cn[a];
-    e[a] = fmax(u * u, w * w);
-  }
-  const double B2 = e[0] + e[1] + e[2];
-  return (d2 < r2) || (B2 > theta2 * d2);
-}
-
-__device__ inline uint32_t source_pixel(int nside, double vx, double vy, double vz) {
-  if (vx == 0.0 && vy == 0.0 && vz == 0.0) return 0u;
-  return (uint32_t)healpix_pixel(nside, vx, vy, vz);
 }
 
 // ------------------------------------------------------------- the walk
@@ -363,144 +217,6 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
     if (ncut > kCutCap) atomicOr(T.err, ERR_CUT);
     atomic_max_u64(&T.counters[CNT_MAX_CUT], ncut);
   }
-}
-
-// ------------------------------------------------- element intensity kernel
-// Shape f(x) of the element-averaged intensity, x = r/(R h), R = (3/4pi)^(1/2)
-// (Section 2.2, eq. intint): 1 + (1-x^2) atanh(x)/x below 1, 1 - (x^2-1)
-// atanh(1/x)/x above, and for x >= 2 the series sum 2 x^-2k/(4k^2-1).
-__device__ inline float fshape(float x) {
-  if (x < 1.0f) {
-    if (x == 0.0f) return 2.0f;
-    const float at = 0.5f * log1pf(2.0f * x / (1.0f - x));
-    return 1.0f + (1.0f - x) * (1.0f + x) * at / x;
-  }
-  if (x < 2.0f) {
-    if (x == 1.0f) return 1.0f;
-    const float at = 0.5f * logf((x + 1.0f) / (x - 1.0f));
-    return 1.0f - (x - 1.0f) * (x + 1.0f) * at / x;
-  }
-  const float y2 = __builtin_amdgcn_rcpf(x * x);
-  float s = 2.0f / 483.0f;
-  s = __builtin_fmaf(s, y2, 2.0f / 399.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 323.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 255.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 195.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 143.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 99.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 63.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 35.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 15.0f);
-  s = __builtin_fmaf(s, y2, 2.0f / 3.0f);
-  return s * y2;
-}
-
-
-struct RecvInfo {
-  double x[3];
-  double h;
-  float rel[3];    // position relative to the bucket centre
-  float inv_rh;    // 1/(R h)
-  float kfac;      // 1/(2 h^2)
-  uint32_t slot;
-};
-
-// ------------------------------------------------------------ near field
-// Particle-particle transfer inside the p-p sphere (Section 2.4), in two
-// kernels of 256 threads per bucket that stage the p-p set through LDS
-// kNChunk elements at a time.  Elements are culled kSub at a time with FP32
-// boxes (each element's position grown by its own size h, plus a margin),
-// which is conservative: an element can only absorb on a line that passes
-// within h of it.  Threads are mapped receiver-fastest, so the lines of a
-// wavefront are nearly parallel and skip the same boxes.
-constexpr int kSub = 16;
-constexpr int kNSub = kNChunk / kSub;
-
-template <int NB> struct NearTile {
-  double x[kNChunk], y[kNChunk], z[kNChunk], h2[kNChunk];
-  float sig[kNChunk], invh[kNChunk];
-  float kap[kNChunk][NB];
-  uint32_t slot[kNChunk];
-  float blo[kNSub][3], bhi[kNSub][3];
-};
-
-template <int NB>
-__device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint32_t* near,
-                                  uint32_t c0, uint32_t cl, const double c[3]) {
-  const int t = threadIdx.x;
-  __syncthreads();
-  if ((uint32_t)t < cl) {
-    const uint32_t l = near[c0 + t];
-    const double hl = T.h[l];
-    S.x[t] = (double)T.x[l];
-    S.y[t] = (double)T.y[l];
-    S.z[t] = (double)T.z[l];
-    S.h2[t] = hl * hl;
-    S.sig[t] = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-    S.invh[t] = (float)(1.0 / hl);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) S.kap[t][b] = T.kappa[(int64_t)b * T.n + l];
-    S.slot[t] = l;
-  }
-  __syncthreads();
-  if (t < kNSub) {
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    const int u1 = min((int)cl, (t + 1) * kSub);
-    for (int u = t * kSub; u < u1; ++u) {
-      const float h = sqrtf((float)S.h2[u]);
-      const float p[3] = {(float)(S.x[u] - c[0]), (float)(S.y[u] - c[1]), (float)(S.z[u] - c[2])};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float m = h + 1e-5f * (fabsf(p[a]) + h);
-        lo[a] = fminf(lo[a], p[a] - m);
-        hi[a] = fmaxf(hi[a], p[a] + m);
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { S.blo[t][a] = lo[a]; S.bhi[t][a] = hi[a]; }
-  }
-  __syncthreads();
-}
-
-// Next chunk of active bucket members (thread 0 keeps the cursor).
-__device__ inline int load_receivers(const DevTree& T, const uint8_t* active, const double c[3],
-                                     uint32_t& member, uint32_t mend, RecvInfo* recv,
-                                     uint32_t* nrecv_s) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t k = 0;
-    while (member < mend && k < (uint32_t)kRMax) {
-      const uint32_t s = member++;
-      if (active == nullptr || active[T.perm[s]]) {
-        RecvInfo ri;
-        ri.x[0] = (double)T.x[s];
-        ri.x[1] = (double)T.y[s];
-        ri.x[2] = (double)T.z[s];
-        ri.h = T.h[s];
-        for (int a = 0; a < 3; ++a) ri.rel[a] = (float)(ri.x[a] - c[a]);
-        ri.inv_rh = (float)(1.0 / (kR * ri.h));
-        ri.kfac = (float)(1.0 / (2.0 * ri.h * ri.h));
-        ri.slot = s;
-        recv[k++] = ri;
-      }
-    }
-    *nrecv_s = k;
-  }
-  __syncthreads();
-  return (int)*nrecv_s;
-}
-
-// FP32 ray-box test on the half line o + t n, t >= 0 (inv = 1/n, +-huge for 0).
-__device__ inline bool ray_meets_box(const float o[3], const float inv[3], const float lo[3],
-                                     const float hi[3]) {
-  float tin = 0.0f, tout = INFINITY;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float t1 = (lo[a] - o[a]) * inv[a], t2 = (hi[a] - o[a]) * inv[a];
-    tin = fmaxf(tin, fminf(t1, t2));
-    tout = fminf(tout, fmaxf(t1, t2));
-  }
-  return tin <= tout;
 }
 
 // For each receiver i and ray k: the optical depth of the p-p elements ahead
@@ -736,27 +452,6 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
 // buckets need it).  Receivers are fixed per thread (t mod P2, P2 the power
 // of two >= the receiver count), so each thread keeps one FP64 accumulator
 // per band, reduced per receiver in a fixed order at the end.
-constexpr int kFT = 256;
-template <int NB> struct SrcCap { static constexpr int value = NB <= 4 ? 512 : 256; };
-
-// Block-wide compaction: position of this thread's item among the set ones
-// (in thread order) and the block total.  Uses wcnt[4] in LDS; two barriers.
-__device__ inline uint32_t block_compact(bool pred, uint32_t* wcnt, uint32_t* total) {
-  const int t = threadIdx.x, wv = t >> 6;
-  const uint64_t m = ballot64(pred);
-  if ((t & 63) == 0) wcnt[wv] = (uint32_t)__popcll(m);
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kFT / 64; ++w) {
-    if (w < wv) base += wcnt[w];
-    tot += wcnt[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return base + (uint32_t)mbcnt(m);
-}
-
 template <int NB>
 __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, const double* brad,
                                              const uint32_t* roff, uint32_t b0, uint32_t nbuck,
@@ -768,28 +463,13 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
   if (bucket >= nbuck) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
-  __shared__ float s_rel[kSrcCap][3];
-  __shared__ float s_s[kSrcCap];
-  __shared__ float s_tau[kSrcCap][NB];
-  __shared__ float s_sfx[kSrcCap][NB];
-  __shared__ float s_L[kSrcCap][NB];
-  __shared__ uint8_t s_ray[kSrcCap];
-  __shared__ uint16_t s_order[kSrcCap];
-  __shared__ uint32_t ray_beg[65], ray_fill[64];
+  __shared__ SrcWindow<kSrcCap, NB> W;
+  __shared__ RayGroup G;
+  __shared__ HitLds H;
   __shared__ float tpp[kRMax][64][NB];
   __shared__ float tex[64][NB];
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nrecv_s, wcnt[kFT / 64], abs_count, cand_total;
-  __shared__ double a_lo[64][3], a_hi[64][3];
-  __shared__ float a_mc[64][3], a_d2[64], a_r2[64];
-  __shared__ uint32_t a_node[64], a_pre[64];
-  __shared__ unsigned long long a_mask[64];
-  __shared__ double g_n[64][3], g_inv[64][3];
-  __shared__ float g_nf[64][3];
-  __shared__ double h_t0[kFT], h_t1[kFT];
-  __shared__ uint32_t h_node[kFT], h_cnt[64], h_beg[65];
-  __shared__ uint8_t h_ray[kFT];
-  __shared__ uint16_t h_ord[kFT];
+  __shared__ uint32_t nrecv_s, wcnt[kFT / 64], abs_count;
   __shared__ double red[kFT / 64][kRMax][NB];
 
   const uint32_t leafb = blist[bucket];
@@ -827,18 +507,8 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
       const int k0 = 64 * g;
       const int kn = min(64, nray - k0);
       const bool rt = t < kn;                  // ray-owning thread
-      int cls = 0;
-      if (rt) {
-        const int k = k0 + t;
-        cls = T.ray_class[k];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const double na = T.ray_n[3 * k + a];
-          g_n[t][a] = na;
-          g_inv[t][a] = (na != 0.0) ? 1.0 / na : 0.0;
-          g_nf[t][a] = (float)na;
-        }
-      }
+      const int cls = rt ? T.ray_class[k0 + t] : 0;
+      load_ray_group(T, k0, kn, G);
       for (int q = t; q < nrecv * kn; q += kFT) {
         const int i = q / kn, kq = q % kn;
 #pragma unroll
@@ -847,260 +517,61 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
       }
 
       for (uint32_t skip = 0;; skip += (uint32_t)kSrcCap) {
-        // ---- sources whose pixel is in this group, window [skip, skip + cap)
-        uint32_t nsg_all = 0;
-        for (uint32_t e0 = 0; e0 < ncut; e0 += kFT) {
-          const uint32_t e = e0 + (uint32_t)t;
-          bool mine = false;
-          uint2 ent = make_uint2(0, 0);
-          uint32_t pix = CUT_NOPIX;
-          if (e < ncut) {
-            ent = mycut[e];
-            pix = ent.y & 0xFFFFu;
-            mine = pix != CUT_NOPIX && (int)pix >= k0 && (int)pix < k0 + kn;
-          }
-          uint32_t tot;
-          const uint32_t gi = nsg_all + block_compact(mine, wcnt, &tot);
-          if (mine && gi >= skip && gi < skip + (uint32_t)kSrcCap) {
-            const uint32_t slot = gi - skip;
-            double p[3];
-            float Lv[NB];
-            if ((ent.y & CUT_KIND_MASK) == CUT_PART) {
-              p[0] = (double)T.x[ent.x];
-              p[1] = (double)T.y[ent.x];
-              p[2] = (double)T.z[ent.x];
-#pragma unroll
-              for (int b = 0; b < NB; ++b) Lv[b] = T.lum[(int64_t)b * n + ent.x];
-            } else {
-              const double4 cn = T.cen[ent.x];
-              p[0] = cn.x;
-              p[1] = cn.y;
-              p[2] = cn.z;
-#pragma unroll
-              for (int b = 0; b < NB; ++b) Lv[b] = (float)T.Lb[(int64_t)ent.x * NB + b];
-            }
-            const double v0 = p[0] - c[0], v1 = p[1] - c[1], v2 = p[2] - c[2];
-            double sd = 0.0;
-            if (!(v0 == 0.0 && v1 == 0.0 && v2 == 0.0)) {
-              const double* nn = &T.ray_n[3 * pix];
-              sd = v0 * nn[0] + v1 * nn[1] + v2 * nn[2];
-            }
-            s_rel[slot][0] = (float)v0;
-            s_rel[slot][1] = (float)v1;
-            s_rel[slot][2] = (float)v2;
-            s_s[slot] = (float)sd;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              s_L[slot][b] = Lv[b];
-              s_tau[slot][b] = 0.0f;
-              s_sfx[slot][b] = 0.0f;
-            }
-            s_ray[slot] = (uint8_t)(pix - k0);
-          }
-          nsg_all += tot;
-        }
+        const uint32_t nsg_all =
+            stage_window<kSrcCap, NB>(T, mycut, ncut, c, k0, kn, skip, W, wcnt, nullptr);
         const uint32_t nsg = min(nsg_all - skip, (uint32_t)kSrcCap);
-        // ---- bin sources by ray, then sort each ray's sources by distance
-        if (t < 64) ray_fill[t] = 0u;
-        __syncthreads();
-        for (uint32_t q = t; q < nsg; q += kFT) atomicAdd(&ray_fill[s_ray[q]], 1u);
-        __syncthreads();
-        if (t < 64) {
-          const uint32_t v = ray_fill[t];
-          const uint32_t ex = wave_excl(v, t);
-          ray_beg[t] = ex;
-          if (t == 63) ray_beg[64] = ex + v;
-          ray_fill[t] = ex;
-        }
-        __syncthreads();
-        for (uint32_t q = t; q < nsg; q += kFT) {
-          const uint32_t pos = atomicAdd(&ray_fill[s_ray[q]], 1u);
-          s_order[pos] = (uint16_t)q;
-        }
-        __syncthreads();
-        const uint32_t q0 = rt ? ray_beg[t] : 0u, q1 = rt ? ray_beg[t + 1] : 0u;
-        for (uint32_t a = q0 + 1; a < q1; ++a) {     // insertion sort by s
-          const uint16_t key = s_order[a];
-          const float ks = s_s[key];
-          uint32_t b = a;
-          while (b > q0 && s_s[s_order[b - 1]] > ks) {
-            s_order[b] = s_order[b - 1];
-            --b;
-          }
-          s_order[b] = key;
-        }
+        uint32_t q0, q1;
+        sort_window<kSrcCap, NB>(W, nsg, rt, q0, q1);
 
-        // ---- cell absorption along each ray (Sections 2.5.1, 2.6).
-        // Absorbing cut entries are staged 64 at a time; a conservative FP32
-        // bounding-sphere test (rays split over the four wavefronts) gives each
-        // its candidate rays; the (entry, ray) candidates are packed across
-        // the block for the exact FP64 ray-box test; each hit is applied by the
-        // thread owning its ray: sources on the ray inside the chord get the
-        // partial length, the nearest source beyond it a suffix add (resolved
-        // by a prefix sum over the ray's sources sorted by distance).
+        // ---- cell absorption along each ray (Sections 2.5.1, 2.6): sources
+        // on the ray inside a hit's chord get the partial length, the nearest
+        // source beyond it a suffix add (resolved by a prefix sum over the
+        // ray's sources sorted by distance).
         float texl[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) texl[b] = 0.0f;
         uint32_t nabs = 0;
-        for (uint32_t e0 = 0; e0 < ncut; e0 += 64) {
-          if (t < 64) {
-            const uint32_t e = e0 + (uint32_t)t;
-            bool is = false;
-            uint32_t node = 0;
-            if (e < ncut) {
-              const uint2 ent = mycut[e];
-              is = (ent.y & CUT_ABS) != 0u;
-              node = ent.x;
-            }
-            const uint64_t am = ballot64(is);
-            if (t == 0) wcnt[0] = (uint32_t)__popcll(am);
-            if (is) {
-              const int pos = mbcnt(am);
-              double lo[3], hi[3];
-              node_box(T.hdr, T.nk[node], lo, hi);
-              float R2 = 0.0f, D2 = 0.0f;
+        for_each_hit(T, mycut, ncut, c, r, kn, G, H,
+                     [&](uint32_t node, double ht0, double ht1, bool) {
+          const float len = (float)(ht1 - ht0);
+          const float* al = &T.alpha[((int64_t)node * T.nclass + cls) * NB];
+          float av[NB];
 #pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                a_lo[pos][a] = lo[a];
-                a_hi[pos][a] = hi[a];
-                const float m = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
-                const float hx = (float)(0.5 * (hi[a] - lo[a]));
-                a_mc[pos][a] = m;
-                R2 += hx * hx;
-                D2 += m * m;
-              }
-              a_node[pos] = node;
-              a_d2[pos] = D2;
-              a_r2[pos] = R2;
-              a_mask[pos] = 0ull;
-            }
+          for (int b = 0; b < NB; ++b) {
+            av[b] = al[b];
+            texl[b] += av[b] * len;
           }
-          __syncthreads();
-          const int na = (int)wcnt[0];
-          {   // candidate rays: entry t%64, rays wv*16 .. wv*16+15
-            const int ej = t & 63;
-            if (ej < na) {
-              const float D2 = a_d2[ej], R2 = a_r2[ej];
-              const float marg = 1e-5f * D2 + 1e-30f;
-              unsigned long long part = 0ull;
-              const int ka = wv * 16, kb = min(kn, ka + 16);
-              if (D2 - R2 <= marg) {
-                for (int kq = ka; kq < kb; ++kq) part |= 1ull << kq;
-              } else {
-                const float thr = D2 - R2 - marg;
-                const float m0 = a_mc[ej][0], m1 = a_mc[ej][1], m2 = a_mc[ej][2];
-                for (int kq = ka; kq < kb; ++kq) {
-                  const float nm = g_nf[kq][0] * m0 + g_nf[kq][1] * m1 + g_nf[kq][2] * m2;
-                  if (nm > 0.0f && nm * nm >= thr) part |= 1ull << kq;
-                }
-              }
-              if (part) atomicOr(&a_mask[ej], part);
-            }
+          ++nabs;
+          uint32_t lo_p = q0, hi_p = q1;     // first source beyond t0
+          while (lo_p < hi_p) {
+            const uint32_t mid = (lo_p + hi_p) >> 1;
+            if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
           }
-          __syncthreads();
-          if (t < 64) {
-            const uint32_t cntc = (t < na) ? (uint32_t)__popcll(a_mask[t]) : 0u;
-            const uint32_t pre = wave_excl(cntc, t);
-            if (t < na) a_pre[t] = pre;
-            if (t == 63) cand_total = pre + cntc;
-          }
-          __syncthreads();
-          const uint32_t C = cand_total;
-          for (uint32_t g0 = 0; g0 < C; g0 += kFT) {
-            const uint32_t gi = g0 + (uint32_t)t;
-            bool hit = false;
-            double t0 = 0.0, t1 = 0.0;
-            uint32_t hnode = 0;
-            int kray = 0;
-            if (gi < C) {
-              int lo_j = 0, hi_j = na - 1;
-              while (lo_j < hi_j) {
-                const int mid = (lo_j + hi_j + 1) >> 1;
-                if (a_pre[mid] <= gi) lo_j = mid; else hi_j = mid - 1;
-              }
-              uint64_t m = a_mask[lo_j];
-              for (uint32_t rr = gi - a_pre[lo_j]; rr > 0; --rr) m &= m - 1ull;
-              kray = __ffsll((long long)m) - 1;
-              const double lo[3] = {a_lo[lo_j][0], a_lo[lo_j][1], a_lo[lo_j][2]};
-              const double hi[3] = {a_hi[lo_j][0], a_hi[lo_j][1], a_hi[lo_j][2]};
-              const double nn[3] = {g_n[kray][0], g_n[kray][1], g_n[kray][2]};
-              const double iv[3] = {g_inv[kray][0], g_inv[kray][1], g_inv[kray][2]};
-              double tin, tout;
-              if (slab(lo, hi, c, nn, iv, tin, tout) && tout > fmax(tin, r)) {
-                hit = true;
-                t0 = fmax(tin, r);
-                t1 = tout;
-                hnode = a_node[lo_j];
-              }
-            }
-            if (t < 64) h_cnt[t] = 0u;
-            uint32_t nh;
-            const uint32_t hp = block_compact(hit, wcnt, &nh);
-            if (hit) {
-              h_t0[hp] = t0;
-              h_t1[hp] = t1;
-              h_node[hp] = hnode;
-              h_ray[hp] = (uint8_t)kray;
-              atomicAdd(&h_cnt[kray], 1u);
-            }
-            __syncthreads();
-            if (t < 64) {
-              const uint32_t v = h_cnt[t];
-              const uint32_t ex = wave_excl(v, t);
-              h_beg[t] = ex;
-              if (t == 63) h_beg[64] = ex + v;
-              h_cnt[t] = ex;
-            }
-            __syncthreads();
-            if (hit) h_ord[atomicAdd(&h_cnt[kray], 1u)] = (uint16_t)hp;
-            __syncthreads();
-            if (rt) {
-              for (uint32_t hq = h_beg[t]; hq < h_beg[t + 1]; ++hq) {
-                const int hi2 = h_ord[hq];
-                const double ht0 = h_t0[hi2], ht1 = h_t1[hi2];
-                const float len = (float)(ht1 - ht0);
-                const float* al = &T.alpha[((int64_t)h_node[hi2] * T.nclass + cls) * NB];
-                float av[NB];
+          uint32_t pq = lo_p;
+          for (; pq < q1; ++pq) {
+            const uint32_t si = W.order[pq];
+            const double sq = (double)W.s[si];
+            if (!(sq < ht1)) break;
+            const float part = (float)(sq - ht0);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                  av[b] = al[b];
-                  texl[b] += av[b] * len;
-                }
-                ++nabs;
-                uint32_t lo_p = q0, hi_p = q1;     // first source beyond t0
-                while (lo_p < hi_p) {
-                  const uint32_t mid = (lo_p + hi_p) >> 1;
-                  if ((double)s_s[s_order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
-                }
-                uint32_t pq = lo_p;
-                for (; pq < q1; ++pq) {
-                  const uint32_t si = s_order[pq];
-                  const double sq = (double)s_s[si];
-                  if (!(sq < ht1)) break;
-                  const float part = (float)(sq - ht0);
-#pragma unroll
-                  for (int b = 0; b < NB; ++b) s_tau[si][b] += av[b] * part;
-                }
-                if (pq < q1) {
-                  const uint32_t si = s_order[pq];
-#pragma unroll
-                  for (int b = 0; b < NB; ++b) s_sfx[si][b] += av[b] * len;
-                }
-              }
-            }
-            __syncthreads();
+            for (int b = 0; b < NB; ++b) W.tau[si][b] += av[b] * part;
           }
-        }
+          if (pq < q1) {
+            const uint32_t si = W.order[pq];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) W.sfx[si][b] += av[b] * len;
+          }
+        });
         if (rt) {   // resolve the suffix adds along each ray
           float run[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) run[b] = 0.0f;
           for (uint32_t pq = q0; pq < q1; ++pq) {
-            const uint32_t si = s_order[pq];
+            const uint32_t si = W.order[pq];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-              run[b] += s_sfx[si][b];
-              s_tau[si][b] += run[b];
+              run[b] += W.sfx[si][b];
+              W.tau[si][b] += run[b];
             }
           }
 #pragma unroll
@@ -1113,19 +584,19 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
         if (has_i) {
           const RecvInfo& ri = recv[my_i];
           for (uint32_t q = (uint32_t)my_q; q < nsg; q += (uint32_t)per_round) {
-            const float dx = s_rel[q][0] - ri.rel[0];
-            const float dy = s_rel[q][1] - ri.rel[1];
-            const float dz = s_rel[q][2] - ri.rel[2];
+            const float dx = W.rel[q][0] - ri.rel[0];
+            const float dy = W.rel[q][1] - ri.rel[1];
+            const float dz = W.rel[q][2] - ri.rel[2];
             const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
             const float Kv = fshape(rr * ri.inv_rh) * ri.kfac;
-            const float ratio = rr * __builtin_amdgcn_rcpf(s_s[q]);
-            const int ray = s_ray[q];
+            const float ratio = rr * __builtin_amdgcn_rcpf(W.s[q]);
+            const int ray = W.ray[q];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-              const float tau = s_tau[q][b];
+              const float tau = W.tau[q][b];
               const float tc = (tau > 0.0f) ? tau * ratio : 0.0f;
               const float e = __expf(-(tpp[my_i][ray][b] + tc));
-              acc[b] += (double)(s_L[q][b] * Kv * e);
+              acc[b] += (double)(W.L[q][b] * Kv * e);
             }
           }
           // ---- isotropic background along each ray (to the root-cube edge)
@@ -1222,17 +693,7 @@ __global__ void k_reorder(const uint32_t* nbp, const uint32_t* bbin, uint32_t* b
 }
 
 // ============================================================ host side
-struct Scratch {
-  uint32_t *blist, *bnact, *ncnt, *nlumc, *roff, *bstat, *nb;
-  uint32_t *blist2, *bnact2, *ncnt2, *nlumc2, *bbin, *bins;
-  double *brad, *brad2;
-  uint2* cut;
-  uint32_t* nidx;
-  float* tpp;
-  size_t fixed;
-};
-
-static Scratch carve_scratch(void* base, int64_t nleaves) {
+static Scratch carve(void* base, int64_t nleaves) {
   Carve cv(base);
   Scratch s{};
   const int64_t L = std::max<int64_t>(nleaves, 1);
@@ -1251,48 +712,23 @@ static Scratch carve_scratch(void* base, int64_t nleaves) {
   s.bbin = cv.take<uint32_t>(L);
   s.bins = cv.take<uint32_t>(kCostBins);
   s.cut = cv.take<uint2>((size_t)std::min<int64_t>(L, kBatch) * kCutCap);
-  s.fixed = cv.off + 256;
+  s.fixed = ((cv.off + 255) & ~(size_t)255) + 256;   // 256-aligned
   return s;
 }
 
-size_t scratch_fixed_bytes(int64_t n) { return carve_scratch(nullptr, n).fixed; }
+Scratch carve_scratch(void* base, int64_t nleaves) { return carve(base, nleaves); }
+size_t scratch_fixed_bytes(int64_t n) { return carve(nullptr, n).fixed; }
 
-template <int NB>
-static void launch_pair(const DevTree& D, const Scratch& S, uint32_t b0, uint32_t nb, uint32_t cnt,
-                        const float* bg, double* J, const uint8_t* active, hipStream_t st,
-                        trevr_tree* T, trevr_status* rc) {
-  hipEvent_t e0 = prof_begin(T);
-  k_pp_rays<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nidx, S.bnact, b0, nb, active, S.tpp);
-  *rc = hip_check(hipGetLastError(), "k_pp_rays");
-  if (*rc != TREVR_OK) return;
-  k_pp_src<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, b0, nb, active, J);
-  *rc = hip_check(hipGetLastError(), "k_pp_src");
-  if (*rc != TREVR_OK) return;
-  prof_end(T, TREVR_PROF_NEAR, e0);
-  hipEvent_t e1 = prof_begin(T);
-  k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp, bg,
-                                J, active);
-  *rc = hip_check(hipGetLastError(), "k_far");
-  prof_end(T, TREVR_PROF_REDUCE, e1);
-}
-
-trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* bg, double* J,
-                            void* scratch, size_t scratch_bytes) {
-  hipStream_t st = T->stream;
-  const int64_t nleaves = T->num_leaves;
-  Scratch S = carve_scratch(scratch, nleaves);
-  if (scratch_bytes < S.fixed) {
-    T->scratch_needed = S.fixed;
-    return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
-  }
-  const DevTree& D = T->dev;
-  trevr_status rc;
 #define TREVR_LAUNCH_CHECK(what)                                               \
   do {                                                                         \
     if ((rc = hip_check(hipGetLastError(), what)) != TREVR_OK) return rc;      \
   } while (0)
-  if ((rc = hip_check(hipMemsetAsync(T->buf.counters, 0, sizeof(unsigned long long) * CNT_N, st),
-                      "memset counters")) != TREVR_OK) return rc;
+
+trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3]) {
+  hipStream_t st = T->stream;
+  const int64_t nleaves = T->num_leaves;
+  const DevTree& D = T->dev;
+  trevr_status rc;
   if ((rc = hip_check(hipMemsetAsync(S.nb, 0, sizeof(uint32_t) * 4, st), "memset")) != TREVR_OK)
     return rc;
   if ((rc = hip_check(hipMemsetAsync(S.ncnt, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) !=
@@ -1301,7 +737,6 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) !=
       TREVR_OK)
     return rc;
-  hipEvent_t ev_setup = prof_begin(T);
   k_active_buckets<<<(unsigned)((T->num_nodes + 255) / 256), 256, 0, st>>>(D, active, S.blist,
                                                                             S.bnact, S.nb);
   TREVR_LAUNCH_CHECK("k_active_buckets");
@@ -1336,40 +771,112 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   hipError_t e = hipMemcpyAsync(hbuf, S.nb, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if ((rc = hip_check(e, "bucket readback")) != TREVR_OK) return rc;
-  const uint32_t nb = hbuf[0], near_total = hbuf[1], act_total = hbuf[2];
-  const size_t near_off = (S.fixed + 255) & ~(size_t)255;
-  const size_t tpp_off = (near_off + sizeof(uint32_t) * (size_t)near_total + 255) & ~(size_t)255;
-  const size_t need = tpp_off + sizeof(float) * (size_t)act_total * T->nray * T->B + 256;
-  T->scratch_needed = need;
-  if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
-  S.nidx = (uint32_t*)((char*)scratch + near_off);
-  S.tpp = (float*)((char*)scratch + tpp_off);
+  for (int i = 0; i < 3; ++i) counts[i] = hbuf[i];
+  return TREVR_OK;
+}
+
+trevr_status near_fill(trevr_tree* T, const Scratch& S, uint32_t nb) {
+  trevr_status rc = TREVR_OK;
   if (nb > 0) {
-    k_near_fill<<<nb, 64, 0, st>>>(D, S.blist, S.nb, S.brad, S.ncnt, S.nlumc, S.nidx);
+    k_near_fill<<<nb, 64, 0, T->stream>>>(T->dev, S.blist, S.nb, S.brad, S.ncnt, S.nlumc, S.nidx);
     TREVR_LAUNCH_CHECK("k_near_fill");
   }
+  return rc;
+}
+
+trevr_status launch_walk(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb, uint32_t cnt) {
+  trevr_status rc;
+  k_walk<<<cnt, 64, 0, T->stream>>>(T->dev, S.blist, S.brad, b0, nb, S.cut, S.bstat);
+  TREVR_LAUNCH_CHECK("k_walk");
+  return rc;
+}
+
+template <int NB>
+static trevr_status pp_rays_nb(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                               uint32_t cnt, const uint8_t* active) {
+  trevr_status rc;
+  k_pp_rays<NB><<<cnt, kNT, 0, T->stream>>>(T->dev, S.blist, S.ncnt, S.nidx, S.bnact, b0, nb,
+                                            active, S.tpp);
+  TREVR_LAUNCH_CHECK("k_pp_rays");
+  return rc;
+}
+
+trevr_status launch_pp_rays(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                            uint32_t cnt, const uint8_t* active) {
+  switch (T->B) {
+    case 1: return pp_rays_nb<1>(T, S, b0, nb, cnt, active);
+    case 2: return pp_rays_nb<2>(T, S, b0, nb, cnt, active);
+    case 3: return pp_rays_nb<3>(T, S, b0, nb, cnt, active);
+    case 4: return pp_rays_nb<4>(T, S, b0, nb, cnt, active);
+    case 5: return pp_rays_nb<5>(T, S, b0, nb, cnt, active);
+    case 6: return pp_rays_nb<6>(T, S, b0, nb, cnt, active);
+    case 7: return pp_rays_nb<7>(T, S, b0, nb, cnt, active);
+    default: return pp_rays_nb<8>(T, S, b0, nb, cnt, active);
+  }
+}
+
+template <int NB>
+static trevr_status launch_pair(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                                uint32_t cnt, const float* bg, double* J, const uint8_t* active) {
+  hipStream_t st = T->stream;
+  const DevTree& D = T->dev;
+  trevr_status rc;
+  hipEvent_t e0 = prof_begin(T);
+  if ((rc = pp_rays_nb<NB>(T, S, b0, nb, cnt, active)) != TREVR_OK) return rc;
+  k_pp_src<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, b0, nb, active, J);
+  TREVR_LAUNCH_CHECK("k_pp_src");
+  prof_end(T, TREVR_PROF_NEAR, e0);
+  hipEvent_t e1 = prof_begin(T);
+  k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp, bg,
+                                J, active);
+  TREVR_LAUNCH_CHECK("k_far");
+  prof_end(T, TREVR_PROF_REDUCE, e1);
+  return rc;
+}
+
+trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* bg, double* J,
+                            void* scratch, size_t scratch_bytes) {
+  hipStream_t st = T->stream;
+  Scratch S = carve(scratch, T->num_leaves);
+  if (scratch_bytes < S.fixed) {
+    T->scratch_needed = S.fixed;
+    return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
+  }
+  trevr_status rc;
+  if ((rc = hip_check(hipMemsetAsync(T->buf.counters, 0, sizeof(unsigned long long) * CNT_N, st),
+                      "memset counters")) != TREVR_OK) return rc;
+  hipEvent_t ev_setup = prof_begin(T);
+  uint32_t counts[3];
+  if ((rc = bucket_setup(T, active, S, counts)) != TREVR_OK) return rc;
+  const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
+  Carve dyn((char*)scratch + S.fixed);
+  S.nidx = dyn.take<uint32_t>(near_total);
+  S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
+  const size_t need = S.fixed + dyn.off + 256;
+  T->scratch_needed = need;
+  if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
+  if ((rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
   prof_end(T, TREVR_PROF_SETUP, ev_setup);
   for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
     const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
     hipEvent_t ev_walk = prof_begin(T);
-    k_walk<<<cnt, 64, 0, st>>>(D, S.blist, S.brad, b0, nb, S.cut, S.bstat);
-    TREVR_LAUNCH_CHECK("k_walk");
+    if ((rc = launch_walk(T, S, b0, nb, cnt)) != TREVR_OK) return rc;
     prof_end(T, TREVR_PROF_WALK, ev_walk);
     switch (T->B) {
-      case 1: launch_pair<1>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
-      case 2: launch_pair<2>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
-      case 3: launch_pair<3>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
-      case 4: launch_pair<4>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
-      case 5: launch_pair<5>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
-      case 6: launch_pair<6>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
-      case 7: launch_pair<7>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
-      default: launch_pair<8>(D, S, b0, nb, cnt, bg, J, active, st, T, &rc); break;
+      case 1: rc = launch_pair<1>(T, S, b0, nb, cnt, bg, J, active); break;
+      case 2: rc = launch_pair<2>(T, S, b0, nb, cnt, bg, J, active); break;
+      case 3: rc = launch_pair<3>(T, S, b0, nb, cnt, bg, J, active); break;
+      case 4: rc = launch_pair<4>(T, S, b0, nb, cnt, bg, J, active); break;
+      case 5: rc = launch_pair<5>(T, S, b0, nb, cnt, bg, J, active); break;
+      case 6: rc = launch_pair<6>(T, S, b0, nb, cnt, bg, J, active); break;
+      case 7: rc = launch_pair<7>(T, S, b0, nb, cnt, bg, J, active); break;
+      default: rc = launch_pair<8>(T, S, b0, nb, cnt, bg, J, active); break;
     }
     if (rc != TREVR_OK) return rc;
   }
-#undef TREVR_LAUNCH_CHECK
   T->counters_valid = true;
   return TREVR_OK;
 }
+#undef TREVR_LAUNCH_CHECK
 
 }  // namespace trevr

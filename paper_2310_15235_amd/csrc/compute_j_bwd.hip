@@ -1,0 +1,1201 @@
+// Adjoint of the mean intensity path: given dE/dJ, the gradients dE/dL,
+// dE/dkappa and dE/drho (Sections 2.1-2.6 of Wadsley, Baumschlager & Shen
+// 2023 define the forward map; its derivative is taken with every discrete
+// decision held fixed: tree, opening, pixel of a source, p-p membership,
+// which element sets the p-p radius, which cells a ray crosses).
+//
+// The forward decisions are recomputed by the forward's own code (bucket
+// setup, walk, p-p optical depths), then each stage is swept in reverse:
+//   k_pp_src_bwd   p-p sources: dL_j, dh_i through K, dkappa_l and dh_l
+//                  through the columns on the source paths; the p-p part of
+//                  the raw J (needed by the thick-element factor);
+//   k_far_bwd      far sources and background: the optical depths are
+//                  recomputed, then per (receiver, source) the adjoints of the
+//                  p-p optical depth per (receiver, ray), of each source's cell
+//                  optical depth, luminosity and position, of h_i; a second
+//                  sweep over the hits turns the source optical-depth
+//                  adjoints into cell-absorption adjoints (per node, direction
+//                  class and band) and the p-p radius adjoint; the
+//                  thick-element factor;
+//   k_pp_rays_bwd  p-p columns per (receiver, ray): dkappa_l, dh_l;
+//   k_rpp_bwd      the p-p radius adjoint to the size of the element that set
+//                  it (member reach |x - c| + h, or h/w while growing);
+//   tree kernels   top-down through the transmission combine, the bucket
+//                  absorption sum(kappa m)/sum(m/rho), luminosity sums and
+//                  luminosity centres; then h = (m/rho)^(1/3) and input order.
+// Per-term arithmetic is FP32 like the forward; sums of many terms and all
+// gradient accumulators are FP64 (hardware FP64 atomics where several
+// buckets meet).
+
+#include <algorithm>
+#include <cmath>
+
+#include "path_device.hpp"
+#include "path_host.hpp"
+
+namespace trevr {
+
+// Gradient accumulators (sorted slots / preorder nodes), FP64.
+struct Grad {
+  double* gL;       // [B][n]
+  double* gk;       // [B][n]
+  double* gh;       // [n]   d/dh (converted to rho at the end)
+  double* gr;       // [n]   direct d/drho
+  double* galpha;   // [node][class][B]
+  double* gLb;      // [node][B]
+  double* gcen;     // [node][4]: d/d centre; later (u, v) of the centre adjoint
+  double* grpp;     // [bucket] d/d r_pp
+};
+
+__device__ inline void gadd(double* a, double v) {
+  if (v != 0.0) unsafeAtomicAdd(a, v);
+}
+
+// d f/d x of the intensity kernel shape f (see fshape): below 1/2 and from 2
+// on by the derivatives of the series 2 - sum 2 x^2k/(4k^2-1) and
+// sum 2 x^-2k/(4k^2-1); in between 1/x - (1 + x^2) atanh(x^+-1)/x^2.
+__device__ inline float fshape_d(float x) {
+  if (x < 0.5f) {
+    const float y = x * x;
+    float s = 44.0f / 483.0f;
+    s = __builtin_fmaf(s, y, 40.0f / 399.0f);
+    s = __builtin_fmaf(s, y, 36.0f / 323.0f);
+    s = __builtin_fmaf(s, y, 32.0f / 255.0f);
+    s = __builtin_fmaf(s, y, 28.0f / 195.0f);
+    s = __builtin_fmaf(s, y, 24.0f / 143.0f);
+    s = __builtin_fmaf(s, y, 20.0f / 99.0f);
+    s = __builtin_fmaf(s, y, 16.0f / 63.0f);
+    s = __builtin_fmaf(s, y, 12.0f / 35.0f);
+    s = __builtin_fmaf(s, y, 8.0f / 15.0f);
+    s = __builtin_fmaf(s, y, 4.0f / 3.0f);
+    return -x * s;
+  }
+  if (x < 1.0f) {
+    const float at = 0.5f * log1pf(2.0f * x / (1.0f - x));
+    return 1.0f / x - (1.0f + x * x) * at / (x * x);
+  }
+  if (x < 2.0f) {
+    if (x == 1.0f) return 0.0f;
+    const float at = 0.5f * logf((x + 1.0f) / (x - 1.0f));
+    return 1.0f / x - (1.0f + x * x) * at / (x * x);
+  }
+  const float y = __builtin_amdgcn_rcpf(x * x);
+  float s = 44.0f / 483.0f;
+  s = __builtin_fmaf(s, y, 40.0f / 399.0f);
+  s = __builtin_fmaf(s, y, 36.0f / 323.0f);
+  s = __builtin_fmaf(s, y, 32.0f / 255.0f);
+  s = __builtin_fmaf(s, y, 28.0f / 195.0f);
+  s = __builtin_fmaf(s, y, 24.0f / 143.0f);
+  s = __builtin_fmaf(s, y, 20.0f / 99.0f);
+  s = __builtin_fmaf(s, y, 16.0f / 63.0f);
+  s = __builtin_fmaf(s, y, 12.0f / 35.0f);
+  s = __builtin_fmaf(s, y, 8.0f / 15.0f);
+  s = __builtin_fmaf(s, y, 4.0f / 3.0f);
+  return -s * y * __builtin_amdgcn_rcpf(x);
+}
+
+// Thick-element factor C(tau) = (1 - e^-tau)/tau (Section 2.1) and C'(tau).
+__device__ inline double thick_C(double tau) { return tau == 0.0 ? 1.0 : -expm1(-tau) / tau; }
+__device__ inline double thick_dC(double tau) {
+  if (tau < 1e-3) return -0.5 + tau * (1.0 / 3.0 + tau * (-0.125 + tau * (1.0 / 30.0)));
+  return (exp(-tau) - thick_C(tau)) / tau;
+}
+
+// Per receiver of a chunk: w_ib = dE/dJ_ib C_ib (the adjoint of the raw J)
+// and 1/h_i.  Threads t < nrecv * NB.
+template <int NB>
+__device__ inline void load_receiver_adjoints(const DevTree& T, const double* gJ,
+                                              const RecvInfo* recv, int nrecv, float (*gw)[NB],
+                                              float* rinvh) {
+  const int t = threadIdx.x;
+  const int64_t n = T.n;
+  if (t < nrecv * NB) {
+    const int i = t / NB, b = t % NB;
+    const uint32_t sl = recv[i].slot;
+    double C = 1.0;
+    if (T.flags & TREVR_THICK_CORR)
+      C = thick_C((double)T.kappa[(int64_t)b * n + sl] * (double)T.rho[sl] * recv[i].h);
+    gw[i][b] = (float)(gJ[(int64_t)b * n + T.perm[sl]] * C);
+  }
+  if (t < nrecv) rinvh[t] = (float)(1.0 / recv[t].h);
+  __syncthreads();
+}
+
+// LDS adjoint accumulators of a staged p-p chunk.
+template <int NB> struct NearGrad {
+  float gk[kNChunk][NB];
+  float gh[kNChunk];
+};
+
+template <int NB>
+__device__ inline void zero_near_grad(NearGrad<NB>& G) {
+  for (int u = threadIdx.x; u < kNChunk; u += kNT) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) G.gk[u][b] = 0.0f;
+    G.gh[u] = 0.0f;
+  }
+  __syncthreads();
+}
+
+template <int NB>
+__device__ inline void flush_near_grad(const NearTile<NB>& S, const NearGrad<NB>& G, uint32_t cl,
+                                       const Grad& g, int64_t n) {
+  __syncthreads();
+  for (uint32_t u = threadIdx.x; u < cl; u += kNT) {
+    const uint32_t sl = S.slot[u];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) gadd(&g.gk[(int64_t)b * n + sl], (double)G.gk[u][b]);
+    gadd(&g.gh[sl], (double)G.gh[u]);
+  }
+}
+
+// ------------------------------------------------------ p-p sources
+// Adjoint of k_pp_src: for each (receiver i, luminous p-p element j) with
+// term_b = L_jb K(r_ij, h_i) exp(-tau_ijb): dL_jb += w_ib K e_b, dh_i +=
+// w_ib L_jb e_b dK/dh, and the column adjoint -w_ib term_b goes to every
+// p-p element l on the path: dkappa_lb += . Sigma_l(b), dh_l += .
+// kappa_lb dSigma_l/dh_l.  Writes the p-p part of the raw J per receiver.
+template <int NB>
+__global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* blist,
+                                                   const uint32_t* noff, const uint32_t* nlumc,
+                                                   const uint32_t* nidx, const uint32_t* roff,
+                                                   uint32_t b0, uint32_t nbuck,
+                                                   const uint8_t* active, const double* gJ,
+                                                   Grad G, double* jraw) {
+  const uint32_t bucket = b0 + blockIdx.x;
+  if (bucket >= nbuck) return;
+  const int t = threadIdx.x;
+  __shared__ NearTile<NB> S;
+  __shared__ NearGrad<NB> SG;
+  __shared__ RecvInfo recv[kRMax];
+  __shared__ uint32_t nrecv_s;
+  __shared__ float gw[kRMax][NB], rinvh[kRMax];
+  __shared__ double red[kNT][NB];
+  __shared__ double redh[kNT];
+  const uint32_t leafb = blist[bucket];
+  double c[3];
+  leaf_centre(T, leafb, c);
+  const uint32_t n0 = noff[bucket], nnear = noff[bucket + 1] - n0, nl = nlumc[bucket];
+  const uint32_t* near = nidx + n0;
+  const uint2 lk = T.nlink[leafb];
+  const int64_t n = T.n;
+  uint32_t member = lk.x;
+  uint32_t rbase = roff[bucket];
+  for (;;) {
+    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    if (nrecv == 0) break;
+    load_receiver_adjoints<NB>(T, gJ, recv, nrecv, gw, rinvh);
+    const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
+    const int i = t % nrecv;
+    const RecvInfo& ri = recv[i];
+    const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
+    const uint32_t si = ri.slot;
+    double acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+    double ghi = 0.0;
+    const uint32_t P = (uint32_t)nrecv * nl;
+    for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
+      const uint32_t p = pb + (uint32_t)t;
+      const bool ok = t < stride && p < P;
+      const uint32_t j = ok ? near[p / nrecv] : near[0];
+      const double xj0 = (double)T.x[j], xj1 = (double)T.y[j], xj2 = (double)T.z[j];
+      const double e0 = xj0 - xi0, e1 = xj1 - xi1, e2 = xj2 - xi2;
+      const double rij2 = e0 * e0 + e1 * e1 + e2 * e2;
+      const double inv2 = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
+      const float jr[3] = {(float)(xj0 - c[0]), (float)(xj1 - c[1]), (float)(xj2 - c[2])};
+      float smin[3], smax[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        smin[a] = fminf(ri.rel[a], jr[a]);
+        smax[a] = fmaxf(ri.rel[a], jr[a]);
+      }
+      const float r2f = (float)rij2 * (1.0f + 1e-5f) + 1e-30f;
+      // the same p-p element test as the forward, with a callback per hit
+      auto sweep = [&](bool active_pass, auto&& on_elem, bool with_grad) {
+        for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
+          const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
+          stage_near<NB>(S, T, near, c0, cl, c);
+          if (with_grad) zero_near_grad<NB>(SG);
+          const int nsub = ((int)cl + kSub - 1) / kSub;
+          for (int sb = 0; sb < nsub; ++sb) {
+            bool need = false;
+            if (active_pass && rij2 > 0.0) {
+              float dmin2 = 0.0f;
+              bool over = true;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                const float lo = S.blo[sb][a], hi = S.bhi[sb][a];
+                over = over && (smax[a] >= lo) && (smin[a] <= hi);
+                const float dj = fmaxf(fmaxf(lo - jr[a], jr[a] - hi), 0.0f);
+                dmin2 += dj * dj;
+              }
+              need = over && dmin2 < r2f;
+            }
+            if (ballot64(need) == 0ull) continue;
+            if (!need) continue;
+            const int u1 = min((int)cl, (sb + 1) * kSub);
+            for (int u = sb * kSub; u < u1; ++u) {
+              const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
+              const double f0 = ux - xj0, f1 = uy - xj1, f2 = uz - xj2;
+              const double w0 = ux - xi0, w1 = uy - xi1, w2 = uz - xi2;
+              double uu = (w0 * e0 + w1 * e1 + w2 * e2) * inv2;
+              uu = fmin(1.0, fmax(0.0, uu));
+              const double g0 = w0 - uu * e0, g1 = w1 - uu * e1, g2 = w2 - uu * e2;
+              const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+              const uint32_t us = S.slot[u];
+              if ((f0 * f0 + f1 * f1 + f2 * f2 < rij2) && b2 < S.h2[u] && us != si && us != j)
+                on_elem(u, sqrtf((float)b2));
+            }
+          }
+          if (with_grad) flush_near_grad<NB>(S, SG, cl, G, n);
+        }
+      };
+      float tau[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) tau[b] = 0.0f;
+      sweep(ok, [&](int u, float bb) {
+        const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) tau[b] += S.kap[u][b] * sg;
+      }, false);
+      float gt[NB];
+      bool any = false;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) gt[b] = 0.0f;
+      if (ok) {
+        const float x = (float)sqrt(rij2) * ri.inv_rh;
+        const float f = fshape(x);
+        const float Kv = f * ri.kfac;
+        const float dKdh = -(2.0f * f + x * fshape_d(x)) * ri.kfac * rinvh[i];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double E = exp(-(double)tau[b]);
+          const double Lj = (double)T.lum[(int64_t)b * n + j];
+          const double term = Lj * (double)Kv * E;
+          acc[b] += term;
+          const double w = (double)gw[i][b];
+          gadd(&G.gL[(int64_t)b * n + j], w * (double)Kv * E);
+          ghi += w * Lj * E * (double)dKdh;
+          gt[b] = (float)(-w * term);
+          any = any || gt[b] != 0.0f;
+        }
+      }
+      if (__syncthreads_or(any)) {
+        sweep(ok && any, [&](int u, float bb) {
+          const float iv = S.invh[u];
+          const float sg = S.sig[u] * (1.0f - bb * iv);
+          const float dsg = S.sig[u] * iv * (3.0f * bb * iv - 2.0f);
+          float gh = 0.0f;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            atomicAdd(&SG.gk[u][b], gt[b] * sg);
+            gh += gt[b] * S.kap[u][b];
+          }
+          atomicAdd(&SG.gh[u], gh * dsg);
+        }, true);
+      }
+    }
+    // receiver-wise sums in thread order
+#pragma unroll
+    for (int b = 0; b < NB; ++b) red[t][b] = acc[b];
+    redh[t] = ghi;
+    __syncthreads();
+    if (t < nrecv * NB) {
+      const int ii = t / NB, b = t % NB;
+      double v = 0.0;
+      for (int u = ii; u < stride; u += nrecv) v += red[u][b];
+      jraw[(int64_t)(rbase + ii) * NB + b] = v;
+    }
+    if (t < nrecv) {
+      double v = 0.0;
+      for (int u = t; u < stride; u += nrecv) v += redh[u];
+      gadd(&G.gh[recv[t].slot], v);
+    }
+    rbase += (uint32_t)nrecv;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ p-p columns
+// Adjoint of k_pp_rays: tau_ikb = sum_l kappa_lb Sigma_l(b_ilk) with the
+// adjoint g_ikb of the far-field kernel: dkappa_lb += g Sigma, dh_l +=
+// g kappa_lb dSigma/dh.
+template <int NB>
+__global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* blist,
+                                                    const uint32_t* noff, const uint32_t* nidx,
+                                                    const uint32_t* roff, uint32_t b0,
+                                                    uint32_t nbuck, const uint8_t* active,
+                                                    const float* gtpp, Grad G) {
+  const uint32_t bucket = b0 + blockIdx.x;
+  if (bucket >= nbuck) return;
+  const int t = threadIdx.x;
+  __shared__ NearTile<NB> S;
+  __shared__ NearGrad<NB> SG;
+  __shared__ RecvInfo recv[kRMax];
+  __shared__ uint32_t nrecv_s;
+  const uint32_t leafb = blist[bucket];
+  double c[3];
+  leaf_centre(T, leafb, c);
+  const uint32_t n0 = noff[bucket], nnear = noff[bucket + 1] - n0;
+  const uint32_t* near = nidx + n0;
+  const uint2 lk = T.nlink[leafb];
+  const int nray = T.nray;
+  const int64_t n = T.n;
+  uint32_t rbase = roff[bucket];
+  uint32_t member = lk.x;
+  for (;;) {
+    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    if (nrecv == 0) break;
+    const int stride = (kNT / nrecv) * nrecv;
+    const int gpr = (nray + 1) / 2;
+    const uint32_t P = (uint32_t)nrecv * (uint32_t)gpr;
+    const int i = t % nrecv;
+    const RecvInfo& ri = recv[i];
+    for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
+      const uint32_t p = pb + (uint32_t)t;
+      const bool ok = t < stride && p < P;
+      const int kb = ok ? 2 * (int)(p / nrecv) : 0;
+      double nv[2][3];
+      float of[3], inv[2][3];
+      bool kok[2];
+      float g[2][NB];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        kok[q] = ok && kb + q < nray;
+        const int kq = kok[q] ? kb + q : 0;
+        bool nz = false;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          g[q][b] = kok[q] ? gtpp[((int64_t)(rbase + i) * nray + kq) * NB + b] : 0.0f;
+          nz = nz || g[q][b] != 0.0f;
+        }
+        kok[q] = kok[q] && nz;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          nv[q][a] = T.ray_n[3 * kq + a];
+          const float nf = (float)nv[q][a];
+          inv[q][a] = (nf != 0.0f) ? 1.0f / nf : 1e30f;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) of[a] = ri.rel[a];
+      const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
+      const uint32_t si = ri.slot;
+      const bool any = kok[0] || kok[1];
+      if (!__syncthreads_or(any)) continue;
+      for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
+        const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
+        stage_near<NB>(S, T, near, c0, cl, c);
+        zero_near_grad<NB>(SG);
+        const int nsub = ((int)cl + kSub - 1) / kSub;
+        for (int sb = 0; sb < nsub; ++sb) {
+          bool need = false;
+          if (any) {
+            const float blo[3] = {S.blo[sb][0], S.blo[sb][1], S.blo[sb][2]};
+            const float bhi[3] = {S.bhi[sb][0], S.bhi[sb][1], S.bhi[sb][2]};
+            need = (kok[0] && ray_meets_box(of, inv[0], blo, bhi)) ||
+                   (kok[1] && ray_meets_box(of, inv[1], blo, bhi));
+          }
+          if (ballot64(need) == 0ull) continue;
+          if (!need) continue;
+          const int u1 = min((int)cl, (sb + 1) * kSub);
+          for (int u = sb * kSub; u < u1; ++u) {
+            const double d0 = S.x[u] - xi0, d1 = S.y[u] - xi1, d2 = S.z[u] - xi2;
+            const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+            const double h2 = S.h2[u];
+            const bool other = S.slot[u] != si;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const double proj = d0 * nv[q][0] + d1 * nv[q][1] + d2 * nv[q][2];
+              const double b2 = dd - proj * proj;
+              if (proj > 0.0 && b2 < h2 && other && kok[q]) {
+                const float bb = sqrtf((float)fmax(b2, 0.0));
+                const float iv = S.invh[u];
+                const float sg = S.sig[u] * (1.0f - bb * iv);
+                const float dsg = S.sig[u] * iv * (3.0f * bb * iv - 2.0f);
+                float gh = 0.0f;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                  atomicAdd(&SG.gk[u][b], g[q][b] * sg);
+                  gh += g[q][b] * S.kap[u][b];
+                }
+                atomicAdd(&SG.gh[u], gh * dsg);
+              }
+            }
+          }
+        }
+        flush_near_grad<NB>(S, SG, cl, G, n);
+      }
+    }
+    rbase += (uint32_t)nrecv;
+  }
+}
+
+// ------------------------------------------------------------- far field
+template <int NB> struct BwdCap { static constexpr int value = NB <= 4 ? 256 : 128; };
+
+// Adjoint of k_far (same workgroup layout).  Per window of sources the cell
+// optical depths are recomputed by a first sweep over the hits; the
+// (receiver, source) pairs then give, for each term
+// L K(r, h_i) exp(-tau_pp - tau_cell r/s) with weight w = w_ib x term:
+//   tau_pp adjoint (receiver, ray)  -= w           (LDS atomics)
+//   source tau_cell adjoint         -= w r/s       (per source, summed over
+//   source s adjoint                += w tau r/s^2  the receivers by shuffles)
+//   source luminosity adjoint       += w_ib K e
+//   |source - receiver| adjoint     -> source position (merged cells)
+//   h_i adjoint                     += w_ib L e dK/dh;
+// the background adds its tau_pp and ray-exit adjoints.  A second sweep over
+// the hits turns the source tau_cell adjoints into the adjoint of each cell's
+// absorption (chord parts inside, whole chords before a source, via suffix
+// sums over the ray's sources sorted by distance), of the source distance s
+// for sources inside a chord, and of r_pp for chords clipped at the sphere.
+template <int NB>
+__global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blist,
+                                                 const double* brad, const uint32_t* roff,
+                                                 uint32_t b0, uint32_t nbuck, const uint2* cut,
+                                                 const uint32_t* bstat, const float* tppg,
+                                                 const float* bg, const uint8_t* active,
+                                                 const double* gJ, const double* jraw,
+                                                 float* gtppg, Grad G) {
+  constexpr int CAP = BwdCap<NB>::value;
+  const uint32_t bucket = b0 + blockIdx.x;
+  if (bucket >= nbuck) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+
+  __shared__ SrcWindow<CAP, NB> W;
+  __shared__ RayGroup RG;
+  __shared__ HitLds H;
+  __shared__ uint32_t sid[CAP];
+  __shared__ float sgL[CAP][NB], sgtau[CAP][NB], sgs[CAP], sgp[CAP][3];
+  __shared__ float tpp[kRMax][64][NB], gtpp[kRMax][64][NB];
+  __shared__ float tex[64][NB], gtex[64][NB];
+  __shared__ RecvInfo recv[kRMax];
+  __shared__ float gw[kRMax][NB], rinvh[kRMax];
+  __shared__ uint32_t nrecv_s, wcnt[kFT / 64];
+  __shared__ double red[kFT / 64][kRMax][NB], redh[kFT / 64][kRMax], redr[kFT / 64];
+
+  const uint32_t leafb = blist[bucket];
+  const double r = brad[bucket];
+  double c[3];
+  leaf_centre(T, leafb, c);
+  const uint32_t ncut = min(bstat[4 * bucket + 0], kCutCap);
+  const uint2* mycut = cut + (size_t)blockIdx.x * kCutCap;
+  const uint2 lk = T.nlink[leafb];
+  const int nray = T.nray;
+  const int ngroups = (nray + 63) / 64;
+  const int64_t n = T.n;
+  const bool use_bg = (T.flags & TREVR_BACKGROUND) && bg != nullptr;
+  const bool thick = (T.flags & TREVR_THICK_CORR) != 0u;
+
+  double grpp = 0.0;   // this thread's share of d/d r_pp
+  uint32_t rbase = roff[bucket];
+  uint32_t member = lk.x;
+  for (;;) {
+    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    if (nrecv == 0) break;
+    load_receiver_adjoints<NB>(T, gJ, recv, nrecv, gw, rinvh);
+    int P2 = 1;
+    while (P2 < nrecv) P2 <<= 1;
+    const int my_i = t & (P2 - 1);
+    const bool has_i = my_i < nrecv;
+    const int ii = has_i ? my_i : 0;
+    const int per_round = kFT / P2;
+    const int my_q = t / P2;
+    double acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+    double ghf = 0.0;
+
+    for (int g = 0; g < ngroups; ++g) {
+      const int k0 = 64 * g;
+      const int kn = min(64, nray - k0);
+      const bool rt = t < kn;
+      const int cls = rt ? T.ray_class[k0 + t] : 0;
+      load_ray_group(T, k0, kn, RG);
+      for (int q = t; q < nrecv * kn; q += kFT) {
+        const int i = q / kn, kq = q % kn;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          tpp[i][kq][b] = tppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
+          gtpp[i][kq][b] = 0.0f;
+        }
+      }
+      if (t < kn) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) gtex[t][b] = 0.0f;
+      }
+
+      for (uint32_t skip = 0;; skip += (uint32_t)CAP) {
+        const uint32_t nsg_all = stage_window<CAP, NB>(T, mycut, ncut, c, k0, kn, skip, W, wcnt, sid);
+        const uint32_t nsg = min(nsg_all - skip, (uint32_t)CAP);
+        for (uint32_t q = t; q < nsg; q += kFT) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            sgL[q][b] = 0.0f;
+            sgtau[q][b] = 0.0f;
+          }
+          sgs[q] = 0.0f;
+          sgp[q][0] = sgp[q][1] = sgp[q][2] = 0.0f;
+        }
+        uint32_t q0, q1;
+        sort_window<CAP, NB>(W, nsg, rt, q0, q1);
+
+        // ---- first sweep: cell optical depths (as the forward)
+        float texl[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) texl[b] = 0.0f;
+        for_each_hit(T, mycut, ncut, c, r, kn, RG, H,
+                     [&](uint32_t node, double ht0, double ht1, bool) {
+          const float len = (float)(ht1 - ht0);
+          const float* al = &T.alpha[((int64_t)node * T.nclass + cls) * NB];
+          float av[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            av[b] = al[b];
+            texl[b] += av[b] * len;
+          }
+          uint32_t lo_p = q0, hi_p = q1;
+          while (lo_p < hi_p) {
+            const uint32_t mid = (lo_p + hi_p) >> 1;
+            if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
+          }
+          uint32_t pq = lo_p;
+          for (; pq < q1; ++pq) {
+            const uint32_t si = W.order[pq];
+            const double sq = (double)W.s[si];
+            if (!(sq < ht1)) break;
+            const float part = (float)(sq - ht0);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) W.tau[si][b] += av[b] * part;
+          }
+          if (pq < q1) {
+            const uint32_t si = W.order[pq];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) W.sfx[si][b] += av[b] * len;
+          }
+        });
+        __syncthreads();
+        if (rt) {
+          float run[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) run[b] = 0.0f;
+          for (uint32_t pq = q0; pq < q1; ++pq) {
+            const uint32_t si = W.order[pq];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              run[b] += W.sfx[si][b];
+              W.tau[si][b] += run[b];
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < NB; ++b) tex[t][b] = texl[b];
+        }
+        __syncthreads();
+
+        // ---- (receiver, source) pairs
+        {
+          const RecvInfo& ri = recv[ii];
+          for (uint32_t q = (uint32_t)my_q; q < nsg; q += (uint32_t)per_round) {
+            const float dx = W.rel[q][0] - ri.rel[0];
+            const float dy = W.rel[q][1] - ri.rel[1];
+            const float dz = W.rel[q][2] - ri.rel[2];
+            const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
+            const float x = rr * ri.inv_rh;
+            const float f = fshape(x);
+            const float fd = fshape_d(x);
+            const float Kv = f * ri.kfac;
+            const float dKdr = fd * ri.inv_rh * ri.kfac;
+            const float dKdh = -(2.0f * f + x * fd) * ri.kfac * rinvh[ii];
+            const float invs = __builtin_amdgcn_rcpf(W.s[q]);
+            const float ratio = rr * invs;
+            const int ray = W.ray[q];
+            float pL[NB], pt[NB];
+            float ps = 0.0f, prr = 0.0f, ph = 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              const float tau = W.tau[q][b];
+              const float tc = (tau > 0.0f) ? tau * ratio : 0.0f;
+              const float e = __expf(-(tpp[ii][ray][b] + tc));
+              const float Le = W.L[q][b] * e;
+              const float LKe = Le * Kv;
+              if (has_i) acc[b] += (double)LKe;
+              const float gwb = has_i ? gw[ii][b] : 0.0f;
+              const float w = gwb * LKe;
+              if (w != 0.0f) atomicAdd(&gtpp[ii][ray][b], -w);
+              pL[b] = gwb * Kv * e;
+              pt[b] = (tau > 0.0f) ? -w * ratio : 0.0f;
+              if (tau > 0.0f) {
+                ps += w * tc * invs;
+                prr -= w * tau * invs;
+              }
+              prr += gwb * Le * dKdr;
+              ph += gwb * Le * dKdh;
+            }
+            ghf += (double)ph;
+            float pp[3] = {0.0f, 0.0f, 0.0f};
+            if (rr > 0.0f) {
+              const float ir = prr / rr;
+              pp[0] = ir * dx;
+              pp[1] = ir * dy;
+              pp[2] = ir * dz;
+            }
+            for (int o = 1; o < P2; o <<= 1) {
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                pL[b] += __shfl_xor(pL[b], o);
+                pt[b] += __shfl_xor(pt[b], o);
+              }
+              ps += __shfl_xor(ps, o);
+#pragma unroll
+              for (int a = 0; a < 3; ++a) pp[a] += __shfl_xor(pp[a], o);
+            }
+            if (my_i == 0) {
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                sgL[q][b] += pL[b];
+                sgtau[q][b] += pt[b];
+              }
+              sgs[q] += ps;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) sgp[q][a] += pp[a];
+            }
+          }
+          // ---- isotropic background
+          if (use_bg && skip == 0) {
+            for (int kq = my_q; kq < kn; kq += per_round) {
+              float pt[NB];
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                const float term = (float)(4.0 * kPi / nray) * bg[b] *
+                                   __expf(-(tpp[ii][kq][b] + tex[kq][b]));
+                if (has_i) acc[b] += (double)term;
+                const float w = has_i ? gw[ii][b] * term : 0.0f;
+                if (w != 0.0f) atomicAdd(&gtpp[ii][kq][b], -w);
+                pt[b] = -w;
+              }
+              for (int o = 1; o < P2; o <<= 1) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) pt[b] += __shfl_xor(pt[b], o);
+              }
+              if (my_i == 0) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) gtex[kq][b] = pt[b];
+              }
+            }
+          }
+        }
+        __syncthreads();
+
+        // ---- second sweep: adjoint of the cell optical depths.  W.sfx now
+        // holds, by sorted position, the suffix sums of the source tau
+        // adjoints along each ray.
+        if (rt) {
+          float run[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) run[b] = 0.0f;
+          for (uint32_t pq = q1; pq > q0; --pq) {
+            const uint32_t si = W.order[pq - 1];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              run[b] += sgtau[si][b];
+              W.sfx[pq - 1][b] = run[b];
+            }
+          }
+        }
+        __syncthreads();
+        const bool bg_here = use_bg && skip == 0;
+        for_each_hit(T, mycut, ncut, c, r, kn, RG, H,
+                     [&](uint32_t node, double ht0, double ht1, bool clipped) {
+          const float len = (float)(ht1 - ht0);
+          const float* al = &T.alpha[((int64_t)node * T.nclass + cls) * NB];
+          float av[NB], ga[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            av[b] = al[b];
+            ga[b] = 0.0f;
+          }
+          uint32_t lo_p = q0, hi_p = q1;
+          while (lo_p < hi_p) {
+            const uint32_t mid = (lo_p + hi_p) >> 1;
+            if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
+          }
+          const uint32_t first = lo_p;
+          uint32_t pq = first;
+          for (; pq < q1; ++pq) {
+            const uint32_t si = W.order[pq];
+            const double sq = (double)W.s[si];
+            if (!(sq < ht1)) break;
+            const float part = (float)(sq - ht0);
+            float gs = 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              ga[b] += sgtau[si][b] * part;
+              gs += sgtau[si][b] * av[b];
+            }
+            sgs[si] += gs;
+          }
+          if (pq < q1) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ga[b] += len * W.sfx[pq][b];
+          }
+          float gr = 0.0f;
+          if (clipped && first < q1) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) gr += av[b] * W.sfx[first][b];
+          }
+          if (bg_here) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              ga[b] += len * gtex[t][b];
+              if (clipped) gr += av[b] * gtex[t][b];
+            }
+          }
+          grpp -= (double)gr;
+          double* dst = &G.galpha[((int64_t)node * T.nclass + cls) * NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) gadd(&dst[b], (double)ga[b]);
+        });
+        __syncthreads();
+
+        // ---- flush the source adjoints
+        for (uint32_t q = t; q < nsg; q += kFT) {
+          const uint32_t id = sid[q];
+          if (id & kSrcCellBit) {
+            const uint32_t node = id & ~kSrcCellBit;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) gadd(&G.gLb[(int64_t)node * NB + b], (double)sgL[q][b]);
+            const float gsv = (W.s[q] != 0.0f) ? sgs[q] : 0.0f;
+            const int ray = W.ray[q];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+              gadd(&G.gcen[(int64_t)node * 4 + a], (double)sgp[q][a] + (double)gsv * RG.n[ray][a]);
+          } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) gadd(&G.gL[(int64_t)b * n + id], (double)sgL[q][b]);
+          }
+        }
+        __syncthreads();
+        if (nsg_all <= skip + (uint32_t)CAP) break;
+      }
+      // p-p column adjoints of this ray group
+      for (int q = t; q < nrecv * kn; q += kFT) {
+        const int i = q / kn, kq = q % kn;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          gtppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b] = gtpp[i][kq][b];
+      }
+      __syncthreads();
+    }
+
+    // ---- per receiver: raw J (p-p + far), the thick-element factor
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double v = acc[b];
+      for (int o = 32; o >= P2 && o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane < P2 && lane < nrecv) red[wv][lane][b] = v;
+    }
+    {
+      double v = ghf;
+      for (int o = 32; o >= P2 && o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane < P2 && lane < nrecv) redh[wv][lane] = v;
+    }
+    __syncthreads();
+    if (t < nrecv * NB) {
+      const int i = t / NB, b = t % NB;
+      double v = 0.0;
+      for (int w = 0; w < kFT / 64; ++w) v += red[w][i][b];
+      if (thick) {
+        const uint32_t sl = recv[i].slot;
+        const double Jr = jraw[(int64_t)(rbase + i) * NB + b] + v;
+        const double kap = (double)T.kappa[(int64_t)b * n + sl], rho = (double)T.rho[sl];
+        const double h = recv[i].h;
+        const double gC = gJ[(int64_t)b * n + T.perm[sl]] * Jr * thick_dC(kap * rho * h);
+        gadd(&G.gk[(int64_t)b * n + sl], gC * rho * h);
+        gadd(&G.gr[sl], gC * kap * h);
+        gadd(&G.gh[sl], gC * kap * rho);
+      }
+    }
+    if (t < nrecv) {
+      double v = 0.0;
+      for (int w = 0; w < kFT / 64; ++w) v += redh[w][t];
+      gadd(&G.gh[recv[t].slot], v);
+    }
+    __syncthreads();
+    rbase += (uint32_t)nrecv;
+  }
+  // ---- r_pp adjoint of the bucket
+  const double v = wave_sum(grpp);
+  if (lane == 0) redr[wv] = v;
+  __syncthreads();
+  if (t == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kFT / 64; ++w) s += redr[w];
+    G.grpp[bucket] = s;
+  }
+}
+
+// ---------------------------------------------------------- p-p radius
+// The p-p radius is a maximum (Section 2.4): of rpp_min and the members'
+// reach |x_s - c| + h_s, then of the beam rule h_j / w while the sphere
+// grows.  Its adjoint goes to the h of the element that set it: the first
+// in sorted order among equal values, and for the beam rule one inside the
+// sphere of the round that set the final radius.
+__device__ inline uint32_t wave_min_u(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+  return v;
+}
+
+// Smallest sorted slot among elements strictly within sqrt(r2) of c with
+// h / w == target (one wavefront; stack of kStackCap words in LDS).
+__device__ inline uint32_t wave_near_argbeam(const DevTree& T, const double c[3], double r2,
+                                             double target, uint32_t* stack, bool* overflow) {
+  const int lane = threadIdx.x & 63;
+  const double prune = r2 * (1.0 + 1e-9);
+  uint32_t best = 0xFFFFFFFFu;
+  int sp = 1;
+  if (lane == 0) stack[0] = 0u;
+  __syncthreads();
+  while (sp > 0) {
+    const int take = min(sp, 64);
+    sp -= take;
+    const bool valid = lane < take;
+    const uint32_t node = valid ? stack[sp + lane] : 0u;
+    __syncthreads();
+    bool push = false;
+    uint2 lk = make_uint2(0, 0);
+    if (valid) {
+      const uint4 nk = T.nk[node];
+      double lo[3], hi[3];
+      node_box(T.hdr, nk, lo, hi);
+      if (!(dist2_box(lo, hi, c) > prune)) {
+        lk = T.nlink[node];
+        if (nk.w & META_LEAF) {
+          for (uint32_t s = lk.x; s < lk.x + lk.y; ++s)
+            if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2 &&
+                T.h[s] / T.wbeam == target)
+              best = min(best, s);
+        } else {
+          push = true;
+        }
+      }
+    }
+    const uint64_t pm = ballot64(push);
+    const int npush = __popcll(pm);
+    if (sp + 2 * npush > kStackCap) {
+      *overflow = true;
+      break;
+    }
+    if (push) {
+      const int ppos = mbcnt(pm);
+      stack[sp + 2 * ppos] = lk.x;
+      stack[sp + 2 * ppos + 1] = node + 1u;
+    }
+    sp += 2 * npush;
+    __syncthreads();
+  }
+  return wave_min_u(best);
+}
+
+__global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist,
+                                                const uint32_t* nbp, const double* brad, Grad G) {
+  const uint32_t b = blockIdx.x;
+  if (b >= *nbp || !(T.flags & TREVR_NEAR_FIELD)) return;
+  const double g = G.grpp[b];
+  if (g == 0.0) return;
+  __shared__ uint32_t stack[kStackCap];
+  const int lane = threadIdx.x;
+  const uint32_t leaf = blist[b];
+  double c[3];
+  leaf_centre(T, leaf, c);
+  // members: largest reach, first slot attaining it (lanes visit their
+  // slots in increasing order, so a strict test keeps the first)
+  const uint2 lk = T.nlink[leaf];
+  double rm = -INFINITY;
+  uint32_t arg = 0xFFFFFFFFu;
+  for (uint32_t s = lk.x + lane; s < lk.x + lk.y; s += 64) {
+    const double v = sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s];
+    if (v > rm) {
+      rm = v;
+      arg = s;
+    }
+  }
+  const double rmax = wave_max(rm);
+  const uint32_t marg = wave_min_u(rm == rmax ? arg : 0xFFFFFFFFu);
+  double r = fmax(T.rpp_min, rmax);
+  double rprev = -1.0;
+  bool overflow = false;
+  for (;;) {
+    double hm = 0.0;
+    wave_near(T, c, r * r, stack, &hm, nullptr, nullptr, 0, &overflow);
+    const double rn = fmax(r, hm / T.wbeam);
+    if (!(rn > r) || overflow) break;
+    rprev = r;
+    r = rn;
+  }
+  uint32_t src = 0xFFFFFFFFu;
+  double fac = 1.0;
+  if (rprev < 0.0) {
+    if (rmax > T.rpp_min) src = marg;
+  } else {
+    src = wave_near_argbeam(T, c, rprev * rprev, r, stack, &overflow);
+    fac = 1.0 / T.wbeam;
+  }
+  if (lane == 0 && src != 0xFFFFFFFFu && !overflow) gadd(&G.gh[src], g * fac);
+}
+
+// ------------------------------------------------------------ the tree
+// Centre adjoint -> (u, v): the centre c = sum(L_s x_s)/L of a node moves
+// by (x_s - c)/L per unit of any band of L_s, so element s collects
+// u.x_s - v over its ancestors with u = dE/dc / L, v = u.c.
+__global__ void k_cen_prep(DevTree T, Grad G) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= T.num_nodes) return;
+  const double4 cn = T.cen[p];
+  double* g = G.gcen + 4 * p;
+  if (cn.w > 0.0) {
+    const double u0 = g[0] / cn.w, u1 = g[1] / cn.w, u2 = g[2] / cn.w;
+    g[0] = u0;
+    g[1] = u1;
+    g[2] = u2;
+    g[3] = u0 * cn.x + u1 * cn.y + u2 * cn.z;
+  } else {
+    g[0] = g[1] = g[2] = g[3] = 0.0;
+  }
+}
+
+// One level of internal nodes (top-down), one thread per (node, class):
+// the transmission average alpha = combine_s(alpha_c0, alpha_c1) grown
+// through the empty prefix boxes (Section 2.6) passes its adjoint to the
+// children; class 0 also passes the luminosity and centre adjoints.
+__global__ void k_tree_bwd(TreeBufs tb, DevTree T, uint32_t lb, uint32_t le, Grad G) {
+  const int B = T.B, nclass = T.nclass;
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)(le - lb) * nclass) return;
+  const uint32_t i = lb + (uint32_t)(gid / nclass);
+  const int c = (int)(gid % nclass);
+  const int s = tb.b_split[i];
+  if (s < 0) return;
+  const uint32_t p = tb.b_pre[i], p0 = p + 1u, p1 = tb.nlink[p].x;
+  const int l = tb.b_lown[i];
+  const double L = tb.hdr[3];
+  for (int b = 0; b < B; ++b) {
+    const double g = G.galpha[((int64_t)p * nclass + c) * B + b];
+    if (g == 0.0) continue;
+    double d1, d2;
+    double A = combine64_d(&tb.geom[((int64_t)s * nclass + c) * 3], L,
+                           tb.alpha64[((int64_t)p0 * nclass + c) * B + b],
+                           tb.alpha64[((int64_t)p1 * nclass + c) * B + b], &d1, &d2);
+    double D = 1.0;
+    for (int mm = s - 1; mm >= l; --mm) {
+      double e1, e2;
+      A = combine64_d(&tb.geom[((int64_t)mm * nclass + c) * 3], L, A, 0.0, &e1, &e2);
+      D *= e1;
+    }
+    G.galpha[((int64_t)p0 * nclass + c) * B + b] += g * D * d1;
+    G.galpha[((int64_t)p1 * nclass + c) * B + b] += g * D * d2;
+  }
+  if (c == 0) {
+    for (int b = 0; b < B; ++b) {
+      const double v = G.gLb[(int64_t)p * B + b];
+      G.gLb[(int64_t)p0 * B + b] += v;
+      G.gLb[(int64_t)p1 * B + b] += v;
+    }
+    for (int a = 0; a < 4; ++a) {
+      const double v = G.gcen[4 * (int64_t)p + a];
+      G.gcen[4 * (int64_t)p0 + a] += v;
+      G.gcen[4 * (int64_t)p1 + a] += v;
+    }
+  }
+}
+
+// Buckets: alpha_b = sum(kappa_b m)/sum(m/rho) for every class, so
+// dkappa_bs += A_b m_s/V and drho_s += sum_b A_b alpha_b m_s/(rho_s^2 V)
+// with A_b the adjoint summed over classes; luminosities collect the
+// accumulated (Lb, centre) adjoints of the path to the root.
+__global__ void k_leaf_bwd(TreeBufs tb, DevTree T, Grad G) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= T.num_nodes) return;
+  if (!(T.nk[p].w & META_LEAF)) return;
+  const int B = T.B, nclass = T.nclass;
+  const int64_t n = T.n;
+  const uint2 lk = T.nlink[p];
+  double A[kMaxBands], ab[kMaxBands];
+  for (int b = 0; b < B; ++b) {
+    double s = 0.0;
+    for (int c = 0; c < nclass; ++c) s += G.galpha[((int64_t)p * nclass + c) * B + b];
+    A[b] = s;
+    ab[b] = tb.alpha64[(int64_t)p * nclass * B + b];
+  }
+  double vol = 0.0;
+  for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) vol += (double)T.m[s] / (double)T.rho[s];
+  const double* gc = G.gcen + 4 * p;
+  for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
+    const double ms = (double)T.m[s], rs = (double)T.rho[s];
+    double gr = 0.0;
+    for (int b = 0; b < B; ++b) {
+      G.gk[(int64_t)b * n + s] += A[b] * ms / vol;
+      gr += A[b] * ab[b];
+    }
+    G.gr[s] += gr * ms / (rs * rs * vol);
+    const double gl = gc[0] * (double)T.x[s] + gc[1] * (double)T.y[s] + gc[2] * (double)T.z[s] - gc[3];
+    for (int b = 0; b < B; ++b) G.gL[(int64_t)b * n + s] += G.gLb[p * B + b] + gl;
+  }
+}
+
+// h = (m/rho)^(1/3): dh/drho = -h/(3 rho).  Gradients to input order.
+__global__ void k_grad_out(DevTree T, Grad G, double* gL, double* gk, double* grho) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= T.n) return;
+  const int64_t n = T.n;
+  const uint32_t i = T.perm[s];
+  grho[i] = G.gr[s] - G.gh[s] * T.h[s] / (3.0 * (double)T.rho[s]);
+  for (int b = 0; b < T.B; ++b) {
+    gL[(int64_t)b * n + i] = G.gL[(int64_t)b * n + s];
+    gk[(int64_t)b * n + i] = G.gk[(int64_t)b * n + s];
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* a, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) a[i] = 0ull;
+}
+
+// ============================================================ host side
+static unsigned grid_of(int64_t work, int threads) {
+  return (unsigned)((work + threads - 1) / threads);
+}
+
+struct GradLayout {
+  Grad g;
+  size_t begin, end;   // byte range of the accumulators in the scratch
+};
+
+static GradLayout carve_grad(void* scratch, size_t at, const trevr_tree* T) {
+  Carve cv(scratch ? (char*)scratch + at : nullptr);
+  GradLayout L{};
+  const int64_t n = T->n, nn = T->num_nodes, B = T->B;
+  const int64_t nl = std::max<int64_t>(T->num_leaves, 1);
+  L.g.gL = cv.take<double>(B * n);
+  L.g.gk = cv.take<double>(B * n);
+  L.g.gh = cv.take<double>(n);
+  L.g.gr = cv.take<double>(n);
+  L.g.galpha = cv.take<double>(nn * T->nclass * B);
+  L.g.gLb = cv.take<double>(nn * B);
+  L.g.gcen = cv.take<double>(nn * 4);
+  L.g.grpp = cv.take<double>(nl);
+  L.begin = at;
+  L.end = at + ((cv.off + 255) & ~(size_t)255);
+  return L;
+}
+
+size_t scratch_bwd_fixed_bytes(const trevr_tree* T) {
+  const size_t f = scratch_fixed_bytes(T->num_leaves);
+  return carve_grad(nullptr, f, T).end;
+}
+
+#define TREVR_LAUNCH_CHECK(what)                                               \
+  do {                                                                         \
+    if ((rc = hip_check(hipGetLastError(), what)) != TREVR_OK) return rc;      \
+  } while (0)
+
+template <int NB>
+static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                              uint32_t cnt, const uint8_t* active, const float* bg,
+                              const double* gJ, const Grad& G, double* jraw, float* gtpp) {
+  hipStream_t st = T->stream;
+  const DevTree& D = T->dev;
+  trevr_status rc;
+  hipEvent_t e0 = prof_begin(T);
+  k_pp_src_bwd<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, S.bnact, b0, nb,
+                                        active, gJ, G, jraw);
+  TREVR_LAUNCH_CHECK("k_pp_src_bwd");
+  prof_end(T, TREVR_PROF_ADJ_NEAR, e0);
+  hipEvent_t e1 = prof_begin(T);
+  k_far_bwd<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp,
+                                     bg, active, gJ, jraw, gtpp, G);
+  TREVR_LAUNCH_CHECK("k_far_bwd");
+  prof_end(T, TREVR_PROF_ADJ_REDUCE, e1);
+  hipEvent_t e2 = prof_begin(T);
+  k_pp_rays_bwd<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nidx, S.bnact, b0, nb, active,
+                                         gtpp, G);
+  TREVR_LAUNCH_CHECK("k_pp_rays_bwd");
+  prof_end(T, TREVR_PROF_ADJ_NEAR, e2);
+  return rc;
+}
+
+trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const float* bg,
+                                     const double* gJ, double* gL, double* gkappa, double* grho,
+                                     void* scratch, size_t scratch_bytes) {
+  hipStream_t st = T->stream;
+  Scratch S = carve_scratch(scratch, T->num_leaves);
+  const GradLayout GL = carve_grad(scratch, S.fixed, T);
+  const Grad& G = GL.g;
+  if (scratch_bytes < GL.end) {
+    T->scratch_needed = GL.end;
+    return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
+  }
+  trevr_status rc;
+  const int64_t words = (int64_t)((GL.end - GL.begin) / 8);
+  k_zero_u64<<<grid_of(words, 256), 256, 0, st>>>((unsigned long long*)((char*)scratch + GL.begin),
+                                                  words);
+  TREVR_LAUNCH_CHECK("k_zero_u64");
+  hipEvent_t ev_setup = prof_begin(T);
+  uint32_t counts[3];
+  if ((rc = bucket_setup(T, active, S, counts)) != TREVR_OK) return rc;
+  const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
+  Carve dyn((char*)scratch + GL.end);
+  S.nidx = dyn.take<uint32_t>(near_total);
+  S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
+  float* gtpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
+  double* jraw = dyn.take<double>((size_t)act_total * T->B);
+  const size_t need = GL.end + dyn.off + 256;
+  T->scratch_needed = need;
+  if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
+  if ((rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
+  prof_end(T, TREVR_PROF_SETUP, ev_setup);
+  for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
+    const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
+    hipEvent_t ev_walk = prof_begin(T);
+    if ((rc = launch_walk(T, S, b0, nb, cnt)) != TREVR_OK) return rc;
+    prof_end(T, TREVR_PROF_WALK, ev_walk);
+    hipEvent_t ev_near = prof_begin(T);
+    if ((rc = launch_pp_rays(T, S, b0, nb, cnt, active)) != TREVR_OK) return rc;
+    prof_end(T, TREVR_PROF_NEAR, ev_near);
+    switch (T->B) {
+      case 1: rc = bwd_batch<1>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      case 2: rc = bwd_batch<2>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      case 3: rc = bwd_batch<3>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      case 4: rc = bwd_batch<4>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      case 5: rc = bwd_batch<5>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      case 6: rc = bwd_batch<6>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      case 7: rc = bwd_batch<7>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      default: rc = bwd_batch<8>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+    }
+    if (rc != TREVR_OK) return rc;
+  }
+  hipEvent_t ev_tree = prof_begin(T);
+  if (nb > 0) {
+    k_rpp_bwd<<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, G);
+    TREVR_LAUNCH_CHECK("k_rpp_bwd");
+  }
+  const DevTree& D = T->dev;
+  k_cen_prep<<<grid_of(T->num_nodes, 256), 256, 0, st>>>(D, G);
+  TREVR_LAUNCH_CHECK("k_cen_prep");
+  for (size_t d = 0; d < T->levels.size(); ++d) {
+    const auto lv = T->levels[d];
+    const int64_t work = (int64_t)(lv.second - lv.first) * T->nclass;
+    k_tree_bwd<<<grid_of(work, 128), 128, 0, st>>>(T->buf, D, lv.first, lv.second, G);
+    TREVR_LAUNCH_CHECK("k_tree_bwd");
+  }
+  k_leaf_bwd<<<grid_of(T->num_nodes, 128), 128, 0, st>>>(T->buf, D, G);
+  TREVR_LAUNCH_CHECK("k_leaf_bwd");
+  k_grad_out<<<grid_of(T->n, 256), 256, 0, st>>>(D, G, gL, gkappa, grho);
+  TREVR_LAUNCH_CHECK("k_grad_out");
+  prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
+  return TREVR_OK;
+}
+#undef TREVR_LAUNCH_CHECK
+
+}  // namespace trevr

@@ -1,0 +1,616 @@
+// Device helpers shared by the forward and adjoint kernels of the mean
+// intensity path (Sections 2.1-2.6 of Wadsley, Baumschlager & Shen 2023):
+// launch constants, wavefront utilities, the p-p range query, the opening
+// test, the element intensity kernel, LDS staging of the p-p set, receiver
+// chunks and block-wide compaction.  Everything here is inline; the kernels
+// that use it live in compute_j.hip (forward) and compute_j_bwd.hip (adjoint).
+#pragma once
+
+#include "trevr_internal.hpp"
+
+namespace trevr {
+constexpr int kRMax = 8;         // receivers per pass
+constexpr int kStackCap = 4096;  // traversal stack entries (LDS)
+constexpr uint32_t kCutCap = 2048;
+constexpr uint32_t kBatch = 65536;   // buckets per launch (bounds the cut-list scratch)
+constexpr int kCostBins = 48;
+constexpr int kNT = 256;         // threads of the near-field kernel
+constexpr int kNChunk = 256;     // p-p elements staged per pass
+constexpr int kNPair = 2;        // (receiver, p-p source) pairs per thread per pass
+constexpr int kRayPer = 2;       // rays per thread in the p-p column pass
+constexpr double kR = 0.48860251190291992;   // (3/(4 pi))^(1/2)
+
+__device__ inline void atomic_max_u64(unsigned long long* a, unsigned long long v) {
+  atomicMax(a, v);
+}
+
+__device__ inline void leaf_centre(const DevTree& T, uint32_t leaf, double c[3]) {
+  double lo[3], hi[3];
+  node_box(T.hdr, T.nk[leaf], lo, hi);
+  for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline uint32_t wave_sum_u(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+  return v;
+}
+// exclusive prefix sum over the wavefront
+__device__ inline uint32_t wave_excl(uint32_t v, int lane) {
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = (uint32_t)__shfl_up((int)incl, o);
+    if (lane >= o) incl += u;
+  }
+  return incl - v;
+}
+
+// Range query by one wavefront: elements strictly within sqrt(r2) of c.
+// Returns the count; *hmax gets their largest size, *nlum the number that
+// emit.  With `out`, writes their sorted slots: luminous ones from out[0],
+// the others from out[lum_total].  Boxes are pruned conservatively (an
+// element can sit an ulp outside its box after quantisation); membership is
+// the exact test.  The traversal stack lives in `stack` (kStackCap words).
+__device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double r2, uint32_t* stack,
+                              double* hmax, uint32_t* nlum, uint32_t* out, uint32_t lum_total,
+                              bool* overflow) {
+  const int lane = threadIdx.x & 63;
+  const double prune = r2 * (1.0 + 1e-9);
+  uint32_t cnt = 0, lum = 0;
+  double hm = 0.0;
+  int sp = 1;
+  if (lane == 0) stack[0] = 0u;
+  __syncthreads();
+  while (sp > 0) {
+    const int take = min(sp, 64);
+    sp -= take;
+    const bool valid = lane < take;
+    const uint32_t node = valid ? stack[sp + lane] : 0u;
+    __syncthreads();
+    bool push = false;
+    uint32_t mine = 0, mylum = 0;
+    uint2 lk = make_uint2(0, 0);
+    bool isleaf = false;
+    if (valid) {
+      const uint4 nk = T.nk[node];
+      double lo[3], hi[3];
+      node_box(T.hdr, nk, lo, hi);
+      if (!(dist2_box(lo, hi, c) > prune)) {
+        isleaf = (nk.w & META_LEAF) != 0u;
+        lk = T.nlink[node];
+        push = !isleaf;
+        if (isleaf) {
+          for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
+            if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
+              ++mine;
+              hm = fmax(hm, T.h[s]);
+              if (T.lbol[s] > 0.0) ++mylum;
+            }
+          }
+        }
+      }
+    }
+    if (out) {
+      const uint32_t lbase = lum + wave_excl(mylum, lane);
+      const uint32_t dbase = lum_total + (cnt - lum) + wave_excl(mine - mylum, lane);
+      if (isleaf && mine) {
+        uint32_t a = 0, b = 0;
+        for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
+          if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
+            if (T.lbol[s] > 0.0) out[lbase + a++] = s;
+            else out[dbase + b++] = s;
+          }
+        }
+      }
+    }
+    cnt += wave_sum_u(mine);
+    lum += wave_sum_u(mylum);
+    const uint64_t pm = ballot64(push);
+    const int npush = __popcll(pm);
+    if (sp + 2 * npush > kStackCap) {
+      *overflow = true;
+      break;
+    }
+    if (push) {
+      const int ppos = mbcnt(pm);
+      stack[sp + 2 * ppos] = lk.x;          // child 1
+      stack[sp + 2 * ppos + 1] = node + 1u; // child 0
+    }
+    sp += 2 * npush;
+    __syncthreads();
+  }
+  if (hmax) *hmax = wave_max(hm);
+  if (nlum) *nlum = lum;
+  return cnt;
+}
+
+// Opening criterion (Section 2.5.2): open if the cell reaches into the p-p
+// sphere or B/d > theta (d to the nearest point of the cell, B from the
+// luminosity centre to the farthest corner), compared as squares.
+__device__ inline bool open_cell(const double lo[3], const double hi[3], const double cn[3],
+                                 const double c[3], double r2, double theta2) {
+  const double d2 = dist2_box(lo, hi, c);
+  double e[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = cn[a] - lo[a], w = hi[a] - cn[a];
+    e[a] = fmax(u * u, w * w);
+  }
+  const double B2 = e[0] + e[1] + e[2];
+  return (d2 < r2) || (B2 > theta2 * d2);
+}
+
+__device__ inline uint32_t source_pixel(int nside, double vx, double vy, double vz) {
+  if (vx == 0.0 && vy == 0.0 && vz == 0.0) return 0u;
+  return (uint32_t)healpix_pixel(nside, vx, vy, vz);
+}
+
+
+// ------------------------------------------------- element intensity kernel
+// Shape f(x) of the element-averaged intensity, x = r/(R h), R = (3/4pi)^(1/2)
+// (Section 2.2, eq. intint): 1 + (1-x^2) atanh(x)/x below 1, 1 - (x^2-1)
+// atanh(1/x)/x above, and for x >= 2 the series sum 2 x^-2k/(4k^2-1).
+__device__ inline float fshape(float x) {
+  if (x < 1.0f) {
+    if (x == 0.0f) return 2.0f;
+    const float at = 0.5f * log1pf(2.0f * x / (1.0f - x));
+    return 1.0f + (1.0f - x) * (1.0f + x) * at / x;
+  }
+  if (x < 2.0f) {
+    if (x == 1.0f) return 1.0f;
+    const float at = 0.5f * logf((x + 1.0f) / (x - 1.0f));
+    return 1.0f - (x - 1.0f) * (x + 1.0f) * at / x;
+  }
+  const float y2 = __builtin_amdgcn_rcpf(x * x);
+  float s = 2.0f / 483.0f;
+  s = __builtin_fmaf(s, y2, 2.0f / 399.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 323.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 255.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 195.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 143.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 99.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 63.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 35.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 15.0f);
+  s = __builtin_fmaf(s, y2, 2.0f / 3.0f);
+  return s * y2;
+}
+
+
+struct RecvInfo {
+  double x[3];
+  double h;
+  float rel[3];    // position relative to the bucket centre
+  float inv_rh;    // 1/(R h)
+  float kfac;      // 1/(2 h^2)
+  uint32_t slot;
+};
+
+// ------------------------------------------------------------ near field
+// Particle-particle transfer inside the p-p sphere (Section 2.4), in two
+// kernels of 256 threads per bucket that stage the p-p set through LDS
+// kNChunk elements at a time.  Elements are culled kSub at a time with FP32
+// boxes (each element's position grown by its own size h, plus a margin),
+// which is conservative: an element can only absorb on a line that passes
+// within h of it.  Threads are mapped receiver-fastest, so the lines of a
+// wavefront are nearly parallel and skip the same boxes.
+constexpr int kSub = 16;
+constexpr int kNSub = kNChunk / kSub;
+
+template <int NB> struct NearTile {
+  double x[kNChunk], y[kNChunk], z[kNChunk], h2[kNChunk];
+  float sig[kNChunk], invh[kNChunk];
+  float kap[kNChunk][NB];
+  uint32_t slot[kNChunk];
+  float blo[kNSub][3], bhi[kNSub][3];
+};
+
+template <int NB>
+__device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint32_t* near,
+                                  uint32_t c0, uint32_t cl, const double c[3]) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  if ((uint32_t)t < cl) {
+    const uint32_t l = near[c0 + t];
+    const double hl = T.h[l];
+    S.x[t] = (double)T.x[l];
+    S.y[t] = (double)T.y[l];
+    S.z[t] = (double)T.z[l];
+    S.h2[t] = hl * hl;
+    S.sig[t] = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+    S.invh[t] = (float)(1.0 / hl);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) S.kap[t][b] = T.kappa[(int64_t)b * T.n + l];
+    S.slot[t] = l;
+  }
+  __syncthreads();
+  if (t < kNSub) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int u1 = min((int)cl, (t + 1) * kSub);
+    for (int u = t * kSub; u < u1; ++u) {
+      const float h = sqrtf((float)S.h2[u]);
+      const float p[3] = {(float)(S.x[u] - c[0]), (float)(S.y[u] - c[1]), (float)(S.z[u] - c[2])};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float m = h + 1e-5f * (fabsf(p[a]) + h);
+        lo[a] = fminf(lo[a], p[a] - m);
+        hi[a] = fmaxf(hi[a], p[a] + m);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { S.blo[t][a] = lo[a]; S.bhi[t][a] = hi[a]; }
+  }
+  __syncthreads();
+}
+
+// Next chunk of active bucket members (thread 0 keeps the cursor).
+__device__ inline int load_receivers(const DevTree& T, const uint8_t* active, const double c[3],
+                                     uint32_t& member, uint32_t mend, RecvInfo* recv,
+                                     uint32_t* nrecv_s) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t k = 0;
+    while (member < mend && k < (uint32_t)kRMax) {
+      const uint32_t s = member++;
+      if (active == nullptr || active[T.perm[s]]) {
+        RecvInfo ri;
+        ri.x[0] = (double)T.x[s];
+        ri.x[1] = (double)T.y[s];
+        ri.x[2] = (double)T.z[s];
+        ri.h = T.h[s];
+        for (int a = 0; a < 3; ++a) ri.rel[a] = (float)(ri.x[a] - c[a]);
+        ri.inv_rh = (float)(1.0 / (kR * ri.h));
+        ri.kfac = (float)(1.0 / (2.0 * ri.h * ri.h));
+        ri.slot = s;
+        recv[k++] = ri;
+      }
+    }
+    *nrecv_s = k;
+  }
+  __syncthreads();
+  return (int)*nrecv_s;
+}
+
+// FP32 ray-box test on the half line o + t n, t >= 0 (inv = 1/n, +-huge for 0).
+__device__ inline bool ray_meets_box(const float o[3], const float inv[3], const float lo[3],
+                                     const float hi[3]) {
+  float tin = 0.0f, tout = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float t1 = (lo[a] - o[a]) * inv[a], t2 = (hi[a] - o[a]) * inv[a];
+    tin = fmaxf(tin, fminf(t1, t2));
+    tout = fminf(tout, fmaxf(t1, t2));
+  }
+  return tin <= tout;
+}
+
+// ------------------------------------------------------------- far field
+constexpr int kFT = 256;   // threads of the far-field kernels
+template <int NB> struct SrcCap { static constexpr int value = NB <= 4 ? 512 : 256; };
+
+// Block-wide compaction: position of this thread's item among the set ones
+// (in thread order) and the block total.  Uses wcnt[4] in LDS; two barriers.
+__device__ inline uint32_t block_compact(bool pred, uint32_t* wcnt, uint32_t* total) {
+  const int t = threadIdx.x, wv = t >> 6;
+  const uint64_t m = ballot64(pred);
+  if ((t & 63) == 0) wcnt[wv] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kFT / 64; ++w) {
+    if (w < wv) base += wcnt[w];
+    tot += wcnt[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + (uint32_t)mbcnt(m);
+}
+
+// Directions of one group of up to 64 rays: FP64 (exact ray-box tests),
+// their reciprocals and an FP32 copy (conservative candidate filter).
+struct RayGroup {
+  double n[64][3], inv[64][3];
+  float nf[64][3];
+};
+
+__device__ inline void load_ray_group(const DevTree& T, int k0, int kn, RayGroup& G) {
+  const int t = threadIdx.x;
+  if (t < kn) {
+    const int k = k0 + t;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double na = T.ray_n[3 * k + a];
+      G.n[t][a] = na;
+      G.inv[t][a] = (na != 0.0) ? 1.0 / na : 0.0;
+      G.nf[t][a] = (float)na;
+    }
+  }
+}
+
+// Far sources of a ray group held in LDS, CAP at a time: position relative
+// to the bucket centre, distance s projected on the ray of their pixel,
+// per-band luminosity, accumulated cell optical depth (tau, plus suffix
+// adds in sfx), the ray (in the group) and the per-ray order by s.
+template <int CAP, int NB> struct SrcWindow {
+  float rel[CAP][3];
+  float s[CAP];
+  float tau[CAP][NB];
+  float sfx[CAP][NB];
+  float L[CAP][NB];
+  uint8_t ray[CAP];
+  uint16_t order[CAP];
+  uint32_t ray_beg[65], ray_fill[64];
+};
+
+// Cut-list source id as kept by the adjoint: element slot, or node with
+// this bit set for merged cell sources.
+constexpr uint32_t kSrcCellBit = 0x80000000u;
+
+// Stage the sources whose pixel lies in rays [k0, k0 + kn), taking those
+// with group index in [skip, skip + CAP) (group index = order in the cut
+// list).  Returns the number of sources of the group.  `ids` (optional)
+// receives each staged source's id.
+template <int CAP, int NB>
+__device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, uint32_t ncut,
+                                        const double c[3], int k0, int kn, uint32_t skip,
+                                        SrcWindow<CAP, NB>& W, uint32_t* wcnt, uint32_t* ids) {
+  const int t = threadIdx.x;
+  const int64_t n = T.n;
+  uint32_t nsg_all = 0;
+  for (uint32_t e0 = 0; e0 < ncut; e0 += kFT) {
+    const uint32_t e = e0 + (uint32_t)t;
+    bool mine = false;
+    uint2 ent = make_uint2(0, 0);
+    uint32_t pix = CUT_NOPIX;
+    if (e < ncut) {
+      ent = mycut[e];
+      pix = ent.y & 0xFFFFu;
+      mine = pix != CUT_NOPIX && (int)pix >= k0 && (int)pix < k0 + kn;
+    }
+    uint32_t tot;
+    const uint32_t gi = nsg_all + block_compact(mine, wcnt, &tot);
+    if (mine && gi >= skip && gi < skip + (uint32_t)CAP) {
+      const uint32_t slot = gi - skip;
+      double p[3];
+      float Lv[NB];
+      const bool part = (ent.y & CUT_KIND_MASK) == CUT_PART;
+      if (part) {
+        p[0] = (double)T.x[ent.x];
+        p[1] = (double)T.y[ent.x];
+        p[2] = (double)T.z[ent.x];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Lv[b] = T.lum[(int64_t)b * n + ent.x];
+      } else {
+        const double4 cn = T.cen[ent.x];
+        p[0] = cn.x;
+        p[1] = cn.y;
+        p[2] = cn.z;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Lv[b] = (float)T.Lb[(int64_t)ent.x * NB + b];
+      }
+      const double v0 = p[0] - c[0], v1 = p[1] - c[1], v2 = p[2] - c[2];
+      double sd = 0.0;
+      if (!(v0 == 0.0 && v1 == 0.0 && v2 == 0.0)) {
+        const double* nn = &T.ray_n[3 * pix];
+        sd = v0 * nn[0] + v1 * nn[1] + v2 * nn[2];
+      }
+      W.rel[slot][0] = (float)v0;
+      W.rel[slot][1] = (float)v1;
+      W.rel[slot][2] = (float)v2;
+      W.s[slot] = (float)sd;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        W.L[slot][b] = Lv[b];
+        W.tau[slot][b] = 0.0f;
+        W.sfx[slot][b] = 0.0f;
+      }
+      W.ray[slot] = (uint8_t)(pix - k0);
+      if (ids) ids[slot] = part ? ent.x : (ent.x | kSrcCellBit);
+    }
+    nsg_all += tot;
+  }
+  return nsg_all;
+}
+
+// Bin the staged sources by ray and sort each ray's sources by s (ray
+// owner threads t < 64); the owner of a ray gets its range [q0, q1) of
+// W.order.
+template <int CAP, int NB>
+__device__ inline void sort_window(SrcWindow<CAP, NB>& W, uint32_t nsg, bool rt, uint32_t& q0,
+                                   uint32_t& q1) {
+  const int t = threadIdx.x;
+  if (t < 64) W.ray_fill[t] = 0u;
+  __syncthreads();
+  for (uint32_t q = t; q < nsg; q += kFT) atomicAdd(&W.ray_fill[W.ray[q]], 1u);
+  __syncthreads();
+  if (t < 64) {
+    const uint32_t v = W.ray_fill[t];
+    const uint32_t ex = wave_excl(v, t);
+    W.ray_beg[t] = ex;
+    if (t == 63) W.ray_beg[64] = ex + v;
+    W.ray_fill[t] = ex;
+  }
+  __syncthreads();
+  for (uint32_t q = t; q < nsg; q += kFT) {
+    const uint32_t pos = atomicAdd(&W.ray_fill[W.ray[q]], 1u);
+    W.order[pos] = (uint16_t)q;
+  }
+  __syncthreads();
+  q0 = rt ? W.ray_beg[t] : 0u;
+  q1 = rt ? W.ray_beg[t + 1] : 0u;
+  for (uint32_t a = q0 + 1; a < q1; ++a) {     // insertion sort by s
+    const uint16_t key = W.order[a];
+    const float ks = W.s[key];
+    uint32_t b = a;
+    while (b > q0 && W.s[W.order[b - 1]] > ks) {
+      W.order[b] = W.order[b - 1];
+      --b;
+    }
+    W.order[b] = key;
+  }
+}
+
+// LDS of the (absorbing cell, ray) hit enumeration.
+struct HitLds {
+  double a_lo[64][3], a_hi[64][3];
+  float a_mc[64][3], a_d2[64], a_r2[64];
+  uint32_t a_node[64], a_pre[64];
+  unsigned long long a_mask[64];
+  double t0[kFT], t1[kFT];
+  uint32_t node[kFT], cnt[64], beg[65];
+  uint8_t ray[kFT], clip[kFT];
+  uint16_t ord[kFT];
+  uint32_t wcnt[kFT / 64], cand_total;
+};
+
+// Every (absorbing cut entry, ray of the group) pair whose ray meets the
+// cell beyond the p-p sphere (Sections 2.5.1, 2.6).  Absorbing entries are
+// staged 64 at a time; a conservative FP32 bounding-sphere test (rays split
+// over the four wavefronts) gives each its candidate rays; the candidates
+// are packed across the block for the exact FP64 ray-box test, and each hit
+// goes to the thread owning its ray (t < kn), which calls
+// on_hit(node, t0, t1, clipped) with the chord [t0, t1], t0 = max(t_in, r),
+// clipped = (t_in < r).  The hits of a ray arrive in cut-list order.
+template <class F>
+__device__ inline void for_each_hit(const DevTree& T, const uint2* mycut, uint32_t ncut,
+                                    const double c[3], double r, int kn, const RayGroup& G,
+                                    HitLds& H, F&& on_hit) {
+  const int t = threadIdx.x, wv = t >> 6;
+  const bool rt = t < kn;
+  for (uint32_t e0 = 0; e0 < ncut; e0 += 64) {
+    if (t < 64) {
+      const uint32_t e = e0 + (uint32_t)t;
+      bool is = false;
+      uint32_t node = 0;
+      if (e < ncut) {
+        const uint2 ent = mycut[e];
+        is = (ent.y & CUT_ABS) != 0u;
+        node = ent.x;
+      }
+      const uint64_t am = ballot64(is);
+      if (t == 0) H.wcnt[0] = (uint32_t)__popcll(am);
+      if (is) {
+        const int pos = mbcnt(am);
+        double lo[3], hi[3];
+        node_box(T.hdr, T.nk[node], lo, hi);
+        float R2 = 0.0f, D2 = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          H.a_lo[pos][a] = lo[a];
+          H.a_hi[pos][a] = hi[a];
+          const float m = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
+          const float hx = (float)(0.5 * (hi[a] - lo[a]));
+          H.a_mc[pos][a] = m;
+          R2 += hx * hx;
+          D2 += m * m;
+        }
+        H.a_node[pos] = node;
+        H.a_d2[pos] = D2;
+        H.a_r2[pos] = R2;
+        H.a_mask[pos] = 0ull;
+      }
+    }
+    __syncthreads();
+    const int na = (int)H.wcnt[0];
+    {   // candidate rays: entry t%64, rays wv*16 .. wv*16+15
+      const int ej = t & 63;
+      if (ej < na) {
+        const float D2 = H.a_d2[ej], R2 = H.a_r2[ej];
+        const float marg = 1e-5f * D2 + 1e-30f;
+        unsigned long long part = 0ull;
+        const int ka = wv * 16, kb = min(kn, ka + 16);
+        if (D2 - R2 <= marg) {
+          for (int kq = ka; kq < kb; ++kq) part |= 1ull << kq;
+        } else {
+          const float thr = D2 - R2 - marg;
+          const float m0 = H.a_mc[ej][0], m1 = H.a_mc[ej][1], m2 = H.a_mc[ej][2];
+          for (int kq = ka; kq < kb; ++kq) {
+            const float nm = G.nf[kq][0] * m0 + G.nf[kq][1] * m1 + G.nf[kq][2] * m2;
+            if (nm > 0.0f && nm * nm >= thr) part |= 1ull << kq;
+          }
+        }
+        if (part) atomicOr(&H.a_mask[ej], part);
+      }
+    }
+    __syncthreads();
+    if (t < 64) {
+      const uint32_t cntc = (t < na) ? (uint32_t)__popcll(H.a_mask[t]) : 0u;
+      const uint32_t pre = wave_excl(cntc, t);
+      if (t < na) H.a_pre[t] = pre;
+      if (t == 63) H.cand_total = pre + cntc;
+    }
+    __syncthreads();
+    const uint32_t C = H.cand_total;
+    for (uint32_t g0 = 0; g0 < C; g0 += kFT) {
+      const uint32_t gi = g0 + (uint32_t)t;
+      bool hit = false, clip = false;
+      double t0 = 0.0, t1 = 0.0;
+      uint32_t hnode = 0;
+      int kray = 0;
+      if (gi < C) {
+        int lo_j = 0, hi_j = na - 1;
+        while (lo_j < hi_j) {
+          const int mid = (lo_j + hi_j + 1) >> 1;
+          if (H.a_pre[mid] <= gi) lo_j = mid; else hi_j = mid - 1;
+        }
+        uint64_t m = H.a_mask[lo_j];
+        for (uint32_t rr = gi - H.a_pre[lo_j]; rr > 0; --rr) m &= m - 1ull;
+        kray = __ffsll((long long)m) - 1;
+        const double lo[3] = {H.a_lo[lo_j][0], H.a_lo[lo_j][1], H.a_lo[lo_j][2]};
+        const double hi[3] = {H.a_hi[lo_j][0], H.a_hi[lo_j][1], H.a_hi[lo_j][2]};
+        const double nn[3] = {G.n[kray][0], G.n[kray][1], G.n[kray][2]};
+        const double iv[3] = {G.inv[kray][0], G.inv[kray][1], G.inv[kray][2]};
+        double tin, tout;
+        if (slab(lo, hi, c, nn, iv, tin, tout) && tout > fmax(tin, r)) {
+          hit = true;
+          clip = tin < r;
+          t0 = fmax(tin, r);
+          t1 = tout;
+          hnode = H.a_node[lo_j];
+        }
+      }
+      if (t < 64) H.cnt[t] = 0u;
+      uint32_t nh;
+      const uint32_t hp = block_compact(hit, H.wcnt, &nh);
+      if (hit) {
+        H.t0[hp] = t0;
+        H.t1[hp] = t1;
+        H.node[hp] = hnode;
+        H.ray[hp] = (uint8_t)kray;
+        H.clip[hp] = clip ? 1u : 0u;
+        atomicAdd(&H.cnt[kray], 1u);
+      }
+      __syncthreads();
+      if (t < 64) {
+        const uint32_t v = H.cnt[t];
+        const uint32_t ex = wave_excl(v, t);
+        H.beg[t] = ex;
+        if (t == 63) H.beg[64] = ex + v;
+        H.cnt[t] = ex;
+      }
+      __syncthreads();
+      if (hit) H.ord[atomicAdd(&H.cnt[kray], 1u)] = (uint16_t)hp;
+      __syncthreads();
+      if (rt) {
+        for (uint32_t hq = H.beg[t]; hq < H.beg[t + 1]; ++hq) {
+          const int h = H.ord[hq];
+          on_hit(H.node[h], H.t0[h], H.t1[h], H.clip[h] != 0);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace trevr

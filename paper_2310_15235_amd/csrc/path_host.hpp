@@ -1,0 +1,38 @@
+// Host-side pieces of the mean intensity path shared by the forward
+// (compute_j.hip) and the adjoint (compute_j_bwd.hip): the scratch layout of
+// the per-bucket arrays and the launches both run unchanged.
+#pragma once
+
+#include "trevr_internal.hpp"
+
+namespace trevr {
+
+// Per-compute scratch: per-bucket arrays (a second copy for the cost
+// reordering), cost bins, cut lists of one batch; then, sized after the
+// bucket readback, the p-p lists and the p-p optical depths per
+// (receiver, ray, band).
+struct Scratch {
+  uint32_t *blist, *bnact, *ncnt, *nlumc, *bstat, *nb;
+  uint32_t *blist2, *bnact2, *ncnt2, *nlumc2, *bbin, *bins;
+  double *brad, *brad2;
+  uint2* cut;
+  uint32_t* nidx;
+  float* tpp;
+  size_t fixed;     // bytes of the part above (before the p-p lists)
+};
+
+Scratch carve_scratch(void* base, int64_t nleaves);
+
+// Active buckets, p-p radii and set sizes, heaviest-first order, offsets of
+// the p-p lists (ncnt) and of the receivers (bnact); reads back
+// counts = {buckets, p-p entries, active receivers} (synchronises).
+trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3]);
+// Fill the p-p lists (S.nidx must be set).
+trevr_status near_fill(trevr_tree* T, const Scratch& S, uint32_t nb);
+// Tree walks of buckets [b0, b0 + cnt) into the cut lists.
+trevr_status launch_walk(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb, uint32_t cnt);
+// p-p optical depth per (receiver, ray, band) of buckets [b0, b0 + cnt) into S.tpp.
+trevr_status launch_pp_rays(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                            uint32_t cnt, const uint8_t* active);
+
+}  // namespace trevr

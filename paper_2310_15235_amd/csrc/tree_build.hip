@@ -339,22 +339,6 @@ __global__ void k_moments(TreeBufs tb, uint32_t lb, uint32_t le, int64_t n, int 
   tb.nk[p] = nk;
 }
 
-// Transmission average of two halves (Section 2.6, eq. transmissionavg):
-// exp(-d alpha) = w1 e^{-d a1} + w1 e^{-d a2} + w12 e^{-d (a1 + a2)/2},
-// with the through-both rays taking half their length in each child.
-__device__ inline double combine64(const double* g, double L, double a1, double a2) {
-  const double lw1 = g[0], lw12 = g[1], d = g[2] * L;
-  double t[3];
-  int nt = 0;
-  if (lw1 > -INFINITY) { t[nt++] = lw1 - d * a1; t[nt++] = lw1 - d * a2; }
-  if (lw12 > -INFINITY) t[nt++] = lw12 - d * (a1 + a2) / 2.0;
-  double mx = t[0];
-  for (int k = 1; k < nt; ++k) mx = fmax(mx, t[k]);
-  double s = 0.0;
-  for (int k = 0; k < nt; ++k) s += exp(t[k] - mx);
-  return -(mx + log(s)) / d;
-}
-
 // Internal nodes of one level, one thread per (node, direction class): the
 // two children combine on the split box, then the result grows through the
 // empty prefix boxes up to the owned box (empty space is vacuum).

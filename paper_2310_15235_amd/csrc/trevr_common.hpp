@@ -161,6 +161,42 @@ __device__ inline int healpix_pixel(int N, double x, double y, double zz) {
   return (int)(12 * N * N - 2 * ir * (ir + 1) + ip);
 }
 
+// Transmission average of two halves (Section 2.6, eq. transmissionavg):
+// exp(-d alpha) = w1 e^{-d a1} + w1 e^{-d a2} + w12 e^{-d (a1 + a2)/2},
+// with the through-both rays taking half their length in each child.
+__device__ inline double combine64(const double* g, double L, double a1, double a2) {
+  const double lw1 = g[0], lw12 = g[1], d = g[2] * L;
+  double t[3];
+  int nt = 0;
+  if (lw1 > -INFINITY) { t[nt++] = lw1 - d * a1; t[nt++] = lw1 - d * a2; }
+  if (lw12 > -INFINITY) t[nt++] = lw12 - d * (a1 + a2) / 2.0;
+  double mx = t[0];
+  for (int k = 1; k < nt; ++k) mx = fmax(mx, t[k]);
+  double s = 0.0;
+  for (int k = 0; k < nt; ++k) s += exp(t[k] - mx);
+  return -(mx + log(s)) / d;
+}
+
+// combine64 and its partial derivatives with respect to a1 and a2: with
+// softmax weights p_k of the three log-terms, d alpha/d a1 = p1 + p3/2 and
+// d alpha/d a2 = p2 + p3/2 (the through-both rays see each half for half
+// their length).
+__device__ inline double combine64_d(const double* g, double L, double a1, double a2, double* d1,
+                                     double* d2) {
+  const double lw1 = g[0], lw12 = g[1], d = g[2] * L;
+  const bool h1 = lw1 > -INFINITY, h12 = lw12 > -INFINITY;
+  const double t1 = h1 ? lw1 - d * a1 : -INFINITY;
+  const double t2 = h1 ? lw1 - d * a2 : -INFINITY;
+  const double t3 = h12 ? lw12 - d * (a1 + a2) / 2.0 : -INFINITY;
+  const double mx = fmax(fmax(t1, t2), t3);
+  const double e1 = h1 ? exp(t1 - mx) : 0.0, e2 = h1 ? exp(t2 - mx) : 0.0;
+  const double e3 = h12 ? exp(t3 - mx) : 0.0;
+  const double s = e1 + e2 + e3;
+  *d1 = (e1 + 0.5 * e3) / s;
+  *d2 = (e2 + 0.5 * e3) / s;
+  return -(mx + log(s)) / d;
+}
+
 // ------------------------------------------------------------ wave helpers
 __device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
 __device__ inline int lane_id() { return __lane_id(); }

@@ -104,7 +104,11 @@ trevr_status build_tree_impl(trevr_tree* t, const float* x, const float* y, cons
                              const float* lum);
 trevr_status compute_J_impl(trevr_tree* t, const uint8_t* active, const float* bg, double* J,
                             void* scratch, size_t scratch_bytes);
+trevr_status compute_J_backward_impl(trevr_tree* t, const uint8_t* active, const float* bg,
+                                     const double* gJ, double* gL, double* gkappa, double* grho,
+                                     void* scratch, size_t scratch_bytes);
 size_t scratch_fixed_bytes(int64_t n);
+size_t scratch_bwd_fixed_bytes(const trevr_tree* t);
 // Record an event pair around a phase (no-op unless profiling is on).
 hipEvent_t prof_begin(trevr_tree* t);
 void prof_end(trevr_tree* t, int slot, hipEvent_t begin);
