@@ -130,7 +130,9 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
  *            not written.
  *   scratch: device buffer of scratch_bytes bytes.
  * Synchronises `stream` once (to size the p-p lists).  Returns
- * TREVR_E_CAPACITY, writing no J, if scratch is too small.
+ * TREVR_E_CAPACITY, writing no J, if scratch is too small.  Cell optical
+ * depths are summed with LDS atomics, so repeated calls agree to FP32
+ * rounding of those sums (about 1e-7 relative), not bit for bit.
  */
 trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* bg, double* J,
                              void* scratch, size_t scratch_bytes, void* stream);

@@ -15,12 +15,14 @@
 //                     per receiver and ray the p-p optical depth (kept for the
 //                     far field);
 //   k_pp_src          the attenuated p-p sources (J starts with these);
-//   k_far             one wavefront reduces the cut ray by ray: rays in groups
-//                     of 64 with one lane per ray, so a lane owns its ray's
-//                     sources and adds the optical depth of every absorbing
-//                     cell its ray crosses without atomics; then the lanes
-//                     sweep the sources against every receiver (FP64 sums),
-//                     add the background and apply the thick-element factor.
+//   k_far             256 threads per bucket reduce the cut: sources are
+//                     staged per group of 64 rays and sorted along each ray;
+//                     every thread takes absorbing cut entries, finds the rays
+//                     that cross them and adds the chord's optical depth to
+//                     the sources on those rays (LDS atomics); then the
+//                     threads sweep the sources against every receiver (FP64
+//                     sums), add the background and apply the thick-element
+//                     factor.
 // Decisions (opening test, p-p membership, the side of a receiver an element
 // lies on, pixel of a source, ray-box intersection) are made in FP64 with the
 // same correctly rounded operation sequence as their definition, so they are
@@ -446,12 +448,13 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
 
 // ------------------------------------------------------------- far field
 // One workgroup of kFT threads per bucket.  Rays are taken in groups of 64;
-// thread k < 64 owns ray k of the group (its sources and their optical
-// depths), so hits update them without atomics.  Sources of a group are held
-// kSrcCap at a time (a second window re-reads the cut; only very source-rich
-// buckets need it).  Receivers are fixed per thread (t mod P2, P2 the power
-// of two >= the receiver count), so each thread keeps one FP64 accumulator
-// per band, reduced per receiver in a fixed order at the end.
+// thread k < 64 owns ray k of the group for the per-ray sort and the suffix
+// sums; hits are found and applied by whichever thread holds the cut entry.
+// Sources of a group are held kSrcCap at a time (a second window re-reads
+// the cut; only source-rich buckets need it).  Receivers are fixed per
+// thread (t mod P2, P2 the power of two >= the receiver count), so each
+// thread keeps one FP64 accumulator per band, reduced per receiver in a
+// fixed order at the end.
 template <int NB>
 __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, const double* brad,
                                              const uint32_t* roff, uint32_t b0, uint32_t nbuck,
@@ -465,7 +468,6 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
 
   __shared__ SrcWindow<kSrcCap, NB> W;
   __shared__ RayGroup G;
-  __shared__ HitLds H;
   __shared__ float tpp[kRMax][64][NB];
   __shared__ float tex[64][NB];
   __shared__ RecvInfo recv[kRMax];
@@ -507,7 +509,6 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
       const int k0 = 64 * g;
       const int kn = min(64, nray - k0);
       const bool rt = t < kn;                  // ray-owning thread
-      const int cls = rt ? T.ray_class[k0 + t] : 0;
       load_ray_group(T, k0, kn, G);
       for (int q = t; q < nrecv * kn; q += kFT) {
         const int i = q / kn, kq = q % kn;
@@ -517,51 +518,57 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
       }
 
       for (uint32_t skip = 0;; skip += (uint32_t)kSrcCap) {
+        if (t < 64) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) tex[t][b] = 0.0f;
+        }
         const uint32_t nsg_all =
             stage_window<kSrcCap, NB>(T, mycut, ncut, c, k0, kn, skip, W, wcnt, nullptr);
         const uint32_t nsg = min(nsg_all - skip, (uint32_t)kSrcCap);
         uint32_t q0, q1;
         sort_window<kSrcCap, NB>(W, nsg, rt, q0, q1);
 
-        // ---- cell absorption along each ray (Sections 2.5.1, 2.6): sources
-        // on the ray inside a hit's chord get the partial length, the nearest
-        // source beyond it a suffix add (resolved by a prefix sum over the
-        // ray's sources sorted by distance).
-        float texl[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) texl[b] = 0.0f;
+        // ---- cell absorption along each ray (Sections 2.5.1, 2.6).  Each
+        // hit is applied by the thread that found it: sources on its ray
+        // inside the chord get the partial length, the nearest source beyond
+        // it a suffix add (resolved by a prefix sum over the ray's sources
+        // sorted by distance).  The LDS atomics make the FP32 sums depend on
+        // the order of the hits at the level of rounding.
         uint32_t nabs = 0;
-        for_each_hit(T, mycut, ncut, c, r, kn, G, H,
-                     [&](uint32_t node, double ht0, double ht1, bool) {
+        for_each_hit_lane(T, mycut, ncut, c, r, kn, G,
+                          [&](uint32_t node, int kq, double ht0, double ht1, bool) {
           const float len = (float)(ht1 - ht0);
-          const float* al = &T.alpha[((int64_t)node * T.nclass + cls) * NB];
+          const float* al = &T.alpha[((int64_t)node * T.nclass + G.cls[kq]) * NB];
           float av[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
             av[b] = al[b];
-            texl[b] += av[b] * len;
+            if (use_bg) atomicAdd(&tex[kq][b], av[b] * len);
           }
           ++nabs;
-          uint32_t lo_p = q0, hi_p = q1;     // first source beyond t0
+          const uint32_t r0 = W.ray_beg[kq], r1 = W.ray_beg[kq + 1];
+          uint32_t lo_p = r0, hi_p = r1;     // first source beyond t0
           while (lo_p < hi_p) {
             const uint32_t mid = (lo_p + hi_p) >> 1;
             if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
           }
           uint32_t pq = lo_p;
-          for (; pq < q1; ++pq) {
+          for (; pq < r1; ++pq) {
             const uint32_t si = W.order[pq];
             const double sq = (double)W.s[si];
             if (!(sq < ht1)) break;
             const float part = (float)(sq - ht0);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) W.tau[si][b] += av[b] * part;
+            for (int b = 0; b < NB; ++b) atomicAdd(&W.tau[si][b], av[b] * part);
           }
-          if (pq < q1) {
+          if (pq < r1) {
             const uint32_t si = W.order[pq];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) W.sfx[si][b] += av[b] * len;
+            for (int b = 0; b < NB; ++b) atomicAdd(&W.sfx[si][b], av[b] * len);
           }
         });
+        if (skip == 0 && first_chunk && nabs) atomicAdd(&abs_count, nabs);
+        __syncthreads();
         if (rt) {   // resolve the suffix adds along each ray
           float run[NB];
 #pragma unroll
@@ -574,9 +581,6 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
               W.tau[si][b] += run[b];
             }
           }
-#pragma unroll
-          for (int b = 0; b < NB; ++b) tex[t][b] = texl[b];
-          if (skip == 0 && first_chunk) atomicAdd(&abs_count, nabs);
         }
         __syncthreads();
 

@@ -233,7 +233,6 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
               need = over && dmin2 < r2f;
             }
             if (ballot64(need) == 0ull) continue;
-            if (!need) continue;
             const int u1 = min((int)cl, (sb + 1) * kSub);
             for (int u = sb * kSub; u < u1; ++u) {
               const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
@@ -244,8 +243,9 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
               const double g0 = w0 - uu * e0, g1 = w1 - uu * e1, g2 = w2 - uu * e2;
               const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
               const uint32_t us = S.slot[u];
-              if ((f0 * f0 + f1 * f1 + f2 * f2 < rij2) && b2 < S.h2[u] && us != si && us != j)
-                on_elem(u, sqrtf((float)b2));
+              const bool pass = need && (f0 * f0 + f1 * f1 + f2 * f2 < rij2) && b2 < S.h2[u] &&
+                                us != si && us != j;
+              on_elem(u, pass ? sqrtf((float)b2) : 0.0f, pass);
             }
           }
           if (with_grad) flush_near_grad<NB>(S, SG, cl, G, n);
@@ -254,10 +254,12 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
       float tau[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) tau[b] = 0.0f;
-      sweep(ok, [&](int u, float bb) {
-        const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
+      sweep(ok, [&](int u, float bb, bool pass) {
+        if (pass) {
+          const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) tau[b] += S.kap[u][b] * sg;
+          for (int b = 0; b < NB; ++b) tau[b] += S.kap[u][b] * sg;
+        }
       }, false);
       float gt[NB];
       bool any = false;
@@ -282,17 +284,32 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
         }
       }
       if (__syncthreads_or(any)) {
-        sweep(ok && any, [&](int u, float bb) {
-          const float iv = S.invh[u];
-          const float sg = S.sig[u] * (1.0f - bb * iv);
-          const float dsg = S.sig[u] * iv * (3.0f * bb * iv - 2.0f);
-          float gh = 0.0f;
+        sweep(ok && any, [&](int u, float bb, bool pass) {
+          // per-lane contributions, summed over rows of 16 lanes before the
+          // LDS atomics (lanes of a wavefront often meet the same element)
+          float ck[NB], gh = 0.0f;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
+          if (pass) {
+            const float iv = S.invh[u];
+            const float sg = S.sig[u] * (1.0f - bb * iv);
+            const float dsg = S.sig[u] * iv * (3.0f * bb * iv - 2.0f);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              ck[b] = gt[b] * sg;
+              gh += gt[b] * S.kap[u][b];
+            }
+            gh *= dsg;
+          }
+          if (ballot64(pass) == 0ull) return;
+          const bool last = (threadIdx.x & 15) == 15;
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            atomicAdd(&SG.gk[u][b], gt[b] * sg);
-            gh += gt[b] * S.kap[u][b];
+            const float v = row_sum16(ck[b]);
+            if (last && v != 0.0f) atomicAdd(&SG.gk[u][b], v);
           }
-          atomicAdd(&SG.gh[u], gh * dsg);
+          const float v = row_sum16(gh);
+          if (last && v != 0.0f) atomicAdd(&SG.gh[u], v);
         }, true);
       }
     }
@@ -398,31 +415,45 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
                    (kok[1] && ray_meets_box(of, inv[1], blo, bhi));
           }
           if (ballot64(need) == 0ull) continue;
-          if (!need) continue;
           const int u1 = min((int)cl, (sb + 1) * kSub);
           for (int u = sb * kSub; u < u1; ++u) {
             const double d0 = S.x[u] - xi0, d1 = S.y[u] - xi1, d2 = S.z[u] - xi2;
             const double dd = d0 * d0 + d1 * d1 + d2 * d2;
             const double h2 = S.h2[u];
             const bool other = S.slot[u] != si;
+            float ck[NB], gh = 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
+            bool any_pass = false;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
               const double proj = d0 * nv[q][0] + d1 * nv[q][1] + d2 * nv[q][2];
               const double b2 = dd - proj * proj;
-              if (proj > 0.0 && b2 < h2 && other && kok[q]) {
+              if (need && proj > 0.0 && b2 < h2 && other && kok[q]) {
                 const float bb = sqrtf((float)fmax(b2, 0.0));
                 const float iv = S.invh[u];
                 const float sg = S.sig[u] * (1.0f - bb * iv);
                 const float dsg = S.sig[u] * iv * (3.0f * bb * iv - 2.0f);
-                float gh = 0.0f;
+                float gq = 0.0f;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                  atomicAdd(&SG.gk[u][b], g[q][b] * sg);
-                  gh += g[q][b] * S.kap[u][b];
+                  ck[b] += g[q][b] * sg;
+                  gq += g[q][b] * S.kap[u][b];
                 }
-                atomicAdd(&SG.gh[u], gh * dsg);
+                gh += gq * dsg;
+                any_pass = true;
               }
             }
+            // sum over rows of 16 lanes before the LDS atomics
+            if (ballot64(any_pass) == 0ull) continue;
+            const bool last = (t & 15) == 15;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              const float v = row_sum16(ck[b]);
+              if (last && v != 0.0f) atomicAdd(&SG.gk[u][b], v);
+            }
+            const float v = row_sum16(gh);
+            if (last && v != 0.0f) atomicAdd(&SG.gh[u], v);
           }
         }
         flush_near_grad<NB>(S, SG, cl, G, n);
@@ -433,7 +464,14 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
 }
 
 // ------------------------------------------------------------- far field
-template <int NB> struct BwdCap { static constexpr int value = NB <= 4 ? 256 : 128; };
+// Sources per LDS window and workgroups per CU of the far-field adjoint:
+// up to four bands the window is sized so that three workgroups fit in
+// the 160 KiB of LDS (and the register budget is held to three wavefronts
+// per SIMD); with more bands, two.
+template <int NB> struct BwdCfg {
+  static constexpr int cap = NB == 1 ? 512 : NB == 2 ? 448 : NB == 3 ? 320 : NB == 4 ? 240 : 128;
+  static constexpr int waves = NB <= 4 ? 3 : 2;
+};
 
 // Adjoint of k_far (same workgroup layout).  Per window of sources the cell
 // optical depths are recomputed by a first sweep over the hits; the
@@ -451,21 +489,20 @@ template <int NB> struct BwdCap { static constexpr int value = NB <= 4 ? 256 : 1
 // sums over the ray's sources sorted by distance), of the source distance s
 // for sources inside a chord, and of r_pp for chords clipped at the sphere.
 template <int NB>
-__global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blist,
+__global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, const uint32_t* blist,
                                                  const double* brad, const uint32_t* roff,
                                                  uint32_t b0, uint32_t nbuck, const uint2* cut,
                                                  const uint32_t* bstat, const float* tppg,
                                                  const float* bg, const uint8_t* active,
                                                  const double* gJ, const double* jraw,
                                                  float* gtppg, Grad G) {
-  constexpr int CAP = BwdCap<NB>::value;
+  constexpr int CAP = BwdCfg<NB>::cap;
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
   __shared__ SrcWindow<CAP, NB> W;
   __shared__ RayGroup RG;
-  __shared__ HitLds H;
   __shared__ uint32_t sid[CAP];
   __shared__ float sgL[CAP][NB], sgtau[CAP][NB], sgs[CAP], sgp[CAP][3];
   __shared__ float tpp[kRMax][64][NB], gtpp[kRMax][64][NB];
@@ -511,7 +548,6 @@ __global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blis
       const int k0 = 64 * g;
       const int kn = min(64, nray - k0);
       const bool rt = t < kn;
-      const int cls = rt ? T.ray_class[k0 + t] : 0;
       load_ray_group(T, k0, kn, RG);
       for (int q = t; q < nrecv * kn; q += kFT) {
         const int i = q / kn, kq = q % kn;
@@ -527,6 +563,10 @@ __global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blis
       }
 
       for (uint32_t skip = 0;; skip += (uint32_t)CAP) {
+        if (t < 64) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) tex[t][b] = 0.0f;
+        }
         const uint32_t nsg_all = stage_window<CAP, NB>(T, mycut, ncut, c, k0, kn, skip, W, wcnt, sid);
         const uint32_t nsg = min(nsg_all - skip, (uint32_t)CAP);
         for (uint32_t q = t; q < nsg; q += kFT) {
@@ -541,38 +581,39 @@ __global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blis
         uint32_t q0, q1;
         sort_window<CAP, NB>(W, nsg, rt, q0, q1);
 
-        // ---- first sweep: cell optical depths (as the forward)
-        float texl[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) texl[b] = 0.0f;
-        for_each_hit(T, mycut, ncut, c, r, kn, RG, H,
-                     [&](uint32_t node, double ht0, double ht1, bool) {
+        // ---- first sweep: cell optical depths.  Each hit is applied by the
+        // thread that found it: sources on its ray inside the chord get the
+        // partial length, the nearest source beyond it a suffix add (resolved
+        // below along the ray's sources sorted by distance).
+        for_each_hit_lane(T, mycut, ncut, c, r, kn, RG,
+                          [&](uint32_t node, int kq, double ht0, double ht1, bool) {
           const float len = (float)(ht1 - ht0);
-          const float* al = &T.alpha[((int64_t)node * T.nclass + cls) * NB];
+          const float* al = &T.alpha[((int64_t)node * T.nclass + RG.cls[kq]) * NB];
           float av[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
             av[b] = al[b];
-            texl[b] += av[b] * len;
+            if (use_bg) atomicAdd(&tex[kq][b], av[b] * len);
           }
-          uint32_t lo_p = q0, hi_p = q1;
+          const uint32_t r0 = W.ray_beg[kq], r1 = W.ray_beg[kq + 1];
+          uint32_t lo_p = r0, hi_p = r1;
           while (lo_p < hi_p) {
             const uint32_t mid = (lo_p + hi_p) >> 1;
             if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
           }
           uint32_t pq = lo_p;
-          for (; pq < q1; ++pq) {
+          for (; pq < r1; ++pq) {
             const uint32_t si = W.order[pq];
             const double sq = (double)W.s[si];
             if (!(sq < ht1)) break;
             const float part = (float)(sq - ht0);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) W.tau[si][b] += av[b] * part;
+            for (int b = 0; b < NB; ++b) atomicAdd(&W.tau[si][b], av[b] * part);
           }
-          if (pq < q1) {
+          if (pq < r1) {
             const uint32_t si = W.order[pq];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) W.sfx[si][b] += av[b] * len;
+            for (int b = 0; b < NB; ++b) atomicAdd(&W.sfx[si][b], av[b] * len);
           }
         });
         __syncthreads();
@@ -588,8 +629,6 @@ __global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blis
               W.tau[si][b] += run[b];
             }
           }
-#pragma unroll
-          for (int b = 0; b < NB; ++b) tex[t][b] = texl[b];
         }
         __syncthreads();
 
@@ -705,9 +744,10 @@ __global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blis
         }
         __syncthreads();
         const bool bg_here = use_bg && skip == 0;
-        for_each_hit(T, mycut, ncut, c, r, kn, RG, H,
-                     [&](uint32_t node, double ht0, double ht1, bool clipped) {
+        for_each_hit_lane(T, mycut, ncut, c, r, kn, RG,
+                          [&](uint32_t node, int kq, double ht0, double ht1, bool clipped) {
           const float len = (float)(ht1 - ht0);
+          const int cls = RG.cls[kq];
           const float* al = &T.alpha[((int64_t)node * T.nclass + cls) * NB];
           float av[NB], ga[NB];
 #pragma unroll
@@ -715,14 +755,15 @@ __global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blis
             av[b] = al[b];
             ga[b] = 0.0f;
           }
-          uint32_t lo_p = q0, hi_p = q1;
+          const uint32_t r0 = W.ray_beg[kq], r1 = W.ray_beg[kq + 1];
+          uint32_t lo_p = r0, hi_p = r1;
           while (lo_p < hi_p) {
             const uint32_t mid = (lo_p + hi_p) >> 1;
             if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
           }
           const uint32_t first = lo_p;
           uint32_t pq = first;
-          for (; pq < q1; ++pq) {
+          for (; pq < r1; ++pq) {
             const uint32_t si = W.order[pq];
             const double sq = (double)W.s[si];
             if (!(sq < ht1)) break;
@@ -733,22 +774,22 @@ __global__ void __launch_bounds__(kFT) k_far_bwd(DevTree T, const uint32_t* blis
               ga[b] += sgtau[si][b] * part;
               gs += sgtau[si][b] * av[b];
             }
-            sgs[si] += gs;
+            if (gs != 0.0f) atomicAdd(&sgs[si], gs);
           }
-          if (pq < q1) {
+          if (pq < r1) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) ga[b] += len * W.sfx[pq][b];
           }
           float gr = 0.0f;
-          if (clipped && first < q1) {
+          if (clipped && first < r1) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) gr += av[b] * W.sfx[first][b];
           }
           if (bg_here) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-              ga[b] += len * gtex[t][b];
-              if (clipped) gr += av[b] * gtex[t][b];
+              ga[b] += len * gtex[kq][b];
+              if (clipped) gr += av[b] * gtex[kq][b];
             }
           }
           grpp -= (double)gr;

@@ -297,7 +297,12 @@ __device__ inline bool ray_meets_box(const float o[3], const float inv[3], const
 
 // ------------------------------------------------------------- far field
 constexpr int kFT = 256;   // threads of the far-field kernels
-template <int NB> struct SrcCap { static constexpr int value = NB <= 4 ? 512 : 256; };
+// Sources per LDS window of the forward far-field kernel: as many as let
+// three workgroups share a CU's 160 KiB of LDS (two from seven bands on,
+// where registers limit it anyway).
+template <int NB> struct SrcCap {
+  static constexpr int value = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 6 ? 224 : 256;
+};
 
 // Block-wide compaction: position of this thread's item among the set ones
 // (in thread order) and the block total.  Uses wcnt[4] in LDS; two barriers.
@@ -322,6 +327,7 @@ __device__ inline uint32_t block_compact(bool pred, uint32_t* wcnt, uint32_t* to
 struct RayGroup {
   double n[64][3], inv[64][3];
   float nf[64][3];
+  int cls[64];   // direction class (transmission tables)
 };
 
 __device__ inline void load_ray_group(const DevTree& T, int k0, int kn, RayGroup& G) {
@@ -335,6 +341,7 @@ __device__ inline void load_ray_group(const DevTree& T, int k0, int kn, RayGroup
       G.inv[t][a] = (na != 0.0) ? 1.0 / na : 0.0;
       G.nf[t][a] = (float)na;
     }
+    G.cls[t] = T.ray_class[k];
   }
 }
 
@@ -425,7 +432,7 @@ __device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, ui
 
 // Bin the staged sources by ray and sort each ray's sources by s (ray
 // owner threads t < 64); the owner of a ray gets its range [q0, q1) of
-// W.order.
+// W.order.  Ends with a barrier: every thread may then read any ray's list.
 template <int CAP, int NB>
 __device__ inline void sort_window(SrcWindow<CAP, NB>& W, uint32_t nsg, bool rt, uint32_t& q0,
                                    uint32_t& q1) {
@@ -459,158 +466,64 @@ __device__ inline void sort_window(SrcWindow<CAP, NB>& W, uint32_t nsg, bool rt,
     }
     W.order[b] = key;
   }
+  __syncthreads();
 }
 
-// LDS of the (absorbing cell, ray) hit enumeration.
-struct HitLds {
-  double a_lo[64][3], a_hi[64][3];
-  float a_mc[64][3], a_d2[64], a_r2[64];
-  uint32_t a_node[64], a_pre[64];
-  unsigned long long a_mask[64];
-  double t0[kFT], t1[kFT];
-  uint32_t node[kFT], cnt[64], beg[65];
-  uint8_t ray[kFT], clip[kFT];
-  uint16_t ord[kFT];
-  uint32_t wcnt[kFT / 64], cand_total;
-};
-
-// Every (absorbing cut entry, ray of the group) pair whose ray meets the
-// cell beyond the p-p sphere (Sections 2.5.1, 2.6).  Absorbing entries are
-// staged 64 at a time; a conservative FP32 bounding-sphere test (rays split
-// over the four wavefronts) gives each its candidate rays; the candidates
-// are packed across the block for the exact FP64 ray-box test, and each hit
-// goes to the thread owning its ray (t < kn), which calls
-// on_hit(node, t0, t1, clipped) with the chord [t0, t1], t0 = max(t_in, r),
-// clipped = (t_in < r).  The hits of a ray arrive in cut-list order.
+// Every (absorbing cut entry, ray of the group) hit found by the thread
+// holding the entry, with no barriers: threads take the cut entries in
+// turn; for an absorbing one the conservative FP32 bounding-sphere test
+// gives its candidate rays, the exact FP64 ray-box test keeps those that
+// meet the cell beyond the p-p sphere, and the same thread calls
+// on_hit(node, ray, t0, t1, clipped) with t0 = max(t_in, r), clipped =
+// (t_in < r).  Hits of one ray arrive from many threads in no fixed order,
+// so on_hit must update shared state atomically.
 template <class F>
-__device__ inline void for_each_hit(const DevTree& T, const uint2* mycut, uint32_t ncut,
-                                    const double c[3], double r, int kn, const RayGroup& G,
-                                    HitLds& H, F&& on_hit) {
-  const int t = threadIdx.x, wv = t >> 6;
-  const bool rt = t < kn;
-  for (uint32_t e0 = 0; e0 < ncut; e0 += 64) {
-    if (t < 64) {
-      const uint32_t e = e0 + (uint32_t)t;
-      bool is = false;
-      uint32_t node = 0;
-      if (e < ncut) {
-        const uint2 ent = mycut[e];
-        is = (ent.y & CUT_ABS) != 0u;
-        node = ent.x;
-      }
-      const uint64_t am = ballot64(is);
-      if (t == 0) H.wcnt[0] = (uint32_t)__popcll(am);
-      if (is) {
-        const int pos = mbcnt(am);
-        double lo[3], hi[3];
-        node_box(T.hdr, T.nk[node], lo, hi);
-        float R2 = 0.0f, D2 = 0.0f;
+__device__ inline void for_each_hit_lane(const DevTree& T, const uint2* mycut, uint32_t ncut,
+                                         const double c[3], double r, int kn, const RayGroup& G,
+                                         F&& on_hit) {
+  const uint64_t all = (kn >= 64) ? ~0ull : ((1ull << kn) - 1ull);
+  for (uint32_t e = threadIdx.x; e < ncut; e += kFT) {
+    const uint2 ent = mycut[e];
+    if (!(ent.y & CUT_ABS)) continue;
+    const uint32_t node = ent.x;
+    double lo[3], hi[3];
+    node_box(T.hdr, T.nk[node], lo, hi);
+    float mc[3], R2 = 0.0f, D2 = 0.0f;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          H.a_lo[pos][a] = lo[a];
-          H.a_hi[pos][a] = hi[a];
-          const float m = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
-          const float hx = (float)(0.5 * (hi[a] - lo[a]));
-          H.a_mc[pos][a] = m;
-          R2 += hx * hx;
-          D2 += m * m;
-        }
-        H.a_node[pos] = node;
-        H.a_d2[pos] = D2;
-        H.a_r2[pos] = R2;
-        H.a_mask[pos] = 0ull;
+    for (int a = 0; a < 3; ++a) {
+      mc[a] = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
+      const float hx = (float)(0.5 * (hi[a] - lo[a]));
+      R2 += hx * hx;
+      D2 += mc[a] * mc[a];
+    }
+    const float marg = 1e-5f * D2 + 1e-30f;
+    uint64_t cand = all;
+    if (D2 - R2 > marg) {
+      const float thr = D2 - R2 - marg;
+      cand = 0ull;
+      for (int kq = 0; kq < kn; ++kq) {
+        const float nm = G.nf[kq][0] * mc[0] + G.nf[kq][1] * mc[1] + G.nf[kq][2] * mc[2];
+        if (nm > 0.0f && nm * nm >= thr) cand |= 1ull << kq;
       }
     }
-    __syncthreads();
-    const int na = (int)H.wcnt[0];
-    {   // candidate rays: entry t%64, rays wv*16 .. wv*16+15
-      const int ej = t & 63;
-      if (ej < na) {
-        const float D2 = H.a_d2[ej], R2 = H.a_r2[ej];
-        const float marg = 1e-5f * D2 + 1e-30f;
-        unsigned long long part = 0ull;
-        const int ka = wv * 16, kb = min(kn, ka + 16);
-        if (D2 - R2 <= marg) {
-          for (int kq = ka; kq < kb; ++kq) part |= 1ull << kq;
-        } else {
-          const float thr = D2 - R2 - marg;
-          const float m0 = H.a_mc[ej][0], m1 = H.a_mc[ej][1], m2 = H.a_mc[ej][2];
-          for (int kq = ka; kq < kb; ++kq) {
-            const float nm = G.nf[kq][0] * m0 + G.nf[kq][1] * m1 + G.nf[kq][2] * m2;
-            if (nm > 0.0f && nm * nm >= thr) part |= 1ull << kq;
-          }
-        }
-        if (part) atomicOr(&H.a_mask[ej], part);
-      }
-    }
-    __syncthreads();
-    if (t < 64) {
-      const uint32_t cntc = (t < na) ? (uint32_t)__popcll(H.a_mask[t]) : 0u;
-      const uint32_t pre = wave_excl(cntc, t);
-      if (t < na) H.a_pre[t] = pre;
-      if (t == 63) H.cand_total = pre + cntc;
-    }
-    __syncthreads();
-    const uint32_t C = H.cand_total;
-    for (uint32_t g0 = 0; g0 < C; g0 += kFT) {
-      const uint32_t gi = g0 + (uint32_t)t;
-      bool hit = false, clip = false;
-      double t0 = 0.0, t1 = 0.0;
-      uint32_t hnode = 0;
-      int kray = 0;
-      if (gi < C) {
-        int lo_j = 0, hi_j = na - 1;
-        while (lo_j < hi_j) {
-          const int mid = (lo_j + hi_j + 1) >> 1;
-          if (H.a_pre[mid] <= gi) lo_j = mid; else hi_j = mid - 1;
-        }
-        uint64_t m = H.a_mask[lo_j];
-        for (uint32_t rr = gi - H.a_pre[lo_j]; rr > 0; --rr) m &= m - 1ull;
-        kray = __ffsll((long long)m) - 1;
-        const double lo[3] = {H.a_lo[lo_j][0], H.a_lo[lo_j][1], H.a_lo[lo_j][2]};
-        const double hi[3] = {H.a_hi[lo_j][0], H.a_hi[lo_j][1], H.a_hi[lo_j][2]};
-        const double nn[3] = {G.n[kray][0], G.n[kray][1], G.n[kray][2]};
-        const double iv[3] = {G.inv[kray][0], G.inv[kray][1], G.inv[kray][2]};
-        double tin, tout;
-        if (slab(lo, hi, c, nn, iv, tin, tout) && tout > fmax(tin, r)) {
-          hit = true;
-          clip = tin < r;
-          t0 = fmax(tin, r);
-          t1 = tout;
-          hnode = H.a_node[lo_j];
-        }
-      }
-      if (t < 64) H.cnt[t] = 0u;
-      uint32_t nh;
-      const uint32_t hp = block_compact(hit, H.wcnt, &nh);
-      if (hit) {
-        H.t0[hp] = t0;
-        H.t1[hp] = t1;
-        H.node[hp] = hnode;
-        H.ray[hp] = (uint8_t)kray;
-        H.clip[hp] = clip ? 1u : 0u;
-        atomicAdd(&H.cnt[kray], 1u);
-      }
-      __syncthreads();
-      if (t < 64) {
-        const uint32_t v = H.cnt[t];
-        const uint32_t ex = wave_excl(v, t);
-        H.beg[t] = ex;
-        if (t == 63) H.beg[64] = ex + v;
-        H.cnt[t] = ex;
-      }
-      __syncthreads();
-      if (hit) H.ord[atomicAdd(&H.cnt[kray], 1u)] = (uint16_t)hp;
-      __syncthreads();
-      if (rt) {
-        for (uint32_t hq = H.beg[t]; hq < H.beg[t + 1]; ++hq) {
-          const int h = H.ord[hq];
-          on_hit(H.node[h], H.t0[h], H.t1[h], H.clip[h] != 0);
-        }
-      }
-      __syncthreads();
+    while (cand) {
+      const int kq = __ffsll((long long)cand) - 1;
+      cand &= cand - 1ull;
+      double tin, tout;
+      if (slab(lo, hi, c, G.n[kq], G.inv[kq], tin, tout) && tout > fmax(tin, r))
+        on_hit(node, kq, fmax(tin, r), tout, tin < r);
     }
   }
+}
+
+// Sum over each row of 16 lanes (DPP row shifts, zero fill); the total is
+// valid in the row's last lane.  Every lane of the wavefront must be active.
+__device__ inline float row_sum16(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xf, 0xf, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xf, true));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xf, true));
+  return v;
 }
 
 }  // namespace trevr

@@ -165,7 +165,8 @@ def test_autograd_matches_abi():
 
 
 def test_adjoint_repeatable_and_tree_unchanged():
-    """A backward call leaves the tree and the forward result unchanged."""
+    """A backward call leaves the tree, the forward result (to FP32 rounding of
+    the atomic optical-depth sums) and the work counters unchanged."""
     api = _api()
     import torch
     sc = scenes.lognormal_scene(n=3000, seed=61, grid=16, bands=(1.0,), nside=1)
@@ -179,5 +180,6 @@ def test_adjoint_repeatable_and_tree_unchanged():
         _close(u, v, 1e-5)
     J2 = T.compute_J().cpu().numpy()
     T.check()
-    assert np.array_equal(J1, J2) and T.counters() == c1
+    assert T.counters() == c1
+    _close(J2, J1, 1e-6)
     T.close()
