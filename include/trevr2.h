@@ -152,10 +152,15 @@ trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* 
  * p-p sets, the element whose size sets each p-p radius, ray-cell hits.
  * Positions and masses are not differentiated.
  *   gJ     : double [n_bands][n] (device), rows of inactive elements ignored.
- * Repeats the forward's setup, walk and p-p columns (the tree is not
- * changed), synchronises `stream` once, and needs more scratch than
- * compute_J (accumulators per node, class and band, and a second p-p column
- * buffer): on TREVR_E_CAPACITY trevr_scratch_needed gives the size.
+ * The forward's bucket setup, walks and p-p columns are needed again.  If
+ * the last compute_J (or backward) on this tree used the same scratch
+ * buffer and an active set with the same contents (checked on the device
+ * with a 64-bit fingerprint of the active indices), they are taken from the
+ * scratch as that call left them; otherwise they are recomputed.  Either
+ * way the result is the same.  Synchronises `stream` once or twice and needs
+ * more scratch than compute_J (accumulators per node, class and band, and a
+ * second p-p column buffer, placed after compute_J's part of the scratch):
+ * on TREVR_E_CAPACITY trevr_scratch_needed gives the size.
  * Partial sums are formed with atomics (FP32 in LDS, FP64 in device memory),
  * so repeated calls agree to FP32 rounding of those sums, not bit for bit.
  */

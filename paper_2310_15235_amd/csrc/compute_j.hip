@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "path_device.hpp"
 #include "path_host.hpp"
@@ -53,12 +54,33 @@ __global__ void k_active_buckets(DevTree T, const uint8_t* active, uint32_t* bli
   bnact[b] = cnt;
 }
 
+// Order-independent 64-bit fingerprint of the active set: the sum over
+// active input indices i of a 64-bit mix of i (splitmix64 finaliser).  A
+// backward call compares it with the forward's to decide whether the
+// forward's bucket setup, walks and p-p columns still apply.
+__device__ inline unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_active_hash(const uint8_t* active, int64_t n, unsigned long long* out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned long long v = 0ull;
+  if (i < n && (active == nullptr || active[i])) v = mix64((unsigned long long)i + 1ull);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
 // p-p radius (Section 2.4): past every bucket member by its size, then grown
 // until no element inside is wider than the beam there (w r).  One
 // wavefront per bucket.
+// Also records the radius before the last growth (-1 if it never grew),
+// which tells the adjoint which element set the final radius.
 __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
-                                              const uint32_t* nbp, double* brad, uint32_t* ncnt,
-                                              uint32_t* nlumc) {
+                                              const uint32_t* nbp, double* brad, double* bprev,
+                                              uint32_t* ncnt, uint32_t* nlumc) {
   const uint32_t b = blockIdx.x;
   if (b >= *nbp) return;
   __shared__ uint32_t stack[kStackCap];
@@ -66,7 +88,7 @@ __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
   const uint32_t leaf = blist[b];
   double c[3];
   leaf_centre(T, leaf, c);
-  double r = 0.0;
+  double r = 0.0, rprev = -1.0;
   uint32_t cnt = 0, nlum = 0;
   bool overflow = false;
   if (T.flags & TREVR_NEAR_FIELD) {
@@ -81,11 +103,13 @@ __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
       cnt = wave_near(T, c, r * r, stack, &hm, &nlum, nullptr, 0, &overflow);
       const double rn = fmax(r, hm / T.wbeam);
       if (!(rn > r) || overflow) break;
+      rprev = r;
       r = rn;
     }
   }
   if (lane == 0) {
     brad[b] = r;
+    bprev[b] = rprev;
     ncnt[b] = cnt;
     nlumc[b] = nlum;
     if (overflow) atomicOr(T.err, ERR_STACK);
@@ -684,8 +708,9 @@ __global__ void k_bins_scan(uint32_t* bins) {
 
 __global__ void k_reorder(const uint32_t* nbp, const uint32_t* bbin, uint32_t* bins,
                           const uint32_t* blist, const uint32_t* bnact, const uint32_t* ncnt,
-                          const uint32_t* nlumc, const double* brad, uint32_t* blist2,
-                          uint32_t* bnact2, uint32_t* ncnt2, uint32_t* nlumc2, double* brad2) {
+                          const uint32_t* nlumc, const double* brad, const double* bprev,
+                          uint32_t* blist2, uint32_t* bnact2, uint32_t* ncnt2, uint32_t* nlumc2,
+                          double* brad2, double* bprev2) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= *nbp) return;
   const uint32_t pos = atomicAdd(&bins[bbin[b]], 1u);
@@ -694,6 +719,7 @@ __global__ void k_reorder(const uint32_t* nbp, const uint32_t* bbin, uint32_t* b
   ncnt2[pos] = ncnt[b];
   nlumc2[pos] = nlumc[b];
   brad2[pos] = brad[b];
+  bprev2[pos] = bprev[b];
 }
 
 // ============================================================ host side
@@ -702,17 +728,23 @@ static Scratch carve(void* base, int64_t nleaves) {
   Scratch s{};
   const int64_t L = std::max<int64_t>(nleaves, 1);
   s.nb = cv.take<uint32_t>(4);           // buckets, p-p total, active total
+  // buckets in processing order (heaviest first); bnact and ncnt are
+  // scanned in place into receiver and p-p list offsets
   s.blist = cv.take<uint32_t>(L);
   s.bnact = cv.take<uint32_t>(L + 1);
   s.ncnt = cv.take<uint32_t>(L + 1);
   s.nlumc = cv.take<uint32_t>(L);
   s.bstat = cv.take<uint32_t>(4 * L);
   s.brad = cv.take<double>(L);
-  s.blist2 = cv.take<uint32_t>(L);
-  s.bnact2 = cv.take<uint32_t>(L + 1);
-  s.ncnt2 = cv.take<uint32_t>(L + 1);
-  s.nlumc2 = cv.take<uint32_t>(L);
-  s.brad2 = cv.take<double>(L);
+  s.bprev = cv.take<double>(L);
+  s.ahash = cv.take<unsigned long long>(2);
+  // the same in discovery order, before the reordering
+  s.blist_raw = cv.take<uint32_t>(L);
+  s.bnact_raw = cv.take<uint32_t>(L);
+  s.ncnt_raw = cv.take<uint32_t>(L);
+  s.nlumc_raw = cv.take<uint32_t>(L);
+  s.brad_raw = cv.take<double>(L);
+  s.bprev_raw = cv.take<double>(L);
   s.bbin = cv.take<uint32_t>(L);
   s.bins = cv.take<uint32_t>(kCostBins);
   s.cut = cv.take<uint2>((size_t)std::min<int64_t>(L, kBatch) * kCutCap);
@@ -728,54 +760,73 @@ size_t scratch_fixed_bytes(int64_t n) { return carve(nullptr, n).fixed; }
     if ((rc = hip_check(hipGetLastError(), what)) != TREVR_OK) return rc;      \
   } while (0)
 
-trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3]) {
+trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3],
+                          uint64_t* hash) {
   hipStream_t st = T->stream;
   const int64_t nleaves = T->num_leaves;
   const DevTree& D = T->dev;
   trevr_status rc;
   if ((rc = hip_check(hipMemsetAsync(S.nb, 0, sizeof(uint32_t) * 4, st), "memset")) != TREVR_OK)
     return rc;
-  if ((rc = hip_check(hipMemsetAsync(S.ncnt, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) !=
-      TREVR_OK)
-    return rc;
-  if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) !=
-      TREVR_OK)
-    return rc;
-  k_active_buckets<<<(unsigned)((T->num_nodes + 255) / 256), 256, 0, st>>>(D, active, S.blist,
-                                                                            S.bnact, S.nb);
+  k_active_buckets<<<(unsigned)((T->num_nodes + 255) / 256), 256, 0, st>>>(D, active, S.blist_raw,
+                                                                            S.bnact_raw, S.nb);
   TREVR_LAUNCH_CHECK("k_active_buckets");
-  k_setup<<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist, S.nb, S.brad, S.ncnt, S.nlumc);
+  k_setup<<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist_raw, S.nb, S.brad_raw, S.bprev_raw,
+                                            S.ncnt_raw, S.nlumc_raw);
   TREVR_LAUNCH_CHECK("k_setup");
-  // heaviest buckets first
+  // heaviest buckets first, into the primary arrays (zero past the last
+  // bucket for the scans)
   if ((rc = hip_check(hipMemsetAsync(S.bins, 0, sizeof(uint32_t) * kCostBins, st), "memset")) != TREVR_OK)
     return rc;
-  if ((rc = hip_check(hipMemsetAsync(S.ncnt2, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
+  if ((rc = hip_check(hipMemsetAsync(S.ncnt, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
     return rc;
-  if ((rc = hip_check(hipMemsetAsync(S.bnact2, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
+  if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
     return rc;
-  k_cost_bins<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(S.nb, S.bnact, S.ncnt, S.nlumc,
-                                                                 T->nray, S.bbin, S.bins);
+  k_cost_bins<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(S.nb, S.bnact_raw, S.ncnt_raw,
+                                                                 S.nlumc_raw, T->nray, S.bbin,
+                                                                 S.bins);
   TREVR_LAUNCH_CHECK("k_cost_bins");
   k_bins_scan<<<1, 64, 0, st>>>(S.bins);
   TREVR_LAUNCH_CHECK("k_bins_scan");
   k_reorder<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(
-      S.nb, S.bbin, S.bins, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.blist2, S.bnact2, S.ncnt2,
-      S.nlumc2, S.brad2);
+      S.nb, S.bbin, S.bins, S.blist_raw, S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw,
+      S.bprev_raw, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev);
   TREVR_LAUNCH_CHECK("k_reorder");
-  std::swap(S.blist, S.blist2);
-  std::swap(S.bnact, S.bnact2);
-  std::swap(S.ncnt, S.ncnt2);
-  std::swap(S.nlumc, S.nlumc2);
-  std::swap(S.brad, S.brad2);
   k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.nb + 1);
   TREVR_LAUNCH_CHECK("k_scan_u32");
   k_scan_u32<<<1, 1024, 0, st>>>(S.bnact, nleaves + 1, S.nb + 2);
   TREVR_LAUNCH_CHECK("k_scan_u32");
+  if ((rc = hip_check(hipMemsetAsync(S.ahash, 0, sizeof(unsigned long long), st), "memset")) !=
+      TREVR_OK)
+    return rc;
+  k_active_hash<<<(unsigned)((T->n + 255) / 256), 256, 0, st>>>(active, T->n, S.ahash);
+  TREVR_LAUNCH_CHECK("k_active_hash");
   uint32_t* hbuf = T->host_u32;
   hipError_t e = hipMemcpyAsync(hbuf, S.nb, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hbuf + 4, S.ahash, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if ((rc = hip_check(e, "bucket readback")) != TREVR_OK) return rc;
   for (int i = 0; i < 3; ++i) counts[i] = hbuf[i];
+  std::memcpy(hash, hbuf + 4, sizeof(uint64_t));
+  return TREVR_OK;
+}
+
+trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long long* dev_slot,
+                         uint64_t* hash) {
+  hipStream_t st = T->stream;
+  trevr_status rc;
+  if ((rc = hip_check(hipMemsetAsync(dev_slot, 0, sizeof(unsigned long long), st), "memset")) !=
+      TREVR_OK)
+    return rc;
+  k_active_hash<<<(unsigned)((T->n + 255) / 256), 256, 0, st>>>(active, T->n, dev_slot);
+  TREVR_LAUNCH_CHECK("k_active_hash");
+  uint32_t* hbuf = T->host_u32;
+  hipError_t e = hipMemcpyAsync(hbuf + 4, dev_slot, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if ((rc = hip_check(e, "hash readback")) != TREVR_OK) return rc;
+  std::memcpy(hash, hbuf + 4, sizeof(uint64_t));
   return TREVR_OK;
 }
 
@@ -847,11 +898,13 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
     return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
   }
   trevr_status rc;
+  T->fwd.valid = false;
   if ((rc = hip_check(hipMemsetAsync(T->buf.counters, 0, sizeof(unsigned long long) * CNT_N, st),
                       "memset counters")) != TREVR_OK) return rc;
   hipEvent_t ev_setup = prof_begin(T);
   uint32_t counts[3];
-  if ((rc = bucket_setup(T, active, S, counts)) != TREVR_OK) return rc;
+  uint64_t hash = 0;
+  if ((rc = bucket_setup(T, active, S, counts, &hash)) != TREVR_OK) return rc;
   const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
   Carve dyn((char*)scratch + S.fixed);
   S.nidx = dyn.take<uint32_t>(near_total);
@@ -879,6 +932,7 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
     if (rc != TREVR_OK) return rc;
   }
   T->counters_valid = true;
+  T->fwd = FwdState{true, scratch, hash, nb, near_total, act_total};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

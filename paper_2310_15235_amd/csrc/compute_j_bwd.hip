@@ -940,46 +940,39 @@ __device__ inline uint32_t wave_near_argbeam(const DevTree& T, const double c[3]
 }
 
 __global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist,
-                                                const uint32_t* nbp, const double* brad, Grad G) {
+                                                const uint32_t* nbp, const double* brad,
+                                                const double* bprev, Grad G) {
   const uint32_t b = blockIdx.x;
   if (b >= *nbp || !(T.flags & TREVR_NEAR_FIELD)) return;
   const double g = G.grpp[b];
   if (g == 0.0) return;
   __shared__ uint32_t stack[kStackCap];
   const int lane = threadIdx.x;
-  const uint32_t leaf = blist[b];
+  const double r = brad[b], rprev = bprev[b];
   double c[3];
-  leaf_centre(T, leaf, c);
-  // members: largest reach, first slot attaining it (lanes visit their
-  // slots in increasing order, so a strict test keeps the first)
-  const uint2 lk = T.nlink[leaf];
-  double rm = -INFINITY;
-  uint32_t arg = 0xFFFFFFFFu;
-  for (uint32_t s = lk.x + lane; s < lk.x + lk.y; s += 64) {
-    const double v = sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s];
-    if (v > rm) {
-      rm = v;
-      arg = s;
-    }
-  }
-  const double rmax = wave_max(rm);
-  const uint32_t marg = wave_min_u(rm == rmax ? arg : 0xFFFFFFFFu);
-  double r = fmax(T.rpp_min, rmax);
-  double rprev = -1.0;
-  bool overflow = false;
-  for (;;) {
-    double hm = 0.0;
-    wave_near(T, c, r * r, stack, &hm, nullptr, nullptr, 0, &overflow);
-    const double rn = fmax(r, hm / T.wbeam);
-    if (!(rn > r) || overflow) break;
-    rprev = r;
-    r = rn;
-  }
+  leaf_centre(T, blist[b], c);
   uint32_t src = 0xFFFFFFFFu;
   double fac = 1.0;
+  bool overflow = false;
   if (rprev < 0.0) {
+    // never grew: the largest member reach |x - c| + h, first slot
+    // attaining it (lanes visit their slots in increasing order, so a
+    // strict test keeps the first), unless rpp_min was larger
+    const uint2 lk = T.nlink[blist[b]];
+    double rm = -INFINITY;
+    uint32_t arg = 0xFFFFFFFFu;
+    for (uint32_t s = lk.x + lane; s < lk.x + lk.y; s += 64) {
+      const double v = sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s];
+      if (v > rm) {
+        rm = v;
+        arg = s;
+      }
+    }
+    const double rmax = wave_max(rm);
+    const uint32_t marg = wave_min_u(rm == rmax ? arg : 0xFFFFFFFFu);
     if (rmax > T.rpp_min) src = marg;
   } else {
+    // the beam rule of the last growth, over the sphere before it
     src = wave_near_argbeam(T, c, rprev * rprev, r, stack, &overflow);
     fac = 1.0 / T.wbeam;
   }
@@ -1108,32 +1101,19 @@ static unsigned grid_of(int64_t work, int threads) {
   return (unsigned)((work + threads - 1) / threads);
 }
 
-struct GradLayout {
-  Grad g;
-  size_t begin, end;   // byte range of the accumulators in the scratch
-};
-
-static GradLayout carve_grad(void* scratch, size_t at, const trevr_tree* T) {
-  Carve cv(scratch ? (char*)scratch + at : nullptr);
-  GradLayout L{};
+static Grad carve_grad(Carve& cv, const trevr_tree* T) {
+  Grad g{};
   const int64_t n = T->n, nn = T->num_nodes, B = T->B;
   const int64_t nl = std::max<int64_t>(T->num_leaves, 1);
-  L.g.gL = cv.take<double>(B * n);
-  L.g.gk = cv.take<double>(B * n);
-  L.g.gh = cv.take<double>(n);
-  L.g.gr = cv.take<double>(n);
-  L.g.galpha = cv.take<double>(nn * T->nclass * B);
-  L.g.gLb = cv.take<double>(nn * B);
-  L.g.gcen = cv.take<double>(nn * 4);
-  L.g.grpp = cv.take<double>(nl);
-  L.begin = at;
-  L.end = at + ((cv.off + 255) & ~(size_t)255);
-  return L;
-}
-
-size_t scratch_bwd_fixed_bytes(const trevr_tree* T) {
-  const size_t f = scratch_fixed_bytes(T->num_leaves);
-  return carve_grad(nullptr, f, T).end;
+  g.gL = cv.take<double>(B * n);
+  g.gk = cv.take<double>(B * n);
+  g.gh = cv.take<double>(n);
+  g.gr = cv.take<double>(n);
+  g.galpha = cv.take<double>(nn * T->nclass * B);
+  g.gLb = cv.take<double>(nn * B);
+  g.gcen = cv.take<double>(nn * 4);
+  g.grpp = cv.take<double>(nl);
+  return g;
 }
 
 #define TREVR_LAUNCH_CHECK(what)                                               \
@@ -1166,44 +1146,70 @@ static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint
   return rc;
 }
 
+// Scratch of the backward: the forward's layout (fixed part, p-p lists,
+// p-p columns), then the p-p column adjoints, the raw J per receiver and the
+// gradient accumulators.  When the scratch still holds the state of a
+// compute_J on this tree for the same active set (same buffer, equal
+// fingerprint), its bucket setup, p-p lists, p-p columns and (with a single
+// batch) cut lists are used as they are.
 trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const float* bg,
                                      const double* gJ, double* gL, double* gkappa, double* grho,
                                      void* scratch, size_t scratch_bytes) {
   hipStream_t st = T->stream;
   Scratch S = carve_scratch(scratch, T->num_leaves);
-  const GradLayout GL = carve_grad(scratch, S.fixed, T);
-  const Grad& G = GL.g;
-  if (scratch_bytes < GL.end) {
-    T->scratch_needed = GL.end;
+  if (scratch_bytes < S.fixed) {
+    T->scratch_needed = S.fixed;
     return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
   }
   trevr_status rc;
-  const int64_t words = (int64_t)((GL.end - GL.begin) / 8);
-  k_zero_u64<<<grid_of(words, 256), 256, 0, st>>>((unsigned long long*)((char*)scratch + GL.begin),
-                                                  words);
-  TREVR_LAUNCH_CHECK("k_zero_u64");
   hipEvent_t ev_setup = prof_begin(T);
+  bool reuse = false;
   uint32_t counts[3];
-  if ((rc = bucket_setup(T, active, S, counts)) != TREVR_OK) return rc;
+  if (T->fwd.valid && T->fwd.scratch == scratch) {
+    uint64_t h = 0;
+    if ((rc = active_hash(T, active, S.ahash + 1, &h)) != TREVR_OK) return rc;
+    reuse = h == T->fwd.hash;
+  }
+  uint64_t hash = T->fwd.hash;
+  if (reuse) {
+    counts[0] = T->fwd.nb;
+    counts[1] = T->fwd.near_total;
+    counts[2] = T->fwd.act_total;
+  } else {
+    T->fwd.valid = false;
+    if ((rc = bucket_setup(T, active, S, counts, &hash)) != TREVR_OK) return rc;
+  }
   const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
-  Carve dyn((char*)scratch + GL.end);
+  Carve dyn((char*)scratch + S.fixed);
   S.nidx = dyn.take<uint32_t>(near_total);
   S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
   float* gtpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
   double* jraw = dyn.take<double>((size_t)act_total * T->B);
-  const size_t need = GL.end + dyn.off + 256;
+  const size_t gbeg = (S.fixed + dyn.off + 255) & ~(size_t)255;
+  Carve gcv((char*)scratch + gbeg);
+  const Grad G = carve_grad(gcv, T);
+  const size_t gbytes = (gcv.off + 255) & ~(size_t)255;
+  const size_t need = gbeg + gbytes + 256;
   T->scratch_needed = need;
-  if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
-  if ((rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
+  if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the adjoint");
+  const int64_t words = (int64_t)(gbytes / 8);
+  k_zero_u64<<<grid_of(words, 256), 256, 0, st>>>((unsigned long long*)((char*)scratch + gbeg),
+                                                  words);
+  TREVR_LAUNCH_CHECK("k_zero_u64");
+  if (!reuse && (rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
   prof_end(T, TREVR_PROF_SETUP, ev_setup);
   for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
     const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
-    hipEvent_t ev_walk = prof_begin(T);
-    if ((rc = launch_walk(T, S, b0, nb, cnt)) != TREVR_OK) return rc;
-    prof_end(T, TREVR_PROF_WALK, ev_walk);
-    hipEvent_t ev_near = prof_begin(T);
-    if ((rc = launch_pp_rays(T, S, b0, nb, cnt, active)) != TREVR_OK) return rc;
-    prof_end(T, TREVR_PROF_NEAR, ev_near);
+    if (!reuse || nb > kBatch) {   // cut lists hold one batch
+      hipEvent_t ev_walk = prof_begin(T);
+      if ((rc = launch_walk(T, S, b0, nb, cnt)) != TREVR_OK) return rc;
+      prof_end(T, TREVR_PROF_WALK, ev_walk);
+    }
+    if (!reuse) {
+      hipEvent_t ev_near = prof_begin(T);
+      if ((rc = launch_pp_rays(T, S, b0, nb, cnt, active)) != TREVR_OK) return rc;
+      prof_end(T, TREVR_PROF_NEAR, ev_near);
+    }
     switch (T->B) {
       case 1: rc = bwd_batch<1>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
       case 2: rc = bwd_batch<2>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
@@ -1218,7 +1224,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   }
   hipEvent_t ev_tree = prof_begin(T);
   if (nb > 0) {
-    k_rpp_bwd<<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, G);
+    k_rpp_bwd<<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, S.bprev, G);
     TREVR_LAUNCH_CHECK("k_rpp_bwd");
   }
   const DevTree& D = T->dev;
@@ -1235,6 +1241,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   k_grad_out<<<grid_of(T->n, 256), 256, 0, st>>>(D, G, gL, gkappa, grho);
   TREVR_LAUNCH_CHECK("k_grad_out");
   prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
+  T->fwd = FwdState{true, scratch, hash, nb, near_total, act_total};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

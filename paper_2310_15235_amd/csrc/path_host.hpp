@@ -7,14 +7,18 @@
 
 namespace trevr {
 
-// Per-compute scratch: per-bucket arrays (a second copy for the cost
-// reordering), cost bins, cut lists of one batch; then, sized after the
+// Per-compute scratch: per-bucket arrays in processing order (and in
+// discovery order, before the cost reordering), cost bins, cut lists of one
+// batch; then, sized after the
 // bucket readback, the p-p lists and the p-p optical depths per
 // (receiver, ray, band).
 struct Scratch {
   uint32_t *blist, *bnact, *ncnt, *nlumc, *bstat, *nb;
-  uint32_t *blist2, *bnact2, *ncnt2, *nlumc2, *bbin, *bins;
-  double *brad, *brad2;
+  double *brad, *bprev;         // p-p radius; before its last growth (-1: none)
+  unsigned long long* ahash;    // [2] active-set fingerprints
+  uint32_t *blist_raw, *bnact_raw, *ncnt_raw, *nlumc_raw;
+  double *brad_raw, *bprev_raw;
+  uint32_t *bbin, *bins;
   uint2* cut;
   uint32_t* nidx;
   float* tpp;
@@ -25,8 +29,13 @@ Scratch carve_scratch(void* base, int64_t nleaves);
 
 // Active buckets, p-p radii and set sizes, heaviest-first order, offsets of
 // the p-p lists (ncnt) and of the receivers (bnact); reads back
-// counts = {buckets, p-p entries, active receivers} (synchronises).
-trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3]);
+// counts = {buckets, p-p entries, active receivers} and the active-set
+// fingerprint (synchronises).
+trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3],
+                          uint64_t* hash);
+// Fingerprint of the active set alone, computed in dev_slot (synchronises).
+trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long long* dev_slot,
+                         uint64_t* hash);
 // Fill the p-p lists (S.nidx must be set).
 trevr_status near_fill(trevr_tree* T, const Scratch& S, uint32_t nb);
 // Tree walks of buckets [b0, b0 + cnt) into the cut lists.

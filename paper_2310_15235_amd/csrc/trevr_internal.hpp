@@ -71,6 +71,16 @@ size_t layout_tree(const trevr_params& p, int64_t n, int nclass, void* base, Tre
 
 }  // namespace trevr
 
+// What the scratch holds after a compute_J (or a backward that redid the
+// setup): bucket lists, p-p radii and lists, the cut lists of the last
+// batch and the p-p columns for the active set with this fingerprint.
+struct FwdState {
+  bool valid;
+  const void* scratch;
+  uint64_t hash;
+  uint32_t nb, near_total, act_total;
+};
+
 struct trevr_tree {
   uint64_t magic;
   trevr_params p;
@@ -86,7 +96,8 @@ struct trevr_tree {
   std::vector<std::pair<uint32_t, uint32_t>> levels;  // BFS index ranges per depth
   size_t scratch_needed;
   bool counters_valid;
-  uint32_t* host_u32;                       // pinned 4-word readback buffer
+  uint32_t* host_u32;                       // pinned 8-word readback buffer
+  FwdState fwd;
   // kernel timing (trevr_profile_enable)
   bool prof_on;
   std::vector<hipEvent_t> ev_pool;
@@ -108,7 +119,6 @@ trevr_status compute_J_backward_impl(trevr_tree* t, const uint8_t* active, const
                                      const double* gJ, double* gL, double* gkappa, double* grho,
                                      void* scratch, size_t scratch_bytes);
 size_t scratch_fixed_bytes(int64_t n);
-size_t scratch_bwd_fixed_bytes(const trevr_tree* t);
 // Record an event pair around a phase (no-op unless profiling is on).
 hipEvent_t prof_begin(trevr_tree* t);
 void prof_end(trevr_tree* t, int slot, hipEvent_t begin);

@@ -183,3 +183,30 @@ def test_adjoint_repeatable_and_tree_unchanged():
     assert T.counters() == c1
     _close(J2, J1, 1e-6)
     T.close()
+
+
+def test_adjoint_reuses_forward_state_only_for_the_same_active_set():
+    """A backward after compute_J on the same scratch takes the forward's
+    setup; one after the active array changed in place recomputes it.  Both
+    must equal a backward on a fresh tree."""
+    api = _api()
+    import torch
+    sc = scenes.lognormal_scene(n=4000, seed=62, grid=16, bands=(1.0, 10.0), nside=2)
+    a1 = torch.as_tensor(scenes.active_subset(sc, 0.5, 1), device="cuda")
+    a2 = scenes.active_subset(sc, 0.3, 2)
+    g = torch.as_tensor(np.random.default_rng(9).normal(size=(2, sc.n)), device="cuda")
+    T = api.Tree.from_scene(sc)
+    T.compute_J(a1)
+    T.compute_J(a1)                      # the scratch now fits; state recorded
+    reused = [x.cpu().numpy() for x in T.compute_J_backward(g, a1)]
+    a1.copy_(torch.as_tensor(a2, device="cuda"))   # same pointer, new contents
+    redone = [x.cpu().numpy() for x in T.compute_J_backward(g, a1)]
+    T.check()
+    T.close()
+    for act, got in ((scenes.active_subset(sc, 0.5, 1), reused), (a2, redone)):
+        F = api.Tree.from_scene(sc)
+        ref = [x.cpu().numpy() for x in
+               F.compute_J_backward(g, torch.as_tensor(act, device="cuda"))]
+        F.close()
+        for u, v in zip(got, ref):
+            _close(u, v, 1e-5)
