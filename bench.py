@@ -121,10 +121,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    scratch = [None]   # one scratch buffer kept across steps, as a time-stepping caller would
+
     def step():
-        T = api.Tree(x, y, z, m, rho, kappa, lum, **kw)
+        T = api.Tree(x, y, z, m, rho, kappa, lum, scratch=scratch[0], **kw)
         T.compute_J(active, None, out=J)
         T.compute_J_backward(gJ, active, None, out=grads)
+        scratch[0] = T.scratch
         return T
 
     # warm-up (also sizes the scratch buffer once)
@@ -146,7 +149,7 @@ def main():
 
     # forward alone and forward + adjoint on a resident tree, with per-phase
     # HIP event timing recorded by the library on its stream
-    T = api.Tree(x, y, z, m, rho, kappa, lum, **kw)
+    T = api.Tree(x, y, z, m, rho, kappa, lum, scratch=scratch[0], **kw)
     T.compute_J(active, None, out=J)
     T.compute_J_backward(gJ, active, None, out=grads)
     T.profile(True)
@@ -172,7 +175,7 @@ def main():
     T.close()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
-    T = api.Tree(x, y, z, m, rho, kappa, lum, **kw)
+    T = api.Tree(x, y, z, m, rho, kappa, lum, scratch=scratch[0], **kw)
     ev1.record()
     torch.cuda.synchronize()
     ms_build = ev0.elapsed_time(ev1)

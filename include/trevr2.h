@@ -154,9 +154,11 @@ trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* 
  *   gJ     : double [n_bands][n] (device), rows of inactive elements ignored.
  * The forward's bucket setup, walks and p-p columns are needed again.  If
  * the last compute_J (or backward) on this tree used the same scratch
- * buffer and an active set with the same contents (checked on the device
- * with a 64-bit fingerprint of the active indices), they are taken from the
- * scratch as that call left them; otherwise they are recomputed.  Either
+ * buffer, no call on any tree has written that buffer since, and the active
+ * set has the same contents (checked on the device with a 64-bit
+ * fingerprint of the active indices), they are taken from the scratch as
+ * that call left them; otherwise they are recomputed.  The caller must not
+ * write the scratch between the calls.  Either
  * way the result is the same.  Synchronises `stream` once or twice and needs
  * more scratch than compute_J (accumulators per node, class and band, and a
  * second p-p column buffer, placed after compute_J's part of the scratch):

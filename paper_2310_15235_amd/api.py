@@ -131,7 +131,11 @@ class Tree:
     """A radiation tree built on the GPU; owns its workspace tensor."""
 
     def __init__(self, x, y, z, m, rho, kappa, lum, *, nside=2, leaf_size=8, theta=0.75,
-                 flags=THICK_CORR | NEAR_FIELD, rpp_min=0.0, box=None):
+                 flags=THICK_CORR | NEAR_FIELD, rpp_min=0.0, box=None, scratch=None):
+        """``scratch`` (optional): a uint8 device tensor to use as the
+        compute scratch, e.g. ``previous_tree.scratch`` when stepping through
+        scenes of similar size; it is replaced by a larger one when a call
+        needs more (``self.scratch`` is always the current one)."""
         torch = _torch()
         n = int(x.shape[0])
         B = int(kappa.shape[0])
@@ -140,7 +144,10 @@ class Tree:
         tb, sb = workspace_bytes(self.params, n)
         self.device = x.device
         self.ws = torch.empty(tb, dtype=torch.uint8, device=x.device)
-        self._scratch = torch.empty(sb, dtype=torch.uint8, device=x.device)
+        if scratch is not None and scratch.numel() >= sb:
+            self._scratch = scratch
+        else:
+            self._scratch = torch.empty(sb, dtype=torch.uint8, device=x.device)
         f = torch.float32
         h = ctypes.c_void_p()
         _check(lib().trevr_build_tree(ctypes.byref(self.params), n, _dev(x, f), _dev(y, f),
@@ -206,6 +213,10 @@ class Tree:
                 self.handle, a, g, _dev(gJ, f64), _dev(gL, f64), _dev(gk, f64), _dev(gr, f64),
                 sp, sb, _stream_ptr()), "trevr_compute_J_backward")
         return gL, gk, gr
+
+    @property
+    def scratch(self):
+        return self._scratch
 
     def check(self):
         _check(lib().trevr_check(self.handle), "trevr_check")

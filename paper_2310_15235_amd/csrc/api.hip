@@ -166,7 +166,7 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->prof_on = false;
   T->ev_used = 0;
   T->host_u32 = nullptr;
-  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0};
+  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0};
   for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }
   const size_t need = layout_tree(*p, n, T->nclass, nullptr, nullptr);
   if (tree_ws_bytes < need) {

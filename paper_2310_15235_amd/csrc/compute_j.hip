@@ -32,6 +32,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 #include "path_device.hpp"
 #include "path_host.hpp"
@@ -753,6 +755,25 @@ static Scratch carve(void* base, int64_t nleaves) {
 }
 
 Scratch carve_scratch(void* base, int64_t nleaves) { return carve(base, nleaves); }
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<const void*, uint64_t> g_scratch_epoch;
+uint64_t g_epoch = 0;
+}  // namespace
+
+uint64_t scratch_mark(const void* scratch) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_epoch.size() > 4096) g_scratch_epoch.clear();   // only disables reuse
+  g_scratch_epoch[scratch] = ++g_epoch;
+  return g_epoch;
+}
+
+bool scratch_unchanged(const void* scratch, uint64_t epoch) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  const auto it = g_scratch_epoch.find(scratch);
+  return it != g_scratch_epoch.end() && it->second == epoch;
+}
 size_t scratch_fixed_bytes(int64_t n) { return carve(nullptr, n).fixed; }
 
 #define TREVR_LAUNCH_CHECK(what)                                               \
@@ -899,6 +920,7 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   }
   trevr_status rc;
   T->fwd.valid = false;
+  const uint64_t epoch = scratch_mark(scratch);
   if ((rc = hip_check(hipMemsetAsync(T->buf.counters, 0, sizeof(unsigned long long) * CNT_N, st),
                       "memset counters")) != TREVR_OK) return rc;
   hipEvent_t ev_setup = prof_begin(T);
@@ -932,7 +954,7 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
     if (rc != TREVR_OK) return rc;
   }
   T->counters_valid = true;
-  T->fwd = FwdState{true, scratch, hash, nb, near_total, act_total};
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

@@ -1149,9 +1149,9 @@ static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint
 // Scratch of the backward: the forward's layout (fixed part, p-p lists,
 // p-p columns), then the p-p column adjoints, the raw J per receiver and the
 // gradient accumulators.  When the scratch still holds the state of a
-// compute_J on this tree for the same active set (same buffer, equal
-// fingerprint), its bucket setup, p-p lists, p-p columns and (with a single
-// batch) cut lists are used as they are.
+// compute_J on this tree for the same active set (same buffer, not written
+// by any call since, equal fingerprint), its bucket setup, p-p lists, p-p
+// columns and (with a single batch) cut lists are used as they are.
 trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const float* bg,
                                      const double* gJ, double* gL, double* gkappa, double* grho,
                                      void* scratch, size_t scratch_bytes) {
@@ -1165,7 +1165,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   hipEvent_t ev_setup = prof_begin(T);
   bool reuse = false;
   uint32_t counts[3];
-  if (T->fwd.valid && T->fwd.scratch == scratch) {
+  if (T->fwd.valid && T->fwd.scratch == scratch && scratch_unchanged(scratch, T->fwd.epoch)) {
     uint64_t h = 0;
     if ((rc = active_hash(T, active, S.ahash + 1, &h)) != TREVR_OK) return rc;
     reuse = h == T->fwd.hash;
@@ -1192,6 +1192,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   const size_t need = gbeg + gbytes + 256;
   T->scratch_needed = need;
   if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the adjoint");
+  const uint64_t epoch = scratch_mark(scratch);
   const int64_t words = (int64_t)(gbytes / 8);
   k_zero_u64<<<grid_of(words, 256), 256, 0, st>>>((unsigned long long*)((char*)scratch + gbeg),
                                                   words);
@@ -1241,7 +1242,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   k_grad_out<<<grid_of(T->n, 256), 256, 0, st>>>(D, G, gL, gkappa, grho);
   TREVR_LAUNCH_CHECK("k_grad_out");
   prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
-  T->fwd = FwdState{true, scratch, hash, nb, near_total, act_total};
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

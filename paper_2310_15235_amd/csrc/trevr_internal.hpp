@@ -77,6 +77,7 @@ size_t layout_tree(const trevr_params& p, int64_t n, int nclass, void* base, Tre
 struct FwdState {
   bool valid;
   const void* scratch;
+  uint64_t epoch;       // the library's write to that scratch that left it
   uint64_t hash;
   uint32_t nb, near_total, act_total;
 };
@@ -119,6 +120,11 @@ trevr_status compute_J_backward_impl(trevr_tree* t, const uint8_t* active, const
                                      const double* gJ, double* gL, double* gkappa, double* grho,
                                      void* scratch, size_t scratch_bytes);
 size_t scratch_fixed_bytes(int64_t n);
+// Every call that writes a scratch buffer takes a new epoch for it; a
+// state recorded at epoch e is still in the buffer iff no call (on any
+// tree) has written it since.
+uint64_t scratch_mark(const void* scratch);
+bool scratch_unchanged(const void* scratch, uint64_t epoch);
 // Record an event pair around a phase (no-op unless profiling is on).
 hipEvent_t prof_begin(trevr_tree* t);
 void prof_end(trevr_tree* t, int slot, hipEvent_t begin);

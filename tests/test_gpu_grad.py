@@ -210,3 +210,29 @@ def test_adjoint_reuses_forward_state_only_for_the_same_active_set():
         F.close()
         for u, v in zip(got, ref):
             _close(u, v, 1e-5)
+
+
+def test_adjoint_with_scratch_shared_between_trees():
+    """Tree B's forward on a scratch shared with tree A overwrites A's state;
+    A's backward must then recompute, not reuse B's setup."""
+    api = _api()
+    import torch
+    sa = scenes.lognormal_scene(n=3000, seed=63, grid=16, bands=(1.0, 10.0), nside=2)
+    sb = scenes.uniform_scene(n=2000, seed=64, n_src=50, bands=(1.0, 10.0), nside=2)
+    g = torch.as_tensor(np.random.default_rng(10).normal(size=(2, sa.n)), device="cuda")
+    A = api.Tree.from_scene(sa)
+    A.compute_J()
+    A.compute_J_backward(g)              # sizes A's scratch for the backward
+    Bt = api.Tree.from_scene(sb)
+    Bt._scratch = A.scratch              # share it
+    Bt.compute_J()
+    assert Bt.scratch.data_ptr() == A.scratch.data_ptr()   # it fitted: B wrote A's scratch
+    got = [x.cpu().numpy() for x in A.compute_J_backward(g)]
+    A.check()
+    Bt.check()
+    F = api.Tree.from_scene(sa)
+    ref = [x.cpu().numpy() for x in F.compute_J_backward(g)]
+    for u, v in zip(got, ref):
+        _close(u, v, 1e-5)
+    for t in (A, Bt, F):
+        t.close()
