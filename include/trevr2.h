@@ -23,11 +23,13 @@
  *     workspace and the scratch buffer, sized with trevr_workspace_bytes.
  *   - Every call returns a trevr_status and never throws.  Parameter and
  *     size errors are found on the host before any launch (TREVR_E_INVALID,
- *     TREVR_E_CAPACITY).  Errors found on the device (non-positive mass or
- *     density, non-finite input, a buffer too small for the data) raise a
- *     sticky per-tree flag reported by trevr_check or the next call that
- *     synchronises (TREVR_E_DATA, TREVR_E_CAPACITY).  HIP runtime failures
- *     map to TREVR_E_HIP with the text in trevr_last_error().
+ *     TREVR_E_CAPACITY).  Invalid element data found on the device
+ *     (non-positive mass or density, non-finite input) raises a sticky
+ *     per-tree flag reported by trevr_check (TREVR_E_DATA).  Per-bucket
+ *     buffers that turn out too small during a call (traversal stacks, cut
+ *     lists) are handled inside the call, which redoes that step with more
+ *     room.  HIP runtime failures map to TREVR_E_HIP with the text in
+ *     trevr_last_error().
  */
 #ifndef TREVR2_H
 #define TREVR2_H
@@ -129,8 +131,10 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
  *   J      : double [n_bands][n], input order; rows of inactive elements are
  *            not written.
  *   scratch: device buffer of scratch_bytes bytes.
- * Synchronises `stream` once (to size the p-p lists).  Returns
- * TREVR_E_CAPACITY, writing no J, if scratch is too small.  Cell optical
+ * Synchronises `stream` to size the p-p lists and once per batch of 65536
+ * buckets after the walks (to see whether a cut list or a traversal stack
+ * needs more room).  Returns TREVR_E_CAPACITY, writing no J, if scratch is
+ * too small.  Cell optical
  * depths are summed with LDS atomics, so repeated calls agree to FP32
  * rounding of those sums (about 1e-7 relative), not bit for bit.
  */
@@ -159,7 +163,7 @@ trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* 
  * fingerprint of the active indices), they are taken from the scratch as
  * that call left them; otherwise they are recomputed.  The caller must not
  * write the scratch between the calls.  Either
- * way the result is the same.  Synchronises `stream` once or twice and needs
+ * way the result is the same.  Synchronises `stream` one to three times and needs
  * more scratch than compute_J (accumulators per node, class and band, and a
  * second p-p column buffer, placed after compute_J's part of the scratch):
  * on TREVR_E_CAPACITY trevr_scratch_needed gives the size.

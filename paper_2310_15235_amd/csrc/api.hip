@@ -166,7 +166,8 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->prof_on = false;
   T->ev_used = 0;
   T->host_u32 = nullptr;
-  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0};
+  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, false};
+  T->stack_large = false;
   for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }
   const size_t need = layout_tree(*p, n, T->nclass, nullptr, nullptr);
   if (tree_ws_bytes < need) {
@@ -244,8 +245,6 @@ static trevr_status read_err(trevr_tree* t) {
   trevr_status rc = hip_check(he, "error readback");
   if (rc != TREVR_OK) return rc;
   if (e & ERR_DATA) return set_error(TREVR_E_DATA, "non-positive or non-finite element data");
-  if (e & (ERR_STACK | ERR_CUT | ERR_SRC))
-    return set_error(TREVR_E_CAPACITY, "a per-bucket buffer overflowed (code " + std::to_string(e) + ")");
   return TREVR_OK;
 }
 

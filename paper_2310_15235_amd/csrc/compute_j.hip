@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <unordered_map>
 
@@ -80,12 +81,13 @@ __global__ void k_active_hash(const uint8_t* active, int64_t n, unsigned long lo
 // wavefront per bucket.
 // Also records the radius before the last growth (-1 if it never grew),
 // which tells the adjoint which element set the final radius.
+template <int SC>
 __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
                                               const uint32_t* nbp, double* brad, double* bprev,
-                                              uint32_t* ncnt, uint32_t* nlumc) {
+                                              uint32_t* ncnt, uint32_t* nlumc, uint32_t* ovf) {
   const uint32_t b = blockIdx.x;
   if (b >= *nbp) return;
-  __shared__ uint32_t stack[kStackCap];
+  __shared__ uint32_t stack[SC];
   const int lane = threadIdx.x;
   const uint32_t leaf = blist[b];
   double c[3];
@@ -102,7 +104,7 @@ __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
     r = fmax(r, wave_max(rm));
     for (;;) {
       double hm = 0.0;
-      cnt = wave_near(T, c, r * r, stack, &hm, &nlum, nullptr, 0, &overflow);
+      cnt = wave_near(T, c, r * r, stack, SC, &hm, &nlum, nullptr, 0, &overflow);
       const double rn = fmax(r, hm / T.wbeam);
       if (!(rn > r) || overflow) break;
       rprev = r;
@@ -114,38 +116,45 @@ __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
     bprev[b] = rprev;
     ncnt[b] = cnt;
     nlumc[b] = nlum;
-    if (overflow) atomicOr(T.err, ERR_STACK);
+    if (overflow) atomicOr(ovf, OVF_SETUP);
   }
 }
 
+// Same spheres as the last query of k_setup, so the same stack suffices.
+template <int SC>
 __global__ void __launch_bounds__(64) k_near_fill(DevTree T, const uint32_t* blist,
                                                   const uint32_t* nbp, const double* brad,
                                                   const uint32_t* noff, const uint32_t* nlumc,
                                                   uint32_t* nidx) {
   const uint32_t b = blockIdx.x;
   if (b >= *nbp || !(T.flags & TREVR_NEAR_FIELD)) return;
-  __shared__ uint32_t stack[kStackCap];
+  __shared__ uint32_t stack[SC];
   double c[3];
   leaf_centre(T, blist[b], c);
   const double r = brad[b];
   bool overflow = false;
-  wave_near(T, c, r * r, stack, nullptr, nullptr, nidx + noff[b], nlumc[b], &overflow);
+  wave_near(T, c, r * r, stack, SC, nullptr, nullptr, nidx + noff[b], nlumc[b], &overflow);
 }
 
 // ------------------------------------------------------------- the walk
+// Cut lists hold cap entries per bucket; a bucket that needs more still
+// counts them all (bstat, and the batch maximum in ovf[1]) so the host can
+// walk it again with room for them.
+template <int SC>
 __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
                                              const double* brad, uint32_t b0, uint32_t nbuck,
-                                             uint2* cut, uint32_t* bstat) {
+                                             uint2* cut, uint32_t cap, uint32_t* bstat,
+                                             uint32_t* ovf) {
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
-  __shared__ uint32_t stack[kStackCap];
+  __shared__ uint32_t stack[SC];
   const int lane = threadIdx.x;
   const uint32_t leafb = blist[bucket];
   const double r = brad[bucket];
   const double r2 = r * r;
   double c[3];
   leaf_centre(T, leafb, c);
-  uint2* out = cut + (size_t)blockIdx.x * kCutCap;
+  uint2* out = cut + (size_t)blockIdx.x * cap;
   uint32_t ncut = 0, nsrc = 0, ncells = 0;
   bool overflow = false;
   int sp = 1;
@@ -176,7 +185,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
     const uint64_t pm = ballot64(push);
     const int ppos = mbcnt(pm);
     const int npush = __popcll(pm);
-    if (sp + 2 * npush > kStackCap) {
+    if (sp + 2 * npush > SC) {
       overflow = true;
       break;
     }
@@ -204,7 +213,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
     const uint64_t wm = ballot64(write);
     if (write) {
       const uint32_t idx = ncut + (uint32_t)mbcnt(wm);
-      if (idx < kCutCap) out[idx] = make_uint2(node, meta);
+      if (idx < cap) out[idx] = make_uint2(node, meta);
     }
     ncut += (uint32_t)__popcll(wm);
     nsrc += (uint32_t)__popcll(ballot64(write && ((meta & 0xFFFFu) != CUT_NOPIX)));
@@ -229,7 +238,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
         const uint64_t sm = ballot64(is_src);
         if (is_src) {
           const uint32_t idx = ncut + (uint32_t)mbcnt(sm);
-          if (idx < kCutCap) out[idx] = make_uint2(s, CUT_PART | pix);
+          if (idx < cap) out[idx] = make_uint2(s, CUT_PART | pix);
         }
         ncut += (uint32_t)__popcll(sm);
         nsrc += (uint32_t)__popcll(sm);
@@ -241,8 +250,8 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
     bstat[4 * bucket + 0] = ncut;
     bstat[4 * bucket + 1] = nsrc;
     bstat[4 * bucket + 2] = ncells;
-    if (overflow) atomicOr(T.err, ERR_STACK);
-    if (ncut > kCutCap) atomicOr(T.err, ERR_CUT);
+    if (overflow) atomicOr(ovf, OVF_WALK);
+    atomicMax(ovf + 1, ncut);
     atomic_max_u64(&T.counters[CNT_MAX_CUT], ncut);
   }
 }
@@ -484,9 +493,9 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
 template <int NB>
 __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, const double* brad,
                                              const uint32_t* roff, uint32_t b0, uint32_t nbuck,
-                                             const uint2* cut, const uint32_t* bstat,
-                                             const float* tppg, const float* bg, double* J,
-                                             const uint8_t* active) {
+                                             const uint2* cut, uint32_t cut_cap,
+                                             const uint32_t* bstat, const float* tppg,
+                                             const float* bg, double* J, const uint8_t* active) {
   constexpr int kSrcCap = SrcCap<NB>::value;
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
@@ -504,8 +513,8 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
   const double r = brad[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
-  const uint32_t ncut = min(bstat[4 * bucket + 0], kCutCap);
-  const uint2* mycut = cut + (size_t)blockIdx.x * kCutCap;
+  const uint32_t ncut = min(bstat[4 * bucket + 0], cut_cap);
+  const uint2* mycut = cut + (size_t)blockIdx.x * cut_cap;
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
   const int ngroups = (nray + 63) / 64;
@@ -730,6 +739,7 @@ static Scratch carve(void* base, int64_t nleaves) {
   Scratch s{};
   const int64_t L = std::max<int64_t>(nleaves, 1);
   s.nb = cv.take<uint32_t>(4);           // buckets, p-p total, active total
+  s.ovf = cv.take<uint32_t>(4);          // overflow bits, largest cut of a batch
   // buckets in processing order (heaviest first); bnact and ncnt are
   // scanned in place into receiver and p-p list offsets
   s.blist = cv.take<uint32_t>(L);
@@ -749,7 +759,8 @@ static Scratch carve(void* base, int64_t nleaves) {
   s.bprev_raw = cv.take<double>(L);
   s.bbin = cv.take<uint32_t>(L);
   s.bins = cv.take<uint32_t>(kCostBins);
-  s.cut = cv.take<uint2>((size_t)std::min<int64_t>(L, kBatch) * kCutCap);
+  s.cut_entries = (size_t)std::min<int64_t>(L, kBatch) * kCutCap;
+  s.cut = cv.take<uint2>(s.cut_entries);
   s.fixed = ((cv.off + 255) & ~(size_t)255) + 256;   // 256-aligned
   return s;
 }
@@ -787,49 +798,70 @@ trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint
   const int64_t nleaves = T->num_leaves;
   const DevTree& D = T->dev;
   trevr_status rc;
-  if ((rc = hip_check(hipMemsetAsync(S.nb, 0, sizeof(uint32_t) * 4, st), "memset")) != TREVR_OK)
-    return rc;
-  k_active_buckets<<<(unsigned)((T->num_nodes + 255) / 256), 256, 0, st>>>(D, active, S.blist_raw,
-                                                                            S.bnact_raw, S.nb);
-  TREVR_LAUNCH_CHECK("k_active_buckets");
-  k_setup<<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist_raw, S.nb, S.brad_raw, S.bprev_raw,
-                                            S.ncnt_raw, S.nlumc_raw);
-  TREVR_LAUNCH_CHECK("k_setup");
-  // heaviest buckets first, into the primary arrays (zero past the last
-  // bucket for the scans)
-  if ((rc = hip_check(hipMemsetAsync(S.bins, 0, sizeof(uint32_t) * kCostBins, st), "memset")) != TREVR_OK)
-    return rc;
-  if ((rc = hip_check(hipMemsetAsync(S.ncnt, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
-    return rc;
-  if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st), "memset")) != TREVR_OK)
-    return rc;
-  k_cost_bins<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(S.nb, S.bnact_raw, S.ncnt_raw,
-                                                                 S.nlumc_raw, T->nray, S.bbin,
-                                                                 S.bins);
-  TREVR_LAUNCH_CHECK("k_cost_bins");
-  k_bins_scan<<<1, 64, 0, st>>>(S.bins);
-  TREVR_LAUNCH_CHECK("k_bins_scan");
-  k_reorder<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(
-      S.nb, S.bbin, S.bins, S.blist_raw, S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw,
-      S.bprev_raw, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev);
-  TREVR_LAUNCH_CHECK("k_reorder");
-  k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.nb + 1);
-  TREVR_LAUNCH_CHECK("k_scan_u32");
-  k_scan_u32<<<1, 1024, 0, st>>>(S.bnact, nleaves + 1, S.nb + 2);
-  TREVR_LAUNCH_CHECK("k_scan_u32");
-  if ((rc = hip_check(hipMemsetAsync(S.ahash, 0, sizeof(unsigned long long), st), "memset")) !=
-      TREVR_OK)
-    return rc;
-  k_active_hash<<<(unsigned)((T->n + 255) / 256), 256, 0, st>>>(active, T->n, S.ahash);
-  TREVR_LAUNCH_CHECK("k_active_hash");
-  uint32_t* hbuf = T->host_u32;
-  hipError_t e = hipMemcpyAsync(hbuf, S.nb, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hbuf + 4, S.ahash, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if ((rc = hip_check(e, "bucket readback")) != TREVR_OK) return rc;
-  for (int i = 0; i < 3; ++i) counts[i] = hbuf[i];
-  std::memcpy(hash, hbuf + 4, sizeof(uint64_t));
+  for (;;) {
+    if ((rc = hip_check(hipMemsetAsync(S.nb, 0, sizeof(uint32_t) * 4, st), "memset")) != TREVR_OK)
+      return rc;
+    if ((rc = hip_check(hipMemsetAsync(S.ovf, 0, sizeof(uint32_t) * 4, st), "memset")) != TREVR_OK)
+      return rc;
+    k_active_buckets<<<(unsigned)((T->num_nodes + 255) / 256), 256, 0, st>>>(
+        D, active, S.blist_raw, S.bnact_raw, S.nb);
+    TREVR_LAUNCH_CHECK("k_active_buckets");
+    if (T->stack_large)
+      k_setup<kStackLarge><<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist_raw, S.nb, S.brad_raw,
+                                                             S.bprev_raw, S.ncnt_raw,
+                                                             S.nlumc_raw, S.ovf);
+    else
+      k_setup<kStackSmall><<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist_raw, S.nb, S.brad_raw,
+                                                             S.bprev_raw, S.ncnt_raw,
+                                                             S.nlumc_raw, S.ovf);
+    TREVR_LAUNCH_CHECK("k_setup");
+    // heaviest buckets first, into the primary arrays (zero past the last
+    // bucket for the scans)
+    if ((rc = hip_check(hipMemsetAsync(S.bins, 0, sizeof(uint32_t) * kCostBins, st), "memset")) !=
+        TREVR_OK)
+      return rc;
+    if ((rc = hip_check(hipMemsetAsync(S.ncnt, 0, sizeof(uint32_t) * (nleaves + 1), st),
+                        "memset")) != TREVR_OK)
+      return rc;
+    if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st),
+                        "memset")) != TREVR_OK)
+      return rc;
+    k_cost_bins<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(S.nb, S.bnact_raw, S.ncnt_raw,
+                                                                   S.nlumc_raw, T->nray, S.bbin,
+                                                                   S.bins);
+    TREVR_LAUNCH_CHECK("k_cost_bins");
+    k_bins_scan<<<1, 64, 0, st>>>(S.bins);
+    TREVR_LAUNCH_CHECK("k_bins_scan");
+    k_reorder<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(
+        S.nb, S.bbin, S.bins, S.blist_raw, S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw,
+        S.bprev_raw, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev);
+    TREVR_LAUNCH_CHECK("k_reorder");
+    k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.nb + 1);
+    TREVR_LAUNCH_CHECK("k_scan_u32");
+    k_scan_u32<<<1, 1024, 0, st>>>(S.bnact, nleaves + 1, S.nb + 2);
+    TREVR_LAUNCH_CHECK("k_scan_u32");
+    if ((rc = hip_check(hipMemsetAsync(S.ahash, 0, sizeof(unsigned long long), st), "memset")) !=
+        TREVR_OK)
+      return rc;
+    k_active_hash<<<(unsigned)((T->n + 255) / 256), 256, 0, st>>>(active, T->n, S.ahash);
+    TREVR_LAUNCH_CHECK("k_active_hash");
+    uint32_t* hbuf = T->host_u32;
+    hipError_t e = hipMemcpyAsync(hbuf, S.nb, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hbuf + 3, S.ovf, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hbuf + 4, S.ahash, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if ((rc = hip_check(e, "bucket readback")) != TREVR_OK) return rc;
+    if (!(hbuf[3] & OVF_SETUP)) break;
+    // a p-p range query ran out of the small traversal stack: use the
+    // large one for this tree from now on
+    if (T->stack_large)
+      return set_error(TREVR_E_CAPACITY, "a p-p range query exceeds the traversal stack");
+    T->stack_large = true;
+  }
+  for (int i = 0; i < 3; ++i) counts[i] = T->host_u32[i];
+  std::memcpy(hash, T->host_u32 + 4, sizeof(uint64_t));
   return TREVR_OK;
 }
 
@@ -854,17 +886,70 @@ trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long lon
 trevr_status near_fill(trevr_tree* T, const Scratch& S, uint32_t nb) {
   trevr_status rc = TREVR_OK;
   if (nb > 0) {
-    k_near_fill<<<nb, 64, 0, T->stream>>>(T->dev, S.blist, S.nb, S.brad, S.ncnt, S.nlumc, S.nidx);
+    if (T->stack_large)
+      k_near_fill<kStackLarge><<<nb, 64, 0, T->stream>>>(T->dev, S.blist, S.nb, S.brad, S.ncnt,
+                                                         S.nlumc, S.nidx);
+    else
+      k_near_fill<kStackSmall><<<nb, 64, 0, T->stream>>>(T->dev, S.blist, S.nb, S.brad, S.ncnt,
+                                                         S.nlumc, S.nidx);
     TREVR_LAUNCH_CHECK("k_near_fill");
   }
   return rc;
 }
 
-trevr_status launch_walk(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb, uint32_t cnt) {
+static trevr_status walk_launch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                                uint32_t cnt, uint32_t cap) {
   trevr_status rc;
-  k_walk<<<cnt, 64, 0, T->stream>>>(T->dev, S.blist, S.brad, b0, nb, S.cut, S.bstat);
+  if ((rc = hip_check(hipMemsetAsync(S.ovf, 0, sizeof(uint32_t) * 2, T->stream), "memset")) !=
+      TREVR_OK)
+    return rc;
+  if (T->stack_large)
+    k_walk<kStackLarge><<<cnt, 64, 0, T->stream>>>(T->dev, S.blist, S.brad, b0, nb, S.cut, cap,
+                                                   S.bstat, S.ovf);
+  else
+    k_walk<kStackSmall><<<cnt, 64, 0, T->stream>>>(T->dev, S.blist, S.brad, b0, nb, S.cut, cap,
+                                                   S.bstat, S.ovf);
   TREVR_LAUNCH_CHECK("k_walk");
   return rc;
+}
+
+trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t cnt, uint32_t nb,
+                        const std::function<trevr_status(uint32_t, uint32_t, uint32_t)>& run,
+                        bool* whole) {
+  trevr_status rc;
+  uint32_t* hbuf = T->host_u32;
+  for (;;) {
+    hipEvent_t ev = prof_begin(T);
+    if ((rc = walk_launch(T, S, b0, nb, cnt, kCutCap)) != TREVR_OK) return rc;
+    prof_end(T, TREVR_PROF_WALK, ev);
+    hipError_t e = hipMemcpyAsync(hbuf, S.ovf, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  T->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(T->stream);
+    if ((rc = hip_check(e, "walk readback")) != TREVR_OK) return rc;
+    if (!(hbuf[0] & OVF_WALK)) break;
+    if (T->stack_large) return set_error(TREVR_E_CAPACITY, "a tree walk exceeds the traversal stack");
+    T->stack_large = true;
+  }
+  const uint32_t maxcut = hbuf[1];
+  if (maxcut <= kCutCap) {
+    *whole = true;
+    return run(b0, cnt, kCutCap);
+  }
+  // some bucket needs a longer cut list: walk the batch again in parts that
+  // fit the cut buffer with room for the longest
+  *whole = false;
+  const size_t cap2 = ((size_t)maxcut + 255) & ~(size_t)255;
+  if (cap2 > S.cut_entries)
+    return set_error(TREVR_E_CAPACITY, "a bucket's cut list exceeds the cut-list buffer");
+  const uint32_t per = (uint32_t)std::max<size_t>(1, S.cut_entries / cap2);
+  for (uint32_t s0 = b0; s0 < b0 + cnt; s0 += per) {
+    const uint32_t scnt = std::min<uint32_t>(per, b0 + cnt - s0);
+    hipEvent_t ev = prof_begin(T);
+    if ((rc = walk_launch(T, S, s0, nb, scnt, (uint32_t)cap2)) != TREVR_OK) return rc;
+    prof_end(T, TREVR_PROF_WALK, ev);
+    if ((rc = run(s0, scnt, (uint32_t)cap2)) != TREVR_OK) return rc;
+  }
+  return TREVR_OK;
 }
 
 template <int NB>
@@ -893,7 +978,8 @@ trevr_status launch_pp_rays(trevr_tree* T, const Scratch& S, uint32_t b0, uint32
 
 template <int NB>
 static trevr_status launch_pair(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                                uint32_t cnt, const float* bg, double* J, const uint8_t* active) {
+                                uint32_t cnt, uint32_t cap, const float* bg, double* J,
+                                const uint8_t* active) {
   hipStream_t st = T->stream;
   const DevTree& D = T->dev;
   trevr_status rc;
@@ -903,8 +989,8 @@ static trevr_status launch_pair(trevr_tree* T, const Scratch& S, uint32_t b0, ui
   TREVR_LAUNCH_CHECK("k_pp_src");
   prof_end(T, TREVR_PROF_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
-  k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp, bg,
-                                J, active);
+  k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, cap, S.bstat, S.tpp,
+                                bg, J, active);
   TREVR_LAUNCH_CHECK("k_far");
   prof_end(T, TREVR_PROF_REDUCE, e1);
   return rc;
@@ -936,25 +1022,26 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
   if ((rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
   prof_end(T, TREVR_PROF_SETUP, ev_setup);
+  bool whole = true;
   for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
     const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
-    hipEvent_t ev_walk = prof_begin(T);
-    if ((rc = launch_walk(T, S, b0, nb, cnt)) != TREVR_OK) return rc;
-    prof_end(T, TREVR_PROF_WALK, ev_walk);
-    switch (T->B) {
-      case 1: rc = launch_pair<1>(T, S, b0, nb, cnt, bg, J, active); break;
-      case 2: rc = launch_pair<2>(T, S, b0, nb, cnt, bg, J, active); break;
-      case 3: rc = launch_pair<3>(T, S, b0, nb, cnt, bg, J, active); break;
-      case 4: rc = launch_pair<4>(T, S, b0, nb, cnt, bg, J, active); break;
-      case 5: rc = launch_pair<5>(T, S, b0, nb, cnt, bg, J, active); break;
-      case 6: rc = launch_pair<6>(T, S, b0, nb, cnt, bg, J, active); break;
-      case 7: rc = launch_pair<7>(T, S, b0, nb, cnt, bg, J, active); break;
-      default: rc = launch_pair<8>(T, S, b0, nb, cnt, bg, J, active); break;
-    }
+    rc = walk_batch(T, S, b0, cnt, nb, [&](uint32_t s0, uint32_t scnt, uint32_t cap) {
+      switch (T->B) {
+        case 1: return launch_pair<1>(T, S, s0, nb, scnt, cap, bg, J, active);
+        case 2: return launch_pair<2>(T, S, s0, nb, scnt, cap, bg, J, active);
+        case 3: return launch_pair<3>(T, S, s0, nb, scnt, cap, bg, J, active);
+        case 4: return launch_pair<4>(T, S, s0, nb, scnt, cap, bg, J, active);
+        case 5: return launch_pair<5>(T, S, s0, nb, scnt, cap, bg, J, active);
+        case 6: return launch_pair<6>(T, S, s0, nb, scnt, cap, bg, J, active);
+        case 7: return launch_pair<7>(T, S, s0, nb, scnt, cap, bg, J, active);
+        default: return launch_pair<8>(T, S, s0, nb, scnt, cap, bg, J, active);
+      }
+    }, &whole);
     if (rc != TREVR_OK) return rc;
   }
   T->counters_valid = true;
-  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total};
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total,
+                    nb <= kBatch && whole};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

@@ -492,7 +492,8 @@ template <int NB>
 __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, const uint32_t* blist,
                                                  const double* brad, const uint32_t* roff,
                                                  uint32_t b0, uint32_t nbuck, const uint2* cut,
-                                                 const uint32_t* bstat, const float* tppg,
+                                                 uint32_t cut_cap, const uint32_t* bstat,
+                                                 const float* tppg,
                                                  const float* bg, const uint8_t* active,
                                                  const double* gJ, const double* jraw,
                                                  float* gtppg, Grad G) {
@@ -516,8 +517,8 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
   const double r = brad[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
-  const uint32_t ncut = min(bstat[4 * bucket + 0], kCutCap);
-  const uint2* mycut = cut + (size_t)blockIdx.x * kCutCap;
+  const uint32_t ncut = min(bstat[4 * bucket + 0], cut_cap);
+  const uint2* mycut = cut + (size_t)blockIdx.x * cut_cap;
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
   const int ngroups = (nray + 63) / 64;
@@ -889,9 +890,10 @@ __device__ inline uint32_t wave_min_u(uint32_t v) {
 }
 
 // Smallest sorted slot among elements strictly within sqrt(r2) of c with
-// h / w == target (one wavefront; stack of kStackCap words in LDS).
+// h / w == target (one wavefront; stack of cap words in LDS).
 __device__ inline uint32_t wave_near_argbeam(const DevTree& T, const double c[3], double r2,
-                                             double target, uint32_t* stack, bool* overflow) {
+                                             double target, uint32_t* stack, int cap,
+                                             bool* overflow) {
   const int lane = threadIdx.x & 63;
   const double prune = r2 * (1.0 + 1e-9);
   uint32_t best = 0xFFFFFFFFu;
@@ -924,7 +926,7 @@ __device__ inline uint32_t wave_near_argbeam(const DevTree& T, const double c[3]
     }
     const uint64_t pm = ballot64(push);
     const int npush = __popcll(pm);
-    if (sp + 2 * npush > kStackCap) {
+    if (sp + 2 * npush > cap) {
       *overflow = true;
       break;
     }
@@ -939,6 +941,9 @@ __device__ inline uint32_t wave_near_argbeam(const DevTree& T, const double c[3]
   return wave_min_u(best);
 }
 
+// (The sphere before the last growth is inside the final one, so the stack
+// that sufficed for the p-p radius suffices here.)
+template <int SC>
 __global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist,
                                                 const uint32_t* nbp, const double* brad,
                                                 const double* bprev, Grad G) {
@@ -946,7 +951,7 @@ __global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist
   if (b >= *nbp || !(T.flags & TREVR_NEAR_FIELD)) return;
   const double g = G.grpp[b];
   if (g == 0.0) return;
-  __shared__ uint32_t stack[kStackCap];
+  __shared__ uint32_t stack[SC];
   const int lane = threadIdx.x;
   const double r = brad[b], rprev = bprev[b];
   double c[3];
@@ -973,7 +978,7 @@ __global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist
     if (rmax > T.rpp_min) src = marg;
   } else {
     // the beam rule of the last growth, over the sphere before it
-    src = wave_near_argbeam(T, c, rprev * rprev, r, stack, &overflow);
+    src = wave_near_argbeam(T, c, rprev * rprev, r, stack, SC, &overflow);
     fac = 1.0 / T.wbeam;
   }
   if (lane == 0 && src != 0xFFFFFFFFu && !overflow) gadd(&G.gh[src], g * fac);
@@ -1123,7 +1128,7 @@ static Grad carve_grad(Carve& cv, const trevr_tree* T) {
 
 template <int NB>
 static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                              uint32_t cnt, const uint8_t* active, const float* bg,
+                              uint32_t cnt, uint32_t cap, const uint8_t* active, const float* bg,
                               const double* gJ, const Grad& G, double* jraw, float* gtpp) {
   hipStream_t st = T->stream;
   const DevTree& D = T->dev;
@@ -1134,8 +1139,8 @@ static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint
   TREVR_LAUNCH_CHECK("k_pp_src_bwd");
   prof_end(T, TREVR_PROF_ADJ_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
-  k_far_bwd<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, S.bstat, S.tpp,
-                                     bg, active, gJ, jraw, gtpp, G);
+  k_far_bwd<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, cap, S.bstat,
+                                     S.tpp, bg, active, gJ, jraw, gtpp, G);
   TREVR_LAUNCH_CHECK("k_far_bwd");
   prof_end(T, TREVR_PROF_ADJ_REDUCE, e1);
   hipEvent_t e2 = prof_begin(T);
@@ -1199,33 +1204,42 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   TREVR_LAUNCH_CHECK("k_zero_u64");
   if (!reuse && (rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
   prof_end(T, TREVR_PROF_SETUP, ev_setup);
-  for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
-    const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
-    if (!reuse || nb > kBatch) {   // cut lists hold one batch
-      hipEvent_t ev_walk = prof_begin(T);
-      if ((rc = launch_walk(T, S, b0, nb, cnt)) != TREVR_OK) return rc;
-      prof_end(T, TREVR_PROF_WALK, ev_walk);
-    }
+  auto run = [&](uint32_t s0, uint32_t scnt, uint32_t cap) -> trevr_status {
+    trevr_status r;
     if (!reuse) {
       hipEvent_t ev_near = prof_begin(T);
-      if ((rc = launch_pp_rays(T, S, b0, nb, cnt, active)) != TREVR_OK) return rc;
+      if ((r = launch_pp_rays(T, S, s0, nb, scnt, active)) != TREVR_OK) return r;
       prof_end(T, TREVR_PROF_NEAR, ev_near);
     }
     switch (T->B) {
-      case 1: rc = bwd_batch<1>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
-      case 2: rc = bwd_batch<2>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
-      case 3: rc = bwd_batch<3>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
-      case 4: rc = bwd_batch<4>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
-      case 5: rc = bwd_batch<5>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
-      case 6: rc = bwd_batch<6>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
-      case 7: rc = bwd_batch<7>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
-      default: rc = bwd_batch<8>(T, S, b0, nb, cnt, active, bg, gJ, G, jraw, gtpp); break;
+      case 1: return bwd_batch<1>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      case 2: return bwd_batch<2>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      case 3: return bwd_batch<3>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      case 4: return bwd_batch<4>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      case 5: return bwd_batch<5>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      case 6: return bwd_batch<6>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      case 7: return bwd_batch<7>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      default: return bwd_batch<8>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
     }
-    if (rc != TREVR_OK) return rc;
+  };
+  bool whole = reuse && T->fwd.cuts_kept;
+  if (whole) {   // one batch, whose cut lists the forward left in place
+    if (nb > 0 && (rc = run(0, nb, kCutCap)) != TREVR_OK) return rc;
+  } else {
+    whole = true;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
+      const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
+      bool w = true;
+      if ((rc = walk_batch(T, S, b0, cnt, nb, run, &w)) != TREVR_OK) return rc;
+      whole = whole && w;
+    }
   }
   hipEvent_t ev_tree = prof_begin(T);
   if (nb > 0) {
-    k_rpp_bwd<<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, S.bprev, G);
+    if (T->stack_large)
+      k_rpp_bwd<kStackLarge><<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, S.bprev, G);
+    else
+      k_rpp_bwd<kStackSmall><<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, S.bprev, G);
     TREVR_LAUNCH_CHECK("k_rpp_bwd");
   }
   const DevTree& D = T->dev;
@@ -1242,7 +1256,8 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   k_grad_out<<<grid_of(T->n, 256), 256, 0, st>>>(D, G, gL, gkappa, grho);
   TREVR_LAUNCH_CHECK("k_grad_out");
   prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
-  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total};
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total,
+                    nb <= kBatch && whole};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

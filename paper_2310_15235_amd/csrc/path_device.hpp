@@ -10,8 +10,15 @@
 
 namespace trevr {
 constexpr int kRMax = 8;         // receivers per pass
-constexpr int kStackCap = 4096;  // traversal stack entries (LDS)
-constexpr uint32_t kCutCap = 2048;
+// Traversal stacks live in LDS: the small one keeps the traversal kernels
+// at 8 wavefronts per SIMD (the deepest stacks seen are a few hundred
+// entries); a tree whose traversal overflows it switches to the large one.
+constexpr int kStackSmall = 1024;
+constexpr int kStackLarge = 8192;
+constexpr uint32_t kCutCap = 2048;   // default cut-list entries per bucket
+// Per-call overflow word (in the scratch): bits of traversals that ran out
+// of stack; the host retries those with the large stack.
+enum : uint32_t { OVF_SETUP = 1u, OVF_WALK = 2u };
 constexpr uint32_t kBatch = 65536;   // buckets per launch (bounds the cut-list scratch)
 constexpr int kCostBins = 48;
 constexpr int kNT = 256;         // threads of the near-field kernel
@@ -61,10 +68,10 @@ __device__ inline uint32_t wave_excl(uint32_t v, int lane) {
 // emit.  With `out`, writes their sorted slots: luminous ones from out[0],
 // the others from out[lum_total].  Boxes are pruned conservatively (an
 // element can sit an ulp outside its box after quantisation); membership is
-// the exact test.  The traversal stack lives in `stack` (kStackCap words).
+// the exact test.  The traversal stack lives in `stack` (cap words).
 __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double r2, uint32_t* stack,
-                              double* hmax, uint32_t* nlum, uint32_t* out, uint32_t lum_total,
-                              bool* overflow) {
+                                     int cap, double* hmax, uint32_t* nlum, uint32_t* out,
+                                     uint32_t lum_total, bool* overflow) {
   const int lane = threadIdx.x & 63;
   const double prune = r2 * (1.0 + 1e-9);
   uint32_t cnt = 0, lum = 0;
@@ -118,7 +125,7 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
     lum += wave_sum_u(mylum);
     const uint64_t pm = ballot64(push);
     const int npush = __popcll(pm);
-    if (sp + 2 * npush > kStackCap) {
+    if (sp + 2 * npush > cap) {
       *overflow = true;
       break;
     }

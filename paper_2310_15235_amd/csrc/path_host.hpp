@@ -3,6 +3,8 @@
 // the per-bucket arrays and the launches both run unchanged.
 #pragma once
 
+#include <functional>
+
 #include "trevr_internal.hpp"
 
 namespace trevr {
@@ -13,13 +15,14 @@ namespace trevr {
 // bucket readback, the p-p lists and the p-p optical depths per
 // (receiver, ray, band).
 struct Scratch {
-  uint32_t *blist, *bnact, *ncnt, *nlumc, *bstat, *nb;
+  uint32_t *blist, *bnact, *ncnt, *nlumc, *bstat, *nb, *ovf;
   double *brad, *bprev;         // p-p radius; before its last growth (-1: none)
   unsigned long long* ahash;    // [2] active-set fingerprints
   uint32_t *blist_raw, *bnact_raw, *ncnt_raw, *nlumc_raw;
   double *brad_raw, *bprev_raw;
   uint32_t *bbin, *bins;
   uint2* cut;
+  size_t cut_entries;           // capacity of the cut-list buffer
   uint32_t* nidx;
   float* tpp;
   size_t fixed;     // bytes of the part above (before the p-p lists)
@@ -38,8 +41,15 @@ trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long lon
                          uint64_t* hash);
 // Fill the p-p lists (S.nidx must be set).
 trevr_status near_fill(trevr_tree* T, const Scratch& S, uint32_t nb);
-// Tree walks of buckets [b0, b0 + cnt) into the cut lists.
-trevr_status launch_walk(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb, uint32_t cnt);
+// Tree walks of buckets [b0, b0 + cnt) into the cut lists, kCutCap entries
+// per bucket; then run(s0, scnt, cap) for the buckets whose cut lists are
+// ready (stride cap).  Synchronises once.  A batch whose walks ran out of
+// the traversal stack is walked again with the large stack; one where a
+// bucket needs more than kCutCap entries again in parts with room for the
+// longest (*whole = false).
+trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t cnt, uint32_t nb,
+                        const std::function<trevr_status(uint32_t, uint32_t, uint32_t)>& run,
+                        bool* whole);
 // p-p optical depth per (receiver, ray, band) of buckets [b0, b0 + cnt) into S.tpp.
 trevr_status launch_pp_rays(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
                             uint32_t cnt, const uint8_t* active);

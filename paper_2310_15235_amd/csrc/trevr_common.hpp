@@ -19,9 +19,8 @@ constexpr double kPi = 3.14159265358979323846;
 // Sticky device error bits.
 enum : uint32_t {
   ERR_DATA = 1u,         // non-positive or non-finite element data
-  ERR_STACK = 2u,        // walk stack overflow
-  ERR_CUT = 4u,          // cut list of a bucket over capacity
-  ERR_SRC = 8u,          // sources of a ray group over capacity
+  // (buffer overflows of a compute are handled by the host, which reruns
+  // the affected step with more room: see OVF_* and walk_batch)
 };
 
 // Node meta word (nk.w): owned prefix length in bits 0..5, flags above.

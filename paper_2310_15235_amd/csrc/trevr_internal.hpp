@@ -80,6 +80,7 @@ struct FwdState {
   uint64_t epoch;       // the library's write to that scratch that left it
   uint64_t hash;
   uint32_t nb, near_total, act_total;
+  bool cuts_kept;       // the cut buffer holds every bucket's cut list
 };
 
 struct trevr_tree {
@@ -99,6 +100,7 @@ struct trevr_tree {
   bool counters_valid;
   uint32_t* host_u32;                       // pinned 8-word readback buffer
   FwdState fwd;
+  bool stack_large;                         // traversals need the large LDS stack
   // kernel timing (trevr_profile_enable)
   bool prof_on;
   std::vector<hipEvent_t> ev_pool;

@@ -162,3 +162,33 @@ def test_J_clumpy_full_size_sampled():
     sc = scenes.config_clumpy()
     act = scenes.active_subset(sc, 0.01, 21)
     compare_J(sc, active=act)
+
+
+# ------------------------------------------ buffers that need more room
+def test_J_cut_lists_longer_than_the_default():
+    """A small opening angle opens nearly every cell, so each bucket's cut
+    list holds thousands of entries (more than the default per-bucket room):
+    the batch is walked again in parts with room for the longest."""
+    sc = scenes.uniform_scene(n=30000, seed=31, n_src=300, bands=(1.0,), nside=1, theta=0.15)
+    act = scenes.active_subset(sc, 0.01, 3)
+    e, cg = compare_J(sc, active=act)
+    api = _gpu()
+    T = api.Tree.from_scene(sc)
+    import torch
+    T.compute_J(torch.as_tensor(act, device="cuda"))
+    T.check()
+    T.close()
+
+
+def test_J_deep_tree_large_traversal_stack():
+    """Half the elements in a clump of width 1e-4: the tree is deep, and with
+    a small opening angle the walks' stacks outgrow the small LDS stack; the
+    call switches to the large one."""
+    sc = scenes.uniform_scene(n=20000, seed=32, n_src=200, bands=(1.0,), nside=1, theta=0.2,
+                              box=(0.0, 0.0, 0.0, 1.0))
+    rng = np.random.default_rng(33)
+    k = sc.n // 2
+    for a in (sc.x, sc.y, sc.z):
+        a[:k] = (0.3 + 1e-4 * rng.standard_normal(k)).astype(np.float32)
+    act = scenes.active_subset(sc, 0.01, 4)
+    compare_J(sc, active=act)
