@@ -86,6 +86,8 @@ typedef struct trevr_counters {
   int64_t src_pairs;        /* sum over active i of its bucket's far sources     */
   int64_t near_src_triples; /* sum over active i of (luminous p-p elements) x
                                (p-p set size): the p-p source paths tested     */
+  int64_t max_cut;          /* longest cut list of a bucket (entries)            */
+  int64_t max_stack;        /* deepest traversal stack (entries)                 */
 } trevr_counters;
 
 typedef struct trevr_tree trevr_tree; /* opaque host handle */
@@ -174,6 +176,19 @@ trevr_status trevr_compute_J_backward(trevr_tree* t, const uint8_t* active, cons
                                       const double* gJ, double* gL, double* gkappa,
                                       double* grho, void* scratch, size_t scratch_bytes,
                                       void* stream);
+
+/*
+ * Tuning knobs of a tree (support call; results do not depend on them):
+ *   TREVR_TUNE_STACK  entries of the small LDS traversal stack, in [64, 1024]
+ *                     (default 1024).  A traversal that needs more switches
+ *                     the tree to an 8192-entry stack.
+ *   TREVR_TUNE_CUT    cut-list entries per bucket tried first, in [64, 2048]
+ *                     (default 2048).  A batch with a longer cut list is
+ *                     walked again in parts with room for the longest.
+ * Returns TREVR_E_INVALID for an unknown key or a value out of range.
+ */
+enum { TREVR_TUNE_STACK = 0, TREVR_TUNE_CUT = 1 };
+trevr_status trevr_tree_tune(trevr_tree* t, int key, int64_t value);
 
 /* Scratch bytes the last compute_J or compute_J_backward on this tree needed
  * (0 before any). */

@@ -21,10 +21,11 @@ OK, E_INVALID, E_CAPACITY, E_HIP, E_STATE, E_DATA = range(6)
 THICK_CORR, NEAR_FIELD, BACKGROUND = 1, 2, 4
 
 EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
-            "trevr_compute_J_backward",
+            "trevr_compute_J_backward", "trevr_tree_tune",
             "trevr_scratch_needed", "trevr_get_counters", "trevr_check", "trevr_tree_destroy",
             "trevr_tree_info", "trevr_tree_export", "trevr_profile_enable",
             "trevr_profile_read", "trevr_status_string", "trevr_last_error")
+TUNE_STACK, TUNE_CUT = 0, 1
 PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree")
 PROF_SLOTS = len(PROF_NAMES)
 
@@ -45,7 +46,8 @@ class Params(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("buckets", "cells", "absorber_entries", "source_entries", "segments",
-                 "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples")]
+                 "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples", "max_cut",
+                 "max_stack")]
 
 
 _lib = None
@@ -66,6 +68,7 @@ def lib():
                                                                                    ctypes.POINTER(vp)]
         L.trevr_compute_J.argtypes = [vp, vp, vp, vp, vp, sz, vp]
         L.trevr_compute_J_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.trevr_tree_tune.argtypes = [vp, ctypes.c_int, i64]
         L.trevr_scratch_needed.argtypes = [vp, ctypes.POINTER(sz)]
         L.trevr_get_counters.argtypes = [vp, ctypes.POINTER(Counters)]
         L.trevr_check.argtypes = [vp]
@@ -217,6 +220,9 @@ class Tree:
     @property
     def scratch(self):
         return self._scratch
+
+    def tune(self, key: int, value: int):
+        _check(lib().trevr_tree_tune(self.handle, int(key), int(value)), "trevr_tree_tune")
 
     def check(self):
         _check(lib().trevr_check(self.handle), "trevr_check")

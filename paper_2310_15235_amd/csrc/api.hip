@@ -166,8 +166,9 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->prof_on = false;
   T->ev_used = 0;
   T->host_u32 = nullptr;
-  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, false};
+  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, false, 0};
   T->stack_large = false;
+  T->cut_default = kCutCap;
   for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }
   const size_t need = layout_tree(*p, n, T->nclass, nullptr, nullptr);
   if (tree_ws_bytes < need) {
@@ -187,6 +188,7 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   D.theta2 = p->theta * p->theta;
   D.rpp_min = p->rpp_min;
   D.wbeam = 2.0 * std::tan(std::acos(1.0 - 2.0 / T->nray));
+  D.stack_limit = kStackSmall;
   D.hdr = b.hdr;
   D.x = b.x; D.y = b.y; D.z = b.z; D.m = b.m; D.rho = b.rho;
   D.h = b.h; D.lbol = b.lbol; D.kappa = b.kappa; D.lum = b.lum; D.perm = b.perm;
@@ -231,6 +233,25 @@ trevr_status trevr_compute_J_backward(trevr_tree* t, const uint8_t* active, cons
   return compute_J_backward_impl(t, active, bg, gJ, gL, gkappa, grho, scratch, scratch_bytes);
 }
 
+trevr_status trevr_tree_tune(trevr_tree* t, int key, int64_t value) {
+  if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
+  switch (key) {
+    case TREVR_TUNE_STACK:
+      if (value < 64 || value > kStackSmall)
+        return set_error(TREVR_E_INVALID, "stack limit must be in [64, 1024]");
+      t->dev.stack_limit = (int32_t)value;
+      t->stack_large = false;
+      return TREVR_OK;
+    case TREVR_TUNE_CUT:
+      if (value < 64 || value > (int64_t)kCutCap)
+        return set_error(TREVR_E_INVALID, "cut-list length must be in [64, 2048]");
+      t->cut_default = (uint32_t)value;
+      return TREVR_OK;
+    default:
+      return set_error(TREVR_E_INVALID, "unknown tuning key");
+  }
+}
+
 trevr_status trevr_scratch_needed(const trevr_tree* t, size_t* bytes) {
   if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
   if (!bytes) return set_error(TREVR_E_INVALID, "NULL output");
@@ -272,6 +293,8 @@ trevr_status trevr_get_counters(trevr_tree* t, trevr_counters* o) {
   o->nodes = t->num_nodes;
   o->src_pairs = (int64_t)c[CNT_SRC_PAIRS];
   o->near_src_triples = (int64_t)c[CNT_NS_TRIPLES];
+  o->max_cut = (int64_t)c[CNT_MAX_CUT];
+  o->max_stack = (int64_t)c[CNT_MAX_STACK];
   return TREVR_OK;
 }
 

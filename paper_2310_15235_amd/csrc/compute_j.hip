@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
     r = fmax(r, wave_max(rm));
     for (;;) {
       double hm = 0.0;
-      cnt = wave_near(T, c, r * r, stack, SC, &hm, &nlum, nullptr, 0, &overflow);
+      cnt = wave_near(T, c, r * r, stack, stack_cap<SC>(T), &hm, &nlum, nullptr, 0, &overflow);
       const double rn = fmax(r, hm / T.wbeam);
       if (!(rn > r) || overflow) break;
       rprev = r;
@@ -133,7 +133,8 @@ __global__ void __launch_bounds__(64) k_near_fill(DevTree T, const uint32_t* bli
   leaf_centre(T, blist[b], c);
   const double r = brad[b];
   bool overflow = false;
-  wave_near(T, c, r * r, stack, SC, nullptr, nullptr, nidx + noff[b], nlumc[b], &overflow);
+  wave_near(T, c, r * r, stack, stack_cap<SC>(T), nullptr, nullptr, nidx + noff[b], nlumc[b],
+            &overflow);
 }
 
 // ------------------------------------------------------------- the walk
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
   uint2* out = cut + (size_t)blockIdx.x * cap;
   uint32_t ncut = 0, nsrc = 0, ncells = 0;
   bool overflow = false;
-  int sp = 1;
+  int sp = 1, maxsp = 1;
   if (lane == 0) stack[0] = 0u;
   __syncthreads();
   while (sp > 0) {
@@ -185,7 +186,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
     const uint64_t pm = ballot64(push);
     const int ppos = mbcnt(pm);
     const int npush = __popcll(pm);
-    if (sp + 2 * npush > SC) {
+    if (sp + 2 * npush > stack_cap<SC>(T)) {
       overflow = true;
       break;
     }
@@ -194,6 +195,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
       stack[sp + 2 * ppos + 1] = node + 1u;        // child 0
     }
     sp += 2 * npush;
+    maxsp = max(maxsp, sp);
     ncells += (uint32_t)__popcll(ballot64(emit));
     // cell entries: absorbers and merged sources
     uint32_t meta = 0u;
@@ -253,6 +255,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
     if (overflow) atomicOr(ovf, OVF_WALK);
     atomicMax(ovf + 1, ncut);
     atomic_max_u64(&T.counters[CNT_MAX_CUT], ncut);
+    atomic_max_u64(&T.counters[CNT_MAX_STACK], (unsigned long long)maxsp);
   }
 }
 
@@ -920,7 +923,7 @@ trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t c
   uint32_t* hbuf = T->host_u32;
   for (;;) {
     hipEvent_t ev = prof_begin(T);
-    if ((rc = walk_launch(T, S, b0, nb, cnt, kCutCap)) != TREVR_OK) return rc;
+    if ((rc = walk_launch(T, S, b0, nb, cnt, T->cut_default)) != TREVR_OK) return rc;
     prof_end(T, TREVR_PROF_WALK, ev);
     hipError_t e = hipMemcpyAsync(hbuf, S.ovf, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                   T->stream);
@@ -931,9 +934,9 @@ trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t c
     T->stack_large = true;
   }
   const uint32_t maxcut = hbuf[1];
-  if (maxcut <= kCutCap) {
+  if (maxcut <= T->cut_default) {
     *whole = true;
-    return run(b0, cnt, kCutCap);
+    return run(b0, cnt, T->cut_default);
   }
   // some bucket needs a longer cut list: walk the batch again in parts that
   // fit the cut buffer with room for the longest
@@ -1041,7 +1044,7 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   }
   T->counters_valid = true;
   T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total,
-                    nb <= kBatch && whole};
+                    nb <= kBatch && whole, T->cut_default};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

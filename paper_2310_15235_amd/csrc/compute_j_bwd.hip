@@ -337,7 +337,15 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
 // ------------------------------------------------------ p-p columns
 // Adjoint of k_pp_rays: tau_ikb = sum_l kappa_lb Sigma_l(b_ilk) with the
 // adjoint g_ikb of the far-field kernel: dkappa_lb += g Sigma, dh_l +=
-// g kappa_lb dSigma/dh.
+// g kappa_lb dSigma/dh.  Element-major: threads take (p-p element l,
+// receiver i) pairs and sweep the rays of a group of 64, a conservative
+// FP32 test skipping rays that cannot pass within h_l of l, the exact FP64
+// test (the forward's operation sequence) deciding the rest; each thread
+// sums its pair's contributions in registers, one LDS atomic per pair
+// collects them per element, one FP64 atomic per element and group writes
+// them out.
+constexpr int kPRChunk = 256;   // p-p elements per LDS chunk
+
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* blist,
                                                     const uint32_t* noff, const uint32_t* nidx,
@@ -347,10 +355,12 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
   const int t = threadIdx.x;
-  __shared__ NearTile<NB> S;
-  __shared__ NearGrad<NB> SG;
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s;
+  __shared__ RayGroup RG;
+  __shared__ float g[kRMax][64][NB];
+  __shared__ float ek[kPRChunk][NB], eh[kPRChunk];
+  __shared__ int gz;
   const uint32_t leafb = blist[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
@@ -364,99 +374,85 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
   for (;;) {
     const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
-    const int stride = (kNT / nrecv) * nrecv;
-    const int gpr = (nray + 1) / 2;
-    const uint32_t P = (uint32_t)nrecv * (uint32_t)gpr;
-    const int i = t % nrecv;
-    const RecvInfo& ri = recv[i];
-    for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
-      const uint32_t p = pb + (uint32_t)t;
-      const bool ok = t < stride && p < P;
-      const int kb = ok ? 2 * (int)(p / nrecv) : 0;
-      double nv[2][3];
-      float of[3], inv[2][3];
-      bool kok[2];
-      float g[2][NB];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        kok[q] = ok && kb + q < nray;
-        const int kq = kok[q] ? kb + q : 0;
-        bool nz = false;
+    for (int k0 = 0; k0 < nray; k0 += 64) {
+      const int kn = min(64, nray - k0);
+      if (t == 0) gz = 0;
+      load_ray_group(T, k0, kn, RG);
+      __syncthreads();
+      int nz = 0;
+      for (int q = t; q < nrecv * kn; q += kNT) {
+        const int i = q / kn, kq = q % kn;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          g[q][b] = kok[q] ? gtpp[((int64_t)(rbase + i) * nray + kq) * NB + b] : 0.0f;
-          nz = nz || g[q][b] != 0.0f;
-        }
-        kok[q] = kok[q] && nz;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          nv[q][a] = T.ray_n[3 * kq + a];
-          const float nf = (float)nv[q][a];
-          inv[q][a] = (nf != 0.0f) ? 1.0f / nf : 1e30f;
+          const float v = gtpp[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
+          g[i][kq][b] = v;
+          nz |= v != 0.0f;
         }
       }
+      if (nz) gz = 1;
+      __syncthreads();
+      if (!gz) continue;                 // no adjoint on these rays
+      for (uint32_t c0 = 0; c0 < nnear; c0 += kPRChunk) {
+        const uint32_t cl = min((uint32_t)kPRChunk, nnear - c0);
+        for (uint32_t u = t; u < cl; u += kNT) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) of[a] = ri.rel[a];
-      const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
-      const uint32_t si = ri.slot;
-      const bool any = kok[0] || kok[1];
-      if (!__syncthreads_or(any)) continue;
-      for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
-        const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
-        stage_near<NB>(S, T, near, c0, cl, c);
-        zero_near_grad<NB>(SG);
-        const int nsub = ((int)cl + kSub - 1) / kSub;
-        for (int sb = 0; sb < nsub; ++sb) {
-          bool need = false;
-          if (any) {
-            const float blo[3] = {S.blo[sb][0], S.blo[sb][1], S.blo[sb][2]};
-            const float bhi[3] = {S.bhi[sb][0], S.bhi[sb][1], S.bhi[sb][2]};
-            need = (kok[0] && ray_meets_box(of, inv[0], blo, bhi)) ||
-                   (kok[1] && ray_meets_box(of, inv[1], blo, bhi));
-          }
-          if (ballot64(need) == 0ull) continue;
-          const int u1 = min((int)cl, (sb + 1) * kSub);
-          for (int u = sb * kSub; u < u1; ++u) {
-            const double d0 = S.x[u] - xi0, d1 = S.y[u] - xi1, d2 = S.z[u] - xi2;
-            const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-            const double h2 = S.h2[u];
-            const bool other = S.slot[u] != si;
-            float ck[NB], gh = 0.0f;
+          for (int b = 0; b < NB; ++b) ek[u][b] = 0.0f;
+          eh[u] = 0.0f;
+        }
+        __syncthreads();
+        for (uint32_t pq = t; pq < cl * (uint32_t)nrecv; pq += kNT) {
+          const uint32_t u = pq / nrecv;
+          const int i = (int)(pq % nrecv);
+          const uint32_t l = near[c0 + u];
+          if (l == recv[i].slot) continue;
+          const double d0 = (double)T.x[l] - recv[i].x[0];
+          const double d1 = (double)T.y[l] - recv[i].x[1];
+          const double d2 = (double)T.z[l] - recv[i].x[2];
+          const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+          const double hl = T.h[l];
+          const double h2 = hl * hl;
+          const float df[3] = {(float)d0, (float)d1, (float)d2};
+          const float ddf = (float)dd;
+          const float lim = (float)(dd - h2) - 1e-5f * ddf - 1e-30f;
+          const float neg = -1e-5f * sqrtf(ddf);
+          const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+          const float iv = (float)(1.0 / hl);
+          float kap[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
-            bool any_pass = false;
+          for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
+          float ck[NB], gh = 0.0f;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-              const double proj = d0 * nv[q][0] + d1 * nv[q][1] + d2 * nv[q][2];
-              const double b2 = dd - proj * proj;
-              if (need && proj > 0.0 && b2 < h2 && other && kok[q]) {
-                const float bb = sqrtf((float)fmax(b2, 0.0));
-                const float iv = S.invh[u];
-                const float sg = S.sig[u] * (1.0f - bb * iv);
-                const float dsg = S.sig[u] * iv * (3.0f * bb * iv - 2.0f);
-                float gq = 0.0f;
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                  ck[b] += g[q][b] * sg;
-                  gq += g[q][b] * S.kap[u][b];
-                }
-                gh += gq * dsg;
-                any_pass = true;
-              }
-            }
-            // sum over rows of 16 lanes before the LDS atomics
-            if (ballot64(any_pass) == 0ull) continue;
-            const bool last = (t & 15) == 15;
+          for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
+          for (int kq = 0; kq < kn; ++kq) {
+            const float pf = RG.nf[kq][0] * df[0] + RG.nf[kq][1] * df[1] + RG.nf[kq][2] * df[2];
+            if (!(pf > neg) || !(pf * pf >= lim)) continue;
+            const double proj = d0 * RG.n[kq][0] + d1 * RG.n[kq][1] + d2 * RG.n[kq][2];
+            const double b2 = dd - proj * proj;
+            if (!(proj > 0.0 && b2 < h2)) continue;
+            const float bb = sqrtf((float)fmax(b2, 0.0));
+            const float sg = sig * (1.0f - bb * iv);
+            const float dsg = sig * iv * (3.0f * bb * iv - 2.0f);
+            float gq = 0.0f;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-              const float v = row_sum16(ck[b]);
-              if (last && v != 0.0f) atomicAdd(&SG.gk[u][b], v);
+              ck[b] += g[i][kq][b] * sg;
+              gq += g[i][kq][b] * kap[b];
             }
-            const float v = row_sum16(gh);
-            if (last && v != 0.0f) atomicAdd(&SG.gh[u], v);
+            gh += gq * dsg;
           }
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            if (ck[b] != 0.0f) atomicAdd(&ek[u][b], ck[b]);
+          if (gh != 0.0f) atomicAdd(&eh[u], gh);
         }
-        flush_near_grad<NB>(S, SG, cl, G, n);
+        __syncthreads();
+        for (uint32_t u = t; u < cl; u += kNT) {
+          const uint32_t l = near[c0 + u];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) gadd(&G.gk[(int64_t)b * n + l], (double)ek[u][b]);
+          gadd(&G.gh[l], (double)eh[u]);
+        }
+        __syncthreads();
       }
     }
     rbase += (uint32_t)nrecv;
@@ -978,7 +974,7 @@ __global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist
     if (rmax > T.rpp_min) src = marg;
   } else {
     // the beam rule of the last growth, over the sphere before it
-    src = wave_near_argbeam(T, c, rprev * rprev, r, stack, SC, &overflow);
+    src = wave_near_argbeam(T, c, rprev * rprev, r, stack, stack_cap<SC>(T), &overflow);
     fac = 1.0 / T.wbeam;
   }
   if (lane == 0 && src != 0xFFFFFFFFu && !overflow) gadd(&G.gh[src], g * fac);
@@ -1224,7 +1220,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   };
   bool whole = reuse && T->fwd.cuts_kept;
   if (whole) {   // one batch, whose cut lists the forward left in place
-    if (nb > 0 && (rc = run(0, nb, kCutCap)) != TREVR_OK) return rc;
+    if (nb > 0 && (rc = run(0, nb, T->fwd.cut_stride)) != TREVR_OK) return rc;
   } else {
     whole = true;
     for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
@@ -1257,7 +1253,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   TREVR_LAUNCH_CHECK("k_grad_out");
   prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
   T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total,
-                    nb <= kBatch && whole};
+                    nb <= kBatch && whole, T->cut_default};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

@@ -10,12 +10,12 @@
 
 namespace trevr {
 constexpr int kRMax = 8;         // receivers per pass
-// Traversal stacks live in LDS: the small one keeps the traversal kernels
-// at 8 wavefronts per SIMD (the deepest stacks seen are a few hundred
-// entries); a tree whose traversal overflows it switches to the large one.
-constexpr int kStackSmall = 1024;
-constexpr int kStackLarge = 8192;
-constexpr uint32_t kCutCap = 2048;   // default cut-list entries per bucket
+// Entries of a traversal stack of SC words that a kernel may use: the small
+// stack honours the tree's (tunable) limit.
+template <int SC> __device__ inline int stack_cap(const DevTree& T) {
+  return SC == kStackSmall ? min(SC, T.stack_limit) : SC;
+}
+
 // Per-call overflow word (in the scratch): bits of traversals that ran out
 // of stack; the host retries those with the large stack.
 enum : uint32_t { OVF_SETUP = 1u, OVF_WALK = 2u };
@@ -76,7 +76,7 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
   const double prune = r2 * (1.0 + 1e-9);
   uint32_t cnt = 0, lum = 0;
   double hm = 0.0;
-  int sp = 1;
+  int sp = 1, maxsp = 1;
   if (lane == 0) stack[0] = 0u;
   __syncthreads();
   while (sp > 0) {
@@ -135,8 +135,10 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
       stack[sp + 2 * ppos + 1] = node + 1u; // child 0
     }
     sp += 2 * npush;
+    maxsp = max(maxsp, sp);
     __syncthreads();
   }
+  if (lane == 0) atomic_max_u64(&T.counters[CNT_MAX_STACK], (unsigned long long)maxsp);
   if (hmax) *hmax = wave_max(hm);
   if (nlum) *nlum = lum;
   return cnt;

@@ -43,7 +43,7 @@ enum : uint32_t {
 
 // Counter slots (uint64 on the device).
 enum { CNT_BUCKETS = 0, CNT_CELLS, CNT_ABS, CNT_SRC, CNT_SEG, CNT_NEAR_PAIRS, CNT_MAX_NEAR,
-       CNT_NODES, CNT_SRC_PAIRS, CNT_NS_TRIPLES, CNT_MAX_CUT, CNT_N = 16 };
+       CNT_NODES, CNT_SRC_PAIRS, CNT_NS_TRIPLES, CNT_MAX_CUT, CNT_MAX_STACK, CNT_N = 16 };
 
 // Device view of a tree (all pointers into the caller's tree workspace).
 struct DevTree {
@@ -51,6 +51,7 @@ struct DevTree {
   int32_t B, nside, nray, nclass, leaf_size;
   uint32_t flags;
   double theta2, rpp_min, wbeam;
+  int32_t stack_limit;        // entries of the small traversal stack in use
   int64_t num_nodes;
   const double* hdr;          // root lo[3], L, quantisation scale
   // sorted elements

@@ -12,6 +12,13 @@
 
 namespace trevr {
 
+// Traversal stacks live in LDS: the small one keeps the traversal kernels
+// at 8 wavefronts per SIMD (the deepest stacks seen are a few hundred
+// entries); a tree whose traversal overflows it switches to the large one.
+constexpr int kStackSmall = 1024;
+constexpr int kStackLarge = 8192;
+constexpr uint32_t kCutCap = 2048;   // cut-list entries per bucket the buffer is sized for
+
 // Bump allocator over a caller-owned buffer (base == nullptr: size only).
 struct Carve {
   char* base;
@@ -81,6 +88,7 @@ struct FwdState {
   uint64_t hash;
   uint32_t nb, near_total, act_total;
   bool cuts_kept;       // the cut buffer holds every bucket's cut list
+  uint32_t cut_stride;  // ... at this many entries per bucket
 };
 
 struct trevr_tree {
@@ -101,6 +109,7 @@ struct trevr_tree {
   uint32_t* host_u32;                       // pinned 8-word readback buffer
   FwdState fwd;
   bool stack_large;                         // traversals need the large LDS stack
+  uint32_t cut_default;                     // cut-list entries per bucket to try first
   // kernel timing (trevr_profile_enable)
   bool prof_on;
   std::vector<hipEvent_t> ev_pool;

@@ -70,3 +70,31 @@ def test_unknown_handle_rejected():
     assert L.trevr_tree_destroy(bogus) == api.E_STATE
     c = api.Counters()
     assert L.trevr_get_counters(bogus, ctypes.byref(c)) == api.E_STATE
+
+
+def _struct_fields(name):
+    import re
+    text = open(os.path.join(ROOT, "include", "trevr2.h")).read()
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.match(r"(\w+)\s+(\w+)(\[\d+\])?$", decl)
+        assert m, decl
+        fields.append(m.group(2))
+    return fields
+
+
+def test_binding_structs_match_header():
+    """The ctypes mirrors of the C structs list the header's fields in order."""
+    assert [f for f, _ in api.Counters._fields_] == _struct_fields("trevr_counters")
+    assert [f for f, _ in api.Params._fields_] == _struct_fields("trevr_params")
+
+
+def test_tune_rejects_unknown_handle():
+    L = api.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    assert L.trevr_tree_tune(bogus, api.TUNE_STACK, 256) == api.E_STATE

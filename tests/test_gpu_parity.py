@@ -55,12 +55,25 @@ def compare_tree(sc):
     T.close()
 
 
-def compare_J(sc, active=None, tol=J_TOL, check_counts=True):
+def compare_J(sc, active=None, tol=J_TOL, check_counts=True, tune=()):
+    """J of the HIP path (tuning knobs `tune` = ((key, value), ...) applied to
+    the tree) against the oracle on the same active set."""
     api = _gpu()
+    import torch
     act = sc.active if active is None else active
-    Jg, cg = api.compute_J(sc, active=act)
+    T = api.Tree.from_scene(sc)
+    for key, value in tune:
+        T.tune(key, value)
+    a = None if act is None else torch.as_tensor(np.ascontiguousarray(act, np.uint8), device="cuda")
+    bg = None
+    if sc.background and sc.bg is not None:
+        bg = torch.as_tensor(np.ascontiguousarray(sc.bg, np.float32), device="cuda")
+    Jg = T.compute_J(a, bg).cpu().numpy()
+    T.check()
+    cg = T.counters()
+    T.close()
     Jo, co = oracle.OracleTree(sc).compute_J(act)
-    a = act.astype(bool)
+    a = np.ones(sc.n, bool) if act is None else act.astype(bool)
     e = jerr(Jg, Jo, a)
     assert np.all(Jg[:, ~a] == 0.0)
     if check_counts:
@@ -172,18 +185,14 @@ def test_J_cut_lists_longer_than_the_default():
     sc = scenes.uniform_scene(n=30000, seed=31, n_src=300, bands=(1.0,), nside=1, theta=0.15)
     act = scenes.active_subset(sc, 0.01, 3)
     e, cg = compare_J(sc, active=act)
-    api = _gpu()
-    T = api.Tree.from_scene(sc)
-    import torch
-    T.compute_J(torch.as_tensor(act, device="cuda"))
-    T.check()
-    T.close()
+    assert cg["max_cut"] > 2048
 
 
 def test_J_deep_tree_large_traversal_stack():
-    """Half the elements in a clump of width 1e-4: the tree is deep, and with
-    a small opening angle the walks' stacks outgrow the small LDS stack; the
-    call switches to the large one."""
+    """Half the elements in a clump of width 1e-4 (a deep tree) and a small
+    opening angle; with the small stack limited to 128 entries the
+    traversals outgrow it and the call switches to the large stack."""
+    api = _gpu()
     sc = scenes.uniform_scene(n=20000, seed=32, n_src=200, bands=(1.0,), nside=1, theta=0.2,
                               box=(0.0, 0.0, 0.0, 1.0))
     rng = np.random.default_rng(33)
@@ -191,4 +200,16 @@ def test_J_deep_tree_large_traversal_stack():
     for a in (sc.x, sc.y, sc.z):
         a[:k] = (0.3 + 1e-4 * rng.standard_normal(k)).astype(np.float32)
     act = scenes.active_subset(sc, 0.01, 4)
-    compare_J(sc, active=act)
+    e, cg = compare_J(sc, active=act, tune=((api.TUNE_STACK, 128),))
+    assert cg["max_stack"] > 128
+
+
+def test_J_small_stack_limit_and_short_cut_lists():
+    """Tuning knobs only change how the work is laid out, never the result:
+    a 64-entry stack limit (every traversal falls back to the large stack)
+    and 64-entry cut lists (every batch is walked again in parts)."""
+    api = _gpu()
+    sc = scenes.lognormal_scene(n=20000, seed=34, grid=32, bands=(1.0, 10.0), nside=2)
+    act = scenes.active_subset(sc, 0.1, 5)
+    e, cg = compare_J(sc, active=act, tune=((api.TUNE_STACK, 64), (api.TUNE_CUT, 64)))
+    assert cg["max_stack"] > 64 and cg["max_cut"] > 64
