@@ -367,11 +367,16 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(DevTree T, const uint32_t* blis
 // r = 0): L_j K(r_ij, h_i) exp(-tau_ij), tau over the p-p elements closer to
 // j than i is (exact FP64 squared distances: discontinuous) and within their
 // size of the segment i-j (continuous).  J of i starts with the sum.
+//
+// The optical depth of each pair is kept in ptau [pair][band] (pairs of a
+// bucket from poff[bucket], receiver-chunk-major, then (source, receiver)),
+// for the adjoint.  J == nullptr: only ptau is written.
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist,
                                                const uint32_t* noff, const uint32_t* nlumc,
-                                               const uint32_t* nidx, uint32_t b0, uint32_t nbuck,
-                                               const uint8_t* active, double* J) {
+                                               const uint32_t* nidx, const uint32_t* poff,
+                                               uint32_t b0, uint32_t nbuck, const uint8_t* active,
+                                               double* J, float* ptau) {
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
   const int t = threadIdx.x;
@@ -391,6 +396,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
   for (;;) {
     const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
+    float* pt = ptau + ((int64_t)poff[bucket] + (int64_t)nact * nl) * NB;
     nact += (uint32_t)nrecv;
     const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
     const int i = t % nrecv;
@@ -462,22 +468,24 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
       if (ok) {
         const float Kv = fshape((float)sqrt(rij2) * ri.inv_rh) * ri.kfac;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b) {
           acc[b] += (double)T.lum[(int64_t)b * n + j] * (double)Kv * exp(-(double)tau[b]);
+          pt[(int64_t)p * NB + b] = tau[b];
+        }
       }
     }
     // receiver-wise sums in thread order (deterministic)
 #pragma unroll
     for (int b = 0; b < NB; ++b) red[t][b] = acc[b];
     __syncthreads();
-    if (t < nrecv * NB) {
+    if (J && t < nrecv * NB) {
       const int ii = t / NB, b = t % NB;
       double v = 0.0;
       for (int u = ii; u < stride; u += nrecv) v += red[u][b];
       J[(int64_t)b * n + T.perm[recv[ii].slot]] = v;
     }
   }
-  if (t == 0) {
+  if (J && t == 0) {
     atomicAdd(&T.counters[CNT_NEAR_PAIRS], (unsigned long long)nact * nnear);
     atomicAdd(&T.counters[CNT_NS_TRIPLES], (unsigned long long)nact * nl * nnear);
     atomic_max_u64(&T.counters[CNT_MAX_NEAR], (unsigned long long)nnear);
@@ -724,12 +732,13 @@ __global__ void k_reorder(const uint32_t* nbp, const uint32_t* bbin, uint32_t* b
                           const uint32_t* blist, const uint32_t* bnact, const uint32_t* ncnt,
                           const uint32_t* nlumc, const double* brad, const double* bprev,
                           uint32_t* blist2, uint32_t* bnact2, uint32_t* ncnt2, uint32_t* nlumc2,
-                          double* brad2, double* bprev2) {
+                          double* brad2, double* bprev2, uint32_t* pcnt2) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= *nbp) return;
   const uint32_t pos = atomicAdd(&bins[bbin[b]], 1u);
   blist2[pos] = blist[b];
   bnact2[pos] = bnact[b];
+  pcnt2[pos] = bnact[b] * nlumc[b];   // (receiver, luminous p-p element) pairs
   ncnt2[pos] = ncnt[b];
   nlumc2[pos] = nlumc[b];
   brad2[pos] = brad[b];
@@ -748,6 +757,7 @@ static Scratch carve(void* base, int64_t nleaves) {
   s.blist = cv.take<uint32_t>(L);
   s.bnact = cv.take<uint32_t>(L + 1);
   s.ncnt = cv.take<uint32_t>(L + 1);
+  s.pcnt = cv.take<uint32_t>(L + 1);
   s.nlumc = cv.take<uint32_t>(L);
   s.bstat = cv.take<uint32_t>(4 * L);
   s.brad = cv.take<double>(L);
@@ -795,7 +805,7 @@ size_t scratch_fixed_bytes(int64_t n) { return carve(nullptr, n).fixed; }
     if ((rc = hip_check(hipGetLastError(), what)) != TREVR_OK) return rc;      \
   } while (0)
 
-trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3],
+trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[4],
                           uint64_t* hash) {
   hipStream_t st = T->stream;
   const int64_t nleaves = T->num_leaves;
@@ -829,6 +839,9 @@ trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint
     if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st),
                         "memset")) != TREVR_OK)
       return rc;
+    if ((rc = hip_check(hipMemsetAsync(S.pcnt, 0, sizeof(uint32_t) * (nleaves + 1), st),
+                        "memset")) != TREVR_OK)
+      return rc;
     k_cost_bins<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(S.nb, S.bnact_raw, S.ncnt_raw,
                                                                    S.nlumc_raw, T->nray, S.bbin,
                                                                    S.bins);
@@ -837,11 +850,13 @@ trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint
     TREVR_LAUNCH_CHECK("k_bins_scan");
     k_reorder<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(
         S.nb, S.bbin, S.bins, S.blist_raw, S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw,
-        S.bprev_raw, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev);
+        S.bprev_raw, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev, S.pcnt);
     TREVR_LAUNCH_CHECK("k_reorder");
     k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.nb + 1);
     TREVR_LAUNCH_CHECK("k_scan_u32");
     k_scan_u32<<<1, 1024, 0, st>>>(S.bnact, nleaves + 1, S.nb + 2);
+    TREVR_LAUNCH_CHECK("k_scan_u32");
+    k_scan_u32<<<1, 1024, 0, st>>>(S.pcnt, nleaves + 1, S.nb + 3);
     TREVR_LAUNCH_CHECK("k_scan_u32");
     if ((rc = hip_check(hipMemsetAsync(S.ahash, 0, sizeof(unsigned long long), st), "memset")) !=
         TREVR_OK)
@@ -849,21 +864,21 @@ trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint
     k_active_hash<<<(unsigned)((T->n + 255) / 256), 256, 0, st>>>(active, T->n, S.ahash);
     TREVR_LAUNCH_CHECK("k_active_hash");
     uint32_t* hbuf = T->host_u32;
-    hipError_t e = hipMemcpyAsync(hbuf, S.nb, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(hbuf + 3, S.ovf, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(hbuf, S.nb, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(hbuf + 4, S.ahash, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hbuf + 6, S.ovf, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if ((rc = hip_check(e, "bucket readback")) != TREVR_OK) return rc;
-    if (!(hbuf[3] & OVF_SETUP)) break;
+    if (!(hbuf[6] & OVF_SETUP)) break;
     // a p-p range query ran out of the small traversal stack: use the
     // large one for this tree from now on
     if (T->stack_large)
       return set_error(TREVR_E_CAPACITY, "a p-p range query exceeds the traversal stack");
     T->stack_large = true;
   }
-  for (int i = 0; i < 3; ++i) counts[i] = T->host_u32[i];
+  for (int i = 0; i < 4; ++i) counts[i] = T->host_u32[i];
   std::memcpy(hash, T->host_u32 + 4, sizeof(uint64_t));
   return TREVR_OK;
 }
@@ -980,6 +995,30 @@ trevr_status launch_pp_rays(trevr_tree* T, const Scratch& S, uint32_t b0, uint32
 }
 
 template <int NB>
+static trevr_status pp_src_nb(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                              uint32_t cnt, const uint8_t* active, double* J) {
+  trevr_status rc;
+  k_pp_src<NB><<<cnt, kNT, 0, T->stream>>>(T->dev, S.blist, S.ncnt, S.nlumc, S.nidx, S.pcnt, b0,
+                                           nb, active, J, S.ptau);
+  TREVR_LAUNCH_CHECK("k_pp_src");
+  return rc;
+}
+
+trevr_status launch_pp_src(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                           uint32_t cnt, const uint8_t* active, double* J) {
+  switch (T->B) {
+    case 1: return pp_src_nb<1>(T, S, b0, nb, cnt, active, J);
+    case 2: return pp_src_nb<2>(T, S, b0, nb, cnt, active, J);
+    case 3: return pp_src_nb<3>(T, S, b0, nb, cnt, active, J);
+    case 4: return pp_src_nb<4>(T, S, b0, nb, cnt, active, J);
+    case 5: return pp_src_nb<5>(T, S, b0, nb, cnt, active, J);
+    case 6: return pp_src_nb<6>(T, S, b0, nb, cnt, active, J);
+    case 7: return pp_src_nb<7>(T, S, b0, nb, cnt, active, J);
+    default: return pp_src_nb<8>(T, S, b0, nb, cnt, active, J);
+  }
+}
+
+template <int NB>
 static trevr_status launch_pair(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
                                 uint32_t cnt, uint32_t cap, const float* bg, double* J,
                                 const uint8_t* active) {
@@ -988,8 +1027,7 @@ static trevr_status launch_pair(trevr_tree* T, const Scratch& S, uint32_t b0, ui
   trevr_status rc;
   hipEvent_t e0 = prof_begin(T);
   if ((rc = pp_rays_nb<NB>(T, S, b0, nb, cnt, active)) != TREVR_OK) return rc;
-  k_pp_src<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, b0, nb, active, J);
-  TREVR_LAUNCH_CHECK("k_pp_src");
+  if ((rc = pp_src_nb<NB>(T, S, b0, nb, cnt, active, J)) != TREVR_OK) return rc;
   prof_end(T, TREVR_PROF_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
   k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, cap, S.bstat, S.tpp,
@@ -1013,13 +1051,15 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   if ((rc = hip_check(hipMemsetAsync(T->buf.counters, 0, sizeof(unsigned long long) * CNT_N, st),
                       "memset counters")) != TREVR_OK) return rc;
   hipEvent_t ev_setup = prof_begin(T);
-  uint32_t counts[3];
+  uint32_t counts[4];
   uint64_t hash = 0;
   if ((rc = bucket_setup(T, active, S, counts, &hash)) != TREVR_OK) return rc;
   const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
+  const uint32_t pairs = counts[3];
   Carve dyn((char*)scratch + S.fixed);
   S.nidx = dyn.take<uint32_t>(near_total);
   S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
+  S.ptau = dyn.take<float>((size_t)pairs * T->B);
   const size_t need = S.fixed + dyn.off + 256;
   T->scratch_needed = need;
   if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
@@ -1043,7 +1083,7 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
     if (rc != TREVR_OK) return rc;
   }
   T->counters_valid = true;
-  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total,
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total, pairs,
                     nb <= kBatch && whole, T->cut_default};
   return TREVR_OK;
 }

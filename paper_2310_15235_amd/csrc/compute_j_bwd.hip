@@ -121,52 +121,38 @@ __device__ inline void load_receiver_adjoints(const DevTree& T, const double* gJ
   __syncthreads();
 }
 
-// LDS adjoint accumulators of a staged p-p chunk.
-template <int NB> struct NearGrad {
-  float gk[kNChunk][NB];
-  float gh[kNChunk];
+// ------------------------------------------------------ p-p sources
+// Adjoint of k_pp_src, with the pair optical depths tau_ijb the forward
+// left in ptau.  Per pass of up to kNT (receiver i, luminous p-p element j)
+// pairs: each thread takes a pair, term_b = L_jb K(r_ij, h_i) e^{-tau_ijb};
+// dL_jb += w_ib K e_b, dh_i += w_ib L_jb e_b dK/dh, and the column adjoint
+// gt_b = -w_ib term_b goes to LDS with the pair.  Then element-major: each
+// thread takes a p-p element l, sweeps the staged pairs (groups of 16
+// culled by their segments' bounding box), decides "l absorbs on i-j" with
+// the forward's FP64 operation sequence and sums dkappa_lb += gt_b Sigma_l,
+// dh_l += gt_b kappa_lb dSigma_l/dh_l in registers.  The p-p part of the
+// raw J goes to jraw per receiver.
+template <int NB> struct PairTile {
+  double xj[kNT][3];
+  double rij2[kNT], inv2[kNT];
+  float gt[kNT][NB];
+  uint32_t j[kNT];
+  uint8_t i[kNT], valid[kNT];
+  float blo[kNT / 16][3], bhi[kNT / 16][3];   // per 16 pairs, relative to the bucket centre
 };
 
-template <int NB>
-__device__ inline void zero_near_grad(NearGrad<NB>& G) {
-  for (int u = threadIdx.x; u < kNChunk; u += kNT) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) G.gk[u][b] = 0.0f;
-    G.gh[u] = 0.0f;
-  }
-  __syncthreads();
-}
-
-template <int NB>
-__device__ inline void flush_near_grad(const NearTile<NB>& S, const NearGrad<NB>& G, uint32_t cl,
-                                       const Grad& g, int64_t n) {
-  __syncthreads();
-  for (uint32_t u = threadIdx.x; u < cl; u += kNT) {
-    const uint32_t sl = S.slot[u];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) gadd(&g.gk[(int64_t)b * n + sl], (double)G.gk[u][b]);
-    gadd(&g.gh[sl], (double)G.gh[u]);
-  }
-}
-
-// ------------------------------------------------------ p-p sources
-// Adjoint of k_pp_src: for each (receiver i, luminous p-p element j) with
-// term_b = L_jb K(r_ij, h_i) exp(-tau_ijb): dL_jb += w_ib K e_b, dh_i +=
-// w_ib L_jb e_b dK/dh, and the column adjoint -w_ib term_b goes to every
-// p-p element l on the path: dkappa_lb += . Sigma_l(b), dh_l += .
-// kappa_lb dSigma_l/dh_l.  Writes the p-p part of the raw J per receiver.
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* blist,
                                                    const uint32_t* noff, const uint32_t* nlumc,
                                                    const uint32_t* nidx, const uint32_t* roff,
+                                                   const uint32_t* poff, const float* ptau,
                                                    uint32_t b0, uint32_t nbuck,
                                                    const uint8_t* active, const double* gJ,
                                                    Grad G, double* jraw) {
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
   const int t = threadIdx.x;
-  __shared__ NearTile<NB> S;
-  __shared__ NearGrad<NB> SG;
+  __shared__ PairTile<NB> PT;
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s;
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
@@ -180,89 +166,30 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
   const uint2 lk = T.nlink[leafb];
   const int64_t n = T.n;
   uint32_t member = lk.x;
-  uint32_t rbase = roff[bucket];
+  uint32_t rbase = roff[bucket], nact = 0;
   for (;;) {
     const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
     load_receiver_adjoints<NB>(T, gJ, recv, nrecv, gw, rinvh);
+    const float* pt = ptau + ((int64_t)poff[bucket] + (int64_t)nact * nl) * NB;
     const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
     const int i = t % nrecv;
     const RecvInfo& ri = recv[i];
-    const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
-    const uint32_t si = ri.slot;
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
     double ghi = 0.0;
     const uint32_t P = (uint32_t)nrecv * nl;
     for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
+      // ---- pairs: terms and column adjoints
       const uint32_t p = pb + (uint32_t)t;
       const bool ok = t < stride && p < P;
       const uint32_t j = ok ? near[p / nrecv] : near[0];
       const double xj0 = (double)T.x[j], xj1 = (double)T.y[j], xj2 = (double)T.z[j];
-      const double e0 = xj0 - xi0, e1 = xj1 - xi1, e2 = xj2 - xi2;
+      const double e0 = xj0 - ri.x[0], e1 = xj1 - ri.x[1], e2 = xj2 - ri.x[2];
       const double rij2 = e0 * e0 + e1 * e1 + e2 * e2;
-      const double inv2 = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
-      const float jr[3] = {(float)(xj0 - c[0]), (float)(xj1 - c[1]), (float)(xj2 - c[2])};
-      float smin[3], smax[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        smin[a] = fminf(ri.rel[a], jr[a]);
-        smax[a] = fmaxf(ri.rel[a], jr[a]);
-      }
-      const float r2f = (float)rij2 * (1.0f + 1e-5f) + 1e-30f;
-      // the same p-p element test as the forward, with a callback per hit
-      auto sweep = [&](bool active_pass, auto&& on_elem, bool with_grad) {
-        for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
-          const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
-          stage_near<NB>(S, T, near, c0, cl, c);
-          if (with_grad) zero_near_grad<NB>(SG);
-          const int nsub = ((int)cl + kSub - 1) / kSub;
-          for (int sb = 0; sb < nsub; ++sb) {
-            bool need = false;
-            if (active_pass && rij2 > 0.0) {
-              float dmin2 = 0.0f;
-              bool over = true;
-#pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                const float lo = S.blo[sb][a], hi = S.bhi[sb][a];
-                over = over && (smax[a] >= lo) && (smin[a] <= hi);
-                const float dj = fmaxf(fmaxf(lo - jr[a], jr[a] - hi), 0.0f);
-                dmin2 += dj * dj;
-              }
-              need = over && dmin2 < r2f;
-            }
-            if (ballot64(need) == 0ull) continue;
-            const int u1 = min((int)cl, (sb + 1) * kSub);
-            for (int u = sb * kSub; u < u1; ++u) {
-              const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
-              const double f0 = ux - xj0, f1 = uy - xj1, f2 = uz - xj2;
-              const double w0 = ux - xi0, w1 = uy - xi1, w2 = uz - xi2;
-              double uu = (w0 * e0 + w1 * e1 + w2 * e2) * inv2;
-              uu = fmin(1.0, fmax(0.0, uu));
-              const double g0 = w0 - uu * e0, g1 = w1 - uu * e1, g2 = w2 - uu * e2;
-              const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-              const uint32_t us = S.slot[u];
-              const bool pass = need && (f0 * f0 + f1 * f1 + f2 * f2 < rij2) && b2 < S.h2[u] &&
-                                us != si && us != j;
-              on_elem(u, pass ? sqrtf((float)b2) : 0.0f, pass);
-            }
-          }
-          if (with_grad) flush_near_grad<NB>(S, SG, cl, G, n);
-        }
-      };
-      float tau[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) tau[b] = 0.0f;
-      sweep(ok, [&](int u, float bb, bool pass) {
-        if (pass) {
-          const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
-#pragma unroll
-          for (int b = 0; b < NB; ++b) tau[b] += S.kap[u][b] * sg;
-        }
-      }, false);
+      bool valid = false;
       float gt[NB];
-      bool any = false;
 #pragma unroll
       for (int b = 0; b < NB; ++b) gt[b] = 0.0f;
       if (ok) {
@@ -272,7 +199,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
         const float dKdh = -(2.0f * f + x * fshape_d(x)) * ri.kfac * rinvh[i];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const double E = exp(-(double)tau[b]);
+          const double E = exp(-(double)pt[(int64_t)p * NB + b]);
           const double Lj = (double)T.lum[(int64_t)b * n + j];
           const double term = Lj * (double)Kv * E;
           acc[b] += term;
@@ -280,38 +207,107 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
           gadd(&G.gL[(int64_t)b * n + j], w * (double)Kv * E);
           ghi += w * Lj * E * (double)dKdh;
           gt[b] = (float)(-w * term);
-          any = any || gt[b] != 0.0f;
+          valid = valid || gt[b] != 0.0f;
+        }
+        valid = valid && rij2 > 0.0;
+      }
+      PT.xj[t][0] = xj0;
+      PT.xj[t][1] = xj1;
+      PT.xj[t][2] = xj2;
+      PT.rij2[t] = rij2;
+      PT.inv2[t] = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) PT.gt[t][b] = gt[b];
+      PT.j[t] = j;
+      PT.i[t] = (uint8_t)i;
+      PT.valid[t] = valid ? 1u : 0u;
+      __syncthreads();
+      if (t < kNT / 16) {   // segment bounding boxes per 16 pairs
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int q = 16 * t; q < 16 * t + 16; ++q) {
+          if (!PT.valid[q]) continue;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float u = recv[PT.i[q]].rel[a];
+            const float v = (float)(PT.xj[q][a] - c[a]);
+            lo[a] = fminf(lo[a], fminf(u, v));
+            hi[a] = fmaxf(hi[a], fmaxf(u, v));
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          PT.blo[t][a] = lo[a];
+          PT.bhi[t][a] = hi[a];
         }
       }
-      if (__syncthreads_or(any)) {
-        sweep(ok && any, [&](int u, float bb, bool pass) {
-          // per-lane contributions, summed over rows of 16 lanes before the
-          // LDS atomics (lanes of a wavefront often meet the same element)
-          float ck[NB], gh = 0.0f;
+      if (__syncthreads_or(valid)) {
+        // ---- p-p elements against the staged pairs
+        for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
+          const uint32_t u = c0 + (uint32_t)t;
+          if (u < nnear) {
+            const uint32_t l = near[u];
+            const double ux = (double)T.x[l], uy = (double)T.y[l], uz = (double)T.z[l];
+            const double hl = T.h[l];
+            const double h2 = hl * hl;
+            const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+            const float iv = (float)(1.0 / hl);
+            float kap[NB];
 #pragma unroll
-          for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
-          if (pass) {
-            const float iv = S.invh[u];
-            const float sg = S.sig[u] * (1.0f - bb * iv);
-            const float dsg = S.sig[u] * iv * (3.0f * bb * iv - 2.0f);
+            for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
+            float elo[3], ehi[3];
+            {
+              const float hf = (float)hl;
+              const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              ck[b] = gt[b] * sg;
-              gh += gt[b] * S.kap[u][b];
+              for (int a = 0; a < 3; ++a) {
+                const float m = hf + 1e-5f * (fabsf(pr[a]) + hf);
+                elo[a] = pr[a] - m;
+                ehi[a] = pr[a] + m;
+              }
             }
-            gh *= dsg;
-          }
-          if (ballot64(pass) == 0ull) return;
-          const bool last = (threadIdx.x & 15) == 15;
+            float ck[NB], gh = 0.0f;
 #pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            const float v = row_sum16(ck[b]);
-            if (last && v != 0.0f) atomicAdd(&SG.gk[u][b], v);
+            for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
+            for (int gq = 0; gq < kNT / 16; ++gq) {
+              bool over = true;
+#pragma unroll
+              for (int a = 0; a < 3; ++a)
+                over = over && PT.bhi[gq][a] >= elo[a] && PT.blo[gq][a] <= ehi[a];
+              if (!over) continue;
+              for (int q = 16 * gq; q < 16 * gq + 16; ++q) {
+                if (!PT.valid[q]) continue;
+                const RecvInfo& rq = recv[PT.i[q]];
+                const double xi0 = rq.x[0], xi1 = rq.x[1], xi2 = rq.x[2];
+                const double qx0 = PT.xj[q][0], qx1 = PT.xj[q][1], qx2 = PT.xj[q][2];
+                const double e0q = qx0 - xi0, e1q = qx1 - xi1, e2q = qx2 - xi2;
+                const double f0 = ux - qx0, f1 = uy - qx1, f2 = uz - qx2;
+                const double w0 = ux - xi0, w1 = uy - xi1, w2 = uz - xi2;
+                double uu = (w0 * e0q + w1 * e1q + w2 * e2q) * PT.inv2[q];
+                uu = fmin(1.0, fmax(0.0, uu));
+                const double g0 = w0 - uu * e0q, g1 = w1 - uu * e1q, g2 = w2 - uu * e2q;
+                const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+                if ((f0 * f0 + f1 * f1 + f2 * f2 < PT.rij2[q]) && b2 < h2 && l != rq.slot &&
+                    l != PT.j[q]) {
+                  const float bb = sqrtf((float)b2);
+                  const float sg = sig * (1.0f - bb * iv);
+                  const float dsg = sig * iv * (3.0f * bb * iv - 2.0f);
+                  float gqk = 0.0f;
+#pragma unroll
+                  for (int b = 0; b < NB; ++b) {
+                    ck[b] += PT.gt[q][b] * sg;
+                    gqk += PT.gt[q][b] * kap[b];
+                  }
+                  gh += gqk * dsg;
+                }
+              }
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) gadd(&G.gk[(int64_t)b * n + l], (double)ck[b]);
+            gadd(&G.gh[l], (double)gh);
           }
-          const float v = row_sum16(gh);
-          if (last && v != 0.0f) atomicAdd(&SG.gh[u], v);
-        }, true);
+        }
       }
+      __syncthreads();
     }
     // receiver-wise sums in thread order
 #pragma unroll
@@ -330,6 +326,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
       gadd(&G.gh[recv[t].slot], v);
     }
     rbase += (uint32_t)nrecv;
+    nact += (uint32_t)nrecv;
     __syncthreads();
   }
 }
@@ -1130,8 +1127,8 @@ static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint
   const DevTree& D = T->dev;
   trevr_status rc;
   hipEvent_t e0 = prof_begin(T);
-  k_pp_src_bwd<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, S.bnact, b0, nb,
-                                        active, gJ, G, jraw);
+  k_pp_src_bwd<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, S.bnact, S.pcnt,
+                                        S.ptau, b0, nb, active, gJ, G, jraw);
   TREVR_LAUNCH_CHECK("k_pp_src_bwd");
   prof_end(T, TREVR_PROF_ADJ_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
@@ -1165,7 +1162,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   trevr_status rc;
   hipEvent_t ev_setup = prof_begin(T);
   bool reuse = false;
-  uint32_t counts[3];
+  uint32_t counts[4];
   if (T->fwd.valid && T->fwd.scratch == scratch && scratch_unchanged(scratch, T->fwd.epoch)) {
     uint64_t h = 0;
     if ((rc = active_hash(T, active, S.ahash + 1, &h)) != TREVR_OK) return rc;
@@ -1176,14 +1173,17 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
     counts[0] = T->fwd.nb;
     counts[1] = T->fwd.near_total;
     counts[2] = T->fwd.act_total;
+    counts[3] = T->fwd.pairs;
   } else {
     T->fwd.valid = false;
     if ((rc = bucket_setup(T, active, S, counts, &hash)) != TREVR_OK) return rc;
   }
   const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
+  const uint32_t pairs = counts[3];
   Carve dyn((char*)scratch + S.fixed);
   S.nidx = dyn.take<uint32_t>(near_total);
   S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
+  S.ptau = dyn.take<float>((size_t)pairs * T->B);
   float* gtpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
   double* jraw = dyn.take<double>((size_t)act_total * T->B);
   const size_t gbeg = (S.fixed + dyn.off + 255) & ~(size_t)255;
@@ -1202,9 +1202,10 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   prof_end(T, TREVR_PROF_SETUP, ev_setup);
   auto run = [&](uint32_t s0, uint32_t scnt, uint32_t cap) -> trevr_status {
     trevr_status r;
-    if (!reuse) {
+    if (!reuse) {   // the forward's p-p columns and pair optical depths
       hipEvent_t ev_near = prof_begin(T);
       if ((r = launch_pp_rays(T, S, s0, nb, scnt, active)) != TREVR_OK) return r;
+      if ((r = launch_pp_src(T, S, s0, nb, scnt, active, nullptr)) != TREVR_OK) return r;
       prof_end(T, TREVR_PROF_NEAR, ev_near);
     }
     switch (T->B) {
@@ -1252,7 +1253,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   k_grad_out<<<grid_of(T->n, 256), 256, 0, st>>>(D, G, gL, gkappa, grho);
   TREVR_LAUNCH_CHECK("k_grad_out");
   prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
-  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total,
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total, pairs,
                     nb <= kBatch && whole, T->cut_default};
   return TREVR_OK;
 }

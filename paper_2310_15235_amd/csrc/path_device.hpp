@@ -525,14 +525,4 @@ __device__ inline void for_each_hit_lane(const DevTree& T, const uint2* mycut, u
   }
 }
 
-// Sum over each row of 16 lanes (DPP row shifts, zero fill); the total is
-// valid in the row's last lane.  Every lane of the wavefront must be active.
-__device__ inline float row_sum16(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xf, 0xf, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xf, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xf, true));
-  return v;
-}
-
 }  // namespace trevr

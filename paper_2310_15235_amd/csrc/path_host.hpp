@@ -15,7 +15,7 @@ namespace trevr {
 // bucket readback, the p-p lists and the p-p optical depths per
 // (receiver, ray, band).
 struct Scratch {
-  uint32_t *blist, *bnact, *ncnt, *nlumc, *bstat, *nb, *ovf;
+  uint32_t *blist, *bnact, *ncnt, *pcnt, *nlumc, *bstat, *nb, *ovf;
   double *brad, *bprev;         // p-p radius; before its last growth (-1: none)
   unsigned long long* ahash;    // [2] active-set fingerprints
   uint32_t *blist_raw, *bnact_raw, *ncnt_raw, *nlumc_raw;
@@ -25,16 +25,17 @@ struct Scratch {
   size_t cut_entries;           // capacity of the cut-list buffer
   uint32_t* nidx;
   float* tpp;
+  float* ptau;                  // optical depth per (receiver, p-p source) pair
   size_t fixed;     // bytes of the part above (before the p-p lists)
 };
 
 Scratch carve_scratch(void* base, int64_t nleaves);
 
 // Active buckets, p-p radii and set sizes, heaviest-first order, offsets of
-// the p-p lists (ncnt) and of the receivers (bnact); reads back
-// counts = {buckets, p-p entries, active receivers} and the active-set
-// fingerprint (synchronises).
-trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[3],
+// the p-p lists (ncnt), the receivers (bnact) and the (receiver, p-p
+// source) pairs (pcnt); reads back counts = {buckets, p-p entries, active
+// receivers, pairs} and the active-set fingerprint (synchronises).
+trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[4],
                           uint64_t* hash);
 // Fingerprint of the active set alone, computed in dev_slot (synchronises).
 trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long long* dev_slot,
@@ -53,5 +54,9 @@ trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t c
 // p-p optical depth per (receiver, ray, band) of buckets [b0, b0 + cnt) into S.tpp.
 trevr_status launch_pp_rays(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
                             uint32_t cnt, const uint8_t* active);
+// p-p sources of buckets [b0, b0 + cnt): the pair optical depths into
+// S.ptau and, with J, the p-p part of J.
+trevr_status launch_pp_src(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
+                           uint32_t cnt, const uint8_t* active, double* J);
 
 }  // namespace trevr

@@ -86,7 +86,7 @@ struct FwdState {
   const void* scratch;
   uint64_t epoch;       // the library's write to that scratch that left it
   uint64_t hash;
-  uint32_t nb, near_total, act_total;
+  uint32_t nb, near_total, act_total, pairs;
   bool cuts_kept;       // the cut buffer holds every bucket's cut list
   uint32_t cut_stride;  // ... at this many entries per bucket
 };
