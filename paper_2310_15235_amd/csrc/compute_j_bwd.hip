@@ -460,9 +460,10 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
 // Sources per LDS window and workgroups per CU of the far-field adjoint:
 // up to four bands the window is sized so that three workgroups fit in
 // the 160 KiB of LDS (and the register budget is held to three wavefronts
-// per SIMD); with more bands, two.
+// per SIMD); with more bands, two (registers limit them anyway).
 template <int NB> struct BwdCfg {
-  static constexpr int cap = NB == 1 ? 512 : NB == 2 ? 448 : NB == 3 ? 320 : NB == 4 ? 240 : 128;
+  static constexpr int cap = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 5 ? 512 : NB == 6 ? 448
+                            : NB == 7 ? 384 : 320;
   static constexpr int waves = NB <= 4 ? 3 : 2;
 };
 
@@ -498,8 +499,8 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
   __shared__ SrcWindow<CAP, NB> W;
   __shared__ RayGroup RG;
   __shared__ uint32_t sid[CAP];
-  __shared__ float sgL[CAP][NB], sgtau[CAP][NB], sgs[CAP], sgp[CAP][3];
-  __shared__ float tpp[kRMax][64][NB], gtpp[kRMax][64][NB];
+  __shared__ float sgtau[CAP][NB], sgs[CAP];
+  __shared__ float gtpp[kRMax][64][NB];
   __shared__ float tex[64][NB], gtex[64][NB];
   __shared__ RecvInfo recv[kRMax];
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
@@ -546,10 +547,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
       for (int q = t; q < nrecv * kn; q += kFT) {
         const int i = q / kn, kq = q % kn;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          tpp[i][kq][b] = tppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
-          gtpp[i][kq][b] = 0.0f;
-        }
+        for (int b = 0; b < NB; ++b) gtpp[i][kq][b] = 0.0f;
       }
       if (t < kn) {
 #pragma unroll
@@ -565,12 +563,8 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         const uint32_t nsg = min(nsg_all - skip, (uint32_t)CAP);
         for (uint32_t q = t; q < nsg; q += kFT) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            sgL[q][b] = 0.0f;
-            sgtau[q][b] = 0.0f;
-          }
+          for (int b = 0; b < NB; ++b) sgtau[q][b] = 0.0f;
           sgs[q] = 0.0f;
-          sgp[q][0] = sgp[q][1] = sgp[q][2] = 0.0f;
         }
         uint32_t q0, q1;
         sort_window<CAP, NB>(W, nsg, rt, q0, q1);
@@ -629,6 +623,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         // ---- (receiver, source) pairs
         {
           const RecvInfo& ri = recv[ii];
+          const float* tpr = tppg + ((int64_t)(rbase + ii) * nray + k0) * NB;
           for (uint32_t q = (uint32_t)my_q; q < nsg; q += (uint32_t)per_round) {
             const float dx = W.rel[q][0] - ri.rel[0];
             const float dy = W.rel[q][1] - ri.rel[1];
@@ -649,7 +644,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
             for (int b = 0; b < NB; ++b) {
               const float tau = W.tau[q][b];
               const float tc = (tau > 0.0f) ? tau * ratio : 0.0f;
-              const float e = __expf(-(tpp[ii][ray][b] + tc));
+              const float e = __expf(-(tpr[ray * NB + b] + tc));
               const float Le = W.L[q][b] * e;
               const float LKe = Le * Kv;
               if (has_i) acc[b] += (double)LKe;
@@ -685,13 +680,20 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
             }
             if (my_i == 0) {
 #pragma unroll
-              for (int b = 0; b < NB; ++b) {
-                sgL[q][b] += pL[b];
-                sgtau[q][b] += pt[b];
-              }
+              for (int b = 0; b < NB; ++b) sgtau[q][b] += pt[b];
               sgs[q] += ps;
+              // luminosity and position adjoints straight to the accumulators
+              const uint32_t id = sid[q];
+              if (id & kSrcCellBit) {
+                const uint32_t node = id & ~kSrcCellBit;
 #pragma unroll
-              for (int a = 0; a < 3; ++a) sgp[q][a] += pp[a];
+                for (int b = 0; b < NB; ++b) gadd(&G.gLb[(int64_t)node * NB + b], (double)pL[b]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) gadd(&G.gcen[(int64_t)node * 4 + a], (double)pp[a]);
+              } else {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) gadd(&G.gL[(int64_t)b * n + id], (double)pL[b]);
+              }
             }
           }
           // ---- isotropic background
@@ -701,7 +703,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
 #pragma unroll
               for (int b = 0; b < NB; ++b) {
                 const float term = (float)(4.0 * kPi / nray) * bg[b] *
-                                   __expf(-(tpp[ii][kq][b] + tex[kq][b]));
+                                   __expf(-(tpr[kq * NB + b] + tex[kq][b]));
                 if (has_i) acc[b] += (double)term;
                 const float w = has_i ? gw[ii][b] * term : 0.0f;
                 if (w != 0.0f) atomicAdd(&gtpp[ii][kq][b], -w);
@@ -794,20 +796,14 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         __syncthreads();
 
         // ---- flush the source adjoints
-        for (uint32_t q = t; q < nsg; q += kFT) {
+        for (uint32_t q = t; q < nsg; q += kFT) {   // s = (p - c).n of merged cells
           const uint32_t id = sid[q];
-          if (id & kSrcCellBit) {
+          if ((id & kSrcCellBit) && W.s[q] != 0.0f && sgs[q] != 0.0f) {
             const uint32_t node = id & ~kSrcCellBit;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) gadd(&G.gLb[(int64_t)node * NB + b], (double)sgL[q][b]);
-            const float gsv = (W.s[q] != 0.0f) ? sgs[q] : 0.0f;
             const int ray = W.ray[q];
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-              gadd(&G.gcen[(int64_t)node * 4 + a], (double)sgp[q][a] + (double)gsv * RG.n[ray][a]);
-          } else {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) gadd(&G.gL[(int64_t)b * n + id], (double)sgL[q][b]);
+              gadd(&G.gcen[(int64_t)node * 4 + a], (double)sgs[q] * RG.n[ray][a]);
           }
         }
         __syncthreads();
