@@ -166,7 +166,7 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->prof_on = false;
   T->ev_used = 0;
   T->host_u32 = nullptr;
-  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, 0, false, 0};
+  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, 0, false, 0, false};
   T->stack_large = false;
   T->cut_default = kCutCap;
   for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }

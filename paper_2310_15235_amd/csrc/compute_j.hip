@@ -423,6 +423,11 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
         smax[a] = fmaxf(ri.rel[a], jr[a]);
       }
       const float r2f = (float)rij2 * (1.0f + 1e-5f) + 1e-30f;
+      // the segment i -> j for the FP32 culling (relative to the bucket centre)
+      const float sd[3] = {jr[0] - ri.rel[0], jr[1] - ri.rel[1], jr[2] - ri.rel[2]};
+      float sinv[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sinv[a] = (sd[a] != 0.0f) ? 1.0f / sd[a] : 0.0f;
       float tau[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) tau[b] = 0.0f;
@@ -433,16 +438,23 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
         for (int sb = 0; sb < nsub; ++sb) {
           bool need = false;
           if (ok && rij2 > 0.0) {
-            float dmin2 = 0.0f;
+            // the sub-box (elements grown by their size) must meet the
+            // segment, and come nearer to j than i is
+            float dmin2 = 0.0f, t0 = 0.0f, t1 = 1.0f;
             bool over = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
               const float lo = S.blo[sb][a], hi = S.bhi[sb][a];
               over = over && (smax[a] >= lo) && (smin[a] <= hi);
+              if (sd[a] != 0.0f) {
+                const float u = (lo - ri.rel[a]) * sinv[a], v = (hi - ri.rel[a]) * sinv[a];
+                t0 = fmaxf(t0, fminf(u, v));
+                t1 = fminf(t1, fmaxf(u, v));
+              }
               const float dj = fmaxf(fmaxf(lo - jr[a], jr[a] - hi), 0.0f);
               dmin2 += dj * dj;
             }
-            need = over && dmin2 < r2f;
+            need = over && t0 <= t1 + 1e-4f && dmin2 < r2f;
           }
           if (ballot64(need) == 0ull) continue;
           if (!need) continue;
@@ -506,7 +518,8 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
                                              const uint32_t* roff, uint32_t b0, uint32_t nbuck,
                                              const uint2* cut, uint32_t cut_cap,
                                              const uint32_t* bstat, const float* tppg,
-                                             const float* bg, double* J, const uint8_t* active) {
+                                             const float* bg, double* J, const uint8_t* active,
+                                             float* kept_tau, float* kept_tex) {
   constexpr int kSrcCap = SrcCap<NB>::value;
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
@@ -629,6 +642,17 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
           }
         }
         __syncthreads();
+        // keep the optical depths for the adjoint when the group fits one
+        // window (of this kernel and of the adjoint)
+        if (kept_tau && first_chunk && nsg_all <= (uint32_t)KeptCap<NB>::value) {
+          float* dst = kept_tau + ((size_t)blockIdx.x * ngroups + g) * KeptCap<NB>::value * NB;
+          for (uint32_t q = t; q < nsg * NB; q += kFT) dst[q] = (&W.tau[0][0])[q];
+          if (use_bg && t < kn) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              kept_tex[((size_t)blockIdx.x * nray + k0 + t) * NB + b] = tex[t][b];
+          }
+        }
 
         // ---- far sources at every receiver (Section 2.5.1, eq. intint)
         if (has_i) {
@@ -779,6 +803,26 @@ static Scratch carve(void* base, int64_t nleaves) {
 }
 
 Scratch carve_scratch(void* base, int64_t nleaves) { return carve(base, nleaves); }
+
+// Cell optical depths the forward keeps for the adjoint: per bucket of a
+// batch and ray group, KeptCap sources x bands (and with a background the
+// exit depth per ray); not kept when that would take more than 1 GiB.
+void take_kept(const trevr_tree* T, Scratch& S, Carve& cv, uint32_t nb) {
+  const size_t buckets = std::min<size_t>(nb, kBatch);
+  const size_t groups = (size_t)(T->nray + 63) / 64;
+  static constexpr int caps[9] = {0, KeptCap<1>::value, KeptCap<2>::value, KeptCap<3>::value,
+                                  KeptCap<4>::value, KeptCap<5>::value, KeptCap<6>::value,
+                                  KeptCap<7>::value, KeptCap<8>::value};
+  const size_t tau_n = buckets * groups * caps[T->B] * T->B;
+  const size_t tex_n = (T->p.flags & TREVR_BACKGROUND) ? buckets * T->nray * T->B : 0;
+  if ((tau_n + tex_n) * sizeof(float) > ((size_t)1 << 30)) {
+    S.kept_tau = nullptr;
+    S.kept_tex = nullptr;
+    return;
+  }
+  S.kept_tau = cv.take<float>(tau_n);
+  S.kept_tex = tex_n ? cv.take<float>(tex_n) : nullptr;
+}
 
 namespace {
 std::mutex g_scratch_mu;
@@ -1031,7 +1075,7 @@ static trevr_status launch_pair(trevr_tree* T, const Scratch& S, uint32_t b0, ui
   prof_end(T, TREVR_PROF_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
   k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, cap, S.bstat, S.tpp,
-                                bg, J, active);
+                                bg, J, active, S.kept_tau, S.kept_tex);
   TREVR_LAUNCH_CHECK("k_far");
   prof_end(T, TREVR_PROF_REDUCE, e1);
   return rc;
@@ -1060,6 +1104,7 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   S.nidx = dyn.take<uint32_t>(near_total);
   S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
   S.ptau = dyn.take<float>((size_t)pairs * T->B);
+  take_kept(T, S, dyn, nb);
   const size_t need = S.fixed + dyn.off + 256;
   T->scratch_needed = need;
   if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
@@ -1084,7 +1129,8 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   }
   T->counters_valid = true;
   T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total, pairs,
-                    nb <= kBatch && whole, T->cut_default};
+                    nb <= kBatch && whole, T->cut_default,
+                    S.kept_tau != nullptr && nb <= kBatch && whole};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

@@ -45,7 +45,24 @@ struct Grad {
   double* gLb;      // [node][B]
   double* gcen;     // [node][4]: d/d centre; later (u, v) of the centre adjoint
   double* grpp;     // [bucket] d/d r_pp
+  // The far field adds to galpha, gLb and gcen from every bucket, and the
+  // cells near the root are shared by most buckets: workgroups add to one
+  // of ka (ks) copies of galpha (of gLb, gcen), chosen by workgroup index,
+  // which spreads the atomics over more addresses; the copies are summed
+  // into the first before the tree pass.
+  uint32_t ka, ks;  // copies (powers of two)
+  int64_t na, ns;   // elements per copy: of galpha; of gLb and of gcen (x 4 / B)
 };
+
+__device__ inline double* galpha_copy(const Grad& G) {
+  return G.galpha + (int64_t)(blockIdx.x & (G.ka - 1)) * G.na;
+}
+__device__ inline double* gLb_copy(const Grad& G) {
+  return G.gLb + (int64_t)(blockIdx.x & (G.ks - 1)) * G.ns;
+}
+__device__ inline double* gcen_copy(const Grad& G, int B) {
+  return G.gcen + (int64_t)(blockIdx.x & (G.ks - 1)) * (G.ns / B) * 4;
+}
 
 __device__ inline void gadd(double* a, double v) {
   if (v != 0.0) unsafeAtomicAdd(a, v);
@@ -255,15 +272,13 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
 #pragma unroll
             for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
             float elo[3], ehi[3];
-            {
-              const float hf = (float)hl;
-              const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
+            const float hf = (float)hl;
+            const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
 #pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                const float m = hf + 1e-5f * (fabsf(pr[a]) + hf);
-                elo[a] = pr[a] - m;
-                ehi[a] = pr[a] + m;
-              }
+            for (int a = 0; a < 3; ++a) {
+              const float m = hf + 1e-5f * (fabsf(pr[a]) + hf);
+              elo[a] = pr[a] - m;
+              ehi[a] = pr[a] + m;
             }
             float ck[NB], gh = 0.0f;
 #pragma unroll
@@ -463,7 +478,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
 // per SIMD); with more bands, two (registers limit them anyway).
 template <int NB> struct BwdCfg {
   static constexpr int cap = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 5 ? 512 : NB == 6 ? 448
-                            : NB == 7 ? 384 : 320;
+                            : NB == 7 ? 320 : 256;
   static constexpr int waves = NB <= 4 ? 3 : 2;
 };
 
@@ -490,17 +505,18 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
                                                  const float* tppg,
                                                  const float* bg, const uint8_t* active,
                                                  const double* gJ, const double* jraw,
-                                                 float* gtppg, Grad G) {
+                                                 float* gtppg, Grad G, const float* kept_tau,
+                                                 const float* kept_tex) {
   constexpr int CAP = BwdCfg<NB>::cap;
   const uint32_t bucket = b0 + blockIdx.x;
   if (bucket >= nbuck) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
-  __shared__ SrcWindow<CAP, NB> W;
+  __shared__ SrcWindow<CAP, NB, false> W;   // suffix adds kept in sgtau
   __shared__ RayGroup RG;
   __shared__ uint32_t sid[CAP];
   __shared__ float sgtau[CAP][NB], sgs[CAP];
-  __shared__ float gtpp[kRMax][64][NB];
+  __shared__ float tpp[kRMax][64][NB], gtpp[kRMax][64][NB];
   __shared__ float tex[64][NB], gtex[64][NB];
   __shared__ RecvInfo recv[kRMax];
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
@@ -521,6 +537,9 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
   const bool thick = (T.flags & TREVR_THICK_CORR) != 0u;
 
   double grpp = 0.0;   // this thread's share of d/d r_pp
+  double* const galpha_c = galpha_copy(G);
+  double* const gLb_c = gLb_copy(G);
+  double* const gcen_c = gcen_copy(G, NB);
   uint32_t rbase = roff[bucket];
   uint32_t member = lk.x;
   for (;;) {
@@ -547,7 +566,10 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
       for (int q = t; q < nrecv * kn; q += kFT) {
         const int i = q / kn, kq = q % kn;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) gtpp[i][kq][b] = 0.0f;
+        for (int b = 0; b < NB; ++b) {
+          tpp[i][kq][b] = tppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
+          gtpp[i][kq][b] = 0.0f;
+        }
       }
       if (t < kn) {
 #pragma unroll
@@ -569,61 +591,74 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         uint32_t q0, q1;
         sort_window<CAP, NB>(W, nsg, rt, q0, q1);
 
-        // ---- first sweep: cell optical depths.  Each hit is applied by the
-        // thread that found it: sources on its ray inside the chord get the
-        // partial length, the nearest source beyond it a suffix add (resolved
-        // below along the ray's sources sorted by distance).
-        for_each_hit_lane(T, mycut, ncut, c, r, kn, RG,
-                          [&](uint32_t node, int kq, double ht0, double ht1, bool) {
-          const float len = (float)(ht1 - ht0);
-          const float* al = &T.alpha[((int64_t)node * T.nclass + RG.cls[kq]) * NB];
-          float av[NB];
+        // ---- cell optical depths: kept by the forward when the group fits
+        // one window; otherwise a first sweep over the hits
+        if (kept_tau && skip == 0 && nsg_all <= (uint32_t)KeptCap<NB>::value) {
+          const float* src = kept_tau + ((size_t)blockIdx.x * ngroups + g) * KeptCap<NB>::value * NB;
+          for (uint32_t q = t; q < nsg * NB; q += kFT) (&W.tau[0][0])[q] = src[q];
+          if (use_bg && t < kn) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            av[b] = al[b];
-            if (use_bg) atomicAdd(&tex[kq][b], av[b] * len);
+            for (int b = 0; b < NB; ++b)
+              tex[t][b] = kept_tex[((size_t)blockIdx.x * nray + k0 + t) * NB + b];
           }
-          const uint32_t r0 = W.ray_beg[kq], r1 = W.ray_beg[kq + 1];
-          uint32_t lo_p = r0, hi_p = r1;
-          while (lo_p < hi_p) {
-            const uint32_t mid = (lo_p + hi_p) >> 1;
-            if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
-          }
-          uint32_t pq = lo_p;
-          for (; pq < r1; ++pq) {
-            const uint32_t si = W.order[pq];
-            const double sq = (double)W.s[si];
-            if (!(sq < ht1)) break;
-            const float part = (float)(sq - ht0);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) atomicAdd(&W.tau[si][b], av[b] * part);
-          }
-          if (pq < r1) {
-            const uint32_t si = W.order[pq];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) atomicAdd(&W.sfx[si][b], av[b] * len);
-          }
-        });
-        __syncthreads();
-        if (rt) {
-          float run[NB];
-#pragma unroll
-          for (int b = 0; b < NB; ++b) run[b] = 0.0f;
-          for (uint32_t pq = q0; pq < q1; ++pq) {
-            const uint32_t si = W.order[pq];
-#pragma unroll
+          __syncthreads();
+        } else {
+          // ---- first sweep: cell optical depths.  Each hit is applied by the
+          // thread that found it: sources on its ray inside the chord get the
+          // partial length, the nearest source beyond it a suffix add (resolved
+          // below along the ray's sources sorted by distance).
+          for_each_hit_lane(T, mycut, ncut, c, r, kn, RG,
+                            [&](uint32_t node, int kq, double ht0, double ht1, bool) {
+            const float len = (float)(ht1 - ht0);
+            const float* al = &T.alpha[((int64_t)node * T.nclass + RG.cls[kq]) * NB];
+            float av[NB];
+  #pragma unroll
             for (int b = 0; b < NB; ++b) {
-              run[b] += W.sfx[si][b];
-              W.tau[si][b] += run[b];
+              av[b] = al[b];
+              if (use_bg) atomicAdd(&tex[kq][b], av[b] * len);
+            }
+            const uint32_t r0 = W.ray_beg[kq], r1 = W.ray_beg[kq + 1];
+            uint32_t lo_p = r0, hi_p = r1;
+            while (lo_p < hi_p) {
+              const uint32_t mid = (lo_p + hi_p) >> 1;
+              if ((double)W.s[W.order[mid]] > ht0) hi_p = mid; else lo_p = mid + 1;
+            }
+            uint32_t pq = lo_p;
+            for (; pq < r1; ++pq) {
+              const uint32_t si = W.order[pq];
+              const double sq = (double)W.s[si];
+              if (!(sq < ht1)) break;
+              const float part = (float)(sq - ht0);
+  #pragma unroll
+              for (int b = 0; b < NB; ++b) atomicAdd(&W.tau[si][b], av[b] * part);
+            }
+            if (pq < r1) {
+              const uint32_t si = W.order[pq];
+  #pragma unroll
+              for (int b = 0; b < NB; ++b) atomicAdd(&sgtau[si][b], av[b] * len);
+            }
+          });
+          __syncthreads();
+          if (rt) {
+            float run[NB];
+  #pragma unroll
+            for (int b = 0; b < NB; ++b) run[b] = 0.0f;
+            for (uint32_t pq = q0; pq < q1; ++pq) {
+              const uint32_t si = W.order[pq];
+  #pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                run[b] += sgtau[si][b];
+                W.tau[si][b] += run[b];
+                sgtau[si][b] = 0.0f;
+              }
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
 
         // ---- (receiver, source) pairs
         {
           const RecvInfo& ri = recv[ii];
-          const float* tpr = tppg + ((int64_t)(rbase + ii) * nray + k0) * NB;
           for (uint32_t q = (uint32_t)my_q; q < nsg; q += (uint32_t)per_round) {
             const float dx = W.rel[q][0] - ri.rel[0];
             const float dy = W.rel[q][1] - ri.rel[1];
@@ -644,7 +679,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
             for (int b = 0; b < NB; ++b) {
               const float tau = W.tau[q][b];
               const float tc = (tau > 0.0f) ? tau * ratio : 0.0f;
-              const float e = __expf(-(tpr[ray * NB + b] + tc));
+              const float e = __expf(-(tpp[ii][ray][b] + tc));
               const float Le = W.L[q][b] * e;
               const float LKe = Le * Kv;
               if (has_i) acc[b] += (double)LKe;
@@ -687,9 +722,9 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
               if (id & kSrcCellBit) {
                 const uint32_t node = id & ~kSrcCellBit;
 #pragma unroll
-                for (int b = 0; b < NB; ++b) gadd(&G.gLb[(int64_t)node * NB + b], (double)pL[b]);
+                for (int b = 0; b < NB; ++b) gadd(&gLb_c[(int64_t)node * NB + b], (double)pL[b]);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) gadd(&G.gcen[(int64_t)node * 4 + a], (double)pp[a]);
+                for (int a = 0; a < 3; ++a) gadd(&gcen_c[(int64_t)node * 4 + a], (double)pp[a]);
               } else {
 #pragma unroll
                 for (int b = 0; b < NB; ++b) gadd(&G.gL[(int64_t)b * n + id], (double)pL[b]);
@@ -703,7 +738,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
 #pragma unroll
               for (int b = 0; b < NB; ++b) {
                 const float term = (float)(4.0 * kPi / nray) * bg[b] *
-                                   __expf(-(tpr[kq * NB + b] + tex[kq][b]));
+                                   __expf(-(tpp[ii][kq][b] + tex[kq][b]));
                 if (has_i) acc[b] += (double)term;
                 const float w = has_i ? gw[ii][b] * term : 0.0f;
                 if (w != 0.0f) atomicAdd(&gtpp[ii][kq][b], -w);
@@ -722,7 +757,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         }
         __syncthreads();
 
-        // ---- second sweep: adjoint of the cell optical depths.  W.sfx now
+        // ---- second sweep: adjoint of the cell optical depths.  W.tau now
         // holds, by sorted position, the suffix sums of the source tau
         // adjoints along each ray.
         if (rt) {
@@ -734,7 +769,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
               run[b] += sgtau[si][b];
-              W.sfx[pq - 1][b] = run[b];
+              W.tau[pq - 1][b] = run[b];
             }
           }
         }
@@ -774,12 +809,12 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
           }
           if (pq < r1) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) ga[b] += len * W.sfx[pq][b];
+            for (int b = 0; b < NB; ++b) ga[b] += len * W.tau[pq][b];
           }
           float gr = 0.0f;
           if (clipped && first < r1) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) gr += av[b] * W.sfx[first][b];
+            for (int b = 0; b < NB; ++b) gr += av[b] * W.tau[first][b];
           }
           if (bg_here) {
 #pragma unroll
@@ -789,7 +824,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
             }
           }
           grpp -= (double)gr;
-          double* dst = &G.galpha[((int64_t)node * T.nclass + cls) * NB];
+          double* dst = &galpha_c[((int64_t)node * T.nclass + cls) * NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) gadd(&dst[b], (double)ga[b]);
         });
@@ -803,7 +838,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
             const int ray = W.ray[q];
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-              gadd(&G.gcen[(int64_t)node * 4 + a], (double)sgs[q] * RG.n[ray][a]);
+              gadd(&gcen_c[(int64_t)node * 4 + a], (double)sgs[q] * RG.n[ray][a]);
           }
         }
         __syncthreads();
@@ -1085,6 +1120,15 @@ __global__ void k_grad_out(DevTree T, Grad G, double* gL, double* gk, double* gr
   }
 }
 
+// Sum the copies of an accumulator into the first.
+__global__ void k_sum_copies(double* a, int64_t per, uint32_t copies) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= per) return;
+  double s = a[i];
+  for (uint32_t k = 1; k < copies; ++k) s += a[(int64_t)k * per + i];
+  a[i] = s;
+}
+
 __global__ void k_zero_u64(unsigned long long* a, int64_t count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < count) a[i] = 0ull;
@@ -1103,9 +1147,17 @@ static Grad carve_grad(Carve& cv, const trevr_tree* T) {
   g.gk = cv.take<double>(B * n);
   g.gh = cv.take<double>(n);
   g.gr = cv.take<double>(n);
-  g.galpha = cv.take<double>(nn * T->nclass * B);
-  g.gLb = cv.take<double>(nn * B);
-  g.gcen = cv.take<double>(nn * 4);
+  // copies of the far-field accumulators within a budget of 256 MiB each
+  const size_t budget = (size_t)256 << 20;
+  g.na = nn * T->nclass * B;
+  g.ns = nn * B;
+  g.ka = 1;
+  while (g.ka < 8 && (size_t)(2 * g.ka) * g.na * sizeof(double) <= budget) g.ka *= 2;
+  g.ks = 1;
+  while (g.ks < 16 && (size_t)(2 * g.ks) * nn * (B + 4) * sizeof(double) <= budget) g.ks *= 2;
+  g.galpha = cv.take<double>((size_t)g.ka * g.na);
+  g.gLb = cv.take<double>((size_t)g.ks * nn * B);
+  g.gcen = cv.take<double>((size_t)g.ks * nn * 4);
   g.grpp = cv.take<double>(nl);
   return g;
 }
@@ -1118,7 +1170,8 @@ static Grad carve_grad(Carve& cv, const trevr_tree* T) {
 template <int NB>
 static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
                               uint32_t cnt, uint32_t cap, const uint8_t* active, const float* bg,
-                              const double* gJ, const Grad& G, double* jraw, float* gtpp) {
+                              const double* gJ, const Grad& G, double* jraw, float* gtpp,
+                              const float* kept_tau, const float* kept_tex) {
   hipStream_t st = T->stream;
   const DevTree& D = T->dev;
   trevr_status rc;
@@ -1129,7 +1182,7 @@ static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint
   prof_end(T, TREVR_PROF_ADJ_NEAR, e0);
   hipEvent_t e1 = prof_begin(T);
   k_far_bwd<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, cap, S.bstat,
-                                     S.tpp, bg, active, gJ, jraw, gtpp, G);
+                                     S.tpp, bg, active, gJ, jraw, gtpp, G, kept_tau, kept_tex);
   TREVR_LAUNCH_CHECK("k_far_bwd");
   prof_end(T, TREVR_PROF_ADJ_REDUCE, e1);
   hipEvent_t e2 = prof_begin(T);
@@ -1180,6 +1233,11 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   S.nidx = dyn.take<uint32_t>(near_total);
   S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
   S.ptau = dyn.take<float>((size_t)pairs * T->B);
+  take_kept(T, S, dyn, nb);
+  // the forward's far-source optical depths apply to its own (single) batch
+  const bool use_kept = reuse && T->fwd.kept && S.kept_tau != nullptr;
+  const float* kept_tau = use_kept ? S.kept_tau : nullptr;
+  const float* kept_tex = use_kept ? S.kept_tex : nullptr;
   float* gtpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
   double* jraw = dyn.take<double>((size_t)act_total * T->B);
   const size_t gbeg = (S.fixed + dyn.off + 255) & ~(size_t)255;
@@ -1205,14 +1263,22 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
       prof_end(T, TREVR_PROF_NEAR, ev_near);
     }
     switch (T->B) {
-      case 1: return bwd_batch<1>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
-      case 2: return bwd_batch<2>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
-      case 3: return bwd_batch<3>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
-      case 4: return bwd_batch<4>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
-      case 5: return bwd_batch<5>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
-      case 6: return bwd_batch<6>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
-      case 7: return bwd_batch<7>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
-      default: return bwd_batch<8>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp);
+      case 1: return bwd_batch<1>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
+      case 2: return bwd_batch<2>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
+      case 3: return bwd_batch<3>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
+      case 4: return bwd_batch<4>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
+      case 5: return bwd_batch<5>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
+      case 6: return bwd_batch<6>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
+      case 7: return bwd_batch<7>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
+      default: return bwd_batch<8>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
+                                   kept_tau, kept_tex);
     }
   };
   bool whole = reuse && T->fwd.cuts_kept;
@@ -1236,6 +1302,16 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
     TREVR_LAUNCH_CHECK("k_rpp_bwd");
   }
   const DevTree& D = T->dev;
+  if (G.ka > 1) {
+    k_sum_copies<<<grid_of(G.na, 256), 256, 0, st>>>(G.galpha, G.na, G.ka);
+    TREVR_LAUNCH_CHECK("k_sum_copies");
+  }
+  if (G.ks > 1) {
+    k_sum_copies<<<grid_of(G.ns, 256), 256, 0, st>>>(G.gLb, G.ns, G.ks);
+    TREVR_LAUNCH_CHECK("k_sum_copies");
+    k_sum_copies<<<grid_of(T->num_nodes * 4, 256), 256, 0, st>>>(G.gcen, T->num_nodes * 4, G.ks);
+    TREVR_LAUNCH_CHECK("k_sum_copies");
+  }
   k_cen_prep<<<grid_of(T->num_nodes, 256), 256, 0, st>>>(D, G);
   TREVR_LAUNCH_CHECK("k_cen_prep");
   for (size_t d = 0; d < T->levels.size(); ++d) {
@@ -1250,7 +1326,7 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   TREVR_LAUNCH_CHECK("k_grad_out");
   prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
   T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total, pairs,
-                    nb <= kBatch && whole, T->cut_default};
+                    nb <= kBatch && whole, T->cut_default, use_kept};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

@@ -306,6 +306,12 @@ __device__ inline bool ray_meets_box(const float o[3], const float inv[3], const
 
 // ------------------------------------------------------------- far field
 constexpr int kFT = 256;   // threads of the far-field kernels
+
+// Sources of a (bucket, ray group) whose cell optical depths the forward
+// keeps for the adjoint when all of them fit one window of both kernels.
+template <int NB> struct KeptCap {
+  static constexpr int value = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 6 ? 224 : 256;
+};
 // Sources per LDS window of the forward far-field kernel: as many as let
 // three workgroups share a CU's 160 KiB of LDS (two from seven bands on,
 // where registers limit it anyway).
@@ -357,12 +363,13 @@ __device__ inline void load_ray_group(const DevTree& T, int k0, int kn, RayGroup
 // Far sources of a ray group held in LDS, CAP at a time: position relative
 // to the bucket centre, distance s projected on the ray of their pixel,
 // per-band luminosity, accumulated cell optical depth (tau, plus suffix
-// adds in sfx), the ray (in the group) and the per-ray order by s.
-template <int CAP, int NB> struct SrcWindow {
+// adds in sfx unless the user keeps those elsewhere), the ray (in the group)
+// and the per-ray order by s.
+template <int CAP, int NB, bool kSfx = true> struct SrcWindow {
   float rel[CAP][3];
   float s[CAP];
   float tau[CAP][NB];
-  float sfx[CAP][NB];
+  float sfx[kSfx ? CAP : 1][NB];
   float L[CAP][NB];
   uint8_t ray[CAP];
   uint16_t order[CAP];
@@ -377,10 +384,11 @@ constexpr uint32_t kSrcCellBit = 0x80000000u;
 // with group index in [skip, skip + CAP) (group index = order in the cut
 // list).  Returns the number of sources of the group.  `ids` (optional)
 // receives each staged source's id.
-template <int CAP, int NB>
+template <int CAP, int NB, bool kSfx>
 __device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, uint32_t ncut,
                                         const double c[3], int k0, int kn, uint32_t skip,
-                                        SrcWindow<CAP, NB>& W, uint32_t* wcnt, uint32_t* ids) {
+                                        SrcWindow<CAP, NB, kSfx>& W, uint32_t* wcnt,
+                                        uint32_t* ids) {
   const int t = threadIdx.x;
   const int64_t n = T.n;
   uint32_t nsg_all = 0;
@@ -429,7 +437,7 @@ __device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, ui
       for (int b = 0; b < NB; ++b) {
         W.L[slot][b] = Lv[b];
         W.tau[slot][b] = 0.0f;
-        W.sfx[slot][b] = 0.0f;
+        if constexpr (kSfx) W.sfx[slot][b] = 0.0f;
       }
       W.ray[slot] = (uint8_t)(pix - k0);
       if (ids) ids[slot] = part ? ent.x : (ent.x | kSrcCellBit);
@@ -442,9 +450,9 @@ __device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, ui
 // Bin the staged sources by ray and sort each ray's sources by s (ray
 // owner threads t < 64); the owner of a ray gets its range [q0, q1) of
 // W.order.  Ends with a barrier: every thread may then read any ray's list.
-template <int CAP, int NB>
-__device__ inline void sort_window(SrcWindow<CAP, NB>& W, uint32_t nsg, bool rt, uint32_t& q0,
-                                   uint32_t& q1) {
+template <int CAP, int NB, bool kSfx>
+__device__ inline void sort_window(SrcWindow<CAP, NB, kSfx>& W, uint32_t nsg, bool rt,
+                                   uint32_t& q0, uint32_t& q1) {
   const int t = threadIdx.x;
   if (t < 64) W.ray_fill[t] = 0u;
   __syncthreads();

@@ -26,10 +26,13 @@ struct Scratch {
   uint32_t* nidx;
   float* tpp;
   float* ptau;                  // optical depth per (receiver, p-p source) pair
+  float *kept_tau, *kept_tex;   // far-source optical depths kept for the adjoint (or null)
   size_t fixed;     // bytes of the part above (before the p-p lists)
 };
 
 Scratch carve_scratch(void* base, int64_t nleaves);
+// Places kept_tau / kept_tex (after the p-p part of the dynamic region).
+void take_kept(const trevr_tree* T, Scratch& S, Carve& cv, uint32_t nb);
 
 // Active buckets, p-p radii and set sizes, heaviest-first order, offsets of
 // the p-p lists (ncnt), the receivers (bnact) and the (receiver, p-p

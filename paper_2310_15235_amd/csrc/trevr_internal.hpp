@@ -89,6 +89,7 @@ struct FwdState {
   uint32_t nb, near_total, act_total, pairs;
   bool cuts_kept;       // the cut buffer holds every bucket's cut list
   uint32_t cut_stride;  // ... at this many entries per bucket
+  bool kept;            // far-source optical depths of the forward are in the scratch
 };
 
 struct trevr_tree {
