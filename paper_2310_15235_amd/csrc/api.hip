@@ -54,17 +54,28 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
 }
 
 hipEvent_t prof_begin(trevr_tree* t) {
-  if (!t->prof_on || t->ev_used + 2 > t->ev_pool.size()) return nullptr;
+  if (!t || !t->prof_on || t->ev_used + 2 > t->ev_pool.size()) return nullptr;
   hipEvent_t e = t->ev_pool[t->ev_used++];
   if (hipEventRecord(e, t->stream) != hipSuccess) return nullptr;
   return e;
 }
 
 void prof_end(trevr_tree* t, int slot, hipEvent_t begin) {
-  if (!begin || t->ev_used + 1 > t->ev_pool.size()) return;
+  if (!t || !begin || t->ev_used + 1 > t->ev_pool.size()) return;
   hipEvent_t e = t->ev_pool[t->ev_used++];
   if (hipEventRecord(e, t->stream) != hipSuccess) return;
   t->ev_pending.push_back({slot, {begin, e}});
+}
+
+trevr_status upload_dev(trevr_tree* t) {
+  t->dev.depth = (int32_t)t->levels.size();
+  hipError_t e = hipMemcpyAsync(t->buf.dev, &t->dev, sizeof(DevTree), hipMemcpyHostToDevice,
+                                t->stream);
+  if (e == hipSuccess && !t->levels.empty())
+    e = hipMemcpyAsync(t->buf.levels, t->levels.data(), t->levels.size() * sizeof(uint2),
+                       hipMemcpyHostToDevice, t->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
+  return hip_check(e, "tree table upload");
 }
 
 // Fold recorded event pairs into the totals (the stream is synchronised).
@@ -166,7 +177,7 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->prof_on = false;
   T->ev_used = 0;
   T->host_u32 = nullptr;
-  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, 0, false, 0, false};
+  T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, 0, 0, false, 0, false};
   T->stack_large = false;
   T->cut_default = kCutCap;
   for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }
@@ -195,17 +206,24 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   D.nk = b.nk; D.nlink = b.nlink; D.next = b.next; D.cen = b.cen; D.Lb = b.Lb;
   D.alpha = b.alpha32; D.ray_n = b.ray_n; D.ray_class = b.ray_class;
   D.err = b.err; D.counters = b.counters;
+  D.b_pre = b.b_pre; D.b_lown = b.b_lown; D.b_split = b.b_split;
+  D.alpha64 = b.alpha64; D.geom = b.geom; D.levels = b.levels;
+  D.boff = 0; D.eoff = 0; D.joff = 0; D.noff = 0; D.lboff = 0; D.aoff = 0;
   {
     std::lock_guard<std::mutex> g(g_reg_mu);
     g_live.insert(T);
   }
-  rc = hip_check(hipHostMalloc((void**)&T->host_u32, 8 * sizeof(uint32_t)), "hipHostMalloc");
+  rc = hip_check(hipHostMalloc((void**)&T->host_u32, kHostWords * sizeof(uint32_t)), "hipHostMalloc");
   if (rc == TREVR_OK) rc = build_tree_impl(T, x, y, z, m, rho, kappa, lum);
   if (rc != TREVR_OK) {
     trevr_tree_destroy(T);
     return rc;
   }
   D.num_nodes = T->num_nodes;
+  if ((rc = upload_dev(T)) != TREVR_OK) {
+    trevr_tree_destroy(T);
+    return rc;
+  }
   *out = T;
   return TREVR_OK;
 }
@@ -241,7 +259,10 @@ trevr_status trevr_tree_tune(trevr_tree* t, int key, int64_t value) {
         return set_error(TREVR_E_INVALID, "stack limit must be in [64, 1024]");
       t->dev.stack_limit = (int32_t)value;
       t->stack_large = false;
-      return TREVR_OK;
+      return hip_check(hipDeviceSynchronize() == hipSuccess
+                           ? hipMemcpy(t->buf.dev, &t->dev, sizeof(DevTree), hipMemcpyHostToDevice)
+                           : hipErrorUnknown,
+                       "tree table upload");
     case TREVR_TUNE_CUT:
       if (value < 64 || value > (int64_t)kCutCap)
         return set_error(TREVR_E_INVALID, "cut-list length must be in [64, 2048]");

@@ -42,18 +42,24 @@
 namespace trevr {
 
 // ------------------------------------------------------ active buckets
-__global__ void k_active_buckets(DevTree T, const uint8_t* active, uint32_t* blist,
-                                 uint32_t* bnact, uint32_t* nb) {
+// One row of the grid per scene (blockIdx.y); buckets of all scenes are
+// appended to one list, with their scene.
+__global__ void k_active_buckets(const DevTree* __restrict__ TT, const uint8_t* active,
+                                 uint32_t* blist, uint32_t* bscene, uint32_t* bnact,
+                                 uint32_t* nb) {
+  const DevTree& T = TT[blockIdx.y];
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= T.num_nodes) return;
   const uint4 nk = T.nk[p];
   if (!(nk.w & META_LEAF)) return;
+  const uint8_t* act = active ? active + T.eoff : nullptr;
   const uint2 lk = T.nlink[p];
   uint32_t cnt = 0;
-  for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) cnt += (active == nullptr || active[T.perm[s]]) ? 1u : 0u;
+  for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) cnt += (act == nullptr || act[T.perm[s]]) ? 1u : 0u;
   if (cnt == 0) return;
   const uint32_t b = atomicAdd(nb, 1u);
   blist[b] = (uint32_t)p;
+  bscene[b] = blockIdx.y;
   bnact[b] = cnt;
 }
 
@@ -67,10 +73,13 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_active_hash(const uint8_t* active, int64_t n, unsigned long long* out) {
+__global__ void k_active_hash(const DevTree* __restrict__ TT, const uint8_t* active,
+                              unsigned long long* out) {
+  const DevTree& T = TT[blockIdx.y];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   unsigned long long v = 0ull;
-  if (i < n && (active == nullptr || active[i])) v = mix64((unsigned long long)i + 1ull);
+  if (i < T.n && (active == nullptr || active[T.eoff + i]))
+    v = mix64((unsigned long long)(T.eoff + i) + 1ull);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o);
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
@@ -82,13 +91,17 @@ __global__ void k_active_hash(const uint8_t* active, int64_t n, unsigned long lo
 // Also records the radius before the last growth (-1 if it never grew),
 // which tells the adjoint which element set the final radius.
 template <int SC>
-__global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
-                                              const uint32_t* nbp, double* brad, double* bprev,
-                                              uint32_t* ncnt, uint32_t* nlumc, uint32_t* ovf) {
-  const uint32_t b = blockIdx.x;
-  if (b >= *nbp) return;
+__global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, Items I,
+                                              const uint32_t* blist, const uint32_t* bscene,
+                                              double* brad, double* bprev, uint32_t* ncnt,
+                                              uint32_t* nlumc, uint32_t* ovf) {
   __shared__ uint32_t stack[SC];
+  __shared__ uint32_t s_item;
   const int lane = threadIdx.x;
+  for (;;) {
+  const uint32_t b = next_item(I, &s_item);
+  if (b == kNoItem) break;
+  const DevTree& T = TT[bscene[b]];
   const uint32_t leaf = blist[b];
   double c[3];
   leaf_centre(T, leaf, c);
@@ -118,23 +131,29 @@ __global__ void __launch_bounds__(64) k_setup(DevTree T, const uint32_t* blist,
     nlumc[b] = nlum;
     if (overflow) atomicOr(ovf, OVF_SETUP);
   }
+  }
 }
 
 // Same spheres as the last query of k_setup, so the same stack suffices.
 template <int SC>
-__global__ void __launch_bounds__(64) k_near_fill(DevTree T, const uint32_t* blist,
-                                                  const uint32_t* nbp, const double* brad,
-                                                  const uint32_t* noff, const uint32_t* nlumc,
-                                                  uint32_t* nidx) {
-  const uint32_t b = blockIdx.x;
-  if (b >= *nbp || !(T.flags & TREVR_NEAR_FIELD)) return;
+__global__ void __launch_bounds__(64) k_near_fill(const DevTree* __restrict__ TT, Items I,
+                                                  const uint32_t* blist, const uint32_t* bscene,
+                                                  const double* brad, const uint32_t* noff,
+                                                  const uint32_t* nlumc, uint32_t* nidx) {
   __shared__ uint32_t stack[SC];
-  double c[3];
-  leaf_centre(T, blist[b], c);
-  const double r = brad[b];
-  bool overflow = false;
-  wave_near(T, c, r * r, stack, stack_cap<SC>(T), nullptr, nullptr, nidx + noff[b], nlumc[b],
-            &overflow);
+  __shared__ uint32_t s_item;
+  for (;;) {
+    const uint32_t b = next_item(I, &s_item);
+    if (b == kNoItem) break;
+    const DevTree& T = TT[bscene[b]];
+    if (!(T.flags & TREVR_NEAR_FIELD)) continue;
+    double c[3];
+    leaf_centre(T, blist[b], c);
+    const double r = brad[b];
+    bool overflow = false;
+    wave_near(T, c, r * r, stack, stack_cap<SC>(T), nullptr, nullptr, nidx + noff[b], nlumc[b],
+              &overflow);
+  }
 }
 
 // ------------------------------------------------------------- the walk
@@ -142,20 +161,23 @@ __global__ void __launch_bounds__(64) k_near_fill(DevTree T, const uint32_t* bli
 // counts them all (bstat, and the batch maximum in ovf[1]) so the host can
 // walk it again with room for them.
 template <int SC>
-__global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
-                                             const double* brad, uint32_t b0, uint32_t nbuck,
-                                             uint2* cut, uint32_t cap, uint32_t* bstat,
-                                             uint32_t* ovf) {
-  const uint32_t bucket = b0 + blockIdx.x;
-  if (bucket >= nbuck) return;
+__global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Items I,
+                                             const uint32_t* blist, const uint32_t* bscene,
+                                             const double* brad, uint2* cut, uint32_t cap,
+                                             uint32_t* bstat, uint32_t* ovf) {
   __shared__ uint32_t stack[SC];
+  __shared__ uint32_t s_item;
   const int lane = threadIdx.x;
+  for (;;) {
+  const uint32_t bucket = next_item(I, &s_item);
+  if (bucket == kNoItem) break;
+  const DevTree& T = TT[bscene[bucket]];
   const uint32_t leafb = blist[bucket];
   const double r = brad[bucket];
   const double r2 = r * r;
   double c[3];
   leaf_centre(T, leafb, c);
-  uint2* out = cut + (size_t)blockIdx.x * cap;
+  uint2* out = cut + (size_t)(bucket - I.lo) * cap;
   uint32_t ncut = 0, nsrc = 0, ncells = 0;
   bool overflow = false;
   int sp = 1, maxsp = 1;
@@ -257,6 +279,7 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
     atomic_max_u64(&T.counters[CNT_MAX_CUT], ncut);
     atomic_max_u64(&T.counters[CNT_MAX_STACK], (unsigned long long)maxsp);
   }
+  }
 }
 
 // For each receiver i and ray k: the optical depth of the p-p elements ahead
@@ -265,16 +288,20 @@ __global__ void __launch_bounds__(64) k_walk(DevTree T, const uint32_t* blist,
 // Sigma -> 0 at b = h): kappa_l Sigma_l(b), Sigma_l(b) = 3 m_l/(pi h_l^2)
 // (1 - b/h_l).  Written to tpp[receiver][ray][band] for the far field.
 template <int NB>
-__global__ void __launch_bounds__(kNT) k_pp_rays(DevTree T, const uint32_t* blist,
+__global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT, Items I,
+                                                const uint32_t* blist, const uint32_t* bscene,
                                                 const uint32_t* noff, const uint32_t* nidx,
-                                                const uint32_t* roff, uint32_t b0, uint32_t nbuck,
-                                                const uint8_t* active, float* tpp) {
-  const uint32_t bucket = b0 + blockIdx.x;
-  if (bucket >= nbuck) return;
+                                                const uint32_t* toff, const uint8_t* active,
+                                                float* tpp) {
   const int t = threadIdx.x;
   __shared__ NearTile<NB> S;
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nrecv_s;
+  __shared__ uint32_t nrecv_s, s_item;
+  for (;;) {
+  const uint32_t bucket = next_item(I, &s_item);
+  if (bucket == kNoItem) break;
+  const DevTree& T = TT[bscene[bucket]];
+  const uint8_t* act = active ? active + T.eoff : nullptr;
   const uint32_t leafb = blist[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
@@ -282,10 +309,11 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(DevTree T, const uint32_t* blis
   const uint32_t* near = nidx + n0;
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
-  uint32_t rbase = roff[bucket];
+  float* tppb = tpp + toff[bucket];
+  uint32_t ract = 0;
   uint32_t member = lk.x;
   for (;;) {
-    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
     const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
     const int gpr = (nray + 1) / 2;                 // two rays per thread
@@ -354,12 +382,13 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(DevTree T, const uint32_t* blis
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         if (!kok[q]) continue;
-        float* o = tpp + ((int64_t)(rbase + i) * nray + kb + q) * NB;
+        float* o = tppb + ((int64_t)(ract + i) * nray + kb + q) * NB;
 #pragma unroll
         for (int b = 0; b < NB; ++b) o[b] = tau[q][b];
       }
     }
-    rbase += (uint32_t)nrecv;
+    ract += (uint32_t)nrecv;
+  }
   }
 }
 
@@ -372,18 +401,23 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(DevTree T, const uint32_t* blis
 // bucket from poff[bucket], receiver-chunk-major, then (source, receiver)),
 // for the adjoint.  J == nullptr: only ptau is written.
 template <int NB>
-__global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist,
+__global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, Items I,
+                                               const uint32_t* blist, const uint32_t* bscene,
                                                const uint32_t* noff, const uint32_t* nlumc,
                                                const uint32_t* nidx, const uint32_t* poff,
-                                               uint32_t b0, uint32_t nbuck, const uint8_t* active,
-                                               double* J, float* ptau) {
-  const uint32_t bucket = b0 + blockIdx.x;
-  if (bucket >= nbuck) return;
+                                               const uint8_t* active, double* Jall,
+                                               float* ptau) {
   const int t = threadIdx.x;
   __shared__ NearTile<NB> S;
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nrecv_s;
+  __shared__ uint32_t nrecv_s, s_item;
   __shared__ double red[kNT][NB];
+  for (;;) {
+  const uint32_t bucket = next_item(I, &s_item);
+  if (bucket == kNoItem) break;
+  const DevTree& T = TT[bscene[bucket]];
+  const uint8_t* act = active ? active + T.eoff : nullptr;
+  double* J = Jall ? Jall + T.joff : nullptr;
   const uint32_t leafb = blist[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
@@ -394,9 +428,9 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
   uint32_t member = lk.x;
   uint32_t nact = 0;
   for (;;) {
-    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
-    float* pt = ptau + ((int64_t)poff[bucket] + (int64_t)nact * nl) * NB;
+    float* pt = ptau + (int64_t)poff[bucket] + (int64_t)nact * nl * NB;
     nact += (uint32_t)nrecv;
     const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
     const int i = t % nrecv;
@@ -502,6 +536,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
     atomicAdd(&T.counters[CNT_NS_TRIPLES], (unsigned long long)nact * nl * nnear);
     atomic_max_u64(&T.counters[CNT_MAX_NEAR], (unsigned long long)nnear);
   }
+  }
 }
 
 // ------------------------------------------------------------- far field
@@ -514,15 +549,15 @@ __global__ void __launch_bounds__(kNT) k_pp_src(DevTree T, const uint32_t* blist
 // thread keeps one FP64 accumulator per band, reduced per receiver in a
 // fixed order at the end.
 template <int NB>
-__global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, const double* brad,
-                                             const uint32_t* roff, uint32_t b0, uint32_t nbuck,
+__global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Items I,
+                                             const uint32_t* blist, const uint32_t* bscene,
+                                             const double* brad, const uint32_t* toff,
                                              const uint2* cut, uint32_t cut_cap,
                                              const uint32_t* bstat, const float* tppg,
-                                             const float* bg, double* J, const uint8_t* active,
-                                             float* kept_tau, float* kept_tex) {
+                                             const float* bgall, double* Jall,
+                                             const uint8_t* active, float* kept_tau,
+                                             float* kept_tex) {
   constexpr int kSrcCap = SrcCap<NB>::value;
-  const uint32_t bucket = b0 + blockIdx.x;
-  if (bucket >= nbuck) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
   __shared__ SrcWindow<kSrcCap, NB> W;
@@ -530,15 +565,23 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
   __shared__ float tpp[kRMax][64][NB];
   __shared__ float tex[64][NB];
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nrecv_s, wcnt[kFT / 64], abs_count;
+  __shared__ uint32_t nrecv_s, wcnt[kFT / 64], abs_count, s_item;
   __shared__ double red[kFT / 64][kRMax][NB];
 
+  for (;;) {
+  const uint32_t bucket = next_item(I, &s_item);
+  if (bucket == kNoItem) break;
+  const DevTree& T = TT[bscene[bucket]];
+  const uint8_t* act = active ? active + T.eoff : nullptr;
+  double* J = Jall + T.joff;
+  const float* bg = bgall ? bgall + T.boff : nullptr;
+  const uint32_t rel = bucket - I.lo;
   const uint32_t leafb = blist[bucket];
   const double r = brad[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
   const uint32_t ncut = min(bstat[4 * bucket + 0], cut_cap);
-  const uint2* mycut = cut + (size_t)blockIdx.x * cut_cap;
+  const uint2* mycut = cut + (size_t)rel * cut_cap;
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
   const int ngroups = (nray + 63) / 64;
@@ -547,10 +590,11 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
 
   if (t == 0) abs_count = 0u;
   uint32_t nact_total = 0;
-  uint32_t rbase = roff[bucket];
+  const float* tppb = tppg + toff[bucket];
+  uint32_t ract = 0;
   uint32_t member = lk.x;
   for (;;) {
-    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
     const bool first_chunk = nact_total == 0;
     nact_total += (uint32_t)nrecv;
@@ -573,7 +617,7 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
         const int i = q / kn, kq = q % kn;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          tpp[i][kq][b] = tppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
+          tpp[i][kq][b] = tppb[((int64_t)(ract + i) * nray + k0 + kq) * NB + b];
       }
 
       for (uint32_t skip = 0;; skip += (uint32_t)kSrcCap) {
@@ -645,12 +689,12 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
         // keep the optical depths for the adjoint when the group fits one
         // window (of this kernel and of the adjoint)
         if (kept_tau && first_chunk && nsg_all <= (uint32_t)KeptCap<NB>::value) {
-          float* dst = kept_tau + ((size_t)blockIdx.x * ngroups + g) * KeptCap<NB>::value * NB;
+          float* dst = kept_tau + ((size_t)rel * ngroups + g) * KeptCap<NB>::value * NB;
           for (uint32_t q = t; q < nsg * NB; q += kFT) dst[q] = (&W.tau[0][0])[q];
           if (use_bg && t < kn) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-              kept_tex[((size_t)blockIdx.x * nray + k0 + t) * NB + b] = tex[t][b];
+              kept_tex[((size_t)rel * nray + k0 + t) * NB + b] = tex[t][b];
           }
         }
 
@@ -708,7 +752,7 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
       }
       J[o] = out;
     }
-    rbase += (uint32_t)nrecv;
+    ract += (uint32_t)nrecv;
   }
 
   __syncthreads();
@@ -723,86 +767,191 @@ __global__ void __launch_bounds__(kFT) k_far(DevTree T, const uint32_t* blist, c
               (unsigned long long)nact_total * ((unsigned long long)nray + nabs_total + nsrc));
     atomicAdd(&T.counters[CNT_SRC_PAIRS], (unsigned long long)nact_total * nsrc);
   }
+  }
 }
 
 // ----------------------------------------------------- bucket ordering
-// Buckets are processed heaviest first (a counting sort by the log2 of an
-// estimate of their p-p work), so the slowest buckets start early instead of
-// forming the tail of a launch.  Each bucket's result is independent of its
-// position.
-__global__ void k_cost_bins(const uint32_t* nbp, const uint32_t* bnact, const uint32_t* ncnt,
-                            const uint32_t* nlumc, int nray, uint32_t* bbin, uint32_t* bins) {
+// Buckets are grouped by their scene's band count (one launch per count)
+// and, within a group, processed heaviest first (a counting sort by the log2
+// of an estimate of their p-p work), so the slowest buckets start early
+// instead of forming the tail of a launch.  Each bucket's result is
+// independent of its position.
+__global__ void k_cost_bins(const DevTree* __restrict__ TT, const uint32_t* nbp,
+                            const uint32_t* bscene, const uint32_t* bnact, const uint32_t* ncnt,
+                            const uint32_t* nlumc, uint32_t* bbin, uint32_t* bins) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= *nbp) return;
+  const DevTree& T = TT[bscene[b]];
   const unsigned long long cost =
-      (unsigned long long)bnact[b] * ((unsigned long long)ncnt[b] * (nray / 2 + nlumc[b]) + 2000ull);
+      (unsigned long long)bnact[b] * ((unsigned long long)ncnt[b] * (T.nray / 2 + nlumc[b]) + 2000ull);
   const int lg = 63 - __clzll((long long)cost);
-  const uint32_t bin = (uint32_t)max(0, (kCostBins - 1) - min(lg, kCostBins - 1));
+  const uint32_t bin = (uint32_t)(T.B - 1) * kCostBins +
+                       (uint32_t)max(0, (kCostBins - 1) - min(lg, kCostBins - 1));
   bbin[b] = bin;
   atomicAdd(&bins[bin], 1u);
 }
 
-__global__ void k_bins_scan(uint32_t* bins) {
+// Exclusive scan of the bins; rng[2 + 2c], rng[3 + 2c] get the range of the
+// buckets with c + 1 bands.
+__global__ void k_bins_scan(uint32_t* bins, uint32_t* rng) {
   if (threadIdx.x != 0) return;
   uint32_t run = 0;
-  for (int i = 0; i < kCostBins; ++i) {
-    const uint32_t v = bins[i];
-    bins[i] = run;
-    run += v;
+  for (int cl = 0; cl < kMaxBands; ++cl) {
+    rng[2 + 2 * cl] = run;
+    for (int i = 0; i < kCostBins; ++i) {
+      const uint32_t v = bins[cl * kCostBins + i];
+      bins[cl * kCostBins + i] = run;
+      run += v;
+    }
+    rng[3 + 2 * cl] = run;
   }
 }
 
-__global__ void k_reorder(const uint32_t* nbp, const uint32_t* bbin, uint32_t* bins,
-                          const uint32_t* blist, const uint32_t* bnact, const uint32_t* ncnt,
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o);
+  return v;
+}
+
+// Per-bucket sizes of the dynamic scratch, in the processing order: p-p list
+// entries (ncnt), p-p column floats (tcnt = receivers x rays x bands), raw-J
+// words of the adjoint (jcnt = receivers x bands) and (receiver, luminous p-p
+// element) pair floats (pcnt = receivers x luminous x bands); their 64-bit
+// totals go to tot[0..3], the receivers to tot[4].
+__global__ void k_reorder(const DevTree* __restrict__ TT, const uint32_t* nbp,
+                          const uint32_t* bbin, uint32_t* bins, const uint32_t* blist,
+                          const uint32_t* bscene, const uint32_t* bnact, const uint32_t* ncnt,
                           const uint32_t* nlumc, const double* brad, const double* bprev,
-                          uint32_t* blist2, uint32_t* bnact2, uint32_t* ncnt2, uint32_t* nlumc2,
-                          double* brad2, double* bprev2, uint32_t* pcnt2) {
+                          uint32_t* blist2, uint32_t* bscene2, uint32_t* bnact2, uint32_t* ncnt2,
+                          uint32_t* nlumc2, double* brad2, double* bprev2, uint32_t* tcnt2,
+                          uint32_t* jcnt2, uint32_t* pcnt2, unsigned long long* tot) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= *nbp) return;
-  const uint32_t pos = atomicAdd(&bins[bbin[b]], 1u);
-  blist2[pos] = blist[b];
-  bnact2[pos] = bnact[b];
-  pcnt2[pos] = bnact[b] * nlumc[b];   // (receiver, luminous p-p element) pairs
-  ncnt2[pos] = ncnt[b];
-  nlumc2[pos] = nlumc[b];
-  brad2[pos] = brad[b];
-  bprev2[pos] = bprev[b];
+  unsigned long long v[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
+  if (b < *nbp) {
+    const uint32_t pos = atomicAdd(&bins[bbin[b]], 1u);
+    const uint32_t sc = bscene[b];
+    const DevTree& T = TT[sc];
+    const uint32_t na = bnact[b], B = (uint32_t)T.B;
+    blist2[pos] = blist[b];
+    bscene2[pos] = sc;
+    bnact2[pos] = na;
+    ncnt2[pos] = ncnt[b];
+    nlumc2[pos] = nlumc[b];
+    brad2[pos] = brad[b];
+    bprev2[pos] = bprev[b];
+    tcnt2[pos] = na * (uint32_t)T.nray * B;
+    jcnt2[pos] = na * B;
+    pcnt2[pos] = na * nlumc[b] * B;
+    v[0] = ncnt[b];
+    v[1] = (unsigned long long)na * T.nray * B;
+    v[2] = (unsigned long long)na * nlumc[b] * B;
+    v[3] = (unsigned long long)na * B;
+    v[4] = na;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const unsigned long long s = wave_sum_u64(v[k]);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&tot[k], s);
+  }
 }
 
 // ============================================================ host side
-static Scratch carve(void* base, int64_t nleaves) {
+__global__ void k_zero_words(uint32_t* a, int64_t count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) a[i] = 0u;
+}
+
+static unsigned grid_of(int64_t work, int threads) {
+  return (unsigned)std::max<int64_t>(1, (work + threads - 1) / threads);
+}
+
+#define TREVR_LAUNCH_CHECK(what)                                               \
+  do {                                                                         \
+    if ((rc = hip_check(hipGetLastError(), what)) != TREVR_OK) return rc;      \
+  } while (0)
+
+trevr_status zero_words(hipStream_t st, void* p, size_t words) {
+  trevr_status rc = TREVR_OK;
+  if (words == 0) return rc;
+  k_zero_words<<<grid_of((int64_t)words, 256), 256, 0, st>>>((uint32_t*)p, (int64_t)words);
+  TREVR_LAUNCH_CHECK("k_zero_words");
+  return rc;
+}
+
+size_t default_cut_entries(int64_t leaves) {
+  return (size_t)std::min<int64_t>(std::max<int64_t>(leaves, 1), kBatch) * kCutCap;
+}
+
+Scratch carve_scratch(void* base, int64_t leaves, size_t cut_entries) {
   Carve cv(base);
   Scratch s{};
-  const int64_t L = std::max<int64_t>(nleaves, 1);
-  s.nb = cv.take<uint32_t>(4);           // buckets, p-p total, active total
-  s.ovf = cv.take<uint32_t>(4);          // overflow bits, largest cut of a batch
-  // buckets in processing order (heaviest first); bnact and ncnt are
-  // scanned in place into receiver and p-p list offsets
-  s.blist = cv.take<uint32_t>(L);
-  s.bnact = cv.take<uint32_t>(L + 1);
+  const int64_t L = std::max<int64_t>(leaves, 1);
+  s.rng = cv.take<uint32_t>(2 + 2 * kMaxBands);
+  s.q = cv.take<uint32_t>(2 * Q_N);
+  s.tot = cv.take<unsigned long long>(TOT_N);
+  s.ovf = cv.take<uint32_t>(4);
+  s.ahash = cv.take<unsigned long long>(2);
+  s.bins = cv.take<uint32_t>(kMaxBands * kCostBins);
   s.ncnt = cv.take<uint32_t>(L + 1);
+  s.tcnt = cv.take<uint32_t>(L + 1);
+  s.jcnt = cv.take<uint32_t>(L + 1);
   s.pcnt = cv.take<uint32_t>(L + 1);
+  s.zero_words = (cv.off - (size_t)((char*)s.rng - (char*)base)) / 4;
+  s.blist = cv.take<uint32_t>(L);
+  s.bscene = cv.take<uint32_t>(L);
+  s.bnact = cv.take<uint32_t>(L);
   s.nlumc = cv.take<uint32_t>(L);
   s.bstat = cv.take<uint32_t>(4 * L);
   s.brad = cv.take<double>(L);
   s.bprev = cv.take<double>(L);
-  s.ahash = cv.take<unsigned long long>(2);
-  // the same in discovery order, before the reordering
   s.blist_raw = cv.take<uint32_t>(L);
+  s.bscene_raw = cv.take<uint32_t>(L);
   s.bnact_raw = cv.take<uint32_t>(L);
   s.ncnt_raw = cv.take<uint32_t>(L);
   s.nlumc_raw = cv.take<uint32_t>(L);
+  s.bbin = cv.take<uint32_t>(L);
   s.brad_raw = cv.take<double>(L);
   s.bprev_raw = cv.take<double>(L);
-  s.bbin = cv.take<uint32_t>(L);
-  s.bins = cv.take<uint32_t>(kCostBins);
-  s.cut_entries = (size_t)std::min<int64_t>(L, kBatch) * kCutCap;
-  s.cut = cv.take<uint2>(s.cut_entries);
+  s.cut_entries = cut_entries;
+  s.cut = cv.take<uint2>(cut_entries);
   s.fixed = ((cv.off + 255) & ~(size_t)255) + 256;   // 256-aligned
   return s;
 }
 
-Scratch carve_scratch(void* base, int64_t nleaves) { return carve(base, nleaves); }
+Launch tree_launch(const trevr_tree* T) {
+  return Launch{T->stream, T->buf.dev, 1, T->num_nodes, T->n, T->num_leaves, T->stack_large};
+}
+
+unsigned persistent_grid(const void* fn, int threads, uint64_t items) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> occ;
+  static std::unordered_map<int, int> cus;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int per_cu = 0, ncu = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = occ.find(fn);
+    if (it == occ.end()) {
+      int b = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, threads, 0) != hipSuccess || b < 1)
+        b = 1;
+      it = occ.emplace(fn, b).first;
+    }
+    per_cu = it->second;
+    auto jt = cus.find(dev);
+    if (jt == cus.end()) {
+      int v = 0;
+      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          v < 1)
+        v = 1;
+      jt = cus.emplace(dev, v).first;
+    }
+    ncu = jt->second;
+  }
+  const uint64_t slots = (uint64_t)per_cu * (uint64_t)ncu;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(items, slots));
+}
 
 // Cell optical depths the forward keeps for the adjoint: per bucket of a
 // batch and ray group, KeptCap sources x bands (and with a background the
@@ -842,88 +991,87 @@ bool scratch_unchanged(const void* scratch, uint64_t epoch) {
   const auto it = g_scratch_epoch.find(scratch);
   return it != g_scratch_epoch.end() && it->second == epoch;
 }
-size_t scratch_fixed_bytes(int64_t n) { return carve(nullptr, n).fixed; }
+size_t scratch_fixed_bytes(int64_t n) {
+  return carve_scratch(nullptr, n, default_cut_entries(n)).fixed;   // leaves <= n
+}
 
-#define TREVR_LAUNCH_CHECK(what)                                               \
-  do {                                                                         \
-    if ((rc = hip_check(hipGetLastError(), what)) != TREVR_OK) return rc;      \
-  } while (0)
-
-trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t counts[4],
-                          uint64_t* hash) {
-  hipStream_t st = T->stream;
-  const int64_t nleaves = T->num_leaves;
-  const DevTree& D = T->dev;
+trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch& S) {
+  hipStream_t st = L.st;
   trevr_status rc;
+  if ((rc = zero_words(st, S.rng, S.zero_words)) != TREVR_OK) return rc;
+  const dim3 gn(grid_of(L.max_nodes, 256), (unsigned)L.S);
+  k_active_buckets<<<gn, 256, 0, st>>>(L.TT, active, S.blist_raw, S.bscene_raw, S.bnact_raw,
+                                       S.rng + 1);
+  TREVR_LAUNCH_CHECK("k_active_buckets");
+  const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_SETUP};
+  if (L.stack_large) {
+    const void* fn = (const void*)&k_setup<kStackLarge>;
+    k_setup<kStackLarge><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.ncnt_raw, S.nlumc_raw,
+        S.ovf);
+  } else {
+    const void* fn = (const void*)&k_setup<kStackSmall>;
+    k_setup<kStackSmall><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.ncnt_raw, S.nlumc_raw,
+        S.ovf);
+  }
+  TREVR_LAUNCH_CHECK("k_setup");
+  const unsigned gl = grid_of(L.leaves, 256);
+  k_cost_bins<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, S.bscene_raw, S.bnact_raw, S.ncnt_raw,
+                                  S.nlumc_raw, S.bbin, S.bins);
+  TREVR_LAUNCH_CHECK("k_cost_bins");
+  k_bins_scan<<<1, 64, 0, st>>>(S.bins, S.rng);
+  TREVR_LAUNCH_CHECK("k_bins_scan");
+  k_reorder<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, S.bbin, S.bins, S.blist_raw, S.bscene_raw,
+                                S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw, S.bprev_raw,
+                                S.blist, S.bscene, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev,
+                                S.tcnt, S.jcnt, S.pcnt, S.tot);
+  TREVR_LAUNCH_CHECK("k_reorder");
+  const int64_t Lp = std::max<int64_t>(L.leaves, 1) + 1;
+  for (uint32_t* a : {S.ncnt, S.tcnt, S.jcnt, S.pcnt}) {
+    k_scan_u32<<<1, 1024, 0, st>>>(a, Lp, nullptr);
+    TREVR_LAUNCH_CHECK("k_scan_u32");
+  }
+  const dim3 ge(grid_of(L.max_n, 256), (unsigned)L.S);
+  k_active_hash<<<ge, 256, 0, st>>>(L.TT, active, S.ahash);
+  TREVR_LAUNCH_CHECK("k_active_hash");
+  return TREVR_OK;
+}
+
+trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t* nb,
+                          uint64_t tot[TOT_N], uint64_t* hash) {
+  hipStream_t st = T->stream;
+  trevr_status rc;
+  uint32_t* hbuf = T->host_u32;
   for (;;) {
-    if ((rc = hip_check(hipMemsetAsync(S.nb, 0, sizeof(uint32_t) * 4, st), "memset")) != TREVR_OK)
-      return rc;
-    if ((rc = hip_check(hipMemsetAsync(S.ovf, 0, sizeof(uint32_t) * 4, st), "memset")) != TREVR_OK)
-      return rc;
-    k_active_buckets<<<(unsigned)((T->num_nodes + 255) / 256), 256, 0, st>>>(
-        D, active, S.blist_raw, S.bnact_raw, S.nb);
-    TREVR_LAUNCH_CHECK("k_active_buckets");
-    if (T->stack_large)
-      k_setup<kStackLarge><<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist_raw, S.nb, S.brad_raw,
-                                                             S.bprev_raw, S.ncnt_raw,
-                                                             S.nlumc_raw, S.ovf);
-    else
-      k_setup<kStackSmall><<<(unsigned)nleaves, 64, 0, st>>>(D, S.blist_raw, S.nb, S.brad_raw,
-                                                             S.bprev_raw, S.ncnt_raw,
-                                                             S.nlumc_raw, S.ovf);
-    TREVR_LAUNCH_CHECK("k_setup");
-    // heaviest buckets first, into the primary arrays (zero past the last
-    // bucket for the scans)
-    if ((rc = hip_check(hipMemsetAsync(S.bins, 0, sizeof(uint32_t) * kCostBins, st), "memset")) !=
-        TREVR_OK)
-      return rc;
-    if ((rc = hip_check(hipMemsetAsync(S.ncnt, 0, sizeof(uint32_t) * (nleaves + 1), st),
-                        "memset")) != TREVR_OK)
-      return rc;
-    if ((rc = hip_check(hipMemsetAsync(S.bnact, 0, sizeof(uint32_t) * (nleaves + 1), st),
-                        "memset")) != TREVR_OK)
-      return rc;
-    if ((rc = hip_check(hipMemsetAsync(S.pcnt, 0, sizeof(uint32_t) * (nleaves + 1), st),
-                        "memset")) != TREVR_OK)
-      return rc;
-    k_cost_bins<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(S.nb, S.bnact_raw, S.ncnt_raw,
-                                                                   S.nlumc_raw, T->nray, S.bbin,
-                                                                   S.bins);
-    TREVR_LAUNCH_CHECK("k_cost_bins");
-    k_bins_scan<<<1, 64, 0, st>>>(S.bins);
-    TREVR_LAUNCH_CHECK("k_bins_scan");
-    k_reorder<<<(unsigned)((nleaves + 255) / 256), 256, 0, st>>>(
-        S.nb, S.bbin, S.bins, S.blist_raw, S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw,
-        S.bprev_raw, S.blist, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev, S.pcnt);
-    TREVR_LAUNCH_CHECK("k_reorder");
-    k_scan_u32<<<1, 1024, 0, st>>>(S.ncnt, nleaves + 1, S.nb + 1);
-    TREVR_LAUNCH_CHECK("k_scan_u32");
-    k_scan_u32<<<1, 1024, 0, st>>>(S.bnact, nleaves + 1, S.nb + 2);
-    TREVR_LAUNCH_CHECK("k_scan_u32");
-    k_scan_u32<<<1, 1024, 0, st>>>(S.pcnt, nleaves + 1, S.nb + 3);
-    TREVR_LAUNCH_CHECK("k_scan_u32");
-    if ((rc = hip_check(hipMemsetAsync(S.ahash, 0, sizeof(unsigned long long), st), "memset")) !=
-        TREVR_OK)
-      return rc;
-    k_active_hash<<<(unsigned)((T->n + 255) / 256), 256, 0, st>>>(active, T->n, S.ahash);
-    TREVR_LAUNCH_CHECK("k_active_hash");
-    uint32_t* hbuf = T->host_u32;
-    hipError_t e = hipMemcpyAsync(hbuf, S.nb, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    const Launch L = tree_launch(T);
+    if ((rc = setup_kernels(L, active, S)) != TREVR_OK) return rc;
+    hipError_t e = hipMemcpyAsync(hbuf, S.tot, TOT_N * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(hbuf + 4, S.ahash, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+      e = hipMemcpyAsync(hbuf + 2 * TOT_N, S.ahash, sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(hbuf + 6, S.ovf, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+      e = hipMemcpyAsync(hbuf + 2 * TOT_N + 2, S.rng + 1, sizeof(uint32_t),
+                         hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hbuf + 2 * TOT_N + 3, S.ovf, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                         st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if ((rc = hip_check(e, "bucket readback")) != TREVR_OK) return rc;
-    if (!(hbuf[6] & OVF_SETUP)) break;
+    if (!(hbuf[2 * TOT_N + 3] & OVF_SETUP)) break;
     // a p-p range query ran out of the small traversal stack: use the
     // large one for this tree from now on
     if (T->stack_large)
       return set_error(TREVR_E_CAPACITY, "a p-p range query exceeds the traversal stack");
     T->stack_large = true;
   }
-  for (int i = 0; i < 4; ++i) counts[i] = T->host_u32[i];
-  std::memcpy(hash, T->host_u32 + 4, sizeof(uint64_t));
+  std::memcpy(tot, hbuf, TOT_N * sizeof(uint64_t));
+  std::memcpy(hash, hbuf + 2 * TOT_N, sizeof(uint64_t));
+  *nb = hbuf[2 * TOT_N + 2];
+  for (int k = 0; k < TOT_RECV; ++k)
+    if (tot[k] > 0xFFFFFFFFull)
+      return set_error(TREVR_E_CAPACITY, "per-call p-p sizes exceed 32-bit offsets");
   return TREVR_OK;
 }
 
@@ -931,58 +1079,62 @@ trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long lon
                          uint64_t* hash) {
   hipStream_t st = T->stream;
   trevr_status rc;
-  if ((rc = hip_check(hipMemsetAsync(dev_slot, 0, sizeof(unsigned long long), st), "memset")) !=
-      TREVR_OK)
-    return rc;
-  k_active_hash<<<(unsigned)((T->n + 255) / 256), 256, 0, st>>>(active, T->n, dev_slot);
+  if ((rc = zero_words(st, dev_slot, 2)) != TREVR_OK) return rc;
+  const dim3 ge(grid_of(T->n, 256), 1u);
+  k_active_hash<<<ge, 256, 0, st>>>(T->buf.dev, active, dev_slot);
   TREVR_LAUNCH_CHECK("k_active_hash");
   uint32_t* hbuf = T->host_u32;
-  hipError_t e = hipMemcpyAsync(hbuf + 4, dev_slot, sizeof(unsigned long long),
+  hipError_t e = hipMemcpyAsync(hbuf + 2 * TOT_N, dev_slot, sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if ((rc = hip_check(e, "hash readback")) != TREVR_OK) return rc;
-  std::memcpy(hash, hbuf + 4, sizeof(uint64_t));
+  std::memcpy(hash, hbuf + 2 * TOT_N, sizeof(uint64_t));
   return TREVR_OK;
 }
 
-trevr_status near_fill(trevr_tree* T, const Scratch& S, uint32_t nb) {
+trevr_status near_fill(const Launch& L, const Scratch& S) {
   trevr_status rc = TREVR_OK;
-  if (nb > 0) {
-    if (T->stack_large)
-      k_near_fill<kStackLarge><<<nb, 64, 0, T->stream>>>(T->dev, S.blist, S.nb, S.brad, S.ncnt,
-                                                         S.nlumc, S.nidx);
-    else
-      k_near_fill<kStackSmall><<<nb, 64, 0, T->stream>>>(T->dev, S.blist, S.nb, S.brad, S.ncnt,
-                                                         S.nlumc, S.nidx);
-    TREVR_LAUNCH_CHECK("k_near_fill");
+  const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_FILL};
+  if (L.stack_large) {
+    const void* fn = (const void*)&k_near_fill<kStackLarge>;
+    k_near_fill<kStackLarge><<<persistent_grid(fn, 64, L.leaves), 64, 0, L.st>>>(
+        L.TT, I, S.blist, S.bscene, S.brad, S.ncnt, S.nlumc, S.nidx);
+  } else {
+    const void* fn = (const void*)&k_near_fill<kStackSmall>;
+    k_near_fill<kStackSmall><<<persistent_grid(fn, 64, L.leaves), 64, 0, L.st>>>(
+        L.TT, I, S.blist, S.bscene, S.brad, S.ncnt, S.nlumc, S.nidx);
   }
+  TREVR_LAUNCH_CHECK("k_near_fill");
   return rc;
 }
 
-static trevr_status walk_launch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                                uint32_t cnt, uint32_t cap) {
+trevr_status walk_launch(const Launch& L, const Scratch& S, const Items& I, uint64_t count,
+                         uint32_t cap) {
   trevr_status rc;
-  if ((rc = hip_check(hipMemsetAsync(S.ovf, 0, sizeof(uint32_t) * 2, T->stream), "memset")) !=
-      TREVR_OK)
-    return rc;
-  if (T->stack_large)
-    k_walk<kStackLarge><<<cnt, 64, 0, T->stream>>>(T->dev, S.blist, S.brad, b0, nb, S.cut, cap,
-                                                   S.bstat, S.ovf);
-  else
-    k_walk<kStackSmall><<<cnt, 64, 0, T->stream>>>(T->dev, S.blist, S.brad, b0, nb, S.cut, cap,
-                                                   S.bstat, S.ovf);
+  if ((rc = zero_words(L.st, S.ovf, 2)) != TREVR_OK) return rc;
+  if (L.stack_large) {
+    const void* fn = (const void*)&k_walk<kStackLarge>;
+    k_walk<kStackLarge><<<persistent_grid(fn, 64, count), 64, 0, L.st>>>(
+        L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap, S.bstat, S.ovf);
+  } else {
+    const void* fn = (const void*)&k_walk<kStackSmall>;
+    k_walk<kStackSmall><<<persistent_grid(fn, 64, count), 64, 0, L.st>>>(
+        L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap, S.bstat, S.ovf);
+  }
   TREVR_LAUNCH_CHECK("k_walk");
   return rc;
 }
 
-trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t cnt, uint32_t nb,
+trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t cnt,
                         const std::function<trevr_status(uint32_t, uint32_t, uint32_t)>& run,
                         bool* whole) {
   trevr_status rc;
   uint32_t* hbuf = T->host_u32;
   for (;;) {
     hipEvent_t ev = prof_begin(T);
-    if ((rc = walk_launch(T, S, b0, nb, cnt, T->cut_default)) != TREVR_OK) return rc;
+    if ((rc = walk_launch(tree_launch(T), S, host_items(S, Q_WALK, b0, cnt), cnt,
+                          T->cut_default)) != TREVR_OK)
+      return rc;
     prof_end(T, TREVR_PROF_WALK, ev);
     hipError_t e = hipMemcpyAsync(hbuf, S.ovf, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                   T->stream);
@@ -1007,7 +1159,9 @@ trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t c
   for (uint32_t s0 = b0; s0 < b0 + cnt; s0 += per) {
     const uint32_t scnt = std::min<uint32_t>(per, b0 + cnt - s0);
     hipEvent_t ev = prof_begin(T);
-    if ((rc = walk_launch(T, S, s0, nb, scnt, (uint32_t)cap2)) != TREVR_OK) return rc;
+    if ((rc = walk_launch(tree_launch(T), S, host_items(S, Q_WALK, s0, scnt), scnt,
+                          (uint32_t)cap2)) != TREVR_OK)
+      return rc;
     prof_end(T, TREVR_PROF_WALK, ev);
     if ((rc = run(s0, scnt, (uint32_t)cap2)) != TREVR_OK) return rc;
   }
@@ -1015,76 +1169,72 @@ trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t c
 }
 
 template <int NB>
-static trevr_status pp_rays_nb(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                               uint32_t cnt, const uint8_t* active) {
+static trevr_status pp_rays_nb(const Launch& L, const Scratch& S, const Items& I, uint64_t count,
+                               const uint8_t* active) {
   trevr_status rc;
-  k_pp_rays<NB><<<cnt, kNT, 0, T->stream>>>(T->dev, S.blist, S.ncnt, S.nidx, S.bnact, b0, nb,
-                                            active, S.tpp);
+  const void* fn = (const void*)&k_pp_rays<NB>;
+  k_pp_rays<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
+      L.TT, I, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, active, S.tpp);
   TREVR_LAUNCH_CHECK("k_pp_rays");
   return rc;
 }
 
-trevr_status launch_pp_rays(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                            uint32_t cnt, const uint8_t* active) {
-  switch (T->B) {
-    case 1: return pp_rays_nb<1>(T, S, b0, nb, cnt, active);
-    case 2: return pp_rays_nb<2>(T, S, b0, nb, cnt, active);
-    case 3: return pp_rays_nb<3>(T, S, b0, nb, cnt, active);
-    case 4: return pp_rays_nb<4>(T, S, b0, nb, cnt, active);
-    case 5: return pp_rays_nb<5>(T, S, b0, nb, cnt, active);
-    case 6: return pp_rays_nb<6>(T, S, b0, nb, cnt, active);
-    case 7: return pp_rays_nb<7>(T, S, b0, nb, cnt, active);
-    default: return pp_rays_nb<8>(T, S, b0, nb, cnt, active);
-  }
-}
-
 template <int NB>
-static trevr_status pp_src_nb(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                              uint32_t cnt, const uint8_t* active, double* J) {
+static trevr_status pp_src_nb(const Launch& L, const Scratch& S, const Items& I, uint64_t count,
+                              const uint8_t* active, double* J) {
   trevr_status rc;
-  k_pp_src<NB><<<cnt, kNT, 0, T->stream>>>(T->dev, S.blist, S.ncnt, S.nlumc, S.nidx, S.pcnt, b0,
-                                           nb, active, J, S.ptau);
+  const void* fn = (const void*)&k_pp_src<NB>;
+  k_pp_src<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
+      L.TT, I, S.blist, S.bscene, S.ncnt, S.nlumc, S.nidx, S.pcnt, active, J, S.ptau);
   TREVR_LAUNCH_CHECK("k_pp_src");
   return rc;
 }
 
-trevr_status launch_pp_src(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                           uint32_t cnt, const uint8_t* active, double* J) {
-  switch (T->B) {
-    case 1: return pp_src_nb<1>(T, S, b0, nb, cnt, active, J);
-    case 2: return pp_src_nb<2>(T, S, b0, nb, cnt, active, J);
-    case 3: return pp_src_nb<3>(T, S, b0, nb, cnt, active, J);
-    case 4: return pp_src_nb<4>(T, S, b0, nb, cnt, active, J);
-    case 5: return pp_src_nb<5>(T, S, b0, nb, cnt, active, J);
-    case 6: return pp_src_nb<6>(T, S, b0, nb, cnt, active, J);
-    case 7: return pp_src_nb<7>(T, S, b0, nb, cnt, active, J);
-    default: return pp_src_nb<8>(T, S, b0, nb, cnt, active, J);
-  }
-}
-
 template <int NB>
-static trevr_status launch_pair(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                                uint32_t cnt, uint32_t cap, const float* bg, double* J,
-                                const uint8_t* active) {
-  hipStream_t st = T->stream;
-  const DevTree& D = T->dev;
+static trevr_status far_nb(const Launch& L, const Scratch& S, const Items& I, uint64_t count,
+                           uint32_t cap, const float* bg, double* J, const uint8_t* active) {
   trevr_status rc;
-  hipEvent_t e0 = prof_begin(T);
-  if ((rc = pp_rays_nb<NB>(T, S, b0, nb, cnt, active)) != TREVR_OK) return rc;
-  if ((rc = pp_src_nb<NB>(T, S, b0, nb, cnt, active, J)) != TREVR_OK) return rc;
-  prof_end(T, TREVR_PROF_NEAR, e0);
-  hipEvent_t e1 = prof_begin(T);
-  k_far<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, cap, S.bstat, S.tpp,
-                                bg, J, active, S.kept_tau, S.kept_tex);
+  const void* fn = (const void*)&k_far<NB>;
+  k_far<NB><<<persistent_grid(fn, kFT, count), kFT, 0, L.st>>>(
+      L.TT, I, S.blist, S.bscene, S.brad, S.tcnt, S.cut, cap, S.bstat, S.tpp, bg, J, active,
+      S.kept_tau, S.kept_tex);
   TREVR_LAUNCH_CHECK("k_far");
-  prof_end(T, TREVR_PROF_REDUCE, e1);
   return rc;
 }
+
+#define TREVR_BAND_SWITCH(B, call)              \
+  switch (B) {                                  \
+    case 1: { constexpr int NB = 1; return call; } \
+    case 2: { constexpr int NB = 2; return call; } \
+    case 3: { constexpr int NB = 3; return call; } \
+    case 4: { constexpr int NB = 4; return call; } \
+    case 5: { constexpr int NB = 5; return call; } \
+    case 6: { constexpr int NB = 6; return call; } \
+    case 7: { constexpr int NB = 7; return call; } \
+    default: { constexpr int NB = 8; return call; } \
+  }
+
+trevr_status launch_pp_rays(const Launch& L, int B, const Scratch& S, const Items& I,
+                            uint64_t count, const uint8_t* active) {
+  TREVR_BAND_SWITCH(B, pp_rays_nb<NB>(L, S, I, count, active))
+}
+
+trevr_status launch_pp_src(const Launch& L, int B, const Scratch& S, const Items& I,
+                           uint64_t count, const uint8_t* active, double* J) {
+  TREVR_BAND_SWITCH(B, pp_src_nb<NB>(L, S, I, count, active, J))
+}
+
+trevr_status launch_far(const Launch& L, int B, const Scratch& S, const Items& I,
+                        uint64_t count, uint32_t cap, const float* bg, double* J,
+                        const uint8_t* active) {
+  TREVR_BAND_SWITCH(B, far_nb<NB>(L, S, I, count, cap, bg, J, active))
+}
+#undef TREVR_BAND_SWITCH
 
 trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* bg, double* J,
                             void* scratch, size_t scratch_bytes) {
   hipStream_t st = T->stream;
-  Scratch S = carve(scratch, T->num_leaves);
+  Scratch S = carve_scratch(scratch, T->num_leaves, default_cut_entries(T->num_leaves));
   if (scratch_bytes < S.fixed) {
     T->scratch_needed = S.fixed;
     return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
@@ -1092,44 +1242,48 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
   trevr_status rc;
   T->fwd.valid = false;
   const uint64_t epoch = scratch_mark(scratch);
-  if ((rc = hip_check(hipMemsetAsync(T->buf.counters, 0, sizeof(unsigned long long) * CNT_N, st),
-                      "memset counters")) != TREVR_OK) return rc;
+  if ((rc = zero_words(st, T->buf.counters, 2 * CNT_N)) != TREVR_OK) return rc;
   hipEvent_t ev_setup = prof_begin(T);
-  uint32_t counts[4];
+  uint32_t nb = 0;
+  uint64_t tot[TOT_N];
   uint64_t hash = 0;
-  if ((rc = bucket_setup(T, active, S, counts, &hash)) != TREVR_OK) return rc;
-  const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
-  const uint32_t pairs = counts[3];
+  if ((rc = bucket_setup(T, active, S, &nb, tot, &hash)) != TREVR_OK) return rc;
   Carve dyn((char*)scratch + S.fixed);
-  S.nidx = dyn.take<uint32_t>(near_total);
-  S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
-  S.ptau = dyn.take<float>((size_t)pairs * T->B);
+  S.nidx = dyn.take<uint32_t>(tot[TOT_NEAR]);
+  S.tpp = dyn.take<float>(tot[TOT_TPP]);
+  S.ptau = dyn.take<float>(tot[TOT_PTAU]);
   take_kept(T, S, dyn, nb);
   const size_t need = S.fixed + dyn.off + 256;
   T->scratch_needed = need;
   if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the p-p lists");
-  if ((rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
+  if ((rc = near_fill(tree_launch(T), S)) != TREVR_OK) return rc;
   prof_end(T, TREVR_PROF_SETUP, ev_setup);
   bool whole = true;
   for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
     const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
-    rc = walk_batch(T, S, b0, cnt, nb, [&](uint32_t s0, uint32_t scnt, uint32_t cap) {
-      switch (T->B) {
-        case 1: return launch_pair<1>(T, S, s0, nb, scnt, cap, bg, J, active);
-        case 2: return launch_pair<2>(T, S, s0, nb, scnt, cap, bg, J, active);
-        case 3: return launch_pair<3>(T, S, s0, nb, scnt, cap, bg, J, active);
-        case 4: return launch_pair<4>(T, S, s0, nb, scnt, cap, bg, J, active);
-        case 5: return launch_pair<5>(T, S, s0, nb, scnt, cap, bg, J, active);
-        case 6: return launch_pair<6>(T, S, s0, nb, scnt, cap, bg, J, active);
-        case 7: return launch_pair<7>(T, S, s0, nb, scnt, cap, bg, J, active);
-        default: return launch_pair<8>(T, S, s0, nb, scnt, cap, bg, J, active);
-      }
+    rc = walk_batch(T, S, b0, cnt, [&](uint32_t s0, uint32_t scnt, uint32_t cap) {
+      const Launch L = tree_launch(T);
+      trevr_status r;
+      hipEvent_t e0 = prof_begin(T);
+      if ((r = launch_pp_rays(L, T->B, S, host_items(S, Q_PPR, s0, scnt), scnt, active)) !=
+          TREVR_OK)
+        return r;
+      if ((r = launch_pp_src(L, T->B, S, host_items(S, Q_PPS, s0, scnt), scnt, active, J)) !=
+          TREVR_OK)
+        return r;
+      prof_end(T, TREVR_PROF_NEAR, e0);
+      hipEvent_t e1 = prof_begin(T);
+      if ((r = launch_far(L, T->B, S, host_items(S, Q_FAR, s0, scnt), scnt, cap, bg, J,
+                          active)) != TREVR_OK)
+        return r;
+      prof_end(T, TREVR_PROF_REDUCE, e1);
+      return r;
     }, &whole);
     if (rc != TREVR_OK) return rc;
   }
   T->counters_valid = true;
-  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total, pairs,
-                    nb <= kBatch && whole, T->cut_default,
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, tot[TOT_NEAR], tot[TOT_TPP], tot[TOT_PTAU],
+                    tot[TOT_JRAW], nb <= kBatch && whole, T->cut_default,
                     S.kept_tau != nullptr && nb <= kBatch && whole};
   return TREVR_OK;
 }

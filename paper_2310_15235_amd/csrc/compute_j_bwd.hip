@@ -35,33 +35,14 @@
 
 namespace trevr {
 
-// Gradient accumulators (sorted slots / preorder nodes), FP64.
-struct Grad {
-  double* gL;       // [B][n]
-  double* gk;       // [B][n]
-  double* gh;       // [n]   d/dh (converted to rho at the end)
-  double* gr;       // [n]   direct d/drho
-  double* galpha;   // [node][class][B]
-  double* gLb;      // [node][B]
-  double* gcen;     // [node][4]: d/d centre; later (u, v) of the centre adjoint
-  double* grpp;     // [bucket] d/d r_pp
-  // The far field adds to galpha, gLb and gcen from every bucket, and the
-  // cells near the root are shared by most buckets: workgroups add to one
-  // of ka (ks) copies of galpha (of gLb, gcen), chosen by workgroup index,
-  // which spreads the atomics over more addresses; the copies are summed
-  // into the first before the tree pass.
-  uint32_t ka, ks;  // copies (powers of two)
-  int64_t na, ns;   // elements per copy: of galpha; of gLb and of gcen (x 4 / B)
-};
-
 __device__ inline double* galpha_copy(const Grad& G) {
   return G.galpha + (int64_t)(blockIdx.x & (G.ka - 1)) * G.na;
 }
 __device__ inline double* gLb_copy(const Grad& G) {
   return G.gLb + (int64_t)(blockIdx.x & (G.ks - 1)) * G.ns;
 }
-__device__ inline double* gcen_copy(const Grad& G, int B) {
-  return G.gcen + (int64_t)(blockIdx.x & (G.ks - 1)) * (G.ns / B) * 4;
+__device__ inline double* gcen_copy(const Grad& G) {
+  return G.gcen + (int64_t)(blockIdx.x & (G.ks - 1)) * G.nc;
 }
 
 __device__ inline void gadd(double* a, double v) {
@@ -159,22 +140,28 @@ template <int NB> struct PairTile {
 };
 
 template <int NB>
-__global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* blist,
+__global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ TT, Items I,
+                                                   const uint32_t* blist, const uint32_t* bscene,
                                                    const uint32_t* noff, const uint32_t* nlumc,
-                                                   const uint32_t* nidx, const uint32_t* roff,
+                                                   const uint32_t* nidx, const uint32_t* joff,
                                                    const uint32_t* poff, const float* ptau,
-                                                   uint32_t b0, uint32_t nbuck,
-                                                   const uint8_t* active, const double* gJ,
-                                                   Grad G, double* jraw) {
-  const uint32_t bucket = b0 + blockIdx.x;
-  if (bucket >= nbuck) return;
+                                                   const uint8_t* active, const double* gJall,
+                                                   Grad Gall, double* jraw) {
   const int t = threadIdx.x;
   __shared__ PairTile<NB> PT;
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nrecv_s;
+  __shared__ uint32_t nrecv_s, s_item;
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
   __shared__ double red[kNT][NB];
   __shared__ double redh[kNT];
+  for (;;) {
+  const uint32_t bucket = next_item(I, &s_item);
+  if (bucket == kNoItem) break;
+  const DevTree& T = TT[bscene[bucket]];
+  const uint8_t* act = active ? active + T.eoff : nullptr;
+  const double* gJ = gJall + T.joff;
+  const Grad G = Gall.at(T);
+  double* jrawb = jraw + joff[bucket];
   const uint32_t leafb = blist[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
@@ -183,12 +170,12 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
   const uint2 lk = T.nlink[leafb];
   const int64_t n = T.n;
   uint32_t member = lk.x;
-  uint32_t rbase = roff[bucket], nact = 0;
+  uint32_t nact = 0;
   for (;;) {
-    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
     load_receiver_adjoints<NB>(T, gJ, recv, nrecv, gw, rinvh);
-    const float* pt = ptau + ((int64_t)poff[bucket] + (int64_t)nact * nl) * NB;
+    const float* pt = ptau + (int64_t)poff[bucket] + (int64_t)nact * nl * NB;
     const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
     const int i = t % nrecv;
     const RecvInfo& ri = recv[i];
@@ -333,16 +320,16 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
       const int ii = t / NB, b = t % NB;
       double v = 0.0;
       for (int u = ii; u < stride; u += nrecv) v += red[u][b];
-      jraw[(int64_t)(rbase + ii) * NB + b] = v;
+      jrawb[(int64_t)(nact + ii) * NB + b] = v;
     }
     if (t < nrecv) {
       double v = 0.0;
       for (int u = t; u < stride; u += nrecv) v += redh[u];
       gadd(&G.gh[recv[t].slot], v);
     }
-    rbase += (uint32_t)nrecv;
     nact += (uint32_t)nrecv;
     __syncthreads();
+  }
   }
 }
 
@@ -359,20 +346,25 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(DevTree T, const uint32_t* b
 constexpr int kPRChunk = 256;   // p-p elements per LDS chunk
 
 template <int NB>
-__global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* blist,
+__global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__ TT, Items I,
+                                                    const uint32_t* blist, const uint32_t* bscene,
                                                     const uint32_t* noff, const uint32_t* nidx,
-                                                    const uint32_t* roff, uint32_t b0,
-                                                    uint32_t nbuck, const uint8_t* active,
-                                                    const float* gtpp, Grad G) {
-  const uint32_t bucket = b0 + blockIdx.x;
-  if (bucket >= nbuck) return;
+                                                    const uint32_t* toff, const uint8_t* active,
+                                                    const float* gtppg, Grad Gall) {
   const int t = threadIdx.x;
   __shared__ RecvInfo recv[kRMax];
-  __shared__ uint32_t nrecv_s;
+  __shared__ uint32_t nrecv_s, s_item;
   __shared__ RayGroup RG;
   __shared__ float g[kRMax][64][NB];
   __shared__ float ek[kPRChunk][NB], eh[kPRChunk];
   __shared__ int gz;
+  for (;;) {
+  const uint32_t bucket = next_item(I, &s_item);
+  if (bucket == kNoItem) break;
+  const DevTree& T = TT[bscene[bucket]];
+  const uint8_t* act = active ? active + T.eoff : nullptr;
+  const Grad G = Gall.at(T);
+  const float* gtpp = gtppg + toff[bucket];
   const uint32_t leafb = blist[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
@@ -381,10 +373,10 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
   const int64_t n = T.n;
-  uint32_t rbase = roff[bucket];
+  uint32_t ract = 0;
   uint32_t member = lk.x;
   for (;;) {
-    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
     for (int k0 = 0; k0 < nray; k0 += 64) {
       const int kn = min(64, nray - k0);
@@ -396,7 +388,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
         const int i = q / kn, kq = q % kn;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const float v = gtpp[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
+          const float v = gtpp[((int64_t)(ract + i) * nray + k0 + kq) * NB + b];
           g[i][kq][b] = v;
           nz |= v != 0.0f;
         }
@@ -467,7 +459,8 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(DevTree T, const uint32_t* 
         __syncthreads();
       }
     }
-    rbase += (uint32_t)nrecv;
+    ract += (uint32_t)nrecv;
+  }
   }
 }
 
@@ -498,18 +491,14 @@ template <int NB> struct BwdCfg {
 // sums over the ray's sources sorted by distance), of the source distance s
 // for sources inside a chord, and of r_pp for chords clipped at the sphere.
 template <int NB>
-__global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, const uint32_t* blist,
-                                                 const double* brad, const uint32_t* roff,
-                                                 uint32_t b0, uint32_t nbuck, const uint2* cut,
-                                                 uint32_t cut_cap, const uint32_t* bstat,
-                                                 const float* tppg,
-                                                 const float* bg, const uint8_t* active,
-                                                 const double* gJ, const double* jraw,
-                                                 float* gtppg, Grad G, const float* kept_tau,
-                                                 const float* kept_tex) {
+__global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
+    k_far_bwd(const DevTree* __restrict__ TT, Items I, const uint32_t* blist,
+              const uint32_t* bscene, const double* brad, const uint32_t* toff,
+              const uint32_t* joff, const uint2* cut, uint32_t cut_cap, const uint32_t* bstat,
+              const float* tppall, const float* bgall, const uint8_t* active,
+              const double* gJall, const double* jrawall, float* gtppall, Grad Gall,
+              const float* kept_tau, const float* kept_tex) {
   constexpr int CAP = BwdCfg<NB>::cap;
-  const uint32_t bucket = b0 + blockIdx.x;
-  if (bucket >= nbuck) return;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 
   __shared__ SrcWindow<CAP, NB, false> W;   // suffix adds kept in sgtau
@@ -520,15 +509,27 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
   __shared__ float tex[64][NB], gtex[64][NB];
   __shared__ RecvInfo recv[kRMax];
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
-  __shared__ uint32_t nrecv_s, wcnt[kFT / 64];
+  __shared__ uint32_t nrecv_s, wcnt[kFT / 64], s_item;
   __shared__ double red[kFT / 64][kRMax][NB], redh[kFT / 64][kRMax], redr[kFT / 64];
 
+  for (;;) {
+  const uint32_t bucket = next_item(I, &s_item);
+  if (bucket == kNoItem) break;
+  const DevTree& T = TT[bscene[bucket]];
+  const uint8_t* act = active ? active + T.eoff : nullptr;
+  const double* gJ = gJall + T.joff;
+  const float* bg = bgall ? bgall + T.boff : nullptr;
+  const Grad G = Gall.at(T);
+  const float* tppg = tppall + toff[bucket];
+  float* gtppg = gtppall + toff[bucket];
+  const double* jraw = jrawall + joff[bucket];
+  const uint32_t rel = bucket - I.lo;
   const uint32_t leafb = blist[bucket];
   const double r = brad[bucket];
   double c[3];
   leaf_centre(T, leafb, c);
   const uint32_t ncut = min(bstat[4 * bucket + 0], cut_cap);
-  const uint2* mycut = cut + (size_t)blockIdx.x * cut_cap;
+  const uint2* mycut = cut + (size_t)rel * cut_cap;
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
   const int ngroups = (nray + 63) / 64;
@@ -539,11 +540,11 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
   double grpp = 0.0;   // this thread's share of d/d r_pp
   double* const galpha_c = galpha_copy(G);
   double* const gLb_c = gLb_copy(G);
-  double* const gcen_c = gcen_copy(G, NB);
-  uint32_t rbase = roff[bucket];
+  double* const gcen_c = gcen_copy(G);
+  uint32_t ract = 0;
   uint32_t member = lk.x;
   for (;;) {
-    const int nrecv = load_receivers(T, active, c, member, lk.x + lk.y, recv, &nrecv_s);
+    const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
     load_receiver_adjoints<NB>(T, gJ, recv, nrecv, gw, rinvh);
     int P2 = 1;
@@ -567,7 +568,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         const int i = q / kn, kq = q % kn;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          tpp[i][kq][b] = tppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b];
+          tpp[i][kq][b] = tppg[((int64_t)(ract + i) * nray + k0 + kq) * NB + b];
           gtpp[i][kq][b] = 0.0f;
         }
       }
@@ -594,12 +595,12 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         // ---- cell optical depths: kept by the forward when the group fits
         // one window; otherwise a first sweep over the hits
         if (kept_tau && skip == 0 && nsg_all <= (uint32_t)KeptCap<NB>::value) {
-          const float* src = kept_tau + ((size_t)blockIdx.x * ngroups + g) * KeptCap<NB>::value * NB;
+          const float* src = kept_tau + ((size_t)rel * ngroups + g) * KeptCap<NB>::value * NB;
           for (uint32_t q = t; q < nsg * NB; q += kFT) (&W.tau[0][0])[q] = src[q];
           if (use_bg && t < kn) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-              tex[t][b] = kept_tex[((size_t)blockIdx.x * nray + k0 + t) * NB + b];
+              tex[t][b] = kept_tex[((size_t)rel * nray + k0 + t) * NB + b];
           }
           __syncthreads();
         } else {
@@ -849,7 +850,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
         const int i = q / kn, kq = q % kn;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          gtppg[((int64_t)(rbase + i) * nray + k0 + kq) * NB + b] = gtpp[i][kq][b];
+          gtppg[((int64_t)(ract + i) * nray + k0 + kq) * NB + b] = gtpp[i][kq][b];
       }
       __syncthreads();
     }
@@ -873,7 +874,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
       for (int w = 0; w < kFT / 64; ++w) v += red[w][i][b];
       if (thick) {
         const uint32_t sl = recv[i].slot;
-        const double Jr = jraw[(int64_t)(rbase + i) * NB + b] + v;
+        const double Jr = jraw[(int64_t)(ract + i) * NB + b] + v;
         const double kap = (double)T.kappa[(int64_t)b * n + sl], rho = (double)T.rho[sl];
         const double h = recv[i].h;
         const double gC = gJ[(int64_t)b * n + T.perm[sl]] * Jr * thick_dC(kap * rho * h);
@@ -888,7 +889,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
       gadd(&G.gh[recv[t].slot], v);
     }
     __syncthreads();
-    rbase += (uint32_t)nrecv;
+    ract += (uint32_t)nrecv;
   }
   // ---- r_pp adjoint of the bucket
   const double v = wave_sum(grpp);
@@ -898,6 +899,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves) k_far_bwd(DevTree T, c
     double s = 0.0;
     for (int w = 0; w < kFT / 64; ++w) s += redr[w];
     G.grpp[bucket] = s;
+  }
   }
 }
 
@@ -968,15 +970,21 @@ __device__ inline uint32_t wave_near_argbeam(const DevTree& T, const double c[3]
 // (The sphere before the last growth is inside the final one, so the stack
 // that sufficed for the p-p radius suffices here.)
 template <int SC>
-__global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist,
-                                                const uint32_t* nbp, const double* brad,
-                                                const double* bprev, Grad G) {
-  const uint32_t b = blockIdx.x;
-  if (b >= *nbp || !(T.flags & TREVR_NEAR_FIELD)) return;
-  const double g = G.grpp[b];
-  if (g == 0.0) return;
+__global__ void __launch_bounds__(64) k_rpp_bwd(const DevTree* __restrict__ TT, Items I,
+                                                const uint32_t* blist, const uint32_t* bscene,
+                                                const double* brad, const double* bprev,
+                                                Grad Gall) {
   __shared__ uint32_t stack[SC];
+  __shared__ uint32_t s_item;
   const int lane = threadIdx.x;
+  for (;;) {
+  const uint32_t b = next_item(I, &s_item);
+  if (b == kNoItem) break;
+  const DevTree& T = TT[bscene[b]];
+  if (!(T.flags & TREVR_NEAR_FIELD)) continue;
+  const double g = Gall.grpp[b];
+  if (g == 0.0) continue;
+  const Grad G = Gall.at(T);
   const double r = brad[b], rprev = bprev[b];
   double c[3];
   leaf_centre(T, blist[b], c);
@@ -1006,13 +1014,16 @@ __global__ void __launch_bounds__(64) k_rpp_bwd(DevTree T, const uint32_t* blist
     fac = 1.0 / T.wbeam;
   }
   if (lane == 0 && src != 0xFFFFFFFFu && !overflow) gadd(&G.gh[src], g * fac);
+  }
 }
 
 // ------------------------------------------------------------ the tree
 // Centre adjoint -> (u, v): the centre c = sum(L_s x_s)/L of a node moves
 // by (x_s - c)/L per unit of any band of L_s, so element s collects
 // u.x_s - v over its ancestors with u = dE/dc / L, v = u.c.
-__global__ void k_cen_prep(DevTree T, Grad G) {
+__global__ void k_cen_prep(const DevTree* __restrict__ TT, Grad Gall) {
+  const DevTree& T = TT[blockIdx.y];
+  const Grad G = Gall.at(T);
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= T.num_nodes) return;
   const double4 cn = T.cen[p];
@@ -1032,28 +1043,33 @@ __global__ void k_cen_prep(DevTree T, Grad G) {
 // the transmission average alpha = combine_s(alpha_c0, alpha_c1) grown
 // through the empty prefix boxes (Section 2.6) passes its adjoint to the
 // children; class 0 also passes the luminosity and centre adjoints.
-__global__ void k_tree_bwd(TreeBufs tb, DevTree T, uint32_t lb, uint32_t le, Grad G) {
+__global__ void k_tree_bwd(const DevTree* __restrict__ TT, int depth, Grad Gall) {
+  const DevTree& T = TT[blockIdx.y];
+  if (depth >= T.depth) return;
+  const Grad G = Gall.at(T);
+  const uint2 lv = T.levels[depth];
+  const uint32_t lb = lv.x, le = lv.y;
   const int B = T.B, nclass = T.nclass;
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gid >= (int64_t)(le - lb) * nclass) return;
   const uint32_t i = lb + (uint32_t)(gid / nclass);
   const int c = (int)(gid % nclass);
-  const int s = tb.b_split[i];
+  const int s = T.b_split[i];
   if (s < 0) return;
-  const uint32_t p = tb.b_pre[i], p0 = p + 1u, p1 = tb.nlink[p].x;
-  const int l = tb.b_lown[i];
-  const double L = tb.hdr[3];
+  const uint32_t p = T.b_pre[i], p0 = p + 1u, p1 = T.nlink[p].x;
+  const int l = T.b_lown[i];
+  const double L = T.hdr[3];
   for (int b = 0; b < B; ++b) {
     const double g = G.galpha[((int64_t)p * nclass + c) * B + b];
     if (g == 0.0) continue;
     double d1, d2;
-    double A = combine64_d(&tb.geom[((int64_t)s * nclass + c) * 3], L,
-                           tb.alpha64[((int64_t)p0 * nclass + c) * B + b],
-                           tb.alpha64[((int64_t)p1 * nclass + c) * B + b], &d1, &d2);
+    double A = combine64_d(&T.geom[((int64_t)s * nclass + c) * 3], L,
+                           T.alpha64[((int64_t)p0 * nclass + c) * B + b],
+                           T.alpha64[((int64_t)p1 * nclass + c) * B + b], &d1, &d2);
     double D = 1.0;
     for (int mm = s - 1; mm >= l; --mm) {
       double e1, e2;
-      A = combine64_d(&tb.geom[((int64_t)mm * nclass + c) * 3], L, A, 0.0, &e1, &e2);
+      A = combine64_d(&T.geom[((int64_t)mm * nclass + c) * 3], L, A, 0.0, &e1, &e2);
       D *= e1;
     }
     G.galpha[((int64_t)p0 * nclass + c) * B + b] += g * D * d1;
@@ -1077,7 +1093,9 @@ __global__ void k_tree_bwd(TreeBufs tb, DevTree T, uint32_t lb, uint32_t le, Gra
 // dkappa_bs += A_b m_s/V and drho_s += sum_b A_b alpha_b m_s/(rho_s^2 V)
 // with A_b the adjoint summed over classes; luminosities collect the
 // accumulated (Lb, centre) adjoints of the path to the root.
-__global__ void k_leaf_bwd(TreeBufs tb, DevTree T, Grad G) {
+__global__ void k_leaf_bwd(const DevTree* __restrict__ TT, Grad Gall) {
+  const DevTree& T = TT[blockIdx.y];
+  const Grad G = Gall.at(T);
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= T.num_nodes) return;
   if (!(T.nk[p].w & META_LEAF)) return;
@@ -1089,7 +1107,7 @@ __global__ void k_leaf_bwd(TreeBufs tb, DevTree T, Grad G) {
     double s = 0.0;
     for (int c = 0; c < nclass; ++c) s += G.galpha[((int64_t)p * nclass + c) * B + b];
     A[b] = s;
-    ab[b] = tb.alpha64[(int64_t)p * nclass * B + b];
+    ab[b] = T.alpha64[(int64_t)p * nclass * B + b];
   }
   double vol = 0.0;
   for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) vol += (double)T.m[s] / (double)T.rho[s];
@@ -1108,7 +1126,13 @@ __global__ void k_leaf_bwd(TreeBufs tb, DevTree T, Grad G) {
 }
 
 // h = (m/rho)^(1/3): dh/drho = -h/(3 rho).  Gradients to input order.
-__global__ void k_grad_out(DevTree T, Grad G, double* gL, double* gk, double* grho) {
+__global__ void k_grad_out(const DevTree* __restrict__ TT, Grad Gall, double* gLall,
+                           double* gkall, double* grhoall) {
+  const DevTree& T = TT[blockIdx.y];
+  const Grad G = Gall.at(T);
+  double* gL = gLall + T.joff;
+  double* gk = gkall + T.joff;
+  double* grho = grhoall + T.eoff;
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= T.n) return;
   const int64_t n = T.n;
@@ -1136,29 +1160,28 @@ __global__ void k_zero_u64(unsigned long long* a, int64_t count) {
 
 // ============================================================ host side
 static unsigned grid_of(int64_t work, int threads) {
-  return (unsigned)((work + threads - 1) / threads);
+  return (unsigned)std::max<int64_t>(1, (work + threads - 1) / threads);
 }
 
-static Grad carve_grad(Carve& cv, const trevr_tree* T) {
+Grad carve_grad(Carve& cv, const GradDims& d) {
   Grad g{};
-  const int64_t n = T->n, nn = T->num_nodes, B = T->B;
-  const int64_t nl = std::max<int64_t>(T->num_leaves, 1);
-  g.gL = cv.take<double>(B * n);
-  g.gk = cv.take<double>(B * n);
-  g.gh = cv.take<double>(n);
-  g.gr = cv.take<double>(n);
+  g.gL = cv.take<double>(d.jn);
+  g.gk = cv.take<double>(d.jn);
+  g.gh = cv.take<double>(d.n);
+  g.gr = cv.take<double>(d.n);
   // copies of the far-field accumulators within a budget of 256 MiB each
   const size_t budget = (size_t)256 << 20;
-  g.na = nn * T->nclass * B;
-  g.ns = nn * B;
+  g.na = d.alpha;
+  g.ns = d.nodesB;
+  g.nc = 4 * d.nodes;
   g.ka = 1;
   while (g.ka < 8 && (size_t)(2 * g.ka) * g.na * sizeof(double) <= budget) g.ka *= 2;
   g.ks = 1;
-  while (g.ks < 16 && (size_t)(2 * g.ks) * nn * (B + 4) * sizeof(double) <= budget) g.ks *= 2;
+  while (g.ks < 16 && (size_t)(2 * g.ks) * (g.ns + g.nc) * sizeof(double) <= budget) g.ks *= 2;
   g.galpha = cv.take<double>((size_t)g.ka * g.na);
-  g.gLb = cv.take<double>((size_t)g.ks * nn * B);
-  g.gcen = cv.take<double>((size_t)g.ks * nn * 4);
-  g.grpp = cv.take<double>(nl);
+  g.gLb = cv.take<double>((size_t)g.ks * g.ns);
+  g.gcen = cv.take<double>((size_t)g.ks * g.nc);
+  g.grpp = cv.take<double>(std::max<int64_t>(d.leaves, 1));
   return g;
 }
 
@@ -1168,42 +1191,108 @@ static Grad carve_grad(Carve& cv, const trevr_tree* T) {
   } while (0)
 
 template <int NB>
-static trevr_status bwd_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t nb,
-                              uint32_t cnt, uint32_t cap, const uint8_t* active, const float* bg,
-                              const double* gJ, const Grad& G, double* jraw, float* gtpp,
-                              const float* kept_tau, const float* kept_tex) {
-  hipStream_t st = T->stream;
-  const DevTree& D = T->dev;
+static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArgs& a,
+                                 const Items& I, uint64_t count, uint32_t cap,
+                                 trevr_tree* prof) {
   trevr_status rc;
-  hipEvent_t e0 = prof_begin(T);
-  k_pp_src_bwd<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nlumc, S.nidx, S.bnact, S.pcnt,
-                                        S.ptau, b0, nb, active, gJ, G, jraw);
-  TREVR_LAUNCH_CHECK("k_pp_src_bwd");
-  prof_end(T, TREVR_PROF_ADJ_NEAR, e0);
-  hipEvent_t e1 = prof_begin(T);
-  k_far_bwd<NB><<<cnt, kFT, 0, st>>>(D, S.blist, S.brad, S.bnact, b0, nb, S.cut, cap, S.bstat,
-                                     S.tpp, bg, active, gJ, jraw, gtpp, G, kept_tau, kept_tex);
-  TREVR_LAUNCH_CHECK("k_far_bwd");
-  prof_end(T, TREVR_PROF_ADJ_REDUCE, e1);
-  hipEvent_t e2 = prof_begin(T);
-  k_pp_rays_bwd<NB><<<cnt, kNT, 0, st>>>(D, S.blist, S.ncnt, S.nidx, S.bnact, b0, nb, active,
-                                         gtpp, G);
-  TREVR_LAUNCH_CHECK("k_pp_rays_bwd");
-  prof_end(T, TREVR_PROF_ADJ_NEAR, e2);
+  hipEvent_t e0 = prof_begin(prof);
+  {
+    const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_PPS_BWD};
+    const void* fn = (const void*)&k_pp_src_bwd<NB>;
+    k_pp_src_bwd<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
+        L.TT, Ii, S.blist, S.bscene, S.ncnt, S.nlumc, S.nidx, S.jcnt, S.pcnt, S.ptau, a.active,
+        a.gJ, a.G, a.jraw);
+    TREVR_LAUNCH_CHECK("k_pp_src_bwd");
+  }
+  prof_end(prof, TREVR_PROF_ADJ_NEAR, e0);
+  hipEvent_t e1 = prof_begin(prof);
+  {
+    const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_FAR_BWD};
+    const void* fn = (const void*)&k_far_bwd<NB>;
+    k_far_bwd<NB><<<persistent_grid(fn, kFT, count), kFT, 0, L.st>>>(
+        L.TT, Ii, S.blist, S.bscene, S.brad, S.tcnt, S.jcnt, S.cut, cap, S.bstat, S.tpp, a.bg,
+        a.active, a.gJ, a.jraw, a.gtpp, a.G, a.kept_tau, a.kept_tex);
+    TREVR_LAUNCH_CHECK("k_far_bwd");
+  }
+  prof_end(prof, TREVR_PROF_ADJ_REDUCE, e1);
+  hipEvent_t e2 = prof_begin(prof);
+  {
+    const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_PPR_BWD};
+    const void* fn = (const void*)&k_pp_rays_bwd<NB>;
+    k_pp_rays_bwd<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
+        L.TT, Ii, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, a.active, a.gtpp, a.G);
+    TREVR_LAUNCH_CHECK("k_pp_rays_bwd");
+  }
+  prof_end(prof, TREVR_PROF_ADJ_NEAR, e2);
   return rc;
 }
 
+trevr_status bwd_items(const Launch& L, int B, const Scratch& S, const BwdArgs& a,
+                       const Items& I, uint64_t count, uint32_t cap, trevr_tree* prof) {
+  switch (B) {
+    case 1: return bwd_items_nb<1>(L, S, a, I, count, cap, prof);
+    case 2: return bwd_items_nb<2>(L, S, a, I, count, cap, prof);
+    case 3: return bwd_items_nb<3>(L, S, a, I, count, cap, prof);
+    case 4: return bwd_items_nb<4>(L, S, a, I, count, cap, prof);
+    case 5: return bwd_items_nb<5>(L, S, a, I, count, cap, prof);
+    case 6: return bwd_items_nb<6>(L, S, a, I, count, cap, prof);
+    case 7: return bwd_items_nb<7>(L, S, a, I, count, cap, prof);
+    default: return bwd_items_nb<8>(L, S, a, I, count, cap, prof);
+  }
+}
+
+trevr_status bwd_tree_pass(const Launch& L, const Scratch& S, const Grad& G,
+                           const std::vector<int64_t>& level_work, double* gL, double* gk,
+                           double* grho) {
+  hipStream_t st = L.st;
+  trevr_status rc;
+  const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_RPP_BWD};
+  if (L.stack_large) {
+    const void* fn = (const void*)&k_rpp_bwd<kStackLarge>;
+    k_rpp_bwd<kStackLarge><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+        L.TT, I, S.blist, S.bscene, S.brad, S.bprev, G);
+  } else {
+    const void* fn = (const void*)&k_rpp_bwd<kStackSmall>;
+    k_rpp_bwd<kStackSmall><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+        L.TT, I, S.blist, S.bscene, S.brad, S.bprev, G);
+  }
+  TREVR_LAUNCH_CHECK("k_rpp_bwd");
+  if (G.ka > 1) {
+    k_sum_copies<<<grid_of(G.na, 256), 256, 0, st>>>(G.galpha, G.na, G.ka);
+    TREVR_LAUNCH_CHECK("k_sum_copies");
+  }
+  if (G.ks > 1) {
+    k_sum_copies<<<grid_of(G.ns, 256), 256, 0, st>>>(G.gLb, G.ns, G.ks);
+    TREVR_LAUNCH_CHECK("k_sum_copies");
+    k_sum_copies<<<grid_of(G.nc, 256), 256, 0, st>>>(G.gcen, G.nc, G.ks);
+    TREVR_LAUNCH_CHECK("k_sum_copies");
+  }
+  const unsigned S_ = (unsigned)L.S;
+  k_cen_prep<<<dim3(grid_of(L.max_nodes, 256), S_), 256, 0, st>>>(L.TT, G);
+  TREVR_LAUNCH_CHECK("k_cen_prep");
+  for (size_t d = 0; d < level_work.size(); ++d) {
+    k_tree_bwd<<<dim3(grid_of(level_work[d], 128), S_), 128, 0, st>>>(L.TT, (int)d, G);
+    TREVR_LAUNCH_CHECK("k_tree_bwd");
+  }
+  k_leaf_bwd<<<dim3(grid_of(L.max_nodes, 128), S_), 128, 0, st>>>(L.TT, G);
+  TREVR_LAUNCH_CHECK("k_leaf_bwd");
+  k_grad_out<<<dim3(grid_of(L.max_n, 256), S_), 256, 0, st>>>(L.TT, G, gL, gk, grho);
+  TREVR_LAUNCH_CHECK("k_grad_out");
+  return TREVR_OK;
+}
+
 // Scratch of the backward: the forward's layout (fixed part, p-p lists,
-// p-p columns), then the p-p column adjoints, the raw J per receiver and the
-// gradient accumulators.  When the scratch still holds the state of a
-// compute_J on this tree for the same active set (same buffer, not written
-// by any call since, equal fingerprint), its bucket setup, p-p lists, p-p
-// columns and (with a single batch) cut lists are used as they are.
+// p-p columns, pair depths, kept depths), then the p-p column adjoints, the
+// raw J per receiver and the gradient accumulators.  When the scratch still
+// holds the state of a compute_J on this tree for the same active set (same
+// buffer, not written by any call since, equal fingerprint), its bucket
+// setup, p-p lists, p-p columns and (with a single batch) cut lists are used
+// as they are.
 trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const float* bg,
                                      const double* gJ, double* gL, double* gkappa, double* grho,
                                      void* scratch, size_t scratch_bytes) {
   hipStream_t st = T->stream;
-  Scratch S = carve_scratch(scratch, T->num_leaves);
+  Scratch S = carve_scratch(scratch, T->num_leaves, default_cut_entries(T->num_leaves));
   if (scratch_bytes < S.fixed) {
     T->scratch_needed = S.fixed;
     return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");
@@ -1211,75 +1300,67 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
   trevr_status rc;
   hipEvent_t ev_setup = prof_begin(T);
   bool reuse = false;
-  uint32_t counts[4];
   if (T->fwd.valid && T->fwd.scratch == scratch && scratch_unchanged(scratch, T->fwd.epoch)) {
     uint64_t h = 0;
     if ((rc = active_hash(T, active, S.ahash + 1, &h)) != TREVR_OK) return rc;
     reuse = h == T->fwd.hash;
   }
   uint64_t hash = T->fwd.hash;
+  uint32_t nb = 0;
+  uint64_t tot[TOT_N] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (reuse) {
-    counts[0] = T->fwd.nb;
-    counts[1] = T->fwd.near_total;
-    counts[2] = T->fwd.act_total;
-    counts[3] = T->fwd.pairs;
+    nb = T->fwd.nb;
+    tot[TOT_NEAR] = T->fwd.near_total;
+    tot[TOT_TPP] = T->fwd.tpp_total;
+    tot[TOT_PTAU] = T->fwd.ptau_total;
+    tot[TOT_JRAW] = T->fwd.jraw_total;
+    // the work-queue counters of the forward are zero after its launches
   } else {
     T->fwd.valid = false;
-    if ((rc = bucket_setup(T, active, S, counts, &hash)) != TREVR_OK) return rc;
+    if ((rc = bucket_setup(T, active, S, &nb, tot, &hash)) != TREVR_OK) return rc;
   }
-  const uint32_t nb = counts[0], near_total = counts[1], act_total = counts[2];
-  const uint32_t pairs = counts[3];
   Carve dyn((char*)scratch + S.fixed);
-  S.nidx = dyn.take<uint32_t>(near_total);
-  S.tpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
-  S.ptau = dyn.take<float>((size_t)pairs * T->B);
+  S.nidx = dyn.take<uint32_t>(tot[TOT_NEAR]);
+  S.tpp = dyn.take<float>(tot[TOT_TPP]);
+  S.ptau = dyn.take<float>(tot[TOT_PTAU]);
   take_kept(T, S, dyn, nb);
   // the forward's far-source optical depths apply to its own (single) batch
   const bool use_kept = reuse && T->fwd.kept && S.kept_tau != nullptr;
-  const float* kept_tau = use_kept ? S.kept_tau : nullptr;
-  const float* kept_tex = use_kept ? S.kept_tex : nullptr;
-  float* gtpp = dyn.take<float>((size_t)act_total * T->nray * T->B);
-  double* jraw = dyn.take<double>((size_t)act_total * T->B);
+  BwdArgs a{};
+  a.active = active;
+  a.bg = bg;
+  a.gJ = gJ;
+  a.kept_tau = use_kept ? S.kept_tau : nullptr;
+  a.kept_tex = use_kept ? S.kept_tex : nullptr;
+  a.gtpp = dyn.take<float>(tot[TOT_TPP]);
+  a.jraw = dyn.take<double>(tot[TOT_JRAW]);
   const size_t gbeg = (S.fixed + dyn.off + 255) & ~(size_t)255;
   Carve gcv((char*)scratch + gbeg);
-  const Grad G = carve_grad(gcv, T);
+  GradDims dims{T->B * T->n, T->n, T->num_nodes, T->num_nodes * T->B,
+                T->num_nodes * T->nclass * T->B, T->num_leaves};
+  a.G = carve_grad(gcv, dims);
   const size_t gbytes = (gcv.off + 255) & ~(size_t)255;
   const size_t need = gbeg + gbytes + 256;
   T->scratch_needed = need;
   if (scratch_bytes < need) return set_error(TREVR_E_CAPACITY, "scratch too small for the adjoint");
   const uint64_t epoch = scratch_mark(scratch);
-  const int64_t words = (int64_t)(gbytes / 8);
-  k_zero_u64<<<grid_of(words, 256), 256, 0, st>>>((unsigned long long*)((char*)scratch + gbeg),
-                                                  words);
-  TREVR_LAUNCH_CHECK("k_zero_u64");
-  if (!reuse && (rc = near_fill(T, S, nb)) != TREVR_OK) return rc;
+  if ((rc = zero_words(st, (char*)scratch + gbeg, gbytes / 4)) != TREVR_OK) return rc;
+  if (!reuse && (rc = near_fill(tree_launch(T), S)) != TREVR_OK) return rc;
   prof_end(T, TREVR_PROF_SETUP, ev_setup);
   auto run = [&](uint32_t s0, uint32_t scnt, uint32_t cap) -> trevr_status {
     trevr_status r;
+    const Launch L = tree_launch(T);
     if (!reuse) {   // the forward's p-p columns and pair optical depths
       hipEvent_t ev_near = prof_begin(T);
-      if ((r = launch_pp_rays(T, S, s0, nb, scnt, active)) != TREVR_OK) return r;
-      if ((r = launch_pp_src(T, S, s0, nb, scnt, active, nullptr)) != TREVR_OK) return r;
+      if ((r = launch_pp_rays(L, T->B, S, host_items(S, Q_PPR, s0, scnt), scnt, active)) !=
+          TREVR_OK)
+        return r;
+      if ((r = launch_pp_src(L, T->B, S, host_items(S, Q_PPS, s0, scnt), scnt, active,
+                             nullptr)) != TREVR_OK)
+        return r;
       prof_end(T, TREVR_PROF_NEAR, ev_near);
     }
-    switch (T->B) {
-      case 1: return bwd_batch<1>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-      case 2: return bwd_batch<2>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-      case 3: return bwd_batch<3>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-      case 4: return bwd_batch<4>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-      case 5: return bwd_batch<5>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-      case 6: return bwd_batch<6>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-      case 7: return bwd_batch<7>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-      default: return bwd_batch<8>(T, S, s0, nb, scnt, cap, active, bg, gJ, G, jraw, gtpp,
-                                   kept_tau, kept_tex);
-    }
+    return bwd_items(L, T->B, S, a, Items{s0, s0 + scnt, nullptr, nullptr}, scnt, cap, T);
   };
   bool whole = reuse && T->fwd.cuts_kept;
   if (whole) {   // one batch, whose cut lists the forward left in place
@@ -1289,44 +1370,18 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
     for (uint32_t b0 = 0; b0 < nb; b0 += kBatch) {
       const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
       bool w = true;
-      if ((rc = walk_batch(T, S, b0, cnt, nb, run, &w)) != TREVR_OK) return rc;
+      if ((rc = walk_batch(T, S, b0, cnt, run, &w)) != TREVR_OK) return rc;
       whole = whole && w;
     }
   }
   hipEvent_t ev_tree = prof_begin(T);
-  if (nb > 0) {
-    if (T->stack_large)
-      k_rpp_bwd<kStackLarge><<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, S.bprev, G);
-    else
-      k_rpp_bwd<kStackSmall><<<nb, 64, 0, st>>>(T->dev, S.blist, S.nb, S.brad, S.bprev, G);
-    TREVR_LAUNCH_CHECK("k_rpp_bwd");
-  }
-  const DevTree& D = T->dev;
-  if (G.ka > 1) {
-    k_sum_copies<<<grid_of(G.na, 256), 256, 0, st>>>(G.galpha, G.na, G.ka);
-    TREVR_LAUNCH_CHECK("k_sum_copies");
-  }
-  if (G.ks > 1) {
-    k_sum_copies<<<grid_of(G.ns, 256), 256, 0, st>>>(G.gLb, G.ns, G.ks);
-    TREVR_LAUNCH_CHECK("k_sum_copies");
-    k_sum_copies<<<grid_of(T->num_nodes * 4, 256), 256, 0, st>>>(G.gcen, T->num_nodes * 4, G.ks);
-    TREVR_LAUNCH_CHECK("k_sum_copies");
-  }
-  k_cen_prep<<<grid_of(T->num_nodes, 256), 256, 0, st>>>(D, G);
-  TREVR_LAUNCH_CHECK("k_cen_prep");
-  for (size_t d = 0; d < T->levels.size(); ++d) {
-    const auto lv = T->levels[d];
-    const int64_t work = (int64_t)(lv.second - lv.first) * T->nclass;
-    k_tree_bwd<<<grid_of(work, 128), 128, 0, st>>>(T->buf, D, lv.first, lv.second, G);
-    TREVR_LAUNCH_CHECK("k_tree_bwd");
-  }
-  k_leaf_bwd<<<grid_of(T->num_nodes, 128), 128, 0, st>>>(T->buf, D, G);
-  TREVR_LAUNCH_CHECK("k_leaf_bwd");
-  k_grad_out<<<grid_of(T->n, 256), 256, 0, st>>>(D, G, gL, gkappa, grho);
-  TREVR_LAUNCH_CHECK("k_grad_out");
+  std::vector<int64_t> level_work;
+  for (const auto& lv : T->levels) level_work.push_back((int64_t)(lv.second - lv.first) * T->nclass);
+  if ((rc = bwd_tree_pass(tree_launch(T), S, a.G, level_work, gL, gkappa, grho)) != TREVR_OK)
+    return rc;
   prof_end(T, TREVR_PROF_ADJ_TREE, ev_tree);
-  T->fwd = FwdState{true, scratch, epoch, hash, nb, near_total, act_total, pairs,
-                    nb <= kBatch && whole, T->cut_default, use_kept};
+  T->fwd = FwdState{true, scratch, epoch, hash, nb, tot[TOT_NEAR], tot[TOT_TPP], tot[TOT_PTAU],
+                    tot[TOT_JRAW], nb <= kBatch && whole, T->cut_default, use_kept};
   return TREVR_OK;
 }
 #undef TREVR_LAUNCH_CHECK

@@ -27,6 +27,48 @@ constexpr int kNPair = 2;        // (receiver, p-p source) pairs per thread per 
 constexpr int kRayPer = 2;       // rays per thread in the p-p column pass
 constexpr double kR = 0.48860251190291992;   // (3/(4 pi))^(1/2)
 
+// Work items of one launch (active buckets, each with its scene): indices
+// [lo, hi), narrowed by the device-resident range rng[0..1] when given, so a
+// launch can cover a count only the device knows.  A fixed grid of
+// workgroups (as many as are resident on the chip at once) takes the items
+// in order through the counter q[0]; q[1] counts the workgroups that found
+// none left, and the last of them clears both, so the pair is zero before
+// and after every launch (the caller zeroes it once per scratch use).
+constexpr uint32_t kNoItem = 0xFFFFFFFFu;
+struct Items {
+  uint32_t lo, hi;
+  const uint32_t* rng;
+  uint32_t* q;
+};
+
+// Next item for the whole workgroup (kNoItem when none is left); a barrier
+// first, so the previous item's LDS is free.
+__device__ inline uint32_t next_item(const Items& I, uint32_t* s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t b = I.lo, e = I.hi;
+    if (I.rng) {
+      b = max(b, I.rng[0]);
+      e = min(e, I.rng[1]);
+    }
+    const uint32_t k = atomicAdd(&I.q[0], 1u);
+    uint32_t it = kNoItem;
+    if (b < e && k < e - b) {
+      it = b + k;
+    } else if (atomicAdd(&I.q[1], 1u) == gridDim.x - 1u) {
+      atomicExch(&I.q[0], 0u);
+      atomicExch(&I.q[1], 0u);
+    }
+    *s_item = it;
+  }
+  __syncthreads();
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)*s_item);
+}
+
+// Queue counter pairs of a scratch, one per item kernel.
+enum { Q_SETUP = 0, Q_FILL, Q_WALK, Q_PPR, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD,
+       Q_RPP_BWD, Q_N };
+
 __device__ inline void atomic_max_u64(unsigned long long* a, unsigned long long v) {
   atomicMax(a, v);
 }
@@ -532,5 +574,48 @@ __device__ inline void for_each_hit_lane(const DevTree& T, const uint2* mycut, u
     }
   }
 }
+
+// Gradient accumulators (sorted slots / preorder nodes), FP64.
+struct Grad {
+  double* gL;       // [B][n]
+  double* gk;       // [B][n]
+  double* gh;       // [n]   d/dh (converted to rho at the end)
+  double* gr;       // [n]   direct d/drho
+  double* galpha;   // [node][class][B]
+  double* gLb;      // [node][B]
+  double* gcen;     // [node][4]: d/d centre; later (u, v) of the centre adjoint
+  double* grpp;     // [bucket] d/d r_pp
+  // The far field adds to galpha, gLb and gcen from every bucket, and the
+  // cells near the root are shared by most buckets: workgroups add to one
+  // of ka (ks) copies of galpha (of gLb, gcen), chosen by workgroup index,
+  // which spreads the atomics over more addresses; the copies are summed
+  // into the first before the tree pass.
+  uint32_t ka, ks;      // copies (powers of two)
+  int64_t na, ns, nc;   // elements per copy: of galpha; of gLb; of gcen
+  // The accumulators of one scene (arrays span every scene of a forest).
+  __device__ Grad at(const DevTree& T) const {
+    Grad g = *this;
+    g.gL += T.joff;
+    g.gk += T.joff;
+    g.gh += T.eoff;
+    g.gr += T.eoff;
+    g.galpha += T.aoff;
+    g.gLb += T.lboff;
+    g.gcen += 4 * T.noff;
+    return g;
+  }
+};
+
+// Inputs and outputs of the adjoint's per-bucket kernels.
+struct BwdArgs {
+  const uint8_t* active;
+  const float* bg;
+  const double* gJ;
+  Grad G;
+  double* jraw;        // raw J per (receiver, band)
+  float* gtpp;         // adjoint of the p-p columns, laid out like them
+  const float* kept_tau;
+  const float* kept_tex;
+};
 
 }  // namespace trevr

@@ -503,6 +503,8 @@ size_t layout_tree(const trevr_params& p, int64_t n, int nclass, void* base, Tre
   t.ray_n = cv.take<double>(3 * nray);
   t.ray_class = cv.take<int32_t>(nray);
   t.geom = cv.take<double>((size_t)kMaxLevels * nclass * 3);
+  t.dev = cv.take<DevTree>(1);
+  t.levels = cv.take<uint2>(kMaxLevels + 3);
   if (o) *o = t;
   return cv.off + 256;
 }

@@ -70,6 +70,21 @@ struct DevTree {
   const int32_t* ray_class;   // [nray]
   uint32_t* err;              // sticky error bits
   unsigned long long* counters;
+  // tables of the build that the adjoint reads
+  const uint32_t* b_pre;      // BFS index -> preorder index
+  const int32_t *b_lown, *b_split;
+  const double* alpha64;      // [node][nclass][B]
+  const double* geom;         // [64][nclass][3]
+  const uint2* levels;        // [depth] BFS index ranges per depth
+  int32_t depth;
+  // offsets of this tree's blocks in arrays shared by the scenes of a
+  // forest (all zero for a tree on its own)
+  int32_t boff;               // bands: background intensities
+  int64_t eoff;               // elements: active flags, density gradients
+  int64_t joff;               // [B][n] blocks: J, its adjoint, L and kappa gradients
+  int64_t noff;               // nodes: centre adjoints (4 per node)
+  int64_t lboff;              // node x band: luminosity adjoints
+  int64_t aoff;               // node x class x band: transmission adjoints
 };
 
 // ------------------------------------------------------------ geometry

@@ -55,6 +55,8 @@ struct TreeBufs {
   double* geom;               // [64][nclass][3]: log w1, log w12, chord / L
   uint32_t* err;
   unsigned long long* counters;
+  DevTree* dev;               // device copy of the tree's DevTree (one-scene table)
+  uint2* levels;              // [kMaxLevels + 3] BFS index ranges per depth
 };
 
 struct SortCfg {
@@ -86,7 +88,8 @@ struct FwdState {
   const void* scratch;
   uint64_t epoch;       // the library's write to that scratch that left it
   uint64_t hash;
-  uint32_t nb, near_total, act_total, pairs;
+  uint32_t nb;
+  uint64_t near_total, tpp_total, ptau_total, jraw_total;
   bool cuts_kept;       // the cut buffer holds every bucket's cut list
   uint32_t cut_stride;  // ... at this many entries per bucket
   bool kept;            // far-source optical depths of the forward are in the scratch
@@ -107,7 +110,7 @@ struct trevr_tree {
   std::vector<std::pair<uint32_t, uint32_t>> levels;  // BFS index ranges per depth
   size_t scratch_needed;
   bool counters_valid;
-  uint32_t* host_u32;                       // pinned 8-word readback buffer
+  uint32_t* host_u32;                       // pinned readback buffer (kHostWords)
   FwdState fwd;
   bool stack_large;                         // traversals need the large LDS stack
   uint32_t cut_default;                     // cut-list entries per bucket to try first
@@ -121,6 +124,10 @@ struct trevr_tree {
 };
 
 namespace trevr {
+constexpr int kHostWords = 64;
+// Copy the host DevTree of a tree (and its level table) to the device copy
+// the kernels read; synchronises.
+trevr_status upload_dev(trevr_tree* t);
 trevr_status set_error(trevr_status s, const std::string& msg);
 trevr_status hip_check(hipError_t e, const char* what);
 trevr_status build_tree_impl(trevr_tree* t, const float* x, const float* y, const float* z,
