@@ -248,6 +248,92 @@ enum { TREVR_PROF_SETUP = 0, TREVR_PROF_WALK = 1, TREVR_PROF_REDUCE = 2, TREVR_P
 trevr_status trevr_profile_enable(trevr_tree* t, int on);
 trevr_status trevr_profile_read(trevr_tree* t, double* ms, int64_t* launches);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent scenes (a forest).
+ *
+ * A simulation with individual time steps (Section 1.2) asks for J of a
+ * varying subset of elements in many scenes of very different sizes; the
+ * calls below compute them together.  Each scene keeps its own parameters
+ * (N_side, band count, theta, bucket size, flags, box, rpp_min) and its own
+ * tree; every per-bucket step is one persistent launch over the (scene,
+ * bucket) work items of all scenes with the same band count.
+ *
+ * Concatenated layouts, for scene s with n_s = offsets[s+1] - offsets[s]
+ * elements and B_s bands:
+ *   x, y, z, m, rho, active, grho : [sum n_s], scene s from offsets[s];
+ *   kappa, lum, J, gJ, gL, gkappa : scene s is a [B_s][n_s] band-major block
+ *                                   starting at sum_{t<s} B_t n_t;
+ *   bg                            : [sum B_s], scene s from sum_{t<s} B_t.
+ * Results per scene equal those of trevr_compute_J / _backward on that
+ * scene's own tree (trevr_forest_scene) up to FP32 rounding of the sums
+ * formed with atomics.
+ *
+ * Sizes are fixed once by trevr_forest_plan (synchronising).  The p-p radius
+ * of a bucket is set by all of its members, active or not, so the plan's
+ * all-active bucket setup and walks bound every later call whatever its
+ * active set.  After it, trevr_compute_J_batched and
+ * trevr_compute_J_backward_batched only enqueue kernels on `stream` -- no
+ * synchronisation, allocation or memset -- so they can be captured in a HIP
+ * graph and replayed with new active flags, opacities' adjoints etc. in the
+ * same buffers.
+ * ------------------------------------------------------------------------ */
+typedef struct trevr_forest trevr_forest;
+
+/* Workspace bytes of a forest of S scenes: params [S] and offsets [S+1] are
+ * HOST arrays, offsets[0] = 0 and every scene non-empty. */
+trevr_status trevr_forest_workspace_bytes(const trevr_params* params, int32_t S,
+                                          const int64_t* offsets, size_t* ws_bytes);
+
+/* Build the trees of every scene (each as trevr_build_tree, Sections
+ * 2.3-2.6) into the caller's workspace ws.  Synchronises `stream`.  The
+ * inputs may be freed afterwards; the forest borrows ws. */
+trevr_status trevr_build_forest(const trevr_params* params, int32_t S, const int64_t* offsets,
+                                const float* x, const float* y, const float* z, const float* m,
+                                const float* rho, const float* kappa, const float* lum, void* ws,
+                                size_t ws_bytes, void* stream, trevr_forest** out);
+
+/* Plan: bytes of device scratch the planning pass needs, then the pass
+ * itself (bucket setup and walks of every scene with all elements active;
+ * picks the traversal stack and the cut-list length of every later call).
+ * Synchronises `stream`.  Afterwards trevr_forest_scratch_bytes gives the
+ * scratch every batched call needs (forward and adjoint alike). */
+trevr_status trevr_forest_plan_bytes(const trevr_forest* f, size_t* bytes);
+trevr_status trevr_forest_plan(trevr_forest* f, void* scratch, size_t scratch_bytes,
+                               void* stream);
+trevr_status trevr_forest_scratch_bytes(const trevr_forest* f, size_t* bytes);
+
+/* J of the active elements of every scene (layouts above; active NULL = all
+ * active; bg may be NULL unless a scene has TREVR_BACKGROUND).  Rows of
+ * inactive elements are left untouched.  Enqueues kernels only (graph
+ * capturable).  TREVR_E_STATE before a plan, TREVR_E_CAPACITY if scratch is
+ * smaller than trevr_forest_scratch_bytes. */
+trevr_status trevr_compute_J_batched(trevr_forest* f, const uint8_t* active, const float* bg,
+                                     double* J, void* scratch, size_t scratch_bytes,
+                                     void* stream);
+
+/* Adjoint of trevr_compute_J_batched (same derivative as
+ * trevr_compute_J_backward, per scene; every gradient row written).  If the
+ * last batched call of this forest was on this scratch and no call has
+ * written the scratch since, its bucket setup, walks and p-p columns are
+ * used as they are; they must be for the same active set -- checked on the
+ * device by fingerprint, a mismatch raising a sticky flag that
+ * trevr_forest_check reports as TREVR_E_STATE.  Otherwise they are
+ * recomputed.  Enqueues kernels only (graph capturable). */
+trevr_status trevr_compute_J_backward_batched(trevr_forest* f, const uint8_t* active,
+                                              const float* bg, const double* gJ, double* gL,
+                                              double* gkappa, double* grho, void* scratch,
+                                              size_t scratch_bytes, void* stream);
+
+/* Synchronise and report sticky device errors of the forest and its scenes. */
+trevr_status trevr_forest_check(trevr_forest* f);
+/* Counters of the last batched call: one scene, or scene = -1 for the sum
+ * over scenes (maxima for max_near, max_cut, max_stack).  Synchronises. */
+trevr_status trevr_forest_get_counters(trevr_forest* f, int32_t scene, trevr_counters* out);
+/* The tree of one scene (owned by the forest), for the single-tree calls. */
+trevr_status trevr_forest_scene(trevr_forest* f, int32_t scene, trevr_tree** out);
+/* Destroy the forest and its scene trees (host handles only). */
+trevr_status trevr_forest_destroy(trevr_forest* f);
+
 const char* trevr_status_string(trevr_status s);
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* trevr_last_error(void);

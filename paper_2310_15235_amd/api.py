@@ -24,7 +24,11 @@ EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_compute_J_backward", "trevr_tree_tune",
             "trevr_scratch_needed", "trevr_get_counters", "trevr_check", "trevr_tree_destroy",
             "trevr_tree_info", "trevr_tree_export", "trevr_profile_enable",
-            "trevr_profile_read", "trevr_status_string", "trevr_last_error")
+            "trevr_profile_read", "trevr_status_string", "trevr_last_error",
+            "trevr_forest_workspace_bytes", "trevr_build_forest", "trevr_forest_plan_bytes",
+            "trevr_forest_plan", "trevr_forest_scratch_bytes", "trevr_compute_J_batched",
+            "trevr_compute_J_backward_batched", "trevr_forest_check",
+            "trevr_forest_get_counters", "trevr_forest_scene", "trevr_forest_destroy")
 TUNE_STACK, TUNE_CUT = 0, 1
 PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree")
 PROF_SLOTS = len(PROF_NAMES)
@@ -78,6 +82,19 @@ def lib():
         L.trevr_tree_export.argtypes = [vp] * 9
         L.trevr_profile_enable.argtypes = [vp, ctypes.c_int]
         L.trevr_profile_read.argtypes = [vp, vp, vp]
+        L.trevr_forest_workspace_bytes.argtypes = [ctypes.POINTER(Params), i32, vp,
+                                                   ctypes.POINTER(sz)]
+        L.trevr_build_forest.argtypes = [ctypes.POINTER(Params), i32, vp] + [vp] * 8 + \
+            [sz, vp, ctypes.POINTER(vp)]
+        L.trevr_forest_plan_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.trevr_forest_plan.argtypes = [vp, vp, sz, vp]
+        L.trevr_forest_scratch_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.trevr_compute_J_batched.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        L.trevr_compute_J_backward_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.trevr_forest_check.argtypes = [vp]
+        L.trevr_forest_get_counters.argtypes = [vp, i32, ctypes.POINTER(Counters)]
+        L.trevr_forest_scene.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        L.trevr_forest_destroy.argtypes = [vp]
         L.trevr_status_string.restype = ctypes.c_char_p
         L.trevr_status_string.argtypes = [ctypes.c_int]
         L.trevr_last_error.restype = ctypes.c_char_p
@@ -271,9 +288,10 @@ class Tree:
                     ray_class=rc, **inf)
 
     def close(self):
-        if getattr(self, "handle", None) is not None and self.handle.value:
+        if getattr(self, "_owned", True) and getattr(self, "handle", None) is not None and \
+                self.handle.value:
             lib().trevr_tree_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -315,6 +333,159 @@ def compute_J_backward(scene, gJ, active=None, device="cuda"):
     out = (gL.cpu().numpy(), gk.cpu().numpy(), gr.cpu().numpy())
     T.close()
     return out
+
+def scene_flags(scene) -> int:
+    return (THICK_CORR if scene.thick_corr else 0) | (NEAR_FIELD if scene.near_field else 0) | \
+        (BACKGROUND if scene.background else 0)
+
+
+class Forest:
+    """Independent scenes computed together (trevr_build_forest and the
+    batched calls of include/trevr2.h).  Element arrays are concatenated
+    over scenes, band arrays as per-scene [B_s, n_s] blocks; ``split``
+    cuts such a flat array back into per-scene views.
+
+    Construction builds every scene's tree and plans the forest (sizes of
+    every later call); ``compute_J`` and ``compute_J_backward`` then only
+    enqueue kernels on torch's current stream, so they can be captured in a
+    ``torch.cuda.CUDAGraph``."""
+
+    def __init__(self, scenes, device="cuda"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.S = len(scenes)
+        self.n = [int(s.n) for s in scenes]
+        self.B = [int(s.n_bands) for s in scenes]
+        self.offsets = np.zeros(self.S + 1, np.int64)
+        self.offsets[1:] = np.cumsum(self.n)
+        self.boff = np.zeros(self.S + 1, np.int64)
+        self.boff[1:] = np.cumsum([b * n for b, n in zip(self.B, self.n)])
+        self.bgoff = np.zeros(self.S + 1, np.int64)
+        self.bgoff[1:] = np.cumsum(self.B)
+        params = (Params * self.S)()
+        for i, s in enumerate(scenes):
+            params[i] = make_params(s.nside, s.leaf_size, s.n_bands, scene_flags(s), s.theta,
+                                    s.rpp_min, s.box)
+        self.params = params
+        f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=self.device)
+        cat = lambda name: f32(np.concatenate([getattr(s, name) for s in scenes]))
+        catb = lambda name: f32(np.concatenate([np.asarray(getattr(s, name)).ravel()
+                                                for s in scenes]))
+        x, y, z, m, rho = (cat(k) for k in ("x", "y", "z", "m", "rho"))
+        kappa, lum = catb("kappa"), catb("lum")
+        off_p = self.offsets.ctypes.data_as(ctypes.c_void_p)
+        wb = ctypes.c_size_t()
+        _check(lib().trevr_forest_workspace_bytes(params, self.S, off_p, ctypes.byref(wb)),
+               "trevr_forest_workspace_bytes")
+        self.ws = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        f = torch.float32
+        _check(lib().trevr_build_forest(params, self.S, off_p, _dev(x, f), _dev(y, f), _dev(z, f),
+                                        _dev(m, f), _dev(rho, f), _dev(kappa, f), _dev(lum, f),
+                                        ctypes.c_void_p(self.ws.data_ptr()), wb.value,
+                                        _stream_ptr(), ctypes.byref(h)), "trevr_build_forest")
+        self.handle = h
+        pb = ctypes.c_size_t()
+        _check(lib().trevr_forest_plan_bytes(h, ctypes.byref(pb)), "trevr_forest_plan_bytes")
+        plan_scratch = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        _check(lib().trevr_forest_plan(h, ctypes.c_void_p(plan_scratch.data_ptr()), pb.value,
+                                       _stream_ptr()), "trevr_forest_plan")
+        del plan_scratch
+        sb = ctypes.c_size_t()
+        _check(lib().trevr_forest_scratch_bytes(h, ctypes.byref(sb)), "trevr_forest_scratch_bytes")
+        self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        self.bg_default = None
+        if any(s.background for s in scenes):
+            self.bg_default = f32(np.concatenate([
+                np.asarray(s.bg if s.bg is not None else np.zeros(s.n_bands), np.float32)
+                for s in scenes]))
+
+    def flat_active(self, actives):
+        """uint8 device tensor [sum n] from per-scene flags (None = all)."""
+        torch = _torch()
+        a = np.concatenate([np.ones(n, np.uint8) if v is None else np.asarray(v, np.uint8)
+                            for v, n in zip(actives, self.n)])
+        return torch.as_tensor(a, device=self.device)
+
+    def split(self, flat):
+        """Per-scene [B_s, n_s] views of a band-major flat array, or [n_s]
+        views of an element array."""
+        if flat.numel() == int(self.boff[-1]):
+            return [flat[self.boff[s]:self.boff[s + 1]].view(self.B[s], self.n[s])
+                    for s in range(self.S)]
+        return [flat[self.offsets[s]:self.offsets[s + 1]] for s in range(self.S)]
+
+    def new_J(self):
+        torch = _torch()
+        return torch.zeros(int(self.boff[-1]), dtype=torch.float64, device=self.device)
+
+    def compute_J(self, active=None, bg=None, out=None):
+        torch = _torch()
+        if out is None:
+            out = self.new_J()
+        bg = self.bg_default if bg is None else bg
+        a = None if active is None else _dev(active, torch.uint8)
+        g = None if bg is None else _dev(bg, torch.float32)
+        _check(lib().trevr_compute_J_batched(self.handle, a, g, _dev(out, torch.float64),
+                                             ctypes.c_void_p(self.scratch.data_ptr()),
+                                             self.scratch.numel(), _stream_ptr()),
+               "trevr_compute_J_batched")
+        return out
+
+    def compute_J_backward(self, gJ, active=None, bg=None, out=None):
+        torch = _torch()
+        f64 = torch.float64
+        if out is None:
+            out = (torch.empty(int(self.boff[-1]), dtype=f64, device=self.device),
+                   torch.empty(int(self.boff[-1]), dtype=f64, device=self.device),
+                   torch.empty(int(self.offsets[-1]), dtype=f64, device=self.device))
+        gL, gk, gr = out
+        bg = self.bg_default if bg is None else bg
+        a = None if active is None else _dev(active, torch.uint8)
+        g = None if bg is None else _dev(bg, torch.float32)
+        _check(lib().trevr_compute_J_backward_batched(
+            self.handle, a, g, _dev(gJ, f64), _dev(gL, f64), _dev(gk, f64), _dev(gr, f64),
+            ctypes.c_void_p(self.scratch.data_ptr()), self.scratch.numel(), _stream_ptr()),
+            "trevr_compute_J_backward_batched")
+        return gL, gk, gr
+
+    def check(self):
+        _check(lib().trevr_forest_check(self.handle), "trevr_forest_check")
+
+    def counters(self, scene=-1) -> dict:
+        c = Counters()
+        _check(lib().trevr_forest_get_counters(self.handle, int(scene), ctypes.byref(c)),
+               "trevr_forest_get_counters")
+        return {k: int(getattr(c, k)) for k, _ in Counters._fields_}
+
+    def scene_tree(self, s: int) -> "Tree":
+        """The tree of scene s as a Tree (owned by the forest) for the
+        single-tree calls."""
+        torch = _torch()
+        h = ctypes.c_void_p()
+        _check(lib().trevr_forest_scene(self.handle, int(s), ctypes.byref(h)), "trevr_forest_scene")
+        t = Tree.__new__(Tree)
+        t.n, t.B, t.nside = self.n[s], self.B[s], int(self.params[s].nside)
+        t.params = self.params[s]
+        t.device = self.device
+        t.ws = self.ws
+        t.handle = h
+        t._owned = False
+        tb, sb = workspace_bytes(self.params[s], self.n[s])
+        t._scratch = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        return t
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().trevr_forest_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class TrevrJ:
     """J as a differentiable torch function of (kappa, lum, rho).

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libtrevr2.so")
-SOURCES = ["api.hip", "tree_build.hip", "compute_j.hip", "compute_j_bwd.hip"]
+SOURCES = ["api.hip", "tree_build.hip", "compute_j.hip", "compute_j_bwd.hip", "forest.hip"]
 
 
 def hipcc_command(out: str = SO, arch: str = "gfx950"):

@@ -1038,6 +1038,16 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
   return TREVR_OK;
 }
 
+trevr_status launch_active_hash(const Launch& L, const uint8_t* active,
+                                unsigned long long* out) {
+  trevr_status rc;
+  if ((rc = zero_words(L.st, out, 2)) != TREVR_OK) return rc;
+  const dim3 ge(grid_of(L.max_n, 256), (unsigned)L.S);
+  k_active_hash<<<ge, 256, 0, L.st>>>(L.TT, active, out);
+  TREVR_LAUNCH_CHECK("k_active_hash");
+  return rc;
+}
+
 trevr_status bucket_setup(trevr_tree* T, const uint8_t* active, Scratch& S, uint32_t* nb,
                           uint64_t tot[TOT_N], uint64_t* hash) {
   hipStream_t st = T->stream;

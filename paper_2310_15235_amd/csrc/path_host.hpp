@@ -75,6 +75,9 @@ trevr_status zero_words(hipStream_t st, void* p, size_t words);
 // per-bucket offsets of the dynamic scratch and their 64-bit totals, the
 // active-set fingerprint in ahash[0].
 trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch& S);
+// Fingerprint of the active set of every scene into *out (zeroed first).
+trevr_status launch_active_hash(const Launch& L, const uint8_t* active,
+                                unsigned long long* out);
 // Fill the p-p lists (S.nidx must be set).
 trevr_status near_fill(const Launch& L, const Scratch& S);
 // Tree walks of the items into the cut lists (cap entries each).

@@ -98,3 +98,33 @@ def test_tune_rejects_unknown_handle():
     L = api.lib()
     bogus = ctypes.c_void_p(0x1234)
     assert L.trevr_tree_tune(bogus, api.TUNE_STACK, 256) == api.E_STATE
+
+
+def test_forest_arguments_checked_on_host():
+    L = api.lib()
+    P = (api.Params * 2)(api.make_params(), api.make_params(n_bands=2))
+    sz = ctypes.c_size_t()
+    ok = (ctypes.c_int64 * 3)(0, 100, 250)
+    assert L.trevr_forest_workspace_bytes(P, 2, ctypes.cast(ok, ctypes.c_void_p),
+                                          ctypes.byref(sz)) == api.OK
+    one, _ = api.workspace_bytes(api.make_params(), 100)
+    two, _ = api.workspace_bytes(api.make_params(n_bands=2), 150)
+    assert sz.value >= one + two
+    for bad, S in (((0, 100, 100), 2), ((5, 100, 250), 2), ((0, 100, 250), 0)):
+        arr = (ctypes.c_int64 * 3)(*bad)
+        assert L.trevr_forest_workspace_bytes(P, S, ctypes.cast(arr, ctypes.c_void_p),
+                                              ctypes.byref(sz)) == api.E_INVALID
+    h = ctypes.c_void_p()
+    st = L.trevr_build_forest(P, 2, ctypes.cast(ok, ctypes.c_void_p), *([None] * 8), 0, None,
+                              ctypes.byref(h))
+    assert st == api.E_INVALID and not h.value
+
+
+def test_unknown_forest_handle_rejected():
+    L = api.lib()
+    bogus = ctypes.c_void_p(87654321)
+    sz = ctypes.c_size_t()
+    assert L.trevr_forest_check(bogus) == api.E_STATE
+    assert L.trevr_forest_destroy(bogus) == api.E_STATE
+    assert L.trevr_forest_plan_bytes(bogus, ctypes.byref(sz)) == api.E_STATE
+    assert L.trevr_compute_J_batched(bogus, None, None, None, None, 0, None) == api.E_STATE
