@@ -79,6 +79,119 @@ def measured_traffic(kernel: str):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+def batched_bench(args, dev):
+    """The batched workload: 64 independent scenes (log-uniform 2^12..2^17
+    elements, uniform or log-normal media, 1-4 bands, N_side 1/2/4), all
+    active, computed by the batched calls replayed from HIP graphs (forward;
+    forward + adjoint); against it the plain path, every scene's own tree
+    called in turn.  Also the same graph replayed with per-scene active
+    fractions of 1%, 10% or 100% written into its active buffer."""
+    import numpy as np
+    import torch
+    from paper_2310_15235_amd import api, scenes
+
+    def note(msg):
+        print(f"[batched] {msg}", file=sys.stderr, flush=True)
+
+    scs = scenes.batched_scenes(64)
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
+    F = api.Forest(scs, device=dev)
+    torch.cuda.synchronize()
+    b1 = time.perf_counter()
+    note(f"forest of {F.S} scenes built and planned in {b1 - b0:.2f} s")
+    a = F.flat_active([None] * F.S)
+    gJ = torch.as_tensor(np.random.default_rng(11).normal(size=int(F.boff[-1])), device=dev)
+    J = F.new_J()
+    outs = (torch.empty_like(gJ), torch.empty_like(gJ),
+            torch.empty(int(F.offsets[-1]), dtype=torch.float64, device=dev))
+    chosen, tune_ms = F.autotune(a, reps=1)   # forward only: the adjoint's p-p work follows it
+    note(f"autotuned: configuration {chosen}, forward ms {[round(float(t), 1) for t in tune_ms]}")
+    F.compute_J(a, out=J)
+    F.compute_J_backward(gJ, a, out=outs)
+    F.check()
+    seg = F.counters(-1)["segments"]
+    note("eager forward + adjoint done")
+    torch.cuda.synchronize()
+    g_f, g_fa = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_f):
+        F.compute_J(a, out=J)
+    with torch.cuda.graph(g_fa):
+        F.compute_J(a, out=J)
+        F.compute_J_backward(gJ, a, out=outs)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    k = max(1, min(args.steps, 2))   # each replay takes seconds at this size
+    ms_f = timed(g_f.replay, k)
+    note(f"graph forward {ms_f:.1f} ms")
+    ms_fa = timed(g_fa.replay, k)
+    note(f"graph forward + adjoint {ms_fa:.1f} ms")
+    # mixed individual time steps: per-scene active fractions in one buffer
+    rng = np.random.default_rng(7)
+    fr = rng.choice([0.01, 0.1, 1.0], size=F.S)
+    acts = [scenes.active_subset(s, f, 300 + i) if f < 1.0 else None
+            for i, (s, f) in enumerate(zip(scs, fr))]
+    a.copy_(F.flat_active(acts))
+    F.compute_J(a, out=J)
+    F.check()
+    seg_mixed = F.counters(-1)["segments"]
+    ms_fa_mixed = timed(g_fa.replay, k)
+    note(f"graph forward + adjoint, mixed active sets {ms_fa_mixed:.1f} ms")
+    a.copy_(F.flat_active([None] * F.S))
+    # the plain path: each scene's own tree, one after another
+    trees = [F.scene_tree(s) for s in range(F.S)]
+    Jp, gLp, gkp, grp = F.split(J), F.split(outs[0]), F.split(outs[1]), F.split(outs[2])
+    gJp = F.split(gJ)
+    ap_ = F.split(a)
+    bgs = [None if not s.background else torch.as_tensor(s.bg, device=dev) for s in scs]
+
+    def plain_f():
+        for s, T in enumerate(trees):
+            T.compute_J(ap_[s], bgs[s], out=Jp[s])
+
+    def plain_fa():
+        for s, T in enumerate(trees):
+            T.compute_J(ap_[s], bgs[s], out=Jp[s])
+            T.compute_J_backward(gJp[s], ap_[s], bgs[s], out=(gLp[s], gkp[s], grp[s]))
+
+    plain_fa()
+    ms_pf = timed(plain_f, k)
+    note(f"plain forward {ms_pf:.1f} ms")
+    ms_pfa = timed(plain_fa, k)
+    note(f"plain forward + adjoint {ms_pfa:.1f} ms")
+    for T in trees:
+        T.check()
+    F.close()
+    n_tot = int(F.offsets[-1])
+    return {
+        "workload": "64 scenes, 2^12..2^17 elements each (log-uniform), uniform or log-normal "
+                    "media, 1-4 bands, N_side 1/2/4, theta 0.75, leaf 8, all active",
+        "scenes": F.S, "elements": n_tot, "segments_per_step": seg,
+        "timed_replays": k,
+        "graph": True,
+        "fwd": {"value": seg / (ms_f * 1e-3), "ms": ms_f},
+        "fwd_adjoint": {"value": seg / (ms_fa * 1e-3), "ms": ms_fa},
+        "plain_fwd": {"value": seg / (ms_pf * 1e-3), "ms": ms_pf},
+        "plain_fwd_adjoint": {"value": seg / (ms_pfa * 1e-3), "ms": ms_pfa},
+        "mixed_active": {"segments_per_step": seg_mixed,
+                         "fwd_adjoint": {"value": seg_mixed / (ms_fa_mixed * 1e-3),
+                                         "ms": ms_fa_mixed},
+                         "fractions": "1% / 10% / 100% per scene"},
+        "build_and_plan_ms": (b1 - b0) * 1e3,
+        "autotune": {"chosen": chosen, "candidate_fwd_ms": [float(t) for t in tune_ms],
+                     "candidates": "bit 2: bucket order (cost / scene), bit 1: persistent "
+                                   "grid (full / half), bit 0: p-p boxes (16 / 8)"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=0.05,
                     help="fraction of receivers the oracle evaluates for the CPU baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched 64-scene measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic, for scaling HBM byte counters)")
@@ -217,6 +332,8 @@ def main():
                          f"scene; full tree build {tb:.2f} s prorated by that fraction, "
                          f"J {tj:.2f} s"}
 
+    batched = None if args.no_batched else batched_bench(args, dev)
+
     out = {
         "metric": METRIC,
         "value": seg / (ms_step * 1e-3),
@@ -241,6 +358,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "counters": counters,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

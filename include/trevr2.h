@@ -324,6 +324,31 @@ trevr_status trevr_compute_J_backward_batched(trevr_forest* f, const uint8_t* ac
                                               double* gkappa, double* grho, void* scratch,
                                               size_t scratch_bytes, void* stream);
 
+/*
+ * Autotuner of a forest (support call; results do not depend on the choice
+ * beyond FP32 rounding of atomic sums).  Candidate launch configurations,
+ * numbered 0 .. TREVR_FOREST_CONFIGS - 1 by three bits:
+ *   bit 2  bucket order within a band count: heaviest first (0), or scene
+ *          by scene with the heaviest first inside each (1);
+ *   bit 1  workgroups of each persistent launch: every slot the device can
+ *          hold at once (0), or half of them (1);
+ *   bit 0  p-p culling boxes of 16 (0) or 8 (1) elements.
+ * trevr_forest_autotune runs trevr_compute_J_batched -- and, when gJ is
+ * not NULL, trevr_compute_J_backward_batched -- on the given buffers under
+ * every candidate (one warm-up run, then `reps` timed runs), keeps the
+ * fastest for later calls and writes the mean milliseconds of each to
+ * times[TREVR_FOREST_CONFIGS] (host array, may be NULL).  Synchronises.
+ * set_config forces a candidate; get_config reads the one in use
+ * (0 until tuned).
+ */
+enum { TREVR_FOREST_CONFIGS = 8 };
+trevr_status trevr_forest_autotune(trevr_forest* f, const uint8_t* active, const float* bg,
+                                   double* J, const double* gJ, double* gL, double* gkappa,
+                                   double* grho, void* scratch, size_t scratch_bytes,
+                                   void* stream, int32_t reps, double* times);
+trevr_status trevr_forest_set_config(trevr_forest* f, int32_t config);
+trevr_status trevr_forest_get_config(const trevr_forest* f, int32_t* config);
+
 /* Synchronise and report sticky device errors of the forest and its scenes. */
 trevr_status trevr_forest_check(trevr_forest* f);
 /* Counters of the last batched call: one scene, or scene = -1 for the sum

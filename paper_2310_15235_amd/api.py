@@ -28,8 +28,10 @@ EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_forest_workspace_bytes", "trevr_build_forest", "trevr_forest_plan_bytes",
             "trevr_forest_plan", "trevr_forest_scratch_bytes", "trevr_compute_J_batched",
             "trevr_compute_J_backward_batched", "trevr_forest_check",
-            "trevr_forest_get_counters", "trevr_forest_scene", "trevr_forest_destroy")
+            "trevr_forest_get_counters", "trevr_forest_scene", "trevr_forest_destroy",
+            "trevr_forest_autotune", "trevr_forest_set_config", "trevr_forest_get_config")
 TUNE_STACK, TUNE_CUT = 0, 1
+CONFIGS = 8          # launch configurations of the forest autotuner
 PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree")
 PROF_SLOTS = len(PROF_NAMES)
 
@@ -95,6 +97,9 @@ def lib():
         L.trevr_forest_get_counters.argtypes = [vp, i32, ctypes.POINTER(Counters)]
         L.trevr_forest_scene.argtypes = [vp, i32, ctypes.POINTER(vp)]
         L.trevr_forest_destroy.argtypes = [vp]
+        L.trevr_forest_autotune.argtypes = [vp] * 9 + [sz, vp, i32, vp]
+        L.trevr_forest_set_config.argtypes = [vp, i32]
+        L.trevr_forest_get_config.argtypes = [vp, ctypes.POINTER(i32)]
         L.trevr_status_string.restype = ctypes.c_char_p
         L.trevr_status_string.argtypes = [ctypes.c_int]
         L.trevr_last_error.restype = ctypes.c_char_p
@@ -448,6 +453,38 @@ class Forest:
             ctypes.c_void_p(self.scratch.data_ptr()), self.scratch.numel(), _stream_ptr()),
             "trevr_compute_J_backward_batched")
         return gL, gk, gr
+
+    def autotune(self, active=None, bg=None, gJ=None, reps=2):
+        """Time the batched calls under every launch configuration, keep the
+        fastest; returns (chosen configuration, ms per candidate)."""
+        torch = _torch()
+        f64 = torch.float64
+        J = self.new_J()
+        bg = self.bg_default if bg is None else bg
+        a = None if active is None else _dev(active, torch.uint8)
+        g = None if bg is None else _dev(bg, torch.float32)
+        grads = [None, None, None]
+        gj = None
+        if gJ is not None:
+            gj = _dev(gJ, f64)
+            bufs = (torch.empty_like(J), torch.empty_like(J),
+                    torch.empty(int(self.offsets[-1]), dtype=f64, device=self.device))
+            grads = [_dev(t, f64) for t in bufs]
+        times = np.zeros(CONFIGS)
+        _check(lib().trevr_forest_autotune(
+            self.handle, a, g, _dev(J, f64), gj, grads[0], grads[1], grads[2],
+            ctypes.c_void_p(self.scratch.data_ptr()), self.scratch.numel(), _stream_ptr(),
+            int(reps), times.ctypes.data_as(ctypes.c_void_p)), "trevr_forest_autotune")
+        return self.config(), times
+
+    def config(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().trevr_forest_get_config(self.handle, ctypes.byref(v)),
+               "trevr_forest_get_config")
+        return int(v.value)
+
+    def set_config(self, k: int):
+        _check(lib().trevr_forest_set_config(self.handle, int(k)), "trevr_forest_set_config")
 
     def check(self):
         _check(lib().trevr_forest_check(self.handle), "trevr_forest_check")

@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
                                                 const uint32_t* blist, const uint32_t* bscene,
                                                 const uint32_t* noff, const uint32_t* nidx,
                                                 const uint32_t* toff, const uint8_t* active,
-                                                float* tpp) {
+                                                float* tpp, int sub) {
   const int t = threadIdx.x;
   __shared__ NearTile<NB> S;
   __shared__ RecvInfo recv[kRMax];
@@ -348,19 +348,21 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
       for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
         const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
         stage_near<NB>(S, T, near, c0, cl, c);
-        const int nsub = ((int)cl + kSub - 1) / kSub;
+        const int nsub = ((int)cl + sub - 1) / sub;
+        const float (*BL)[3] = near_boxes(S, sub, false);
+        const float (*BH)[3] = near_boxes(S, sub, true);
         for (int sb = 0; sb < nsub; ++sb) {
           bool need = false;
           if (ok) {
-            const float blo[3] = {S.blo[sb][0], S.blo[sb][1], S.blo[sb][2]};
-            const float bhi[3] = {S.bhi[sb][0], S.bhi[sb][1], S.bhi[sb][2]};
+            const float blo[3] = {BL[sb][0], BL[sb][1], BL[sb][2]};
+            const float bhi[3] = {BH[sb][0], BH[sb][1], BH[sb][2]};
             need = (kok[0] && ray_meets_box(of, inv[0], blo, bhi)) ||
                    (kok[1] && ray_meets_box(of, inv[1], blo, bhi));
           }
           if (ballot64(need) == 0ull) continue;
           if (!need) continue;
-          const int u1 = min((int)cl, (sb + 1) * kSub);
-          for (int u = sb * kSub; u < u1; ++u) {
+          const int u1 = min((int)cl, (sb + 1) * sub);
+          for (int u = sb * sub; u < u1; ++u) {
             const double d0 = S.x[u] - xi0, d1 = S.y[u] - xi1, d2 = S.z[u] - xi2;
             const double dd = d0 * d0 + d1 * d1 + d2 * d2;
             const double h2 = S.h2[u];
@@ -406,7 +408,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, 
                                                const uint32_t* noff, const uint32_t* nlumc,
                                                const uint32_t* nidx, const uint32_t* poff,
                                                const uint8_t* active, double* Jall,
-                                               float* ptau) {
+                                               float* ptau, int sub) {
   const int t = threadIdx.x;
   __shared__ NearTile<NB> S;
   __shared__ RecvInfo recv[kRMax];
@@ -468,7 +470,9 @@ __global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, 
       for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
         const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
         stage_near<NB>(S, T, near, c0, cl, c);
-        const int nsub = ((int)cl + kSub - 1) / kSub;
+        const int nsub = ((int)cl + sub - 1) / sub;
+        const float (*BL)[3] = near_boxes(S, sub, false);
+        const float (*BH)[3] = near_boxes(S, sub, true);
         for (int sb = 0; sb < nsub; ++sb) {
           bool need = false;
           if (ok && rij2 > 0.0) {
@@ -478,7 +482,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, 
             bool over = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-              const float lo = S.blo[sb][a], hi = S.bhi[sb][a];
+              const float lo = BL[sb][a], hi = BH[sb][a];
               over = over && (smax[a] >= lo) && (smin[a] <= hi);
               if (sd[a] != 0.0f) {
                 const float u = (lo - ri.rel[a]) * sinv[a], v = (hi - ri.rel[a]) * sinv[a];
@@ -492,8 +496,8 @@ __global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, 
           }
           if (ballot64(need) == 0ull) continue;
           if (!need) continue;
-          const int u1 = min((int)cl, (sb + 1) * kSub);
-          for (int u = sb * kSub; u < u1; ++u) {
+          const int u1 = min((int)cl, (sb + 1) * sub);
+          for (int u = sb * sub; u < u1; ++u) {
             const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
             const double f0 = ux - xj0, f1 = uy - xj1, f2 = uz - xj2;
             const double w0 = ux - xi0, w1 = uy - xi1, w2 = uz - xi2;
@@ -774,37 +778,37 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
 // Buckets are grouped by their scene's band count (one launch per count)
 // and, within a group, processed heaviest first (a counting sort by the log2
 // of an estimate of their p-p work), so the slowest buckets start early
-// instead of forming the tail of a launch.  Each bucket's result is
-// independent of its position.
+// instead of forming the tail of a launch; or (ORDER_SCENE) scene by scene,
+// heaviest first within each, which keeps a scene's tree in the caches.
+// Each bucket's result is independent of its position.
 __global__ void k_cost_bins(const DevTree* __restrict__ TT, const uint32_t* nbp,
                             const uint32_t* bscene, const uint32_t* bnact, const uint32_t* ncnt,
-                            const uint32_t* nlumc, uint32_t* bbin, uint32_t* bins) {
+                            const uint32_t* nlumc, uint32_t order, uint32_t nscenes,
+                            uint32_t* bbin, uint32_t* bins) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= *nbp) return;
-  const DevTree& T = TT[bscene[b]];
+  const uint32_t sc = bscene[b];
+  const DevTree& T = TT[sc];
   const unsigned long long cost =
       (unsigned long long)bnact[b] * ((unsigned long long)ncnt[b] * (T.nray / 2 + nlumc[b]) + 2000ull);
   const int lg = 63 - __clzll((long long)cost);
-  const uint32_t bin = (uint32_t)(T.B - 1) * kCostBins +
-                       (uint32_t)max(0, (kCostBins - 1) - min(lg, kCostBins - 1));
+  uint32_t key = (uint32_t)max(0, (kCostBins - 1) - min(lg, kCostBins - 1));
+  if (order == ORDER_SCENE) {   // scene groups in input order, heaviest first inside
+    constexpr uint32_t kGroups = kOrderBins / kCostBins;
+    key += (uint32_t)((unsigned long long)sc * kGroups / nscenes) * kCostBins;
+  }
+  const uint32_t bin = (uint32_t)(T.B - 1) * kOrderBins + key;
   bbin[b] = bin;
   atomicAdd(&bins[bin], 1u);
 }
 
-// Exclusive scan of the bins; rng[2 + 2c], rng[3 + 2c] get the range of the
-// buckets with c + 1 bands.
-__global__ void k_bins_scan(uint32_t* bins, uint32_t* rng) {
-  if (threadIdx.x != 0) return;
-  uint32_t run = 0;
-  for (int cl = 0; cl < kMaxBands; ++cl) {
-    rng[2 + 2 * cl] = run;
-    for (int i = 0; i < kCostBins; ++i) {
-      const uint32_t v = bins[cl * kCostBins + i];
-      bins[cl * kCostBins + i] = run;
-      run += v;
-    }
-    rng[3 + 2 * cl] = run;
-  }
+// After the exclusive scan of the bins: rng[2 + 2c], rng[3 + 2c] get the
+// range of the buckets with c + 1 bands.
+__global__ void k_class_ranges(const uint32_t* bins, uint32_t* rng) {
+  const int cl = threadIdx.x;
+  if (cl >= kMaxBands) return;
+  rng[2 + 2 * cl] = bins[cl * kOrderBins];
+  rng[3 + 2 * cl] = cl + 1 < kMaxBands ? bins[(cl + 1) * kOrderBins] : rng[1];
 }
 
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
@@ -891,7 +895,7 @@ Scratch carve_scratch(void* base, int64_t leaves, size_t cut_entries) {
   s.tot = cv.take<unsigned long long>(TOT_N);
   s.ovf = cv.take<uint32_t>(4);
   s.ahash = cv.take<unsigned long long>(2);
-  s.bins = cv.take<uint32_t>(kMaxBands * kCostBins);
+  s.bins = cv.take<uint32_t>(kMaxBands * kOrderBins);
   s.ncnt = cv.take<uint32_t>(L + 1);
   s.tcnt = cv.take<uint32_t>(L + 1);
   s.jcnt = cv.take<uint32_t>(L + 1);
@@ -919,10 +923,11 @@ Scratch carve_scratch(void* base, int64_t leaves, size_t cut_entries) {
 }
 
 Launch tree_launch(const trevr_tree* T) {
-  return Launch{T->stream, T->buf.dev, 1, T->num_nodes, T->n, T->num_leaves, T->stack_large};
+  return Launch{T->stream, T->buf.dev, 1, T->num_nodes, T->n, T->num_leaves, T->stack_large,
+                LaunchCfg{}};
 }
 
-unsigned persistent_grid(const void* fn, int threads, uint64_t items) {
+unsigned persistent_grid(const void* fn, int threads, uint64_t items, uint32_t div) {
   static std::mutex mu;
   static std::unordered_map<const void*, int> occ;
   static std::unordered_map<int, int> cus;
@@ -949,7 +954,7 @@ unsigned persistent_grid(const void* fn, int threads, uint64_t items) {
     }
     ncu = jt->second;
   }
-  const uint64_t slots = (uint64_t)per_cu * (uint64_t)ncu;
+  const uint64_t slots = std::max<uint64_t>(1, (uint64_t)per_cu * (uint64_t)ncu / std::max(div, 1u));
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(items, slots));
 }
 
@@ -1006,22 +1011,24 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
   const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_SETUP};
   if (L.stack_large) {
     const void* fn = (const void*)&k_setup<kStackLarge>;
-    k_setup<kStackLarge><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+    k_setup<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
         L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.ncnt_raw, S.nlumc_raw,
         S.ovf);
   } else {
     const void* fn = (const void*)&k_setup<kStackSmall>;
-    k_setup<kStackSmall><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+    k_setup<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
         L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.ncnt_raw, S.nlumc_raw,
         S.ovf);
   }
   TREVR_LAUNCH_CHECK("k_setup");
   const unsigned gl = grid_of(L.leaves, 256);
   k_cost_bins<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, S.bscene_raw, S.bnact_raw, S.ncnt_raw,
-                                  S.nlumc_raw, S.bbin, S.bins);
+                                  S.nlumc_raw, L.cfg.order, (uint32_t)L.S, S.bbin, S.bins);
   TREVR_LAUNCH_CHECK("k_cost_bins");
-  k_bins_scan<<<1, 64, 0, st>>>(S.bins, S.rng);
-  TREVR_LAUNCH_CHECK("k_bins_scan");
+  k_scan_u32<<<1, 1024, 0, st>>>(S.bins, (int64_t)kMaxBands * kOrderBins, nullptr);
+  TREVR_LAUNCH_CHECK("k_scan_u32");
+  k_class_ranges<<<1, 64, 0, st>>>(S.bins, S.rng);
+  TREVR_LAUNCH_CHECK("k_class_ranges");
   k_reorder<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, S.bbin, S.bins, S.blist_raw, S.bscene_raw,
                                 S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw, S.bprev_raw,
                                 S.blist, S.bscene, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev,
@@ -1107,11 +1114,11 @@ trevr_status near_fill(const Launch& L, const Scratch& S) {
   const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_FILL};
   if (L.stack_large) {
     const void* fn = (const void*)&k_near_fill<kStackLarge>;
-    k_near_fill<kStackLarge><<<persistent_grid(fn, 64, L.leaves), 64, 0, L.st>>>(
+    k_near_fill<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, L.st>>>(
         L.TT, I, S.blist, S.bscene, S.brad, S.ncnt, S.nlumc, S.nidx);
   } else {
     const void* fn = (const void*)&k_near_fill<kStackSmall>;
-    k_near_fill<kStackSmall><<<persistent_grid(fn, 64, L.leaves), 64, 0, L.st>>>(
+    k_near_fill<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, L.st>>>(
         L.TT, I, S.blist, S.bscene, S.brad, S.ncnt, S.nlumc, S.nidx);
   }
   TREVR_LAUNCH_CHECK("k_near_fill");
@@ -1124,11 +1131,11 @@ trevr_status walk_launch(const Launch& L, const Scratch& S, const Items& I, uint
   if ((rc = zero_words(L.st, S.ovf, 2)) != TREVR_OK) return rc;
   if (L.stack_large) {
     const void* fn = (const void*)&k_walk<kStackLarge>;
-    k_walk<kStackLarge><<<persistent_grid(fn, 64, count), 64, 0, L.st>>>(
+    k_walk<kStackLarge><<<persistent_grid(fn, 64, count, L.cfg.grid_div), 64, 0, L.st>>>(
         L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap, S.bstat, S.ovf);
   } else {
     const void* fn = (const void*)&k_walk<kStackSmall>;
-    k_walk<kStackSmall><<<persistent_grid(fn, 64, count), 64, 0, L.st>>>(
+    k_walk<kStackSmall><<<persistent_grid(fn, 64, count, L.cfg.grid_div), 64, 0, L.st>>>(
         L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap, S.bstat, S.ovf);
   }
   TREVR_LAUNCH_CHECK("k_walk");
@@ -1183,8 +1190,8 @@ static trevr_status pp_rays_nb(const Launch& L, const Scratch& S, const Items& I
                                const uint8_t* active) {
   trevr_status rc;
   const void* fn = (const void*)&k_pp_rays<NB>;
-  k_pp_rays<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
-      L.TT, I, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, active, S.tpp);
+  k_pp_rays<NB><<<persistent_grid(fn, kNT, count, L.cfg.grid_div), kNT, 0, L.st>>>(
+      L.TT, I, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, active, S.tpp, L.cfg.pp_sub);
   TREVR_LAUNCH_CHECK("k_pp_rays");
   return rc;
 }
@@ -1194,8 +1201,9 @@ static trevr_status pp_src_nb(const Launch& L, const Scratch& S, const Items& I,
                               const uint8_t* active, double* J) {
   trevr_status rc;
   const void* fn = (const void*)&k_pp_src<NB>;
-  k_pp_src<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
-      L.TT, I, S.blist, S.bscene, S.ncnt, S.nlumc, S.nidx, S.pcnt, active, J, S.ptau);
+  k_pp_src<NB><<<persistent_grid(fn, kNT, count, L.cfg.grid_div), kNT, 0, L.st>>>(
+      L.TT, I, S.blist, S.bscene, S.ncnt, S.nlumc, S.nidx, S.pcnt, active, J, S.ptau,
+      L.cfg.pp_sub);
   TREVR_LAUNCH_CHECK("k_pp_src");
   return rc;
 }
@@ -1205,7 +1213,7 @@ static trevr_status far_nb(const Launch& L, const Scratch& S, const Items& I, ui
                            uint32_t cap, const float* bg, double* J, const uint8_t* active) {
   trevr_status rc;
   const void* fn = (const void*)&k_far<NB>;
-  k_far<NB><<<persistent_grid(fn, kFT, count), kFT, 0, L.st>>>(
+  k_far<NB><<<persistent_grid(fn, kFT, count, L.cfg.grid_div), kFT, 0, L.st>>>(
       L.TT, I, S.blist, S.bscene, S.brad, S.tcnt, S.cut, cap, S.bstat, S.tpp, bg, J, active,
       S.kept_tau, S.kept_tex);
   TREVR_LAUNCH_CHECK("k_far");

@@ -1199,7 +1199,7 @@ static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArg
   {
     const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_PPS_BWD};
     const void* fn = (const void*)&k_pp_src_bwd<NB>;
-    k_pp_src_bwd<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
+    k_pp_src_bwd<NB><<<persistent_grid(fn, kNT, count, L.cfg.grid_div), kNT, 0, L.st>>>(
         L.TT, Ii, S.blist, S.bscene, S.ncnt, S.nlumc, S.nidx, S.jcnt, S.pcnt, S.ptau, a.active,
         a.gJ, a.G, a.jraw);
     TREVR_LAUNCH_CHECK("k_pp_src_bwd");
@@ -1209,7 +1209,7 @@ static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArg
   {
     const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_FAR_BWD};
     const void* fn = (const void*)&k_far_bwd<NB>;
-    k_far_bwd<NB><<<persistent_grid(fn, kFT, count), kFT, 0, L.st>>>(
+    k_far_bwd<NB><<<persistent_grid(fn, kFT, count, L.cfg.grid_div), kFT, 0, L.st>>>(
         L.TT, Ii, S.blist, S.bscene, S.brad, S.tcnt, S.jcnt, S.cut, cap, S.bstat, S.tpp, a.bg,
         a.active, a.gJ, a.jraw, a.gtpp, a.G, a.kept_tau, a.kept_tex);
     TREVR_LAUNCH_CHECK("k_far_bwd");
@@ -1219,7 +1219,7 @@ static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArg
   {
     const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_PPR_BWD};
     const void* fn = (const void*)&k_pp_rays_bwd<NB>;
-    k_pp_rays_bwd<NB><<<persistent_grid(fn, kNT, count), kNT, 0, L.st>>>(
+    k_pp_rays_bwd<NB><<<persistent_grid(fn, kNT, count, L.cfg.grid_div), kNT, 0, L.st>>>(
         L.TT, Ii, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, a.active, a.gtpp, a.G);
     TREVR_LAUNCH_CHECK("k_pp_rays_bwd");
   }
@@ -1249,11 +1249,11 @@ trevr_status bwd_tree_pass(const Launch& L, const Scratch& S, const Grad& G,
   const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_RPP_BWD};
   if (L.stack_large) {
     const void* fn = (const void*)&k_rpp_bwd<kStackLarge>;
-    k_rpp_bwd<kStackLarge><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+    k_rpp_bwd<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
         L.TT, I, S.blist, S.bscene, S.brad, S.bprev, G);
   } else {
     const void* fn = (const void*)&k_rpp_bwd<kStackSmall>;
-    k_rpp_bwd<kStackSmall><<<persistent_grid(fn, 64, L.leaves), 64, 0, st>>>(
+    k_rpp_bwd<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
         L.TT, I, S.blist, S.bscene, S.brad, S.bprev, G);
   }
   TREVR_LAUNCH_CHECK("k_rpp_bwd");

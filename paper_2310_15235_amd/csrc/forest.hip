@@ -53,6 +53,8 @@ struct trevr_forest {
   // the scratch holding the last batched forward state of this forest
   const void* fwd_scratch;
   uint64_t fwd_epoch;
+  trevr::LaunchCfg cfg;                // launch options (trevr_forest_autotune)
+  int32_t cfg_index;
 };
 
 namespace trevr {
@@ -105,7 +107,7 @@ trevr_status forest_layout(const trevr_params* params, int32_t S, const int64_t*
 
 Launch forest_launch(const trevr_forest* f) {
   return Launch{f->stream, f->dtab, f->S, f->max_nodes, f->max_n, f->leaves_total,
-                f->stack_large};
+                f->stack_large, f->cfg};
 }
 
 __global__ void k_zero_counters(const DevTree* __restrict__ TT) {
@@ -194,6 +196,18 @@ trevr_status batched_checks(trevr_forest* f, const float* bg, void* scratch, siz
   if (f->any_bg && !bg) return set_error(TREVR_E_INVALID, "a scene with TREVR_BACKGROUND needs bg");
   if (bytes < need) return set_error(TREVR_E_CAPACITY, "scratch smaller than the forest's plan");
   return TREVR_OK;
+}
+
+// Launch configuration number k of the autotuner's candidates: bit 2 the
+// bucket order (heaviest first / scene by scene), bit 1 the persistent grid
+// (every resident slot / half of them), bit 0 the p-p culling granularity
+// (kSub / kSub / 2 elements per box).
+LaunchCfg config_of(int k) {
+  LaunchCfg c;
+  c.order = (k & 4) ? ORDER_SCENE : ORDER_COST;
+  c.grid_div = (k & 2) ? 2u : 1u;
+  c.pp_sub = (k & 1) ? kSub / 2 : kSub;
+  return c;
 }
 
 }  // namespace
@@ -364,6 +378,8 @@ trevr_status trevr_build_forest(const trevr_params* params, int32_t S, const int
   f->scratch_run = 0;
   f->fwd_scratch = nullptr;
   f->fwd_epoch = 0;
+  f->cfg = LaunchCfg{};
+  f->cfg_index = 0;
   std::memset(f->tot, 0, sizeof(f->tot));
   std::memset(f->class_leaves, 0, sizeof(f->class_leaves));
   {
@@ -521,6 +537,69 @@ trevr_status trevr_forest_get_counters(trevr_forest* f, int32_t scene, trevr_cou
     o->max_stack = std::max(o->max_stack, c.max_stack);
   }
   return TREVR_OK;
+}
+
+trevr_status trevr_forest_set_config(trevr_forest* f, int32_t config) {
+  if (!forest_live(f)) return set_error(TREVR_E_STATE, "unknown or destroyed forest");
+  if (config < 0 || config >= TREVR_FOREST_CONFIGS)
+    return set_error(TREVR_E_INVALID, "configuration out of range");
+  f->cfg = config_of(config);
+  f->cfg_index = config;
+  return TREVR_OK;
+}
+
+trevr_status trevr_forest_get_config(const trevr_forest* f, int32_t* config) {
+  if (!forest_live(f)) return set_error(TREVR_E_STATE, "unknown or destroyed forest");
+  if (!config) return set_error(TREVR_E_INVALID, "NULL output");
+  *config = f->cfg_index;
+  return TREVR_OK;
+}
+
+trevr_status trevr_forest_autotune(trevr_forest* f, const uint8_t* active, const float* bg,
+                                   double* J, const double* gJ, double* gL, double* gkappa,
+                                   double* grho, void* scratch, size_t scratch_bytes,
+                                   void* stream, int32_t reps, double* times) {
+  if (!forest_live(f)) return set_error(TREVR_E_STATE, "unknown or destroyed forest");
+  if (!J) return set_error(TREVR_E_INVALID, "NULL J");
+  const bool adj = gJ != nullptr;
+  if (adj && (!gL || !gkappa || !grho))
+    return set_error(TREVR_E_INVALID, "NULL gradient pointer");
+  trevr_status rc = batched_checks(f, bg, scratch, scratch_bytes, f->scratch_run);
+  if (rc != TREVR_OK) return rc;
+  f->stream = (hipStream_t)stream;
+  reps = std::max(reps, 1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if ((rc = hip_check(he, "hipEventCreate")) != TREVR_OK) return rc;
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int k = 0; k < TREVR_FOREST_CONFIGS && rc == TREVR_OK; ++k) {
+    f->cfg = config_of(k);
+    float ms = 0.0f;
+    for (int r = 0; r <= reps && rc == TREVR_OK; ++r) {   // the first run warms up
+      if (r == 1) he = hipEventRecord(e0, f->stream);
+      rc = forest_compute_impl(f, active, bg, J, scratch);
+      if (rc == TREVR_OK && adj)
+        rc = forest_backward_impl(f, active, bg, gJ, gL, gkappa, grho, scratch);
+    }
+    if (rc != TREVR_OK) break;
+    he = hipEventRecord(e1, f->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if ((rc = hip_check(he, "autotune timing")) != TREVR_OK) break;
+    ms /= (float)reps;
+    if (times) times[k] = ms;
+    if (k == 0 || ms < best_ms) {
+      best = k;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  f->cfg = config_of(best);
+  f->cfg_index = best;
+  return rc;
 }
 
 trevr_status trevr_forest_scene(trevr_forest* f, int32_t scene, trevr_tree** out) {

@@ -21,6 +21,8 @@ template <int SC> __device__ inline int stack_cap(const DevTree& T) {
 enum : uint32_t { OVF_SETUP = 1u, OVF_WALK = 2u };
 constexpr uint32_t kBatch = 65536;   // buckets per launch (bounds the cut-list scratch)
 constexpr int kCostBins = 48;
+constexpr int kOrderBins = 4096;   // counting-sort bins per band count
+enum : uint32_t { ORDER_COST = 0, ORDER_SCENE = 1 };
 constexpr int kNT = 256;         // threads of the near-field kernel
 constexpr int kNChunk = 256;     // p-p elements staged per pass
 constexpr int kNPair = 2;        // (receiver, p-p source) pairs per thread per pass
@@ -251,8 +253,9 @@ struct RecvInfo {
 // ------------------------------------------------------------ near field
 // Particle-particle transfer inside the p-p sphere (Section 2.4), in two
 // kernels of 256 threads per bucket that stage the p-p set through LDS
-// kNChunk elements at a time.  Elements are culled kSub at a time with FP32
-// boxes (each element's position grown by its own size h, plus a margin),
+// kNChunk elements at a time.  Elements are culled kSub (or kSub / 2, a
+// launch option) at a time with FP32 boxes (each element's position grown by
+// its own size h, plus a margin),
 // which is conservative: an element can only absorb on a line that passes
 // within h of it.  Threads are mapped receiver-fastest, so the lines of a
 // wavefront are nearly parallel and skip the same boxes.
@@ -264,8 +267,16 @@ template <int NB> struct NearTile {
   float sig[kNChunk], invh[kNChunk];
   float kap[kNChunk][NB];
   uint32_t slot[kNChunk];
-  float blo[kNSub][3], bhi[kNSub][3];
+  float blo[kNSub][3], bhi[kNSub][3];              // per kSub elements
+  float blo8[2 * kNSub][3], bhi8[2 * kNSub][3];    // per kSub / 2 elements
 };
+
+// Culling boxes of a staged chunk at the granularity `sub` (kSub or kSub / 2).
+template <int NB>
+__device__ inline const float (*near_boxes(const NearTile<NB>& S, int sub, bool hi))[3] {
+  if (sub == kSub) return hi ? S.bhi : S.blo;
+  return hi ? S.bhi8 : S.blo8;
+}
 
 template <int NB>
 __device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint32_t* near,
@@ -286,10 +297,11 @@ __device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint3
     S.slot[t] = l;
   }
   __syncthreads();
-  if (t < kNSub) {
+  if (t < 2 * kNSub) {
+    constexpr int kHalf = kSub / 2;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    const int u1 = min((int)cl, (t + 1) * kSub);
-    for (int u = t * kSub; u < u1; ++u) {
+    const int u1 = min((int)cl, (t + 1) * kHalf);
+    for (int u = t * kHalf; u < u1; ++u) {
       const float h = sqrtf((float)S.h2[u]);
       const float p[3] = {(float)(S.x[u] - c[0]), (float)(S.y[u] - c[1]), (float)(S.z[u] - c[2])};
 #pragma unroll
@@ -300,7 +312,15 @@ __device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint3
       }
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) { S.blo[t][a] = lo[a]; S.bhi[t][a] = hi[a]; }
+    for (int a = 0; a < 3; ++a) { S.blo8[t][a] = lo[a]; S.bhi8[t][a] = hi[a]; }
+  }
+  __syncthreads();
+  if (t < kNSub) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      S.blo[t][a] = fminf(S.blo8[2 * t][a], S.blo8[2 * t + 1][a]);
+      S.bhi[t][a] = fmaxf(S.bhi8[2 * t][a], S.bhi8[2 * t + 1][a]);
+    }
   }
   __syncthreads();
 }

@@ -54,6 +54,15 @@ size_t default_cut_entries(int64_t leaves);
 // Where the launches of a call run: the device table of trees (one per
 // scene), the largest tree (for grids over nodes and elements) and the
 // number of leaves of all scenes (no call has more buckets).
+// Launch options that change speed, never results beyond FP32 rounding of
+// atomic sums: bucket order, persistent workgroups per CU (all that fit,
+// divided by grid_div) and the p-p culling granularity (kSub or kSub / 2).
+struct LaunchCfg {
+  uint32_t order = ORDER_COST;
+  uint32_t grid_div = 1;
+  int pp_sub = kSub;
+};
+
 struct Launch {
   hipStream_t st;
   const DevTree* TT;
@@ -61,12 +70,14 @@ struct Launch {
   int64_t max_nodes, max_n;
   int64_t leaves;
   bool stack_large;
+  LaunchCfg cfg;
 };
 Launch tree_launch(const trevr_tree* T);
 
 // Workgroups of a persistent launch of `fn` (threads each): as many as are
-// resident on the device at once, at most `items`, at least 1.
-unsigned persistent_grid(const void* fn, int threads, uint64_t items);
+// resident on the device at once (divided by div), at most `items`, at
+// least 1.
+unsigned persistent_grid(const void* fn, int threads, uint64_t items, uint32_t div);
 
 trevr_status zero_words(hipStream_t st, void* p, size_t words);
 

@@ -260,3 +260,34 @@ def test_forest_graph_of_forward_and_adjoint():
         for x, y in zip(got[1:], ref[1:]):
             _close(x, y, 1e-5)
     F.close()
+
+
+def test_forest_launch_configurations_agree_and_autotune_picks_one():
+    """Every launch configuration of the autotuner gives the same J (to FP32
+    rounding of atomic sums) and the same gradients; the autotuner times all
+    of them and keeps the fastest."""
+    api = _api()
+    import torch
+    scs = mixed_scenes()
+    F = api.Forest(scs)
+    a = F.flat_active(_actives(scs, 0.5, 21))
+    gJ = torch.as_tensor(np.random.default_rng(4).normal(size=int(F.boff[-1])), device="cuda")
+    ref = None
+    for k in range(api.CONFIGS):
+        F.set_config(k)
+        J = F.compute_J(a).cpu().numpy()
+        g = [t.cpu().numpy() for t in F.compute_J_backward(gJ, a)]
+        F.check()
+        if ref is None:
+            ref = (J, g)
+            continue
+        assert np.max(_rel(J, ref[0])) <= SAME_TOL, k
+        for x, y in zip(g, ref[1]):
+            _close(x, y, 1e-5)
+    chosen, times = F.autotune(a, gJ=gJ, reps=1)
+    F.check()
+    assert 0 <= chosen < api.CONFIGS
+    assert np.all(times > 0) and times[chosen] == times.min()
+    J = F.compute_J(a).cpu().numpy()
+    assert np.max(_rel(J, ref[0])) <= SAME_TOL
+    F.close()
