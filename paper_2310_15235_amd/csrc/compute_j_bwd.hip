@@ -136,7 +136,10 @@ template <int NB> struct PairTile {
   float gt[kNT][NB];
   uint32_t j[kNT];
   uint8_t i[kNT], valid[kNT];
-  float blo[kNT / 16][3], bhi[kNT / 16][3];   // per 16 pairs, relative to the bucket centre
+  // the source of each pair relative to the bucket centre, 1/|.|^2 and the
+  // square of (|.| + the receivers' reach): every receiver's segment to the
+  // source lies within that reach of the centre's segment
+  float jr[kNT][3], jinv[kNT], jlim[kNT];
 };
 
 template <int NB>
@@ -179,6 +182,10 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
     const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
     const int i = t % nrecv;
     const RecvInfo& ri = recv[i];
+    float reach = 0.0f;   // largest receiver distance from the centre
+    for (int k = 0; k < nrecv; ++k)
+      reach = fmaxf(reach, sqrtf(recv[k].rel[0] * recv[k].rel[0] + recv[k].rel[1] * recv[k].rel[1] +
+                                 recv[k].rel[2] * recv[k].rel[2]));
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -220,31 +227,24 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
       PT.xj[t][2] = xj2;
       PT.rij2[t] = rij2;
       PT.inv2[t] = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
+      {
+        const float j0 = (float)(xj0 - c[0]), j1 = (float)(xj1 - c[1]), j2 = (float)(xj2 - c[2]);
+        const float jj = j0 * j0 + j1 * j1 + j2 * j2;
+        const float lim = (sqrtf(jj) + reach) * (1.0f + 1e-5f);
+        PT.jr[t][0] = j0;
+        PT.jr[t][1] = j1;
+        PT.jr[t][2] = j2;
+        PT.jinv[t] = jj > 0.0f ? 1.0f / jj : 0.0f;
+        PT.jlim[t] = lim * lim;
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) PT.gt[t][b] = gt[b];
       PT.j[t] = j;
       PT.i[t] = (uint8_t)i;
       PT.valid[t] = valid ? 1u : 0u;
       __syncthreads();
-      if (t < kNT / 16) {   // segment bounding boxes per 16 pairs
-        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int q = 16 * t; q < 16 * t + 16; ++q) {
-          if (!PT.valid[q]) continue;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const float u = recv[PT.i[q]].rel[a];
-            const float v = (float)(PT.xj[q][a] - c[a]);
-            lo[a] = fminf(lo[a], fminf(u, v));
-            hi[a] = fmaxf(hi[a], fmaxf(u, v));
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          PT.blo[t][a] = lo[a];
-          PT.bhi[t][a] = hi[a];
-        }
-      }
       if (__syncthreads_or(valid)) {
+        const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
         // ---- p-p elements against the staged pairs
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
           const uint32_t u = c0 + (uint32_t)t;
@@ -270,13 +270,25 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
             float ck[NB], gh = 0.0f;
 #pragma unroll
             for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
-            for (int gq = 0; gq < kNT / 16; ++gq) {
-              bool over = true;
-#pragma unroll
-              for (int a = 0; a < 3; ++a)
-                over = over && PT.bhi[gq][a] >= elo[a] && PT.blo[gq][a] <= ehi[a];
-              if (!over) continue;
-              for (int q = 16 * gq; q < 16 * gq + 16; ++q) {
+            // pairs come in runs of nrecv sharing a source: one FP32 test per
+            // run against the centre's segment to the source grown by the
+            // receivers' reach (and the element no farther from the source
+            // than the farthest receiver) before the exact tests of its
+            // receivers
+            for (int q0 = 0; q0 < qend; q0 += nrecv) {
+              {
+                const float s0 = PT.jr[q0][0], s1 = PT.jr[q0][1], s2 = PT.jr[q0][2];
+                const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
+                float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * PT.jinv[q0];
+                tt = fminf(1.0f, fmaxf(0.0f, tt));
+                const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
+                const float rad = (hf + reach) * (1.0f + 1e-5f) +
+                                  1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
+                if (!(f0 * f0 + f1 * f1 + f2 * f2 <= PT.jlim[q0] * (1.0f + 1e-4f) &&
+                      d0 * d0 + d1 * d1 + d2 * d2 <= rad * rad))
+                  continue;
+              }
+              for (int q = q0; q < q0 + nrecv; ++q) {
                 if (!PT.valid[q]) continue;
                 const RecvInfo& rq = recv[PT.i[q]];
                 const double xi0 = rq.x[0], xi1 = rq.x[1], xi2 = rq.x[2];
