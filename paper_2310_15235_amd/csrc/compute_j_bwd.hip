@@ -142,6 +142,19 @@ template <int NB> struct PairTile {
   float jr[kNT][3], jinv[kNT], jlim[kNT];
 };
 
+// Queue of exact-test jobs per wavefront: room for one batch of 64 plus the
+// largest enqueue (64 lanes x kRMax receivers).
+constexpr uint32_t kJobQ = 1024;
+
+// Order LDS writes of some lanes before reads by other lanes of the same
+// wavefront (the lanes execute together; this keeps the compiler and the
+// memory model from reordering across the hand-off).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ TT, Items I,
                                                    const uint32_t* blist, const uint32_t* bscene,
@@ -157,6 +170,9 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
   __shared__ double red[kNT][NB];
   __shared__ double redh[kNT];
+  __shared__ uint16_t jobq[kNT / 64][kJobQ];      // per wavefront: (element lane, pair)
+  __shared__ float eacc[kNT / 64][64][NB + 1];     // per wavefront: element sums
+  const int lane = t & 63, wv = t >> 6;
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -245,80 +261,108 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
       __syncthreads();
       if (__syncthreads_or(valid)) {
         const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
-        // ---- p-p elements against the staged pairs
+        uint16_t* Q = jobq[wv];
+        float (*A)[NB + 1] = eacc[wv];
+        // ---- p-p elements against the staged pairs.  Each lane owns an
+        // element; per source run it tests the element against the centre's
+        // segment to the source grown by the receivers' reach (and the
+        // element no farther from the source than the farthest receiver).
+        // Passing (element, pair) jobs are queued per wavefront and run 64
+        // at a time, so the exact FP64 tests keep every lane busy.
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
           const uint32_t u = c0 + (uint32_t)t;
-          if (u < nnear) {
-            const uint32_t l = near[u];
-            const double ux = (double)T.x[l], uy = (double)T.y[l], uz = (double)T.z[l];
-            const double hl = T.h[l];
-            const double h2 = hl * hl;
-            const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-            const float iv = (float)(1.0 / hl);
-            float kap[NB];
+          const bool has = u < nnear;
+          const uint32_t l = has ? near[u] : near[0];
+          const double ux = (double)T.x[l], uy = (double)T.y[l], uz = (double)T.z[l];
+          const double hl = T.h[l];
+          const double h2 = hl * hl;
+          const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+          const float iv = (float)(1.0 / hl);
+          float kap[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
-            float elo[3], ehi[3];
-            const float hf = (float)hl;
-            const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
+          for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
+          const float hf = (float)hl;
+          const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
+          const float rad = (hf + reach) * (1.0f + 1e-5f) +
+                            1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
+          const float rad2 = rad * rad;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const float m = hf + 1e-5f * (fabsf(pr[a]) + hf);
-              elo[a] = pr[a] - m;
-              ehi[a] = pr[a] + m;
-            }
-            float ck[NB], gh = 0.0f;
+          for (int b = 0; b <= NB; ++b) A[lane][b] = 0.0f;
+          uint32_t head = 0, tail = 0;   // wave-uniform queue cursors
+
+          // one batch of up to 64 queued jobs, job head + lane on this lane
+          auto run_jobs = [&](uint32_t cnt) {
+            const bool mine = (uint32_t)lane < cnt;
+            const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
+            const int L = mine ? (int)(job >> 8) : lane;
+            const int q = (int)(job & 0xFFu);
+            const double vx = __shfl(ux, L), vy = __shfl(uy, L), vz = __shfl(uz, L);
+            const double vh2 = __shfl(h2, L);
+            const float vsig = __shfl(sig, L), viv = __shfl(iv, L);
+            const uint32_t vl = (uint32_t)__shfl((int)l, L);
+            float vkap[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
-            // pairs come in runs of nrecv sharing a source: one FP32 test per
-            // run against the centre's segment to the source grown by the
-            // receivers' reach (and the element no farther from the source
-            // than the farthest receiver) before the exact tests of its
-            // receivers
-            for (int q0 = 0; q0 < qend; q0 += nrecv) {
-              {
-                const float s0 = PT.jr[q0][0], s1 = PT.jr[q0][1], s2 = PT.jr[q0][2];
-                const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
-                float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * PT.jinv[q0];
-                tt = fminf(1.0f, fmaxf(0.0f, tt));
-                const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
-                const float rad = (hf + reach) * (1.0f + 1e-5f) +
-                                  1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
-                if (!(f0 * f0 + f1 * f1 + f2 * f2 <= PT.jlim[q0] * (1.0f + 1e-4f) &&
-                      d0 * d0 + d1 * d1 + d2 * d2 <= rad * rad))
-                  continue;
-              }
-              for (int q = q0; q < q0 + nrecv; ++q) {
-                if (!PT.valid[q]) continue;
-                const RecvInfo& rq = recv[PT.i[q]];
-                const double xi0 = rq.x[0], xi1 = rq.x[1], xi2 = rq.x[2];
-                const double qx0 = PT.xj[q][0], qx1 = PT.xj[q][1], qx2 = PT.xj[q][2];
-                const double e0q = qx0 - xi0, e1q = qx1 - xi1, e2q = qx2 - xi2;
-                const double f0 = ux - qx0, f1 = uy - qx1, f2 = uz - qx2;
-                const double w0 = ux - xi0, w1 = uy - xi1, w2 = uz - xi2;
-                double uu = (w0 * e0q + w1 * e1q + w2 * e2q) * PT.inv2[q];
-                uu = fmin(1.0, fmax(0.0, uu));
-                const double g0 = w0 - uu * e0q, g1 = w1 - uu * e1q, g2 = w2 - uu * e2q;
-                const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-                if ((f0 * f0 + f1 * f1 + f2 * f2 < PT.rij2[q]) && b2 < h2 && l != rq.slot &&
-                    l != PT.j[q]) {
-                  const float bb = sqrtf((float)b2);
-                  const float sg = sig * (1.0f - bb * iv);
-                  const float dsg = sig * iv * (3.0f * bb * iv - 2.0f);
-                  float gqk = 0.0f;
+            for (int b = 0; b < NB; ++b) vkap[b] = __shfl(kap[b], L);
+            if (mine && PT.valid[q]) {
+              const RecvInfo& rq = recv[PT.i[q]];
+              const double xi0 = rq.x[0], xi1 = rq.x[1], xi2 = rq.x[2];
+              const double qx0 = PT.xj[q][0], qx1 = PT.xj[q][1], qx2 = PT.xj[q][2];
+              const double e0q = qx0 - xi0, e1q = qx1 - xi1, e2q = qx2 - xi2;
+              const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
+              const double w0 = vx - xi0, w1 = vy - xi1, w2 = vz - xi2;
+              double uu = (w0 * e0q + w1 * e1q + w2 * e2q) * PT.inv2[q];
+              uu = fmin(1.0, fmax(0.0, uu));
+              const double g0 = w0 - uu * e0q, g1 = w1 - uu * e1q, g2 = w2 - uu * e2q;
+              const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+              if ((f0 * f0 + f1 * f1 + f2 * f2 < PT.rij2[q]) && b2 < vh2 && vl != rq.slot &&
+                  vl != PT.j[q]) {
+                const float bb = sqrtf((float)b2);
+                const float sg = vsig * (1.0f - bb * viv);
+                const float dsg = vsig * viv * (3.0f * bb * viv - 2.0f);
+                float gqk = 0.0f;
 #pragma unroll
-                  for (int b = 0; b < NB; ++b) {
-                    ck[b] += PT.gt[q][b] * sg;
-                    gqk += PT.gt[q][b] * kap[b];
-                  }
-                  gh += gqk * dsg;
+                for (int b = 0; b < NB; ++b) {
+                  atomicAdd(&A[L][b], PT.gt[q][b] * sg);
+                  gqk += PT.gt[q][b] * vkap[b];
                 }
+                atomicAdd(&A[L][NB], gqk * dsg);
               }
             }
-#pragma unroll
-            for (int b = 0; b < NB; ++b) gadd(&G.gk[(int64_t)b * n + l], (double)ck[b]);
-            gadd(&G.gh[l], (double)gh);
+          };
+
+          for (int q0 = 0; q0 < qend; q0 += nrecv) {
+            bool pass = false;
+            if (has) {
+              const float s0 = PT.jr[q0][0], s1 = PT.jr[q0][1], s2 = PT.jr[q0][2];
+              const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
+              float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * PT.jinv[q0];
+              tt = fminf(1.0f, fmaxf(0.0f, tt));
+              const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
+              pass = f0 * f0 + f1 * f1 + f2 * f2 <= PT.jlim[q0] * (1.0f + 1e-4f) &&
+                     d0 * d0 + d1 * d1 + d2 * d2 <= rad2;
+            }
+            const uint64_t m = ballot64(pass);
+            if (m == 0ull) continue;
+            if (pass) {
+              const uint32_t pos = tail + (uint32_t)mbcnt(m) * (uint32_t)nrecv;
+              for (int k = 0; k < nrecv; ++k)
+                Q[(pos + (uint32_t)k) & (kJobQ - 1)] = (uint16_t)((lane << 8) | (q0 + k));
+            }
+            tail += (uint32_t)__popcll(m) * (uint32_t)nrecv;
+            wave_lds_sync();
+            while (tail - head >= 64u) {
+              run_jobs(64u);
+              head += 64u;
+            }
           }
+          if (tail > head) run_jobs(tail - head);
+          wave_lds_sync();
+          if (has) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) gadd(&G.gk[(int64_t)b * n + l], (double)A[lane][b]);
+            gadd(&G.gh[l], (double)A[lane][NB]);
+          }
+          wave_lds_sync();
         }
       }
       __syncthreads();
