@@ -146,15 +146,6 @@ template <int NB> struct PairTile {
 // largest enqueue (64 lanes x kRMax receivers).
 constexpr uint32_t kJobQ = 1024;
 
-// Order LDS writes of some lanes before reads by other lanes of the same
-// wavefront (the lanes execute together; this keeps the compiler and the
-// memory model from reordering across the hand-off).
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ TT, Items I,
                                                    const uint32_t* blist, const uint32_t* bscene,

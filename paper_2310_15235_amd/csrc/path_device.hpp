@@ -71,6 +71,15 @@ __device__ inline uint32_t next_item(const Items& I, uint32_t* s_item) {
 enum { Q_SETUP = 0, Q_FILL, Q_WALK, Q_PPR, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD,
        Q_RPP_BWD, Q_N };
 
+// Order LDS writes of some lanes before reads by other lanes of the same
+// wavefront (the lanes execute together; this keeps the compiler and the
+// memory model from reordering across the hand-off).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline void atomic_max_u64(unsigned long long* a, unsigned long long v) {
   atomicMax(a, v);
 }
