@@ -192,6 +192,22 @@ def batched_bench(args, dev):
     }
 
 
+def measured_counters(kernel: str):
+    """VALU issue utilisation, L2 hit rate and LDS figures of `kernel` from
+    the committed rocprofv3 counter runs (profiles/), or None when the kernel
+    source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_clumpy2e18_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return {k: rec[k] for k in ("valu_issue_util", "l2_hit_rate", "lds_instr_per_valu",
+                                "lds_bank_conflicts_per_lds_instr")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +324,7 @@ def main():
                 "achieved": achieved,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                 "traffic": measured_traffic(kernel),
+                "counters": measured_counters(kernel),
                 "launches_per_step": red_calls / args.steps,
                 "avg_launch_ms": red_ms / max(red_calls, 1),
                 "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
