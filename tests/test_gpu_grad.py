@@ -256,3 +256,48 @@ def test_adjoint_with_large_stack_and_short_cut_lists():
         T.close()
     for u, v in zip(*out):
         _close(u, v, 1e-5)
+
+
+@pytest.mark.parametrize("which", ["kappa", "rho", "lum"])
+def test_adjoint_against_central_differences_on_the_small_copy(which):
+    """The differentiation workload's 2^12-element copy (2 bands, N_side 2):
+    the GPU adjoint of E = <w, J> against FP64 central differences of the
+    oracle with relative step 1e-6 along x (1 + h v), the counted discrete
+    decisions unmoved within the step.  J components at a kink of the map --
+    a column profile where an impact parameter meets an element's size, or a
+    maximum with a tie (the p-p radius rule max h/w: elements of one grid
+    cell of the log-normal medium share rho and m, hence h), where the
+    frozen-decision derivative takes the first tied element's slope and a
+    central difference their mean -- have different one-sided quotients;
+    they are skipped (weight zero) and counted."""
+    api = _api()
+    sc = scenes.config_differentiation_small()
+    act = np.ones(sc.n, np.uint8)
+    rng = np.random.default_rng({"kappa": 11, "rho": 12, "lum": 13}[which])
+    w = rng.normal(size=(sc.n_bands, sc.n))
+    base = dict(lum=sc.lum.astype(np.float64), kappa=sc.kappa.astype(np.float64),
+                rho=sc.rho.astype(np.float64))
+    v = rng.normal(size=base[which].shape)
+    eps = 1e-6
+    Js, cnt = [], []
+    for sgn in (+1, 0, -1):
+        kw = dict(base)
+        kw[which] = base[which] * (1.0 + sgn * eps * v)
+        J, _, c = oracle.jvp(sc, active=act, **kw)
+        Js.append(J)
+        cnt.append(c)
+    assert cnt[0] == cnt[1] == cnt[2], "a counted decision moved within the step"
+    right, left = (Js[0] - Js[1]) / eps, (Js[1] - Js[2]) / eps
+    central = (Js[0] - Js[2]) / (2 * eps)
+    den = np.maximum(np.abs(central), 1e-3 * np.abs(central).max(axis=1, keepdims=True))
+    kink = np.abs(right - left) / den > 1e-4
+    assert kink.mean() < 0.25, kink.mean()
+    w[kink] = 0.0
+    gL, gk, gr = api.compute_J_backward(sc, w, active=act)
+    g = {"lum": gL, "kappa": gk, "rho": gr}[which]
+    terms = g * base[which] * v
+    lhs = float(np.sum(terms))
+    rhs = float(np.sum(w * central))
+    scale = max(float(np.sum(np.abs(terms))), float(np.sum(np.abs(w * central))))
+    print(f"{which}: {int(kink.sum())} of {kink.size} components at a kink skipped")
+    assert abs(lhs - rhs) <= 1e-4 * scale, (lhs, rhs, scale, int(kink.sum()))

@@ -177,6 +177,32 @@ def test_J_clumpy_full_size_sampled():
     compare_J(sc, active=act)
 
 
+@pytest.mark.parametrize("frac", [0.01, 0.1, 1.0])
+def test_J_diffuse_full_size_sampled(frac):
+    """2^21 elements of the off-centre isothermal sphere, every element
+    emitting, background, N_side 4, 1%, 10% or 100% active on the GPU.  J of
+    a receiver does not depend on which other elements are active (p-p radii
+    are set by all bucket members), so the oracle evaluates about 2,000 of
+    those receivers and they are compared one by one."""
+    api = _gpu()
+    import torch
+    sc = scenes.config_diffuse(active_frac=frac)
+    act = sc.active
+    T = api.Tree.from_scene(sc)
+    a = torch.as_tensor(np.ascontiguousarray(act, np.uint8), device="cuda")
+    bg = torch.as_tensor(np.ascontiguousarray(sc.bg, np.float32), device="cuda")
+    Jg = T.compute_J(a, bg).cpu().numpy()
+    T.check()
+    T.close()
+    rng = np.random.default_rng(31)
+    idx = np.flatnonzero(act)
+    sub = np.zeros(sc.n, np.uint8)
+    sub[rng.choice(idx, size=min(idx.size, 2048), replace=False)] = 1
+    Jo, _ = oracle.OracleTree(sc).compute_J(sub)
+    e = jerr(Jg, Jo, sub.astype(bool))
+    assert e.max() < J_TOL, e.max()
+
+
 # ------------------------------------------ buffers that need more room
 def test_J_cut_lists_longer_than_the_default():
     """A small opening angle opens nearly every cell, so each bucket's cut
