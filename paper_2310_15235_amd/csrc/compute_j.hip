@@ -571,6 +571,7 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s, wcnt[kFT / 64], abs_count, s_item;
   __shared__ double red[kFT / 64][kRMax][NB];
+  __shared__ uint32_t hitq[kFT / 64][kHitQ];   // per wavefront: queued (entry, ray) tests
 
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
@@ -642,7 +643,7 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
         // sorted by distance).  The LDS atomics make the FP32 sums depend on
         // the order of the hits at the level of rounding.
         uint32_t nabs = 0;
-        for_each_hit_lane(T, mycut, ncut, c, r, kn, G,
+        for_each_hit_queued(T, mycut, ncut, c, r, kn, G, hitq[wv],
                           [&](uint32_t node, int kq, double ht0, double ht1, bool) {
           const float len = (float)(ht1 - ht0);
           const float* al = &T.alpha[((int64_t)node * T.nclass + G.cls[kq]) * NB];

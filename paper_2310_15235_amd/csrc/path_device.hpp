@@ -604,6 +604,83 @@ __device__ inline void for_each_hit_lane(const DevTree& T, const uint2* mycut, u
   }
 }
 
+// The same hits, queued: for light callbacks (the forward's), where lanes
+// with few candidate rays would otherwise wait for the busiest.  No workgroup
+// barriers: threads take the cut entries in turn; for each ray of the group
+// the conservative FP32 bounding-sphere test marks the thread's entry as a
+// candidate, candidates are queued per wavefront in Q (kHitQ words) and run
+// 64 at a time, one per lane: the exact FP64 ray-box test keeps those that
+// meet the cell beyond the p-p sphere and that lane calls on_hit(node, ray,
+// t0, t1, clipped) with t0 = max(t_in, r), clipped = (t_in < r).  Hits of
+// one ray arrive from many lanes in no fixed order, so on_hit must update
+// shared state atomically.
+constexpr uint32_t kHitQ = 128;   // one batch of 64 plus one step's 64
+
+template <class F>
+__device__ inline void for_each_hit_queued(const DevTree& T, const uint2* mycut, uint32_t ncut,
+                                           const double c[3], double r, int kn, const RayGroup& G,
+                                           uint32_t* Q, F&& on_hit) {
+  const int lane = threadIdx.x & 63;
+  uint32_t head = 0, tail = 0;   // wave-uniform queue cursors
+  auto run = [&](uint32_t cnt) {
+    if ((uint32_t)lane < cnt) {
+      const uint32_t job = Q[(head + (uint32_t)lane) & (kHitQ - 1)];
+      const uint32_t e = job >> 6;
+      const int kq = (int)(job & 63u);
+      const uint32_t node = mycut[e].x;
+      double lo[3], hi[3];
+      node_box(T.hdr, T.nk[node], lo, hi);
+      double tin, tout;
+      if (slab(lo, hi, c, G.n[kq], G.inv[kq], tin, tout) && tout > fmax(tin, r))
+        on_hit(node, kq, fmax(tin, r), tout, tin < r);
+    }
+  };
+  const uint32_t rounds = (ncut + kFT - 1) / kFT;
+  for (uint32_t rd = 0; rd < rounds; ++rd) {
+    const uint32_t e = rd * kFT + threadIdx.x;
+    bool live = false, every = false;
+    float mc[3] = {0.0f, 0.0f, 0.0f}, thr = 0.0f;
+    if (e < ncut) {
+      const uint2 ent = mycut[e];
+      if (ent.y & CUT_ABS) {
+        live = true;
+        double lo[3], hi[3];
+        node_box(T.hdr, T.nk[ent.x], lo, hi);
+        float R2 = 0.0f, D2 = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          mc[a] = (float)(0.5 * (lo[a] + hi[a]) - c[a]);
+          const float hx = (float)(0.5 * (hi[a] - lo[a]));
+          R2 += hx * hx;
+          D2 += mc[a] * mc[a];
+        }
+        const float marg = 1e-5f * D2 + 1e-30f;
+        every = !(D2 - R2 > marg);   // the centre may be inside: every ray
+        thr = D2 - R2 - marg;
+      }
+    }
+    if (ballot64(live) == 0ull) continue;
+    for (int kq = 0; kq < kn; ++kq) {
+      bool cand = false;
+      if (live) {
+        const float nm = G.nf[kq][0] * mc[0] + G.nf[kq][1] * mc[1] + G.nf[kq][2] * mc[2];
+        cand = every || (nm > 0.0f && nm * nm >= thr);
+      }
+      const uint64_t m = ballot64(cand);
+      if (m == 0ull) continue;
+      if (cand) Q[(tail + (uint32_t)mbcnt(m)) & (kHitQ - 1)] = (e << 6) | (uint32_t)kq;
+      tail += (uint32_t)__popcll(m);
+      wave_lds_sync();
+      if (tail - head >= 64u) {
+        run(64u);
+        head += 64u;
+        wave_lds_sync();
+      }
+    }
+  }
+  if (tail > head) run(tail - head);
+}
+
 // Gradient accumulators (sorted slots / preorder nodes), FP64.
 struct Grad {
   double* gL;       // [B][n]
