@@ -88,13 +88,14 @@ __global__ void k_active_hash(const DevTree* __restrict__ TT, const uint8_t* act
 // p-p radius (Section 2.4): past every bucket member by its size, then grown
 // until no element inside is wider than the beam there (w r).  One
 // wavefront per bucket.
-// Also records the radius before the last growth (-1 if it never grew),
-// which tells the adjoint which element set the final radius.
+// Also records the radius before the last growth (-1 if it never grew) and
+// the element whose size set the final radius by that growth (the smallest
+// sorted slot among equal sizes), for the adjoint.
 template <int SC>
 __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, Items I,
                                               const uint32_t* blist, const uint32_t* bscene,
-                                              double* brad, double* bprev, uint32_t* ncnt,
-                                              uint32_t* nlumc, uint32_t* ovf) {
+                                              double* brad, double* bprev, uint32_t* barg,
+                                              uint32_t* ncnt, uint32_t* nlumc, uint32_t* ovf) {
   __shared__ uint32_t stack[SC];
   __shared__ uint32_t s_item;
   const int lane = threadIdx.x;
@@ -106,7 +107,7 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
   double c[3];
   leaf_centre(T, leaf, c);
   double r = 0.0, rprev = -1.0;
-  uint32_t cnt = 0, nlum = 0;
+  uint32_t cnt = 0, nlum = 0, arg = 0xFFFFFFFFu;
   bool overflow = false;
   if (T.flags & TREVR_NEAR_FIELD) {
     r = T.rpp_min;
@@ -117,16 +118,20 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
     r = fmax(r, wave_max(rm));
     for (;;) {
       double hm = 0.0;
-      cnt = wave_near(T, c, r * r, stack, stack_cap<SC>(T), &hm, &nlum, nullptr, 0, &overflow);
+      uint32_t ha = 0xFFFFFFFFu;
+      cnt = wave_near(T, c, r * r, stack, stack_cap<SC>(T), &hm, &nlum, nullptr, 0, &overflow,
+                      &ha);
       const double rn = fmax(r, hm / T.wbeam);
       if (!(rn > r) || overflow) break;
       rprev = r;
       r = rn;
+      arg = ha;   // the widest element inside the sphere set the new radius
     }
   }
   if (lane == 0) {
     brad[b] = r;
     bprev[b] = rprev;
+    barg[b] = arg;
     ncnt[b] = cnt;
     nlumc[b] = nlum;
     if (overflow) atomicOr(ovf, OVF_SETUP);
@@ -782,12 +787,26 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
 // instead of forming the tail of a launch; or (ORDER_SCENE) scene by scene,
 // heaviest first within each, which keeps a scene's tree in the caches.
 // Each bucket's result is independent of its position.
-__global__ void k_cost_bins(const DevTree* __restrict__ TT, const uint32_t* nbp,
-                            const uint32_t* bscene, const uint32_t* bnact, const uint32_t* ncnt,
-                            const uint32_t* nlumc, uint32_t order, uint32_t nscenes,
-                            uint32_t* bbin, uint32_t* bins) {
+// Heaviest-first order bins, counted per workgroup in LDS (one global add
+// per workgroup and bin) so the few hot bins are not serialised.
+constexpr int kLocalBins = kMaxBands * kCostBins;
+__device__ inline int local_bin(uint32_t bin) {
+  return (int)(bin / kOrderBins) * kCostBins + (int)(bin % kOrderBins);
+}
+
+__global__ void __launch_bounds__(256) k_cost_bins(const DevTree* __restrict__ TT,
+                                                   const uint32_t* nbp, const uint32_t* bscene,
+                                                   const uint32_t* bnact, const uint32_t* ncnt,
+                                                   const uint32_t* nlumc, uint32_t order,
+                                                   uint32_t nscenes, uint32_t* bbin,
+                                                   uint32_t* bins) {
+  __shared__ uint32_t lcnt[kLocalBins];
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= *nbp) return;
+  const bool local = order == ORDER_COST;
+  if (local)
+    for (int i = threadIdx.x; i < kLocalBins; i += blockDim.x) lcnt[i] = 0u;
+  __syncthreads();
+  if (b < *nbp) {
   const uint32_t sc = bscene[b];
   const DevTree& T = TT[sc];
   const unsigned long long cost =
@@ -800,7 +819,14 @@ __global__ void k_cost_bins(const DevTree* __restrict__ TT, const uint32_t* nbp,
   }
   const uint32_t bin = (uint32_t)(T.B - 1) * kOrderBins + key;
   bbin[b] = bin;
-  atomicAdd(&bins[bin], 1u);
+  if (local) atomicAdd(&lcnt[local_bin(bin)], 1u);
+  else atomicAdd(&bins[bin], 1u);
+  }
+  if (local) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < kLocalBins; i += blockDim.x)
+      if (lcnt[i]) atomicAdd(&bins[(i / kCostBins) * kOrderBins + i % kCostBins], lcnt[i]);
+  }
 }
 
 // After the exclusive scan of the bins: rng[2 + 2c], rng[3 + 2c] get the
@@ -823,17 +849,35 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 // words of the adjoint (jcnt = receivers x bands) and (receiver, luminous p-p
 // element) pair floats (pcnt = receivers x luminous x bands); their 64-bit
 // totals go to tot[0..3], the receivers to tot[4].
-__global__ void k_reorder(const DevTree* __restrict__ TT, const uint32_t* nbp,
-                          const uint32_t* bbin, uint32_t* bins, const uint32_t* blist,
+__global__ void __launch_bounds__(256) k_reorder(const DevTree* __restrict__ TT,
+                                                 const uint32_t* nbp, uint32_t order,
+                                                 const uint32_t* bbin, uint32_t* bins,
+                                                 const uint32_t* blist,
                           const uint32_t* bscene, const uint32_t* bnact, const uint32_t* ncnt,
                           const uint32_t* nlumc, const double* brad, const double* bprev,
-                          uint32_t* blist2, uint32_t* bscene2, uint32_t* bnact2, uint32_t* ncnt2,
-                          uint32_t* nlumc2, double* brad2, double* bprev2, uint32_t* tcnt2,
+                          const uint32_t* barg, uint32_t* blist2, uint32_t* bscene2,
+                          uint32_t* bnact2, uint32_t* ncnt2, uint32_t* nlumc2, double* brad2,
+                          double* bprev2, uint32_t* barg2, uint32_t* tcnt2,
                           uint32_t* jcnt2, uint32_t* pcnt2, unsigned long long* tot) {
+  __shared__ uint32_t lcnt[kLocalBins], lbase[kLocalBins];
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool local = order == ORDER_COST;
+  const bool valid = b < *nbp;
+  // positions: a rank within the workgroup's share of each bin, that share
+  // reserved with one global add per bin
+  uint32_t rank = 0u;
+  if (local) {
+    for (int i = threadIdx.x; i < kLocalBins; i += blockDim.x) lcnt[i] = 0u;
+    __syncthreads();
+    if (valid) rank = atomicAdd(&lcnt[local_bin(bbin[b])], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kLocalBins; i += blockDim.x)
+      if (lcnt[i]) lbase[i] = atomicAdd(&bins[(i / kCostBins) * kOrderBins + i % kCostBins], lcnt[i]);
+    __syncthreads();
+  }
   unsigned long long v[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
-  if (b < *nbp) {
-    const uint32_t pos = atomicAdd(&bins[bbin[b]], 1u);
+  if (valid) {
+    const uint32_t pos = local ? lbase[local_bin(bbin[b])] + rank : atomicAdd(&bins[bbin[b]], 1u);
     const uint32_t sc = bscene[b];
     const DevTree& T = TT[sc];
     const uint32_t na = bnact[b], B = (uint32_t)T.B;
@@ -844,6 +888,7 @@ __global__ void k_reorder(const DevTree* __restrict__ TT, const uint32_t* nbp,
     nlumc2[pos] = nlumc[b];
     brad2[pos] = brad[b];
     bprev2[pos] = bprev[b];
+    barg2[pos] = barg[b];
     tcnt2[pos] = na * (uint32_t)T.nray * B;
     jcnt2[pos] = na * B;
     pcnt2[pos] = na * nlumc[b] * B;
@@ -909,6 +954,7 @@ Scratch carve_scratch(void* base, int64_t leaves, size_t cut_entries) {
   s.bstat = cv.take<uint32_t>(4 * L);
   s.brad = cv.take<double>(L);
   s.bprev = cv.take<double>(L);
+  s.barg = cv.take<uint32_t>(L);
   s.blist_raw = cv.take<uint32_t>(L);
   s.bscene_raw = cv.take<uint32_t>(L);
   s.bnact_raw = cv.take<uint32_t>(L);
@@ -917,6 +963,7 @@ Scratch carve_scratch(void* base, int64_t leaves, size_t cut_entries) {
   s.bbin = cv.take<uint32_t>(L);
   s.brad_raw = cv.take<double>(L);
   s.bprev_raw = cv.take<double>(L);
+  s.barg_raw = cv.take<uint32_t>(L);
   s.cut_entries = cut_entries;
   s.cut = cv.take<uint2>(cut_entries);
   s.fixed = ((cv.off + 255) & ~(size_t)255) + 256;   // 256-aligned
@@ -1013,13 +1060,13 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
   if (L.stack_large) {
     const void* fn = (const void*)&k_setup<kStackLarge>;
     k_setup<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
-        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.ncnt_raw, S.nlumc_raw,
-        S.ovf);
+        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.barg_raw, S.ncnt_raw,
+        S.nlumc_raw, S.ovf);
   } else {
     const void* fn = (const void*)&k_setup<kStackSmall>;
     k_setup<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
-        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.ncnt_raw, S.nlumc_raw,
-        S.ovf);
+        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.barg_raw, S.ncnt_raw,
+        S.nlumc_raw, S.ovf);
   }
   TREVR_LAUNCH_CHECK("k_setup");
   const unsigned gl = grid_of(L.leaves, 256);
@@ -1030,10 +1077,11 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
   TREVR_LAUNCH_CHECK("k_scan_u32");
   k_class_ranges<<<1, 64, 0, st>>>(S.bins, S.rng);
   TREVR_LAUNCH_CHECK("k_class_ranges");
-  k_reorder<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, S.bbin, S.bins, S.blist_raw, S.bscene_raw,
+  k_reorder<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, L.cfg.order, S.bbin, S.bins, S.blist_raw,
+                                S.bscene_raw,
                                 S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw, S.bprev_raw,
-                                S.blist, S.bscene, S.bnact, S.ncnt, S.nlumc, S.brad, S.bprev,
-                                S.tcnt, S.jcnt, S.pcnt, S.tot);
+                                S.barg_raw, S.blist, S.bscene, S.bnact, S.ncnt, S.nlumc, S.brad,
+                                S.bprev, S.barg, S.tcnt, S.jcnt, S.pcnt, S.tot);
   TREVR_LAUNCH_CHECK("k_reorder");
   const int64_t Lp = std::max<int64_t>(L.leaves, 1) + 1;
   for (uint32_t* a : {S.ncnt, S.tcnt, S.jcnt, S.pcnt}) {

@@ -954,114 +954,38 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
 // The p-p radius is a maximum (Section 2.4): of rpp_min and the members'
 // reach |x_s - c| + h_s, then of the beam rule h_j / w while the sphere
 // grows.  Its adjoint goes to the h of the element that set it: the first
-// in sorted order among equal values, and for the beam rule one inside the
-// sphere of the round that set the final radius.
-__device__ inline uint32_t wave_min_u(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
-  return v;
-}
-
-// Smallest sorted slot among elements strictly within sqrt(r2) of c with
-// h / w == target (one wavefront; stack of cap words in LDS).
-__device__ inline uint32_t wave_near_argbeam(const DevTree& T, const double c[3], double r2,
-                                             double target, uint32_t* stack, int cap,
-                                             bool* overflow) {
-  const int lane = threadIdx.x & 63;
-  const double prune = r2 * (1.0 + 1e-9);
-  uint32_t best = 0xFFFFFFFFu;
-  int sp = 1;
-  if (lane == 0) stack[0] = 0u;
-  __syncthreads();
-  while (sp > 0) {
-    const int take = min(sp, 64);
-    sp -= take;
-    const bool valid = lane < take;
-    const uint32_t node = valid ? stack[sp + lane] : 0u;
-    __syncthreads();
-    bool push = false;
-    uint2 lk = make_uint2(0, 0);
-    if (valid) {
-      const uint4 nk = T.nk[node];
-      double lo[3], hi[3];
-      node_box(T.hdr, nk, lo, hi);
-      if (!(dist2_box(lo, hi, c) > prune)) {
-        lk = T.nlink[node];
-        if (nk.w & META_LEAF) {
-          for (uint32_t s = lk.x; s < lk.x + lk.y; ++s)
-            if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2 &&
-                T.h[s] / T.wbeam == target)
-              best = min(best, s);
-        } else {
-          push = true;
-        }
-      }
-    }
-    const uint64_t pm = ballot64(push);
-    const int npush = __popcll(pm);
-    if (sp + 2 * npush > cap) {
-      *overflow = true;
-      break;
-    }
-    if (push) {
-      const int ppos = mbcnt(pm);
-      stack[sp + 2 * ppos] = lk.x;
-      stack[sp + 2 * ppos + 1] = node + 1u;
-    }
-    sp += 2 * npush;
-    __syncthreads();
-  }
-  return wave_min_u(best);
-}
-
-// (The sphere before the last growth is inside the final one, so the stack
-// that sufficed for the p-p radius suffices here.)
-template <int SC>
-__global__ void __launch_bounds__(64) k_rpp_bwd(const DevTree* __restrict__ TT, Items I,
-                                                const uint32_t* blist, const uint32_t* bscene,
-                                                const double* brad, const double* bprev,
-                                                Grad Gall) {
-  __shared__ uint32_t stack[SC];
-  __shared__ uint32_t s_item;
-  const int lane = threadIdx.x;
-  for (;;) {
-  const uint32_t b = next_item(I, &s_item);
-  if (b == kNoItem) break;
-  const DevTree& T = TT[bscene[b]];
-  if (!(T.flags & TREVR_NEAR_FIELD)) continue;
+// in sorted order among equal values; for the beam rule the setup recorded
+// that element (inside the sphere of the round that set the final radius).
+// One thread per bucket (the work per bucket is a few loads).
+__global__ void k_rpp_bwd(const DevTree* __restrict__ TT, const uint32_t* nbp,
+                          const uint32_t* blist, const uint32_t* bscene, const double* bprev,
+                          const uint32_t* barg, Grad Gall) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= *nbp) return;
   const double g = Gall.grpp[b];
-  if (g == 0.0) continue;
+  if (g == 0.0) return;
+  const DevTree& T = TT[bscene[b]];
+  if (!(T.flags & TREVR_NEAR_FIELD)) return;
   const Grad G = Gall.at(T);
-  const double r = brad[b], rprev = bprev[b];
+  if (bprev[b] >= 0.0) {   // the beam rule of the last growth
+    if (barg[b] != 0xFFFFFFFFu) gadd(&G.gh[barg[b]], g / T.wbeam);
+    return;
+  }
+  // never grew: the largest member reach |x - c| + h, first slot attaining
+  // it, unless rpp_min was larger
   double c[3];
   leaf_centre(T, blist[b], c);
-  uint32_t src = 0xFFFFFFFFu;
-  double fac = 1.0;
-  bool overflow = false;
-  if (rprev < 0.0) {
-    // never grew: the largest member reach |x - c| + h, first slot
-    // attaining it (lanes visit their slots in increasing order, so a
-    // strict test keeps the first), unless rpp_min was larger
-    const uint2 lk = T.nlink[blist[b]];
-    double rm = -INFINITY;
-    uint32_t arg = 0xFFFFFFFFu;
-    for (uint32_t s = lk.x + lane; s < lk.x + lk.y; s += 64) {
-      const double v = sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s];
-      if (v > rm) {
-        rm = v;
-        arg = s;
-      }
+  const uint2 lk = T.nlink[blist[b]];
+  double rm = -INFINITY;
+  uint32_t arg = 0xFFFFFFFFu;
+  for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
+    const double v = sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s];
+    if (v > rm) {
+      rm = v;
+      arg = s;
     }
-    const double rmax = wave_max(rm);
-    const uint32_t marg = wave_min_u(rm == rmax ? arg : 0xFFFFFFFFu);
-    if (rmax > T.rpp_min) src = marg;
-  } else {
-    // the beam rule of the last growth, over the sphere before it
-    src = wave_near_argbeam(T, c, rprev * rprev, r, stack, stack_cap<SC>(T), &overflow);
-    fac = 1.0 / T.wbeam;
   }
-  if (lane == 0 && src != 0xFFFFFFFFu && !overflow) gadd(&G.gh[src], g * fac);
-  }
+  if (rm > T.rpp_min && arg != 0xFFFFFFFFu) gadd(&G.gh[arg], g);
 }
 
 // ------------------------------------------------------------ the tree
@@ -1293,16 +1217,8 @@ trevr_status bwd_tree_pass(const Launch& L, const Scratch& S, const Grad& G,
                            double* grho) {
   hipStream_t st = L.st;
   trevr_status rc;
-  const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_RPP_BWD};
-  if (L.stack_large) {
-    const void* fn = (const void*)&k_rpp_bwd<kStackLarge>;
-    k_rpp_bwd<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
-        L.TT, I, S.blist, S.bscene, S.brad, S.bprev, G);
-  } else {
-    const void* fn = (const void*)&k_rpp_bwd<kStackSmall>;
-    k_rpp_bwd<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
-        L.TT, I, S.blist, S.bscene, S.brad, S.bprev, G);
-  }
+  k_rpp_bwd<<<grid_of(L.leaves, 256), 256, 0, st>>>(L.TT, S.rng + 1, S.blist, S.bscene,
+                                                     S.bprev, S.barg, G);
   TREVR_LAUNCH_CHECK("k_rpp_bwd");
   if (G.ka > 1) {
     k_sum_copies<<<grid_of(G.na, 256), 256, 0, st>>>(G.galpha, G.na, G.ka);

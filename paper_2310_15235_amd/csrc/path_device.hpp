@@ -68,8 +68,7 @@ __device__ inline uint32_t next_item(const Items& I, uint32_t* s_item) {
 }
 
 // Queue counter pairs of a scratch, one per item kernel.
-enum { Q_SETUP = 0, Q_FILL, Q_WALK, Q_PPR, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD,
-       Q_RPP_BWD, Q_N };
+enum { Q_SETUP = 0, Q_FILL, Q_WALK, Q_PPR, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD, Q_N };
 
 // Order LDS writes of some lanes before reads by other lanes of the same
 // wavefront (the lanes execute together; this keeps the compiler and the
@@ -93,6 +92,11 @@ __device__ inline void leaf_centre(const DevTree& T, uint32_t leaf, double c[3])
 __device__ inline double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline uint32_t wave_min_u(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
   return v;
 }
 __device__ inline double wave_sum(double v) {
@@ -124,10 +128,10 @@ __device__ inline uint32_t wave_excl(uint32_t v, int lane) {
 // the exact test.  The traversal stack lives in `stack` (cap words).
 __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double r2, uint32_t* stack,
                                      int cap, double* hmax, uint32_t* nlum, uint32_t* out,
-                                     uint32_t lum_total, bool* overflow) {
+                                     uint32_t lum_total, bool* overflow, uint32_t* harg = nullptr) {
   const int lane = threadIdx.x & 63;
   const double prune = r2 * (1.0 + 1e-9);
-  uint32_t cnt = 0, lum = 0;
+  uint32_t cnt = 0, lum = 0, ha = 0xFFFFFFFFu;
   double hm = 0.0;
   int sp = 1, maxsp = 1;
   if (lane == 0) stack[0] = 0u;
@@ -154,7 +158,11 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
           for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
             if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
               ++mine;
-              hm = fmax(hm, T.h[s]);
+              const double hs = T.h[s];
+              if (hs > hm || (hs == hm && s < ha)) {   // smallest slot among equal sizes
+                hm = hs;
+                ha = s;
+              }
               if (T.lbol[s] > 0.0) ++mylum;
             }
           }
@@ -192,7 +200,9 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
     __syncthreads();
   }
   if (lane == 0) atomic_max_u64(&T.counters[CNT_MAX_STACK], (unsigned long long)maxsp);
-  if (hmax) *hmax = wave_max(hm);
+  const double hw = wave_max(hm);
+  if (hmax) *hmax = hw;
+  if (harg) *harg = wave_min_u(hm == hw ? ha : 0xFFFFFFFFu);
   if (nlum) *nlum = lum;
   return cnt;
 }

@@ -31,8 +31,9 @@ struct Scratch {
   // processing order
   uint32_t *blist, *bscene, *bnact, *nlumc, *bstat;
   double *brad, *bprev;         // p-p radius; before its last growth (-1: none)
+  uint32_t* barg;               // element that set the radius by that growth
   // discovery order
-  uint32_t *blist_raw, *bscene_raw, *bnact_raw, *ncnt_raw, *nlumc_raw, *bbin;
+  uint32_t *blist_raw, *bscene_raw, *bnact_raw, *ncnt_raw, *nlumc_raw, *bbin, *barg_raw;
   double *brad_raw, *bprev_raw;
   uint2* cut;
   size_t cut_entries;           // capacity of the cut-list buffer
