@@ -88,6 +88,7 @@ __global__ void k_active_hash(const DevTree* __restrict__ TT, const uint8_t* act
 // p-p radius (Section 2.4): past every bucket member by its size, then grown
 // until no element inside is wider than the beam there (w r).  One
 // wavefront per bucket.
+// Each round queries only the shell the sphere grew by.
 // Also records the radius before the last growth (-1 if it never grew) and
 // the element whose size set the final radius by that growth (the smallest
 // sorted slot among equal sizes), for the adjoint.
@@ -116,16 +117,26 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
     for (uint32_t s = lk.x + lane; s < lk.x + lk.y; s += 64)
       rm = fmax(rm, sqrt(dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c)) + T.h[s]);
     r = fmax(r, wave_max(rm));
+    // each round counts only the shell the sphere grew by; the widest
+    // element so far (smallest slot among equal sizes) is kept across rounds
+    double r2in = -1.0, hw = 0.0;
+    uint32_t hwa = 0xFFFFFFFFu;
     for (;;) {
       double hm = 0.0;
-      uint32_t ha = 0xFFFFFFFFu;
-      cnt = wave_near(T, c, r * r, stack, stack_cap<SC>(T), &hm, &nlum, nullptr, 0, &overflow,
-                      &ha);
-      const double rn = fmax(r, hm / T.wbeam);
+      uint32_t ha = 0xFFFFFFFFu, nl = 0;
+      cnt += wave_near(T, c, r * r, stack, stack_cap<SC>(T), &hm, &nl, nullptr, 0, &overflow,
+                       &ha, r2in);
+      nlum += nl;
+      if (hm > hw || (hm == hw && ha < hwa)) {
+        hw = hm;
+        hwa = ha;
+      }
+      const double rn = fmax(r, hw / T.wbeam);
       if (!(rn > r) || overflow) break;
+      r2in = r * r;
       rprev = r;
       r = rn;
-      arg = ha;   // the widest element inside the sphere set the new radius
+      arg = hwa;   // the widest element inside the sphere set the new radius
     }
   }
   if (lane == 0) {
@@ -1084,10 +1095,8 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
                                 S.bprev, S.barg, S.tcnt, S.jcnt, S.pcnt, S.tot);
   TREVR_LAUNCH_CHECK("k_reorder");
   const int64_t Lp = std::max<int64_t>(L.leaves, 1) + 1;
-  for (uint32_t* a : {S.ncnt, S.tcnt, S.jcnt, S.pcnt}) {
-    k_scan_u32<<<1, 1024, 0, st>>>(a, Lp, nullptr);
-    TREVR_LAUNCH_CHECK("k_scan_u32");
-  }
+  k_scan_arrays<<<4, 1024, 0, st>>>(ScanArrays{{S.ncnt, S.tcnt, S.jcnt, S.pcnt}}, Lp);
+  TREVR_LAUNCH_CHECK("k_scan_arrays");
   const dim3 ge(grid_of(L.max_n, 256), (unsigned)L.S);
   k_active_hash<<<ge, 256, 0, st>>>(L.TT, active, S.ahash);
   TREVR_LAUNCH_CHECK("k_active_hash");

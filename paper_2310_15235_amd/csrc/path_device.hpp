@@ -120,17 +120,25 @@ __device__ inline uint32_t wave_excl(uint32_t v, int lane) {
   return incl - v;
 }
 
+constexpr int kLeafBatch = 8;   // leaf elements loaded together by one lane
+
 // Range query by one wavefront: elements strictly within sqrt(r2) of c.
 // Returns the count; *hmax gets their largest size, *nlum the number that
 // emit.  With `out`, writes their sorted slots: luminous ones from out[0],
 // the others from out[lum_total].  Boxes are pruned conservatively (an
 // element can sit an ulp outside its box after quantisation); membership is
-// the exact test.  The traversal stack lives in `stack` (cap words).
+// the exact test.  With r2in >= 0, only the shell r2in <= d2 < r2 (cells
+// surely inside the inner sphere are skipped), so a sphere that grows can be
+// counted shell by shell with the same memberships.  The traversal stack
+// lives in `stack` (cap words).
 __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double r2, uint32_t* stack,
                                      int cap, double* hmax, uint32_t* nlum, uint32_t* out,
-                                     uint32_t lum_total, bool* overflow, uint32_t* harg = nullptr) {
+                                     uint32_t lum_total, bool* overflow, uint32_t* harg = nullptr,
+                                     double r2in = -1.0) {
   const int lane = threadIdx.x & 63;
   const double prune = r2 * (1.0 + 1e-9);
+  // cells surely inside the inner sphere (every element d2 < r2in)
+  const double inner = r2in * (1.0 - 1e-9) - 1e-12 * T.hdr[3] * T.hdr[3];
   uint32_t cnt = 0, lum = 0, ha = 0xFFFFFFFFu;
   double hm = 0.0;
   int sp = 1, maxsp = 1;
@@ -150,20 +158,39 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
       const uint4 nk = T.nk[node];
       double lo[3], hi[3];
       node_box(T.hdr, nk, lo, hi);
-      if (!(dist2_box(lo, hi, c) > prune)) {
+      if (!(dist2_box(lo, hi, c) > prune) && !(far2_box(lo, hi, c) < inner)) {
         isleaf = (nk.w & META_LEAF) != 0u;
         lk = T.nlink[node];
         push = !isleaf;
         if (isleaf) {
-          for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
-            if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
-              ++mine;
-              const double hs = T.h[s];
-              if (hs > hm || (hs == hm && s < ha)) {   // smallest slot among equal sizes
-                hm = hs;
-                ha = s;
+          // the leaf's elements kLeafBatch at a time, loads issued together
+          const uint32_t end = lk.x + lk.y;
+          for (uint32_t s0 = lk.x; s0 < end; s0 += kLeafBatch) {
+            float px[kLeafBatch], py[kLeafBatch], pz[kLeafBatch];
+            double ph[kLeafBatch], pl[kLeafBatch];
+#pragma unroll
+            for (int k = 0; k < kLeafBatch; ++k) {
+              const uint32_t s = min(s0 + (uint32_t)k, end - 1u);
+              px[k] = T.x[s];
+              py[k] = T.y[s];
+              pz[k] = T.z[s];
+              ph[k] = T.h[s];
+              pl[k] = T.lbol[s];
+            }
+#pragma unroll
+            for (int k = 0; k < kLeafBatch; ++k) {
+              const uint32_t s = s0 + (uint32_t)k;
+              if (s >= end) break;
+              const double d2 = dist2_pt3((double)px[k], (double)py[k], (double)pz[k], c);
+              if (d2 < r2 && !(d2 < r2in)) {
+                ++mine;
+                const double hs = ph[k];
+                if (hs > hm || (hs == hm && s < ha)) {   // smallest slot among equal sizes
+                  hm = hs;
+                  ha = s;
+                }
+                if (pl[k] > 0.0) ++mylum;
               }
-              if (T.lbol[s] > 0.0) ++mylum;
             }
           }
         }
@@ -174,10 +201,27 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
       const uint32_t dbase = lum_total + (cnt - lum) + wave_excl(mine - mylum, lane);
       if (isleaf && mine) {
         uint32_t a = 0, b = 0;
-        for (uint32_t s = lk.x; s < lk.x + lk.y; ++s) {
-          if (dist2_pt3((double)T.x[s], (double)T.y[s], (double)T.z[s], c) < r2) {
-            if (T.lbol[s] > 0.0) out[lbase + a++] = s;
-            else out[dbase + b++] = s;
+        const uint32_t end = lk.x + lk.y;
+        for (uint32_t s0 = lk.x; s0 < end; s0 += kLeafBatch) {
+          float px[kLeafBatch], py[kLeafBatch], pz[kLeafBatch];
+          double pl[kLeafBatch];
+#pragma unroll
+          for (int k = 0; k < kLeafBatch; ++k) {
+            const uint32_t s = min(s0 + (uint32_t)k, end - 1u);
+            px[k] = T.x[s];
+            py[k] = T.y[s];
+            pz[k] = T.z[s];
+            pl[k] = T.lbol[s];
+          }
+#pragma unroll
+          for (int k = 0; k < kLeafBatch; ++k) {
+            const uint32_t s = s0 + (uint32_t)k;
+            if (s >= end) break;
+            const double d2 = dist2_pt3((double)px[k], (double)py[k], (double)pz[k], c);
+            if (d2 < r2 && !(d2 < r2in)) {
+              if (pl[k] > 0.0) out[lbase + a++] = s;
+              else out[dbase + b++] = s;
+            }
           }
         }
       }

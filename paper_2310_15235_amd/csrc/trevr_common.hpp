@@ -221,30 +221,61 @@ __device__ inline int mbcnt(uint64_t mask) {
 }
 
 // Exclusive scan of `total` uint32 in place by one workgroup of 1024
-// threads; the grand total goes to *sum_out when given.
+// threads, in chunks of 1024 x kScanPer words (each thread's kScanPer
+// consecutive words loaded together, wavefront scans, then the 16 wavefront
+// totals); the grand total goes to *sum_out when given.
+constexpr int kScanPer = 16;
+__device__ inline void block_scan_u32(uint32_t* a, int64_t total, uint32_t* sum_out) {
+  __shared__ uint32_t wtot[16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < total; base += 1024 * kScanPer) {
+    const int64_t i0 = base + (int64_t)t * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = (i0 + k < total) ? a[i0 + k] : 0u;
+      s += v[k];
+    }
+    uint32_t incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = (uint32_t)__shfl_up((int)incl, o);
+      if (lane >= o) incl += u;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    uint32_t wbase = 0, btot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const uint32_t x = wtot[w];
+      if (w < wv) wbase += x;
+      btot += x;
+    }
+    __syncthreads();
+    uint32_t run = carry + wbase + (incl - s);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < total) a[i0 + k] = run;
+      run += v[k];
+    }
+    carry += btot;
+  }
+  if (t == 0 && sum_out) *sum_out = carry;
+}
+
 static __global__ void __launch_bounds__(1024) k_scan_u32(uint32_t* a, int64_t total,
                                                           uint32_t* sum_out) {
-  __shared__ uint32_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (total + 1023) / 1024;
-  const int64_t b0 = t * per, b1 = (b0 + per < total) ? b0 + per : total;
-  uint32_t s = 0;
-  for (int64_t i = b0; i < b1; ++i) s += a[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = (t >= off) ? part[t - off] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = t ? part[t - 1] : 0u;
-  for (int64_t i = b0; i < b1; ++i) {
-    const uint32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
-  if (t == 1023 && sum_out) *sum_out = part[1023];
+  block_scan_u32(a, total, sum_out);
+}
+
+// Up to four arrays of `total` words scanned at once, one workgroup each.
+struct ScanArrays {
+  uint32_t* a[4];
+};
+static __global__ void __launch_bounds__(1024) k_scan_arrays(ScanArrays s, int64_t total) {
+  block_scan_u32(s.a[blockIdx.x], total, nullptr);
 }
 
 }  // namespace trevr
