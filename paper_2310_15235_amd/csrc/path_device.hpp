@@ -388,16 +388,22 @@ __device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint3
   __syncthreads();
 }
 
-// Next chunk of active bucket members (thread 0 keeps the cursor).
+// Next chunk of active bucket members: the first kRMax active ones from the
+// cursor, in member order.  Wavefront 0 tests 64 members at a time (its lanes
+// keep the cursor, identical in each).
 __device__ inline int load_receivers(const DevTree& T, const uint8_t* active, const double c[3],
                                      uint32_t& member, uint32_t mend, RecvInfo* recv,
                                      uint32_t* nrecv_s) {
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     uint32_t k = 0;
     while (member < mend && k < (uint32_t)kRMax) {
-      const uint32_t s = member++;
-      if (active == nullptr || active[T.perm[s]]) {
+      const uint32_t s = member + (uint32_t)lane;
+      const bool act = s < mend && (active == nullptr || active[T.perm[s]]);
+      const uint64_t m = ballot64(act);
+      const uint32_t pos = k + (uint32_t)mbcnt(m);
+      if (act && pos < (uint32_t)kRMax) {
         RecvInfo ri;
         ri.x[0] = (double)T.x[s];
         ri.x[1] = (double)T.y[s];
@@ -407,10 +413,20 @@ __device__ inline int load_receivers(const DevTree& T, const uint8_t* active, co
         ri.inv_rh = (float)(1.0 / (kR * ri.h));
         ri.kfac = (float)(1.0 / (2.0 * ri.h * ri.h));
         ri.slot = s;
-        recv[k++] = ri;
+        recv[pos] = ri;
+      }
+      const uint32_t cnt = (uint32_t)__popcll(m);
+      if (k + cnt > (uint32_t)kRMax) {   // resume at the first active member not taken
+        uint64_t rest = m;
+        for (uint32_t j = k; j < (uint32_t)kRMax; ++j) rest &= rest - 1ull;
+        member += (uint32_t)(__ffsll((long long)rest) - 1);
+        k = (uint32_t)kRMax;
+      } else {
+        k += cnt;
+        member = min(member + 64u, mend);
       }
     }
-    *nrecv_s = k;
+    if (lane == 0) *nrecv_s = k;
   }
   __syncthreads();
   return (int)*nrecv_s;
