@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
                                              const double* brad, uint2* cut, uint32_t cap,
                                              uint32_t* bstat, uint32_t* ovf) {
   __shared__ uint32_t stack[SC];
-  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_item, lfirst[64], lbeg[64];
   const int lane = threadIdx.x;
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
@@ -257,20 +257,31 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
     }
     ncut += (uint32_t)__popcll(wm);
     nsrc += (uint32_t)__popcll(ballot64(write && ((meta & 0xFFFFu) != CUT_NOPIX)));
-    // element sources of opened luminous buckets, outside the p-p sphere
-    uint64_t lm = ballot64(emit && opened && (nk.w & META_LUM));
-    while (lm) {
-      const int src_lane = __ffsll((long long)lm) - 1;
-      lm &= lm - 1;
-      const uint32_t lnode = (uint32_t)__shfl((int)node, src_lane);
-      const uint2 lk = T.nlink[lnode];
-      for (uint32_t base = 0; base < lk.y; base += 64) {
-        const uint32_t s = lk.x + base + lane;
+    // element sources of opened luminous buckets, outside the p-p sphere:
+    // the (bucket, element) pairs of this step spread over the lanes, in
+    // lane order then element order
+    const bool lumleaf = emit && opened && (nk.w & META_LUM);
+    const uint2 llk = lumleaf ? T.nlink[node] : make_uint2(0u, 0u);
+    const uint32_t lbase = wave_excl(llk.y, lane);
+    const uint32_t ltot = (uint32_t)__shfl((int)(lbase + llk.y), 63);
+    if (ltot) {
+      lfirst[lane] = llk.x;
+      lbeg[lane] = lbase;
+      __syncthreads();
+      for (uint32_t e0 = 0; e0 < ltot; e0 += 64) {
+        const uint32_t e = e0 + (uint32_t)lane;
         bool is_src = false;
-        uint32_t pix = 0u;
-        if (base + lane < lk.y && T.lbol[s] > 0.0) {
+        uint32_t pix = 0u, s = 0u;
+        if (e < ltot) {
+          int lo = 0, hi = 63;   // the last lane whose elements start at or before e
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (lbeg[mid] <= e) lo = mid; else hi = mid - 1;
+          }
+          s = lfirst[lo] + (e - lbeg[lo]);
+          const double lb = T.lbol[s];
           const double px = (double)T.x[s], py = (double)T.y[s], pz = (double)T.z[s];
-          if (!(dist2_pt3(px, py, pz, c) < r2)) {
+          if (lb > 0.0 && !(dist2_pt3(px, py, pz, c) < r2)) {
             is_src = true;
             pix = source_pixel(T.nside, px - c[0], py - c[1], pz - c[2]);
           }
