@@ -430,17 +430,22 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
 // bucket from poff[bucket], receiver-chunk-major, then (source, receiver)),
 // for the adjoint.  J == nullptr: only ptau is written.
 template <int NB>
-__global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, Items I,
+__global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ TT, Items I,
                                                const uint32_t* blist, const uint32_t* bscene,
                                                const uint32_t* noff, const uint32_t* nlumc,
                                                const uint32_t* nidx, const uint32_t* poff,
                                                const uint8_t* active, double* Jall,
                                                float* ptau, int sub) {
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   __shared__ NearTile<NB> S;
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s, s_item;
   __shared__ double red[kNT][NB];
+  // each thread's pair, for lanes that test it on the thread's behalf
+  __shared__ double pd_xj[kNT][3], pd_r2[kNT], pd_inv2[kNT];
+  __shared__ uint32_t pd_j[kNT];
+  __shared__ float tacc[kNT][NB];
+  __shared__ uint8_t nlist[kNT / 64][64];
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -493,7 +498,16 @@ __global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, 
       for (int a = 0; a < 3; ++a) sinv[a] = (sd[a] != 0.0f) ? 1.0f / sd[a] : 0.0f;
       float tau[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) tau[b] = 0.0f;
+      for (int b = 0; b < NB; ++b) {
+        tau[b] = 0.0f;
+        tacc[t][b] = 0.0f;
+      }
+      pd_xj[t][0] = xj0;
+      pd_xj[t][1] = xj1;
+      pd_xj[t][2] = xj2;
+      pd_r2[t] = rij2;
+      pd_inv2[t] = inv2;
+      pd_j[t] = j;
       for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
         const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
         stage_near<NB>(S, T, near, c0, cl, c);
@@ -521,9 +535,56 @@ __global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, 
             }
             need = over && t0 <= t1 + 1e-4f && dmin2 < r2f;
           }
-          if (ballot64(need) == 0ull) continue;
-          if (!need) continue;
+          const uint64_t m = ballot64(need);
+          if (m == 0ull) continue;
+          const int nneed = __popcll(m);
+          const int per = 64 / sub;   // lanes served per round when spread
           const int u1 = min((int)cl, (sb + 1) * sub);
+          if (2 * ((nneed + per - 1) / per) < sub) {
+            // few lanes need this sub-box: their (pair, element) tests spread
+            // over the wavefront, sub lanes (one element each) per pair, the
+            // same FP64 operation sequence as below
+            if (need) nlist[wv][mbcnt(m)] = (uint8_t)lane;
+            wave_lds_sync();
+            const int grp = lane / sub, u = sb * sub + (lane - grp * sub);
+            for (int r0 = 0; r0 < nneed; r0 += per) {
+              const int which = r0 + grp;
+              const bool serve = which < nneed;
+              const int ts = serve ? wv * 64 + nlist[wv][which] : t;
+              float ct[NB];
+#pragma unroll
+              for (int b = 0; b < NB; ++b) ct[b] = 0.0f;
+              if (serve && u < u1) {
+                const RecvInfo& rq = recv[ts % nrecv];
+                const double qx0 = pd_xj[ts][0], qx1 = pd_xj[ts][1], qx2 = pd_xj[ts][2];
+                const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
+                const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
+                const double f0 = ux - qx0, f1 = uy - qx1, f2 = uz - qx2;
+                const double w0 = ux - rq.x[0], w1 = uy - rq.x[1], w2 = uz - rq.x[2];
+                double uu = (w0 * pe0 + w1 * pe1 + w2 * pe2) * pd_inv2[ts];
+                uu = fmin(1.0, fmax(0.0, uu));
+                const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
+                const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+                const uint32_t us = S.slot[u];
+                if ((f0 * f0 + f1 * f1 + f2 * f2 < pd_r2[ts]) && b2 < S.h2[u] &&
+                    us != rq.slot && us != pd_j[ts]) {
+                  const float bb = sqrtf((float)b2);
+                  const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
+#pragma unroll
+                  for (int b = 0; b < NB; ++b) ct[b] = S.kap[u][b] * sg;
+                }
+              }
+#pragma unroll
+              for (int b = 0; b < NB; ++b) ct[b] = group_sum_dpp(ct[b], sub);
+              if (serve && u == sb * sub) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) tacc[ts][b] += ct[b];
+              }
+            }
+            wave_lds_sync();
+            continue;
+          }
+          if (!need) continue;
           for (int u = sb * sub; u < u1; ++u) {
             const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
             const double f0 = ux - xj0, f1 = uy - xj1, f2 = uz - xj2;
@@ -542,6 +603,9 @@ __global__ void __launch_bounds__(kNT) k_pp_src(const DevTree* __restrict__ TT, 
           }
         }
       }
+      wave_lds_sync();
+#pragma unroll
+      for (int b = 0; b < NB; ++b) tau[b] += tacc[t][b];
       if (ok) {
         const float Kv = fshape((float)sqrt(rij2) * ri.inv_rh) * ri.kfac;
 #pragma unroll

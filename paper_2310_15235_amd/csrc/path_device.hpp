@@ -341,6 +341,18 @@ __device__ inline const float (*near_boxes(const NearTile<NB>& S, int sub, bool 
   return hi ? S.bhi8 : S.blo8;
 }
 
+// Sum over each group of `sub` (16 or 8) consecutive lanes, returned in every
+// lane of the group, by DPP moves (swap neighbours, swap pairs, mirror half
+// rows, mirror rows).  Call with every lane active.
+__device__ inline float group_sum_dpp(float v, int sub) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
+  if (sub == 16)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
+  return v;
+}
+
 template <int NB>
 __device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint32_t* near,
                                   uint32_t c0, uint32_t cl, const double c[3]) {
