@@ -437,13 +437,23 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
                                                const uint8_t* active, double* Jall,
                                                float* ptau, int sub) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  __shared__ NearTile<NB> S;
+  // the staged elements (pair-major passes), the exact-test job queues
+  // (element-major passes) and the receiver sums share their LDS
+  __shared__ union {
+    NearTile<NB> S;
+    uint16_t jobq[kNT / 64][kJobQ];
+    double red[kNT][NB];
+  } U;
+  NearTile<NB>& S = U.S;
+  double (*red)[NB] = U.red;
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s, s_item;
-  __shared__ double red[kNT][NB];
-  // each thread's pair, for lanes that test it on the thread's behalf
+  // each thread's pair, for lanes that test it on the thread's behalf; the
+  // optical depths gathered for it by other lanes (tacc)
   __shared__ double pd_xj[kNT][3], pd_r2[kNT], pd_inv2[kNT];
   __shared__ uint32_t pd_j[kNT];
+  __shared__ float pd_jr[kNT][3], pd_jinv[kNT], pd_jlim[kNT];
+  __shared__ uint8_t pd_valid[kNT];
   __shared__ float tacc[kNT][NB];
   __shared__ uint8_t nlist[kNT / 64][64];
   for (;;) {
@@ -471,6 +481,11 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     const RecvInfo& ri = recv[i];
     const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
     const uint32_t si = ri.slot;
+    const bool em = nnear >= kPpElementMajor;
+    float reach = 0.0f;   // largest receiver distance from the centre
+    for (int k = 0; k < nrecv; ++k)
+      reach = fmaxf(reach, sqrtf(recv[k].rel[0] * recv[k].rel[0] + recv[k].rel[1] * recv[k].rel[1] +
+                                 recv[k].rel[2] * recv[k].rel[2]));
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -508,6 +523,106 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
       pd_r2[t] = rij2;
       pd_inv2[t] = inv2;
       pd_j[t] = j;
+      if (em) {
+        // ---- element-major: each lane owns a p-p element; per source run
+        // (the nrecv pairs of one source) it tests the element against the
+        // centre's segment to the source grown by the receivers' reach, and
+        // the element no farther from the source than the farthest receiver
+        // (a superset of the exact test's passes); passing (element, pair)
+        // jobs are queued per wavefront and run 64 at a time with the exact
+        // FP64 test of the pair-major sweep, LDS atomics adding into tacc
+        {
+          const float jj = jr[0] * jr[0] + jr[1] * jr[1] + jr[2] * jr[2];
+          const float lim = (sqrtf(jj) + reach) * (1.0f + 1e-5f);
+          pd_jr[t][0] = jr[0];
+          pd_jr[t][1] = jr[1];
+          pd_jr[t][2] = jr[2];
+          pd_jinv[t] = jj > 0.0f ? 1.0f / jj : 0.0f;
+          pd_jlim[t] = lim * lim;
+          pd_valid[t] = (ok && rij2 > 0.0) ? 1u : 0u;
+        }
+        __syncthreads();
+        const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
+        uint16_t* Q = U.jobq[wv];
+        for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
+          const uint32_t u = c0 + (uint32_t)t;
+          const bool has = u < nnear;
+          const uint32_t l = has ? near[u] : near[0];
+          const double ux = (double)T.x[l], uy = (double)T.y[l], uz = (double)T.z[l];
+          const double hl = T.h[l];
+          const double h2 = hl * hl;
+          const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+          const float iv = (float)(1.0 / hl);
+          float kap[NB];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
+          const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
+          const float rad = ((float)hl + reach) * (1.0f + 1e-5f) +
+                            1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
+          const float rad2 = rad * rad;
+          uint32_t head = 0, tail = 0;   // wave-uniform queue cursors
+          // one batch of up to 64 queued jobs, job head + lane on this lane
+          auto run_jobs = [&](uint32_t cnt) {
+            const bool mine = (uint32_t)lane < cnt;
+            const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
+            const int L = mine ? (int)(job >> 8) : lane;
+            const int q = (int)(job & 0xFFu);
+            const double vx = __shfl(ux, L), vy = __shfl(uy, L), vz = __shfl(uz, L);
+            const double vh2 = __shfl(h2, L);
+            const float vsig = __shfl(sig, L), viv = __shfl(iv, L);
+            const uint32_t vl = (uint32_t)__shfl((int)l, L);
+            float vkap[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) vkap[b] = __shfl(kap[b], L);
+            if (mine && pd_valid[q]) {
+              const RecvInfo& rq = recv[q % nrecv];
+              const double qx0 = pd_xj[q][0], qx1 = pd_xj[q][1], qx2 = pd_xj[q][2];
+              const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
+              const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
+              const double w0 = vx - rq.x[0], w1 = vy - rq.x[1], w2 = vz - rq.x[2];
+              double uu = (w0 * pe0 + w1 * pe1 + w2 * pe2) * pd_inv2[q];
+              uu = fmin(1.0, fmax(0.0, uu));
+              const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
+              const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+              if ((f0 * f0 + f1 * f1 + f2 * f2 < pd_r2[q]) && b2 < vh2 && vl != rq.slot &&
+                  vl != pd_j[q]) {
+                const float bb = sqrtf((float)b2);
+                const float sg = vsig * (1.0f - bb * viv);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) atomicAdd(&tacc[q][b], vkap[b] * sg);
+              }
+            }
+          };
+          for (int q0 = 0; q0 < qend; q0 += nrecv) {
+            bool pass = false;
+            if (has) {
+              const float s0 = pd_jr[q0][0], s1 = pd_jr[q0][1], s2 = pd_jr[q0][2];
+              const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
+              float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * pd_jinv[q0];
+              tt = fminf(1.0f, fmaxf(0.0f, tt));
+              const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
+              pass = f0 * f0 + f1 * f1 + f2 * f2 <= pd_jlim[q0] * (1.0f + 1e-4f) &&
+                     d0 * d0 + d1 * d1 + d2 * d2 <= rad2;
+            }
+            const uint64_t m = ballot64(pass);
+            if (m == 0ull) continue;
+            if (pass) {
+              const uint32_t pos = tail + (uint32_t)mbcnt(m) * (uint32_t)nrecv;
+              for (int k = 0; k < nrecv; ++k)
+                Q[(pos + (uint32_t)k) & (kJobQ - 1)] = (uint16_t)((lane << 8) | (q0 + k));
+            }
+            tail += (uint32_t)__popcll(m) * (uint32_t)nrecv;
+            wave_lds_sync();
+            while (tail - head >= 64u) {
+              run_jobs(64u);
+              head += 64u;
+            }
+          }
+          if (tail > head) run_jobs(tail - head);
+          wave_lds_sync();
+        }
+        __syncthreads();
+      } else
       for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
         const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
         stage_near<NB>(S, T, near, c0, cl, c);
@@ -615,7 +730,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
         }
       }
     }
-    // receiver-wise sums in thread order (deterministic)
+    // receiver-wise sums in thread order (deterministic); red shares its LDS
+    // with the last pass's tile or queues
+    __syncthreads();
 #pragma unroll
     for (int b = 0; b < NB; ++b) red[t][b] = acc[b];
     __syncthreads();

@@ -142,9 +142,6 @@ template <int NB> struct PairTile {
   float jr[kNT][3], jinv[kNT], jlim[kNT];
 };
 
-// Queue of exact-test jobs per wavefront: room for one batch of 64 plus the
-// largest enqueue (64 lanes x kRMax receivers).
-constexpr uint32_t kJobQ = 1024;
 
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ TT, Items I,

@@ -325,6 +325,14 @@ struct RecvInfo {
 constexpr int kSub = 16;
 constexpr int kNSub = kNChunk / kSub;
 
+// Queue of exact-test jobs per wavefront (element-major p-p passes): room
+// for one batch of 64 plus the largest enqueue (64 lanes x kRMax receivers).
+constexpr uint32_t kJobQ = 1024;
+// p-p sets from this size on are swept element-major by the p-p source kernel
+// (each element against the pass's source runs, exact tests queued); smaller
+// ones pair-major over culling boxes of staged elements.
+constexpr uint32_t kPpElementMajor = 4096;
+
 template <int NB> struct NearTile {
   double x[kNChunk], y[kNChunk], z[kNChunk], h2[kNChunk];
   float sig[kNChunk], invh[kNChunk];
