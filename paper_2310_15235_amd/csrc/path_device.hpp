@@ -608,12 +608,15 @@ __device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, ui
   return nsg_all;
 }
 
-// Bin the staged sources by ray and sort each ray's sources by s (ray
-// owner threads t < 64); the owner of a ray gets its range [q0, q1) of
-// W.order.  Ends with a barrier: every thread may then read any ray's list.
+// Bin the staged sources by ray and order each ray's sources by s (ties by
+// staging index): each source's rank among its ray's sources is counted by
+// the thread holding it, O(sources on the ray) each, all threads at once.  The
+// owner of a ray (threads t < 64) gets its range [q0, q1) of W.order.  Ends
+// with a barrier: every thread may then read any ray's list.
 template <int CAP, int NB, bool kSfx>
 __device__ inline void sort_window(SrcWindow<CAP, NB, kSfx>& W, uint32_t nsg, bool rt,
                                    uint32_t& q0, uint32_t& q1) {
+  constexpr int kPer = (CAP + kFT - 1) / kFT;   // sources per thread
   const int t = threadIdx.x;
   if (t < 64) W.ray_fill[t] = 0u;
   __syncthreads();
@@ -632,18 +635,29 @@ __device__ inline void sort_window(SrcWindow<CAP, NB, kSfx>& W, uint32_t nsg, bo
     W.order[pos] = (uint16_t)q;
   }
   __syncthreads();
+  uint32_t dst[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t q = (uint32_t)t + (uint32_t)k * kFT;
+    dst[k] = 0xFFFFFFFFu;
+    if (q < nsg) {
+      const uint32_t r = W.ray[q], b0 = W.ray_beg[r], b1 = W.ray_beg[r + 1];
+      const float sq = W.s[q];
+      uint32_t rank = 0;
+      for (uint32_t a = b0; a < b1; ++a) {
+        const uint32_t o = W.order[a];
+        const float so = W.s[o];
+        rank += (so < sq || (so == sq && o < q)) ? 1u : 0u;
+      }
+      dst[k] = b0 + rank;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (dst[k] != 0xFFFFFFFFu) W.order[dst[k]] = (uint16_t)((uint32_t)t + (uint32_t)k * kFT);
   q0 = rt ? W.ray_beg[t] : 0u;
   q1 = rt ? W.ray_beg[t + 1] : 0u;
-  for (uint32_t a = q0 + 1; a < q1; ++a) {     // insertion sort by s
-    const uint16_t key = W.order[a];
-    const float ks = W.s[key];
-    uint32_t b = a;
-    while (b > q0 && W.s[W.order[b - 1]] > ks) {
-      W.order[b] = W.order[b - 1];
-      --b;
-    }
-    W.order[b] = key;
-  }
   __syncthreads();
 }
 
