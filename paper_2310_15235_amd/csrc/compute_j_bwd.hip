@@ -758,22 +758,35 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
 #pragma unroll
               for (int a = 0; a < 3; ++a) pp[a] += __shfl_xor(pp[a], o);
             }
-            if (my_i == 0) {
+            // every lane of the group now holds the source's totals; the
+            // group's lanes share its writes (lane my_i takes outputs my_i,
+            // my_i + P2, ...): the NB tau adjoints and the s adjoint to LDS,
+            // the NB luminosity adjoints and (merged cells) the 3 position
+            // adjoints straight to the accumulators
+            const uint32_t id = sid[q];
+            const bool cell = (id & kSrcCellBit) != 0u;
+            const uint32_t node = id & ~kSrcCellBit;
+            for (int o = my_i; o <= NB; o += P2) {
+              float v = ps;
 #pragma unroll
-              for (int b = 0; b < NB; ++b) sgtau[q][b] += pt[b];
-              sgs[q] += ps;
-              // luminosity and position adjoints straight to the accumulators
-              const uint32_t id = sid[q];
-              if (id & kSrcCellBit) {
-                const uint32_t node = id & ~kSrcCellBit;
+              for (int b = 0; b < NB; ++b)
+                if (o == b) v = pt[b];
+              if (o < NB) sgtau[q][o] += v;
+              else sgs[q] += v;
+            }
+            const int nglob = cell ? NB + 3 : NB;
+            for (int o = my_i; o < nglob; o += P2) {
+              float v = 0.0f;
 #pragma unroll
-                for (int b = 0; b < NB; ++b) gadd(&gLb_c[(int64_t)node * NB + b], (double)pL[b]);
+              for (int b = 0; b < NB; ++b)
+                if (o == b) v = pL[b];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) gadd(&gcen_c[(int64_t)node * 4 + a], (double)pp[a]);
-              } else {
-#pragma unroll
-                for (int b = 0; b < NB; ++b) gadd(&G.gL[(int64_t)b * n + id], (double)pL[b]);
-              }
+              for (int a = 0; a < 3; ++a)
+                if (o == NB + a) v = pp[a];
+              double* dst = o >= NB ? &gcen_c[(int64_t)node * 4 + (o - NB)]
+                            : cell   ? &gLb_c[(int64_t)node * NB + o]
+                                     : &G.gL[(int64_t)o * n + id];
+              gadd(dst, (double)v);
             }
           }
           // ---- isotropic background
