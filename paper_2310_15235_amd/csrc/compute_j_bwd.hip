@@ -205,8 +205,12 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
       const double rij2 = e0 * e0 + e1 * e1 + e2 * e2;
       bool valid = false;
       float gt[NB];
+      double gl[NB];   // luminosity adjoint of source j from this pair
 #pragma unroll
-      for (int b = 0; b < NB; ++b) gt[b] = 0.0f;
+      for (int b = 0; b < NB; ++b) {
+        gt[b] = 0.0f;
+        gl[b] = 0.0;
+      }
       if (ok) {
         const float x = (float)sqrt(rij2) * ri.inv_rh;
         const float f = fshape(x);
@@ -219,11 +223,35 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
           const double term = Lj * (double)Kv * E;
           acc[b] += term;
           const double w = (double)gw[i][b];
-          gadd(&G.gL[(int64_t)b * n + j], w * (double)Kv * E);
+          gl[b] = w * (double)Kv * E;
           ghi += w * Lj * E * (double)dKdh;
           gt[b] = (float)(-w * term);
           valid = valid || gt[b] != 0.0f;
         }
+      }
+      {
+        // the nrecv pairs of one source sit on consecutive lanes: the first
+        // lane of each run (or of its part in this wavefront) adds the run's
+        // sum, one atomic per source and band instead of one per pair
+        const uint32_t k0 = p % (uint32_t)nrecv;
+        const bool head = k0 == 0u || lane == 0;
+        double g0[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) g0[b] = gl[b];
+        for (int k = 1; k < nrecv; ++k) {
+          const bool same = k0 + (uint32_t)k < (uint32_t)nrecv && lane + k < 64;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const double v = __shfl_down(g0[b], (unsigned)k);
+            if (same) gl[b] += v;
+          }
+        }
+        if (ok && head) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) gadd(&G.gL[(int64_t)b * n + j], gl[b]);
+        }
+      }
+      if (ok) {
         valid = valid && rij2 > 0.0;
       }
       PT.xj[t][0] = xj0;
