@@ -789,8 +789,10 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
             // every lane of the group now holds the source's totals; the
             // group's lanes share its writes (lane my_i takes outputs my_i,
             // my_i + P2, ...): the NB tau adjoints and the s adjoint to LDS,
-            // the NB luminosity adjoints and (merged cells) the 3 position
-            // adjoints straight to the accumulators
+            // the NB luminosity adjoints straight to the accumulators, and
+            // for merged cells the 3 position adjoints into the source's
+            // (no longer read) relative position, added with the s adjoint's
+            // part in the flush below
             const uint32_t id = sid[q];
             const bool cell = (id & kSrcCellBit) != 0u;
             const uint32_t node = id & ~kSrcCellBit;
@@ -811,10 +813,9 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
 #pragma unroll
               for (int a = 0; a < 3; ++a)
                 if (o == NB + a) v = pp[a];
-              double* dst = o >= NB ? &gcen_c[(int64_t)node * 4 + (o - NB)]
-                            : cell   ? &gLb_c[(int64_t)node * NB + o]
-                                     : &G.gL[(int64_t)o * n + id];
-              gadd(dst, (double)v);
+              if (o >= NB) W.rel[q][o - NB] = v;
+              else gadd(cell ? &gLb_c[(int64_t)node * NB + o] : &G.gL[(int64_t)o * n + id],
+                        (double)v);
             }
           }
           // ---- isotropic background
@@ -917,14 +918,15 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
         __syncthreads();
 
         // ---- flush the source adjoints
-        for (uint32_t q = t; q < nsg; q += kFT) {   // s = (p - c).n of merged cells
+        for (uint32_t q = t; q < nsg; q += kFT) {   // merged cells: position adjoints
           const uint32_t id = sid[q];
-          if ((id & kSrcCellBit) && W.s[q] != 0.0f && sgs[q] != 0.0f) {
+          if (id & kSrcCellBit) {
             const uint32_t node = id & ~kSrcCellBit;
             const int ray = W.ray[q];
+            const double gs = W.s[q] != 0.0f ? (double)sgs[q] : 0.0;   // s = (p - c).n
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-              gadd(&gcen_c[(int64_t)node * 4 + a], (double)sgs[q] * RG.n[ray][a]);
+              gadd(&gcen_c[(int64_t)node * 4 + a], (double)W.rel[q][a] + gs * RG.n[ray][a]);
           }
         }
         __syncthreads();
