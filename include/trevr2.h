@@ -56,8 +56,18 @@ enum {
                             (Section 2.1, eq. taucorr)                       */
   TREVR_NEAR_FIELD = 2u, /* particle-particle transfer inside the p-p sphere
                             (Section 2.4); off: r_pp = 0                      */
-  TREVR_BACKGROUND = 4u  /* isotropic background intensity entering at the
+  TREVR_BACKGROUND = 4u, /* isotropic background intensity entering at the
                             root-cube boundary (abstract; Section 4)          */
+  TREVR_KEEP_DEPTHS = 8u /* memory for time in the adjoint: the forward keeps
+                            each far source's cell optical depth (and each
+                            ray's exit depth with TREVR_BACKGROUND) in the
+                            scratch, per (bucket, ray group) whose sources fit
+                            one window, and compute_J_backward reads them
+                            instead of sweeping the cells again.  Off: the
+                            adjoint recomputes every ray's optical-depth
+                            prefixes from the cut lists.  Results agree to
+                            FP32 rounding.  Single trees only (a forest always
+                            recomputes).                                      */
 };
 
 typedef struct trevr_params {

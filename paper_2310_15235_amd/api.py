@@ -18,7 +18,7 @@ SO_PATH = os.path.join(HERE, "libtrevr2.so")
 
 # status codes and flags (include/trevr2.h)
 OK, E_INVALID, E_CAPACITY, E_HIP, E_STATE, E_DATA = range(6)
-THICK_CORR, NEAR_FIELD, BACKGROUND = 1, 2, 4
+THICK_CORR, NEAR_FIELD, BACKGROUND, KEEP_DEPTHS = 1, 2, 4, 8
 
 EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_compute_J_backward", "trevr_tree_tune",
@@ -182,11 +182,12 @@ class Tree:
         self.handle = h
 
     @classmethod
-    def from_scene(cls, scene, device="cuda"):
+    def from_scene(cls, scene, device="cuda", extra_flags=0):
+        """The tree of a scene; extra_flags (e.g. KEEP_DEPTHS) are or-ed into
+        the scene's own option flags."""
         torch = _torch()
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
-        flags = (THICK_CORR if scene.thick_corr else 0) | (NEAR_FIELD if scene.near_field else 0) | \
-            (BACKGROUND if scene.background else 0)
+        flags = scene_flags(scene) | int(extra_flags)
         return cls(t(scene.x), t(scene.y), t(scene.z), t(scene.m), t(scene.rho), t(scene.kappa),
                    t(scene.lum), nside=scene.nside, leaf_size=scene.leaf_size, theta=scene.theta,
                    flags=flags, rpp_min=scene.rpp_min, box=scene.box)
@@ -322,11 +323,11 @@ def compute_J(scene, active=None, device="cuda"):
     return out, cnt
 
 
-def compute_J_backward(scene, gJ, active=None, device="cuda"):
+def compute_J_backward(scene, gJ, active=None, device="cuda", extra_flags=0):
     """Build the tree of a scene, run the adjoint of compute_J for
     gJ = dE/dJ [B, n]; returns numpy (gL [B, n], gkappa [B, n], grho [n])."""
     torch = _torch()
-    T = Tree.from_scene(scene, device=device)
+    T = Tree.from_scene(scene, device=device, extra_flags=extra_flags)
     act = scene.active if active is None else active
     a = None if act is None else torch.as_tensor(np.ascontiguousarray(act, np.uint8), device=device)
     bg = None

@@ -1209,9 +1209,10 @@ unsigned persistent_grid(const void* fn, int threads, uint64_t items, uint32_t d
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(items, slots));
 }
 
-// Cell optical depths the forward keeps for the adjoint: per bucket of a
-// batch and ray group, KeptCap sources x bands (and with a background the
-// exit depth per ray); not kept when that would take more than 1 GiB.
+// Cell optical depths the forward keeps for the adjoint (TREVR_KEEP_DEPTHS):
+// per bucket of a batch and ray group, KeptCap sources x bands (and with a
+// background the exit depth per ray); not kept without the flag or when that
+// would take more than 1 GiB.
 void take_kept(const trevr_tree* T, Scratch& S, Carve& cv, uint32_t nb) {
   const size_t buckets = std::min<size_t>(nb, kBatch);
   const size_t groups = (size_t)(T->nray + 63) / 64;
@@ -1220,7 +1221,7 @@ void take_kept(const trevr_tree* T, Scratch& S, Carve& cv, uint32_t nb) {
                                   KeptCap<7>::value, KeptCap<8>::value};
   const size_t tau_n = buckets * groups * caps[T->B] * T->B;
   const size_t tex_n = (T->p.flags & TREVR_BACKGROUND) ? buckets * T->nray * T->B : 0;
-  if ((tau_n + tex_n) * sizeof(float) > ((size_t)1 << 30)) {
+  if (!(T->p.flags & TREVR_KEEP_DEPTHS) || (tau_n + tex_n) * sizeof(float) > ((size_t)1 << 30)) {
     S.kept_tau = nullptr;
     S.kept_tex = nullptr;
     return;

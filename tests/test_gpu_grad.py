@@ -49,11 +49,11 @@ def _weights(sc, active, seed):
     return gJ
 
 
-def _dot_check(sc, active, seed=0, ndir=3):
+def _dot_check(sc, active, seed=0, ndir=3, extra_flags=0):
     api = _api()
     act = np.ones(sc.n, np.uint8) if active is None else active
     gJ = _weights(sc, act, seed)
-    gL, gk, gr = api.compute_J_backward(sc, gJ, active=act)
+    gL, gk, gr = api.compute_J_backward(sc, gJ, active=act, extra_flags=extra_flags)
     assert np.all(np.isfinite(gL)) and np.all(np.isfinite(gk)) and np.all(np.isfinite(gr))
     rng = np.random.default_rng(seed + 100)
     B, n = sc.n_bands, sc.n
@@ -134,12 +134,32 @@ def test_adjoint_ragged_active_subset():
     _component_check(sc, act, gJ, (gL, gk, gr), picks_per_array=3, seed=2)
 
 
-def test_adjoint_differentiation_full_size_dot():
+@pytest.mark.parametrize("keep", [False, True], ids=["recompute", "keep_depths"])
+def test_adjoint_differentiation_full_size_dot(keep):
     """2^18 elements, 2 bands, N_side 2 at full size; the objective weights
-    1% of the receivers so the oracle's derivative finishes in seconds."""
+    1% of the receivers so the oracle's derivative finishes in seconds.  The
+    adjoint recomputes the rays' optical-depth prefixes, or (KEEP_DEPTHS)
+    reads the depths the forward kept."""
+    api = _api()
     sc = scenes.config_differentiation()
     act = scenes.active_subset(sc, 0.01, 7)
-    _dot_check(sc, act, seed=7, ndir=3)
+    _dot_check(sc, act, seed=7, ndir=3, extra_flags=api.KEEP_DEPTHS if keep else 0)
+
+
+@pytest.mark.parametrize("name", ["lognormal_nside2_3bands", "uniform_nside4", "background"])
+def test_adjoint_keep_depths_matches_recompute(name):
+    """The kept far-source depths are the forward's own, so the adjoint with
+    KEEP_DEPTHS equals the recomputing one up to FP32 rounding of sums formed
+    with atomics."""
+    api = _api()
+    sc = SCENES[name]()
+    act = np.ones(sc.n, np.uint8) if sc.active is None else sc.active
+    gJ = _weights(sc, act, 3)
+    a = api.compute_J_backward(sc, gJ, active=act)
+    b = api.compute_J_backward(sc, gJ, active=act, extra_flags=api.KEEP_DEPTHS)
+    for x, y in zip(a, b):
+        tol = 1e-5 * np.abs(x) + 1e-7 * np.abs(x).max()
+        assert np.all(np.abs(x - y) <= tol), float(np.max(np.abs(x - y) - tol))
 
 
 def test_autograd_matches_abi():
