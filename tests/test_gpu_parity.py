@@ -103,7 +103,12 @@ def test_J_tiny_config():
 @pytest.mark.parametrize("nside,bands", [(1, (1.0,)), (2, (1.0, 10.0, 100.0)), (4, (1.0, 10.0))])
 def test_J_lognormal(nside, bands):
     sc = scenes.lognormal_scene(n=2 ** 14, seed=7 + nside, grid=32, bands=bands, nside=nside)
-    compare_J(sc)
+    _, cg = compare_J(sc)
+    if nside == 4:
+        # the p-p sets of this scene reach past 4096 elements, where the p-p
+        # source kernel sweeps element-major, so both of its sweeps meet the
+        # oracle here
+        assert cg["max_near"] >= 4096, cg["max_near"]
 
 
 def test_J_diffuse_background_active_subset():
