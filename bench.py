@@ -218,6 +218,8 @@ def main():
                     help="fraction of receivers the oracle evaluates for the CPU baseline")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched 64-scene measurement")
+    ap.add_argument("--no-keep-depths", action="store_true",
+                    help="skip the forward + adjoint timing with the depth cache")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched 64-scene measurement and print its record")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -320,20 +322,22 @@ def main():
     # forward + adjoint again with the depth cache (KEEP_DEPTHS): the forward
     # keeps the far sources' cell optical depths and the adjoint reads them
     # instead of recomputing every ray's prefixes (the default above)
-    kw_keep = dict(kw, flags=flags | api.KEEP_DEPTHS)
-    T = api.Tree(x, y, z, m, rho, kappa, lum, **kw_keep)
-    T.compute_J(active, None, out=J)
-    T.compute_J_backward(gJ, active, None, out=grads)
-    torch.cuda.synchronize()
-    k0 = time.perf_counter()
-    for _ in range(args.steps):
+    ms_fwd_adj_keep = None
+    if not args.no_keep_depths:
+        kw_keep = dict(kw, flags=flags | api.KEEP_DEPTHS)
+        T = api.Tree(x, y, z, m, rho, kappa, lum, **kw_keep)
         T.compute_J(active, None, out=J)
         T.compute_J_backward(gJ, active, None, out=grads)
-    torch.cuda.synchronize()
-    k1 = time.perf_counter()
-    T.check()
-    T.close()
-    ms_fwd_adj_keep = (k1 - k0) * 1e3 / args.steps
+        torch.cuda.synchronize()
+        k0 = time.perf_counter()
+        for _ in range(args.steps):
+            T.compute_J(active, None, out=J)
+            T.compute_J_backward(gJ, active, None, out=grads)
+        torch.cuda.synchronize()
+        k1 = time.perf_counter()
+        T.check()
+        T.close()
+        ms_fwd_adj_keep = (k1 - k0) * 1e3 / args.steps
 
     # the dominant single kernel of a step: the far-field reduction or its
     # adjoint (the p-p phases are two kernels each and shorter)
@@ -394,8 +398,8 @@ def main():
                    "segments_per_step": seg},
         "fwd": {"value": seg / (ms_fwd * 1e-3), "ms": ms_fwd},
         "fwd_adjoint": {"value": seg / (ms_fwd_adj * 1e-3), "ms": ms_fwd_adj},
-        "fwd_adjoint_keep_depths": {"value": seg / (ms_fwd_adj_keep * 1e-3),
-                                    "ms": ms_fwd_adj_keep},
+        "fwd_adjoint_keep_depths": None if ms_fwd_adj_keep is None else
+            {"value": seg / (ms_fwd_adj_keep * 1e-3), "ms": ms_fwd_adj_keep},
         "build_ms": ms_build,
         "roofline": roofline,
         "cpu_baseline": cpu,
