@@ -409,9 +409,9 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
 // Adjoint of k_pp_rays: tau_ikb = sum_l kappa_lb Sigma_l(b_ilk) with the
 // adjoint g_ikb of the far-field kernel: dkappa_lb += g Sigma, dh_l +=
 // g kappa_lb dSigma/dh.  Element-major: threads take (p-p element l,
-// receiver i) pairs and sweep the rays of a group of 64, a conservative
-// FP32 test skipping rays that cannot pass within h_l of l, the exact FP64
-// test (the forward's operation sequence) deciding the rest; each thread
+// receiver i) pairs and mark the rays of a group of 64 that a conservative
+// FP32 test cannot rule out (within h_l of l), then run the exact FP64 test
+// (the forward's operation sequence) over their own marked rays only; each thread
 // sums its pair's contributions in registers, one LDS atomic per pair
 // collects them per element, one FP64 atomic per element and group writes
 // them out.
@@ -499,9 +499,16 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
           float ck[NB], gh = 0.0f;
 #pragma unroll
           for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
+          // the FP32 test over the whole ray group first, then the exact
+          // test for this lane's candidates only (in ray order as before)
+          uint64_t cand = 0ull;
           for (int kq = 0; kq < kn; ++kq) {
             const float pf = RG.nf[kq][0] * df[0] + RG.nf[kq][1] * df[1] + RG.nf[kq][2] * df[2];
-            if (!(pf > neg) || !(pf * pf >= lim)) continue;
+            if (pf > neg && pf * pf >= lim) cand |= 1ull << kq;
+          }
+          while (cand) {
+            const int kq = __ffsll((long long)cand) - 1;
+            cand &= cand - 1ull;
             const double proj = d0 * RG.n[kq][0] + d1 * RG.n[kq][1] + d2 * RG.n[kq][2];
             const double b2 = dd - proj * proj;
             if (!(proj > 0.0 && b2 < h2)) continue;
