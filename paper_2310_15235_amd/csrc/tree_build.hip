@@ -207,14 +207,18 @@ __global__ void k_root(TreeBufs tb, int64_t n) {
   tb.b_count[0] = (uint32_t)n;
   tb.b_lown[0] = 0;
   tb.b_pre[0] = 0u;
+  tb.levels[0] = make_uint2(0u, 1u);
 }
 
 // One level: a node is a bucket if it holds at most leaf_size elements or
 // all its keys are equal; otherwise it splits at the first bit in which its
 // keys differ (its sorted range splits where that bit turns on).
-__global__ void k_level(TreeBufs tb, uint32_t lb, uint32_t le, int leaf_size) {
-  const uint32_t i = lb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= le) return;
+// The level's range [lb, le) is read from levels[d] (written by the previous
+// level's k_level_next), so levels follow each other without the host.
+__global__ void k_level(TreeBufs tb, int d, int leaf_size) {
+  const uint2 lv = tb.levels[d];
+  const uint32_t i = lv.x + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= lv.y) return;
   const uint32_t f = tb.b_first[i], c = tb.b_count[i];
   const uint64_t k0 = tb.keys[f], k1 = tb.keys[f + c - 1];
   if (c <= (uint32_t)leaf_size || k0 == k1) {
@@ -238,6 +242,11 @@ __global__ void k_level(TreeBufs tb, uint32_t lb, uint32_t le, int leaf_size) {
   tb.b_c0[i] = pos;
   tb.b_c1[i] = pos + 1;
   tb.b_split[i] = s;
+}
+
+// Range of level d + 1: the nodes allocated by the splits of level d.
+__global__ void k_level_next(TreeBufs tb, int d) {
+  if (threadIdx.x == 0) tb.levels[d + 1] = make_uint2(tb.levels[d].y, *tb.alloc);
 }
 
 __global__ void k_sizes(TreeBufs tb, uint32_t lb, uint32_t le) {
@@ -570,22 +579,39 @@ trevr_status build_tree_impl(trevr_tree* T, const float* x, const float* y, cons
   // topology, top-down by level
   k_root<<<1, 64, 0, st>>>(tb, n);
   TREVR_LAUNCH_CHECK("k_root");
+  // levels in batches, each level's range on the device; the host reads the
+  // ranges back once per batch.  A level has at most twice the nodes of the
+  // one above, which sizes the grids from the last width read back.
   T->levels.clear();
-  uint32_t lb = 0, le = 1;
-  uint32_t* host_alloc = T->host_u32;
-  while (lb < le) {
-    T->levels.emplace_back(lb, le);
-    k_level<<<grid_for(le - lb, 256), 256, 0, st>>>(tb, lb, le, T->p.leaf_size);
-    TREVR_LAUNCH_CHECK("k_level");
-    hipError_t e = hipMemcpyAsync(host_alloc, tb.alloc, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  constexpr int kLevelBatch = 6;
+  uint64_t width = 1;   // nodes of level d
+  int d = 0;
+  for (bool done = false; !done;) {
+    const int nb = std::min(kLevelBatch, kMaxLevels + 2 - d);
+    if (nb <= 0) return set_error(TREVR_E_DATA, "tree deeper than the key allows");
+    uint64_t bound = width;
+    for (int k = 0; k < nb; ++k) {
+      k_level<<<grid_for((int64_t)bound, 256), 256, 0, st>>>(tb, d + k, T->p.leaf_size);
+      TREVR_LAUNCH_CHECK("k_level");
+      k_level_next<<<1, 64, 0, st>>>(tb, d + k);
+      TREVR_LAUNCH_CHECK("k_level_next");
+      bound = std::min<uint64_t>(2 * bound, 2 * (uint64_t)n);
+    }
+    uint2* rb = reinterpret_cast<uint2*>(T->host_u32);   // levels d .. d + nb
+    hipError_t e = hipMemcpyAsync(rb, tb.levels + d, sizeof(uint2) * (nb + 1),
+                                  hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if ((rc = hip_check(e, "level readback")) != TREVR_OK) return rc;
-    lb = le;
-    le = *host_alloc;
-    if (T->levels.size() > (size_t)kMaxLevels + 2)
-      return set_error(TREVR_E_DATA, "tree deeper than the key allows");
+    for (int k = 0; k <= nb && !done; ++k) {
+      if (rb[k].x >= rb[k].y) done = true;
+      else if (k < nb) T->levels.emplace_back(rb[k].x, rb[k].y);
+    }
+    if (!done) width = rb[nb].y - rb[nb].x;
+    d += nb;
   }
-  const uint32_t total = le;
+  if (T->levels.size() > (size_t)kMaxLevels + 2)
+    return set_error(TREVR_E_DATA, "tree deeper than the key allows");
+  const uint32_t total = T->levels.back().second;
   T->num_nodes = total;
   T->num_leaves = (total + 1) / 2;
   T->depth = (int32_t)T->levels.size();
