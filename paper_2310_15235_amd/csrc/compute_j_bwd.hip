@@ -671,8 +671,9 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
         uint32_t q0, q1;
         sort_window<CAP, NB>(W, nsg, rt, q0, q1);
 
-        // ---- cell optical depths: kept by the forward when the group fits
-        // one window; otherwise a first sweep over the hits
+        // ---- cell optical depths: recomputed by a first sweep over the hits,
+        // or read where the forward kept them (TREVR_KEEP_DEPTHS, the group
+        // fitting one window)
         if (kept_tau && skip == 0 && nsg_all <= (uint32_t)KeptCap<NB>::value) {
           const float* src = kept_tau + ((size_t)rel * ngroups + g) * KeptCap<NB>::value * NB;
           for (uint32_t q = t; q < nsg * NB; q += kFT) (&W.tau[0][0])[q] = src[q];
