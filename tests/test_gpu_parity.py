@@ -157,6 +157,36 @@ def test_no_sources_gives_zero():
     assert np.all(J == 0.0) and c["source_entries"] == 0
 
 
+def test_empty_active_set():
+    """No active receiver, in a lone tree and in a forest: no bucket is set up
+    or walked, J keeps its zeros and the adjoint of any weights is zero."""
+    api = _gpu()
+    import torch
+    sc = scenes.lognormal_scene(n=3000, seed=61, grid=16, bands=(1.0, 10.0), nside=2)
+    a = torch.zeros(sc.n, dtype=torch.uint8, device="cuda")
+    T = api.Tree.from_scene(sc)
+    J = T.compute_J(a)
+    T.check()
+    assert bool(torch.all(J == 0.0))
+    gJ = torch.as_tensor(np.random.default_rng(1).normal(size=(sc.n_bands, sc.n)), device="cuda")
+    for g in T.compute_J_backward(gJ, a):
+        assert bool(torch.all(g == 0.0))
+    T.check()
+    c = T.counters()
+    assert c["buckets"] == 0 and c["segments"] == 0
+    T.close()
+    sc2 = scenes.uniform_scene(n=2000, seed=62, n_src=30, bands=(1.0,), nside=1)
+    F = api.Forest([sc, sc2])
+    fa = F.flat_active([np.zeros(sc.n, np.uint8), np.zeros(sc2.n, np.uint8)])
+    assert bool(torch.all(F.compute_J(fa) == 0.0))
+    gJf = torch.as_tensor(np.random.default_rng(2).normal(size=int(F.boff[-1])), device="cuda")
+    for g in F.compute_J_backward(gJf, fa):
+        assert bool(torch.all(g == 0.0))
+    F.check()
+    assert F.counters(-1)["buckets"] == 0
+    F.close()
+
+
 def test_zero_opacity_band():
     sc = scenes.uniform_scene(n=3000, seed=17, n_src=30, bands=(0.0, 1.0), nside=2)
     compare_J(sc)
