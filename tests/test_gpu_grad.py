@@ -109,6 +109,9 @@ SCENES = {
                                                         leaf_size=12),
     "rpp_min": lambda: scenes.uniform_scene(n=2000, seed=58, n_src=40, bands=(1.0,), nside=2,
                                             rpp_min=0.1),
+    "eight_bands": lambda: scenes.lognormal_scene(n=3000, seed=60, grid=16,
+                                                  bands=tuple(float(2 ** k) for k in range(8)),
+                                                  nside=2),
 }
 
 

@@ -129,6 +129,15 @@ def test_J_many_bands_and_leaf12():
     compare_J(sc)
 
 
+@pytest.mark.parametrize("nb", [7, 8])
+def test_J_seven_and_eight_bands(nb):
+    """The largest band counts (their own window sizes and occupancy; a
+    window of 256 sources, so source-rich buckets take several)."""
+    bands = tuple(float(2 ** k) for k in range(nb))
+    sc = scenes.lognormal_scene(n=6000, seed=70 + nb, grid=16, bands=bands, nside=2)
+    compare_J(sc)
+
+
 def test_J_ragged_active_subset():
     sc = scenes.lognormal_scene(n=10000, seed=13, grid=32, bands=(1.0, 10.0), nside=2)
     act = scenes.active_subset(sc, 0.013, 5)
