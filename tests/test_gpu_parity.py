@@ -138,6 +138,13 @@ def test_J_seven_and_eight_bands(nb):
     compare_J(sc)
 
 
+def test_J_nside8():
+    """768 rays: twelve ray groups of 64 per bucket in the far field and the
+    p-p columns."""
+    sc = scenes.uniform_scene(n=2500, seed=80, n_src=40, bands=(1.0, 5.0), nside=8)
+    compare_J(sc)
+
+
 def test_J_ragged_active_subset():
     sc = scenes.lognormal_scene(n=10000, seed=13, grid=32, bands=(1.0, 10.0), nside=2)
     act = scenes.active_subset(sc, 0.013, 5)
