@@ -1172,11 +1172,6 @@ __global__ void k_sum_copies(double* a, int64_t per, uint32_t copies) {
   a[i] = s;
 }
 
-__global__ void k_zero_u64(unsigned long long* a, int64_t count) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < count) a[i] = 0ull;
-}
-
 // ============================================================ host side
 static unsigned grid_of(int64_t work, int threads) {
   return (unsigned)std::max<int64_t>(1, (work + threads - 1) / threads);

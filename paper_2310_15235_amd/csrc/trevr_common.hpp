@@ -214,7 +214,6 @@ __device__ inline double combine64_d(const double* g, double L, double a1, doubl
 
 // ------------------------------------------------------------ wave helpers
 __device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
-__device__ inline int lane_id() { return __lane_id(); }
 __device__ inline int mbcnt(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
