@@ -175,7 +175,9 @@ trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* 
  * fingerprint of the active indices), they are taken from the scratch as
  * that call left them; otherwise they are recomputed.  The caller must not
  * write the scratch between the calls.  Either
- * way the result is the same.  Synchronises `stream` one to three times and needs
+ * way the result is the same.  The rays' optical-depth prefixes are recomputed
+ * from the cut lists (with TREVR_KEEP_DEPTHS: read where the forward kept
+ * them).  Synchronises `stream` one to three times and needs
  * more scratch than compute_J (accumulators per node, class and band, and a
  * second p-p column buffer, placed after compute_J's part of the scratch):
  * on TREVR_E_CAPACITY trevr_scratch_needed gives the size.
