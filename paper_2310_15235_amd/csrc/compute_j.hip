@@ -88,7 +88,10 @@ __global__ void k_active_hash(const DevTree* __restrict__ TT, const uint8_t* act
 // p-p radius (Section 2.4): past every bucket member by its size, then grown
 // until no element inside is wider than the beam there (w r).  One
 // wavefront per bucket.
-// Each round queries only the shell the sphere grew by.
+// Each round queries only the shell the sphere grew by.  The shells are
+// disjoint and together make up the final sphere, so their elements are the
+// p-p set: the rounds leave it as runs (NearOut) in the bucket's stage_cap
+// staging words, {run count or kNoRuns, unused, runs...}, for k_near_fill.
 // Also records the radius before the last growth (-1 if it never grew) and
 // the element whose size set the final radius by that growth (the smallest
 // sorted slot among equal sizes), for the adjoint.
@@ -96,7 +99,8 @@ template <int SC>
 __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, Items I,
                                               const uint32_t* blist, const uint32_t* bscene,
                                               double* brad, double* bprev, uint32_t* barg,
-                                              uint32_t* ncnt, uint32_t* nlumc, uint32_t* ovf) {
+                                              uint32_t* ncnt, uint32_t* nlumc, uint32_t* ovf,
+                                              uint32_t* stage, uint32_t stage_cap) {
   __shared__ uint32_t stack[SC];
   __shared__ uint32_t s_item;
   const int lane = threadIdx.x;
@@ -110,6 +114,8 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
   double r = 0.0, rprev = -1.0;
   uint32_t cnt = 0, nlum = 0, arg = 0xFFFFFFFFu;
   bool overflow = false;
+  NearOut o{stage_cap ? stage + (size_t)b * stage_cap + 2 : nullptr, true, 0u, 0u, 0u,
+            stage_cap ? (stage_cap - 2u) / 2u : 0u};
   if (T.flags & TREVR_NEAR_FIELD) {
     r = T.rpp_min;
     const uint2 lk = T.nlink[leaf];
@@ -124,8 +130,7 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
     for (;;) {
       double hm = 0.0;
       uint32_t ha = 0xFFFFFFFFu, nl = 0;
-      cnt += wave_near(T, c, r * r, stack, stack_cap<SC>(T), &hm, &nl, nullptr, 0, &overflow,
-                       &ha, r2in);
+      cnt += wave_near(T, c, r * r, stack, stack_cap<SC>(T), &hm, &nl, o, &overflow, &ha, r2in);
       nlum += nl;
       if (hm > hw || (hm == hw && ha < hwa)) {
         hw = hm;
@@ -145,31 +150,90 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
     barg[b] = arg;
     ncnt[b] = cnt;
     nlumc[b] = nlum;
+    if (stage_cap) stage[(size_t)b * stage_cap] = o.out ? o.nrun : kNoRuns;
     if (overflow) atomicOr(ovf, OVF_SETUP);
   }
   }
 }
 
-// Same spheres as the last query of k_setup, so the same stack suffices.
+// One workgroup (one wavefront) per bucket: a plain grid, since most buckets
+// take a few microseconds, too short to be worth a work-queue claim.  A
+// bucket whose set k_setup staged writes it in slot order, which keeps
+// consecutive list entries close in space for the p-p kernels' culling
+// boxes: its runs are sorted in LDS by (first slot, staging index) (bitonic,
+// the staging index breaks ties between two shells' members of one window),
+// then placed by a prefix over their member counts.  The others query the
+// sphere again (the same sphere as the last query of k_setup, so the same
+// stack suffices).
 template <int SC>
-__global__ void __launch_bounds__(64) k_near_fill(const DevTree* __restrict__ TT, Items I,
-                                                  const uint32_t* blist, const uint32_t* bscene,
-                                                  const double* brad, const uint32_t* noff,
-                                                  const uint32_t* nlumc, uint32_t* nidx) {
-  __shared__ uint32_t stack[SC];
-  __shared__ uint32_t s_item;
-  for (;;) {
-    const uint32_t b = next_item(I, &s_item);
-    if (b == kNoItem) break;
-    const DevTree& T = TT[bscene[b]];
-    if (!(T.flags & TREVR_NEAR_FIELD)) continue;
-    double c[3];
-    leaf_centre(T, blist[b], c);
-    const double r = brad[b];
-    bool overflow = false;
-    wave_near(T, c, r * r, stack, stack_cap<SC>(T), nullptr, nullptr, nidx + noff[b], nlumc[b],
-              &overflow);
+__global__ void __launch_bounds__(64) k_near_fill(const DevTree* __restrict__ TT,
+                                                  const uint32_t* rng, const uint32_t* blist,
+                                                  const uint32_t* bscene, const double* brad,
+                                                  const uint32_t* noff, const uint32_t* nlumc,
+                                                  const uint32_t* bsrc,
+                                                  const uint32_t* __restrict__ stage,
+                                                  uint32_t stage_cap,
+                                                  uint32_t* __restrict__ nidx) {
+  constexpr int kWords = SC / 2 > (int)kSortRuns ? SC / 2 : (int)kSortRuns;
+  __shared__ unsigned long long lds[kWords];   // the traversal stack, or sort keys
+  const uint32_t lane = threadIdx.x;
+  const uint32_t b = blockIdx.x;
+  if (b >= rng[1]) return;
+  const DevTree& T = TT[bscene[b]];
+  if (!(T.flags & TREVR_NEAR_FIELD)) return;
+  const uint32_t nl = nlumc[b];
+  uint32_t* out = nidx + noff[b];
+  const uint32_t* sg = stage_cap ? stage + (size_t)bsrc[b] * stage_cap : nullptr;
+  const uint32_t nrun = sg ? sg[0] : kNoRuns;
+  if (nrun != kNoRuns) {
+    const uint2* run = reinterpret_cast<const uint2*>(sg + 2);
+    uint32_t P = 2;
+    while (P < nrun) P <<= 1;
+    for (uint32_t t = lane; t < P; t += 64)
+      lds[t] = t < nrun ? ((unsigned long long)run[t].x << kSortIdxBits) | t : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t q = lane; q < P / 2; q += 64) {
+          const uint32_t t = ((q & ~(j - 1u)) << 1) | (q & (j - 1u)), u = t | j;
+          const unsigned long long x = lds[t], y = lds[u];
+          if ((x > y) == ((t & k) == 0u)) {
+            lds[t] = y;
+            lds[u] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    uint32_t bl = 0, bd = 0;   // luminous and other members placed so far
+    for (uint32_t p0 = 0; p0 < nrun; p0 += 64) {
+      const uint32_t p = p0 + lane;
+      uint32_t first = 0, m = 0;
+      if (p < nrun) {
+        const unsigned long long key = lds[p];
+        first = (uint32_t)(key >> kSortIdxBits);
+        m = run[(uint32_t)key & ((1u << kSortIdxBits) - 1u)].y;
+      }
+      uint32_t tl, td;
+      uint32_t a = bl + wave_excl_bits<kLeafBatchBits>((uint32_t)__popc(m & 0xFFFFu), &tl);
+      uint32_t d = nl + bd + wave_excl_bits<kLeafBatchBits>((uint32_t)__popc(m >> 16), &td);
+#pragma unroll
+      for (int k = 0; k < kLeafBatch; ++k) {
+        if ((m >> k) & 1u) out[a++] = first + (uint32_t)k;
+        if ((m >> (16 + k)) & 1u) out[d++] = first + (uint32_t)k;
+      }
+      bl += tl;
+      bd += td;
+    }
+    return;
   }
+  double c[3];
+  leaf_centre(T, blist[b], c);
+  const double r = brad[b];
+  bool overflow = false;
+  NearOut o{out, false, 0u, nl, 0u, 0u};
+  wave_near(T, c, r * r, reinterpret_cast<uint32_t*>(lds), stack_cap<SC>(T), nullptr, nullptr, o,
+            &overflow);
 }
 
 // ------------------------------------------------------------- the walk
@@ -1058,7 +1122,8 @@ __global__ void __launch_bounds__(256) k_reorder(const DevTree* __restrict__ TT,
                                                  const uint32_t* blist,
                           const uint32_t* bscene, const uint32_t* bnact, const uint32_t* ncnt,
                           const uint32_t* nlumc, const double* brad, const double* bprev,
-                          const uint32_t* barg, uint32_t* blist2, uint32_t* bscene2,
+                          const uint32_t* barg, uint32_t* bsrc2, uint32_t* blist2,
+                          uint32_t* bscene2,
                           uint32_t* bnact2, uint32_t* ncnt2, uint32_t* nlumc2, double* brad2,
                           double* bprev2, uint32_t* barg2, uint32_t* tcnt2,
                           uint32_t* jcnt2, uint32_t* pcnt2, unsigned long long* tot) {
@@ -1084,6 +1149,7 @@ __global__ void __launch_bounds__(256) k_reorder(const DevTree* __restrict__ TT,
     const uint32_t sc = bscene[b];
     const DevTree& T = TT[sc];
     const uint32_t na = bnact[b], B = (uint32_t)T.B;
+    bsrc2[pos] = b;
     blist2[pos] = blist[b];
     bscene2[pos] = sc;
     bnact2[pos] = na;
@@ -1158,6 +1224,7 @@ Scratch carve_scratch(void* base, int64_t leaves, size_t cut_entries) {
   s.brad = cv.take<double>(L);
   s.bprev = cv.take<double>(L);
   s.barg = cv.take<uint32_t>(L);
+  s.bsrc = cv.take<uint32_t>(L);
   s.blist_raw = cv.take<uint32_t>(L);
   s.bscene_raw = cv.take<uint32_t>(L);
   s.bnact_raw = cv.take<uint32_t>(L);
@@ -1169,6 +1236,9 @@ Scratch carve_scratch(void* base, int64_t leaves, size_t cut_entries) {
   s.barg_raw = cv.take<uint32_t>(L);
   s.cut_entries = cut_entries;
   s.cut = cv.take<uint2>(cut_entries);
+  s.stage = reinterpret_cast<uint32_t*>(s.cut);
+  const size_t per = std::min<size_t>(kStageCap, 2 * cut_entries / (size_t)L) & ~(size_t)63;
+  s.stage_cap = (uint32_t)per;
   s.fixed = ((cv.off + 255) & ~(size_t)255) + 256;   // 256-aligned
   return s;
 }
@@ -1265,12 +1335,12 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
     const void* fn = (const void*)&k_setup<kStackLarge>;
     k_setup<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
         L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.barg_raw, S.ncnt_raw,
-        S.nlumc_raw, S.ovf);
+        S.nlumc_raw, S.ovf, S.stage, S.stage_cap);
   } else {
     const void* fn = (const void*)&k_setup<kStackSmall>;
     k_setup<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
         L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.barg_raw, S.ncnt_raw,
-        S.nlumc_raw, S.ovf);
+        S.nlumc_raw, S.ovf, S.stage, S.stage_cap);
   }
   TREVR_LAUNCH_CHECK("k_setup");
   const unsigned gl = grid_of(L.leaves, 256);
@@ -1282,10 +1352,10 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
   k_class_ranges<<<1, 64, 0, st>>>(S.bins, S.rng);
   TREVR_LAUNCH_CHECK("k_class_ranges");
   k_reorder<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, L.cfg.order, S.bbin, S.bins, S.blist_raw,
-                                S.bscene_raw,
-                                S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw, S.bprev_raw,
-                                S.barg_raw, S.blist, S.bscene, S.bnact, S.ncnt, S.nlumc, S.brad,
-                                S.bprev, S.barg, S.tcnt, S.jcnt, S.pcnt, S.tot);
+                                S.bscene_raw, S.bnact_raw, S.ncnt_raw, S.nlumc_raw, S.brad_raw,
+                                S.bprev_raw, S.barg_raw, S.bsrc, S.blist, S.bscene, S.bnact,
+                                S.ncnt, S.nlumc, S.brad, S.bprev, S.barg, S.tcnt, S.jcnt, S.pcnt,
+                                S.tot);
   TREVR_LAUNCH_CHECK("k_reorder");
   const int64_t Lp = std::max<int64_t>(L.leaves, 1) + 1;
   k_scan_arrays<<<4, 1024, 0, st>>>(ScanArrays{{S.ncnt, S.tcnt, S.jcnt, S.pcnt}}, Lp);
@@ -1362,16 +1432,13 @@ trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long lon
 
 trevr_status near_fill(const Launch& L, const Scratch& S) {
   trevr_status rc = TREVR_OK;
-  const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_FILL};
-  if (L.stack_large) {
-    const void* fn = (const void*)&k_near_fill<kStackLarge>;
-    k_near_fill<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, L.st>>>(
-        L.TT, I, S.blist, S.bscene, S.brad, S.ncnt, S.nlumc, S.nidx);
-  } else {
-    const void* fn = (const void*)&k_near_fill<kStackSmall>;
-    k_near_fill<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, L.st>>>(
-        L.TT, I, S.blist, S.bscene, S.brad, S.ncnt, S.nlumc, S.nidx);
-  }
+  const unsigned g = grid_of(L.leaves, 1);
+  if (L.stack_large)
+    k_near_fill<kStackLarge><<<g, 64, 0, L.st>>>(L.TT, S.rng, S.blist, S.bscene, S.brad, S.ncnt,
+                                                  S.nlumc, S.bsrc, S.stage, S.stage_cap, S.nidx);
+  else
+    k_near_fill<kStackSmall><<<g, 64, 0, L.st>>>(L.TT, S.rng, S.blist, S.bscene, S.brad, S.ncnt,
+                                                  S.nlumc, S.bsrc, S.stage, S.stage_cap, S.nidx);
   TREVR_LAUNCH_CHECK("k_near_fill");
   return rc;
 }

@@ -68,7 +68,7 @@ __device__ inline uint32_t next_item(const Items& I, uint32_t* s_item) {
 }
 
 // Queue counter pairs of a scratch, one per item kernel.
-enum { Q_SETUP = 0, Q_FILL, Q_WALK, Q_PPR, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD, Q_N };
+enum { Q_SETUP = 0, Q_WALK, Q_PPR, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD, Q_N };
 
 // Order LDS writes of some lanes before reads by other lanes of the same
 // wavefront (the lanes execute together; this keeps the compiler and the
@@ -120,20 +120,54 @@ __device__ inline uint32_t wave_excl(uint32_t v, int lane) {
   return incl - v;
 }
 
+// Exclusive prefix over the wavefront of v < 2^BITS, from one ballot per
+// bit (no cross-lane data movement); *total gets the wavefront's sum.
+template <int BITS>
+__device__ inline uint32_t wave_excl_bits(uint32_t v, uint32_t* total) {
+  uint32_t e = 0, t = 0;
+#pragma unroll
+  for (int i = 0; i < BITS; ++i) {
+    const uint64_t m = ballot64((v >> i) & 1u);
+    e += (uint32_t)mbcnt(m) << i;
+    t += (uint32_t)__popcll(m) << i;
+  }
+  *total = t;
+  return e;
+}
+
 constexpr int kLeafBatch = 8;   // leaf elements loaded together by one lane
+static_assert(kLeafBatch <= 16, "a run keeps 16 member bits of each kind");
+constexpr int kLeafBatchBits = 4;   // bits of a count in [0, kLeafBatch]
+static_assert(kLeafBatch < (1 << kLeafBatchBits), "kLeafBatchBits too small");
+
+// Where a range query puts the elements it finds (out == nullptr: nowhere,
+// it only counts them).
+//  * slots (runs == false): the k-th luminous element found goes to
+//    out[lum0 + k], the k-th other one to out[dark0 + k];
+//  * runs (runs == true): each lane's members among kLeafBatch consecutive
+//    slots of one leaf make one run of two words, {first slot of the window,
+//    luminous member bits | other member bits << 16}; the i-th run found
+//    goes to out[2 (nrun + i)], and nrun counts the runs written.  A step
+//    that would take nrun past cap ends the writing (out becomes null: the
+//    set did not fit).
+struct NearOut {
+  uint32_t* out;
+  bool runs;
+  uint32_t lum0, dark0;
+  uint32_t nrun, cap;
+};
 
 // Range query by one wavefront: elements strictly within sqrt(r2) of c.
 // Returns the count; *hmax gets their largest size, *nlum the number that
-// emit.  With `out`, writes their sorted slots: luminous ones from out[0],
-// the others from out[lum_total].  Boxes are pruned conservatively (an
+// emit; the elements go where `o` says.  Boxes are pruned conservatively (an
 // element can sit an ulp outside its box after quantisation); membership is
 // the exact test.  With r2in >= 0, only the shell r2in <= d2 < r2 (cells
 // surely inside the inner sphere are skipped), so a sphere that grows can be
 // counted shell by shell with the same memberships.  The traversal stack
 // lives in `stack` (cap words).
 __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double r2, uint32_t* stack,
-                                     int cap, double* hmax, uint32_t* nlum, uint32_t* out,
-                                     uint32_t lum_total, bool* overflow, uint32_t* harg = nullptr,
+                                     int cap, double* hmax, uint32_t* nlum, NearOut& o,
+                                     bool* overflow, uint32_t* harg = nullptr,
                                      double r2in = -1.0) {
   const int lane = threadIdx.x & 63;
   const double prune = r2 * (1.0 + 1e-9);
@@ -151,83 +185,76 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
     const uint32_t node = valid ? stack[sp + lane] : 0u;
     __syncthreads();
     bool push = false;
-    uint32_t mine = 0, mylum = 0;
     uint2 lk = make_uint2(0, 0);
-    bool isleaf = false;
+    uint32_t len = 0;   // elements of the leaf this lane opened
     if (valid) {
       const uint4 nk = T.nk[node];
       double lo[3], hi[3];
       node_box(T.hdr, nk, lo, hi);
       if (!(dist2_box(lo, hi, c) > prune) && !(far2_box(lo, hi, c) < inner)) {
-        isleaf = (nk.w & META_LEAF) != 0u;
+        const bool isleaf = (nk.w & META_LEAF) != 0u;
         lk = T.nlink[node];
         push = !isleaf;
-        if (isleaf) {
-          // the leaf's elements kLeafBatch at a time, loads issued together
-          const uint32_t end = lk.x + lk.y;
-          for (uint32_t s0 = lk.x; s0 < end; s0 += kLeafBatch) {
-            float px[kLeafBatch], py[kLeafBatch], pz[kLeafBatch];
-            double ph[kLeafBatch], pl[kLeafBatch];
-#pragma unroll
-            for (int k = 0; k < kLeafBatch; ++k) {
-              const uint32_t s = min(s0 + (uint32_t)k, end - 1u);
-              px[k] = T.x[s];
-              py[k] = T.y[s];
-              pz[k] = T.z[s];
-              ph[k] = T.h[s];
-              pl[k] = T.lbol[s];
-            }
-#pragma unroll
-            for (int k = 0; k < kLeafBatch; ++k) {
-              const uint32_t s = s0 + (uint32_t)k;
-              if (s >= end) break;
-              const double d2 = dist2_pt3((double)px[k], (double)py[k], (double)pz[k], c);
-              if (d2 < r2 && !(d2 < r2in)) {
-                ++mine;
-                const double hs = ph[k];
-                if (hs > hm || (hs == hm && s < ha)) {   // smallest slot among equal sizes
-                  hm = hs;
-                  ha = s;
-                }
-                if (pl[k] > 0.0) ++mylum;
-              }
-            }
-          }
-        }
+        if (isleaf) len = lk.y;
       }
     }
-    if (out) {
-      const uint32_t lbase = lum + wave_excl(mylum, lane);
-      const uint32_t dbase = lum_total + (cnt - lum) + wave_excl(mine - mylum, lane);
-      if (isleaf && mine) {
-        uint32_t a = 0, b = 0;
-        const uint32_t end = lk.x + lk.y;
-        for (uint32_t s0 = lk.x; s0 < end; s0 += kLeafBatch) {
-          float px[kLeafBatch], py[kLeafBatch], pz[kLeafBatch];
-          double pl[kLeafBatch];
+    // the opened leaves' elements, kLeafBatch per lane at a time with the
+    // loads issued together, in step across the wavefront (ballots place the
+    // writes)
+    for (uint32_t s0 = 0; ballot64(s0 < len) != 0ull; s0 += kLeafBatch) {
+      float px[kLeafBatch], py[kLeafBatch], pz[kLeafBatch];
+      double ph[kLeafBatch], pl[kLeafBatch];
 #pragma unroll
-          for (int k = 0; k < kLeafBatch; ++k) {
-            const uint32_t s = min(s0 + (uint32_t)k, end - 1u);
-            px[k] = T.x[s];
-            py[k] = T.y[s];
-            pz[k] = T.z[s];
-            pl[k] = T.lbol[s];
-          }
+      for (int k = 0; k < kLeafBatch; ++k) {
+        const uint32_t s = len ? lk.x + min(s0 + (uint32_t)k, len - 1u) : 0u;
+        px[k] = T.x[s];
+        py[k] = T.y[s];
+        pz[k] = T.z[s];
+        ph[k] = T.h[s];
+        pl[k] = T.lbol[s];
+      }
+      uint32_t ml = 0, md = 0;   // members of this step that emit / do not
 #pragma unroll
-          for (int k = 0; k < kLeafBatch; ++k) {
-            const uint32_t s = s0 + (uint32_t)k;
-            if (s >= end) break;
-            const double d2 = dist2_pt3((double)px[k], (double)py[k], (double)pz[k], c);
-            if (d2 < r2 && !(d2 < r2in)) {
-              if (pl[k] > 0.0) out[lbase + a++] = s;
-              else out[dbase + b++] = s;
-            }
+      for (int k = 0; k < kLeafBatch; ++k) {
+        const uint32_t s = lk.x + s0 + (uint32_t)k;
+        const double d2 = dist2_pt3((double)px[k], (double)py[k], (double)pz[k], c);
+        if (s0 + (uint32_t)k < len && d2 < r2 && !(d2 < r2in)) {
+          const double hs = ph[k];
+          if (hs > hm || (hs == hm && s < ha)) {   // smallest slot among equal sizes
+            hm = hs;
+            ha = s;
           }
+          if (pl[k] > 0.0) ml |= 1u << k;
+          else md |= 1u << k;
         }
       }
+      uint32_t tl, td;
+      const uint32_t el = wave_excl_bits<kLeafBatchBits>((uint32_t)__popc(ml), &tl);
+      const uint32_t ed = wave_excl_bits<kLeafBatchBits>((uint32_t)__popc(md), &td);
+      if (o.out && o.runs) {
+        const bool has = (ml | md) != 0u;
+        const uint64_t hb = ballot64(has);
+        const uint32_t nr = (uint32_t)__popcll(hb);
+        if (nr > o.cap - o.nrun) {   // nrun <= cap while writing
+          o.out = nullptr;
+        } else {
+          if (has)
+            reinterpret_cast<uint2*>(o.out)[o.nrun + (uint32_t)mbcnt(hb)] =
+                make_uint2(lk.x + s0, ml | (md << 16));
+          o.nrun += nr;
+        }
+      } else if (o.out) {
+        uint32_t a = o.lum0 + lum + el, b = o.dark0 + (cnt - lum) + ed;
+#pragma unroll
+        for (int k = 0; k < kLeafBatch; ++k) {
+          const uint32_t s = lk.x + s0 + (uint32_t)k;
+          if ((ml >> k) & 1u) o.out[a++] = s;
+          if ((md >> k) & 1u) o.out[b++] = s;
+        }
+      }
+      cnt += tl + td;
+      lum += tl;
     }
-    cnt += wave_sum_u(mine);
-    lum += wave_sum_u(mylum);
     const uint64_t pm = ballot64(push);
     const int npush = __popcll(pm);
     if (sp + 2 * npush > cap) {

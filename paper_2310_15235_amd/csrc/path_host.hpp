@@ -32,11 +32,17 @@ struct Scratch {
   uint32_t *blist, *bscene, *bnact, *nlumc, *bstat;
   double *brad, *bprev;         // p-p radius; before its last growth (-1: none)
   uint32_t* barg;               // element that set the radius by that growth
+  uint32_t* bsrc;               // discovery index of each bucket
   // discovery order
   uint32_t *blist_raw, *bscene_raw, *bnact_raw, *ncnt_raw, *nlumc_raw, *bbin, *barg_raw;
   double *brad_raw, *bprev_raw;
   uint2* cut;
   size_t cut_entries;           // capacity of the cut-list buffer
+  // the p-p sets the bucket setup found, stage_cap words per bucket (a
+  // multiple of 64; 0: none) in discovery order; they live in the cut-list
+  // buffer, which holds nothing between the setup and the p-p lists
+  uint32_t* stage;
+  uint32_t stage_cap;
   // dynamic part
   uint32_t* nidx;
   float* tpp;

@@ -18,6 +18,14 @@ namespace trevr {
 constexpr int kStackSmall = 1024;
 constexpr int kStackLarge = 8192;
 constexpr uint32_t kCutCap = 2048;   // cut-list entries per bucket the buffer is sized for
+constexpr size_t kStageCap = 4096;   // most staging words per bucket for the p-p set
+constexpr uint32_t kNoRuns = 0xFFFFFFFFu;   // a staged p-p set that did not fit
+// Staged runs (two words each after a two-word header) sorted in LDS: their
+// count bound and the bits of a staging index in a sort key.
+constexpr uint32_t kSortRuns = 2048;
+constexpr int kSortIdxBits = 11;
+static_assert((kStageCap - 2) / 2 <= kSortRuns && kSortRuns <= (1u << kSortIdxBits),
+              "staged runs must fit the sort");
 
 // Bump allocator over a caller-owned buffer (base == nullptr: size only).
 struct Carve {
