@@ -272,9 +272,11 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
     bool push = false, emit = false, opened = false, isleaf = false;
     uint4 nk = make_uint4(0, 0, 0, 0);
     double4 cn = make_double4(0, 0, 0, 0);
+    uint2 nl = make_uint2(0u, 0u);   // loaded with the key, off the tests' path
     if (valid) {
       nk = T.nk[node];
       cn = T.cen[node];
+      nl = T.nlink[node];
       double lo[3], hi[3];
       node_box(T.hdr, nk, lo, hi);
       if (!(far2_box(lo, hi, c) < r2)) {
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
       break;
     }
     if (push) {
-      stack[sp + 2 * ppos] = T.nlink[node].x;      // child 1
+      stack[sp + 2 * ppos] = nl.x;                 // child 1
       stack[sp + 2 * ppos + 1] = node + 1u;        // child 0
     }
     sp += 2 * npush;
@@ -325,7 +327,7 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
     // the (bucket, element) pairs of this step spread over the lanes, in
     // lane order then element order
     const bool lumleaf = emit && opened && (nk.w & META_LUM);
-    const uint2 llk = lumleaf ? T.nlink[node] : make_uint2(0u, 0u);
+    const uint2 llk = lumleaf ? nl : make_uint2(0u, 0u);
     const uint32_t lbase = wave_excl(llk.y, lane);
     const uint32_t ltot = (uint32_t)__shfl((int)(lbase + llk.y), 63);
     if (ltot) {

@@ -189,11 +189,12 @@ __device__ inline uint32_t wave_near(const DevTree& T, const double c[3], double
     uint32_t len = 0;   // elements of the leaf this lane opened
     if (valid) {
       const uint4 nk = T.nk[node];
+      const uint2 nl = T.nlink[node];   // loaded with the key, off the box test's path
       double lo[3], hi[3];
       node_box(T.hdr, nk, lo, hi);
       if (!(dist2_box(lo, hi, c) > prune) && !(far2_box(lo, hi, c) < inner)) {
         const bool isleaf = (nk.w & META_LEAF) != 0u;
-        lk = T.nlink[node];
+        lk = nl;
         push = !isleaf;
         if (isleaf) len = lk.y;
       }
