@@ -197,9 +197,15 @@ trevr_status trevr_compute_J_backward(trevr_tree* t, const uint8_t* active, cons
  *   TREVR_TUNE_CUT    cut-list entries per bucket tried first, in [64, 2048]
  *                     (default 2048).  A batch with a longer cut list is
  *                     walked again in parts with room for the longest.
+ *   TREVR_TUNE_STAGE  words per bucket in which the bucket setup stages its
+ *                     p-p set for the list fill, in [0, 4096] (default 4096,
+ *                     used rounded down to a multiple of 64).  A set that
+ *                     does not fit is found again by a range query (0: every
+ *                     set), and its list is in traversal order instead of
+ *                     slot order.
  * Returns TREVR_E_INVALID for an unknown key or a value out of range.
  */
-enum { TREVR_TUNE_STACK = 0, TREVR_TUNE_CUT = 1 };
+enum { TREVR_TUNE_STACK = 0, TREVR_TUNE_CUT = 1, TREVR_TUNE_STAGE = 2 };
 trevr_status trevr_tree_tune(trevr_tree* t, int key, int64_t value);
 
 /* Scratch bytes the last compute_J or compute_J_backward on this tree needed

@@ -30,7 +30,7 @@ EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_compute_J_backward_batched", "trevr_forest_check",
             "trevr_forest_get_counters", "trevr_forest_scene", "trevr_forest_destroy",
             "trevr_forest_autotune", "trevr_forest_set_config", "trevr_forest_get_config")
-TUNE_STACK, TUNE_CUT = 0, 1
+TUNE_STACK, TUNE_CUT, TUNE_STAGE = 0, 1, 2
 CONFIGS = 8          # launch configurations of the forest autotuner
 PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree")
 PROF_SLOTS = len(PROF_NAMES)

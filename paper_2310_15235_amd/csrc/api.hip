@@ -181,6 +181,7 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, 0, 0, false, 0, false};
   T->stack_large = false;
   T->cut_default = kCutCap;
+  T->stage_limit = (uint32_t)kStageCap;
   for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }
   const size_t need = layout_tree(*p, n, T->nclass, nullptr, nullptr);
   if (tree_ws_bytes < need) {
@@ -268,6 +269,11 @@ trevr_status trevr_tree_tune(trevr_tree* t, int key, int64_t value) {
       if (value < 64 || value > (int64_t)kCutCap)
         return set_error(TREVR_E_INVALID, "cut-list length must be in [64, 2048]");
       t->cut_default = (uint32_t)value;
+      return TREVR_OK;
+    case TREVR_TUNE_STAGE:
+      if (value < 0 || value > (int64_t)kStageCap)
+        return set_error(TREVR_E_INVALID, "staging words must be in [0, 4096]");
+      t->stage_limit = (uint32_t)value;
       return TREVR_OK;
     default:
       return set_error(TREVR_E_INVALID, "unknown tuning key");

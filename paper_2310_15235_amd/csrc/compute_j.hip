@@ -1573,6 +1573,7 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
                             void* scratch, size_t scratch_bytes) {
   hipStream_t st = T->stream;
   Scratch S = carve_scratch(scratch, T->num_leaves, default_cut_entries(T->num_leaves));
+  S.stage_cap = std::min(S.stage_cap, T->stage_limit & ~63u);
   if (scratch_bytes < S.fixed) {
     T->scratch_needed = S.fixed;
     return set_error(TREVR_E_CAPACITY, "scratch smaller than its fixed part");

@@ -122,6 +122,7 @@ struct trevr_tree {
   FwdState fwd;
   bool stack_large;                         // traversals need the large LDS stack
   uint32_t cut_default;                     // cut-list entries per bucket to try first
+  uint32_t stage_limit;                     // most staging words per bucket for p-p sets
   // kernel timing (trevr_profile_enable)
   bool prof_on;
   std::vector<hipEvent_t> ev_pool;

@@ -263,13 +263,14 @@ def test_adjoint_with_scratch_shared_between_trees():
 
 def test_adjoint_with_large_stack_and_short_cut_lists():
     """The adjoint on a tree tuned to fall back to the large traversal stack
-    and to re-walk with longer cut lists equals the default one."""
+    and to re-walk with longer cut lists, or to find most p-p sets again in
+    the list fill, equals the default one."""
     api = _api()
     import torch
     sc = scenes.lognormal_scene(n=5000, seed=65, grid=16, bands=(1.0, 10.0), nside=2)
     g = torch.as_tensor(np.random.default_rng(11).normal(size=(2, sc.n)), device="cuda")
     out = []
-    for tune in ((), ((api.TUNE_STACK, 64), (api.TUNE_CUT, 64))):
+    for tune in ((), ((api.TUNE_STACK, 64), (api.TUNE_CUT, 64)), ((api.TUNE_STAGE, 64),)):
         T = api.Tree.from_scene(sc)
         for k, v in tune:
             T.tune(k, v)
@@ -277,8 +278,9 @@ def test_adjoint_with_large_stack_and_short_cut_lists():
         out.append([x.cpu().numpy() for x in T.compute_J_backward(g)])
         T.check()
         T.close()
-    for u, v in zip(*out):
-        _close(u, v, 1e-5)
+    for tuned in out[1:]:
+        for u, v in zip(out[0], tuned):
+            _close(u, v, 1e-5)
 
 
 @pytest.mark.parametrize("which", ["kappa", "rho", "lum"])

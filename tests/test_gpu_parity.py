@@ -290,3 +290,17 @@ def test_J_small_stack_limit_and_short_cut_lists():
     act = scenes.active_subset(sc, 0.1, 5)
     e, cg = compare_J(sc, active=act, tune=((api.TUNE_STACK, 64), (api.TUNE_CUT, 64)))
     assert cg["max_stack"] > 64 and cg["max_cut"] > 64
+
+
+@pytest.mark.parametrize("words", [0, 64])
+def test_J_p_p_lists_found_again_by_the_fill(words):
+    """The p-p lists are the same sets whether the bucket setup stages them
+    (written in slot order) or the list fill finds them again by a range
+    query (traversal order): staging off, and 64 words per bucket (31 runs:
+    the smallest sets staged, the others queried again, side by side in one
+    call).  J and every count match the oracle."""
+    api = _gpu()
+    sc = scenes.lognormal_scene(n=20000, seed=35, grid=32, bands=(1.0, 10.0), nside=2)
+    act = scenes.active_subset(sc, 0.3, 6)
+    e, cg = compare_J(sc, active=act, tune=((api.TUNE_STAGE, words),))
+    assert cg["max_near"] > 31 * 8
