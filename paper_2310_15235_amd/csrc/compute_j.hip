@@ -102,11 +102,9 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
                                               uint32_t* ncnt, uint32_t* nlumc, uint32_t* ovf,
                                               uint32_t* stage, uint32_t stage_cap) {
   __shared__ uint32_t stack[SC];
-  __shared__ uint32_t s_item;
   const int lane = threadIdx.x;
-  for (;;) {
-  const uint32_t b = next_item(I, &s_item);
-  if (b == kNoItem) break;
+  const uint32_t b = grid_item(I);
+  if (b == kNoItem) return;
   const DevTree& T = TT[bscene[b]];
   const uint32_t leaf = blist[b];
   double c[3];
@@ -152,7 +150,6 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
     nlumc[b] = nlum;
     if (stage_cap) stage[(size_t)b * stage_cap] = o.out ? o.nrun : kNoRuns;
     if (overflow) atomicOr(ovf, OVF_SETUP);
-  }
   }
 }
 
@@ -246,11 +243,10 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
                                              const double* brad, uint2* cut, uint32_t cap,
                                              uint32_t* bstat, uint32_t* ovf) {
   __shared__ uint32_t stack[SC];
-  __shared__ uint32_t s_item, lfirst[64], lbeg[64];
+  __shared__ uint32_t lfirst[64], lbeg[64];
   const int lane = threadIdx.x;
-  for (;;) {
-  const uint32_t bucket = next_item(I, &s_item);
-  if (bucket == kNoItem) break;
+  const uint32_t bucket = grid_item(I);
+  if (bucket == kNoItem) return;
   const DevTree& T = TT[bscene[bucket]];
   const uint32_t leafb = blist[bucket];
   const double r = brad[bucket];
@@ -371,7 +367,6 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
     atomicMax(ovf + 1, ncut);
     atomic_max_u64(&T.counters[CNT_MAX_CUT], ncut);
     atomic_max_u64(&T.counters[CNT_MAX_STACK], (unsigned long long)maxsp);
-  }
   }
 }
 
@@ -1332,18 +1327,16 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
   k_active_buckets<<<gn, 256, 0, st>>>(L.TT, active, S.blist_raw, S.bscene_raw, S.bnact_raw,
                                        S.rng + 1);
   TREVR_LAUNCH_CHECK("k_active_buckets");
-  const Items I{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_SETUP};
-  if (L.stack_large) {
-    const void* fn = (const void*)&k_setup<kStackLarge>;
-    k_setup<kStackLarge><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
-        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.barg_raw, S.ncnt_raw,
-        S.nlumc_raw, S.ovf, S.stage, S.stage_cap);
-  } else {
-    const void* fn = (const void*)&k_setup<kStackSmall>;
-    k_setup<kStackSmall><<<persistent_grid(fn, 64, L.leaves, L.cfg.grid_div), 64, 0, st>>>(
-        L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw, S.bprev_raw, S.barg_raw, S.ncnt_raw,
-        S.nlumc_raw, S.ovf, S.stage, S.stage_cap);
-  }
+  const Items I{0u, 0xFFFFFFFFu, S.rng, nullptr};
+  const unsigned gb = grid_of(L.leaves, 1);
+  if (L.stack_large)
+    k_setup<kStackLarge><<<gb, 64, 0, st>>>(L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw,
+                                             S.bprev_raw, S.barg_raw, S.ncnt_raw, S.nlumc_raw,
+                                             S.ovf, S.stage, S.stage_cap);
+  else
+    k_setup<kStackSmall><<<gb, 64, 0, st>>>(L.TT, I, S.blist_raw, S.bscene_raw, S.brad_raw,
+                                             S.bprev_raw, S.barg_raw, S.ncnt_raw, S.nlumc_raw,
+                                             S.ovf, S.stage, S.stage_cap);
   TREVR_LAUNCH_CHECK("k_setup");
   const unsigned gl = grid_of(L.leaves, 256);
   k_cost_bins<<<gl, 256, 0, st>>>(L.TT, S.rng + 1, S.bscene_raw, S.bnact_raw, S.ncnt_raw,
@@ -1449,15 +1442,13 @@ trevr_status walk_launch(const Launch& L, const Scratch& S, const Items& I, uint
                          uint32_t cap) {
   trevr_status rc;
   if ((rc = zero_words(L.st, S.ovf, 2)) != TREVR_OK) return rc;
-  if (L.stack_large) {
-    const void* fn = (const void*)&k_walk<kStackLarge>;
-    k_walk<kStackLarge><<<persistent_grid(fn, 64, count, L.cfg.grid_div), 64, 0, L.st>>>(
-        L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap, S.bstat, S.ovf);
-  } else {
-    const void* fn = (const void*)&k_walk<kStackSmall>;
-    k_walk<kStackSmall><<<persistent_grid(fn, 64, count, L.cfg.grid_div), 64, 0, L.st>>>(
-        L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap, S.bstat, S.ovf);
-  }
+  const unsigned gb = grid_of((int64_t)count, 1);
+  if (L.stack_large)
+    k_walk<kStackLarge><<<gb, 64, 0, L.st>>>(L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap,
+                                              S.bstat, S.ovf);
+  else
+    k_walk<kStackSmall><<<gb, 64, 0, L.st>>>(L.TT, I, S.blist, S.bscene, S.brad, S.cut, cap,
+                                              S.bstat, S.ovf);
   TREVR_LAUNCH_CHECK("k_walk");
   return rc;
 }
@@ -1469,7 +1460,7 @@ trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t c
   uint32_t* hbuf = T->host_u32;
   for (;;) {
     hipEvent_t ev = prof_begin(T);
-    if ((rc = walk_launch(tree_launch(T), S, host_items(S, Q_WALK, b0, cnt), cnt,
+    if ((rc = walk_launch(tree_launch(T), S, Items{b0, b0 + cnt, nullptr, nullptr}, cnt,
                           T->cut_default)) != TREVR_OK)
       return rc;
     prof_end(T, TREVR_PROF_WALK, ev);
@@ -1496,7 +1487,7 @@ trevr_status walk_batch(trevr_tree* T, const Scratch& S, uint32_t b0, uint32_t c
   for (uint32_t s0 = b0; s0 < b0 + cnt; s0 += per) {
     const uint32_t scnt = std::min<uint32_t>(per, b0 + cnt - s0);
     hipEvent_t ev = prof_begin(T);
-    if ((rc = walk_launch(tree_launch(T), S, host_items(S, Q_WALK, s0, scnt), scnt,
+    if ((rc = walk_launch(tree_launch(T), S, Items{s0, s0 + scnt, nullptr, nullptr}, scnt,
                           (uint32_t)cap2)) != TREVR_OK)
       return rc;
     prof_end(T, TREVR_PROF_WALK, ev);

@@ -172,7 +172,7 @@ trevr_status forward_body(const trevr_forest* f, const Scratch& S, const uint8_t
   const Launch L = forest_launch(f);
   trevr_status rc;
   if ((rc = near_fill(L, S)) != TREVR_OK) return rc;
-  if ((rc = walk_launch(L, S, Items{0u, 0xFFFFFFFFu, S.rng, S.q + 2 * Q_WALK},
+  if ((rc = walk_launch(L, S, Items{0u, 0xFFFFFFFFu, S.rng, nullptr},
                         (uint64_t)f->leaves_total, f->cut_cap)) != TREVR_OK)
     return rc;
   for (int B = 1; B <= kMaxBands; ++B) {
@@ -239,7 +239,7 @@ trevr_status forest_plan_impl(trevr_forest* f, void* scratch, size_t bytes) {
     // its capacity, so one pass gives the longest cut list
     for (uint32_t b0 = 0; b0 < nb && !over; b0 += kBatch) {
       const uint32_t cnt = std::min<uint32_t>(kBatch, nb - b0);
-      if ((rc = walk_launch(L, S, Items{b0, b0 + cnt, nullptr, S.q + 2 * Q_WALK}, cnt,
+      if ((rc = walk_launch(L, S, Items{b0, b0 + cnt, nullptr, nullptr}, cnt,
                             kCutCap)) != TREVR_OK)
         return rc;
       e = hipMemcpyAsync(hb, S.ovf, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);

@@ -35,7 +35,8 @@ constexpr double kR = 0.48860251190291992;   // (3/(4 pi))^(1/2)
 // workgroups (as many as are resident on the chip at once) takes the items
 // in order through the counter q[0]; q[1] counts the workgroups that found
 // none left, and the last of them clears both, so the pair is zero before
-// and after every launch (the caller zeroes it once per scratch use).
+// and after every launch (the caller zeroes it once per scratch use).  A plain
+// grid launch (grid_item) leaves q unused; it may be null there.
 constexpr uint32_t kNoItem = 0xFFFFFFFFu;
 struct Items {
   uint32_t lo, hi;
@@ -67,8 +68,23 @@ __device__ inline uint32_t next_item(const Items& I, uint32_t* s_item) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)*s_item);
 }
 
+// The item of this workgroup in a plain grid launch of one workgroup per
+// item (blockIdx.x counts from the start of the range), kNoItem past its
+// end.  The light per-bucket kernels (setup, walk) launch this way: the
+// hardware hands out workgroups in order, and a work-queue claim would cost
+// them more than it balances.
+__device__ inline uint32_t grid_item(const Items& I) {
+  uint32_t b = I.lo, e = I.hi;
+  if (I.rng) {
+    b = max(b, I.rng[0]);
+    e = min(e, I.rng[1]);
+  }
+  const uint32_t it = b + blockIdx.x;
+  return (b < e && it < e) ? it : kNoItem;
+}
+
 // Queue counter pairs of a scratch, one per item kernel.
-enum { Q_SETUP = 0, Q_WALK, Q_PPR, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD, Q_N };
+enum { Q_PPR = 0, Q_PPS, Q_FAR, Q_PPS_BWD, Q_FAR_BWD, Q_PPR_BWD, Q_N };
 
 // Order LDS writes of some lanes before reads by other lanes of the same
 // wavefront (the lanes execute together; this keeps the compiler and the
