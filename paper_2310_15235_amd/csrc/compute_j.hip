@@ -161,7 +161,8 @@ __global__ void __launch_bounds__(64) k_setup(const DevTree* __restrict__ TT, It
 // the staging index breaks ties between two shells' members of one window),
 // then placed by a prefix over their member counts.  The others query the
 // sphere again (the same sphere as the last query of k_setup, so the same
-// stack suffices).
+// stack suffices) and, for trees of up to 64 x (LDS words) elements, are put
+// in slot order through a bitmap.
 template <int SC>
 __global__ void __launch_bounds__(64) k_near_fill(const DevTree* __restrict__ TT,
                                                   const uint32_t* rng, const uint32_t* blist,
@@ -231,6 +232,37 @@ __global__ void __launch_bounds__(64) k_near_fill(const DevTree* __restrict__ TT
   NearOut o{out, false, 0u, nl, 0u, 0u};
   wave_near(T, c, r * r, reinterpret_cast<uint32_t*>(lds), stack_cap<SC>(T), nullptr, nullptr, o,
             &overflow);
+  // the queried list into slot order as well, when a bitmap of the tree's
+  // slots fits the LDS: each part (luminous, others) marked, then read back
+  // in order, a contiguous range of bitmap words per lane
+  uint32_t* bits = reinterpret_cast<uint32_t*>(lds);
+  constexpr uint32_t kBitWords = 2u * (uint32_t)kWords;
+  const uint32_t words = (uint32_t)((T.n + 31) / 32), n = noff[b + 1] - noff[b];
+  if (overflow || words > kBitWords) return;
+  for (int part = 0; part < 2; ++part) {
+    const uint32_t lo = part ? nl : 0u, hi = part ? n : nl;
+    if (hi - lo < 2u) continue;
+    __syncthreads();
+    for (uint32_t w = lane; w < words; w += 64) bits[w] = 0u;
+    __syncthreads();
+    for (uint32_t k = lo + lane; k < hi; k += 64) {
+      const uint32_t e = out[k];
+      if (e < (uint32_t)T.n) atomicOr(&bits[e >> 5], 1u << (e & 31u));
+    }
+    __syncthreads();
+    const uint32_t per = (words + 63u) / 64u;
+    const uint32_t w0 = min(words, lane * per), w1 = min(words, w0 + per);
+    uint32_t cnt = 0;
+    for (uint32_t w = w0; w < w1; ++w) cnt += (uint32_t)__popc(bits[w]);
+    uint32_t pos = lo + wave_excl(cnt, (int)lane);
+    for (uint32_t w = w0; w < w1; ++w) {
+      uint32_t m = bits[w];
+      while (m && pos < hi) {
+        out[pos++] = w * 32u + (uint32_t)(__ffs(m) - 1);
+        m &= m - 1u;
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------- the walk
