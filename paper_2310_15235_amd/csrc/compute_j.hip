@@ -73,16 +73,27 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_active_hash(const DevTree* __restrict__ TT, const uint8_t* active,
-                              unsigned long long* out) {
+// A few workgroups per scene, each striding over the elements and adding
+// its sum with one atomic (one atomic per wavefront over all elements queued
+// thousands of them on the one address).
+constexpr unsigned kHashBlocks = 128;
+__global__ void __launch_bounds__(256) k_active_hash(const DevTree* __restrict__ TT,
+                                                     const uint8_t* active,
+                                                     unsigned long long* out) {
+  __shared__ unsigned long long part[4];
   const DevTree& T = TT[blockIdx.y];
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   unsigned long long v = 0ull;
-  if (i < T.n && (active == nullptr || active[T.eoff + i]))
-    v = mix64((unsigned long long)(T.eoff + i) + 1ull);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < T.n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (active == nullptr || active[T.eoff + i]) v += mix64((unsigned long long)(T.eoff + i) + 1ull);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += (unsigned long long)__shfl_xor((long long)v, o);
-  if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long sum = part[0] + part[1] + part[2] + part[3];
+    if (sum) atomicAdd(out, sum);
+  }
 }
 
 // p-p radius (Section 2.4): past every bucket member by its size, then grown
@@ -1387,7 +1398,7 @@ trevr_status setup_kernels(const Launch& L, const uint8_t* active, const Scratch
   const int64_t Lp = std::max<int64_t>(L.leaves, 1) + 1;
   k_scan_arrays<<<4, 1024, 0, st>>>(ScanArrays{{S.ncnt, S.tcnt, S.jcnt, S.pcnt}}, Lp);
   TREVR_LAUNCH_CHECK("k_scan_arrays");
-  const dim3 ge(grid_of(L.max_n, 256), (unsigned)L.S);
+  const dim3 ge(std::min(grid_of(L.max_n, 256), kHashBlocks), (unsigned)L.S);
   k_active_hash<<<ge, 256, 0, st>>>(L.TT, active, S.ahash);
   TREVR_LAUNCH_CHECK("k_active_hash");
   return TREVR_OK;
@@ -1397,7 +1408,7 @@ trevr_status launch_active_hash(const Launch& L, const uint8_t* active,
                                 unsigned long long* out) {
   trevr_status rc;
   if ((rc = zero_words(L.st, out, 2)) != TREVR_OK) return rc;
-  const dim3 ge(grid_of(L.max_n, 256), (unsigned)L.S);
+  const dim3 ge(std::min(grid_of(L.max_n, 256), kHashBlocks), (unsigned)L.S);
   k_active_hash<<<ge, 256, 0, L.st>>>(L.TT, active, out);
   TREVR_LAUNCH_CHECK("k_active_hash");
   return rc;
@@ -1445,7 +1456,7 @@ trevr_status active_hash(trevr_tree* T, const uint8_t* active, unsigned long lon
   hipStream_t st = T->stream;
   trevr_status rc;
   if ((rc = zero_words(st, dev_slot, 2)) != TREVR_OK) return rc;
-  const dim3 ge(grid_of(T->n, 256), 1u);
+  const dim3 ge(std::min(grid_of(T->n, 256), kHashBlocks), 1u);
   k_active_hash<<<ge, 256, 0, st>>>(T->buf.dev, active, dev_slot);
   TREVR_LAUNCH_CHECK("k_active_hash");
   uint32_t* hbuf = T->host_u32;
