@@ -1207,10 +1207,19 @@ __global__ void __launch_bounds__(256) k_reorder(const DevTree* __restrict__ TT,
     v[3] = (unsigned long long)na * B;
     v[4] = na;
   }
+  // per-workgroup sums, then one atomic per total (the totals share a cache
+  // line, so every atomic on them queues behind the others)
+  __shared__ unsigned long long part[4][5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const unsigned long long s = wave_sum_u64(v[k]);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&tot[k], s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const unsigned long long s = part[0][threadIdx.x] + part[1][threadIdx.x] +
+                                 part[2][threadIdx.x] + part[3][threadIdx.x];
+    if (s) atomicAdd(&tot[threadIdx.x], s);
   }
 }
 
