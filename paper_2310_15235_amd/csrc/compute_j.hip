@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
     bstat[4 * bucket + 1] = nsrc;
     bstat[4 * bucket + 2] = ncells;
     if (overflow) atomicOr(ovf, OVF_WALK);
-    atomicMax(ovf + 1, ncut);
+    if (ncut > __atomic_load_n(ovf + 1, __ATOMIC_RELAXED)) atomicMax(ovf + 1, ncut);
     atomic_max_u64(&T.counters[CNT_MAX_CUT], ncut);
     atomic_max_u64(&T.counters[CNT_MAX_STACK], (unsigned long long)maxsp);
   }
@@ -525,6 +525,17 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
   }
 }
 
+// Adds (none when dst is null) and clears the p-p source kernel's counter
+// sums: near pairs, (receiver, source, element) triples and the largest set.
+__device__ inline void pp_counters_flush(unsigned long long* dst, unsigned long long* s) {
+  if (dst) {
+    if (s[0]) atomicAdd(&dst[CNT_NEAR_PAIRS], s[0]);
+    if (s[1]) atomicAdd(&dst[CNT_NS_TRIPLES], s[1]);
+    if (s[2]) atomic_max_u64(&dst[CNT_MAX_NEAR], s[2]);
+  }
+  s[0] = s[1] = s[2] = 0ull;
+}
+
 // For each receiver i and luminous p-p element j (i itself included, at
 // r = 0): L_j K(r_ij, h_i) exp(-tau_ij), tau over the p-p elements closer to
 // j than i is (exact FP64 squared distances: discontinuous) and within their
@@ -560,6 +571,14 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   __shared__ uint8_t pd_valid[kNT];
   __shared__ float tacc[kNT][NB];
   __shared__ uint8_t nlist[kNT / 64][64];
+  // the workgroup's sums of the per-bucket counters (thread 0), added to a
+  // scene's counters when it turns to another scene and after its last bucket
+  __shared__ unsigned long long csum[3];   // near pairs, triples, largest set
+  __shared__ unsigned long long* cdst;
+  if (threadIdx.x == 0) {
+    cdst = nullptr;
+    csum[0] = csum[1] = csum[2] = 0ull;
+  }
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -848,14 +867,34 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     }
   }
   if (J && t == 0) {
-    atomicAdd(&T.counters[CNT_NEAR_PAIRS], (unsigned long long)nact * nnear);
-    atomicAdd(&T.counters[CNT_NS_TRIPLES], (unsigned long long)nact * nl * nnear);
-    atomic_max_u64(&T.counters[CNT_MAX_NEAR], (unsigned long long)nnear);
+    if (T.counters != cdst) {
+      pp_counters_flush(cdst, csum);
+      cdst = T.counters;
+    }
+    csum[0] += (unsigned long long)nact * nnear;
+    csum[1] += (unsigned long long)nact * nl * nnear;
+    csum[2] = max(csum[2], (unsigned long long)nnear);
   }
   }
+  if (Jall && threadIdx.x == 0) pp_counters_flush(cdst, csum);
 }
 
 // ------------------------------------------------------------- far field
+// Adds a workgroup's sums of the far field's per-bucket counters to a
+// scene's counters (none when dst is null) and clears them.  Thread 0 keeps
+// the sums in LDS across its workgroup's buckets and adds them when it turns
+// to another scene and after its last bucket: the counters share a cache
+// line, so a set of atomics per bucket queued behind one another.
+constexpr int kFarCounters = 6;
+__device__ inline void far_counters_flush(unsigned long long* dst, unsigned long long* s) {
+  const int slot[kFarCounters] = {CNT_BUCKETS, CNT_CELLS, CNT_ABS, CNT_SRC, CNT_SEG, CNT_SRC_PAIRS};
+#pragma unroll
+  for (int k = 0; k < kFarCounters; ++k) {
+    if (dst && s[k]) atomicAdd(&dst[slot[k]], s[k]);
+    s[k] = 0ull;
+  }
+}
+
 // One workgroup of kFT threads per bucket.  Rays are taken in groups of 64;
 // thread k < 64 owns ray k of the group for the per-ray sort and the suffix
 // sums; hits are found and applied by whichever thread holds the cut entry.
@@ -884,7 +923,13 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
   __shared__ uint32_t nrecv_s, wcnt[kFT / 64], abs_count, s_item;
   __shared__ double red[kFT / 64][kRMax][NB];
   __shared__ uint32_t hitq[kFT / 64][kHitQ];   // per wavefront: queued (entry, ray) tests
+  __shared__ unsigned long long csum[kFarCounters];
+  __shared__ unsigned long long* cdst;
 
+  if (threadIdx.x == 0) {
+    cdst = nullptr;
+    far_counters_flush(nullptr, csum);
+  }
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -1076,15 +1121,19 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
   if (t == 0) {
     const uint32_t nsrc = bstat[4 * bucket + 1], ncells = bstat[4 * bucket + 2];
     const uint32_t nabs_total = abs_count;
-    atomicAdd(&T.counters[CNT_BUCKETS], 1ull);
-    atomicAdd(&T.counters[CNT_CELLS], (unsigned long long)ncells);
-    atomicAdd(&T.counters[CNT_ABS], (unsigned long long)nabs_total);
-    atomicAdd(&T.counters[CNT_SRC], (unsigned long long)nsrc);
-    atomicAdd(&T.counters[CNT_SEG],
-              (unsigned long long)nact_total * ((unsigned long long)nray + nabs_total + nsrc));
-    atomicAdd(&T.counters[CNT_SRC_PAIRS], (unsigned long long)nact_total * nsrc);
+    if (T.counters != cdst) {
+      far_counters_flush(cdst, csum);
+      cdst = T.counters;
+    }
+    csum[0] += 1ull;
+    csum[1] += (unsigned long long)ncells;
+    csum[2] += (unsigned long long)nabs_total;
+    csum[3] += (unsigned long long)nsrc;
+    csum[4] += (unsigned long long)nact_total * ((unsigned long long)nray + nabs_total + nsrc);
+    csum[5] += (unsigned long long)nact_total * nsrc;
   }
   }
+  if (threadIdx.x == 0) far_counters_flush(cdst, csum);
 }
 
 // ----------------------------------------------------- bucket ordering

@@ -95,8 +95,11 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The atomic only when v exceeds the value read first (a stale read is never
+// larger than the current value, so no update is lost): most callers'
+// values stop exceeding the maximum early, and atomics on one address queue.
 __device__ inline void atomic_max_u64(unsigned long long* a, unsigned long long v) {
-  atomicMax(a, v);
+  if (v > __atomic_load_n(a, __ATOMIC_RELAXED)) atomicMax(a, v);
 }
 
 __device__ inline void leaf_centre(const DevTree& T, uint32_t leaf, double c[3]) {
