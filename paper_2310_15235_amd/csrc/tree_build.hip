@@ -42,8 +42,8 @@ __global__ void k_init(uint32_t* bbox_u, uint32_t* err, unsigned long long* coun
   if (t == 0) *alloc = 1u;
 }
 
-__global__ void k_bbox(const float* x, const float* y, const float* z, int64_t n,
-                       uint32_t* bbox_u) {
+__global__ void __launch_bounds__(256) k_bbox(const float* x, const float* y, const float* z,
+                                              int64_t n, uint32_t* bbox_u) {
   uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -58,9 +58,24 @@ __global__ void k_bbox(const float* x, const float* y, const float* z, int64_t n
       mx[a] = max(mx[a], (uint32_t)__shfl_xor((int)mx[a], o));
     }
   }
+  // per workgroup, then one set of atomics (the six words share a cache line,
+  // so atomics on them queue behind one another)
+  __shared__ uint32_t part[4][6];
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) { atomicMin(&bbox_u[a], mn[a]); atomicMax(&bbox_u[3 + a], mx[a]); }
+    for (int a = 0; a < 3; ++a) {
+      part[threadIdx.x >> 6][a] = mn[a];
+      part[threadIdx.x >> 6][3 + a] = mx[a];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    uint32_t v = part[0][a];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w)
+      v = a < 3 ? min(v, part[w][a]) : max(v, part[w][a]);
+    if (a < 3) atomicMin(&bbox_u[a], v);
+    else atomicMax(&bbox_u[a], v);
   }
 }
 
@@ -548,7 +563,7 @@ trevr_status build_tree_impl(trevr_tree* T, const float* x, const float* y, cons
   k_init<<<1, 64, 0, st>>>(tb.bbox_u, tb.err, tb.counters, tb.alloc);
   TREVR_LAUNCH_CHECK("k_init");
   if (!(T->p.box[3] > 0.0)) {
-    k_bbox<<<std::min<int64_t>(1024, grid_for(n, 256)), 256, 0, st>>>(x, y, z, n, tb.bbox_u);
+    k_bbox<<<std::min<int64_t>(64, grid_for(n, 256)), 256, 0, st>>>(x, y, z, n, tb.bbox_u);
     TREVR_LAUNCH_CHECK("k_bbox");
   }
   k_header<<<1, 64, 0, st>>>(tb.bbox_u, T->p.box[0], T->p.box[1], T->p.box[2], T->p.box[3],
