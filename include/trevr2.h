@@ -58,7 +58,16 @@ enum {
                             (Section 2.4); off: r_pp = 0                      */
   TREVR_BACKGROUND = 4u, /* isotropic background intensity entering at the
                             root-cube boundary (abstract; Section 4)          */
-  TREVR_KEEP_DEPTHS = 8u /* memory for time in the adjoint: the forward keeps
+  TREVR_ABSORPTION_AVG = 8u, /* linear absorption averaging (Section 2.6, the
+                            scheme the transmission average replaces): a
+                            cell larger than a bucket takes the volume-weighted
+                            linear mean of its two halves' absorption
+                            coefficients, (a1 + a2)/2 on the split box, halved
+                            again for every empty prefix box up to the owned
+                            box (vacuum), the same in every direction.  This
+                            is the first-order limit of the transmission
+                            average; buckets keep sum(kappa m)/sum(m/rho).    */
+  TREVR_KEEP_DEPTHS = 16u /* memory for time in the adjoint: the forward keeps
                             each far source's cell optical depth (and each
                             ray's exit depth with TREVR_BACKGROUND) in the
                             scratch, per (bucket, ray group) whose sources fit
@@ -74,7 +83,8 @@ typedef struct trevr_params {
   int32_t nside;     /* HEALPix N_side, a power of two in [1, 8]; N_ray = 12 nside^2
                         (Sections 1.3, 2.5; paper default 2, i.e. 48 rays)          */
   int32_t leaf_size; /* bucket capacity, >= 1 (Section 2.3; paper default 12)       */
-  int32_t n_bands;   /* B in [1, 8]                                                 */
+  int32_t n_bands;   /* B in [1, 16] (kernels are compiled per band count; the
+                        paper runs up to 10 bands, Section 3.1)                    */
   uint32_t flags;    /* TREVR_* flags                                               */
   double theta;      /* opening parameter theta_rad >= 0 (Section 2.5.2; 0.75)      */
   double rpp_min;    /* lower bound of the p-p radius (>= 0; 0 = paper's rule)      */

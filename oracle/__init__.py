@@ -26,6 +26,7 @@ _SO = os.path.join(_HERE, "liboracle_trevr.so")
 THICK_CORR = 1
 NEAR_FIELD = 2
 BACKGROUND = 4
+ABSORPTION_AVG = 8
 
 COUNTER_NAMES = ("buckets", "cells", "absorber_entries", "source_entries", "segments",
                  "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples")
@@ -100,6 +101,8 @@ def scene_flags(scene) -> int:
         f |= NEAR_FIELD
     if scene.background:
         f |= BACKGROUND
+    if getattr(scene, "absorption_avg", False):
+        f |= ABSORPTION_AVG
     return f
 
 

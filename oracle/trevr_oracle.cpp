@@ -82,7 +82,7 @@ struct Params {
   double rpp_min;
   double box[4];
 };
-enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u };
+enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u, F_AVG = 8u };
 
 enum { C_BUCKETS = 0, C_CELLS, C_ABS, C_SRC, C_SEG, C_NEAR_PAIRS, C_MAX_NEAR, C_NODES,
        C_SRC_PAIRS, C_NS_TRIPLES, C_N };
@@ -495,8 +495,20 @@ void compute_moments(const Tree& t, const PartT<T>& P, Mom<T>& mo) {
           chain.push_back(combine_geom(s, l % 3, n));
         }
         for (int b = 0; b < B; ++b) {
-          T A = combine_alpha(geo, mo.alpha[(a0 * D + j) * B + b], mo.alpha[(a1 * D + j) * B + b]);
-          for (const CombineGeom& cg : chain) A = combine_alpha(cg, A, T(0.0));
+          const T& al1 = mo.alpha[(a0 * D + j) * B + b];
+          const T& al2 = mo.alpha[(a1 * D + j) * B + b];
+          T A;
+          if (t.p.flags & F_AVG) {
+            // Linear absorption average (Section 2.6, the scheme transmission
+            // averaging replaces): absorption coefficients weighted by volume.
+            // The two children fill equal halves of the split box; every
+            // empty prefix box above it doubles the volume with vacuum.
+            A = (al1 + al2) / 2.0;
+            for (size_t q = 0; q < chain.size(); ++q) A = A / 2.0;
+          } else {
+            A = combine_alpha(geo, al1, al2);
+            for (const CombineGeom& cg : chain) A = combine_alpha(cg, A, T(0.0));
+          }
           mo.alpha[(nd * D + j) * B + b] = A;
         }
       }

@@ -18,7 +18,7 @@ SO_PATH = os.path.join(HERE, "libtrevr2.so")
 
 # status codes and flags (include/trevr2.h)
 OK, E_INVALID, E_CAPACITY, E_HIP, E_STATE, E_DATA = range(6)
-THICK_CORR, NEAR_FIELD, BACKGROUND, KEEP_DEPTHS = 1, 2, 4, 8
+THICK_CORR, NEAR_FIELD, BACKGROUND, ABSORPTION_AVG, KEEP_DEPTHS = 1, 2, 4, 8, 16
 
 EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_compute_J_backward", "trevr_tree_tune",
@@ -342,7 +342,8 @@ def compute_J_backward(scene, gJ, active=None, device="cuda", extra_flags=0):
 
 def scene_flags(scene) -> int:
     return (THICK_CORR if scene.thick_corr else 0) | (NEAR_FIELD if scene.near_field else 0) | \
-        (BACKGROUND if scene.background else 0)
+        (BACKGROUND if scene.background else 0) | \
+        (ABSORPTION_AVG if getattr(scene, "absorption_avg", False) else 0)
 
 
 class Forest:

@@ -39,9 +39,9 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
     return set_error(TREVR_E_INVALID, "nside must be a power of two in [1, 8]");
   if (p->leaf_size < 1) return set_error(TREVR_E_INVALID, "leaf_size must be >= 1");
   if (p->n_bands < 1 || p->n_bands > kMaxBands)
-    return set_error(TREVR_E_INVALID, "n_bands must be in [1, 8]");
+    return set_error(TREVR_E_INVALID, "n_bands must be in [1, 16]");
   if (p->flags & ~(uint32_t)(TREVR_THICK_CORR | TREVR_NEAR_FIELD | TREVR_BACKGROUND |
-                            TREVR_KEEP_DEPTHS))
+                            TREVR_ABSORPTION_AVG | TREVR_KEEP_DEPTHS))
     return set_error(TREVR_E_INVALID, "unknown flag bits");
   if (!(p->theta >= 0.0) || !std::isfinite(p->theta))
     return set_error(TREVR_E_INVALID, "theta must be finite and >= 0");

@@ -1641,7 +1641,15 @@ static trevr_status far_nb(const Launch& L, const Scratch& S, const Items& I, ui
     case 5: { constexpr int NB = 5; return call; } \
     case 6: { constexpr int NB = 6; return call; } \
     case 7: { constexpr int NB = 7; return call; } \
-    default: { constexpr int NB = 8; return call; } \
+    case 8: { constexpr int NB = 8; return call; } \
+    case 9: { constexpr int NB = 9; return call; } \
+    case 10: { constexpr int NB = 10; return call; } \
+    case 11: { constexpr int NB = 11; return call; } \
+    case 12: { constexpr int NB = 12; return call; } \
+    case 13: { constexpr int NB = 13; return call; } \
+    case 14: { constexpr int NB = 14; return call; } \
+    case 15: { constexpr int NB = 15; return call; } \
+    default: { constexpr int NB = 16; return call; } \
   }
 
 trevr_status launch_pp_rays(const Launch& L, int B, const Scratch& S, const Items& I,

@@ -1082,14 +1082,19 @@ __global__ void k_tree_bwd(const DevTree* __restrict__ TT, int depth, Grad Gall)
     const double g = G.galpha[((int64_t)p * nclass + c) * B + b];
     if (g == 0.0) continue;
     double d1, d2;
-    double A = combine64_d(&T.geom[((int64_t)s * nclass + c) * 3], L,
-                           T.alpha64[((int64_t)p0 * nclass + c) * B + b],
-                           T.alpha64[((int64_t)p1 * nclass + c) * B + b], &d1, &d2);
     double D = 1.0;
-    for (int mm = s - 1; mm >= l; --mm) {
-      double e1, e2;
-      A = combine64_d(&T.geom[((int64_t)mm * nclass + c) * 3], L, A, 0.0, &e1, &e2);
-      D *= e1;
+    if (T.flags & TREVR_ABSORPTION_AVG) {
+      d1 = d2 = 0.5;
+      for (int mm = s - 1; mm >= l; --mm) D *= 0.5;
+    } else {
+      double A = combine64_d(&T.geom[((int64_t)s * nclass + c) * 3], L,
+                             T.alpha64[((int64_t)p0 * nclass + c) * B + b],
+                             T.alpha64[((int64_t)p1 * nclass + c) * B + b], &d1, &d2);
+      for (int mm = s - 1; mm >= l; --mm) {
+        double e1, e2;
+        A = combine64_d(&T.geom[((int64_t)mm * nclass + c) * 3], L, A, 0.0, &e1, &e2);
+        D *= e1;
+      }
     }
     G.galpha[((int64_t)p0 * nclass + c) * B + b] += g * D * d1;
     G.galpha[((int64_t)p1 * nclass + c) * B + b] += g * D * d2;
@@ -1251,7 +1256,15 @@ trevr_status bwd_items(const Launch& L, int B, const Scratch& S, const BwdArgs& 
     case 5: return bwd_items_nb<5>(L, S, a, I, count, cap, prof);
     case 6: return bwd_items_nb<6>(L, S, a, I, count, cap, prof);
     case 7: return bwd_items_nb<7>(L, S, a, I, count, cap, prof);
-    default: return bwd_items_nb<8>(L, S, a, I, count, cap, prof);
+    case 8: return bwd_items_nb<8>(L, S, a, I, count, cap, prof);
+    case 9: return bwd_items_nb<9>(L, S, a, I, count, cap, prof);
+    case 10: return bwd_items_nb<10>(L, S, a, I, count, cap, prof);
+    case 11: return bwd_items_nb<11>(L, S, a, I, count, cap, prof);
+    case 12: return bwd_items_nb<12>(L, S, a, I, count, cap, prof);
+    case 13: return bwd_items_nb<13>(L, S, a, I, count, cap, prof);
+    case 14: return bwd_items_nb<14>(L, S, a, I, count, cap, prof);
+    case 15: return bwd_items_nb<15>(L, S, a, I, count, cap, prof);
+    default: return bwd_items_nb<16>(L, S, a, I, count, cap, prof);
   }
 }
 

@@ -365,8 +365,10 @@ __global__ void k_moments(TreeBufs tb, uint32_t lb, uint32_t le, int64_t n, int 
 
 // Internal nodes of one level, one thread per (node, direction class): the
 // two children combine on the split box, then the result grows through the
-// empty prefix boxes up to the owned box (empty space is vacuum).
-__global__ void k_alpha(TreeBufs tb, uint32_t lb, uint32_t le, int B, int nclass) {
+// empty prefix boxes up to the owned box (empty space is vacuum).  With
+// `linear` (TREVR_ABSORPTION_AVG) the combine is the linear volume-weighted
+// mean instead of the transmission average.
+__global__ void k_alpha(TreeBufs tb, uint32_t lb, uint32_t le, int B, int nclass, int linear) {
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t cnt = (int64_t)(le - lb) * nclass;
   if (gid >= cnt) return;
@@ -378,11 +380,17 @@ __global__ void k_alpha(TreeBufs tb, uint32_t lb, uint32_t le, int B, int nclass
   const int l = tb.b_lown[i];
   const double L = tb.hdr[3];
   for (int b = 0; b < B; ++b) {
-    double A = combine64(&tb.geom[((int64_t)s * nclass + c) * 3], L,
-                         tb.alpha64[((int64_t)p0 * nclass + c) * B + b],
-                         tb.alpha64[((int64_t)p1 * nclass + c) * B + b]);
-    for (int mm = s - 1; mm >= l; --mm)
-      A = combine64(&tb.geom[((int64_t)mm * nclass + c) * 3], L, A, 0.0);
+    const double a1 = tb.alpha64[((int64_t)p0 * nclass + c) * B + b];
+    const double a2 = tb.alpha64[((int64_t)p1 * nclass + c) * B + b];
+    double A;
+    if (linear) {
+      A = combine_linear(a1, a2);
+      for (int mm = s - 1; mm >= l; --mm) A = combine_linear(A, 0.0);
+    } else {
+      A = combine64(&tb.geom[((int64_t)s * nclass + c) * 3], L, a1, a2);
+      for (int mm = s - 1; mm >= l; --mm)
+        A = combine64(&tb.geom[((int64_t)mm * nclass + c) * 3], L, A, 0.0);
+    }
     tb.alpha64[((int64_t)p * nclass + c) * B + b] = A;
     tb.alpha32[((int64_t)p * nclass + c) * B + b] = (float)A;
   }
@@ -648,7 +656,8 @@ trevr_status build_tree_impl(trevr_tree* T, const float* x, const float* y, cons
                                                                    nclass);
     TREVR_LAUNCH_CHECK("k_moments");
     const int64_t work = (int64_t)(lv.second - lv.first) * nclass;
-    k_alpha<<<grid_for(work, 128), 128, 0, st>>>(tb, lv.first, lv.second, B, nclass);
+    k_alpha<<<grid_for(work, 128), 128, 0, st>>>(tb, lv.first, lv.second, B, nclass,
+                                                  (T->p.flags & TREVR_ABSORPTION_AVG) ? 1 : 0);
     TREVR_LAUNCH_CHECK("k_alpha");
   }
 #undef TREVR_LAUNCH_CHECK

@@ -9,7 +9,7 @@
 
 namespace trevr {
 
-constexpr int kMaxBands = 8;
+constexpr int kMaxBands = 16;
 constexpr int kMaxNside = 8;
 constexpr int kMaxRays = 12 * kMaxNside * kMaxNside;
 constexpr int kKeyBits = 21;           // bits per axis of the Morton key
@@ -191,6 +191,11 @@ __device__ inline double combine64(const double* g, double L, double a1, double 
   for (int k = 0; k < nt; ++k) s += exp(t[k] - mx);
   return -(mx + log(s)) / d;
 }
+
+// Linear volume-weighted absorption average of two equal halves (Section
+// 2.6, the scheme the transmission average replaces; TREVR_ABSORPTION_AVG).
+// Its partial derivatives are 1/2 each.
+__device__ inline double combine_linear(double a1, double a2) { return 0.5 * (a1 + a2); }
 
 // combine64 and its partial derivatives with respect to a1 and a2: with
 // softmax weights p_k of the three log-terms, d alpha/d a1 = p1 + p3/2 and

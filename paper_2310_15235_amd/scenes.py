@@ -34,6 +34,7 @@ class Scene:
     thick_corr: bool = True
     near_field: bool = True
     background: bool = False
+    absorption_avg: bool = False      # linear absorption averaging instead of transmission
     bg: Optional[np.ndarray] = None   # float32 [B] isotropic background intensity
     rpp_min: float = 0.0
     box: Optional[Tuple[float, float, float, float]] = (0.0, 0.0, 0.0, 1.0)
