@@ -2,10 +2,14 @@
 
 TEST INFRASTRUCTURE ONLY.  This package is the reference that the HIP
 implementation is checked against; only the tests, ``__graft_entry__.smoke``
-and the CPU-baseline leg of ``bench.py`` may import it.  It shares no code with
-``paper_2310_15235_amd``; the two meet only through the seeded scene
+and the CPU-baseline leg of ``bench.py`` may import it.  Neither side imports,
+includes or links the other; the two meet only through the seeded scene
 generators (``paper_2310_15235_amd.scenes``), which hold inputs and no part of
-the method.
+the method.  The FP64 decisions (HEALPix pixel of a direction, point-box
+distances, the opening test, the ray-box slab test, the combine geometry) are
+written on both sides with the same operation order, so that discrete
+decisions agree bit for bit; each is pinned here by tests that do not use the
+HIP library (closed forms, brute force, the paper's table).
 
 The C++ source (``trevr_oracle.cpp``) follows Wadsley, Baumschlager & Shen
 (2023) section by section; see the comments there for the reading taken at

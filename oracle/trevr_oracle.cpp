@@ -4,8 +4,12 @@
 //
 // TEST INFRASTRUCTURE ONLY.  Nothing in the product path may load or call this
 // library: only the test suite, the smoke check and the benchmark's CPU
-// baseline leg use it.  It shares no code, header, table or helper with the
-// HIP implementation.
+// baseline leg use it.  It includes no header of, and is linked with nothing
+// from, the HIP implementation.  The FP64 decisions below (Healpix::pixel and
+// the centres, dist2_box, far2_box, open_cell, slab, combine_geom) use the
+// same operation order as the HIP library's so that discrete decisions agree
+// bit for bit; they are pinned by CPU tests that do not involve the HIP
+// library (closed forms, brute force, the paper's printed values).
 //
 // Every function follows the paper's definitions step by step, with plain
 // loops and recursion and no blocking or reordering beyond what the

@@ -87,3 +87,52 @@ def pairwise_pp(pos, m, rho, kappa, lum, thick_corr=True):
     if thick_corr:
         J *= thick(kappa * rho[None, :] * h[None, :])
     return J
+
+
+def column_sigma(b, m, h):
+    """Section 2.4: the column of an element at impact parameter b falls
+    linearly to zero at b = h and integrates to m over the disc b < h."""
+    return np.where(b < h, 3.0 * m / (np.pi * h * h) * (1.0 - b / h), 0.0)
+
+
+def ray_depth(pos, m, h, kappa, i, n, members):
+    """Optical depth [B] of the elements `members` (not i) on the ray from
+    element i along unit vector n: those ahead of it (positive projection)
+    within their size of the ray line (Section 2.4)."""
+    idx = np.asarray([l for l in members if l != i], dtype=np.int64)
+    if idx.size == 0:
+        return np.zeros(kappa.shape[0])
+    d = pos[idx] - pos[i]
+    proj = d @ n
+    b = np.linalg.norm(np.cross(d, n), axis=1)
+    ok = (proj > 0) & (b < h[idx])
+    return kappa[:, idx[ok]] @ column_sigma(b[ok], m[idx[ok]], h[idx[ok]])
+
+
+def segment_depth(pos, m, h, kappa, i, j, members):
+    """Optical depth [B] of the elements `members` (not i, not j) between
+    element i and a source j: those closer to j than i is, within their size
+    of the segment (Section 2.4)."""
+    idx = np.asarray([l for l in members if l != i and l != j], dtype=np.int64)
+    e = pos[j] - pos[i]
+    r2 = e @ e
+    if idx.size == 0 or r2 == 0.0:          # no column between i and itself
+        return np.zeros(kappa.shape[0])
+    w = pos[idx] - pos[i]
+    front = ((pos[idx] - pos[j]) ** 2).sum(1) < r2
+    u = np.clip((w @ e) / r2, 0.0, 1.0)
+    b = np.linalg.norm(w - u[:, None] * e, axis=1)
+    ok = front & (b < h[idx])
+    return kappa[:, idx[ok]] @ column_sigma(b[ok], m[idx[ok]], h[idx[ok]])
+
+
+def box_exit(c, n, lo, L):
+    """Distance from c (inside the cube [lo, lo + L]^3) along unit n to the
+    cube's boundary."""
+    t = np.inf
+    for a in range(3):
+        if n[a] > 0:
+            t = min(t, (lo[a] + L - c[a]) / n[a])
+        elif n[a] < 0:
+            t = min(t, (lo[a] - c[a]) / n[a])
+    return t

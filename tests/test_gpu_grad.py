@@ -112,6 +112,12 @@ SCENES = {
     "eight_bands": lambda: scenes.lognormal_scene(n=3000, seed=60, grid=16,
                                                   bands=tuple(float(2 ** k) for k in range(8)),
                                                   nside=2),
+    "ten_bands": lambda: scenes.lognormal_scene(n=3000, seed=63, grid=16,
+                                                bands=tuple(float(2 ** (k / 2)) for k in range(10)),
+                                                nside=2),
+    "absorption_average": lambda: scenes.lognormal_scene(n=4000, seed=64, grid=16,
+                                                         bands=(1.0, 10.0), nside=2,
+                                                         absorption_avg=True),
 }
 
 

@@ -129,12 +129,35 @@ def test_J_many_bands_and_leaf12():
     compare_J(sc)
 
 
-@pytest.mark.parametrize("nb", [7, 8])
-def test_J_seven_and_eight_bands(nb):
-    """The largest band counts (their own window sizes and occupancy; a
-    window of 256 sources, so source-rich buckets take several)."""
-    bands = tuple(float(2 ** k) for k in range(nb))
+@pytest.mark.parametrize("nb", [7, 8, 10, 16])
+def test_J_seven_to_sixteen_bands(nb):
+    """Large band counts (their own window sizes and occupancy; a window of
+    256 sources, so source-rich buckets take several), up to the paper's ten
+    bands (Section 3.1) and the library's limit of sixteen.  Opacities span
+    1..128 in equal ratios: a band whose optical depths reach thousands
+    holds J only to the FP32 rounding of e^-tau, about tau x 6e-8 relative."""
+    bands = tuple(float(2 ** (k * 7.0 / (nb - 1))) for k in range(nb))
     sc = scenes.lognormal_scene(n=6000, seed=70 + nb, grid=16, bands=bands, nside=2)
+    compare_J(sc)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: scenes.lognormal_scene(n=20000, seed=3, grid=32, bands=(1.0, 10.0, 100.0), nside=2,
+                                   absorption_avg=True),
+    lambda: scenes.uniform_scene(n=5000, seed=4, n_src=50, bands=(1.0, 2.0), nside=4, box=None,
+                                 absorption_avg=True),
+])
+def test_tree_tables_absorption_average(maker):
+    """Linear absorption averaging (Section 2.6): the tables of larger cells
+    are the volume-weighted means of their halves, the same in every
+    direction."""
+    compare_tree(maker())
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4])
+def test_J_absorption_average(nside):
+    sc = scenes.lognormal_scene(n=2 ** 13, seed=90 + nside, grid=16, bands=(1.0, 10.0, 100.0),
+                                nside=nside, absorption_avg=True)
     compare_J(sc)
 
 

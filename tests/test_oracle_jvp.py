@@ -39,18 +39,21 @@ def test_jvp_matches_central_differences(which):
     kw[{"lum": "tL", "kappa": "tkappa", "rho": "trho"}[which]] = t
     J, dJ, c0 = oracle.jvp(sc, **kw)
     fd6, cnts6 = _fd(sc, which, v, 1e-6)
-    fd7, cnts7 = _fd(sc, which, v, 1e-7)
-    assert cnts6[0] == cnts6[1] == cnts7[0] == cnts7[1] == c0, "a counted decision moved"
+    fd5, cnts5 = _fd(sc, which, v, 1e-5)
+    assert cnts6[0] == cnts6[1] == cnts5[0] == cnts5[1] == c0, "a counted decision moved"
     scale = np.abs(dJ).max(axis=1, keepdims=True)
     den = np.maximum(np.abs(dJ), 1e-3 * scale)
     # A column profile has a kink where an impact parameter meets the element
     # size (Sigma -> 0 with a finite slope); a step straddling it spoils that
     # component's difference quotient.  Such components show two quotients
-    # that disagree; they are skipped and counted.
-    kink = np.abs(fd6 - fd7) / den > 1e-4
+    # (steps 1e-5 and 1e-6) that disagree by more than 1e-6; they are skipped
+    # and counted.
+    # Elsewhere the two agree to ~1e-7 (rounding of the 1e-6 step), and the
+    # 1e-5 step's quotient (truncation ~1e-10) is compared with the JVP.
+    kink = np.abs(fd6 - fd5) / den > 1e-6
     assert kink.mean() < 0.005
-    err = np.abs(dJ - fd6) / den
-    assert np.max(err[~kink]) < 1e-5
+    err = np.abs(dJ - fd5) / den
+    assert np.max(err[~kink]) < 1e-6
     # the derivative is not trivially zero
     assert np.all(scale > 0)
 

@@ -262,8 +262,9 @@ def test_active_subset_matches_full_run():
 # ------------------------------------------------------------- cost law
 @pytest.mark.parametrize("kind", ["uniform", "lognormal"])
 def test_cost_grows_as_log2_n(kind):
-    """Section 3.1 (and 2.5.1): work per active receiver grows as log2 N."""
-    lg = np.arange(10, 17)
+    """Section 3.1 (and 2.5.1): work per active receiver grows as log2 N,
+    over N = 2^12 .. 2^21 (linear fit in log2 N, R^2 >= 0.98)."""
+    lg = np.arange(12, 22)
     seg = []
     for k in lg:
         n = 2 ** int(k)
@@ -279,4 +280,4 @@ def test_cost_grows_as_log2_n(kind):
     coef, res, _, _ = np.linalg.lstsq(A, seg, rcond=None)
     r2 = 1 - res[0] / ((seg - seg.mean()) ** 2).sum()
     assert coef[0] > 0
-    assert r2 > 0.96
+    assert r2 >= 0.98

@@ -138,14 +138,6 @@ def test_healpix_pixel_is_compact_region(nside):
     assert (np.abs(ang - near) < 1e-9).mean() > 0.8
 
 
-def test_beam_half_angle_48():
-    """Section 2.5.2: the average half-angle of 48 HEALPix beams is 16.5 deg;
-    the equal-solid-angle cone cos(theta_b) = 1 - 2/N_ray gives 16.6 deg."""
-    g = json.load(open(os.path.join(GOLD, "opening_angles.json")))
-    tb = np.degrees(np.arccos(1 - 2 / 48))
-    assert tb == pytest.approx(g["beam48_half_angle_deg"], abs=0.15)
-
-
 # ------------------------------------------------------------- combining
 def _two_cell(phi_deg, a1=10.0, a2=0.0):
     ph = np.radians(phi_deg)
