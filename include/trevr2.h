@@ -164,6 +164,26 @@ trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* 
                              void* scratch, size_t scratch_bytes, void* stream);
 
 /*
+ * trevr_compute_J without a caller scratch buffer, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The scratch comes from a fixed device
+ * array of TREVR_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held
+ * from the library's first such call on that GPU until the process ends; the
+ * call itself allocates nothing.  Arguments and results as trevr_compute_J
+ * (the GPU is the current device, which must be the tree's).  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (several
+ * streams or threads) race and must be serialised by the caller; each call
+ * clears the part of the array that must start at zero.  A call whose
+ * scratch would exceed the array returns TREVR_E_CAPACITY, writing no J
+ * (trevr_scratch_needed gives the size it needed).  The cut lists take
+ * 16 KiB per bucket of the array, so trees of up to about 2 x 10^4 elements
+ * (leaf size 8) fit.
+ */
+#define TREVR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+trevr_status trevr_compute_J_noalloc(trevr_tree* t, const uint8_t* active, const float* bg,
+                                     double* J, void* stream);
+
+/*
  * Adjoint of trevr_compute_J (reverse-mode derivative; not in the paper,
  * which defines only the forward map of Sections 2.1-2.6).  Given
  * gJ = dE/dJ for a scalar objective E of the J that trevr_compute_J returns

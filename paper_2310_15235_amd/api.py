@@ -29,7 +29,9 @@ EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_forest_plan", "trevr_forest_scratch_bytes", "trevr_compute_J_batched",
             "trevr_compute_J_backward_batched", "trevr_forest_check",
             "trevr_forest_get_counters", "trevr_forest_scene", "trevr_forest_destroy",
-            "trevr_forest_autotune", "trevr_forest_set_config", "trevr_forest_get_config")
+            "trevr_forest_autotune", "trevr_forest_set_config", "trevr_forest_get_config",
+            "trevr_compute_J_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20   # the fixed device array of trevr_compute_J_noalloc
 TUNE_STACK, TUNE_CUT, TUNE_STAGE = 0, 1, 2
 CONFIGS = 8          # launch configurations of the forest autotuner
 PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree")
@@ -203,6 +205,18 @@ class Tree:
         self._call_with_scratch(
             lambda sp, sb: lib().trevr_compute_J(self.handle, a, g, _dev(out, torch.float64), sp,
                                                  sb, _stream_ptr()), "trevr_compute_J")
+        return out
+
+    def compute_J_noalloc(self, active=None, bg=None, out=None):
+        """compute_J through trevr_compute_J_noalloc: the library's fixed
+        per-GPU scratch array instead of this tree's scratch tensor."""
+        torch = _torch()
+        if out is None:
+            out = torch.zeros((self.B, self.n), dtype=torch.float64, device=self.device)
+        a = None if active is None else _dev(active, torch.uint8)
+        g = None if bg is None else _dev(bg, torch.float32)
+        _check(lib().trevr_compute_J_noalloc(self.handle, a, g, _dev(out, torch.float64),
+                                             _stream_ptr()), "trevr_compute_J_noalloc")
         return out
 
     def _call_with_scratch(self, fn, where):

@@ -2,6 +2,7 @@
 // workspace sizing, tree handles, counters, sticky errors and table export.
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -238,6 +239,54 @@ trevr_status trevr_compute_J(trevr_tree* t, const uint8_t* active, const float* 
     return set_error(TREVR_E_INVALID, "TREVR_BACKGROUND needs bg");
   t->stream = (hipStream_t)stream;
   return compute_J_impl(t, active, bg, J, scratch, scratch_bytes);
+}
+
+// Scratch of trevr_compute_J_noalloc: a fixed device array, one copy per GPU.
+// Host code never passes the array's name to the device: its device address
+// on each GPU is looked up once (hipGetSymbolAddress, with that GPU current)
+// and kept in g_noalloc_ptr.
+static __device__ __align__(256) unsigned char noalloc_scratch[TREVR_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[kMaxDevices] = {};
+
+static trevr_status noalloc_scratch_ptr(void** out) {
+  int dev = -1;
+  trevr_status rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (rc != TREVR_OK) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(TREVR_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)), "hipGetSymbolAddress");
+    if (rc != TREVR_OK) return rc;
+    if (!p) return set_error(TREVR_E_HIP, "no device address for the fixed scratch array");
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return TREVR_OK;
+}
+
+trevr_status trevr_compute_J_noalloc(trevr_tree* t, const uint8_t* active, const float* bg,
+                                     double* J, void* stream) {
+  if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
+  if (!J) return set_error(TREVR_E_INVALID, "NULL J");
+  if ((t->p.flags & TREVR_BACKGROUND) && !bg)
+    return set_error(TREVR_E_INVALID, "TREVR_BACKGROUND needs bg");
+  void* ptr = nullptr;
+  trevr_status rc = noalloc_scratch_ptr(&ptr);
+  if (rc != TREVR_OK) return rc;
+  t->stream = (hipStream_t)stream;
+  rc = compute_J_impl(t, active, bg, J, ptr, TREVR_NOALLOC_SCRATCH_BYTES);
+  if (rc == TREVR_E_CAPACITY) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg,
+                  "compute_J_noalloc: this call needs %zu bytes of scratch, more than the fixed "
+                  "%zu-byte device array",
+                  t->scratch_needed, (size_t)TREVR_NOALLOC_SCRATCH_BYTES);
+    return set_error(TREVR_E_CAPACITY, msg);
+  }
+  return rc;
 }
 
 trevr_status trevr_compute_J_backward(trevr_tree* t, const uint8_t* active, const float* bg,
