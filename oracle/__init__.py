@@ -31,6 +31,7 @@ THICK_CORR = 1
 NEAR_FIELD = 2
 BACKGROUND = 4
 ABSORPTION_AVG = 8
+DIRECTED = 32
 
 COUNTER_NAMES = ("buckets", "cells", "absorber_entries", "source_entries", "segments",
                  "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples")
@@ -90,7 +91,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
                 ("n_bands", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("theta", ctypes.c_double), ("rpp_min", ctypes.c_double),
-                ("box", ctypes.c_double * 4)]
+                ("box", ctypes.c_double * 4), ("target", ctypes.c_double * 3)]
 
 
 def _ptr(a):
@@ -107,6 +108,8 @@ def scene_flags(scene) -> int:
         f |= BACKGROUND
     if getattr(scene, "absorption_avg", False):
         f |= ABSORPTION_AVG
+    if getattr(scene, "directed", None) is not None:
+        f |= DIRECTED
     return f
 
 
@@ -121,6 +124,9 @@ def _params(scene) -> _Params:
     box = scene.box if scene.box is not None else (0.0, 0.0, 0.0, 0.0)
     for a in range(4):
         p.box[a] = float(box[a])
+    tgt = getattr(scene, "directed", None)
+    for a in range(3):
+        p.target[a] = 0.0 if tgt is None else float(tgt[a])
     return p
 
 

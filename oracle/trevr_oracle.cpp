@@ -85,8 +85,9 @@ struct Params {
   double theta;
   double rpp_min;
   double box[4];
+  double target[3];
 };
-enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u, F_AVG = 8u };
+enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u, F_AVG = 8u, F_DIRECTED = 32u };
 
 enum { C_BUCKETS = 0, C_CELLS, C_ABS, C_SRC, C_SEG, C_NEAR_PAIRS, C_MAX_NEAR, C_NODES,
        C_SRC_PAIRS, C_NS_TRIPLES, C_N };
@@ -655,6 +656,7 @@ template <class T> struct Walker {
   double c[3];
   T r;
   double r2, theta2;
+  std::vector<double> dir;  // [nray][3] ray directions of this bucket
   std::vector<double> inv;  // [nray][3]
   std::vector<std::vector<AbsE<T>>> abs;
   std::vector<std::vector<SrcE<T>>> src;
@@ -667,7 +669,7 @@ template <class T> struct Walker {
     const double rv = val(r);
     for (int k = 0; k < t.nray; ++k) {
       double tin, tout;
-      if (!slab(g.lo, g.hi, c, &t.hp.v[3 * k], &inv[3 * k], tin, tout)) continue;
+      if (!slab(g.lo, g.hi, c, &dir[3 * k], &inv[3 * k], tin, tout)) continue;
       if (!(tout > std::max(tin, rv))) continue;  // nothing beyond the p-p sphere
       AbsE<T> e;
       e.t0 = (tin < rv) ? r : T(tin);
@@ -686,7 +688,7 @@ template <class T> struct Walker {
     T s = T(0.0);
     if (!(val(v[0]) == 0.0 && val(v[1]) == 0.0 && val(v[2]) == 0.0)) {
       k = t.hp.pixel(val(v[0]), val(v[1]), val(v[2]));
-      const double* n = &t.hp.v[3 * k];
+      const double* n = &dir[3 * k];
       s = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
     }
     SrcE<T> e;
@@ -752,10 +754,23 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
   Walker<T> W(t, P, mo);
   for (int a = 0; a < 3; ++a) W.c[a] = 0.5 * (g.lo[a] + g.hi[a]);  // bucket centre
   W.theta2 = p.theta * p.theta;
+  // Ray directions: the HEALPix centres.  Directed rays (Sections 3.4.1, 4):
+  // the ray whose pixel holds the direction from the bucket centre to the
+  // target point is aimed exactly at it (its transmission averages stay
+  // those of its HEALPix direction).
+  W.dir = t.hp.v;
+  if (p.flags & F_DIRECTED) {
+    double v[3] = {p.target[0] - W.c[0], p.target[1] - W.c[1], p.target[2] - W.c[2]};
+    if (!(v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0)) {
+      double d = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      int kd = t.hp.pixel(v[0], v[1], v[2]);
+      for (int a = 0; a < 3; ++a) W.dir[3 * kd + a] = v[a] / d;
+    }
+  }
   W.inv.resize(3 * K);
   for (int k = 0; k < K; ++k)
     for (int a = 0; a < 3; ++a) {
-      double na = t.hp.v[3 * k + a];
+      double na = W.dir[3 * k + a];
       W.inv[3 * k + a] = (na != 0.0) ? 1.0 / na : 0.0;
     }
   // p-p radius (Section 2.4): a sphere about the bucket centre reaching past
@@ -805,7 +820,7 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
     for (int a = 0; a < 3; ++a) { rlo[a] = t.lo[a]; rhi[a] = t.lo[a] + t.L; }
     for (int k = 0; k < K; ++k) {
       double tin, tout;
-      slab(rlo, rhi, W.c, &t.hp.v[3 * k], &W.inv[3 * k], tin, tout);
+      slab(rlo, rhi, W.c, &W.dir[3 * k], &W.inv[3 * k], tin, tout);
       for (int b = 0; b < B; ++b) tau_bg[k * B + b] = W.tau_to(k, T(tout), b);
     }
   }
@@ -821,7 +836,7 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
     // p-p particle ahead of the receiver on the ray and within its own size
     // of the ray line adds kappa * Sigma(b); the receiver itself is excluded.
     for (int k = 0; k < K; ++k) {
-      const double* n = &t.hp.v[3 * k];
+      const double* n = &W.dir[3 * k];
       for (int b = 0; b < B; ++b) tpp[k * B + b] = T(0.0);
       for (int64_t l : nearv) {
         if (l == i) continue;

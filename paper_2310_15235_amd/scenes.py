@@ -35,6 +35,7 @@ class Scene:
     near_field: bool = True
     background: bool = False
     absorption_avg: bool = False      # linear absorption averaging instead of transmission
+    directed: Optional[Tuple[float, float, float]] = None   # target of directed rays
     bg: Optional[np.ndarray] = None   # float32 [B] isotropic background intensity
     rpp_min: float = 0.0
     box: Optional[Tuple[float, float, float, float]] = (0.0, 0.0, 0.0, 1.0)
@@ -260,4 +261,122 @@ def active_subset(scene: Scene, frac: float, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     a = np.zeros(scene.n, np.uint8)
     a[rng.choice(scene.n, size=max(1, int(round(frac * scene.n))), replace=False)] = 1
+    return a
+
+
+# ------------------------------------------- the paper's fixed-opacity tests
+def _jittered_lattice(rng, lo, hi, spacing, jitter=0.25):
+    """Cubic lattice of the given spacing filling the box [lo, hi)^3, each
+    point moved by up to +-jitter*spacing per axis: a stand-in for the glass
+    initial conditions of Section 3.3, with the same spacing and no two
+    elements at one position."""
+    axes = [np.arange(lo[a] + 0.5 * spacing, hi[a], spacing) for a in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    p = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    return p + rng.uniform(-jitter, jitter, p.shape) * spacing
+
+
+def _escape_scene(pos, spacing, alpha, src_pos, src_lum, box, meta, nside, theta, leaf_size,
+                  avg, name):
+    """Elements of density 1 and volume spacing^3 (so h is the local
+    spacing) with opacity alpha (alpha = kappa rho), one band, plus a source
+    element at each of src_pos with luminosity src_lum and the local medium
+    around it.  The thick-element factor is off: these tests measure the
+    incident intensity.  All elements are receivers (the tests pick a shell
+    as the active set)."""
+    n_med = pos.shape[0]
+    pos = np.concatenate([pos, np.asarray(src_pos, float)], axis=0)
+    spacing = np.concatenate([spacing, meta.pop("src_spacing")])
+    alpha = np.concatenate([alpha, meta.pop("src_alpha")])
+    n = pos.shape[0]
+    lum = np.zeros(n)
+    lum[n_med:] = src_lum
+    meta.update(sources=np.arange(n_med, n), src_pos=np.asarray(src_pos, float),
+                src_lum=np.asarray(src_lum, float))
+    return Scene(x=_f32(pos[:, 0]), y=_f32(pos[:, 1]), z=_f32(pos[:, 2]), m=_f32(spacing ** 3),
+                 rho=_f32(np.ones(n)), kappa=_f32(alpha[None, :]), lum=_f32(lum[None, :]),
+                 active=np.ones(n, np.uint8), nside=nside, leaf_size=leaf_size, theta=theta,
+                 thick_corr=False, box=box, absorption_avg=avg, name=name, meta=meta)
+
+
+def source_features_scene(feature="clouds", seed=7, avg=False, nside=2, theta=0.75,
+                          leaf_size=12, outer=0.0625, inner=0.0209) -> Scene:
+    """Section 3.4 tests: a source of L = 1 at (0.17, 0.17, 0.17) in a
+    medium of alpha = 1 filling the sphere of radius 2.5 about the origin,
+    element spacing 0.0625 outside and 0.0209 within 0.4 of the source, and
+      feature = "none":   nothing else (escape at r = 2 is e^-2);
+      feature = "clouds": two clouds of radius 0.1 and alpha = 10 offset by
+                          +-0.25 along the main diagonal (Section 3.4.1);
+      feature = "wall":   alpha = 10 beyond the plane 0.25 from the source
+                          along -(1,1,1)/sqrt(3) (Section 3.4.2).
+    Escape fractions are measured at distance 2 from the source."""
+    rng = np.random.default_rng(seed)
+    src = np.array([0.17, 0.17, 0.17])
+    diag = np.ones(3) / np.sqrt(3.0)
+    po = _jittered_lattice(rng, (-2.5,) * 3, (2.5,) * 3, outer)
+    po = po[(np.linalg.norm(po, axis=1) < 2.5) & (np.linalg.norm(po - src, axis=1) >= 0.4)]
+    pi = _jittered_lattice(rng, src - 0.4, src + 0.4, inner)
+    pi = pi[np.linalg.norm(pi - src, axis=1) < 0.4]
+    pos = np.concatenate([po, pi], axis=0)
+    spacing = np.concatenate([np.full(len(po), outer), np.full(len(pi), inner)])
+
+    def alpha_at(p):
+        a = np.ones(len(p))
+        if feature == "clouds":
+            for sgn in (1.0, -1.0):
+                a[np.linalg.norm(p - (src + sgn * 0.25 * diag), axis=1) < 0.1] = 10.0
+        elif feature == "wall":
+            a[(p - src) @ diag < -0.25] = 10.0
+        elif feature != "none":
+            raise ValueError(feature)
+        return a
+
+    meta = dict(test=f"source+{feature}", centre=src, radius=2.0, medium_alpha=1.0,
+                src_spacing=np.array([inner]), src_alpha=alpha_at(src[None, :]))
+    return _escape_scene(pos, spacing, alpha_at(pos), [src], [1.0], (-2.5, -2.5, -2.5, 5.0),
+                         meta, nside, theta, leaf_size, avg,
+                         f"source_{feature}{'_absavg' if avg else ''}")
+
+
+def two_sources_cloud_scene(seed=8, avg=False, nside=2, theta=0.75, leaf_size=12,
+                            outer=0.25, inner=0.0625, cloud=True) -> Scene:
+    """Section 3.3: a sphere of radius 0.5 at the origin with alpha = 10^4
+    (element spacing 0.0625) in a medium of alpha = 10^-4 (spacing 0.25), two
+    sources of L = 0.5 at (-2, 0, 0) and (0, -2, 0); the volume is centred on
+    (-2.1, -2.1, -2.1) so that the sources and the cloud share a moderately
+    sized tree cell (Appendix A), and reaches past radius 6 about the origin,
+    where escape fractions are measured."""
+    rng = np.random.default_rng(seed)
+    half = 8.2
+    c = np.array([-2.1, -2.1, -2.1])
+    po = _jittered_lattice(rng, c - half, c + half, outer)
+    pos_list, sp_list = [po[np.linalg.norm(po, axis=1) >= 0.5]], []
+    sp_list.append(np.full(len(pos_list[0]), outer))
+    if cloud:
+        pi = _jittered_lattice(rng, (-0.5,) * 3, (0.5,) * 3, inner)
+        pi = pi[np.linalg.norm(pi, axis=1) < 0.5]
+        pos_list.append(pi)
+        sp_list.append(np.full(len(pi), inner))
+    pos = np.concatenate(pos_list, axis=0)
+    spacing = np.concatenate(sp_list)
+    alpha = np.where(np.linalg.norm(pos, axis=1) < 0.5, 1e4 if cloud else 1e-4, 1e-4)
+    srcs = np.array([[-2.0, 0.0, 0.0], [0.0, -2.0, 0.0]])
+    meta = dict(test="two sources+cloud" if cloud else "two sources", centre=np.zeros(3),
+                radius=6.0, medium_alpha=1e-4, src_spacing=np.full(2, outer),
+                src_alpha=np.full(2, 1e-4))
+    box = (c[0] - half, c[1] - half, c[2] - half, 2 * half)
+    return _escape_scene(pos, spacing, alpha, srcs, [0.5, 0.5], box, meta, nside, theta,
+                         leaf_size, avg, f"two_sources_cloud{'_absavg' if avg else ''}")
+
+
+def shell_active(scene: Scene, width=None) -> np.ndarray:
+    """Receivers of an escape measurement: elements within `width` (default
+    one outer spacing, 0.0625 or 0.25) of the measuring radius about the
+    test's centre."""
+    c, R = scene.meta["centre"], scene.meta["radius"]
+    if width is None:
+        width = 0.25 if R > 3 else 0.0625
+    r = np.linalg.norm(scene.positions().astype(np.float64) - c, axis=1)
+    a = (np.abs(r - R) < width).astype(np.uint8)
+    a[scene.meta["sources"]] = 0
     return a
