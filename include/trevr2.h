@@ -67,6 +67,16 @@ enum {
                             box (vacuum), the same in every direction.  This
                             is the first-order limit of the transmission
                             average; buckets keep sum(kappa m)/sum(m/rho).    */
+  TREVR_DIRECTED = 32u,  /* directed rays (Sections 3.4.1, 4; the 'Directed'
+                            rows of table escape), for tests with one source
+                            at the point trevr_params.target: in every bucket
+                            the ray whose pixel holds the direction from the
+                            bucket centre to target is aimed exactly at target
+                            instead of along its HEALPix centre.  That ray's
+                            cell chords, p-p columns, source projections and
+                            background exit use the new direction; its
+                            transmission averages stay those of its HEALPix
+                            direction.  Other rays are unchanged.             */
   TREVR_KEEP_DEPTHS = 16u /* memory for time in the adjoint: the forward keeps
                             each far source's cell optical depth (and each
                             ray's exit depth with TREVR_BACKGROUND) in the
@@ -90,6 +100,9 @@ typedef struct trevr_params {
   double rpp_min;    /* lower bound of the p-p radius (>= 0; 0 = paper's rule)      */
   double box[4];     /* root cube {lo_x, lo_y, lo_z, L}; L <= 0: bounding cube of
                         the particles                                              */
+  double target[3];  /* with TREVR_DIRECTED: the point the directed ray of each
+                        bucket aims at (the source of a single-source test);
+                        ignored otherwise                                         */
 } trevr_params;
 
 /* Work counters of the last compute_J on a tree (see trevr_get_counters). */

@@ -18,7 +18,7 @@ SO_PATH = os.path.join(HERE, "libtrevr2.so")
 
 # status codes and flags (include/trevr2.h)
 OK, E_INVALID, E_CAPACITY, E_HIP, E_STATE, E_DATA = range(6)
-THICK_CORR, NEAR_FIELD, BACKGROUND, ABSORPTION_AVG, KEEP_DEPTHS = 1, 2, 4, 8, 16
+THICK_CORR, NEAR_FIELD, BACKGROUND, ABSORPTION_AVG, KEEP_DEPTHS, DIRECTED = 1, 2, 4, 8, 16, 32
 
 EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_compute_J_backward", "trevr_tree_tune",
@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
                 ("n_bands", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("theta", ctypes.c_double), ("rpp_min", ctypes.c_double),
-                ("box", ctypes.c_double * 4)]
+                ("box", ctypes.c_double * 4), ("target", ctypes.c_double * 3)]
 
 
 class Counters(ctypes.Structure):
@@ -118,13 +118,15 @@ def _check(status: int, where: str):
 
 
 def make_params(nside=2, leaf_size=8, n_bands=1, flags=THICK_CORR | NEAR_FIELD, theta=0.75,
-                rpp_min=0.0, box=None) -> Params:
+                rpp_min=0.0, box=None, target=None) -> Params:
     p = Params()
     p.nside, p.leaf_size, p.n_bands, p.flags = int(nside), int(leaf_size), int(n_bands), int(flags)
     p.theta, p.rpp_min = float(theta), float(rpp_min)
     b = (0.0, 0.0, 0.0, 0.0) if box is None else box
     for a in range(4):
         p.box[a] = float(b[a])
+    for a in range(3):
+        p.target[a] = 0.0 if target is None else float(target[a])
     return p
 
 
@@ -158,7 +160,8 @@ class Tree:
     """A radiation tree built on the GPU; owns its workspace tensor."""
 
     def __init__(self, x, y, z, m, rho, kappa, lum, *, nside=2, leaf_size=8, theta=0.75,
-                 flags=THICK_CORR | NEAR_FIELD, rpp_min=0.0, box=None, scratch=None):
+                 flags=THICK_CORR | NEAR_FIELD, rpp_min=0.0, box=None, scratch=None,
+                 target=None):
         """``scratch`` (optional): a uint8 device tensor to use as the
         compute scratch, e.g. ``previous_tree.scratch`` when stepping through
         scenes of similar size; it is replaced by a larger one when a call
@@ -167,7 +170,7 @@ class Tree:
         n = int(x.shape[0])
         B = int(kappa.shape[0])
         self.n, self.B, self.nside = n, B, int(nside)
-        self.params = make_params(nside, leaf_size, B, flags, theta, rpp_min, box)
+        self.params = make_params(nside, leaf_size, B, flags, theta, rpp_min, box, target)
         tb, sb = workspace_bytes(self.params, n)
         self.device = x.device
         self.ws = torch.empty(tb, dtype=torch.uint8, device=x.device)
@@ -192,7 +195,8 @@ class Tree:
         flags = scene_flags(scene) | int(extra_flags)
         return cls(t(scene.x), t(scene.y), t(scene.z), t(scene.m), t(scene.rho), t(scene.kappa),
                    t(scene.lum), nside=scene.nside, leaf_size=scene.leaf_size, theta=scene.theta,
-                   flags=flags, rpp_min=scene.rpp_min, box=scene.box)
+                   flags=flags, rpp_min=scene.rpp_min, box=scene.box,
+                   target=getattr(scene, "directed", None))
 
     def compute_J(self, active=None, bg=None, out=None):
         """J [B, n] float64 on the device (rows of inactive elements keep
@@ -357,7 +361,8 @@ def compute_J_backward(scene, gJ, active=None, device="cuda", extra_flags=0):
 def scene_flags(scene) -> int:
     return (THICK_CORR if scene.thick_corr else 0) | (NEAR_FIELD if scene.near_field else 0) | \
         (BACKGROUND if scene.background else 0) | \
-        (ABSORPTION_AVG if getattr(scene, "absorption_avg", False) else 0)
+        (ABSORPTION_AVG if getattr(scene, "absorption_avg", False) else 0) | \
+        (DIRECTED if getattr(scene, "directed", None) is not None else 0)
 
 
 class Forest:
@@ -386,7 +391,7 @@ class Forest:
         params = (Params * self.S)()
         for i, s in enumerate(scenes):
             params[i] = make_params(s.nside, s.leaf_size, s.n_bands, scene_flags(s), s.theta,
-                                    s.rpp_min, s.box)
+                                    s.rpp_min, s.box, getattr(s, "directed", None))
         self.params = params
         f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=self.device)
         cat = lambda name: f32(np.concatenate([getattr(s, name) for s in scenes]))

@@ -42,7 +42,7 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
   if (p->n_bands < 1 || p->n_bands > kMaxBands)
     return set_error(TREVR_E_INVALID, "n_bands must be in [1, 16]");
   if (p->flags & ~(uint32_t)(TREVR_THICK_CORR | TREVR_NEAR_FIELD | TREVR_BACKGROUND |
-                            TREVR_ABSORPTION_AVG | TREVR_KEEP_DEPTHS))
+                            TREVR_ABSORPTION_AVG | TREVR_DIRECTED | TREVR_KEEP_DEPTHS))
     return set_error(TREVR_E_INVALID, "unknown flag bits");
   if (!(p->theta >= 0.0) || !std::isfinite(p->theta))
     return set_error(TREVR_E_INVALID, "theta must be finite and >= 0");
@@ -51,6 +51,11 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
   if (p->box[3] > 0.0) {
     for (int a = 0; a < 4; ++a)
       if (!std::isfinite(p->box[a])) return set_error(TREVR_E_INVALID, "box must be finite");
+  }
+  if (p->flags & TREVR_DIRECTED) {
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->target[a]))
+        return set_error(TREVR_E_INVALID, "TREVR_DIRECTED needs a finite target");
   }
   return TREVR_OK;
 }
@@ -202,6 +207,7 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   D.theta2 = p->theta * p->theta;
   D.rpp_min = p->rpp_min;
   D.wbeam = 2.0 * std::tan(std::acos(1.0 - 2.0 / T->nray));
+  for (int a = 0; a < 3; ++a) D.target[a] = p->target[a];
   D.stack_limit = kStackSmall;
   D.hdr = b.hdr;
   D.x = b.x; D.y = b.y; D.z = b.z; D.m = b.m; D.rho = b.rho;

@@ -459,13 +459,15 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
       float of[3], inv[2][3];
       bool kok[2];
       float tau[2][NB];
+      double ud[3];
+      const int kd = directed_ray(T, c, ud);   // the bucket's directed ray, if any
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         kok[q] = ok && kb + q < nray;
         const int kq = kok[q] ? kb + q : 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          nv[q][a] = T.ray_n[3 * kq + a];
+          nv[q][a] = (kq == kd) ? ud[a] : T.ray_n[3 * kq + a];
           const float nf = (float)nv[q][a];
           inv[q][a] = (nf != 0.0f) ? 1.0f / nf : 1e30f;
         }
@@ -974,7 +976,7 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
       const int k0 = 64 * g;
       const int kn = min(64, nray - k0);
       const bool rt = t < kn;                  // ray-owning thread
-      load_ray_group(T, k0, kn, G);
+      load_ray_group(T, c, k0, kn, G);
       for (int q = t; q < nrecv * kn; q += kFT) {
         const int i = q / kn, kq = q % kn;
 #pragma unroll

@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
     for (int k0 = 0; k0 < nray; k0 += 64) {
       const int kn = min(64, nray - k0);
       if (t == 0) gz = 0;
-      load_ray_group(T, k0, kn, RG);
+      load_ray_group(T, c, k0, kn, RG);
       __syncthreads();
       int nz = 0;
       for (int q = t; q < nrecv * kn; q += kNT) {
@@ -642,7 +642,7 @@ __global__ void __launch_bounds__(kFT, BwdCfg<NB>::waves)
       const int k0 = 64 * g;
       const int kn = min(64, nray - k0);
       const bool rt = t < kn;
-      load_ray_group(T, k0, kn, RG);
+      load_ray_group(T, c, k0, kn, RG);
       for (int q = t; q < nrecv * kn; q += kFT) {
         const int i = q / kn, kq = q % kn;
 #pragma unroll

@@ -553,13 +553,18 @@ struct RayGroup {
   int cls[64];   // direction class (transmission tables)
 };
 
-__device__ inline void load_ray_group(const DevTree& T, int k0, int kn, RayGroup& G) {
+// The directed ray of the bucket centred at c (TREVR_DIRECTED) takes its
+// aimed direction; its class stays that of its HEALPix direction.
+__device__ inline void load_ray_group(const DevTree& T, const double c[3], int k0, int kn,
+                                      RayGroup& G) {
   const int t = threadIdx.x;
   if (t < kn) {
     const int k = k0 + t;
+    double u[3];
+    const int kd = directed_ray(T, c, u);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double na = T.ray_n[3 * k + a];
+      const double na = (k == kd) ? u[a] : T.ray_n[3 * k + a];
       G.n[t][a] = na;
       G.inv[t][a] = (na != 0.0) ? 1.0 / na : 0.0;
       G.nf[t][a] = (float)na;
@@ -634,7 +639,9 @@ __device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, ui
       const double v0 = p[0] - c[0], v1 = p[1] - c[1], v2 = p[2] - c[2];
       double sd = 0.0;
       if (!(v0 == 0.0 && v1 == 0.0 && v2 == 0.0)) {
-        const double* nn = &T.ray_n[3 * pix];
+        double u[3];
+        const bool dir = directed_ray(T, c, u) == (int)pix;
+        const double* nn = dir ? u : &T.ray_n[3 * pix];
         sd = v0 * nn[0] + v1 * nn[1] + v2 * nn[2];
       }
       W.rel[slot][0] = (float)v0;

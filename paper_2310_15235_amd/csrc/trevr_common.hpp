@@ -51,6 +51,7 @@ struct DevTree {
   int32_t B, nside, nray, nclass, leaf_size;
   uint32_t flags;
   double theta2, rpp_min, wbeam;
+  double target[3];           // aim of the directed ray (TREVR_DIRECTED)
   int32_t stack_limit;        // entries of the small traversal stack in use
   int64_t num_nodes;
   const double* hdr;          // root lo[3], L, quantisation scale
@@ -174,6 +175,21 @@ __device__ inline int healpix_pixel(int N, double x, double y, double zz) {
   ip = ((ip % (4 * ir)) + 4 * ir) % (4 * ir);
   if (z > 0) return (int)(2 * ir * (ir - 1) + ip);
   return (int)(12 * N * N - 2 * ir * (ir + 1) + ip);
+}
+
+// Directed rays (TREVR_DIRECTED; Sections 3.4.1, 4): the ray of a bucket
+// with centre c whose pixel holds the direction to T.target is aimed exactly
+// at the target.  Returns that ray's index and its unit direction u, or -1
+// when the flag is off or the target is the bucket centre.
+__device__ inline int directed_ray(const DevTree& T, const double c[3], double u[3]) {
+  if (!(T.flags & TREVR_DIRECTED)) return -1;
+  const double v0 = T.target[0] - c[0], v1 = T.target[1] - c[1], v2 = T.target[2] - c[2];
+  if (v0 == 0.0 && v1 == 0.0 && v2 == 0.0) return -1;
+  const double d = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+  u[0] = v0 / d;
+  u[1] = v1 / d;
+  u[2] = v2 / d;
+  return healpix_pixel(T.nside, v0, v1, v2);
 }
 
 // Transmission average of two halves (Section 2.6, eq. transmissionavg):

@@ -37,3 +37,45 @@ def test_escape_scene_parity(test, avg):
     eo, co = escape_covering(sc, Jo, act)
     assert eg == pytest.approx(eo, rel=1e-5)
     assert cg == co
+
+
+DIRECTED = {
+    "source+none": lambda: scenes.source_features_scene("none"),
+    "source+clouds": lambda: scenes.source_features_scene("clouds"),
+    "source+wall": lambda: scenes.source_features_scene("wall"),
+}
+
+
+@pytest.mark.parametrize("test", list(DIRECTED))
+def test_directed_rays_parity(test):
+    """Directed rays (Sections 3.4.1, 4): each bucket's ray toward the source
+    is aimed exactly at it; J on the shell and the escape figures against the
+    oracle."""
+    import torch
+    from paper_2310_15235_amd import api
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = DIRECTED[test]()
+    sc = sc.with_(directed=tuple(float(v) for v in sc.meta["src_pos"][0]))
+    act = scenes.shell_active(sc)
+    compare_J(sc, active=act)
+    Jg, _ = api.compute_J(sc, active=act)
+    Jo, _ = oracle.OracleTree(sc).compute_J(act)
+    eg, cg = escape_covering(sc, Jg, act)
+    eo, co = escape_covering(sc, Jo, act)
+    assert eg == pytest.approx(eo, rel=1e-5)
+    assert cg == co
+
+
+@pytest.mark.parametrize("kw", [dict(nside=1), dict(nside=2, background=True),
+                                dict(nside=4, thick_corr=True)])
+def test_directed_rays_general_scene(kw):
+    """Directed rays in a clumpy medium with many sources, the background and
+    the thick factor (every part of the path that uses a ray direction), all
+    receivers: J and every counter against the oracle."""
+    bg = kw.pop("background", False)
+    sc = scenes.lognormal_scene(n=6000, seed=110 + kw["nside"], grid=16, bands=(1.0, 10.0),
+                                directed=(0.31, 0.62, 0.45), **kw)
+    if bg:
+        sc = sc.with_(background=True, bg=np.array([0.3, 0.1], np.float32))
+    compare_J(sc)

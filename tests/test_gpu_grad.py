@@ -332,3 +332,11 @@ def test_adjoint_against_central_differences_on_the_small_copy(which):
     scale = max(float(np.sum(np.abs(terms))), float(np.sum(np.abs(w * central))))
     print(f"{which}: {int(kink.sum())} of {kink.size} components at a kink skipped")
     assert abs(lhs - rhs) <= 1e-4 * scale, (lhs, rhs, scale, int(kink.sum()))
+
+
+def test_adjoint_directed_rays():
+    """The adjoint with directed rays (the source-position adjoint uses the
+    aimed direction of the ray its source sits on)."""
+    sc = scenes.lognormal_scene(n=4000, seed=65, grid=16, bands=(1.0, 10.0), nside=2,
+                                directed=(0.31, 0.62, 0.45))
+    _dot_check(sc, sc.active)

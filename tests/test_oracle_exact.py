@@ -294,3 +294,41 @@ def test_absorption_average_vacuum_halving_and_first_order_limit():
     # and the transmission average never exceeds the linear one (Jensen's
     # inequality; -ln(T)/d at T = 1 - 1e-5 carries ~1e-11 relative rounding)
     assert np.all(a_tr <= a_lin * (1 + 1e-9))
+
+
+# ------------------------------------------------------- directed rays
+@pytest.mark.parametrize("nside", [1, 2])
+def test_directed_ray_lattice_closed_form(nside):
+    """Directed rays (Sections 3.4.1, 4) on the gap-free lattice with one
+    source p: the ray that carries p is aimed at it, so p sits on the ray at
+    s = |p - c| and the chords from r to s add up to s - r along the aimed
+    direction u; the p-p column of that ray is taken along u:
+      J_i = L K(r_i, h_i) exp(-tpp_i(u) - kappa rho (|p - c| - r) r_i / |p - c|)."""
+    sc = _lattice(nside=nside, near_field=True)
+    pos = sc.positions().astype(np.float64)
+    rc = np.linalg.norm(pos - 0.5, axis=1)
+    j = int(np.flatnonzero(rc < 0.05)[0])
+    sc.lum[:, j] = [1.0, 2.0]
+    sc = sc.with_(directed=tuple(float(v) for v in pos[j]))
+    act = ((rc < 0.12) & (rc > 0.06)).astype(np.uint8)
+    J, c = oracle.OracleTree(sc).compute_J(act)
+    r = _rpp_of(sc, act)
+    h = _h(sc)
+    kap = sc.kappa.astype(np.float64)
+    m = sc.m.astype(np.float64)
+    cen = _bucket_centre(pos)
+    checked = 0
+    for i in np.flatnonzero(act):
+        cb = cen[i]
+        v = pos[j] - cb
+        d = np.sqrt(v @ v)
+        if d < r[i]:
+            continue                      # a near source: p-p path, pinned above
+        u = v / d
+        near_set = np.flatnonzero(np.linalg.norm(pos - cb, axis=1) < r[i])
+        rij = np.linalg.norm(pos[j] - pos[i])
+        tau = bf.ray_depth(pos, m, h, kap, i, u, near_set) + kap[:, 0] * (d - r[i]) * rij / d
+        ref = sc.lum[:, j].astype(np.float64) * bf.kernel(rij, h[i]) * np.exp(-tau)
+        assert np.max(np.abs(J[:, i] - ref) / ref) < 1e-12, (i, J[:, i], ref)
+        checked += 1
+    assert checked > 100
