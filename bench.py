@@ -1,23 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the TREVR2 hot path on one MI355X, in receiver-ray segments/s.
 
-A step is one pass of the whole path over one scene resident in HBM: build
-the radiation tree (Morton sort, topology, moments, transmission tables),
-compute J at the active elements, and run the adjoint for a fixed seeded
-dE/dJ (gradients with respect to L, kappa and rho).  The segment count (per
-active element and ray: 1 + absorbing cells with a chord beyond r_pp +
-sources on the ray) is the library's counter, equal to the oracle's by
-test; `value` is segments per step over the step time (build + forward +
-adjoint), and the forward alone and forward + adjoint on a resident tree
-are reported beside it.
+Headline (`value`): batched forward + adjoint.  A step is one replay of a HIP
+graph holding the batched forward (J of every active element of 64
+independent scenes) and its adjoint (gradients of a fixed seeded
+<dE/dJ, J> with respect to L, kappa and rho), with the scenes' trees and
+inputs resident in HBM.  Segments (per active element and ray: 1 + absorbing
+cells with a chord beyond r_pp + sources on the ray) are the library's
+counter, equal to the oracle's by test; `value` = segments per step / step
+time.
 
-Workload: the clumpy medium -- 2^18 elements drawn from a log-normal density
-field (P(k) ~ k^-3, sigma_ln rho = 1.5), 10% sources with log-normal
-luminosities, 3 bands (opacity 1:10:100), N_side 2 (48 rays), theta 0.75,
-leaf 8, all elements active.
+Workload: 64 scenes of log-uniform size 2^12..2^17 elements (2.2M in all),
+each a uniform or a log-normal medium (C1 / C2 generators), 1-4 bands, N_side
+1, 2 or 4, theta 0.75, leaf 8, all elements active.
 
-Prints one JSON line (see the keys below).  `--gpus N` with N > 1 is not
-supported: this build runs on one GPU.
+Beside it (extra keys): the batched forward alone, the same graph with mixed
+per-scene active fractions, the plain path (each scene's own tree called in
+turn), the single-scene clumpy 2^18 workload, the diffuse 2^21 workload at 1%,
+10% and 100% active, the cost of 10 bands against 1, the roofline of the
+dominant kernel, the traversal-byte HBM fraction, and the oracle's CPU rate.
+
+Prints one JSON line.  `--gpus N` with N > 1 is not supported: this build
+runs on one GPU.
 """
 from __future__ import annotations
 
@@ -32,66 +36,93 @@ sys.path.insert(0, ROOT)
 
 METRIC = "receiver-ray segments/sec (fwd, fwd+adjoint) at J rel. err ≤1e-4 vs FP64"
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 
 
-def flop_model(c: dict, B: int, nray: int) -> float:
-    """Algorithmic floating-point operations of one compute_J (each add,
-    multiply, divide, square root and exponential counts one):
-      far source at a receiver      37 + 6B per (receiver, source entry)
-      cell-ray intersection         20 + 2B per (bucket, absorber entry)
-      p-p column along a ray        24      per (receiver, ray, p-p element)
-      p-p source path               35      per (receiver, p-p source, p-p element)"""
-    return (c["src_pairs"] * (37 + 6 * B) + c["absorber_entries"] * (20 + 2 * B)
-            + nray * c["near_pairs"] * 24 + c["near_src_triples"] * 35)
+def note(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def near_flops(c: dict, nray: int) -> float:
-    """The p-p part of flop_model (the work of the near-field kernel)."""
-    return nray * c["near_pairs"] * 24 + c["near_src_triples"] * 35
+# ----------------------------------------------------------- work models
+# Algorithmic floating-point operations (each add, multiply, divide, square
+# root and exponential counts one), per unit of work the oracle counts:
+#   far source at a receiver        37 + 6B   per (receiver, source entry)
+#   cell-ray intersection           20 + 2B   per (bucket, absorber entry)
+#   p-p column along a ray          24        per (receiver, ray, p-p element)
+#   p-p source path                 35        per (receiver, p-p source, p-p element)
+# and for the adjoint kernels the forward arithmetic again plus the
+# derivatives:
+#   far source                      61 + 19B  (kernel slope 14, dK/dr, dK/dh 6,
+#                                              position 4, 13 per band)
+#   cell-ray intersection           40 + 8B   (two sweeps + absorption adjoint)
+#   p-p column                      24 + 8    (column slope in h, kappa term)
+#   p-p source path                 35 + 8
+def kernel_flops(c: dict, B: int, nray: int) -> dict:
+    return {
+        "k_pp_src": c["near_src_triples"] * 35.0,
+        "k_pp_rays": nray * c["near_pairs"] * 24.0,
+        "k_far": c["src_pairs"] * (37 + 6 * B) + c["absorber_entries"] * (20 + 2 * B),
+        "k_pp_src_bwd": c["near_src_triples"] * 43.0,
+        "k_pp_rays_bwd": nray * c["near_pairs"] * 32.0,
+        "k_far_bwd": c["src_pairs"] * (61 + 19 * B) + c["absorber_entries"] * (40 + 8 * B),
+    }
 
 
-def far_flops(c: dict, B: int) -> float:
-    return c["src_pairs"] * (37 + 6 * B) + c["absorber_entries"] * (20 + 2 * B)
+# Traversal bytes (HBM roofline model): per bucket, each accepted cell is read
+# once (box 24 B, luminosity centre 12 B, luminosity 4B B), each (cell, ray)
+# intersection reads its transmission average (4B B), each active receiver
+# is read and its J written (20 + 8B B).
+def traversal_bytes(c: dict, B: int) -> float:
+    return (c["cells"] * (36 + 4 * B) + c["absorber_entries"] * 4 * B
+            + c["active"] * (20 + 8 * B))
 
 
-def far_adjoint_flops(c: dict, B: int) -> float:
-    """Arithmetic of the far-field adjoint kernel: per (receiver, source
-    entry) the forward term (37 + 6B) plus its derivatives (intensity-kernel
-    slope 14, dK/dr and dK/dh 6, position 4, 13 per band); per (bucket,
-    absorber entry) two sweeps of the hit arithmetic (2 x (20 + 2B)) and the
-    cell-absorption adjoint (4B)."""
-    return c["src_pairs"] * (61 + 19 * B) + c["absorber_entries"] * (40 + 8 * B)
+# Which profile slots time which kernel (the p-p columns are the near-field
+# phase minus the p-p source kernel).
+def kernel_ms(prof: dict) -> dict:
+    g = lambda k: prof[k][0]
+    n = lambda k: prof[k][1]
+    return {
+        "k_pp_src": (g("pp_src"), n("pp_src")),
+        "k_pp_rays": (g("near") - g("pp_src"), n("pp_src")),
+        "k_far": (g("reduce"), n("reduce")),
+        "k_pp_src_bwd": (g("adj_pp_src"), n("adj_pp_src")),
+        "k_pp_rays_bwd": (g("adj_near") - g("adj_pp_src"), n("adj_pp_src")),
+        "k_far_bwd": (g("adj_reduce"), n("adj_reduce")),
+    }
 
 
-def measured_traffic(kernel: str):
-    """HBM-side bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE runs (profiles/), or None when the kernel source
-    changed since they were taken."""
+def committed_profile(kernel: str, workload: str, kind: str):
+    """Figures of `kernel` from the committed rocprofv3 runs (profiles/),
+    or None when the kernel's sources changed since they were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_clumpy2e18_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{kind}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec["sources_sha256"]:
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return rec
 
 
-def batched_bench(args, dev):
-    """The batched workload: 64 independent scenes (log-uniform 2^12..2^17
-    elements, uniform or log-normal media, 1-4 bands, N_side 1/2/4), all
-    active, computed by the batched calls replayed from HIP graphs (forward;
-    forward + adjoint); against it the plain path, every scene's own tree
-    called in turn.  Also the same graph replayed with per-scene active
-    fractions of 1%, 10% or 100% written into its active buffer."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ------------------------------------------------------------- batched C4
+def batched(args, dev, extras: bool):
     import numpy as np
     import torch
     from paper_2310_15235_amd import api, scenes
-
-    def note(msg):
-        print(f"[batched] {msg}", file=sys.stderr, flush=True)
 
     scs = scenes.batched_scenes(64)
     torch.cuda.synchronize()
@@ -105,13 +136,36 @@ def batched_bench(args, dev):
     J = F.new_J()
     outs = (torch.empty_like(gJ), torch.empty_like(gJ),
             torch.empty(int(F.offsets[-1]), dtype=torch.float64, device=dev))
-    chosen, tune_ms = F.autotune(a, reps=1)   # forward only: the adjoint's p-p work follows it
+    chosen, tune_ms = F.autotune(a, reps=1)   # forward: the adjoint's p-p work follows it
     note(f"autotuned: configuration {chosen}, forward ms {[round(float(t), 1) for t in tune_ms]}")
     F.compute_J(a, out=J)
+    F.check()
+    per_scene = [F.counters(s) for s in range(F.S)]
+    seg = sum(c["segments"] for c in per_scene)
     F.compute_J_backward(gJ, a, out=outs)
     F.check()
-    seg = F.counters(-1)["segments"]
-    note("eager forward + adjoint done")
+
+    # kernel times of one forward + adjoint (HIP events on the stream the
+    # library launches on), and the algorithmic work of each kernel
+    F.profile(True)
+    F.compute_J(a, out=J)
+    F.compute_J_backward(gJ, a, out=outs)
+    prof = F.profile_read()
+    F.profile(False)
+    F.check()
+    kms = kernel_ms(prof)
+    flops = {}
+    tbytes = 0.0
+    for s, c in enumerate(per_scene):
+        c = dict(c, active=scs[s].n)
+        for k, v in kernel_flops(c, scs[s].n_bands, 12 * scs[s].nside ** 2).items():
+            flops[k] = flops.get(k, 0.0) + v
+        tbytes += traversal_bytes(c, scs[s].n_bands)
+    dom = max(kms, key=lambda k: kms[k][0])
+    d_ms, d_launch = kms[dom]
+    achieved = flops[dom] / (d_ms * 1e-3) / 1e12
+    note(f"dominant kernel {dom}: {d_ms:.1f} ms in {d_launch} launches, {achieved:.2f} TFLOP/s")
+
     torch.cuda.synchronize()
     g_f, g_fa = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
     with torch.cuda.graph(g_f):
@@ -120,92 +174,222 @@ def batched_bench(args, dev):
         F.compute_J(a, out=J)
         F.compute_J_backward(gJ, a, out=outs)
 
+    # headline: W warm-up replays, then K replays timed together
+    for _ in range(args.warmup):
+        g_fa.replay()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record()
+        g_fa.replay()
+        e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    per_replay = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    note(f"graph forward + adjoint: {ms_step:.1f} ms per step (median replay "
+         f"{per_replay[len(per_replay) // 2]:.1f} ms)")
+    Jg = J.cpu().numpy()
+
     def timed(fn, k):
         fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        ts = []
         for _ in range(k):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / k
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
 
-    k = max(1, min(args.steps, 2))   # each replay takes seconds at this size
-    ms_f = timed(g_f.replay, k)
+    ms_f = timed(g_f.replay, 3)
     note(f"graph forward {ms_f:.1f} ms")
-    ms_fa = timed(g_fa.replay, k)
-    note(f"graph forward + adjoint {ms_fa:.1f} ms")
-    # mixed individual time steps: per-scene active fractions in one buffer
-    rng = np.random.default_rng(7)
-    fr = rng.choice([0.01, 0.1, 1.0], size=F.S)
-    acts = [scenes.active_subset(s, f, 300 + i) if f < 1.0 else None
-            for i, (s, f) in enumerate(zip(scs, fr))]
-    a.copy_(F.flat_active(acts))
-    F.compute_J(a, out=J)
-    F.check()
-    seg_mixed = F.counters(-1)["segments"]
-    ms_fa_mixed = timed(g_fa.replay, k)
-    note(f"graph forward + adjoint, mixed active sets {ms_fa_mixed:.1f} ms")
-    a.copy_(F.flat_active([None] * F.S))
-    # the plain path: each scene's own tree, one after another
-    trees = [F.scene_tree(s) for s in range(F.S)]
-    Jp, gLp, gkp, grp = F.split(J), F.split(outs[0]), F.split(outs[1]), F.split(outs[2])
-    gJp = F.split(gJ)
-    ap_ = F.split(a)
-    bgs = [None if not s.background else torch.as_tensor(s.bg, device=dev) for s in scs]
-
-    def plain_f():
-        for s, T in enumerate(trees):
-            T.compute_J(ap_[s], bgs[s], out=Jp[s])
-
-    def plain_fa():
-        for s, T in enumerate(trees):
-            T.compute_J(ap_[s], bgs[s], out=Jp[s])
-            T.compute_J_backward(gJp[s], ap_[s], bgs[s], out=(gLp[s], gkp[s], grp[s]))
-
-    plain_fa()
-    ms_pf = timed(plain_f, k)
-    note(f"plain forward {ms_pf:.1f} ms")
-    ms_pfa = timed(plain_fa, k)
-    note(f"plain forward + adjoint {ms_pfa:.1f} ms")
-    for T in trees:
-        T.check()
-    F.close()
-    n_tot = int(F.offsets[-1])
-    return {
-        "workload": "64 scenes, 2^12..2^17 elements each (log-uniform), uniform or log-normal "
-                    "media, 1-4 bands, N_side 1/2/4, theta 0.75, leaf 8, all active",
-        "scenes": F.S, "elements": n_tot, "segments_per_step": seg,
-        "timed_replays": k,
-        "graph": True,
-        "fwd": {"value": seg / (ms_f * 1e-3), "ms": ms_f},
-        "fwd_adjoint": {"value": seg / (ms_fa * 1e-3), "ms": ms_fa},
-        "plain_fwd": {"value": seg / (ms_pf * 1e-3), "ms": ms_pf},
-        "plain_fwd_adjoint": {"value": seg / (ms_pfa * 1e-3), "ms": ms_pfa},
-        "mixed_active": {"segments_per_step": seg_mixed,
-                         "fwd_adjoint": {"value": seg_mixed / (ms_fa_mixed * 1e-3),
-                                         "ms": ms_fa_mixed},
-                         "fractions": "1% / 10% / 100% per scene"},
-        "build_and_plan_ms": (b1 - b0) * 1e3,
+    rec = {
+        "seg": seg, "ms_step": ms_step, "per_replay_ms": {"median": per_replay[len(per_replay) // 2],
+                                                          "min": per_replay[0]},
+        "fwd_ms": ms_f, "prof": prof, "kernel_ms": kms, "flops": flops,
+        "dominant": dom, "achieved": achieved, "launches": d_launch, "dom_ms": d_ms,
+        "traversal_bytes": tbytes, "build_and_plan_ms": (b1 - b0) * 1e3,
         "autotune": {"chosen": chosen, "candidate_fwd_ms": [float(t) for t in tune_ms],
                      "candidates": "bit 2: bucket order (cost / scene), bit 1: persistent "
                                    "grid (full / half), bit 0: p-p boxes (16 / 8)"},
+        "J": Jg, "scenes": scs, "forest": F, "n_total": int(F.offsets[-1]),
     }
+    if extras:
+        # mixed individual time steps: per-scene active fractions in one buffer
+        rng = np.random.default_rng(7)
+        fr = rng.choice([0.01, 0.1, 1.0], size=F.S)
+        acts = [scenes.active_subset(s, f, 300 + i) if f < 1.0 else None
+                for i, (s, f) in enumerate(zip(scs, fr))]
+        a.copy_(F.flat_active(acts))
+        F.compute_J(a, out=J)
+        F.check()
+        seg_mixed = F.counters(-1)["segments"]
+        ms_mixed = timed(g_fa.replay, 1)
+        note(f"graph forward + adjoint, mixed active sets {ms_mixed:.1f} ms")
+        a.copy_(F.flat_active([None] * F.S))
+        # the plain path: each scene's own tree, one after another
+        trees = [F.scene_tree(s) for s in range(F.S)]
+        Jp, gLp, gkp, grp = F.split(J), F.split(outs[0]), F.split(outs[1]), F.split(outs[2])
+        gJp, ap_ = F.split(gJ), F.split(a)
+        bgs = [None if not s.background else torch.as_tensor(s.bg, device=dev) for s in scs]
+
+        def plain_f():
+            for s, T in enumerate(trees):
+                T.compute_J(ap_[s], bgs[s], out=Jp[s])
+
+        def plain_fa():
+            for s, T in enumerate(trees):
+                T.compute_J(ap_[s], bgs[s], out=Jp[s])
+                T.compute_J_backward(gJp[s], ap_[s], bgs[s], out=(gLp[s], gkp[s], grp[s]))
+
+        ms_pf = timed(plain_f, 1)
+        ms_pfa = timed(plain_fa, 1)
+        note(f"plain forward {ms_pf:.1f} ms, forward + adjoint {ms_pfa:.1f} ms")
+        for T in trees:
+            T.check()
+        rec.update(seg_mixed=seg_mixed, ms_mixed=ms_mixed, ms_plain_f=ms_pf, ms_plain_fa=ms_pfa)
+    return rec
 
 
-def measured_counters(kernel: str):
-    """VALU issue utilisation, L2 hit rate and LDS figures of `kernel` from
-    the committed rocprofv3 counter runs (profiles/), or None when the kernel
-    source changed since they were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_clumpy2e18_counters.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
-        return None
-    return {k: rec[k] for k in ("valu_issue_util", "l2_hit_rate", "lds_instr_per_valu",
-                                "lds_bank_conflicts_per_lds_instr")}
+def c4_cpu_baseline(rec, per_scene_recv=24, one_core_scenes=16):
+    """The oracle (OpenMP over buckets) on a bounded sample: `per_scene_recv`
+    random receivers of every scene, each scene's tree built in full and its
+    build time prorated by the sampled fraction; the same with one thread on
+    the first scenes.  Returns the record and the sampled J for the
+    self-check."""
+    import numpy as np
+    import oracle
+    from paper_2310_15235_amd import scenes as S
+    scs = rec["scenes"]
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+
+    def run(idx, nt, k):
+        seg, t_j, t_b = 0, 0.0, 0.0
+        samples = []
+        for s in idx:
+            sc = scs[s]
+            rng = np.random.default_rng(500 + s)
+            act = np.zeros(sc.n, np.uint8)
+            act[rng.choice(sc.n, size=min(k, sc.n), replace=False)] = 1
+            c0 = time.perf_counter()
+            O = oracle.OracleTree(sc)
+            c1 = time.perf_counter()
+            Jo, oc = O.compute_J(act, nthreads=nt)
+            c2 = time.perf_counter()
+            seg += oc["segments"]
+            t_j += c2 - c1
+            t_b += (c1 - c0) * act.sum() / sc.n
+            samples.append((s, act, Jo))
+        return seg, t_j, t_b, samples
+
+    seg, t_j, t_b, samples = run(range(len(scs)), nthreads, per_scene_recv)
+    seg1, t_j1, t_b1, _ = run(range(one_core_scenes), 1, per_scene_recv // 3)
+    return {"value": seg / (t_j + t_b), "unit": "segments/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{per_scene_recv} random receivers of each of the {len(scs)} scenes "
+                      f"(forward; the oracle has no adjoint), every tree built in full with its "
+                      f"build time prorated by the sampled fraction: {seg} segments, J "
+                      f"{t_j:.2f} s + build {t_b:.3f} s",
+            "single_core": {"value": seg1 / (t_j1 + t_b1), "cores": 1,
+                            "sample": f"{per_scene_recv // 3} receivers of each of the first "
+                                      f"{one_core_scenes} scenes"},
+            "cpu_model": cpu_model()}, samples
+
+
+def self_check(rec, samples):
+    """The headline's own J against the oracle's at the sampled receivers."""
+    import numpy as np
+    F = rec["forest"]
+    Jg = rec["J"]
+    worst, count = 0.0, 0
+    for s, act, Jo in samples:
+        g = Jg[int(F.boff[s]):int(F.boff[s + 1])].reshape(F.B[s], F.n[s])
+        a = act.astype(bool)
+        floor = 1e-12 * np.abs(Jo[:, a]).max(axis=1, keepdims=True)
+        e = np.abs(g[:, a] - Jo[:, a]) / np.maximum(np.abs(Jo[:, a]), np.maximum(floor, 1e-300))
+        worst = max(worst, float(e.max()))
+        count += int(a.sum())
+    return {"receivers": count, "max_rel_err": worst, "tol": 1e-4, "pass": worst <= 1e-4}
+
+
+# ------------------------------------------------------- one-scene legs
+def single_tree(sc, dev, reps=3, active=None, label=""):
+    """Forward and forward + adjoint on a resident tree (median of `reps`),
+    tree build time, per-phase kernel times, counters."""
+    import numpy as np
+    import torch
+    from paper_2310_15235_amd import api
+    n, B = sc.n, sc.n_bands
+    act = torch.as_tensor(sc.active if active is None else active, device=dev)
+    bg = None if not sc.background else torch.as_tensor(sc.bg, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    T = api.Tree.from_scene(sc, device=dev)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_build = ev0.elapsed_time(ev1)
+    J = torch.zeros((B, n), dtype=torch.float64, device=dev)
+    gJ = torch.as_tensor(np.random.default_rng(7).normal(size=(B, n)), device=dev)
+    grads = (torch.empty((B, n), dtype=torch.float64, device=dev),
+             torch.empty((B, n), dtype=torch.float64, device=dev),
+             torch.empty((n,), dtype=torch.float64, device=dev))
+    T.compute_J(act, bg, out=J)
+    T.compute_J_backward(gJ, act, bg, out=grads)
+    T.check()
+    c = T.counters()
+
+    def med(fn):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    ms_f = med(lambda: T.compute_J(act, bg, out=J))
+    T.profile(True)
+    ms_fa = med(lambda: (T.compute_J(act, bg, out=J), T.compute_J_backward(gJ, act, bg,
+                                                                             out=grads)))
+    prof = T.profile_read()
+    T.profile(False)
+    T.check()
+    T.close()
+    seg = c["segments"]
+    note(f"{label}: build {ms_build:.1f} ms, forward {ms_f:.2f} ms, forward + adjoint "
+         f"{ms_fa:.2f} ms, {seg} segments")
+    return {"segments": seg, "build_ms": ms_build,
+            "fwd": {"value": seg / (ms_f * 1e-3), "ms": ms_f},
+            "fwd_adjoint": {"value": seg / (ms_fa * 1e-3), "ms": ms_fa},
+            "kernel_ms_per_step": {k: v[0] / reps for k, v in prof.items() if v[1]},
+            "counters": c}
+
+
+def bands_cost(dev):
+    """Section 3.1: ten bands cost about 1.3x one band.  The clumpy 2^18
+    geometry with 1 band and with 10 (opacities 1..100), forward time on a
+    resident tree."""
+    import numpy as np
+    from paper_2310_15235_amd import scenes
+    out = {}
+    for nb in (1, 10):
+        bands = tuple(float(10 ** (2 * k / 9)) for k in range(nb)) if nb > 1 else (1.0,)
+        sc = scenes.lognormal_scene(n=2 ** 18, seed=2, grid=64, bands=bands, nside=2,
+                                    name=f"clumpy_b{nb}")
+        r = single_tree(sc, dev, reps=3, label=f"clumpy 2^18, {nb} band(s)")
+        out[f"B{nb}"] = {"fwd_ms": r["fwd"]["ms"], "fwd_adjoint_ms": r["fwd_adjoint"]["ms"]}
+    out["fwd_ratio"] = out["B10"]["fwd_ms"] / out["B1"]["fwd_ms"]
+    out["fwd_adjoint_ratio"] = out["B10"]["fwd_adjoint_ms"] / out["B1"]["fwd_adjoint_ms"]
+    out["paper"] = "10 bands cost about 1.3x one band (Section 3.1, serial CPU run)"
+    return out
 
 
 def main():
@@ -214,14 +398,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=float, default=0.05,
-                    help="fraction of receivers the oracle evaluates for the CPU baseline")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched 64-scene measurement")
-    ap.add_argument("--no-keep-depths", action="store_true",
-                    help="skip the forward + adjoint timing with the depth cache")
-    ap.add_argument("--only-batched", action="store_true",
-                    help="run only the batched 64-scene measurement and print its record")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the batched headline (for profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic, for scaling HBM byte counters)")
@@ -230,182 +408,105 @@ def main():
         print("bench.py runs on exactly one GPU (this build has no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
+    args.steps = max(1, args.steps)
 
-    import numpy as np
     import torch
-    from paper_2310_15235_amd import api, scenes
+    from paper_2310_15235_amd import scenes
 
     dev = torch.device("cuda:0")
-    if args.only_batched:
-        print(json.dumps({"batched": batched_bench(args, dev)}), flush=True)
-        return
-    sc = scenes.config_clumpy()
-    n, B, nray = sc.n, sc.n_bands, 12 * sc.nside ** 2
-    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
-    x, y, z, m, rho = f32(sc.x), f32(sc.y), f32(sc.z), f32(sc.m), f32(sc.rho)
-    kappa, lum = f32(sc.kappa), f32(sc.lum)
-    active = torch.as_tensor(sc.active, device=dev)
-    flags = api.THICK_CORR | api.NEAR_FIELD
-    kw = dict(nside=sc.nside, leaf_size=sc.leaf_size, theta=sc.theta, flags=flags, box=sc.box)
-    J = torch.zeros((B, n), dtype=torch.float64, device=dev)
-    gJ = torch.as_tensor(np.random.default_rng(7).normal(size=(B, n)), device=dev)
-    grads = (torch.empty((B, n), dtype=torch.float64, device=dev),
-             torch.empty((B, n), dtype=torch.float64, device=dev),
-             torch.empty((n,), dtype=torch.float64, device=dev))
     if args.calibrate_copy:
         src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    scratch = [None]   # one scratch buffer kept across steps, as a time-stepping caller would
-
-    def step():
-        T = api.Tree(x, y, z, m, rho, kappa, lum, scratch=scratch[0], **kw)
-        T.compute_J(active, None, out=J)
-        T.compute_J_backward(gJ, active, None, out=grads)
-        scratch[0] = T.scratch
-        return T
-
-    # warm-up (also sizes the scratch buffer once)
-    for _ in range(max(args.warmup, 1)):
-        T = step()
-        T.check()
-        counters = T.counters()
-        T.close()
-    seg = counters["segments"]
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        T = step()
-        T.close()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-
-    # forward alone and forward + adjoint on a resident tree, with per-phase
-    # HIP event timing recorded by the library on its stream
-    T = api.Tree(x, y, z, m, rho, kappa, lum, scratch=scratch[0], **kw)
-    T.compute_J(active, None, out=J)
-    T.compute_J_backward(gJ, active, None, out=grads)
-    T.profile(True)
-    torch.cuda.synchronize()
-    f0 = time.perf_counter()
-    for _ in range(args.steps):
-        T.compute_J(active, None, out=J)
-    torch.cuda.synchronize()
-    f1 = time.perf_counter()
-    prof_fwd = T.profile_read()
-    T.profile(True)
-    torch.cuda.synchronize()
-    a0 = time.perf_counter()
-    for _ in range(args.steps):
-        T.compute_J(active, None, out=J)
-        T.compute_J_backward(gJ, active, None, out=grads)
-    torch.cuda.synchronize()
-    a1 = time.perf_counter()
-    prof = T.profile_read()
-    T.check()
-    ms_fwd = (f1 - f0) * 1e3 / args.steps
-    ms_fwd_adj = (a1 - a0) * 1e3 / args.steps
-    T.close()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    T = api.Tree(x, y, z, m, rho, kappa, lum, scratch=scratch[0], **kw)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_build = ev0.elapsed_time(ev1)
-    T.close()
-
-    # forward + adjoint again with the depth cache (KEEP_DEPTHS): the forward
-    # keeps the far sources' cell optical depths and the adjoint reads them
-    # instead of recomputing every ray's prefixes (the default above)
-    ms_fwd_adj_keep = None
-    if not args.no_keep_depths:
-        kw_keep = dict(kw, flags=flags | api.KEEP_DEPTHS)
-        T = api.Tree(x, y, z, m, rho, kappa, lum, **kw_keep)
-        T.compute_J(active, None, out=J)
-        T.compute_J_backward(gJ, active, None, out=grads)
-        torch.cuda.synchronize()
-        k0 = time.perf_counter()
-        for _ in range(args.steps):
-            T.compute_J(active, None, out=J)
-            T.compute_J_backward(gJ, active, None, out=grads)
-        torch.cuda.synchronize()
-        k1 = time.perf_counter()
-        T.check()
-        T.close()
-        ms_fwd_adj_keep = (k1 - k0) * 1e3 / args.steps
-
-    # the dominant single kernel of a step: the far-field reduction or its
-    # adjoint (the p-p phases are two kernels each and shorter)
-    kname = max(("reduce", "adj_reduce"), key=lambda k: prof[k][0])
-    red_ms, red_calls = prof[kname]
-    flops = far_flops(counters, B) if kname == "reduce" else far_adjoint_flops(counters, B)
-    per_launch = flops / max(red_calls / args.steps, 1)
-    achieved = per_launch / (red_ms / max(red_calls, 1) * 1e-3) / 1e12
-    kernel = {"reduce": "k_far", "adj_reduce": "k_far_bwd"}[kname]
-    roofline = {"kernel": kernel, "bound": "alu",
-                "achieved": achieved,
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": measured_traffic(kernel),
-                "counters": measured_counters(kernel),
-                "launches_per_step": red_calls / args.steps,
-                "avg_launch_ms": red_ms / max(red_calls, 1),
-                "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
-                "fwd_kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof_fwd.items()
-                                           if v[1]}}
-
+    extras = not args.headline_only
+    rec = batched(args, dev, extras)
+    seg = rec["seg"]
+    dom = rec["dominant"]
+    traffic = committed_profile(dom, "batched64", "traffic")
+    counters = committed_profile(dom, "batched64", "counters")
+    roofline = {"kernel": dom, "bound": "alu", "achieved": rec["achieved"],
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": rec["achieved"] / PEAK_FP32_TFLOPS,
+                "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                "counters": None if counters is None else
+                {k: counters[k] for k in counters if k not in ("sources", "sources_sha256")},
+                "launches_per_step": rec["launches"],
+                "avg_launch_ms": rec["dom_ms"] / max(rec["launches"], 1),
+                "algorithmic_flops_per_launch": rec["flops"][dom] / max(rec["launches"], 1),
+                "kernel_ms_per_step": {k: v[0] for k, v in rec["kernel_ms"].items()},
+                "timing": "HIP events on the library's stream around each launch, one eager "
+                          "forward + adjoint of the same forest"}
+    fa_s = rec["ms_step"] * 1e-3
+    hbm = {"traversal_bytes_per_step": 2 * rec["traversal_bytes"],
+           "achieved_GBs": 2 * rec["traversal_bytes"] / fa_s / 1e9,
+           "peak_GBs": PEAK_HBM_GBS,
+           "frac": 2 * rec["traversal_bytes"] / fa_s / 1e9 / PEAK_HBM_GBS,
+           "model": "per bucket: accepted cells x (36 + 4B) B + (cell, ray) intersections x 4B B "
+                    "+ active receivers x (20 + 8B) B, read once by the forward and once by "
+                    "the adjoint"}
     cpu = None
+    check = None
     if not args.no_cpu_baseline:
-        import oracle
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-        act = scenes.active_subset(sc, args.cpu_sample, 123)
-        c0 = time.perf_counter()
-        O = oracle.OracleTree(sc)
-        c1 = time.perf_counter()
-        _, oc = O.compute_J(act, nthreads=nthreads)
-        c2 = time.perf_counter()
-        tb, tj = c1 - c0, c2 - c1
-        frac = act.sum() / n
-        cpu = {"value": oc["segments"] / (tj + frac * tb), "unit": "segments/s",
-               "cores": nthreads, "kind": "oracle",
-               "sample": f"{int(act.sum())} of {n} receivers ({args.cpu_sample:.0%}) of the same "
-                         f"scene; full tree build {tb:.2f} s prorated by that fraction, "
-                         f"J {tj:.2f} s"}
-
-    batched = None if args.no_batched else batched_bench(args, dev)
-
+        note("CPU baseline (oracle) on sampled receivers of the 64 scenes")
+        cpu, samples = c4_cpu_baseline(rec)
+        check = self_check(rec, samples)
+        note(f"self-check against the oracle: {check}")
+        if not check["pass"]:
+            print("warning: batched J differs from the oracle beyond 1e-4", file=sys.stderr)
     out = {
         "metric": METRIC,
-        "value": seg / (ms_step * 1e-3),
+        "value": seg / fa_s,
         "unit": "segments/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": rec["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "clumpy log-normal medium: 2^18 elements, 10% sources, 3 bands "
-                               "(kappa 1:10:100), N_side 2 (48 rays), theta 0.75, leaf 8, "
+        "config": {"workload": "batched forward + adjoint, HIP-graph replay: 64 scenes of "
+                               "2^12..2^17 elements (log-uniform, 2.2M in all), uniform or "
+                               "log-normal media, 1-4 bands, N_side 1/2/4, theta 0.75, leaf 8, "
                                "all active",
-                   "n": n, "bands": B, "nside": sc.nside, "active": int(sc.active.sum()),
+                   "scenes": len(rec["scenes"]), "elements": rec["n_total"],
                    "segments_per_step": seg},
-        "fwd": {"value": seg / (ms_fwd * 1e-3), "ms": ms_fwd},
-        "fwd_adjoint": {"value": seg / (ms_fwd_adj * 1e-3), "ms": ms_fwd_adj},
-        "fwd_adjoint_keep_depths": None if ms_fwd_adj_keep is None else
-            {"value": seg / (ms_fwd_adj_keep * 1e-3), "ms": ms_fwd_adj_keep},
-        "build_ms": ms_build,
+        "fwd_adjoint": {"value": seg / fa_s, "ms": rec["ms_step"],
+                        "replay_ms": rec["per_replay_ms"]},
+        "fwd": {"value": seg / (rec["fwd_ms"] * 1e-3), "ms": rec["fwd_ms"]},
         "roofline": roofline,
+        "hbm_traversal": hbm,
         "cpu_baseline": cpu,
-        "counters": counters,
-        "batched": batched,
+        "self_check": check,
+        "build_and_plan_ms": rec["build_and_plan_ms"],
+        "autotune": rec["autotune"],
     }
+    if extras:
+        out["mixed_active"] = {"segments_per_step": rec["seg_mixed"],
+                               "fwd_adjoint": {"value": rec["seg_mixed"] / (rec["ms_mixed"] * 1e-3),
+                                               "ms": rec["ms_mixed"]},
+                               "fractions": "1% / 10% / 100% per scene"}
+        out["plain"] = {"fwd": {"value": seg / (rec["ms_plain_f"] * 1e-3), "ms": rec["ms_plain_f"]},
+                        "fwd_adjoint": {"value": seg / (rec["ms_plain_fa"] * 1e-3),
+                                        "ms": rec["ms_plain_fa"]},
+                        "what": "each scene's own tree with the single-tree calls, in turn"}
+        rec["forest"].close()
+        out["clumpy2e18"] = single_tree(scenes.config_clumpy(), dev, reps=3,
+                                        label="clumpy 2^18")
+        sc3 = scenes.config_diffuse(active_frac=1.0)
+        diffuse = {}
+        for frac in (0.01, 0.1, 1.0):
+            act = None if frac == 1.0 else scenes.active_subset(sc3, frac, 17)
+            r = single_tree(sc3, dev, reps=2, active=act, label=f"diffuse 2^21, {frac:.0%} active")
+            diffuse[f"{frac:g}"] = {k: r[k] for k in ("segments", "build_ms", "fwd",
+                                                      "fwd_adjoint", "kernel_ms_per_step")}
+        out["diffuse2e21"] = diffuse
+        out["bands_cost"] = bands_cost(dev)
+    else:
+        rec["forest"].close()
     print(json.dumps(out), flush=True)
 
 

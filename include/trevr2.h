@@ -299,13 +299,15 @@ trevr_status trevr_tree_export(trevr_tree* t, int64_t* perm, int64_t* ints, doub
  *   ms[TREVR_PROF_ADJ_NEAR]   adjoint of the particle-particle transfer
  *   ms[TREVR_PROF_ADJ_TREE]   adjoint of the p-p radii and of the tree
  *                             moments, gradients to input order
+ *   ms[TREVR_PROF_PP_SRC]     the p-p source-path kernel alone (part of NEAR)
+ *   ms[TREVR_PROF_ADJ_PP_SRC] its adjoint alone (part of ADJ_NEAR)
  * (compute_J_backward also records SETUP, WALK and NEAR for the forward
  * steps it repeats), with launches[] the number of timed launches of each.
  * Totals accumulate from the last enable; `on` = 0 stops recording.
  */
 enum { TREVR_PROF_SETUP = 0, TREVR_PROF_WALK = 1, TREVR_PROF_REDUCE = 2, TREVR_PROF_NEAR = 3,
        TREVR_PROF_ADJ_REDUCE = 4, TREVR_PROF_ADJ_NEAR = 5, TREVR_PROF_ADJ_TREE = 6,
-       TREVR_PROF_SLOTS = 7 };
+       TREVR_PROF_PP_SRC = 7, TREVR_PROF_ADJ_PP_SRC = 8, TREVR_PROF_SLOTS = 9 };
 trevr_status trevr_profile_enable(trevr_tree* t, int on);
 trevr_status trevr_profile_read(trevr_tree* t, double* ms, int64_t* launches);
 
@@ -378,8 +380,9 @@ trevr_status trevr_compute_J_batched(trevr_forest* f, const uint8_t* active, con
  * written the scratch since, its bucket setup, walks and p-p columns are
  * used as they are; they must be for the same active set -- checked on the
  * device by fingerprint, a mismatch raising a sticky flag that
- * trevr_forest_check reports as TREVR_E_STATE.  Otherwise they are
- * recomputed.  Enqueues kernels only (graph capturable). */
+ * trevr_forest_check reports as TREVR_E_STATE and filling gL, gkappa and
+ * grho with NaN.  Otherwise they are recomputed.  Enqueues kernels only
+ * (graph capturable). */
 trevr_status trevr_compute_J_backward_batched(trevr_forest* f, const uint8_t* active,
                                               const float* bg, const double* gJ, double* gL,
                                               double* gkappa, double* grho, void* scratch,
@@ -409,6 +412,13 @@ trevr_status trevr_forest_autotune(trevr_forest* f, const uint8_t* active, const
                                    void* stream, int32_t reps, double* times);
 trevr_status trevr_forest_set_config(trevr_forest* f, int32_t config);
 trevr_status trevr_forest_get_config(const trevr_forest* f, int32_t* config);
+
+/* Kernel timing of the batched calls (support call, as trevr_profile_enable
+ * and trevr_profile_read for a tree, same slots; every launch covers all
+ * scenes with one band count).  Recording must be off while a call is
+ * captured in a HIP graph. */
+trevr_status trevr_forest_profile_enable(trevr_forest* f, int on);
+trevr_status trevr_forest_profile_read(trevr_forest* f, double* ms, int64_t* launches);
 
 /* Synchronise and report sticky device errors of the forest and its scenes. */
 trevr_status trevr_forest_check(trevr_forest* f);

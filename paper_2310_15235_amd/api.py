@@ -30,11 +30,13 @@ EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_compute_J_backward_batched", "trevr_forest_check",
             "trevr_forest_get_counters", "trevr_forest_scene", "trevr_forest_destroy",
             "trevr_forest_autotune", "trevr_forest_set_config", "trevr_forest_get_config",
-            "trevr_compute_J_noalloc")
+            "trevr_compute_J_noalloc", "trevr_forest_profile_enable",
+            "trevr_forest_profile_read")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # the fixed device array of trevr_compute_J_noalloc
 TUNE_STACK, TUNE_CUT, TUNE_STAGE = 0, 1, 2
 CONFIGS = 8          # launch configurations of the forest autotuner
-PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree")
+PROF_NAMES = ("setup", "walk", "reduce", "near", "adj_reduce", "adj_near", "adj_tree", "pp_src",
+              "adj_pp_src")
 PROF_SLOTS = len(PROF_NAMES)
 
 
@@ -515,6 +517,19 @@ class Forest:
         _check(lib().trevr_forest_get_counters(self.handle, int(scene), ctypes.byref(c)),
                "trevr_forest_get_counters")
         return {k: int(getattr(c, k)) for k, _ in Counters._fields_}
+
+    def profile(self, on: bool = True):
+        _check(lib().trevr_forest_profile_enable(self.handle, int(on)),
+               "trevr_forest_profile_enable")
+
+    def profile_read(self):
+        """{phase: (milliseconds, launches)} recorded since profile(True)."""
+        ms = np.zeros(PROF_SLOTS)
+        calls = np.zeros(PROF_SLOTS, np.int64)
+        _check(lib().trevr_forest_profile_read(self.handle, ms.ctypes.data_as(ctypes.c_void_p),
+                                               calls.ctypes.data_as(ctypes.c_void_p)),
+               "trevr_forest_profile_read")
+        return {nm: (float(ms[i]), int(calls[i])) for i, nm in enumerate(PROF_NAMES)}
 
     def scene_tree(self, s: int) -> "Tree":
         """The tree of scene s as a Tree (owned by the forest) for the

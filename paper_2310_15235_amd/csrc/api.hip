@@ -60,18 +60,64 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
   return TREVR_OK;
 }
 
-hipEvent_t prof_begin(trevr_tree* t) {
-  if (!t || !t->prof_on || t->ev_used + 2 > t->ev_pool.size()) return nullptr;
-  hipEvent_t e = t->ev_pool[t->ev_used++];
-  if (hipEventRecord(e, t->stream) != hipSuccess) return nullptr;
+hipEvent_t prof_begin(Prof* p, hipStream_t st) {
+  if (!p || !p->on || p->used + 2 > p->pool.size()) return nullptr;
+  hipEvent_t e = p->pool[p->used++];
+  if (hipEventRecord(e, st) != hipSuccess) return nullptr;
   return e;
 }
 
-void prof_end(trevr_tree* t, int slot, hipEvent_t begin) {
-  if (!t || !begin || t->ev_used + 1 > t->ev_pool.size()) return;
-  hipEvent_t e = t->ev_pool[t->ev_used++];
-  if (hipEventRecord(e, t->stream) != hipSuccess) return;
-  t->ev_pending.push_back({slot, {begin, e}});
+void prof_end(Prof* p, hipStream_t st, int slot, hipEvent_t begin) {
+  if (!p || !begin || p->used + 1 > p->pool.size()) return;
+  hipEvent_t e = p->pool[p->used++];
+  if (hipEventRecord(e, st) != hipSuccess) return;
+  p->pending.push_back({slot, {begin, e}});
+}
+
+// Fold recorded event pairs into the totals (the stream is synchronised).
+static void prof_collect(Prof* p) {
+  for (auto& pe : p->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      p->ms[pe.first] += ms;
+      p->calls[pe.first] += 1;
+    }
+  }
+  p->pending.clear();
+  p->used = 0;
+}
+
+trevr_status prof_enable(Prof* p, hipStream_t st, bool on) {
+  hipError_t he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_check(he, "sync");
+  p->pending.clear();
+  p->used = 0;
+  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { p->ms[i] = 0.0; p->calls[i] = 0; }
+  if (on && p->pool.empty()) {
+    p->pool.resize(4096);
+    for (auto& e : p->pool) {
+      he = hipEventCreate(&e);
+      if (he != hipSuccess) return hip_check(he, "hipEventCreate");
+    }
+  }
+  p->on = on;
+  return TREVR_OK;
+}
+
+trevr_status prof_read(Prof* p, hipStream_t st, double* ms, int64_t* launches) {
+  hipError_t he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_check(he, "sync");
+  prof_collect(p);
+  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) {
+    if (ms) ms[i] = p->ms[i];
+    if (launches) launches[i] = p->calls[i];
+  }
+  return TREVR_OK;
+}
+
+void prof_destroy(Prof* p) {
+  for (auto& e : p->pool) (void)hipEventDestroy(e);
+  p->pool.clear();
 }
 
 trevr_status upload_dev(trevr_tree* t) {
@@ -83,19 +129,6 @@ trevr_status upload_dev(trevr_tree* t) {
                        hipMemcpyHostToDevice, t->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(t->stream);
   return hip_check(e, "tree table upload");
-}
-
-// Fold recorded event pairs into the totals (the stream is synchronised).
-static void prof_collect(trevr_tree* t) {
-  for (auto& pe : t->ev_pending) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
-      t->prof_ms[pe.first] += ms;
-      t->prof_calls[pe.first] += 1;
-    }
-  }
-  t->ev_pending.clear();
-  t->ev_used = 0;
 }
 
 }  // namespace trevr
@@ -120,32 +153,12 @@ const char* trevr_last_error(void) { return g_last_error.c_str(); }
 
 trevr_status trevr_profile_enable(trevr_tree* t, int on) {
   if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
-  hipError_t he = hipStreamSynchronize(t->stream);
-  if (he != hipSuccess) return hip_check(he, "sync");
-  t->ev_pending.clear();
-  t->ev_used = 0;
-  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { t->prof_ms[i] = 0.0; t->prof_calls[i] = 0; }
-  if (on && t->ev_pool.empty()) {
-    t->ev_pool.resize(512);
-    for (auto& e : t->ev_pool) {
-      he = hipEventCreate(&e);
-      if (he != hipSuccess) return hip_check(he, "hipEventCreate");
-    }
-  }
-  t->prof_on = on != 0;
-  return TREVR_OK;
+  return prof_enable(&t->prof, t->stream, on != 0);
 }
 
 trevr_status trevr_profile_read(trevr_tree* t, double* ms, int64_t* launches) {
   if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
-  hipError_t he = hipStreamSynchronize(t->stream);
-  if (he != hipSuccess) return hip_check(he, "sync");
-  prof_collect(t);
-  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) {
-    if (ms) ms[i] = t->prof_ms[i];
-    if (launches) launches[i] = t->prof_calls[i];
-  }
-  return TREVR_OK;
+  return prof_read(&t->prof, t->stream, ms, launches);
 }
 
 trevr_status trevr_workspace_bytes(const trevr_params* p, int64_t n, size_t* tree_bytes,
@@ -181,14 +194,11 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   T->ws_bytes = tree_ws_bytes;
   T->scratch_needed = 0;
   T->counters_valid = false;
-  T->prof_on = false;
-  T->ev_used = 0;
   T->host_u32 = nullptr;
   T->fwd = FwdState{false, nullptr, 0, 0, 0, 0, 0, 0, 0, false, 0, false};
   T->stack_large = false;
   T->cut_default = kCutCap;
   T->stage_limit = (uint32_t)kStageCap;
-  for (int i = 0; i < TREVR_PROF_SLOTS; ++i) { T->prof_ms[i] = 0.0; T->prof_calls[i] = 0; }
   const size_t need = layout_tree(*p, n, T->nclass, nullptr, nullptr);
   if (tree_ws_bytes < need) {
     delete T;
@@ -389,7 +399,7 @@ trevr_status trevr_tree_destroy(trevr_tree* t) {
   }
   t->magic = 0;
   (void)hipStreamSynchronize(t->stream);
-  for (auto& e : t->ev_pool) (void)hipEventDestroy(e);
+  prof_destroy(&t->prof);
   if (t->host_u32) (void)hipHostFree(t->host_u32);
   delete t;
   return TREVR_OK;

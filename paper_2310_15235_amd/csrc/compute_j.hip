@@ -1709,9 +1709,11 @@ trevr_status compute_J_impl(trevr_tree* T, const uint8_t* active, const float* b
       if ((r = launch_pp_rays(L, T->B, S, host_items(S, Q_PPR, s0, scnt), scnt, active)) !=
           TREVR_OK)
         return r;
+      hipEvent_t e2 = prof_begin(T);
       if ((r = launch_pp_src(L, T->B, S, host_items(S, Q_PPS, s0, scnt), scnt, active, J)) !=
           TREVR_OK)
         return r;
+      prof_end(T, TREVR_PROF_PP_SRC, e2);
       prof_end(T, TREVR_PROF_NEAR, e0);
       hipEvent_t e1 = prof_begin(T);
       if ((r = launch_far(L, T->B, S, host_items(S, Q_FAR, s0, scnt), scnt, cap, bg, J,

@@ -1212,9 +1212,9 @@ Grad carve_grad(Carve& cv, const GradDims& d) {
 template <int NB>
 static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArgs& a,
                                  const Items& I, uint64_t count, uint32_t cap,
-                                 trevr_tree* prof) {
+                                 Prof* prof) {
   trevr_status rc;
-  hipEvent_t e0 = prof_begin(prof);
+  hipEvent_t e0 = prof_begin(prof, L.st);
   {
     const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_PPS_BWD};
     const void* fn = (const void*)&k_pp_src_bwd<NB>;
@@ -1223,8 +1223,11 @@ static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArg
         a.gJ, a.G, a.jraw);
     TREVR_LAUNCH_CHECK("k_pp_src_bwd");
   }
-  prof_end(prof, TREVR_PROF_ADJ_NEAR, e0);
-  hipEvent_t e1 = prof_begin(prof);
+  const size_t recorded = prof ? prof->pending.size() : 0;
+  prof_end(prof, L.st, TREVR_PROF_ADJ_NEAR, e0);
+  if (prof && prof->pending.size() == recorded + 1)   // the same span, p-p source adjoint alone
+    prof->pending.push_back({TREVR_PROF_ADJ_PP_SRC, prof->pending.back().second});
+  hipEvent_t e1 = prof_begin(prof, L.st);
   {
     const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_FAR_BWD};
     const void* fn = (const void*)&k_far_bwd<NB>;
@@ -1233,8 +1236,8 @@ static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArg
         a.active, a.gJ, a.jraw, a.gtpp, a.G, a.kept_tau, a.kept_tex);
     TREVR_LAUNCH_CHECK("k_far_bwd");
   }
-  prof_end(prof, TREVR_PROF_ADJ_REDUCE, e1);
-  hipEvent_t e2 = prof_begin(prof);
+  prof_end(prof, L.st, TREVR_PROF_ADJ_REDUCE, e1);
+  hipEvent_t e2 = prof_begin(prof, L.st);
   {
     const Items Ii{I.lo, I.hi, I.rng, S.q + 2 * Q_PPR_BWD};
     const void* fn = (const void*)&k_pp_rays_bwd<NB>;
@@ -1242,12 +1245,12 @@ static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArg
         L.TT, Ii, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, a.active, a.gtpp, a.G);
     TREVR_LAUNCH_CHECK("k_pp_rays_bwd");
   }
-  prof_end(prof, TREVR_PROF_ADJ_NEAR, e2);
+  prof_end(prof, L.st, TREVR_PROF_ADJ_NEAR, e2);
   return rc;
 }
 
 trevr_status bwd_items(const Launch& L, int B, const Scratch& S, const BwdArgs& a,
-                       const Items& I, uint64_t count, uint32_t cap, trevr_tree* prof) {
+                       const Items& I, uint64_t count, uint32_t cap, Prof* prof) {
   switch (B) {
     case 1: return bwd_items_nb<1>(L, S, a, I, count, cap, prof);
     case 2: return bwd_items_nb<2>(L, S, a, I, count, cap, prof);
@@ -1380,7 +1383,8 @@ trevr_status compute_J_backward_impl(trevr_tree* T, const uint8_t* active, const
         return r;
       prof_end(T, TREVR_PROF_NEAR, ev_near);
     }
-    return bwd_items(L, T->B, S, a, Items{s0, s0 + scnt, nullptr, nullptr}, scnt, cap, T);
+    return bwd_items(L, T->B, S, a, Items{s0, s0 + scnt, nullptr, nullptr}, scnt, cap,
+                     &T->prof);
   };
   bool whole = reuse && T->fwd.cuts_kept;
   if (whole) {   // one batch, whose cut lists the forward left in place

@@ -55,6 +55,7 @@ struct trevr_forest {
   uint64_t fwd_epoch;
   trevr::LaunchCfg cfg;                // launch options (trevr_forest_autotune)
   int32_t cfg_index;
+  trevr::Prof prof;                    // kernel timing (trevr_forest_profile_enable)
 };
 
 namespace trevr {
@@ -119,6 +120,23 @@ __global__ void k_hash_check(const unsigned long long* h, uint32_t* err) {
   if (threadIdx.x == 0 && h[0] != h[1]) atomicOr(err, FERR_ACTIVE);
 }
 
+// After an adjoint that reused the forward's state: when the active set did
+// not match (FERR_ACTIVE), the gradients were computed for the wrong set,
+// so every output is overwritten with NaN rather than left plausible.
+__global__ void k_poison_if_stale(const uint32_t* err, double* gL, double* gk, int64_t nj,
+                                  double* grho, int64_t n) {
+  if (!(*err & FERR_ACTIVE)) return;
+  const double nan = __longlong_as_double(0x7FF8000000000000ll);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nj;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    gL[i] = nan;
+    gk[i] = nan;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    grho[i] = nan;
+}
+
 #define TREVR_LAUNCH_CHECK(what)                                               \
   do {                                                                         \
     if ((rc = hip_check(hipGetLastError(), what)) != TREVR_OK) return rc;      \
@@ -167,24 +185,38 @@ Items class_items(const Scratch& S, int B, int slot) {
 // The forward's per-bucket work after the setup: p-p lists, walks of every
 // active bucket, then per band count the p-p columns, p-p sources (J
 // starts with them; J == nullptr: pair depths only) and the far field.
-trevr_status forward_body(const trevr_forest* f, const Scratch& S, const uint8_t* active,
+trevr_status forward_body(trevr_forest* f, const Scratch& S, const uint8_t* active,
                           const float* bg, double* J, bool far) {
   const Launch L = forest_launch(f);
+  Prof* P = &f->prof;
   trevr_status rc;
+  hipEvent_t e = prof_begin(P, L.st);
   if ((rc = near_fill(L, S)) != TREVR_OK) return rc;
+  prof_end(P, L.st, TREVR_PROF_SETUP, e);
+  e = prof_begin(P, L.st);
   if ((rc = walk_launch(L, S, Items{0u, 0xFFFFFFFFu, S.rng, nullptr},
                         (uint64_t)f->leaves_total, f->cut_cap)) != TREVR_OK)
     return rc;
+  prof_end(P, L.st, TREVR_PROF_WALK, e);
   for (int B = 1; B <= kMaxBands; ++B) {
     const uint64_t cnt = (uint64_t)f->class_leaves[B - 1];
     if (cnt == 0) continue;
+    e = prof_begin(P, L.st);
     if ((rc = launch_pp_rays(L, B, S, class_items(S, B, Q_PPR), cnt, active)) != TREVR_OK)
       return rc;
+    prof_end(P, L.st, TREVR_PROF_NEAR, e);
+    e = prof_begin(P, L.st);
     if ((rc = launch_pp_src(L, B, S, class_items(S, B, Q_PPS), cnt, active, J)) != TREVR_OK)
       return rc;
+    const size_t recorded = P->pending.size();
+    prof_end(P, L.st, TREVR_PROF_PP_SRC, e);
+    if (P->pending.size() == recorded + 1)   // the same span in the near-field total
+      P->pending.push_back({TREVR_PROF_NEAR, P->pending.back().second});
+    e = prof_begin(P, L.st);
     if (far && (rc = launch_far(L, B, S, class_items(S, B, Q_FAR), cnt, f->cut_cap, bg, J,
                                 active)) != TREVR_OK)
       return rc;
+    prof_end(P, L.st, TREVR_PROF_REDUCE, e);
   }
   return TREVR_OK;
 }
@@ -270,7 +302,9 @@ trevr_status forest_compute_impl(trevr_forest* f, const uint8_t* active, const f
   const uint64_t epoch = scratch_mark(scratch);
   f->fwd_scratch = nullptr;
   if ((rc = zero_counters(f)) != TREVR_OK) return rc;
+  hipEvent_t e = prof_begin(&f->prof, f->stream);
   if ((rc = setup_kernels(forest_launch(f), active, fs.S)) != TREVR_OK) return rc;
+  prof_end(&f->prof, f->stream, TREVR_PROF_SETUP, e);
   if ((rc = forward_body(f, fs.S, active, bg, J, true)) != TREVR_OK) return rc;
   for (trevr_tree* t : f->trees) t->counters_valid = true;
   f->fwd_scratch = scratch;
@@ -309,10 +343,18 @@ trevr_status forest_backward_impl(trevr_forest* f, const uint8_t* active, const 
   for (int B = 1; B <= kMaxBands; ++B) {
     const uint64_t cnt = (uint64_t)f->class_leaves[B - 1];
     if (cnt == 0) continue;
-    if ((rc = bwd_items(L, B, S, a, class_items(S, B, 0), cnt, f->cut_cap, nullptr)) != TREVR_OK)
+    if ((rc = bwd_items(L, B, S, a, class_items(S, B, 0), cnt, f->cut_cap, &f->prof)) !=
+        TREVR_OK)
       return rc;
   }
+  hipEvent_t e = prof_begin(&f->prof, f->stream);
   if ((rc = bwd_tree_pass(L, S, a.G, f->level_work, gL, gk, grho)) != TREVR_OK) return rc;
+  prof_end(&f->prof, f->stream, TREVR_PROF_ADJ_TREE, e);
+  if (reuse) {
+    k_poison_if_stale<<<256, 256, 0, f->stream>>>(f->ferr, gL, gk, f->jn_total, grho,
+                                                  f->n_total);
+    TREVR_LAUNCH_CHECK("k_poison_if_stale");
+  }
   f->fwd_scratch = scratch;
   f->fwd_epoch = epoch;
   return TREVR_OK;
@@ -343,6 +385,7 @@ trevr_status trevr_forest_destroy(trevr_forest* f) {
   for (trevr_tree* t : f->trees)
     if (t) trevr_tree_destroy(t);
   if (f->host) (void)hipHostFree(f->host);
+  prof_destroy(&f->prof);
   f->magic = 0;
   delete f;
   return TREVR_OK;
@@ -490,6 +533,16 @@ trevr_status trevr_compute_J_backward_batched(trevr_forest* f, const uint8_t* ac
   if (rc != TREVR_OK) return rc;
   f->stream = (hipStream_t)stream;
   return forest_backward_impl(f, active, bg, gJ, gL, gkappa, grho, scratch);
+}
+
+trevr_status trevr_forest_profile_enable(trevr_forest* f, int on) {
+  if (!forest_live(f)) return set_error(TREVR_E_STATE, "unknown or destroyed forest");
+  return prof_enable(&f->prof, f->stream, on != 0);
+}
+
+trevr_status trevr_forest_profile_read(trevr_forest* f, double* ms, int64_t* launches) {
+  if (!forest_live(f)) return set_error(TREVR_E_STATE, "unknown or destroyed forest");
+  return prof_read(&f->prof, f->stream, ms, launches);
 }
 
 trevr_status trevr_forest_check(trevr_forest* f) {

@@ -143,7 +143,7 @@ Grad carve_grad(Carve& cv, const GradDims& d);
 // The adjoint's per-bucket kernels (p-p sources, far field, p-p columns) for
 // the items of band count B; prof (nullable) records their times.
 trevr_status bwd_items(const Launch& L, int B, const Scratch& S, const BwdArgs& a,
-                       const Items& I, uint64_t count, uint32_t cap, trevr_tree* prof);
+                       const Items& I, uint64_t count, uint32_t cap, Prof* prof);
 // After the per-bucket kernels: r_pp adjoints, sums of the accumulator
 // copies, the tree top-down per depth (level_work[d]: the widest scene's
 // (nodes x classes) at depth d) and the gradients in input order.

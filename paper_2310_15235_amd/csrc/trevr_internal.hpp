@@ -103,6 +103,20 @@ struct FwdState {
   bool kept;            // far-source optical depths of the forward are in the scratch
 };
 
+namespace trevr {
+// Kernel timing of a tree or a forest (trevr_profile_enable,
+// trevr_forest_profile_enable): HIP event pairs recorded on the owner's
+// stream around launches, folded into per-slot totals when read.
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[TREVR_PROF_SLOTS] = {};
+  int64_t calls[TREVR_PROF_SLOTS] = {};
+};
+}  // namespace trevr
+
 struct trevr_tree {
   uint64_t magic;
   trevr_params p;
@@ -123,13 +137,7 @@ struct trevr_tree {
   bool stack_large;                         // traversals need the large LDS stack
   uint32_t cut_default;                     // cut-list entries per bucket to try first
   uint32_t stage_limit;                     // most staging words per bucket for p-p sets
-  // kernel timing (trevr_profile_enable)
-  bool prof_on;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-  double prof_ms[TREVR_PROF_SLOTS];
-  int64_t prof_calls[TREVR_PROF_SLOTS];
+  trevr::Prof prof;                         // kernel timing (trevr_profile_enable)
 };
 
 namespace trevr {
@@ -153,7 +161,17 @@ size_t scratch_fixed_bytes(int64_t n);
 // tree) has written it since.
 uint64_t scratch_mark(const void* scratch);
 bool scratch_unchanged(const void* scratch, uint64_t epoch);
-// Record an event pair around a phase (no-op unless profiling is on).
-hipEvent_t prof_begin(trevr_tree* t);
-void prof_end(trevr_tree* t, int slot, hipEvent_t begin);
+// Record an event pair on stream st around a phase (no-op unless profiling
+// is on; p may be null).
+hipEvent_t prof_begin(Prof* p, hipStream_t st);
+void prof_end(Prof* p, hipStream_t st, int slot, hipEvent_t begin);
+inline hipEvent_t prof_begin(trevr_tree* t) { return t ? prof_begin(&t->prof, t->stream) : nullptr; }
+inline void prof_end(trevr_tree* t, int slot, hipEvent_t begin) {
+  if (t) prof_end(&t->prof, t->stream, slot, begin);
+}
+// Start (clearing the totals) or stop recording; creates the event pool.
+trevr_status prof_enable(Prof* p, hipStream_t st, bool on);
+// Synchronise st and copy the totals out (any pointer may be null).
+trevr_status prof_read(Prof* p, hipStream_t st, double* ms, int64_t* launches);
+void prof_destroy(Prof* p);
 }  // namespace trevr

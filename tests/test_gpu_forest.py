@@ -224,9 +224,36 @@ def test_forest_adjoint_with_a_different_active_set_is_reported():
     a2 = F.flat_active(_actives(scs, 0.5, 9))
     F.compute_J(a1)
     gJ = torch.zeros(int(F.boff[-1]), dtype=torch.float64, device="cuda")
-    F.compute_J_backward(gJ, a2)
+    outs = F.compute_J_backward(gJ, a2)
+    # the gradients of the wrong active set are not left plausible: NaN
+    for g in outs:
+        assert bool(torch.all(torch.isnan(g)))
     with pytest.raises(api.TrevrError):
         F.check()
+    F.close()
+
+
+def test_forest_profile_records_every_phase():
+    """Kernel timing of the batched calls: every phase of a forward and an
+    adjoint is timed, one launch per band count for the per-bucket kernels,
+    the p-p source kernels inside the near-field totals."""
+    api = _api()
+    scs = mixed_scenes()[:4]
+    F = api.Forest(scs)
+    import torch
+    a = F.flat_active(_actives(scs, 1.0, 0))
+    gJ = torch.as_tensor(np.random.default_rng(3).normal(size=int(F.boff[-1])), device="cuda")
+    F.profile(True)
+    F.compute_J(a)
+    F.compute_J_backward(gJ, a)
+    p = F.profile_read()
+    F.profile(False)
+    F.check()
+    nclass = len(set(int(s.n_bands) for s in scs))
+    for k in ("setup", "walk", "reduce", "pp_src", "adj_reduce", "adj_pp_src", "adj_tree"):
+        assert p[k][1] > 0 and p[k][0] > 0.0, k
+    assert p["pp_src"][1] == nclass and p["reduce"][1] == nclass
+    assert p["near"][0] >= p["pp_src"][0] and p["adj_near"][0] >= p["adj_pp_src"][0]
     F.close()
 
 
