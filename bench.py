@@ -49,20 +49,26 @@ def note(msg):
 #   far source at a receiver        37 + 6B   per (receiver, source entry)
 #   cell-ray intersection           20 + 2B   per (bucket, absorber entry)
 #   p-p column along a ray          24        per (receiver, ray, p-p element)
-#   p-p source path                 35        per (receiver, p-p source, p-p element)
+#   p-p source path                 29 + 2B   per hit: a (receiver, source,
+#                                   element) triple whose element absorbs on
+#                                   the path (its exact test 25, the column 4,
+#                                   a multiply-add per band); the kernel finds
+#                                   the hits by conservative culling, so
+#                                   triples that cannot be hits are not work
 # and for the adjoint kernels the forward arithmetic again plus the
 # derivatives:
 #   far source                      61 + 19B  (kernel slope 14, dK/dr, dK/dh 6,
 #                                              position 4, 13 per band)
 #   cell-ray intersection           40 + 8B   (two sweeps + absorption adjoint)
 #   p-p column                      24 + 8    (column slope in h, kappa term)
-#   p-p source path                 35 + 8
+#   p-p source path                 35 + 5B   per hit (column slope in h,
+#                                              kappa and h adjoints per band)
 def kernel_flops(c: dict, B: int, nray: int) -> dict:
     return {
-        "k_pp_src": c["near_src_triples"] * 35.0,
+        "k_pp_src": c["near_src_hits"] * (29.0 + 2 * B),
         "k_pp_rays": nray * c["near_pairs"] * 24.0,
         "k_far": c["src_pairs"] * (37 + 6 * B) + c["absorber_entries"] * (20 + 2 * B),
-        "k_pp_src_bwd": c["near_src_triples"] * 43.0,
+        "k_pp_src_bwd": c["near_src_hits"] * (35.0 + 5 * B),
         "k_pp_rays_bwd": nray * c["near_pairs"] * 32.0,
         "k_far_bwd": c["src_pairs"] * (61 + 19 * B) + c["absorber_entries"] * (40 + 8 * B),
     }

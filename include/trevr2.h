@@ -121,6 +121,10 @@ typedef struct trevr_counters {
                                (p-p set size): the p-p source paths tested     */
   int64_t max_cut;          /* longest cut list of a bucket (entries)            */
   int64_t max_stack;        /* deepest traversal stack (entries)                 */
+  int64_t near_src_hits;    /* (receiver, luminous p-p element, p-p element)
+                               triples whose element absorbs on the path:
+                               nearer the source than the receiver and within
+                               its size of the segment                        */
 } trevr_counters;
 
 typedef struct trevr_tree trevr_tree; /* opaque host handle */

@@ -34,7 +34,8 @@ ABSORPTION_AVG = 8
 DIRECTED = 32
 
 COUNTER_NAMES = ("buckets", "cells", "absorber_entries", "source_entries", "segments",
-                 "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples")
+                 "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples",
+                 "near_src_hits")
 
 
 def build() -> str:

@@ -90,7 +90,7 @@ struct Params {
 enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u, F_AVG = 8u, F_DIRECTED = 32u };
 
 enum { C_BUCKETS = 0, C_CELLS, C_ABS, C_SRC, C_SEG, C_NEAR_PAIRS, C_MAX_NEAR, C_NODES,
-       C_SRC_PAIRS, C_NS_TRIPLES, C_N };
+       C_SRC_PAIRS, C_NS_TRIPLES, C_NS_HITS, C_N };
 
 // ------------------------------------------------- element physics (2.1-2.4)
 // Finite-element intensity kernel, Section 2.2, eq. (intint): the volume
@@ -825,7 +825,7 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
     }
   }
 
-  int64_t nact = 0;
+  int64_t nact = 0, nhits = 0;
   std::vector<T> tpp(K * B);
   for (int64_t i = g.first; i < g.first + g.count; ++i) {
     if (!act_sorted[i]) continue;
@@ -891,6 +891,7 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
         double f[3] = {w[0] - u * e[0], w[1] - u * e[1], w[2] - u * e[2]};
         double bb = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
         if (!(bb < val(P.h[l]))) continue;
+        ++nhits;
         T sig = column_sigma(bb, t.m[l], P.h[l]);
         for (int b = 0; b < B; ++b) tau[b] += P.kappa[b * t.n + l] * sig;
       }
@@ -920,6 +921,7 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
   int64_t nlum = 0;
   for (int64_t j : nearv) nlum += (val(P.Lbol[j]) > 0.0) ? 1 : 0;
   cnt[C_NS_TRIPLES] += nact * nlum * (int64_t)nearv.size();
+  cnt[C_NS_HITS] += nhits;
   cnt[C_MAX_NEAR] = std::max<int64_t>(cnt[C_MAX_NEAR], (int64_t)nearv.size());
   if (info) {
     info->rpp = val(r);
@@ -1068,9 +1070,10 @@ void ora_nodes(void* h, int64_t* ints, double* box, double* cen, double* Lb, dou
   if (alpha) std::memcpy(alpha, H->mo.alpha.data(), sizeof(double) * nn * D * B);
 }
 // J [B][n] in input order (rows of inactive particles untouched).
-// counters[10]: buckets, cells, absorber entries, source entries, segments,
+// counters[11]: buckets, cells, absorber entries, source entries, segments,
 // near pairs, largest near set, nodes, receiver-source pairs, p-p source
-// path tests.  bucket_info (optional) [nb][6]:
+// path tests, p-p source path hits (element within its size of the segment
+// and nearer the source than the receiver).  bucket_info (optional) [nb][6]:
 // leaf node, r_pp, near count, cells, absorber entries, source entries.
 int64_t ora_compute_J(void* h, const uint8_t* active, const double* bg, double* J,
                       int64_t* counters, double* bucket_info, int nthreads) {

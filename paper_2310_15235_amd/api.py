@@ -57,7 +57,7 @@ class Counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("buckets", "cells", "absorber_entries", "source_entries", "segments",
                  "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples", "max_cut",
-                 "max_stack")]
+                 "max_stack", "near_src_hits")]
 
 
 _lib = None

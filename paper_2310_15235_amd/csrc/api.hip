@@ -388,6 +388,7 @@ trevr_status trevr_get_counters(trevr_tree* t, trevr_counters* o) {
   o->near_src_triples = (int64_t)c[CNT_NS_TRIPLES];
   o->max_cut = (int64_t)c[CNT_MAX_CUT];
   o->max_stack = (int64_t)c[CNT_MAX_STACK];
+  o->near_src_hits = (int64_t)c[CNT_NS_HITS];
   return TREVR_OK;
 }
 

@@ -528,14 +528,16 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
 }
 
 // Adds (none when dst is null) and clears the p-p source kernel's counter
-// sums: near pairs, (receiver, source, element) triples and the largest set.
+// sums: near pairs, (receiver, source, element) triples, the largest set and
+// the triples whose element absorbs on the path.
 __device__ inline void pp_counters_flush(unsigned long long* dst, unsigned long long* s) {
   if (dst) {
     if (s[0]) atomicAdd(&dst[CNT_NEAR_PAIRS], s[0]);
     if (s[1]) atomicAdd(&dst[CNT_NS_TRIPLES], s[1]);
     if (s[2]) atomic_max_u64(&dst[CNT_MAX_NEAR], s[2]);
+    if (s[3]) atomicAdd(&dst[CNT_NS_HITS], s[3]);
   }
-  s[0] = s[1] = s[2] = 0ull;
+  s[0] = s[1] = s[2] = s[3] = 0ull;
 }
 
 // For each receiver i and luminous p-p element j (i itself included, at
@@ -575,12 +577,15 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   __shared__ uint8_t nlist[kNT / 64][64];
   // the workgroup's sums of the per-bucket counters (thread 0), added to a
   // scene's counters when it turns to another scene and after its last bucket
-  __shared__ unsigned long long csum[3];   // near pairs, triples, largest set
+  __shared__ unsigned long long csum[4];   // near pairs, triples, largest set, hits
   __shared__ unsigned long long* cdst;
+  __shared__ unsigned long long s_hits;    // this bucket's hits so far
   if (threadIdx.x == 0) {
     cdst = nullptr;
-    csum[0] = csum[1] = csum[2] = 0ull;
+    csum[0] = csum[1] = csum[2] = csum[3] = 0ull;
+    s_hits = 0ull;
   }
+  uint32_t hits = 0;   // this thread's exact-test passes in the current bucket
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -711,6 +716,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
               if ((f0 * f0 + f1 * f1 + f2 * f2 < pd_r2[q]) && b2 < vh2 && vl != rq.slot &&
                   vl != pd_j[q]) {
+                ++hits;
                 const float bb = sqrtf((float)b2);
                 const float sg = vsig * (1.0f - bb * viv);
 #pragma unroll
@@ -808,6 +814,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
                 const uint32_t us = S.slot[u];
                 if ((f0 * f0 + f1 * f1 + f2 * f2 < pd_r2[ts]) && b2 < S.h2[u] &&
                     us != rq.slot && us != pd_j[ts]) {
+                  ++hits;
                   const float bb = sqrtf((float)b2);
                   const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
 #pragma unroll
@@ -835,6 +842,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
             const uint32_t us = S.slot[u];
             if ((f0 * f0 + f1 * f1 + f2 * f2 < rij2) && b2 < S.h2[u] && us != si && us != j) {
+              ++hits;
               const float bb = sqrtf((float)b2);
               const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
 #pragma unroll
@@ -857,6 +865,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     }
     // receiver-wise sums in thread order (deterministic); red shares its LDS
     // with the last pass's tile or queues
+    if (hits) atomicAdd(&s_hits, (unsigned long long)hits);
+    hits = 0;
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < NB; ++b) red[t][b] = acc[b];
@@ -876,7 +886,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     csum[0] += (unsigned long long)nact * nnear;
     csum[1] += (unsigned long long)nact * nl * nnear;
     csum[2] = max(csum[2], (unsigned long long)nnear);
+    csum[3] += s_hits;
   }
+  if (t == 0) s_hits = 0ull;
   }
   if (Jall && threadIdx.x == 0) pp_counters_flush(cdst, csum);
 }

@@ -588,6 +588,7 @@ trevr_status trevr_forest_get_counters(trevr_forest* f, int32_t scene, trevr_cou
     o->near_src_triples += c.near_src_triples;
     o->max_cut = std::max(o->max_cut, c.max_cut);
     o->max_stack = std::max(o->max_stack, c.max_stack);
+    o->near_src_hits += c.near_src_hits;
   }
   return TREVR_OK;
 }

@@ -318,3 +318,50 @@ def test_forest_launch_configurations_agree_and_autotune_picks_one():
     J = F.compute_J(a).cpu().numpy()
     assert np.max(_rel(J, ref[0])) <= SAME_TOL
     F.close()
+
+
+def test_full_batched_workload_against_the_oracle_sampled():
+    """The 64-scene workload, all active, batched on the GPU, against the
+    oracle on 96 random receivers of every scene (J of a receiver does not
+    depend on which others are active), and, per scene, the batched adjoint
+    of weights on those receivers against the oracle's forward-mode
+    derivative along random L, kappa and rho directions."""
+    api = _api()
+    import torch
+    scs = scenes.batched_scenes(64)
+    F = api.Forest(scs)
+    a = F.flat_active([None] * F.S)
+    J = F.split(F.compute_J(a))
+    F.check()
+    rng = np.random.default_rng(123)
+    gparts, samples = [], []
+    for s, sc in enumerate(scs):
+        sub = np.zeros(sc.n, np.uint8)
+        sub[rng.choice(sc.n, size=min(96, sc.n), replace=False)] = 1
+        samples.append(sub)
+        g = rng.normal(size=(sc.n_bands, sc.n))
+        g[:, ~sub.astype(bool)] = 0.0
+        gparts.append(g)
+    gJ = torch.as_tensor(np.concatenate([g.ravel() for g in gparts]), device="cuda")
+    gL, gk, gr = (F.split(x) for x in F.compute_J_backward(gJ, a))
+    F.check()
+    worst = 0.0
+    for s, sc in enumerate(scs):
+        m = samples[s].astype(bool)
+        Jo, _ = oracle.OracleTree(sc).compute_J(samples[s])
+        Jg = J[s].cpu().numpy()
+        e = float(np.max(_rel(Jg[:, m], Jo[:, m])))
+        worst = max(worst, e)
+        assert e < J_TOL, (sc.name, e)
+        tL = rng.normal(size=(sc.n_bands, sc.n)) * sc.lum
+        tk = rng.normal(size=(sc.n_bands, sc.n)) * sc.kappa
+        tr = rng.normal(size=sc.n) * sc.rho
+        _, dJ, _ = oracle.jvp(sc, tL=tL, tkappa=tk, trho=tr, active=samples[s])
+        lhs = float(np.sum(gparts[s] * dJ))
+        terms = [gL[s].cpu().numpy() * tL, gk[s].cpu().numpy() * tk, gr[s].cpu().numpy() * tr]
+        rhs = float(sum(np.sum(x) for x in terms))
+        scale = max(float(np.sum(np.abs(gparts[s] * dJ))),
+                    float(sum(np.sum(np.abs(x)) for x in terms)))
+        assert abs(lhs - rhs) <= 1e-4 * scale, (sc.name, lhs, rhs, scale)
+    print(f"[forest] 64 scenes x 96 receivers: max rel err {worst:.2e}")
+    F.close()

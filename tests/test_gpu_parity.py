@@ -78,7 +78,8 @@ def compare_J(sc, active=None, tol=J_TOL, check_counts=True, tune=()):
     assert np.all(Jg[:, ~a] == 0.0)
     if check_counts:
         for k in ("buckets", "cells", "absorber_entries", "source_entries", "segments",
-                  "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples"):
+                  "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples",
+                  "near_src_hits"):
             assert cg[k] == co[k], (k, cg[k], co[k])
     assert e.max() < tol, (e.max(), np.unravel_index(np.argmax(e), e.shape))
     return e, cg

@@ -40,7 +40,11 @@ def test_jvp_matches_central_differences(which):
     J, dJ, c0 = oracle.jvp(sc, **kw)
     fd6, cnts6 = _fd(sc, which, v, 1e-6)
     fd5, cnts5 = _fd(sc, which, v, 1e-5)
-    assert cnts6[0] == cnts6[1] == cnts5[0] == cnts5[1] == c0, "a counted decision moved"
+    # structural decisions stay put; the hit count (elements within their size
+    # of a p-p path) follows h continuously and may move at a kink
+    strip = lambda c: {k: v for k, v in c.items() if k != "near_src_hits"}
+    assert strip(cnts6[0]) == strip(cnts6[1]) == strip(cnts5[0]) == strip(cnts5[1]) == strip(c0), \
+        "a counted decision moved"
     scale = np.abs(dJ).max(axis=1, keepdims=True)
     den = np.maximum(np.abs(dJ), 1e-3 * scale)
     # A column profile has a kink where an impact parameter meets the element
