@@ -32,6 +32,7 @@ NEAR_FIELD = 2
 BACKGROUND = 4
 ABSORPTION_AVG = 8
 DIRECTED = 32
+COMPLEX_SOURCE = 64
 
 COUNTER_NAMES = ("buckets", "cells", "absorber_entries", "source_entries", "segments",
                  "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples",
@@ -80,6 +81,7 @@ def lib():
         L.ora_dirs.argtypes = [vp, vp, vp]
         L.ora_perm.argtypes = [vp, vp, vp]
         L.ora_nodes.argtypes = [vp] * 8
+        L.ora_complex.argtypes = [vp, vp, vp, vp]
         L.ora_compute_J.restype = i64
         L.ora_compute_J.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int]
         L.ora_jvp.restype = i64
@@ -111,6 +113,8 @@ def scene_flags(scene) -> int:
         f |= ABSORPTION_AVG
     if getattr(scene, "directed", None) is not None:
         f |= DIRECTED
+    if getattr(scene, "complex_source", False):
+        f |= COMPLEX_SOURCE
     return f
 
 
@@ -236,6 +240,17 @@ class OracleTree:
         return dict(first=ints[:, 0], count=ints[:, 1], lown=ints[:, 2], split=ints[:, 3],
                     child0=ints[:, 4], child1=ints[:, 5], next=ints[:, 6], lo=box[:, :3],
                     hi=box[:, 3:], cen=cen, Lb=Lb, Lbol=Lbol, kmass=kmass, alpha=alpha)
+
+    def complex_tables(self):
+        """Complex source model tables: (cd [nodes, nray], ca [nodes, nray, B],
+        antipode [nray])."""
+        nn, B = self.num_nodes, self.B
+        K = 12 * self.scene.nside ** 2
+        cd = np.zeros((nn, K))
+        ca = np.zeros((nn, K, B))
+        ap = np.zeros(K, dtype=np.int32)
+        lib().ora_complex(self.h, _ptr(cd), _ptr(ca), _ptr(ap))
+        return cd, ca, ap
 
     def compute_J(self, active=None, nthreads: int = 0, bucket_info: bool = False,
                   J_init=None):

@@ -87,7 +87,8 @@ struct Params {
   double box[4];
   double target[3];
 };
-enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u, F_AVG = 8u, F_DIRECTED = 32u };
+enum : uint32_t { F_THICK = 1u, F_NEAR = 2u, F_BG = 4u, F_AVG = 8u, F_DIRECTED = 32u,
+                  F_CPLX = 64u };
 
 enum { C_BUCKETS = 0, C_CELLS, C_ABS, C_SRC, C_SEG, C_NEAR_PAIRS, C_MAX_NEAR, C_NODES,
        C_SRC_PAIRS, C_NS_TRIPLES, C_NS_HITS, C_N };
@@ -301,6 +302,7 @@ struct Tree {
   Healpix hp;
   std::vector<int> dir_of_ray;  // stored direction index of each ray
   std::vector<int> ray_of_dir;  // representative ray of each stored direction
+  std::vector<int> antipode;    // ray of the opposite direction
   explicit Tree(int nside) : hp(nside) {}
 };
 
@@ -430,6 +432,11 @@ Tree* build_geometry(const Params& p, int64_t n, const double* xs, const double*
     }
   }
   t->ndir = (int)t->ray_of_dir.size();
+  t->antipode.resize(t->nray);
+  for (int k = 0; k < t->nray; ++k) {
+    const double* v = &t->hp.v[3 * k];
+    t->antipode[k] = t->hp.pixel(-v[0], -v[1], -v[2]);
+  }
   return t;
 }
 
@@ -448,7 +455,91 @@ template <class T> struct PartT {
 template <class T> struct Mom {
   std::vector<T> Lb, Lbol, SL, cen, alpha;  // Lb [node][B]; SL, cen [node][3]; alpha [node][ndir][B]
   std::vector<double> kmass;                // sum over particles and bands of kappa*m (value)
+  // complex source model: per node and emission direction k (all N_ray), the
+  // length of the ray from the luminosity centre to the edge of the node's
+  // box and the absorption coefficient along it (per band)
+  std::vector<T> cd, ca;                    // cd [node][nray]; ca [node][nray][B]
 };
+
+// Distance from c (inside the box) along n to the box's boundary.
+template <class T> T exit_distance(const double lo[3], const double hi[3], const T c[3],
+                                   const double n[3]) {
+  T t = T(std::numeric_limits<double>::infinity());
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] > 0.0) {
+      T u = (hi[a] - c[a]) / n[a];
+      if (val(u) < val(t)) t = u;
+    } else if (n[a] < 0.0) {
+      T u = (lo[a] - c[a]) / n[a];
+      if (val(u) < val(t)) t = u;
+    }
+  }
+  return vmax(t, T(0.0));
+}
+
+// Complex source model (Section 2.7, eq. srccomb, Fig. sourcecombine), built
+// bottom-up after the transmission tables.  For node n and direction k the
+// stored ray runs from the luminosity centre c_n along n_k to the edge of
+// n's box (length d_n).  A bucket's ray sees the bucket absorption.  For a
+// merged node the rays of the two children are brought to the same
+// projected stopping point (the plane through c_n + d_n n_k normal to n_k):
+// child i's ray needs length D_i = d_n + (c_n - c_i).n_k; its own segment
+// covers up to d_i (clipped when D_i < d_i, none when D_i <= 0) and beyond it
+// the ray crosses the rest of n with n's transmission-averaged absorption in
+// direction k.  The optical depths combine so that the attenuated
+// luminosities add: L_n e^{-tau_n} = L_1 e^{-tau_1} + L_2 e^{-tau_2}, and the
+// node stores alpha_n = tau_n / d_n (zero when d_n = 0 or L_n = 0).
+template <class T>
+void complex_sources(const Tree& t, Mom<T>& mo) {
+  const int64_t nn = (int64_t)t.node.size();
+  const int B = t.B, K = t.nray, D = t.ndir;
+  mo.cd.assign(nn * K, T(0.0));
+  mo.ca.assign(nn * K * B, T(0.0));
+  for (int64_t nd = nn - 1; nd >= 0; --nd) {
+    const NodeG& g = t.node[nd];
+    const T c[3] = {mo.cen[nd * 3 + 0], mo.cen[nd * 3 + 1], mo.cen[nd * 3 + 2]};
+    for (int k = 0; k < K; ++k) {
+      const double* n = &t.hp.v[3 * k];
+      const T dn = exit_distance(g.lo, g.hi, c, n);
+      mo.cd[nd * K + k] = dn;
+      for (int b = 0; b < B; ++b) {
+        T al = T(0.0);
+        if (g.leaf) {
+          al = mo.alpha[(nd * D + 0) * B + b];   // the bucket absorption, any direction
+        } else if (val(mo.Lb[nd * B + b]) > 0.0 && val(dn) > 0.0) {
+          const T aext = mo.alpha[(nd * D + t.dir_of_ray[k]) * B + b];
+          T tau[2], w[2];
+          const int64_t ch[2] = {g.c0, g.c1};
+          for (int q = 0; q < 2; ++q) {
+            const int64_t ci = ch[q];
+            w[q] = mo.Lb[ci * B + b] / mo.Lb[nd * B + b];
+            T Di = dn;
+            for (int a = 0; a < 3; ++a) Di += (c[a] - mo.cen[ci * 3 + a]) * n[a];
+            const T di = mo.cd[ci * K + k];
+            const T ai = mo.ca[(ci * K + k) * B + b];
+            if (!(val(Di) > 0.0)) {
+              tau[q] = T(0.0);
+            } else if (val(Di) <= val(di)) {
+              tau[q] = ai * Di;
+            } else {
+              tau[q] = ai * di + aext * (Di - di);
+            }
+          }
+          // -ln(w1 e^{-tau1} + w2 e^{-tau2}) about the smaller depth among
+          // the luminous children
+          int first = -1;
+          for (int q = 0; q < 2; ++q)
+            if (val(w[q]) > 0.0 && (first < 0 || val(tau[q]) < val(tau[first]))) first = q;
+          T sum = T(0.0);
+          for (int q = 0; q < 2; ++q)
+            if (val(w[q]) > 0.0) sum += w[q] * exp(-(tau[q] - tau[first]));
+          al = (tau[first] - log(sum)) / dn;
+        }
+        mo.ca[(nd * K + k) * B + b] = al;
+      }
+    }
+  }
+}
 
 template <class T>
 void compute_moments(const Tree& t, const PartT<T>& P, Mom<T>& mo) {
@@ -631,7 +722,13 @@ inline bool slab(const double lo[3], const double hi[3], const double c[3], cons
 
 // -------------------------------------------------- per-bucket computation --
 template <class T> struct AbsE { T t0; double t1; int64_t node; };
-template <class T> struct SrcE { T s; T p[3]; std::vector<T> L; };
+template <class T> struct SrcE {
+  T s;                 // projected distance on the ray
+  T p[3];              // position
+  std::vector<T> L;    // luminosity per band
+  T d;                 // complex source model: length of the source's own ray
+  std::vector<T> tin;  // complex source model: optical depth along it, per band
+};
 
 struct BucketInfo { double rpp; int64_t nnear, cells, nabs, nsrc; };
 
@@ -680,8 +777,11 @@ template <class T> struct Walker {
   }
 
   // A source at p is assigned to the ray whose pixel contains the direction
-  // from the bucket centre, at the distance projected on that ray.
-  void add_source(const T p[3], const T* L) {
+  // from the bucket centre, at the distance projected on that ray.  With
+  // the complex source model a merged cell source (node >= 0) carries the
+  // length and optical depth of its own ray toward the receiver (emission
+  // direction -n_k, the antipodal pixel).
+  void add_source(const T p[3], const T* L, int64_t node = -1) {
     T v[3];
     for (int a = 0; a < 3; ++a) v[a] = p[a] - c[a];
     int k = 0;
@@ -695,6 +795,13 @@ template <class T> struct Walker {
     e.s = s;
     for (int a = 0; a < 3; ++a) e.p[a] = p[a];
     e.L.assign(L, L + t.B);
+    e.d = T(0.0);
+    e.tin.assign(t.B, T(0.0));
+    if (node >= 0 && (t.p.flags & F_CPLX)) {
+      const int ka = t.antipode[k];
+      e.d = mo.cd[node * t.nray + ka];
+      for (int b = 0; b < t.B; ++b) e.tin[b] = mo.ca[(node * t.nray + ka) * t.B + b] * e.d;
+    }
     src[k].push_back(e);
   }
 
@@ -726,7 +833,7 @@ template <class T> struct Walker {
         add_source(p, L.data());
       }
     } else if (val(mo.Lbol[nd]) > 0.0) {
-      add_source(&mo.cen[nd * 3], &mo.Lb[nd * t.B]);
+      add_source(&mo.cen[nd * 3], &mo.Lb[nd * t.B], nd);
     }
   }
 
@@ -810,7 +917,10 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
     tau_src[k].resize(W.src[k].size());
     for (size_t e = 0; e < W.src[k].size(); ++e) {
       tau_src[k][e].resize(B);
-      for (int b = 0; b < B; ++b) tau_src[k][e][b] = W.tau_to(k, W.src[k][e].s, b);
+      // the cell absorption up to the source (complex source model: up to
+      // the edge of the source's cell, the projected end of its own ray)
+      const SrcE<T>& S = W.src[k][e];
+      for (int b = 0; b < B; ++b) tau_src[k][e][b] = W.tau_to(k, S.s - S.d, b);
     }
   }
   std::vector<T> tau_bg;
@@ -866,7 +976,7 @@ void eval_bucket(const Tree& t, const PartT<T>& P, const Mom<T>& mo, int64_t lea
         for (int b = 0; b < B; ++b) {
           T tc = tau_src[k][e][b];
           T ex = (val(tc) > 0.0) ? tc * rr / S.s : T(0.0);
-          Jb[b] += S.L[b] * Kv * exp(-tpp[k * B + b] - ex);
+          Jb[b] += S.L[b] * Kv * exp(-tpp[k * B + b] - ex - S.tin[b]);
         }
       }
     }
@@ -1025,6 +1135,7 @@ void* ora_build(const Params* p, int64_t n, const double* x, const double* y, co
   H->t = build_geometry(*p, n, x, y, z, m);
   particle_props<double>(*H->t, rho, kappa, lum, nullptr, nullptr, nullptr, H->P);
   compute_moments<double>(*H->t, H->P, H->mo);
+  if (p->flags & F_CPLX) complex_sources<double>(*H->t, H->mo);
   return H;
 }
 void ora_free(void* h) {
@@ -1069,6 +1180,18 @@ void ora_nodes(void* h, int64_t* ints, double* box, double* cen, double* Lb, dou
   }
   if (alpha) std::memcpy(alpha, H->mo.alpha.data(), sizeof(double) * nn * D * B);
 }
+// Complex source model tables (nodes in preorder): cd [node][nray] lengths,
+// ca [node][nray][B] absorption coefficients; antipode [nray].  Zeros when
+// the model is off.
+void ora_complex(void* h, double* cd, double* ca, int32_t* antipode) {
+  Handle* H = (Handle*)h;
+  Tree* t = H->t;
+  const size_t nn = t->node.size(), K = (size_t)t->nray, B = (size_t)t->B;
+  for (size_t i = 0; i < nn * K; ++i) cd[i] = H->mo.cd.empty() ? 0.0 : H->mo.cd[i];
+  for (size_t i = 0; i < nn * K * B; ++i) ca[i] = H->mo.ca.empty() ? 0.0 : H->mo.ca[i];
+  for (size_t k = 0; k < K; ++k) antipode[k] = t->antipode[k];
+}
+
 // J [B][n] in input order (rows of inactive particles untouched).
 // counters[11]: buckets, cells, absorber entries, source entries, segments,
 // near pairs, largest near set, nodes, receiver-source pairs, p-p source
@@ -1092,6 +1215,7 @@ int64_t ora_jvp(const Params* p, int64_t n, const double* x, const double* y, co
   particle_props<Dual>(*t, rho, kappa, lum, trho, tk, tL, P);
   Mom<Dual> mo;
   compute_moments<Dual>(*t, P, mo);
+  if (p->flags & F_CPLX) complex_sources<Dual>(*t, mo);
   std::vector<Dual> Jd((size_t)t->B * n);
   for (size_t i = 0; i < Jd.size(); ++i) Jd[i] = Dual(J[i], dJ[i]);
   run_all<Dual>(*t, P, mo, active, bg, Jd.data(), counters, nullptr, nthreads);

@@ -36,6 +36,7 @@ class Scene:
     background: bool = False
     absorption_avg: bool = False      # linear absorption averaging instead of transmission
     directed: Optional[Tuple[float, float, float]] = None   # target of directed rays
+    complex_source: bool = False      # complex source model (per-direction source absorption)
     bg: Optional[np.ndarray] = None   # float32 [B] isotropic background intensity
     rpp_min: float = 0.0
     box: Optional[Tuple[float, float, float, float]] = (0.0, 0.0, 0.0, 1.0)

@@ -332,3 +332,56 @@ def test_directed_ray_lattice_closed_form(nside):
         assert np.max(np.abs(J[:, i] - ref) / ref) < 1e-12, (i, J[:, i], ref)
         checked += 1
     assert checked > 100
+
+
+# ------------------------------------------------- complex source model
+def _exit(lo, hi, p, n):
+    t = np.inf
+    for a in range(3):
+        if n[a] > 0:
+            t = min(t, (hi[a] - p[a]) / n[a])
+        elif n[a] < 0:
+            t = min(t, (lo[a] - p[a]) / n[a])
+    return max(t, 0.0)
+
+
+@pytest.mark.parametrize("nside", [1, 2])
+def test_complex_source_single_source_uniform_medium(nside):
+    """Section 2.7 with one source in a uniform gap-free medium: every cell
+    holding the source has its luminosity centre at the source, the child
+    rays are extended (never clipped) through a cell of the same absorption,
+    so the stored optical depth of the source's own ray in direction k is
+    kappa rho times the distance from the source to the cell's edge along
+    n_k; buckets store their absorption in every direction."""
+    sc = _lattice(kappa=(4.0, 1.0), nside=nside, theta=0.75, complex_source=True)
+    j = (17 * 32 + 9) * 32 + 21
+    sc.lum[:, j] = [1.0, 3.0]
+    T = oracle.OracleTree(sc)
+    nd = T.nodes(with_alpha=False)
+    cd, ca, ap = T.complex_tables()
+    hp = oracle.healpix_centres(nside)
+    pos = sc.positions().astype(np.float64)
+    perm, _ = T.perm()
+    slot = int(np.flatnonzero(perm == j)[0])
+    lum_nodes = np.flatnonzero((nd["first"] <= slot) & (slot < nd["first"] + nd["count"]))
+    assert len(lum_nodes) > 5
+    for n_ in lum_nodes:
+        for k in range(hp.shape[0]):
+            d = _exit(nd["lo"][n_], nd["hi"][n_], pos[j], hp[k])
+            assert cd[n_, k] == pytest.approx(d, rel=1e-12, abs=1e-15)
+            np.testing.assert_allclose(ca[n_, k] * cd[n_, k], np.array([4.0, 1.0]) * d,
+                                       rtol=1e-12, atol=1e-15)
+    leaves = np.flatnonzero(nd["split"] < 0)
+    assert np.allclose(ca[leaves], np.array([4.0, 1.0])[None, None, :], rtol=1e-14)
+    # antipodes: opposite directions
+    np.testing.assert_allclose(hp[ap], -hp, atol=1e-12)
+
+
+def test_complex_source_transparent_equals_standard():
+    """Without absorption the complex source model changes nothing: the
+    sources' own rays and the shortened cell trace carry no optical depth."""
+    sc = scenes.lognormal_scene(n=3000, seed=86, grid=16, bands=(0.0, 0.0), nside=2)
+    J0, c0 = oracle.compute_J(sc)
+    J1, c1 = oracle.compute_J(sc.with_(complex_source=True))
+    assert c0 == c1
+    assert np.max(np.abs(J1 - J0) / J0) < 1e-13
