@@ -77,6 +77,20 @@ enum {
                             background exit use the new direction; its
                             transmission averages stay those of its HEALPix
                             direction.  Other rays are unchanged.             */
+  TREVR_COMPLEX_SRC = 64u, /* complex source model (Section 2.7, eq. srccomb):
+                            the build stores for every node and each of the
+                            N_ray directions the length of the ray from its
+                            luminosity centre to its box edge and the
+                            absorption along it (buckets: their absorption;
+                            merged nodes: the children's rays brought to the
+                            same projected end, extended through the node
+                            with its transmission average or clipped, and
+                            combined so that attenuated luminosities add).  A
+                            merged source is then attenuated along its own ray
+                            toward the receiver and the cell trace stops at
+                            that ray's projected end.  Forward only: the
+                            adjoint calls return TREVR_E_INVALID.  Tree
+                            workspace grows by 8 (1 + B) N_ray bytes per node. */
   TREVR_KEEP_DEPTHS = 16u /* memory for time in the adjoint: the forward keeps
                             each far source's cell optical depth (and each
                             ray's exit depth with TREVR_BACKGROUND) in the

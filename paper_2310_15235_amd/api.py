@@ -18,7 +18,8 @@ SO_PATH = os.path.join(HERE, "libtrevr2.so")
 
 # status codes and flags (include/trevr2.h)
 OK, E_INVALID, E_CAPACITY, E_HIP, E_STATE, E_DATA = range(6)
-THICK_CORR, NEAR_FIELD, BACKGROUND, ABSORPTION_AVG, KEEP_DEPTHS, DIRECTED = 1, 2, 4, 8, 16, 32
+THICK_CORR, NEAR_FIELD, BACKGROUND, ABSORPTION_AVG, KEEP_DEPTHS, DIRECTED, COMPLEX_SOURCE = \
+    1, 2, 4, 8, 16, 32, 64
 
 EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_compute_J_backward", "trevr_tree_tune",
@@ -364,7 +365,8 @@ def scene_flags(scene) -> int:
     return (THICK_CORR if scene.thick_corr else 0) | (NEAR_FIELD if scene.near_field else 0) | \
         (BACKGROUND if scene.background else 0) | \
         (ABSORPTION_AVG if getattr(scene, "absorption_avg", False) else 0) | \
-        (DIRECTED if getattr(scene, "directed", None) is not None else 0)
+        (DIRECTED if getattr(scene, "directed", None) is not None else 0) | \
+        (COMPLEX_SOURCE if getattr(scene, "complex_source", False) else 0)
 
 
 class Forest:

@@ -42,7 +42,8 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
   if (p->n_bands < 1 || p->n_bands > kMaxBands)
     return set_error(TREVR_E_INVALID, "n_bands must be in [1, 16]");
   if (p->flags & ~(uint32_t)(TREVR_THICK_CORR | TREVR_NEAR_FIELD | TREVR_BACKGROUND |
-                            TREVR_ABSORPTION_AVG | TREVR_DIRECTED | TREVR_KEEP_DEPTHS))
+                            TREVR_ABSORPTION_AVG | TREVR_DIRECTED | TREVR_KEEP_DEPTHS |
+                            TREVR_COMPLEX_SRC))
     return set_error(TREVR_E_INVALID, "unknown flag bits");
   if (!(p->theta >= 0.0) || !std::isfinite(p->theta))
     return set_error(TREVR_E_INVALID, "theta must be finite and >= 0");
@@ -224,6 +225,7 @@ trevr_status trevr_build_tree(const trevr_params* p, int64_t n, const float* x, 
   D.h = b.h; D.lbol = b.lbol; D.kappa = b.kappa; D.lum = b.lum; D.perm = b.perm;
   D.nk = b.nk; D.nlink = b.nlink; D.next = b.next; D.cen = b.cen; D.Lb = b.Lb;
   D.alpha = b.alpha32; D.ray_n = b.ray_n; D.ray_class = b.ray_class;
+  D.ray_anti = b.ray_anti; D.csrc_d = b.csrc_d; D.csrc_a = b.csrc_a;
   D.err = b.err; D.counters = b.counters;
   D.b_pre = b.b_pre; D.b_lown = b.b_lown; D.b_split = b.b_split;
   D.alpha64 = b.alpha64; D.geom = b.geom; D.levels = b.levels;
@@ -312,6 +314,8 @@ trevr_status trevr_compute_J_backward(trevr_tree* t, const uint8_t* active, cons
   if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
   if (!gJ || !gL || !gkappa || !grho || !scratch)
     return set_error(TREVR_E_INVALID, "NULL gradient or scratch pointer");
+  if (t->p.flags & TREVR_COMPLEX_SRC)
+    return set_error(TREVR_E_INVALID, "the adjoint does not cover the complex source model");
   if ((t->p.flags & TREVR_BACKGROUND) && !bg)
     return set_error(TREVR_E_INVALID, "TREVR_BACKGROUND needs bg");
   t->stream = (hipStream_t)stream;

@@ -1083,8 +1083,13 @@ __global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Ite
             const float dz = W.rel[q][2] - ri.rel[2];
             const float rr = sqrtf(dx * dx + dy * dy + dz * dz);
             const float Kv = fshape(rr * ri.inv_rh) * ri.kfac;
-            const float ratio = rr * __builtin_amdgcn_rcpf(W.s[q]);
             const int ray = W.ray[q];
+            // true over projected distance of the source (W.s ends the cell
+            // trace, shorter than the projection with the complex source model)
+            const float sproj = T.csrc_d ? W.rel[q][0] * G.nf[ray][0] + W.rel[q][1] * G.nf[ray][1] +
+                                               W.rel[q][2] * G.nf[ray][2]
+                                         : W.s[q];
+            const float ratio = rr * __builtin_amdgcn_rcpf(sproj);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
               const float tau = W.tau[q][b];

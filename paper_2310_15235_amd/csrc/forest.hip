@@ -44,6 +44,7 @@ struct trevr_forest {
   bool any_bg;
   std::vector<int64_t> level_work;     // widest scene's nodes x classes per depth
   int64_t class_leaves[trevr::kMaxBands];
+  bool any_complex;                    // a scene uses the complex source model
   // plan
   bool planned;
   bool stack_large;
@@ -435,6 +436,7 @@ trevr_status trevr_build_forest(const trevr_params* params, int32_t S, const int
   f->n_total = f->jn_total = f->nodes_total = f->nodesB_total = f->alpha_total = 0;
   f->leaves_total = f->max_nodes = f->max_n = 0;
   f->any_bg = false;
+  f->any_complex = false;
   for (int32_t s = 0; s < S && rc == TREVR_OK; ++s) {
     const int64_t n = offsets[s + 1] - offsets[s], e0 = offsets[s];
     rc = trevr_build_tree(&params[s], n, x + e0, y + e0, z + e0, m + e0, rho + e0, kappa + koff,
@@ -460,6 +462,7 @@ trevr_status trevr_build_forest(const trevr_params* params, int32_t S, const int
     f->max_nodes = std::max<int64_t>(f->max_nodes, T->num_nodes);
     f->max_n = std::max<int64_t>(f->max_n, n);
     if (T->p.flags & TREVR_BACKGROUND) f->any_bg = true;
+    if (T->p.flags & TREVR_COMPLEX_SRC) f->any_complex = true;
     for (size_t d = 0; d < T->levels.size(); ++d) {
       if (f->level_work.size() <= d) f->level_work.push_back(0);
       const int64_t w = (int64_t)(T->levels[d].second - T->levels[d].first) * T->nclass;
@@ -529,6 +532,8 @@ trevr_status trevr_compute_J_backward_batched(trevr_forest* f, const uint8_t* ac
   if (!forest_live(f)) return set_error(TREVR_E_STATE, "unknown or destroyed forest");
   if (!gJ || !gL || !gkappa || !grho)
     return set_error(TREVR_E_INVALID, "NULL gradient pointer");
+  if (f->any_complex)
+    return set_error(TREVR_E_INVALID, "the adjoint does not cover the complex source model");
   trevr_status rc = batched_checks(f, bg, scratch, scratch_bytes, f->scratch_run);
   if (rc != TREVR_OK) return rc;
   f->stream = (hipStream_t)stream;

@@ -574,7 +574,9 @@ __device__ inline void load_ray_group(const DevTree& T, const double c[3], int k
 }
 
 // Far sources of a ray group held in LDS, CAP at a time: position relative
-// to the bucket centre, distance s projected on the ray of their pixel,
+// to the bucket centre, distance s projected on the ray of their pixel (the
+// end of the cell trace: with the complex source model, s less the length
+// of the source's own ray),
 // per-band luminosity, accumulated cell optical depth (tau, plus suffix
 // adds in sfx unless the user keeps those elsewhere), the ray (in the group)
 // and the per-ray order by s.
@@ -643,6 +645,18 @@ __device__ inline uint32_t stage_window(const DevTree& T, const uint2* mycut, ui
         const bool dir = directed_ray(T, c, u) == (int)pix;
         const double* nn = dir ? u : &T.ray_n[3 * pix];
         sd = v0 * nn[0] + v1 * nn[1] + v2 * nn[2];
+      }
+      if (!part && T.csrc_d) {
+        // complex source model (Section 2.7): the merged source's own ray
+        // toward the receiver (emission direction -n_k, the antipodal
+        // pixel) attenuates its luminosity, and the cell trace stops at the
+        // projected end of that ray, the edge of the source's cell
+        const int64_t row = (int64_t)ent.x * T.nray + T.ray_anti[pix];
+        const double d = T.csrc_d[row];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          Lv[b] = (float)((double)Lv[b] * exp(-T.csrc_a[row * NB + b] * d));
+        sd -= d;
       }
       W.rel[slot][0] = (float)v0;
       W.rel[slot][1] = (float)v1;

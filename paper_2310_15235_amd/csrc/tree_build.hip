@@ -396,6 +396,79 @@ __global__ void k_alpha(TreeBufs tb, uint32_t lb, uint32_t le, int B, int nclass
   }
 }
 
+// Complex source model (Section 2.7, eq. srccomb, Fig. sourcecombine): the
+// nodes of one level, one thread per (node, direction k over all N_ray).
+// The ray from the node's luminosity centre c along n_k runs to the edge of
+// the node's box (length d).  A bucket's ray sees the bucket absorption.  A
+// merged node brings its children's rays to the same projected stopping
+// point, the plane through c + d n_k normal to n_k: child i needs length
+// D_i = d + (c - c_i).n_k, of which its own ray covers up to d_i (clipped
+// when shorter, nothing when D_i <= 0) and the rest crosses the node with
+// its transmission-averaged absorption in direction k; the optical depths
+// combine so that attenuated luminosities add, per band:
+//   L e^{-tau} = L_1 e^{-tau_1} + L_2 e^{-tau_2},
+// and the node keeps alpha = tau / d (zero when d = 0 or L = 0).  Runs after
+// k_alpha of the same level (it reads the node's transmission averages).
+__global__ void k_csrc(TreeBufs tb, uint32_t lb, uint32_t le, int B, int nclass, int nray) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)(le - lb) * nray) return;
+  const uint32_t i = lb + (uint32_t)(gid / nray);
+  const int k = (int)(gid % nray);
+  const uint32_t p = tb.b_pre[i];
+  const double4 cp = tb.cen[p];
+  const double c[3] = {cp.x, cp.y, cp.z};
+  double lo[3], hi[3];
+  node_box(tb.hdr, tb.nk[p], lo, hi);
+  const double* nv = &tb.ray_n[3 * k];
+  double dn = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (nv[a] > 0.0) dn = fmin(dn, (hi[a] - c[a]) / nv[a]);
+    else if (nv[a] < 0.0) dn = fmin(dn, (lo[a] - c[a]) / nv[a]);
+  }
+  dn = fmax(dn, 0.0);
+  tb.csrc_d[(int64_t)p * nray + k] = dn;
+  double* out = &tb.csrc_a[((int64_t)p * nray + k) * B];
+  if (tb.b_split[i] < 0) {
+    for (int b = 0; b < B; ++b) out[b] = tb.alpha64[(int64_t)p * nclass * B + b];
+    return;
+  }
+  const uint32_t ch[2] = {p + 1u, tb.nlink[p].x};
+  double Dq[2], dq[2];
+  for (int q = 0; q < 2; ++q) {
+    const double4 cc = tb.cen[ch[q]];
+    double D = dn;
+    D += (c[0] - cc.x) * nv[0];
+    D += (c[1] - cc.y) * nv[1];
+    D += (c[2] - cc.z) * nv[2];
+    Dq[q] = D;
+    dq[q] = tb.csrc_d[(int64_t)ch[q] * nray + k];
+  }
+  const int cls = tb.ray_class[k];
+  for (int b = 0; b < B; ++b) {
+    const double Ln = tb.Lb[(int64_t)p * B + b];
+    double al = 0.0;
+    if (Ln > 0.0 && dn > 0.0) {
+      const double aext = tb.alpha64[((int64_t)p * nclass + cls) * B + b];
+      double tau[2], w[2];
+      for (int q = 0; q < 2; ++q) {
+        w[q] = tb.Lb[(int64_t)ch[q] * B + b] / Ln;
+        const double ai = tb.csrc_a[((int64_t)ch[q] * nray + k) * B + b];
+        if (!(Dq[q] > 0.0)) tau[q] = 0.0;
+        else if (Dq[q] <= dq[q]) tau[q] = ai * Dq[q];
+        else tau[q] = ai * dq[q] + aext * (Dq[q] - dq[q]);
+      }
+      int first = -1;
+      for (int q = 0; q < 2; ++q)
+        if (w[q] > 0.0 && (first < 0 || tau[q] < tau[first])) first = q;
+      double sum = 0.0;
+      for (int q = 0; q < 2; ++q)
+        if (w[q] > 0.0) sum += w[q] * exp(-(tau[q] - tau[first]));
+      al = (tau[first] - log(sum)) / dn;
+    }
+    out[b] = al;
+  }
+}
+
 // ======================================================== host side
 static void healpix_centres(int N, std::vector<double>& v) {
   v.assign(3 * 12 * N * N, 0.0);
@@ -478,6 +551,20 @@ DirTables make_dir_tables(int nside) {
     t.ray_class[k] = found;
   }
   t.nclass = (int)rep.size();
+  // antipodes: HEALPix centres come in opposite pairs, so -n_k is the centre
+  // nearest to it
+  t.ray_anti.assign(t.nray, 0);
+  for (int k = 0; k < t.nray; ++k) {
+    double best = INFINITY;
+    for (int j = 0; j < t.nray; ++j) {
+      double d2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        const double u = t.ray_n[3 * j + a] + t.ray_n[3 * k + a];
+        d2 += u * u;
+      }
+      if (d2 < best) { best = d2; t.ray_anti[k] = j; }
+    }
+  }
   t.geom.assign((size_t)kMaxLevels * t.nclass * 3, 0.0);
   for (int l = 0; l < kMaxLevels; ++l) {
     double s[3];
@@ -534,6 +621,13 @@ size_t layout_tree(const trevr_params& p, int64_t n, int nclass, void* base, Tre
   t.alpha32 = cv.take<float>(M * nclass * B);
   t.ray_n = cv.take<double>(3 * nray);
   t.ray_class = cv.take<int32_t>(nray);
+  t.ray_anti = cv.take<int32_t>(nray);
+  t.csrc_d = nullptr;
+  t.csrc_a = nullptr;
+  if (p.flags & TREVR_COMPLEX_SRC) {
+    t.csrc_d = cv.take<double>(M * nray);
+    t.csrc_a = cv.take<double>(M * nray * B);
+  }
   t.geom = cv.take<double>((size_t)kMaxLevels * nclass * 3);
   t.dev = cv.take<DevTree>(1);
   t.levels = cv.take<uint2>(kMaxLevels + 3);
@@ -564,6 +658,10 @@ trevr_status build_tree_impl(trevr_tree* T, const float* x, const float* y, cons
   if ((rc = hip_check(hipMemcpyAsync(tb.ray_class, T->dirs.ray_class.data(),
                                      sizeof(int32_t) * T->dirs.ray_class.size(),
                                      hipMemcpyHostToDevice, st), "copy classes")) != TREVR_OK) return rc;
+  if ((rc = hip_check(hipMemcpyAsync(tb.ray_anti, T->dirs.ray_anti.data(),
+                                     sizeof(int32_t) * T->dirs.ray_anti.size(),
+                                     hipMemcpyHostToDevice, st), "copy antipodes")) != TREVR_OK)
+    return rc;
   if ((rc = hip_check(hipMemcpyAsync(tb.geom, T->dirs.geom.data(),
                                      sizeof(double) * T->dirs.geom.size(),
                                      hipMemcpyHostToDevice, st), "copy geometry")) != TREVR_OK) return rc;
@@ -659,6 +757,11 @@ trevr_status build_tree_impl(trevr_tree* T, const float* x, const float* y, cons
     k_alpha<<<grid_for(work, 128), 128, 0, st>>>(tb, lv.first, lv.second, B, nclass,
                                                   (T->p.flags & TREVR_ABSORPTION_AVG) ? 1 : 0);
     TREVR_LAUNCH_CHECK("k_alpha");
+    if (T->p.flags & TREVR_COMPLEX_SRC) {
+      const int64_t cw = (int64_t)(lv.second - lv.first) * T->nray;
+      k_csrc<<<grid_for(cw, 128), 128, 0, st>>>(tb, lv.first, lv.second, B, nclass, T->nray);
+      TREVR_LAUNCH_CHECK("k_csrc");
+    }
   }
 #undef TREVR_LAUNCH_CHECK
   return TREVR_OK;

@@ -70,6 +70,10 @@ struct DevTree {
   const float* alpha;         // [node][nclass][B]
   const double* ray_n;        // [nray][3]
   const int32_t* ray_class;   // [nray]
+  const int32_t* ray_anti;    // [nray] ray of the opposite direction
+  const double* csrc_d;       // complex source model (TREVR_COMPLEX_SRC): [node][nray]
+  const double* csrc_a;       //   lengths and [node][nray][B] absorption of the
+                              //   rays from each node's luminosity centre
   uint32_t* err;              // sticky error bits
   unsigned long long* counters;
   // tables of the build that the adjoint reads

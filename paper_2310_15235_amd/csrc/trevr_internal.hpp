@@ -60,6 +60,9 @@ struct TreeBufs {
   float* alpha32;
   double* ray_n;
   int32_t* ray_class;
+  int32_t* ray_anti;          // [nray] ray of the opposite direction
+  double *csrc_d, *csrc_a;    // complex source model: [node][nray] lengths,
+                              // [node][nray][B] absorption (null when off)
   double* geom;               // [64][nclass][3]: log w1, log w12, chord / L
   uint32_t* err;
   unsigned long long* counters;
@@ -80,6 +83,7 @@ struct DirTables {
   int nside = 0, nray = 0, nclass = 0;
   std::vector<double> ray_n;      // [nray][3]
   std::vector<int32_t> ray_class; // [nray]
+  std::vector<int32_t> ray_anti;  // [nray] ray of the opposite direction
   std::vector<double> geom;       // [64][nclass][3]
 };
 DirTables make_dir_tables(int nside);

@@ -79,3 +79,41 @@ def test_directed_rays_general_scene(kw):
     if bg:
         sc = sc.with_(background=True, bg=np.array([0.3, 0.1], np.float32))
     compare_J(sc)
+
+
+@pytest.mark.parametrize("test", ["source+clouds", "source+wall", "two sources+cloud"])
+def test_complex_source_parity(test):
+    """The complex source model (Section 2.7): the per-direction source rays
+    built with the tree and used by merged sources; J on the shell and the
+    escape figures against the oracle."""
+    import torch
+    from paper_2310_15235_amd import api
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = MAKERS[test](False).with_(complex_source=True)
+    act = scenes.shell_active(sc)
+    compare_J(sc, active=act)
+    Jg, _ = api.compute_J(sc, active=act)
+    Jo, _ = oracle.OracleTree(sc).compute_J(act)
+    eg, cg = escape_covering(sc, Jg, act)
+    eo, co = escape_covering(sc, Jo, act)
+    assert eg == pytest.approx(eo, rel=1e-5)
+    assert cg == co
+
+
+@pytest.mark.parametrize("kw", [dict(nside=1), dict(nside=2, absorption_avg=True),
+                                dict(nside=4, background=True)])
+def test_complex_source_general_scene(kw):
+    """The complex source model in a clumpy medium with many sources, three
+    bands, all receivers: J and every counter against the oracle; the
+    adjoint refuses the model."""
+    from paper_2310_15235_amd import api
+    bg = kw.pop("background", False)
+    sc = scenes.lognormal_scene(n=6000, seed=120 + kw["nside"], grid=16,
+                                bands=(1.0, 10.0, 100.0), complex_source=True, **kw)
+    if bg:
+        sc = sc.with_(background=True, bg=np.array([0.3, 0.1, 0.05], np.float32))
+    compare_J(sc)
+    with pytest.raises(api.TrevrError) as e:
+        api.compute_J_backward(sc, np.zeros((sc.n_bands, sc.n)))
+    assert e.value.status == api.E_INVALID
