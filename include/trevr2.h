@@ -299,11 +299,16 @@ trevr_status trevr_tree_info(const trevr_tree* t, int64_t* num_nodes, int32_t* n
  *   Lb      double [nodes][B] luminosity per band;  Lbol double [nodes]
  *   alpha   float [nodes][classes][B] transmission-averaged absorption
  *   ray_class int32 [N_ray]  direction class of each HEALPix ray
+ *   kmass   double [nodes]   sum over elements and bands of kappa m
+ *   csrc_d  double [nodes][N_ray], csrc_a double [nodes][N_ray][B]: the
+ *           complex source model's ray lengths and absorption (only for a
+ *           tree built with TREVR_COMPLEX_SRC; TREVR_E_STATE otherwise)
  * Synchronises the tree's stream.
  */
 trevr_status trevr_tree_export(trevr_tree* t, int64_t* perm, int64_t* ints, double* box,
                                double* cen, double* Lb, double* Lbol, float* alpha,
-                               int32_t* ray_class);
+                               int32_t* ray_class, double* kmass, double* csrc_d,
+                               double* csrc_a);
 
 /*
  * Kernel timing (support call, not part of the method): when enabled, each

@@ -305,14 +305,20 @@ class Tree:
         Lb = np.zeros((nn, B))
         Lbol = np.zeros(nn)
         alpha = np.zeros((nn, C, B), np.float32)
-        rc = np.zeros(12 * self.nside ** 2, np.int32)
-        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        K = 12 * self.nside ** 2
+        rc = np.zeros(K, np.int32)
+        kmass = np.zeros(nn)
+        cplx = bool(self.params.flags & COMPLEX_SOURCE)
+        cd = np.zeros((nn, K)) if cplx else None
+        ca = np.zeros((nn, K, B)) if cplx else None
+        p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         _check(lib().trevr_tree_export(self.handle, p(perm), p(ints), p(box), p(cen), p(Lb),
-                                       p(Lbol), p(alpha), p(rc)), "trevr_tree_export")
+                                       p(Lbol), p(alpha), p(rc), p(kmass), p(cd), p(ca)),
+               "trevr_tree_export")
         return dict(perm=perm, first=ints[:, 0], count=ints[:, 1], lown=ints[:, 2],
                     split=ints[:, 3], child0=ints[:, 4], child1=ints[:, 5], next=ints[:, 6],
                     lo=box[:, :3], hi=box[:, 3:], cen=cen, Lb=Lb, Lbol=Lbol, alpha=alpha,
-                    ray_class=rc, **inf)
+                    ray_class=rc, kmass=kmass, csrc_d=cd, csrc_a=ca, **inf)
 
     def close(self):
         if getattr(self, "_owned", True) and getattr(self, "handle", None) is not None and \

@@ -426,7 +426,8 @@ trevr_status trevr_tree_info(const trevr_tree* t, int64_t* num_nodes, int32_t* n
 
 trevr_status trevr_tree_export(trevr_tree* t, int64_t* perm, int64_t* ints, double* box,
                                double* cen, double* Lb, double* Lbol, float* alpha,
-                               int32_t* ray_class) {
+                               int32_t* ray_class, double* kmass, double* csrc_d,
+                               double* csrc_a) {
   if (!live(t)) return set_error(TREVR_E_STATE, "unknown or destroyed tree handle");
   hipError_t he = hipStreamSynchronize(t->stream);
   if (he != hipSuccess) return hip_check(he, "sync");
@@ -489,6 +490,11 @@ trevr_status trevr_tree_export(trevr_tree* t, int64_t* perm, int64_t* ints, doub
   if (Lb) ok = ok && dl(Lb, t->buf.Lb, sizeof(double) * nn * B);
   if (alpha) ok = ok && dl(alpha, t->buf.alpha32, sizeof(float) * nn * C * B);
   if (ray_class) std::memcpy(ray_class, t->dirs.ray_class.data(), sizeof(int32_t) * t->nray);
+  if (kmass) ok = ok && dl(kmass, t->buf.kmass, sizeof(double) * nn);
+  if ((csrc_d || csrc_a) && !t->buf.csrc_d)
+    return set_error(TREVR_E_STATE, "the tree has no complex source tables");
+  if (csrc_d) ok = ok && dl(csrc_d, t->buf.csrc_d, sizeof(double) * nn * t->nray);
+  if (csrc_a) ok = ok && dl(csrc_a, t->buf.csrc_a, sizeof(double) * nn * t->nray * B);
   if (!ok) return set_error(TREVR_E_HIP, "export copy failed");
   return TREVR_OK;
 }

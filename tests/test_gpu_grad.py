@@ -152,7 +152,7 @@ def test_adjoint_differentiation_full_size_dot(keep):
     api = _api()
     sc = scenes.config_differentiation()
     act = scenes.active_subset(sc, 0.01, 7)
-    _dot_check(sc, act, seed=7, ndir=3, extra_flags=api.KEEP_DEPTHS if keep else 0)
+    _dot_check(sc, act, seed=7, ndir=8, extra_flags=api.KEEP_DEPTHS if keep else 0)
 
 
 @pytest.mark.parametrize("name", ["lognormal_nside2_3bands", "uniform_nside4", "background"])
@@ -317,12 +317,16 @@ def test_adjoint_against_central_differences_on_the_small_copy(which):
         J, _, c = oracle.jvp(sc, active=act, **kw)
         Js.append(J)
         cnt.append(c)
-    assert cnt[0] == cnt[1] == cnt[2], "a counted decision moved within the step"
+    strip = lambda c: {k: v for k, v in c.items() if k != "near_src_hits"}
+    assert strip(cnt[0]) == strip(cnt[1]) == strip(cnt[2]), \
+        "a counted decision moved within the step"
     right, left = (Js[0] - Js[1]) / eps, (Js[1] - Js[2]) / eps
     central = (Js[0] - Js[2]) / (2 * eps)
     den = np.maximum(np.abs(central), 1e-3 * np.abs(central).max(axis=1, keepdims=True))
     kink = np.abs(right - left) / den > 1e-4
-    assert kink.mean() < 0.25, kink.mean()
+    # observed: 12.5% of J components for rho directions (ties of the p-p
+    # radius maximum), none for kappa and L
+    assert kink.mean() <= (0.15 if which == "rho" else 0.0), kink.mean()
     w[kink] = 0.0
     gL, gk, gr = api.compute_J_backward(sc, w, active=act)
     g = {"lum": gL, "kappa": gk, "rho": gr}[which]
@@ -340,3 +344,67 @@ def test_adjoint_directed_rays():
     sc = scenes.lognormal_scene(n=4000, seed=65, grid=16, bands=(1.0, 10.0), nside=2,
                                 directed=(0.31, 0.62, 0.45))
     _dot_check(sc, sc.active)
+
+
+def test_adjoint_against_central_differences_tie_free_copy():
+    """The 2^12 copy with every element's mass jittered by up to 1% (so no
+    two elements of a grid cell share their size h and the p-p radius
+    maximum has no ties): central differences along rho leave almost no
+    component at a kink, and the adjoint matches them."""
+    api = _api()
+    sc = scenes.config_differentiation_small()
+    rng = np.random.default_rng(21)
+    sc = sc.with_(m=(sc.m * (1.0 + 0.01 * rng.random(sc.n))).astype(np.float32))
+    act = np.ones(sc.n, np.uint8)
+    w = rng.normal(size=(sc.n_bands, sc.n))
+    base = sc.rho.astype(np.float64)
+    v = rng.normal(size=sc.n)
+    eps = 1e-6
+    Js = [oracle.jvp(sc, active=act, rho=base * (1.0 + sgn * eps * v))[0] for sgn in (+1, 0, -1)]
+    right, left = (Js[0] - Js[1]) / eps, (Js[1] - Js[2]) / eps
+    central = (Js[0] - Js[2]) / (2 * eps)
+    den = np.maximum(np.abs(central), 1e-3 * np.abs(central).max(axis=1, keepdims=True))
+    kink = np.abs(right - left) / den > 1e-4
+    print(f"tie-free rho: {int(kink.sum())} of {kink.size} components at a kink skipped")
+    assert kink.mean() < 0.005, kink.mean()
+    w[kink] = 0.0
+    _, _, gr = api.compute_J_backward(sc, w, active=act)
+    terms = gr * base * v
+    lhs, rhs = float(np.sum(terms)), float(np.sum(w * central))
+    scale = max(float(np.sum(np.abs(terms))), float(np.sum(np.abs(w * central))))
+    assert abs(lhs - rhs) <= 1e-4 * scale, (lhs, rhs, scale)
+
+
+def test_adjoint_per_component_small_copy():
+    """64 components of each gradient array of the 2^12 copy -- the 16
+    largest, the 16 smallest nonzero and 32 random -- each against the
+    oracle's forward-mode derivative along that component's unit vector:
+    |g - g_oracle| <= 1e-4 |g_oracle| + 1e-7 max|g| (per-term FP32
+    arithmetic; a component that is a sum of terms of both signs keeps an
+    absolute error on the scale of its largest terms)."""
+    api = _api()
+    sc = scenes.config_differentiation_small()
+    act = np.ones(sc.n, np.uint8)
+    rng = np.random.default_rng(31)
+    gJ = rng.normal(size=(sc.n_bands, sc.n))
+    grads = api.compute_J_backward(sc, gJ, active=act)
+    worst = {}
+    for name, g in zip(("L", "kappa", "rho"), grads):
+        flat = np.abs(g).ravel()
+        order = np.argsort(flat)
+        nz = order[flat[order] > 0]
+        picks = list(nz[-16:]) + list(nz[:16]) + list(rng.choice(flat.size, 32, replace=False))
+        gmax = flat.max()
+        errs = []
+        for fi in picks:
+            t = np.zeros(g.size)
+            t[fi] = 1.0
+            t = t.reshape(g.shape)
+            kw = {"L": dict(tL=t), "kappa": dict(tkappa=t), "rho": dict(trho=t)}[name]
+            _, dJ, _ = oracle.jvp(sc, active=act, **kw)
+            go = float(np.sum(gJ * dJ))
+            gg = float(g.ravel()[fi])
+            errs.append(abs(gg - go) / (abs(go) + 1e-12 * gmax))
+            assert abs(gg - go) <= 1e-4 * abs(go) + 1e-7 * gmax, (name, int(fi), gg, go, gmax)
+        worst[name] = max(errs)
+    print("largest relative component errors:", worst)

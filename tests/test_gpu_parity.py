@@ -47,6 +47,12 @@ def compare_tree(sc):
     np.testing.assert_allclose(g["cen"], o["cen"], rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(g["Lb"], o["Lb"], rtol=1e-12, atol=0)
     np.testing.assert_allclose(g["Lbol"], o["Lbol"], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(g["kmass"], o["kmass"], rtol=1e-12, atol=0)
+    if g["csrc_d"] is not None:
+        cd, ca, ap = O.complex_tables()
+        np.testing.assert_allclose(g["csrc_d"], cd, rtol=1e-9, atol=1e-12)
+        scale = np.maximum(np.abs(ca), 1e-30)
+        assert np.max(np.abs(g["csrc_a"] - ca) / scale) < 1e-5
     dir_of_ray, _ = O.dirs()
     ga = g["alpha"][:, g["ray_class"], :].astype(np.float64)     # [node][ray][B]
     oa = o["alpha"][:, dir_of_ray, :]
@@ -140,6 +146,14 @@ def test_J_seven_to_sixteen_bands(nb):
     bands = tuple(float(2 ** (k * 7.0 / (nb - 1))) for k in range(nb))
     sc = scenes.lognormal_scene(n=6000, seed=70 + nb, grid=16, bands=bands, nside=2)
     compare_J(sc)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4])
+def test_tree_tables_complex_source(nside):
+    """Complex source model tables (Section 2.7): per node and direction the
+    length of the source's own ray and its absorption, against the oracle."""
+    compare_tree(scenes.lognormal_scene(n=6000, seed=130 + nside, grid=16, bands=(1.0, 10.0),
+                                        nside=nside, complex_source=True))
 
 
 @pytest.mark.parametrize("maker", [
