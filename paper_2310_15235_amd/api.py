@@ -86,7 +86,7 @@ def lib():
         L.trevr_tree_destroy.argtypes = [vp]
         L.trevr_tree_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32),
                                       ctypes.POINTER(i32), vp]
-        L.trevr_tree_export.argtypes = [vp] * 9
+        L.trevr_tree_export.argtypes = [vp] * 12
         L.trevr_profile_enable.argtypes = [vp, ctypes.c_int]
         L.trevr_profile_read.argtypes = [vp, vp, vp]
         L.trevr_forest_workspace_bytes.argtypes = [ctypes.POINTER(Params), i32, vp,
@@ -105,6 +105,9 @@ def lib():
         L.trevr_forest_autotune.argtypes = [vp] * 9 + [sz, vp, i32, vp]
         L.trevr_forest_set_config.argtypes = [vp, i32]
         L.trevr_forest_get_config.argtypes = [vp, ctypes.POINTER(i32)]
+        L.trevr_forest_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.trevr_forest_profile_read.argtypes = [vp, vp, vp]
+        L.trevr_compute_J_noalloc.argtypes = [vp, vp, vp, vp, vp]
         L.trevr_status_string.restype = ctypes.c_char_p
         L.trevr_status_string.argtypes = [ctypes.c_int]
         L.trevr_last_error.restype = ctypes.c_char_p
