@@ -575,6 +575,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   __shared__ uint8_t pd_valid[kNT];
   __shared__ float tacc[kNT][NB];
   __shared__ uint8_t nlist[kNT / 64][64];
+  __shared__ float egrp[kNT / 64][5];      // each wavefront's element sphere
   // the workgroup's sums of the per-bucket counters (thread 0), added to a
   // scene's counters when it turns to another scene and after its last bucket
   __shared__ unsigned long long csum[4];   // near pairs, triples, largest set, hits
@@ -724,29 +725,38 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               }
             }
           };
-          for (int q0 = 0; q0 < qend; q0 += nrecv) {
-            bool pass = false;
-            if (has) {
-              const float s0 = pd_jr[q0][0], s1 = pd_jr[q0][1], s2 = pd_jr[q0][2];
-              const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
-              float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * pd_jinv[q0];
-              tt = fminf(1.0f, fmaxf(0.0f, tt));
-              const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
-              pass = f0 * f0 + f1 * f1 + f2 * f2 <= pd_jlim[q0] * (1.0f + 1e-4f) &&
-                     d0 * d0 + d1 * d1 + d2 * d2 <= rad2;
-            }
-            const uint64_t m = ballot64(pass);
-            if (m == 0ull) continue;
-            if (pass) {
-              const uint32_t pos = tail + (uint32_t)mbcnt(m) * (uint32_t)nrecv;
-              for (int k = 0; k < nrecv; ++k)
-                Q[(pos + (uint32_t)k) & (kJobQ - 1)] = (uint16_t)((lane << 8) | (q0 + k));
-            }
-            tail += (uint32_t)__popcll(m) * (uint32_t)nrecv;
-            wave_lds_sync();
-            while (tail - head >= 64u) {
-              run_jobs(64u);
-              head += 64u;
+          // the wavefront's elements as one sphere first: only the source
+          // runs that may reach it go through the per-element tests
+          elem_group(pr, rad, has, egrp[wv]);
+          const int nruns = qend / nrecv;
+          for (int k0 = 0; k0 < nruns; k0 += 64) {
+            uint64_t gm = group_runs(egrp[wv], pd_jr, pd_jinv, pd_jlim, k0, nruns, nrecv);
+            while (gm != 0ull) {
+              const int q0 = (k0 + (int)__builtin_ctzll(gm)) * nrecv;
+              gm &= gm - 1ull;
+              bool pass = false;
+              if (has) {
+                const float s0 = pd_jr[q0][0], s1 = pd_jr[q0][1], s2 = pd_jr[q0][2];
+                const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
+                float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * pd_jinv[q0];
+                tt = fminf(1.0f, fmaxf(0.0f, tt));
+                const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
+                pass = f0 * f0 + f1 * f1 + f2 * f2 <= pd_jlim[q0] * (1.0f + 1e-4f) &&
+                       d0 * d0 + d1 * d1 + d2 * d2 <= rad2;
+              }
+              const uint64_t m = ballot64(pass);
+              if (m == 0ull) continue;
+              if (pass) {
+                const uint32_t pos = tail + (uint32_t)mbcnt(m) * (uint32_t)nrecv;
+                for (int k = 0; k < nrecv; ++k)
+                  Q[(pos + (uint32_t)k) & (kJobQ - 1)] = (uint16_t)((lane << 8) | (q0 + k));
+              }
+              tail += (uint32_t)__popcll(m) * (uint32_t)nrecv;
+              wave_lds_sync();
+              while (tail - head >= 64u) {
+                run_jobs(64u);
+                head += 64u;
+              }
             }
           }
           if (tail > head) run_jobs(tail - head);

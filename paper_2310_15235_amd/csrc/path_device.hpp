@@ -380,6 +380,73 @@ constexpr uint32_t kJobQ = 1024;
 // ones pair-major over culling boxes of staged elements.
 constexpr uint32_t kPpElementMajor = 4096;
 
+__device__ inline float wave_fmin(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline float wave_fmax(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// The p-p elements of a wavefront in an element-major sweep (one per lane
+// with `has`, positions pr relative to the bucket centre, each with its test
+// radius rad = its size + the receivers' reach) as one sphere, written to
+// the wavefront's G[5]: centre g = G[0..2] (the middle of their box), G[3] =
+// rp the farthest position from g, G[4] = rr the farthest position plus its
+// radius (< 0 when no lane holds an element).  The elements of a
+// slot-ordered p-p list are spatially close in runs of 64, so most source
+// runs miss the sphere and skip the per-element tests.
+__device__ inline void elem_group(const float pr[3], float rad, bool has, float* G) {
+  float g[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    g[a] = 0.5f * (wave_fmin(has ? pr[a] : INFINITY) + wave_fmax(has ? pr[a] : -INFINITY));
+  const float d0 = pr[0] - g[0], d1 = pr[1] - g[1], d2 = pr[2] - g[2];
+  const float dl = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  const float rp = wave_fmax(has ? dl : -1.0f);
+  const float rr = wave_fmax(has ? dl + rad : -1.0f);
+  if ((threadIdx.x & 63) == 0) {
+    G[0] = g[0];
+    G[1] = g[1];
+    G[2] = g[2];
+    G[3] = rp;
+    G[4] = rr;
+  }
+  wave_lds_sync();
+}
+
+// The source runs k0 + k (k < 64, lane k; pair (k0 + k) * nrecv) whose
+// centre segment to the source, s = jr, comes within rr of the sphere's
+// centre and whose source lies within sqrt(jlim) + rp of it: the runs for
+// which some element of the group can pass the per-element test (distance
+// to the segment within rad, distance to the source within sqrt(jlim)).
+// Margins of 1e-4 relative and 1e-5 of the coordinates' size cover FP32
+// rounding on both sides.  Wave-uniform mask over k.
+__device__ inline uint64_t group_runs(const float* G, const float (*jr)[3], const float* jinv,
+                                      const float* jlim, int k0, int nruns, int nrecv) {
+  const float rr = G[4];
+  if (rr < 0.0f) return 0ull;
+  const int k = k0 + (int)(threadIdx.x & 63);
+  bool pass = false;
+  if (k < nruns) {
+    const float g0 = G[0], g1 = G[1], g2 = G[2], rp = G[3];
+    const int q = k * nrecv;
+    const float s0 = jr[q][0], s1 = jr[q][1], s2 = jr[q][2];
+    const float tol = 1e-5f * (fabsf(g0) + fabsf(g1) + fabsf(g2) + fabsf(s0) + fabsf(s1) + fabsf(s2));
+    float tt = (g0 * s0 + g1 * s1 + g2 * s2) * jinv[q];
+    tt = fminf(1.0f, fmaxf(0.0f, tt));
+    const float d0 = g0 - tt * s0, d1 = g1 - tt * s1, d2 = g2 - tt * s2;
+    const float r1 = rr * (1.0f + 1e-4f) + tol;
+    const float f0 = g0 - s0, f1 = g1 - s1, f2 = g2 - s2;
+    const float r2 = (sqrtf(jlim[q]) + rp) * (1.0f + 1e-4f) + tol;
+    pass = d0 * d0 + d1 * d1 + d2 * d2 <= r1 * r1 && f0 * f0 + f1 * f1 + f2 * f2 <= r2 * r2;
+  }
+  return ballot64(pass);
+}
+
 template <int NB> struct NearTile {
   double x[kNChunk], y[kNChunk], z[kNChunk], h2[kNChunk];
   float sig[kNChunk], invh[kNChunk];
