@@ -659,9 +659,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
         // (the nrecv pairs of one source) it tests the element against the
         // centre's segment to the source grown by the receivers' reach, and
         // the element no farther from the source than the farthest receiver
-        // (a superset of the exact test's passes); passing (element, pair)
-        // jobs are queued per wavefront and run 64 at a time with the exact
-        // FP64 test of the pair-major sweep, LDS atomics adding into tacc
+        // (a superset of the exact test's passes); passing (element, source
+        // run) jobs are queued per wavefront and run 64 at a time with the
+        // exact FP64 test of the pair-major sweep on each pair of the run,
+        // LDS atomics adding into tacc
         {
           const float jj = jr[0] * jr[0] + jr[1] * jr[1] + jr[2] * jr[2];
           const float lim = (sqrtf(jj) + reach) * (1.0f + 1e-5f);
@@ -692,12 +693,15 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
                             1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
           const float rad2 = rad * rad;
           uint32_t head = 0, tail = 0;   // wave-uniform queue cursors
-          // one batch of up to 64 queued jobs, job head + lane on this lane
+          // one batch of up to 64 queued jobs, job head + lane on this lane:
+          // a job is (element, source run); its lane runs the exact test of
+          // the element on each of the run's nrecv pairs (pair q0 + k has
+          // receiver k), the element and source read once
           auto run_jobs = [&](uint32_t cnt) {
             const bool mine = (uint32_t)lane < cnt;
             const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
             const int L = mine ? (int)(job >> 8) : lane;
-            const int q = (int)(job & 0xFFu);
+            const int q0 = (int)(job & 0xFFu);
             const double vx = __shfl(ux, L), vy = __shfl(uy, L), vz = __shfl(uz, L);
             const double vh2 = __shfl(h2, L);
             const float vsig = __shfl(sig, L), viv = __shfl(iv, L);
@@ -705,23 +709,28 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             float vkap[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) vkap[b] = __shfl(kap[b], L);
-            if (mine && pd_valid[q]) {
-              const RecvInfo& rq = recv[q % nrecv];
-              const double qx0 = pd_xj[q][0], qx1 = pd_xj[q][1], qx2 = pd_xj[q][2];
-              const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
+            if (mine) {
+              const double qx0 = pd_xj[q0][0], qx1 = pd_xj[q0][1], qx2 = pd_xj[q0][2];
+              const uint32_t qj = pd_j[q0];
               const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
-              const double w0 = vx - rq.x[0], w1 = vy - rq.x[1], w2 = vz - rq.x[2];
-              double uu = (w0 * pe0 + w1 * pe1 + w2 * pe2) * pd_inv2[q];
-              uu = fmin(1.0, fmax(0.0, uu));
-              const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
-              const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-              if ((f0 * f0 + f1 * f1 + f2 * f2 < pd_r2[q]) && b2 < vh2 && vl != rq.slot &&
-                  vl != pd_j[q]) {
-                ++hits;
-                const float bb = sqrtf((float)b2);
-                const float sg = vsig * (1.0f - bb * viv);
+              const double ff = f0 * f0 + f1 * f1 + f2 * f2;
+              for (int k = 0; k < nrecv; ++k) {
+                const int q = q0 + k;
+                if (!pd_valid[q]) continue;
+                const RecvInfo& rq = recv[k];
+                const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
+                const double w0 = vx - rq.x[0], w1 = vy - rq.x[1], w2 = vz - rq.x[2];
+                double uu = (w0 * pe0 + w1 * pe1 + w2 * pe2) * pd_inv2[q];
+                uu = fmin(1.0, fmax(0.0, uu));
+                const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
+                const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+                if (ff < pd_r2[q] && b2 < vh2 && vl != rq.slot && vl != qj) {
+                  ++hits;
+                  const float bb = sqrtf((float)b2);
+                  const float sg = vsig * (1.0f - bb * viv);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) atomicAdd(&tacc[q][b], vkap[b] * sg);
+                  for (int b = 0; b < NB; ++b) atomicAdd(&tacc[q][b], vkap[b] * sg);
+                }
               }
             }
           };
@@ -746,12 +755,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               }
               const uint64_t m = ballot64(pass);
               if (m == 0ull) continue;
-              if (pass) {
-                const uint32_t pos = tail + (uint32_t)mbcnt(m) * (uint32_t)nrecv;
-                for (int k = 0; k < nrecv; ++k)
-                  Q[(pos + (uint32_t)k) & (kJobQ - 1)] = (uint16_t)((lane << 8) | (q0 + k));
-              }
-              tail += (uint32_t)__popcll(m) * (uint32_t)nrecv;
+              if (pass) Q[(tail + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((lane << 8) | q0);
+              tail += (uint32_t)__popcll(m);
               wave_lds_sync();
               while (tail - head >= 64u) {
                 run_jobs(64u);

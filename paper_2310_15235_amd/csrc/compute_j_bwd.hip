@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
   __shared__ double red[kNT][NB];
   __shared__ double redh[kNT];
-  __shared__ uint16_t jobq[kNT / 64][kJobQ];      // per wavefront: (element lane, pair)
+  __shared__ uint16_t jobq[kNT / 64][kJobQ];      // per wavefront: (element lane, source run)
   __shared__ float eacc[kNT / 64][64][NB + 1];     // per wavefront: element sums
   __shared__ float egrp[kNT / 64][5];              // per wavefront: element sphere
   const int lane = t & 63, wv = t >> 6;
@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
         // element; per source run it tests the element against the centre's
         // segment to the source grown by the receivers' reach (and the
         // element no farther from the source than the farthest receiver).
-        // Passing (element, pair) jobs are queued per wavefront and run 64
-        // at a time, so the exact FP64 tests keep every lane busy.
+        // Passing (element, source run) jobs are queued per wavefront and
+        // run 64 at a time, so the exact FP64 tests keep every lane busy.
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
           const uint32_t u = c0 + (uint32_t)t;
           const bool has = u < nnear;
@@ -307,12 +307,16 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
           for (int b = 0; b <= NB; ++b) A[lane][b] = 0.0f;
           uint32_t head = 0, tail = 0;   // wave-uniform queue cursors
 
-          // one batch of up to 64 queued jobs, job head + lane on this lane
+          // one batch of up to 64 queued jobs, job head + lane on this lane:
+          // a job is (element, source run); its lane runs the exact test of
+          // the element on each of the run's nrecv pairs (pair q0 + k has
+          // receiver k), sums the element's adjoints over them and adds
+          // them to the element's LDS sums once
           auto run_jobs = [&](uint32_t cnt) {
             const bool mine = (uint32_t)lane < cnt;
             const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
             const int L = mine ? (int)(job >> 8) : lane;
-            const int q = (int)(job & 0xFFu);
+            const int q0 = (int)(job & 0xFFu);
             const double vx = __shfl(ux, L), vy = __shfl(uy, L), vz = __shfl(uz, L);
             const double vh2 = __shfl(h2, L);
             const float vsig = __shfl(sig, L), viv = __shfl(iv, L);
@@ -320,33 +324,47 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
             float vkap[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) vkap[b] = __shfl(kap[b], L);
-            if (mine && PT.valid[q]) {
-              const RecvInfo& rq = recv[PT.i[q]];
-              const double xi0 = rq.x[0], xi1 = rq.x[1], xi2 = rq.x[2];
-              const double qx0 = PT.xj[q][0], qx1 = PT.xj[q][1], qx2 = PT.xj[q][2];
-              const double e0q = qx0 - xi0, e1q = qx1 - xi1, e2q = qx2 - xi2;
+            if (mine) {
+              const double qx0 = PT.xj[q0][0], qx1 = PT.xj[q0][1], qx2 = PT.xj[q0][2];
+              const uint32_t qj = PT.j[q0];
               const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
-              const double w0 = vx - xi0, w1 = vy - xi1, w2 = vz - xi2;
-              double uu = (w0 * e0q + w1 * e1q + w2 * e2q) * PT.inv2[q];
-              uu = fmin(1.0, fmax(0.0, uu));
-              const double g0 = w0 - uu * e0q, g1 = w1 - uu * e1q, g2 = w2 - uu * e2q;
-              const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-              if ((f0 * f0 + f1 * f1 + f2 * f2 < PT.rij2[q]) && b2 < vh2 && vl != rq.slot &&
-                  vl != PT.j[q]) {
-                const float bb = sqrtf((float)b2);
-                const float sg = vsig * (1.0f - bb * viv);
-                const float dsg = vsig * viv * (3.0f * bb * viv - 2.0f);
-                float gqk = 0.0f;
+              const double ff = f0 * f0 + f1 * f1 + f2 * f2;
+              float ga[NB], gh = 0.0f;
+              bool any = false;
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                  atomicAdd(&A[L][b], PT.gt[q][b] * sg);
-                  gqk += PT.gt[q][b] * vkap[b];
+              for (int b = 0; b < NB; ++b) ga[b] = 0.0f;
+              for (int k = 0; k < nrecv; ++k) {
+                const int q = q0 + k;
+                if (!PT.valid[q]) continue;
+                const RecvInfo& rq = recv[k];
+                const double xi0 = rq.x[0], xi1 = rq.x[1], xi2 = rq.x[2];
+                const double e0q = qx0 - xi0, e1q = qx1 - xi1, e2q = qx2 - xi2;
+                const double w0 = vx - xi0, w1 = vy - xi1, w2 = vz - xi2;
+                double uu = (w0 * e0q + w1 * e1q + w2 * e2q) * PT.inv2[q];
+                uu = fmin(1.0, fmax(0.0, uu));
+                const double g0 = w0 - uu * e0q, g1 = w1 - uu * e1q, g2 = w2 - uu * e2q;
+                const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+                if (ff < PT.rij2[q] && b2 < vh2 && vl != rq.slot && vl != qj) {
+                  const float bb = sqrtf((float)b2);
+                  const float sg = vsig * (1.0f - bb * viv);
+                  const float dsg = vsig * viv * (3.0f * bb * viv - 2.0f);
+                  float gqk = 0.0f;
+#pragma unroll
+                  for (int b = 0; b < NB; ++b) {
+                    ga[b] += PT.gt[q][b] * sg;
+                    gqk += PT.gt[q][b] * vkap[b];
+                  }
+                  gh += gqk * dsg;
+                  any = true;
                 }
-                atomicAdd(&A[L][NB], gqk * dsg);
+              }
+              if (any) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) atomicAdd(&A[L][b], ga[b]);
+                atomicAdd(&A[L][NB], gh);
               }
             }
           };
-
           // the wavefront's elements as one sphere first: only the source
           // runs that may reach it go through the per-element tests
           elem_group(pr, rad, has, egrp[wv]);
@@ -368,12 +386,8 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
               }
               const uint64_t m = ballot64(pass);
               if (m == 0ull) continue;
-              if (pass) {
-                const uint32_t pos = tail + (uint32_t)mbcnt(m) * (uint32_t)nrecv;
-                for (int k = 0; k < nrecv; ++k)
-                  Q[(pos + (uint32_t)k) & (kJobQ - 1)] = (uint16_t)((lane << 8) | (q0 + k));
-              }
-              tail += (uint32_t)__popcll(m) * (uint32_t)nrecv;
+              if (pass) Q[(tail + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((lane << 8) | q0);
+              tail += (uint32_t)__popcll(m);
               wave_lds_sync();
               while (tail - head >= 64u) {
                 run_jobs(64u);

@@ -372,9 +372,10 @@ struct RecvInfo {
 constexpr int kSub = 16;
 constexpr int kNSub = kNChunk / kSub;
 
-// Queue of exact-test jobs per wavefront (element-major p-p passes): room
-// for one batch of 64 plus the largest enqueue (64 lanes x kRMax receivers).
-constexpr uint32_t kJobQ = 1024;
+// Queue of exact-test jobs per wavefront (element-major p-p passes), one
+// job per (element, source run): room for the 63 a batch of 64 leaves plus
+// the largest enqueue (one per lane).
+constexpr uint32_t kJobQ = 128;
 // p-p sets from this size on are swept element-major by the p-p source kernel
 // (each element against the pass's source runs, exact tests queued); smaller
 // ones pair-major over culling boxes of staged elements.
