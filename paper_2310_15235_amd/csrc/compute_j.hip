@@ -680,7 +680,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
           const uint32_t u = c0 + (uint32_t)t;
           const bool has = u < nnear;
           const uint32_t l = has ? near[u] : near[0];
-          const double ux = (double)T.x[l], uy = (double)T.y[l], uz = (double)T.z[l];
+          // positions stay FP32 (as stored) until a job widens them
+          const float ux = T.x[l], uy = T.y[l], uz = T.z[l];
           const double hl = T.h[l];
           const double h2 = hl * hl;
           const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
@@ -688,7 +689,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
           float kap[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
-          const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
+          const float pr[3] = {(float)((double)ux - c[0]), (float)((double)uy - c[1]),
+                               (float)((double)uz - c[2])};
           const float rad = ((float)hl + reach) * (1.0f + 1e-5f) +
                             1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
           const float rad2 = rad * rad;
@@ -702,7 +704,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
             const int L = mine ? (int)(job >> 8) : lane;
             const int q0 = (int)(job & 0xFFu);
-            const double vx = __shfl(ux, L), vy = __shfl(uy, L), vz = __shfl(uz, L);
+            const double vx = (double)__shfl(ux, L), vy = (double)__shfl(uy, L),
+                         vz = (double)__shfl(uz, L);
             const double vh2 = __shfl(h2, L);
             const float vsig = __shfl(sig, L), viv = __shfl(iv, L);
             const uint32_t vl = (uint32_t)__shfl((int)l, L);

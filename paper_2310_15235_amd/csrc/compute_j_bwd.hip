@@ -144,7 +144,7 @@ template <int NB> struct PairTile {
 
 
 template <int NB>
-__global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ TT, Items I,
+__global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict__ TT, Items I,
                                                    const uint32_t* blist, const uint32_t* bscene,
                                                    const uint32_t* noff, const uint32_t* nlumc,
                                                    const uint32_t* nidx, const uint32_t* joff,
@@ -191,10 +191,11 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
     for (int k = 0; k < nrecv; ++k)
       reach = fmaxf(reach, sqrtf(recv[k].rel[0] * recv[k].rel[0] + recv[k].rel[1] * recv[k].rel[1] +
                                  recv[k].rel[2] * recv[k].rel[2]));
-    double acc[NB];
+    // each thread's sums over its pairs (its own LDS slots, registers stay
+    // free for the sweep)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
-    double ghi = 0.0;
+    for (int b = 0; b < NB; ++b) red[t][b] = 0.0;
+    redh[t] = 0.0;
     const uint32_t P = (uint32_t)nrecv * nl;
     for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
       // ---- pairs: terms and column adjoints
@@ -217,18 +218,20 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
         const float f = fshape(x);
         const float Kv = f * ri.kfac;
         const float dKdh = -(2.0f * f + x * fshape_d(x)) * ri.kfac * rinvh[i];
+        double ghi = 0.0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const double E = exp(-(double)pt[(int64_t)p * NB + b]);
           const double Lj = (double)T.lum[(int64_t)b * n + j];
           const double term = Lj * (double)Kv * E;
-          acc[b] += term;
+          red[t][b] += term;
           const double w = (double)gw[i][b];
           gl[b] = w * (double)Kv * E;
           ghi += w * Lj * E * (double)dKdh;
           gt[b] = (float)(-w * term);
           valid = valid || gt[b] != 0.0f;
         }
+        redh[t] += ghi;
       }
       {
         // the nrecv pairs of one source sit on consecutive lanes: the first
@@ -290,7 +293,8 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
           const uint32_t u = c0 + (uint32_t)t;
           const bool has = u < nnear;
           const uint32_t l = has ? near[u] : near[0];
-          const double ux = (double)T.x[l], uy = (double)T.y[l], uz = (double)T.z[l];
+          // positions stay FP32 (as stored) until a job widens them
+          const float ux = T.x[l], uy = T.y[l], uz = T.z[l];
           const double hl = T.h[l];
           const double h2 = hl * hl;
           const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
@@ -299,7 +303,8 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
 #pragma unroll
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
           const float hf = (float)hl;
-          const float pr[3] = {(float)(ux - c[0]), (float)(uy - c[1]), (float)(uz - c[2])};
+          const float pr[3] = {(float)((double)ux - c[0]), (float)((double)uy - c[1]),
+                               (float)((double)uz - c[2])};
           const float rad = (hf + reach) * (1.0f + 1e-5f) +
                             1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
           const float rad2 = rad * rad;
@@ -310,14 +315,15 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
           // one batch of up to 64 queued jobs, job head + lane on this lane:
           // a job is (element, source run); its lane runs the exact test of
           // the element on each of the run's nrecv pairs (pair q0 + k has
-          // receiver k), sums the element's adjoints over them and adds
-          // them to the element's LDS sums once
+          // receiver k), the element and source read once, and adds each
+          // hit's adjoints to the element's LDS sums
           auto run_jobs = [&](uint32_t cnt) {
             const bool mine = (uint32_t)lane < cnt;
             const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
             const int L = mine ? (int)(job >> 8) : lane;
             const int q0 = (int)(job & 0xFFu);
-            const double vx = __shfl(ux, L), vy = __shfl(uy, L), vz = __shfl(uz, L);
+            const double vx = (double)__shfl(ux, L), vy = (double)__shfl(uy, L),
+                         vz = (double)__shfl(uz, L);
             const double vh2 = __shfl(h2, L);
             const float vsig = __shfl(sig, L), viv = __shfl(iv, L);
             const uint32_t vl = (uint32_t)__shfl((int)l, L);
@@ -329,10 +335,7 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
               const uint32_t qj = PT.j[q0];
               const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
               const double ff = f0 * f0 + f1 * f1 + f2 * f2;
-              float ga[NB], gh = 0.0f;
-              bool any = false;
-#pragma unroll
-              for (int b = 0; b < NB; ++b) ga[b] = 0.0f;
+#pragma unroll 1
               for (int k = 0; k < nrecv; ++k) {
                 const int q = q0 + k;
                 if (!PT.valid[q]) continue;
@@ -351,17 +354,11 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
                   float gqk = 0.0f;
 #pragma unroll
                   for (int b = 0; b < NB; ++b) {
-                    ga[b] += PT.gt[q][b] * sg;
+                    atomicAdd(&A[L][b], PT.gt[q][b] * sg);
                     gqk += PT.gt[q][b] * vkap[b];
                   }
-                  gh += gqk * dsg;
-                  any = true;
+                  atomicAdd(&A[L][NB], gqk * dsg);
                 }
-              }
-              if (any) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b) atomicAdd(&A[L][b], ga[b]);
-                atomicAdd(&A[L][NB], gh);
               }
             }
           };
@@ -408,9 +405,6 @@ __global__ void __launch_bounds__(kNT) k_pp_src_bwd(const DevTree* __restrict__ 
       __syncthreads();
     }
     // receiver-wise sums in thread order
-#pragma unroll
-    for (int b = 0; b < NB; ++b) red[t][b] = acc[b];
-    redh[t] = ghi;
     __syncthreads();
     if (t < nrecv * NB) {
       const int ii = t / NB, b = t % NB;
