@@ -315,8 +315,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
           // one batch of up to 64 queued jobs, job head + lane on this lane:
           // a job is (element, source run); its lane runs the exact test of
           // the element on each of the run's nrecv pairs (pair q0 + k has
-          // receiver k), the element and source read once, and adds each
-          // hit's adjoints to the element's LDS sums
+          // receiver k), the element and source read once, sums the
+          // element's adjoints over the run and adds them to its LDS sums
           auto run_jobs = [&](uint32_t cnt) {
             const bool mine = (uint32_t)lane < cnt;
             const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
@@ -335,7 +335,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
               const uint32_t qj = PT.j[q0];
               const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
               const double ff = f0 * f0 + f1 * f1 + f2 * f2;
-#pragma unroll 1
+              float ga[NB], gh = 0.0f;
+              bool any = false;
+#pragma unroll
+              for (int b = 0; b < NB; ++b) ga[b] = 0.0f;
               for (int k = 0; k < nrecv; ++k) {
                 const int q = q0 + k;
                 if (!PT.valid[q]) continue;
@@ -354,11 +357,17 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
                   float gqk = 0.0f;
 #pragma unroll
                   for (int b = 0; b < NB; ++b) {
-                    atomicAdd(&A[L][b], PT.gt[q][b] * sg);
+                    ga[b] += PT.gt[q][b] * sg;
                     gqk += PT.gt[q][b] * vkap[b];
                   }
-                  atomicAdd(&A[L][NB], gqk * dsg);
+                  gh += gqk * dsg;
+                  any = true;
                 }
+              }
+              if (any) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) atomicAdd(&A[L][b], ga[b]);
+                atomicAdd(&A[L][NB], gh);
               }
             }
           };
