@@ -560,7 +560,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   // (element-major passes) and the receiver sums share their LDS
   __shared__ union {
     NearTile<NB> S;
-    uint16_t jobq[kNT / 64][kJobQ];
+    uint16_t jobq[kNT / 64][2][kJobQ];
     double red[kNT][NB];
   } U;
   NearTile<NB>& S = U.S;
@@ -657,25 +657,22 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
       if (em) {
         // ---- element-major: each lane owns a p-p element; per source run
         // (the nrecv pairs of one source) it tests the element against the
-        // centre's segment to the source grown by the receivers' reach, and
-        // the element no farther from the source than the farthest receiver
-        // (a superset of the exact test's passes); passing (element, source
-        // run) jobs are queued per wavefront and run 64 at a time with the
-        // exact FP64 test of the pair-major sweep on each pair of the run,
-        // LDS atomics adding into tacc
-        {
-          const float jj = jr[0] * jr[0] + jr[1] * jr[1] + jr[2] * jr[2];
-          const float lim = (sqrtf(jj) + reach) * (1.0f + 1e-5f);
-          pd_jr[t][0] = jr[0];
-          pd_jr[t][1] = jr[1];
-          pd_jr[t][2] = jr[2];
-          pd_jinv[t] = jj > 0.0f ? 1.0f / jj : 0.0f;
-          pd_jlim[t] = lim * lim;
-          pd_valid[t] = (ok && rij2 > 0.0) ? 1u : 0u;
-        }
+        // cylinder of the receivers' reach around the centre's segment to
+        // the source, and the element no farther from the source than the
+        // farthest receiver; passing (element, source run) jobs are queued
+        // per wavefront, filtered 64 at a time by the round cone (the
+        // reach at the centre, none at the source), and run 64 at a time
+        // with the exact FP64 test of the pair-major sweep on each pair of
+        // the run, LDS atomics adding into tacc.  Both tests are supersets
+        // of the exact test's passes
+        run_tab_entry(jr, reach, pd_jr, pd_jinv, pd_jlim, t);
+        pd_valid[t] = (ok && rij2 > 0.0) ? 1u : 0u;
+        const RunTab RT{pd_jr, pd_jinv, pd_jlim};
+        const float Rm = reach * (1.0f + 1e-5f);
         __syncthreads();
         const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
-        uint16_t* Q = U.jobq[wv];
+        uint16_t* QA = U.jobq[wv][0];   // per-element test passes
+        uint16_t* Q = U.jobq[wv][1];    // round-cone passes: exact tests
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
           const uint32_t u = c0 + (uint32_t)t;
           const bool has = u < nnear;
@@ -691,10 +688,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
           const float pr[3] = {(float)((double)ux - c[0]), (float)((double)uy - c[1]),
                                (float)((double)uz - c[2])};
-          const float rad = ((float)hl + reach) * (1.0f + 1e-5f) +
-                            1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
-          const float rad2 = rad * rad;
-          uint32_t head = 0, tail = 0;   // wave-uniform queue cursors
+          const float hrad = (float)hl * (1.0f + 1e-5f) +
+                             1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
+          uint32_t head = 0, tail = 0, ha = 0, ta = 0;   // wave-uniform queue cursors
           // one batch of up to 64 queued jobs, job head + lane on this lane:
           // a job is (element, source run); its lane runs the exact test of
           // the element on each of the run's nrecv pairs (pair q0 + k has
@@ -737,36 +733,46 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               }
             }
           };
+          // the round-cone filter over up to 64 jobs of the first queue (job
+          // ha + lane on this lane); the survivors go to the exact tests
+          auto filter_jobs = [&](uint32_t cnt) {
+            const bool mine = (uint32_t)lane < cnt;
+            const uint16_t job = QA[(ha + (uint32_t)lane) & (kJobQ - 1)];
+            const int L = mine ? (int)(job >> 8) : lane;
+            const float vp[3] = {__shfl(pr[0], L), __shfl(pr[1], L), __shfl(pr[2], L)};
+            const float vh = __shfl(hrad, L);
+            const bool keep = mine && elem_run_cone(vp, vh, RT, Rm, (int)(job & 0xFFu));
+            const uint64_t m = ballot64(keep);
+            if (keep) Q[(tail + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = job;
+            tail += (uint32_t)__popcll(m);
+            wave_lds_sync();
+            while (tail - head >= 64u) {
+              run_jobs(64u);
+              head += 64u;
+            }
+          };
           // the wavefront's elements as one sphere first: only the source
           // runs that may reach it go through the per-element tests
-          elem_group(pr, rad, has, egrp[wv]);
+          elem_group(pr, hrad, has, egrp[wv]);
           const int nruns = qend / nrecv;
           for (int k0 = 0; k0 < nruns; k0 += 64) {
-            uint64_t gm = group_runs(egrp[wv], pd_jr, pd_jinv, pd_jlim, k0, nruns, nrecv);
+            uint64_t gm = group_runs(egrp[wv], RT, Rm, k0, nruns, nrecv);
             while (gm != 0ull) {
               const int q0 = (k0 + (int)__builtin_ctzll(gm)) * nrecv;
               gm &= gm - 1ull;
-              bool pass = false;
-              if (has) {
-                const float s0 = pd_jr[q0][0], s1 = pd_jr[q0][1], s2 = pd_jr[q0][2];
-                const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
-                float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * pd_jinv[q0];
-                tt = fminf(1.0f, fmaxf(0.0f, tt));
-                const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
-                pass = f0 * f0 + f1 * f1 + f2 * f2 <= pd_jlim[q0] * (1.0f + 1e-4f) &&
-                       d0 * d0 + d1 * d1 + d2 * d2 <= rad2;
-              }
+              const bool pass = has && elem_run_test(pr, hrad, RT, Rm, q0);
               const uint64_t m = ballot64(pass);
               if (m == 0ull) continue;
-              if (pass) Q[(tail + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((lane << 8) | q0);
-              tail += (uint32_t)__popcll(m);
+              if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((lane << 8) | q0);
+              ta += (uint32_t)__popcll(m);
               wave_lds_sync();
-              while (tail - head >= 64u) {
-                run_jobs(64u);
-                head += 64u;
+              while (ta - ha >= 64u) {
+                filter_jobs(64u);
+                ha += 64u;
               }
             }
           }
+          if (ta > ha) filter_jobs(ta - ha);
           if (tail > head) run_jobs(tail - head);
           wave_lds_sync();
         }

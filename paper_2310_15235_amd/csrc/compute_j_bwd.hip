@@ -136,9 +136,9 @@ template <int NB> struct PairTile {
   float gt[kNT][NB];
   uint32_t j[kNT];
   uint8_t i[kNT], valid[kNT];
-  // the source of each pair relative to the bucket centre, 1/|.|^2 and the
-  // square of (|.| + the receivers' reach): every receiver's segment to the
-  // source lies within that reach of the centre's segment
+  // the source of each pair relative to the bucket centre and its run's
+  // test values (RunTab): every receiver's segment to the source lies within
+  // the round cone of the receivers' reach around the centre's segment
   float jr[kNT][3], jinv[kNT], jlim[kNT];
 };
 
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
   __shared__ float gw[kRMax][NB], rinvh[kRMax];
   __shared__ double red[kNT][NB];
   __shared__ double redh[kNT];
-  __shared__ uint16_t jobq[kNT / 64][kJobQ];      // per wavefront: (element lane, source run)
+  __shared__ uint16_t jobq[kNT / 64][2][kJobQ];   // per wavefront: (element lane, source run)
   __shared__ float eacc[kNT / 64][64][NB + 1];     // per wavefront: element sums
   __shared__ float egrp[kNT / 64][5];              // per wavefront: element sphere
   const int lane = t & 63, wv = t >> 6;
@@ -264,14 +264,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
       PT.rij2[t] = rij2;
       PT.inv2[t] = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
       {
-        const float j0 = (float)(xj0 - c[0]), j1 = (float)(xj1 - c[1]), j2 = (float)(xj2 - c[2]);
-        const float jj = j0 * j0 + j1 * j1 + j2 * j2;
-        const float lim = (sqrtf(jj) + reach) * (1.0f + 1e-5f);
-        PT.jr[t][0] = j0;
-        PT.jr[t][1] = j1;
-        PT.jr[t][2] = j2;
-        PT.jinv[t] = jj > 0.0f ? 1.0f / jj : 0.0f;
-        PT.jlim[t] = lim * lim;
+        const float js[3] = {(float)(xj0 - c[0]), (float)(xj1 - c[1]), (float)(xj2 - c[2])};
+        run_tab_entry(js, reach, PT.jr, PT.jinv, PT.jlim, t);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) PT.gt[t][b] = gt[b];
@@ -281,12 +275,17 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
       __syncthreads();
       if (__syncthreads_or(valid)) {
         const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
-        uint16_t* Q = jobq[wv];
+        const RunTab RT{PT.jr, PT.jinv, PT.jlim};
+        const float Rm = reach * (1.0f + 1e-5f);
+        uint16_t* QA = jobq[wv][0];   // per-element test passes
+        uint16_t* Q = jobq[wv][1];    // round-cone passes: exact tests
         float (*A)[NB + 1] = eacc[wv];
         // ---- p-p elements against the staged pairs.  Each lane owns an
-        // element; per source run it tests the element against the centre's
-        // segment to the source grown by the receivers' reach (and the
-        // element no farther from the source than the farthest receiver).
+        // element; per source run it tests the element against the
+        // cylinder of the receivers' reach around the centre's segment to
+        // the source and the element no farther from the source than the
+        // farthest receiver; passing jobs are filtered by the round cone
+        // (the reach at the centre, none at the source).
         // Passing (element, source run) jobs are queued per wavefront and
         // run 64 at a time, so the exact FP64 tests keep every lane busy.
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
@@ -302,15 +301,13 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
           float kap[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
-          const float hf = (float)hl;
           const float pr[3] = {(float)((double)ux - c[0]), (float)((double)uy - c[1]),
                                (float)((double)uz - c[2])};
-          const float rad = (hf + reach) * (1.0f + 1e-5f) +
-                            1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
-          const float rad2 = rad * rad;
+          const float hrad = (float)hl * (1.0f + 1e-5f) +
+                             1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
 #pragma unroll
           for (int b = 0; b <= NB; ++b) A[lane][b] = 0.0f;
-          uint32_t head = 0, tail = 0;   // wave-uniform queue cursors
+          uint32_t head = 0, tail = 0, ha = 0, ta = 0;   // wave-uniform queue cursors
 
           // one batch of up to 64 queued jobs, job head + lane on this lane:
           // a job is (element, source run); its lane runs the exact test of
@@ -371,36 +368,46 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
               }
             }
           };
+          // the round-cone filter over up to 64 jobs of the first queue (job
+          // ha + lane on this lane); the survivors go to the exact tests
+          auto filter_jobs = [&](uint32_t cnt) {
+            const bool mine = (uint32_t)lane < cnt;
+            const uint16_t job = QA[(ha + (uint32_t)lane) & (kJobQ - 1)];
+            const int L = mine ? (int)(job >> 8) : lane;
+            const float vp[3] = {__shfl(pr[0], L), __shfl(pr[1], L), __shfl(pr[2], L)};
+            const float vh = __shfl(hrad, L);
+            const bool keep = mine && elem_run_cone(vp, vh, RT, Rm, (int)(job & 0xFFu));
+            const uint64_t m = ballot64(keep);
+            if (keep) Q[(tail + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = job;
+            tail += (uint32_t)__popcll(m);
+            wave_lds_sync();
+            while (tail - head >= 64u) {
+              run_jobs(64u);
+              head += 64u;
+            }
+          };
           // the wavefront's elements as one sphere first: only the source
           // runs that may reach it go through the per-element tests
-          elem_group(pr, rad, has, egrp[wv]);
+          elem_group(pr, hrad, has, egrp[wv]);
           const int nruns = qend / nrecv;
           for (int k0 = 0; k0 < nruns; k0 += 64) {
-            uint64_t gm = group_runs(egrp[wv], PT.jr, PT.jinv, PT.jlim, k0, nruns, nrecv);
+            uint64_t gm = group_runs(egrp[wv], RT, Rm, k0, nruns, nrecv);
             while (gm != 0ull) {
               const int q0 = (k0 + (int)__builtin_ctzll(gm)) * nrecv;
               gm &= gm - 1ull;
-              bool pass = false;
-              if (has) {
-                const float s0 = PT.jr[q0][0], s1 = PT.jr[q0][1], s2 = PT.jr[q0][2];
-                const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
-                float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * PT.jinv[q0];
-                tt = fminf(1.0f, fmaxf(0.0f, tt));
-                const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
-                pass = f0 * f0 + f1 * f1 + f2 * f2 <= PT.jlim[q0] * (1.0f + 1e-4f) &&
-                       d0 * d0 + d1 * d1 + d2 * d2 <= rad2;
-              }
+              const bool pass = has && elem_run_test(pr, hrad, RT, Rm, q0);
               const uint64_t m = ballot64(pass);
               if (m == 0ull) continue;
-              if (pass) Q[(tail + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((lane << 8) | q0);
-              tail += (uint32_t)__popcll(m);
+              if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((lane << 8) | q0);
+              ta += (uint32_t)__popcll(m);
               wave_lds_sync();
-              while (tail - head >= 64u) {
-                run_jobs(64u);
-                head += 64u;
+              while (ta - ha >= 64u) {
+                filter_jobs(64u);
+                ha += 64u;
               }
             }
           }
+          if (ta > ha) filter_jobs(ta - ha);
           if (tail > head) run_jobs(tail - head);
           wave_lds_sync();
           if (has) {

@@ -392,15 +392,69 @@ __device__ inline float wave_fmax(float v) {
   return v;
 }
 
+// Per source run of an element-major p-p sweep (LDS, one entry per pair,
+// read at the run's first pair): s = jr the source relative to the bucket
+// centre, jinv = 1/|s|^2 and jlim the square of (|s| + the receivers'
+// reach).
+struct RunTab {
+  const float (*jr)[3];
+  const float *jinv, *jlim;
+};
+
+__device__ inline void run_tab_entry(const float s[3], float reach, float (*jr)[3], float* jinv,
+                                     float* jlim, int t) {
+  const float L2 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
+  const float lim = (sqrtf(L2) + reach) * (1.0f + 1e-5f);
+  jr[t][0] = s[0];
+  jr[t][1] = s[1];
+  jr[t][2] = s[2];
+  jinv[t] = L2 > 0.0f ? 1.0f / L2 : 0.0f;
+  jlim[t] = lim * lim;
+}
+
+// Whether p comes within A - R u of the point u s of the segment from the
+// origin to s, for some u in [0, 1]: the round cone swept by spheres shrinking
+// from radius A at the origin to A - R at s.  Every segment from a point
+// within R of the origin to s lies inside the cone of radius R (1 - u)
+// around u s, so an element of size h can touch one only if it passes with
+// A = h + R.  min over u of |p - u s| + R u is convex; its free minimum is
+// at u* = t0 - d m (t0 the projection parameter, d the distance to the
+// line, m = R / (|s| sqrt(|s|^2 - R^2))) with value d sqrt(1 - R^2/|s|^2)
+// + R t0, else at an end (u = 0: |p|, u = 1: |p - s| + R); when |s| <= R it
+// is at u = 0.  All in squares (no square roots); A is widened by 1e-4
+// relative plus tol for FP32 rounding.
+__device__ inline bool round_cone(const float p[3], const float s[3], float jinv, float R, float A,
+                                  float tol) {
+  const float Ap = A * (1.0f + 1e-4f) + tol;
+  const float pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  const float f0 = p[0] - s[0], f1 = p[1] - s[1], f2 = p[2] - s[2];
+  const float fs = f0 * f0 + f1 * f1 + f2 * f2;
+  const float L2 = jinv > 0.0f ? 1.0f / jinv : 0.0f, R2 = R * R;
+  const bool cone = L2 > R2;
+  const float k2 = cone ? 1.0f - R2 * jinv : 0.0f;          // 1 - R^2/|s|^2
+  const float m2 = cone ? R2 * jinv / (L2 - R2) : 0.0f;    // m^2
+  const float t0 = (p[0] * s[0] + p[1] * s[1] + p[2] * s[2]) * jinv;
+  const float d0 = p[0] - t0 * s[0], d1 = p[1] - t0 * s[1], d2 = p[2] - t0 * s[2];
+  const float dp2 = d0 * d0 + d1 * d1 + d2 * d2;
+  const float dm = dp2 * m2;
+  const bool lo = !cone || t0 < 0.0f || t0 * t0 < dm;
+  const bool hi = t0 > 1.0f && (t0 - 1.0f) * (t0 - 1.0f) > dm;
+  const float B = Ap - R, e = Ap - R * t0;
+  const bool at0 = pp <= Ap * Ap;
+  const bool at1 = B >= 0.0f && fs <= B * B;
+  const bool mid = e >= 0.0f && dp2 * k2 <= e * e;
+  return lo ? at0 : (hi ? at1 : mid);
+}
+
 // The p-p elements of a wavefront in an element-major sweep (one per lane
-// with `has`, positions pr relative to the bucket centre, each with its test
-// radius rad = its size + the receivers' reach) as one sphere, written to
-// the wavefront's G[5]: centre g = G[0..2] (the middle of their box), G[3] =
-// rp the farthest position from g, G[4] = rr the farthest position plus its
-// radius (< 0 when no lane holds an element).  The elements of a
-// slot-ordered p-p list are spatially close in runs of 64, so most source
-// runs miss the sphere and skip the per-element tests.
-__device__ inline void elem_group(const float pr[3], float rad, bool has, float* G) {
+// with `has`, positions pr relative to the bucket centre, each with its
+// size hrad, margins included) as one sphere, written to the wavefront's
+// G[5]: centre g = G[0..2] (the middle of their box), G[3] = rp the farthest
+// position from g, G[4] = rr the farthest position plus its size (< 0 when no
+// lane holds an element).  The elements of a slot-ordered p-p list are
+// spatially close in runs of 64, so most source runs miss the sphere and
+// skip the per-element tests.
+__device__ inline void elem_group(const float pr[3], float hrad, bool has, float* G) {
   float g[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -408,7 +462,7 @@ __device__ inline void elem_group(const float pr[3], float rad, bool has, float*
   const float d0 = pr[0] - g[0], d1 = pr[1] - g[1], d2 = pr[2] - g[2];
   const float dl = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
   const float rp = wave_fmax(has ? dl : -1.0f);
-  const float rr = wave_fmax(has ? dl + rad : -1.0f);
+  const float rr = wave_fmax(has ? dl + hrad : -1.0f);
   if ((threadIdx.x & 63) == 0) {
     G[0] = g[0];
     G[1] = g[1];
@@ -419,33 +473,59 @@ __device__ inline void elem_group(const float pr[3], float rad, bool has, float*
   wave_lds_sync();
 }
 
-// The source runs k0 + k (k < 64, lane k; pair (k0 + k) * nrecv) whose
-// centre segment to the source, s = jr, comes within rr of the sphere's
-// centre and whose source lies within sqrt(jlim) + rp of it: the runs for
-// which some element of the group can pass the per-element test (distance
-// to the segment within rad, distance to the source within sqrt(jlim)).
-// Margins of 1e-4 relative and 1e-5 of the coordinates' size cover FP32
-// rounding on both sides.  Wave-uniform mask over k.
-__device__ inline uint64_t group_runs(const float* G, const float (*jr)[3], const float* jinv,
-                                      const float* jlim, int k0, int nruns, int nrecv) {
+// The source runs k0 + k (k < 64, lane k; pair (k0 + k) * nrecv) for which
+// some element of the group can pass the per-element test: the sphere's
+// centre within the round cone of radius rr + R(1 - u) (R the reach, with
+// its margin) and within sqrt(jlim) + rp of the source.  Margins of 1e-4
+// relative and 1e-5 of the coordinates' size cover FP32 rounding on both
+// sides.  Wave-uniform mask over k.
+__device__ inline uint64_t group_runs(const float* G, const RunTab& RT, float R, int k0, int nruns,
+                                      int nrecv) {
   const float rr = G[4];
   if (rr < 0.0f) return 0ull;
   const int k = k0 + (int)(threadIdx.x & 63);
   bool pass = false;
   if (k < nruns) {
-    const float g0 = G[0], g1 = G[1], g2 = G[2], rp = G[3];
+    const float g[3] = {G[0], G[1], G[2]};
+    const float rp = G[3];
     const int q = k * nrecv;
-    const float s0 = jr[q][0], s1 = jr[q][1], s2 = jr[q][2];
-    const float tol = 1e-5f * (fabsf(g0) + fabsf(g1) + fabsf(g2) + fabsf(s0) + fabsf(s1) + fabsf(s2));
-    float tt = (g0 * s0 + g1 * s1 + g2 * s2) * jinv[q];
-    tt = fminf(1.0f, fmaxf(0.0f, tt));
-    const float d0 = g0 - tt * s0, d1 = g1 - tt * s1, d2 = g2 - tt * s2;
-    const float r1 = rr * (1.0f + 1e-4f) + tol;
-    const float f0 = g0 - s0, f1 = g1 - s1, f2 = g2 - s2;
-    const float r2 = (sqrtf(jlim[q]) + rp) * (1.0f + 1e-4f) + tol;
-    pass = d0 * d0 + d1 * d1 + d2 * d2 <= r1 * r1 && f0 * f0 + f1 * f1 + f2 * f2 <= r2 * r2;
+    const float s[3] = {RT.jr[q][0], RT.jr[q][1], RT.jr[q][2]};
+    const float tol = 1e-5f * (fabsf(g[0]) + fabsf(g[1]) + fabsf(g[2]) + fabsf(s[0]) +
+                               fabsf(s[1]) + fabsf(s[2]));
+    const float f0 = g[0] - s[0], f1 = g[1] - s[1], f2 = g[2] - s[2];
+    const float r2 = (sqrtf(RT.jlim[q]) + rp) * (1.0f + 1e-4f) + tol;
+    pass = f0 * f0 + f1 * f1 + f2 * f2 <= r2 * r2 &&
+           round_cone(g, s, RT.jinv[q], R, rr * (1.0f + 1e-4f) + R, tol);
   }
   return ballot64(pass);
+}
+
+// The per-element test of an element-major sweep against source run q (its
+// first pair): no farther from the source than sqrt(jlim), and within hrad
+// + R of the centre's segment to the source (the cylinder around the round
+// cone, cheaper to test); a superset of the elements the exact test finds
+// on any of the run's pairs.
+__device__ inline bool elem_run_test(const float pr[3], float hrad, const RunTab& RT, float R,
+                                     int q) {
+  const float s0 = RT.jr[q][0], s1 = RT.jr[q][1], s2 = RT.jr[q][2];
+  const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
+  float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * RT.jinv[q];
+  tt = fminf(1.0f, fmaxf(0.0f, tt));
+  const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
+  const float rad = hrad + R;
+  return f0 * f0 + f1 * f1 + f2 * f2 <= RT.jlim[q] * (1.0f + 1e-4f) &&
+         d0 * d0 + d1 * d1 + d2 * d2 <= rad * rad;
+}
+
+// The queued (element, source run) jobs that also pass the round cone
+// (elements within hrad + R (1 - u) of the centre's segment): the filter
+// between the per-element test and the exact tests.
+__device__ inline bool elem_run_cone(const float pr[3], float hrad, const RunTab& RT, float R,
+                                     int q) {
+  const float s[3] = {RT.jr[q][0], RT.jr[q][1], RT.jr[q][2]};
+  const float tol = 1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]) + fabsf(s[0]) +
+                             fabsf(s[1]) + fabsf(s[2]));
+  return round_cone(pr, s, RT.jinv[q], R, hrad + R, tol);
 }
 
 template <int NB> struct NearTile {
