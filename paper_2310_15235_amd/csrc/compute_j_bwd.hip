@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
   __shared__ double redh[kNT];
   __shared__ uint16_t jobq[kNT / 64][2][kJobQ];   // per wavefront: (element lane, source run)
   __shared__ float eacc[kNT / 64][64][NB + 1];     // per wavefront: element sums
-  __shared__ float egrp[kNT / 64][5];              // per wavefront: element sphere
+  __shared__ float egrp[kNT / 64][4][5];   // per wavefront: element spheres of its quarters
   const int lane = t & 63, wv = t >> 6;
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
@@ -390,15 +390,21 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
           // runs that may reach it go through the per-element tests
           elem_group(pr, hrad, has, egrp[wv]);
           const int nruns = qend / nrecv;
-          for (int k0 = 0; k0 < nruns; k0 += 64) {
+          for (int k0 = 0; k0 < nruns; k0 += kElemGroup) {
             uint64_t gm = group_runs(egrp[wv], RT, Rm, k0, nruns, nrecv);
             while (gm != 0ull) {
-              const int q0 = (k0 + (int)__builtin_ctzll(gm)) * nrecv;
-              gm &= gm - 1ull;
-              const bool pass = has && elem_run_test(pr, hrad, RT, Rm, q0);
+              // four (quarter, run) pairs at a time, 16 lanes each: lane
+              // 16 i + j tests element j of its pair's quarter
+              const int pq = take_quarter_pair(&gm);
+              const int eL = pq >= 0 ? (pq >> 4) * kElemGroup + (lane & (kElemGroup - 1)) : lane;
+              const int q0 = pq >= 0 ? (k0 + (pq & (kElemGroup - 1))) * nrecv : 0;
+              const float vp[3] = {__shfl(pr[0], eL), __shfl(pr[1], eL), __shfl(pr[2], eL)};
+              const float vh = __shfl(hrad, eL);
+              const bool vhas = __shfl((int)has, eL) != 0;
+              const bool pass = pq >= 0 && vhas && elem_run_test(vp, vh, RT, Rm, q0);
               const uint64_t m = ballot64(pass);
               if (m == 0ull) continue;
-              if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((lane << 8) | q0);
+              if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((eL << 8) | q0);
               ta += (uint32_t)__popcll(m);
               wave_lds_sync();
               while (ta - ha >= 64u) {

@@ -448,46 +448,62 @@ __device__ inline bool round_cone(const float p[3], const float s[3], float jinv
 
 // The p-p elements of a wavefront in an element-major sweep (one per lane
 // with `has`, positions pr relative to the bucket centre, each with its
-// size hrad, margins included) as one sphere, written to the wavefront's
-// G[5]: centre g = G[0..2] (the middle of their box), G[3] = rp the farthest
-// position from g, G[4] = rr the farthest position plus its size (< 0 when no
-// lane holds an element).  The elements of a slot-ordered p-p list are
-// spatially close in runs of 64, so most source runs miss the sphere and
-// skip the per-element tests.
-__device__ inline void elem_group(const float pr[3], float hrad, bool has, float* G) {
+// size hrad, margins included) as one sphere per quarter-wavefront (16
+// lanes), written to G[4][5]: centre g = G[q][0..2] (the middle of their
+// box), G[q][3] = rp the farthest position from g, G[q][4] = rr the
+// farthest position plus its size (< 0 when no lane of the quarter holds an
+// element).  The elements of a slot-ordered p-p list are spatially close in
+// runs of 16, so most source runs miss a quarter's sphere and skip its
+// per-element tests.
+constexpr int kElemGroup = 16;
+__device__ inline float quarter_fmin(float v) {
+#pragma unroll
+  for (int o = kElemGroup / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline float quarter_fmax(float v) {
+#pragma unroll
+  for (int o = kElemGroup / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline void elem_group(const float pr[3], float hrad, bool has, float (*G)[5]) {
   float g[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
-    g[a] = 0.5f * (wave_fmin(has ? pr[a] : INFINITY) + wave_fmax(has ? pr[a] : -INFINITY));
+    g[a] = 0.5f * (quarter_fmin(has ? pr[a] : INFINITY) + quarter_fmax(has ? pr[a] : -INFINITY));
   const float d0 = pr[0] - g[0], d1 = pr[1] - g[1], d2 = pr[2] - g[2];
   const float dl = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-  const float rp = wave_fmax(has ? dl : -1.0f);
-  const float rr = wave_fmax(has ? dl + hrad : -1.0f);
-  if ((threadIdx.x & 63) == 0) {
-    G[0] = g[0];
-    G[1] = g[1];
-    G[2] = g[2];
-    G[3] = rp;
-    G[4] = rr;
+  const float rp = quarter_fmax(has ? dl : -1.0f);
+  const float rr = quarter_fmax(has ? dl + hrad : -1.0f);
+  const int lane = (int)(threadIdx.x & 63);
+  if ((lane & (kElemGroup - 1)) == 0) {
+    float* q = G[lane / kElemGroup];
+    q[0] = g[0];
+    q[1] = g[1];
+    q[2] = g[2];
+    q[3] = rp;
+    q[4] = rr;
   }
   wave_lds_sync();
 }
 
-// The source runs k0 + k (k < 64, lane k; pair (k0 + k) * nrecv) for which
-// some element of the group can pass the per-element test: the sphere's
-// centre within the round cone of radius rr + R(1 - u) (R the reach, with
-// its margin) and within sqrt(jlim) + rp of the source.  Margins of 1e-4
+// The (quarter, source run) pairs, bit 16 quarter + k for run k0 + k (k <
+// 16; lane 16 quarter + k tests it; pair (k0 + k) * nrecv), for which some
+// element of the quarter can pass the per-element test: the sphere's centre
+// within the round cone of radius rr + R(1 - u) (R the reach, with its
+// margin) and within sqrt(jlim) + rp of the source.  Margins of 1e-4
 // relative and 1e-5 of the coordinates' size cover FP32 rounding on both
-// sides.  Wave-uniform mask over k.
-__device__ inline uint64_t group_runs(const float* G, const RunTab& RT, float R, int k0, int nruns,
-                                      int nrecv) {
-  const float rr = G[4];
-  if (rr < 0.0f) return 0ull;
-  const int k = k0 + (int)(threadIdx.x & 63);
+// sides.  Wave-uniform mask.
+__device__ inline uint64_t group_runs(const float (*G)[5], const RunTab& RT, float R, int k0,
+                                      int nruns, int nrecv) {
+  const int lane = (int)(threadIdx.x & 63);
+  const float* Gq = G[lane / kElemGroup];
+  const int k = k0 + (lane & (kElemGroup - 1));
+  const float rr = Gq[4];
   bool pass = false;
-  if (k < nruns) {
-    const float g[3] = {G[0], G[1], G[2]};
-    const float rp = G[3];
+  if (k < nruns && rr >= 0.0f) {
+    const float g[3] = {Gq[0], Gq[1], Gq[2]};
+    const float rp = Gq[3];
     const int q = k * nrecv;
     const float s[3] = {RT.jr[q][0], RT.jr[q][1], RT.jr[q][2]};
     const float tol = 1e-5f * (fabsf(g[0]) + fabsf(g[1]) + fabsf(g[2]) + fabsf(s[0]) +
@@ -498,6 +514,22 @@ __device__ inline uint64_t group_runs(const float* G, const RunTab& RT, float R,
            round_cone(g, s, RT.jinv[q], R, rr * (1.0f + 1e-4f) + R, tol);
   }
   return ballot64(pass);
+}
+
+// Takes up to four set bits from the wave-uniform mask *gm (lowest first)
+// and gives lane 16 i + j the i-th of them (-1 past the last): the (quarter,
+// run) pair whose element j that lane tests.
+__device__ inline int take_quarter_pair(uint64_t* gm) {
+  uint64_t m = *gm;
+  int b[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    b[i] = m ? (int)__builtin_ctzll(m) : -1;
+    m &= m - 1ull;
+  }
+  *gm = m;
+  const int i = (int)(threadIdx.x & 63) / kElemGroup;
+  return i == 0 ? b[0] : i == 1 ? b[1] : i == 2 ? b[2] : b[3];
 }
 
 // The per-element test of an element-major sweep against source run q (its
