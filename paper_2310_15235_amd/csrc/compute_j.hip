@@ -569,9 +569,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   __shared__ uint32_t nrecv_s, s_item;
   // each thread's pair, for lanes that test it on the thread's behalf; the
   // optical depths gathered for it by other lanes (tacc)
-  __shared__ double pd_xj[kNT][3], pd_r2[kNT], pd_inv2[kNT];
+  __shared__ float pd_xj[kNT][3];   // FP32 as stored, widened where read
+  __shared__ double pd_r2[kNT], pd_inv2[kNT];
   __shared__ uint32_t pd_j[kNT];
-  __shared__ float pd_jr[kNT][3], pd_jinv[kNT], pd_jlim[kNT];
+  __shared__ float pd_jr[kNT][3], pd_jinv[kNT], pd_jlim[kNT], pd_k2[kNT], pd_m2[kNT];
   __shared__ uint8_t pd_valid[kNT];
   __shared__ float tacc[kNT][NB];
   __shared__ uint8_t nlist[kNT / 64][64];
@@ -648,9 +649,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
         tau[b] = 0.0f;
         tacc[t][b] = 0.0f;
       }
-      pd_xj[t][0] = xj0;
-      pd_xj[t][1] = xj1;
-      pd_xj[t][2] = xj2;
+      pd_xj[t][0] = (float)xj0;   // exact: the positions are FP32
+      pd_xj[t][1] = (float)xj1;
+      pd_xj[t][2] = (float)xj2;
       pd_r2[t] = rij2;
       pd_inv2[t] = inv2;
       pd_j[t] = j;
@@ -665,9 +666,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
         // with the exact FP64 test of the pair-major sweep on each pair of
         // the run, LDS atomics adding into tacc.  Both tests are supersets
         // of the exact test's passes
-        run_tab_entry(jr, reach, pd_jr, pd_jinv, pd_jlim, t);
+        run_tab_entry(jr, reach, pd_jr, pd_jinv, pd_jlim, pd_k2, pd_m2, t);
         pd_valid[t] = (ok && rij2 > 0.0) ? 1u : 0u;
-        const RunTab RT{pd_jr, pd_jinv, pd_jlim};
+        const RunTab RT{pd_jr, pd_jinv, pd_jlim, pd_k2, pd_m2};
         const float Rm = reach * (1.0f + 1e-5f);
         __syncthreads();
         const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
@@ -709,7 +710,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
 #pragma unroll
             for (int b = 0; b < NB; ++b) vkap[b] = __shfl(kap[b], L);
             if (mine) {
-              const double qx0 = pd_xj[q0][0], qx1 = pd_xj[q0][1], qx2 = pd_xj[q0][2];
+              const double qx0 = (double)pd_xj[q0][0], qx1 = (double)pd_xj[q0][1],
+                           qx2 = (double)pd_xj[q0][2];
               const uint32_t qj = pd_j[q0];
               const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
               const double ff = f0 * f0 + f1 * f1 + f2 * f2;
@@ -832,7 +834,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               for (int b = 0; b < NB; ++b) ct[b] = 0.0f;
               if (serve && u < u1) {
                 const RecvInfo& rq = recv[ts % nrecv];
-                const double qx0 = pd_xj[ts][0], qx1 = pd_xj[ts][1], qx2 = pd_xj[ts][2];
+                const double qx0 = (double)pd_xj[ts][0], qx1 = (double)pd_xj[ts][1],
+                             qx2 = (double)pd_xj[ts][2];
                 const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
                 const double ux = S.x[u], uy = S.y[u], uz = S.z[u];
                 const double f0 = ux - qx0, f1 = uy - qx1, f2 = uz - qx2;

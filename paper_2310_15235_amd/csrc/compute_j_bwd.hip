@@ -131,7 +131,7 @@ __device__ inline void load_receiver_adjoints(const DevTree& T, const double* gJ
 // dh_l += gt_b kappa_lb dSigma_l/dh_l in registers.  The p-p part of the
 // raw J goes to jraw per receiver.
 template <int NB> struct PairTile {
-  double xj[kNT][3];
+  float xj[kNT][3];   // FP32 as stored, widened where read
   double rij2[kNT], inv2[kNT];
   float gt[kNT][NB];
   uint32_t j[kNT];
@@ -139,7 +139,7 @@ template <int NB> struct PairTile {
   // the source of each pair relative to the bucket centre and its run's
   // test values (RunTab): every receiver's segment to the source lies within
   // the round cone of the receivers' reach around the centre's segment
-  float jr[kNT][3], jinv[kNT], jlim[kNT];
+  float jr[kNT][3], jinv[kNT], jlim[kNT], k2[kNT], m2[kNT];
 };
 
 
@@ -258,14 +258,14 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
       if (ok) {
         valid = valid && rij2 > 0.0;
       }
-      PT.xj[t][0] = xj0;
-      PT.xj[t][1] = xj1;
-      PT.xj[t][2] = xj2;
+      PT.xj[t][0] = (float)xj0;   // exact: the positions are FP32
+      PT.xj[t][1] = (float)xj1;
+      PT.xj[t][2] = (float)xj2;
       PT.rij2[t] = rij2;
       PT.inv2[t] = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
       {
         const float js[3] = {(float)(xj0 - c[0]), (float)(xj1 - c[1]), (float)(xj2 - c[2])};
-        run_tab_entry(js, reach, PT.jr, PT.jinv, PT.jlim, t);
+        run_tab_entry(js, reach, PT.jr, PT.jinv, PT.jlim, PT.k2, PT.m2, t);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) PT.gt[t][b] = gt[b];
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
       __syncthreads();
       if (__syncthreads_or(valid)) {
         const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
-        const RunTab RT{PT.jr, PT.jinv, PT.jlim};
+        const RunTab RT{PT.jr, PT.jinv, PT.jlim, PT.k2, PT.m2};
         const float Rm = reach * (1.0f + 1e-5f);
         uint16_t* QA = jobq[wv][0];   // per-element test passes
         uint16_t* Q = jobq[wv][1];    // round-cone passes: exact tests
@@ -328,7 +328,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
 #pragma unroll
             for (int b = 0; b < NB; ++b) vkap[b] = __shfl(kap[b], L);
             if (mine) {
-              const double qx0 = PT.xj[q0][0], qx1 = PT.xj[q0][1], qx2 = PT.xj[q0][2];
+              const double qx0 = (double)PT.xj[q0][0], qx1 = (double)PT.xj[q0][1],
+                           qx2 = (double)PT.xj[q0][2];
               const uint32_t qj = PT.j[q0];
               const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
               const double ff = f0 * f0 + f1 * f1 + f2 * f2;

@@ -394,22 +394,25 @@ __device__ inline float wave_fmax(float v) {
 
 // Per source run of an element-major p-p sweep (LDS, one entry per pair,
 // read at the run's first pair): s = jr the source relative to the bucket
-// centre, jinv = 1/|s|^2 and jlim the square of (|s| + the receivers'
-// reach).
+// centre, jinv = 1/|s|^2, lim = |s| + the receivers' reach R (a 1e-5
+// margin), and the round cone's k2 = 1 - R^2/|s|^2 and m2 = R^2 / (|s|^2
+// (|s|^2 - R^2)), m2 < 0 when |s| <= R.
 struct RunTab {
   const float (*jr)[3];
-  const float *jinv, *jlim;
+  const float *jinv, *lim, *k2, *m2;
 };
 
 __device__ inline void run_tab_entry(const float s[3], float reach, float (*jr)[3], float* jinv,
-                                     float* jlim, int t) {
+                                     float* lim, float* k2, float* m2, int t) {
   const float L2 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
-  const float lim = (sqrtf(L2) + reach) * (1.0f + 1e-5f);
+  const float R = reach * (1.0f + 1e-5f), R2 = R * R;
   jr[t][0] = s[0];
   jr[t][1] = s[1];
   jr[t][2] = s[2];
   jinv[t] = L2 > 0.0f ? 1.0f / L2 : 0.0f;
-  jlim[t] = lim * lim;
+  lim[t] = (sqrtf(L2) + reach) * (1.0f + 1e-5f);
+  k2[t] = L2 > R2 ? (L2 - R2) / L2 : 0.0f;
+  m2[t] = L2 > R2 ? R2 / (L2 * (L2 - R2)) : -1.0f;
 }
 
 // Whether p comes within A - R u of the point u s of the segment from the
@@ -423,21 +426,17 @@ __device__ inline void run_tab_entry(const float s[3], float reach, float (*jr)[
 // + R t0, else at an end (u = 0: |p|, u = 1: |p - s| + R); when |s| <= R it
 // is at u = 0.  All in squares (no square roots); A is widened by 1e-4
 // relative plus tol for FP32 rounding.
-__device__ inline bool round_cone(const float p[3], const float s[3], float jinv, float R, float A,
-                                  float tol) {
+__device__ inline bool round_cone(const float p[3], const float s[3], float jinv, float k2, float m2,
+                                  float R, float A, float tol) {
   const float Ap = A * (1.0f + 1e-4f) + tol;
   const float pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
   const float f0 = p[0] - s[0], f1 = p[1] - s[1], f2 = p[2] - s[2];
   const float fs = f0 * f0 + f1 * f1 + f2 * f2;
-  const float L2 = jinv > 0.0f ? 1.0f / jinv : 0.0f, R2 = R * R;
-  const bool cone = L2 > R2;
-  const float k2 = cone ? 1.0f - R2 * jinv : 0.0f;          // 1 - R^2/|s|^2
-  const float m2 = cone ? R2 * jinv / (L2 - R2) : 0.0f;    // m^2
   const float t0 = (p[0] * s[0] + p[1] * s[1] + p[2] * s[2]) * jinv;
   const float d0 = p[0] - t0 * s[0], d1 = p[1] - t0 * s[1], d2 = p[2] - t0 * s[2];
   const float dp2 = d0 * d0 + d1 * d1 + d2 * d2;
   const float dm = dp2 * m2;
-  const bool lo = !cone || t0 < 0.0f || t0 * t0 < dm;
+  const bool lo = m2 < 0.0f || t0 < 0.0f || t0 * t0 < dm;
   const bool hi = t0 > 1.0f && (t0 - 1.0f) * (t0 - 1.0f) > dm;
   const float B = Ap - R, e = Ap - R * t0;
   const bool at0 = pp <= Ap * Ap;
@@ -456,14 +455,25 @@ __device__ inline bool round_cone(const float p[3], const float s[3], float jinv
 // runs of 16, so most source runs miss a quarter's sphere and skip its
 // per-element tests.
 constexpr int kElemGroup = 16;
+// Minimum / maximum over each group of 16 lanes, in every lane of the group,
+// by DPP moves (swap neighbours, swap pairs, mirror half rows, mirror rows).
+// Call with every lane active.
+__device__ inline float dpp_mov(float v, int ctrl) {
+  switch (ctrl) {
+    case 0: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+    case 1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
+    case 2: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
+    default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
+  }
+}
 __device__ inline float quarter_fmin(float v) {
 #pragma unroll
-  for (int o = kElemGroup / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  for (int k = 0; k < 4; ++k) v = fminf(v, dpp_mov(v, k));
   return v;
 }
 __device__ inline float quarter_fmax(float v) {
 #pragma unroll
-  for (int o = kElemGroup / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  for (int k = 0; k < 4; ++k) v = fmaxf(v, dpp_mov(v, k));
   return v;
 }
 __device__ inline void elem_group(const float pr[3], float hrad, bool has, float (*G)[5]) {
@@ -491,7 +501,7 @@ __device__ inline void elem_group(const float pr[3], float hrad, bool has, float
 // 16; lane 16 quarter + k tests it; pair (k0 + k) * nrecv), for which some
 // element of the quarter can pass the per-element test: the sphere's centre
 // within the round cone of radius rr + R(1 - u) (R the reach, with its
-// margin) and within sqrt(jlim) + rp of the source.  Margins of 1e-4
+// margin) and within lim + rp of the source.  Margins of 1e-4
 // relative and 1e-5 of the coordinates' size cover FP32 rounding on both
 // sides.  Wave-uniform mask.
 __device__ inline uint64_t group_runs(const float (*G)[5], const RunTab& RT, float R, int k0,
@@ -509,9 +519,9 @@ __device__ inline uint64_t group_runs(const float (*G)[5], const RunTab& RT, flo
     const float tol = 1e-5f * (fabsf(g[0]) + fabsf(g[1]) + fabsf(g[2]) + fabsf(s[0]) +
                                fabsf(s[1]) + fabsf(s[2]));
     const float f0 = g[0] - s[0], f1 = g[1] - s[1], f2 = g[2] - s[2];
-    const float r2 = (sqrtf(RT.jlim[q]) + rp) * (1.0f + 1e-4f) + tol;
+    const float r2 = (RT.lim[q] + rp) * (1.0f + 1e-4f) + tol;
     pass = f0 * f0 + f1 * f1 + f2 * f2 <= r2 * r2 &&
-           round_cone(g, s, RT.jinv[q], R, rr * (1.0f + 1e-4f) + R, tol);
+           round_cone(g, s, RT.jinv[q], RT.k2[q], RT.m2[q], R, rr * (1.0f + 1e-4f) + R, tol);
   }
   return ballot64(pass);
 }
@@ -533,7 +543,7 @@ __device__ inline int take_quarter_pair(uint64_t* gm) {
 }
 
 // The per-element test of an element-major sweep against source run q (its
-// first pair): no farther from the source than sqrt(jlim), and within hrad
+// first pair): no farther from the source than lim, and within hrad
 // + R of the centre's segment to the source (the cylinder around the round
 // cone, cheaper to test); a superset of the elements the exact test finds
 // on any of the run's pairs.
@@ -544,8 +554,8 @@ __device__ inline bool elem_run_test(const float pr[3], float hrad, const RunTab
   float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * RT.jinv[q];
   tt = fminf(1.0f, fmaxf(0.0f, tt));
   const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
-  const float rad = hrad + R;
-  return f0 * f0 + f1 * f1 + f2 * f2 <= RT.jlim[q] * (1.0f + 1e-4f) &&
+  const float rad = hrad + R, lim = RT.lim[q];
+  return f0 * f0 + f1 * f1 + f2 * f2 <= lim * lim * (1.0f + 1e-4f) &&
          d0 * d0 + d1 * d1 + d2 * d2 <= rad * rad;
 }
 
@@ -557,7 +567,7 @@ __device__ inline bool elem_run_cone(const float pr[3], float hrad, const RunTab
   const float s[3] = {RT.jr[q][0], RT.jr[q][1], RT.jr[q][2]};
   const float tol = 1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]) + fabsf(s[0]) +
                              fabsf(s[1]) + fabsf(s[2]));
-  return round_cone(pr, s, RT.jinv[q], R, hrad + R, tol);
+  return round_cone(pr, s, RT.jinv[q], RT.k2[q], RT.m2[q], R, hrad + R, tol);
 }
 
 template <int NB> struct NearTile {
