@@ -682,8 +682,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
           const float ux = T.x[l], uy = T.y[l], uz = T.z[l];
           const double hl = T.h[l];
           const double h2 = hl * hl;
-          const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-          const float iv = (float)(1.0 / hl);
+          // column density scale 3m/(pi h^2) and 1/h in FP32 (they set the
+          // values added, not the decisions)
+          const float iv = __builtin_amdgcn_rcpf((float)hl);
+          const float sig = (float)(3.0 / kPi) * T.m[l] * iv * iv;
           float kap[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
