@@ -560,7 +560,11 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   // (element-major passes) and the receiver sums share their LDS
   __shared__ union {
     NearTile<NB> S;
-    uint16_t jobq[kNT / 64][2][kJobQ];
+    struct {
+      uint16_t qa[kNT / 64][kJobQ];   // per-element test passes (lane, run)
+      uint32_t xl[kNT / 64][kJobQ];   // round-cone passes: element ...
+      uint8_t xq[kNT / 64][kJobQ];    // ... and run, for the exact tests
+    } JQ;
     double red[kNT][NB];
   } U;
   NearTile<NB>& S = U.S;
@@ -672,71 +676,66 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
         const float Rm = reach * (1.0f + 1e-5f);
         __syncthreads();
         const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
-        uint16_t* QA = U.jobq[wv][0];   // per-element test passes
-        uint16_t* Q = U.jobq[wv][1];    // round-cone passes: exact tests
+        uint16_t* QA = U.JQ.qa[wv];
+        uint32_t* XL = U.JQ.xl[wv];
+        uint8_t* XQ = U.JQ.xq[wv];
+        uint32_t head = 0, tail = 0;   // the exact-test queue, kept across chunks
+        // one batch of up to 64 queued exact-test jobs, job head + lane on
+        // this lane: a job is (element, source run); its lane reads the
+        // element and runs the exact test on each of the run's nrecv pairs
+        // (pair q0 + k has receiver k), the source read once
+        auto run_jobs = [&](uint32_t cnt) {
+          if ((uint32_t)lane < cnt) {
+            const uint32_t slot = (head + (uint32_t)lane) & (kJobQ - 1);
+            const uint32_t vl = XL[slot];
+            const int q0 = XQ[slot];
+            const double vx = (double)T.x[vl], vy = (double)T.y[vl], vz = (double)T.z[vl];
+            const double vhl = T.h[vl];
+            const double vh2 = vhl * vhl;
+            // column density scale 3m/(pi h^2) and 1/h in FP32 (they set the
+            // values added, not the decisions)
+            const float viv = __builtin_amdgcn_rcpf((float)vhl);
+            const float vsig = (float)(3.0 / kPi) * T.m[vl] * viv * viv;
+            float vkap[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) vkap[b] = T.kappa[(int64_t)b * n + vl];
+            const double qx0 = (double)pd_xj[q0][0], qx1 = (double)pd_xj[q0][1],
+                         qx2 = (double)pd_xj[q0][2];
+            const uint32_t qj = pd_j[q0];
+            const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
+            const double ff = f0 * f0 + f1 * f1 + f2 * f2;
+            for (int k = 0; k < nrecv; ++k) {
+              const int q = q0 + k;
+              if (!pd_valid[q]) continue;
+              const RecvInfo& rq = recv[k];
+              const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
+              const double w0 = vx - rq.x[0], w1 = vy - rq.x[1], w2 = vz - rq.x[2];
+              double uu = (w0 * pe0 + w1 * pe1 + w2 * pe2) * pd_inv2[q];
+              uu = fmin(1.0, fmax(0.0, uu));
+              const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
+              const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
+              if (ff < pd_r2[q] && b2 < vh2 && vl != rq.slot && vl != qj) {
+                ++hits;
+                const float bb = sqrtf((float)b2);
+                const float sg = vsig * (1.0f - bb * viv);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) atomicAdd(&tacc[q][b], vkap[b] * sg);
+              }
+            }
+          }
+        };
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
           const uint32_t u = c0 + (uint32_t)t;
           const bool has = u < nnear;
           const uint32_t l = has ? near[u] : near[0];
-          // positions stay FP32 (as stored) until a job widens them
-          const float ux = T.x[l], uy = T.y[l], uz = T.z[l];
+          // the lane keeps what the element tests need; an exact-test job
+          // reads the rest of its element itself
           const double hl = T.h[l];
-          const double h2 = hl * hl;
-          // column density scale 3m/(pi h^2) and 1/h in FP32 (they set the
-          // values added, not the decisions)
-          const float iv = __builtin_amdgcn_rcpf((float)hl);
-          const float sig = (float)(3.0 / kPi) * T.m[l] * iv * iv;
-          float kap[NB];
-#pragma unroll
-          for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
-          const float pr[3] = {(float)((double)ux - c[0]), (float)((double)uy - c[1]),
-                               (float)((double)uz - c[2])};
+          const float pr[3] = {(float)((double)T.x[l] - c[0]), (float)((double)T.y[l] - c[1]),
+                               (float)((double)T.z[l] - c[2])};
           const float hrad = (float)hl * (1.0f + 1e-5f) +
                              1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
-          uint32_t head = 0, tail = 0, ha = 0, ta = 0;   // wave-uniform queue cursors
-          // one batch of up to 64 queued jobs, job head + lane on this lane:
-          // a job is (element, source run); its lane runs the exact test of
-          // the element on each of the run's nrecv pairs (pair q0 + k has
-          // receiver k), the element and source read once
-          auto run_jobs = [&](uint32_t cnt) {
-            const bool mine = (uint32_t)lane < cnt;
-            const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
-            const int L = mine ? (int)(job >> 8) : lane;
-            const int q0 = (int)(job & 0xFFu);
-            const double vx = (double)__shfl(ux, L), vy = (double)__shfl(uy, L),
-                         vz = (double)__shfl(uz, L);
-            const double vh2 = __shfl(h2, L);
-            const float vsig = __shfl(sig, L), viv = __shfl(iv, L);
-            const uint32_t vl = (uint32_t)__shfl((int)l, L);
-            float vkap[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) vkap[b] = __shfl(kap[b], L);
-            if (mine) {
-              const double qx0 = (double)pd_xj[q0][0], qx1 = (double)pd_xj[q0][1],
-                           qx2 = (double)pd_xj[q0][2];
-              const uint32_t qj = pd_j[q0];
-              const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
-              const double ff = f0 * f0 + f1 * f1 + f2 * f2;
-              for (int k = 0; k < nrecv; ++k) {
-                const int q = q0 + k;
-                if (!pd_valid[q]) continue;
-                const RecvInfo& rq = recv[k];
-                const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
-                const double w0 = vx - rq.x[0], w1 = vy - rq.x[1], w2 = vz - rq.x[2];
-                double uu = (w0 * pe0 + w1 * pe1 + w2 * pe2) * pd_inv2[q];
-                uu = fmin(1.0, fmax(0.0, uu));
-                const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
-                const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-                if (ff < pd_r2[q] && b2 < vh2 && vl != rq.slot && vl != qj) {
-                  ++hits;
-                  const float bb = sqrtf((float)b2);
-                  const float sg = vsig * (1.0f - bb * viv);
-#pragma unroll
-                  for (int b = 0; b < NB; ++b) atomicAdd(&tacc[q][b], vkap[b] * sg);
-                }
-              }
-            }
-          };
+          uint32_t ha = 0, ta = 0;   // wave-uniform cursors of the first queue
           // the round-cone filter over up to 64 jobs of the first queue (job
           // ha + lane on this lane); the survivors go to the exact tests
           auto filter_jobs = [&](uint32_t cnt) {
@@ -745,9 +744,15 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             const int L = mine ? (int)(job >> 8) : lane;
             const float vp[3] = {__shfl(pr[0], L), __shfl(pr[1], L), __shfl(pr[2], L)};
             const float vh = __shfl(hrad, L);
-            const bool keep = mine && elem_run_cone(vp, vh, RT, Rm, (int)(job & 0xFFu));
+            const uint32_t vl = (uint32_t)__shfl((int)l, L);
+            const int q0 = (int)(job & 0xFFu);
+            const bool keep = mine && elem_run_cone(vp, vh, RT, Rm, q0);
             const uint64_t m = ballot64(keep);
-            if (keep) Q[(tail + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = job;
+            if (keep) {
+              const uint32_t slot = (tail + (uint32_t)mbcnt(m)) & (kJobQ - 1);
+              XL[slot] = vl;
+              XQ[slot] = (uint8_t)q0;
+            }
             tail += (uint32_t)__popcll(m);
             wave_lds_sync();
             while (tail - head >= 64u) {
@@ -783,9 +788,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             }
           }
           if (ta > ha) filter_jobs(ta - ha);
-          if (tail > head) run_jobs(tail - head);
           wave_lds_sync();
         }
+        if (tail > head) run_jobs(tail - head);
+        wave_lds_sync();
         __syncthreads();
       } else
       for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
