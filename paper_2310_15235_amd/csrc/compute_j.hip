@@ -11,9 +11,10 @@
 //                     ballot compaction) and writes the bucket's cut: accepted
 //                     cells, opened buckets and resolved element sources, each
 //                     source tagged with its HEALPix pixel;
-//   k_pp_rays         256 threads per bucket stage the p-p set through LDS:
-//                     per receiver and ray the p-p optical depth (kept for the
-//                     far field);
+//   k_pp_rays         256 threads per bucket take (p-p element, receiver)
+//                     pairs, each testing the rays of the element's HEALPix
+//                     ring range: per receiver and ray the p-p optical depth
+//                     (kept for the far field);
 //   k_pp_src          the attenuated p-p sources (J starts with these);
 //   k_far             256 threads per bucket reduce the cut: sources are
 //                     staged per group of 64 rays and sorted along each ray;
@@ -418,16 +419,24 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
 // size h reaches the ray line (b < h, with b^2 = |d|^2 - proj^2: continuous,
 // Sigma -> 0 at b = h): kappa_l Sigma_l(b), Sigma_l(b) = 3 m_l/(pi h_l^2)
 // (1 - b/h_l).  Written to tpp[receiver][ray][band] for the far field.
+//
+// Element-major: per receiver chunk and group of 64 rays, threads take
+// (p-p element, receiver) pairs; a pair tests only the group's rays in the
+// element's ring range (and the directed ray), first with a conservative
+// FP32 test, then with the exact FP64 one, and adds each hit's kappa Sigma
+// to the (receiver, ray) sums in LDS, written out once per group.
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT, Items I,
                                                 const uint32_t* blist, const uint32_t* bscene,
                                                 const uint32_t* noff, const uint32_t* nidx,
                                                 const uint32_t* toff, const uint8_t* active,
-                                                float* tpp, int sub) {
+                                                float* tpp) {
   const int t = threadIdx.x;
-  __shared__ NearTile<NB> S;
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s, s_item;
+  __shared__ double rn[64][3];
+  __shared__ float rnf[64][3];
+  __shared__ float acc[kRMax][64][NB];
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -440,87 +449,83 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
   const uint32_t* near = nidx + n0;
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
+  const int64_t n = T.n;
   float* tppb = tpp + toff[bucket];
+  double ud[3];
+  const int kd = directed_ray(T, c, ud);   // the bucket's directed ray, if any
   uint32_t ract = 0;
   uint32_t member = lk.x;
   for (;;) {
     const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
-    const int stride = (kNT / nrecv) * nrecv;       // thread t keeps receiver t % nrecv
-    const int gpr = (nray + 1) / 2;                 // two rays per thread
-    const uint32_t P = (uint32_t)nrecv * (uint32_t)gpr;
-    const int i = t % nrecv;
-    const RecvInfo& ri = recv[i];
-    for (uint32_t pb = 0; pb < P; pb += (uint32_t)stride) {
-      const uint32_t p = pb + (uint32_t)t;
-      const bool ok = t < stride && p < P;
-      const int kb = ok ? 2 * (int)(p / nrecv) : 0;
-      double nv[2][3];
-      float of[3], inv[2][3];
-      bool kok[2];
-      float tau[2][NB];
-      double ud[3];
-      const int kd = directed_ray(T, c, ud);   // the bucket's directed ray, if any
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        kok[q] = ok && kb + q < nray;
-        const int kq = kok[q] ? kb + q : 0;
+    for (int k0 = 0; k0 < nray; k0 += 64) {
+      const int kn = min(64, nray - k0);
+      // the directed ray, when it is in this group: its direction is not a
+      // HEALPix centre, so it is tested whatever the ring range
+      const int kdg = (kd >= k0 && kd < k0 + kn) ? kd - k0 : -1;
+      if (t < kn) {
+        const int k = k0 + t;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          nv[q][a] = (kq == kd) ? ud[a] : T.ray_n[3 * kq + a];
-          const float nf = (float)nv[q][a];
-          inv[q][a] = (nf != 0.0f) ? 1.0f / nf : 1e30f;
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) tau[q][b] = 0.0f;
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) of[a] = ri.rel[a];
-      const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
-      const uint32_t si = ri.slot;
-      for (uint32_t c0 = 0; c0 < nnear; c0 += kNChunk) {
-        const uint32_t cl = min((uint32_t)kNChunk, nnear - c0);
-        stage_near<NB>(S, T, near, c0, cl, c);
-        const int nsub = ((int)cl + sub - 1) / sub;
-        const float (*BL)[3] = near_boxes(S, sub, false);
-        const float (*BH)[3] = near_boxes(S, sub, true);
-        for (int sb = 0; sb < nsub; ++sb) {
-          bool need = false;
-          if (ok) {
-            const float blo[3] = {BL[sb][0], BL[sb][1], BL[sb][2]};
-            const float bhi[3] = {BH[sb][0], BH[sb][1], BH[sb][2]};
-            need = (kok[0] && ray_meets_box(of, inv[0], blo, bhi)) ||
-                   (kok[1] && ray_meets_box(of, inv[1], blo, bhi));
-          }
-          if (ballot64(need) == 0ull) continue;
-          if (!need) continue;
-          const int u1 = min((int)cl, (sb + 1) * sub);
-          for (int u = sb * sub; u < u1; ++u) {
-            const double d0 = S.x[u] - xi0, d1 = S.y[u] - xi1, d2 = S.z[u] - xi2;
-            const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-            const double h2 = S.h2[u];
-            const bool other = S.slot[u] != si;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-              const double proj = d0 * nv[q][0] + d1 * nv[q][1] + d2 * nv[q][2];
-              const double b2 = dd - proj * proj;
-              if (proj > 0.0 && b2 < h2 && other && kok[q]) {
-                const float bb = sqrtf((float)fmax(b2, 0.0));
-                const float sg = S.sig[u] * (1.0f - bb * S.invh[u]);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) tau[q][b] += S.kap[u][b] * sg;
-              }
-            }
-          }
+          const double na = (k == kd) ? ud[a] : T.ray_n[3 * k + a];
+          rn[t][a] = na;
+          rnf[t][a] = (float)na;
         }
       }
+      for (int q = t; q < kRMax * 64 * NB; q += kNT) (&acc[0][0][0])[q] = 0.0f;
+      __syncthreads();
+      for (uint32_t pq = (uint32_t)t; pq < nnear * (uint32_t)nrecv; pq += kNT) {
+        const uint32_t u = pq / (uint32_t)nrecv;
+        const int i = (int)(pq % (uint32_t)nrecv);
+        const uint32_t l = near[u];
+        if (l == recv[i].slot) continue;
+        const double d0 = (double)T.x[l] - recv[i].x[0];
+        const double d1 = (double)T.y[l] - recv[i].x[1];
+        const double d2 = (double)T.z[l] - recv[i].x[2];
+        const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+        const double hl = T.h[l];
+        const double h2 = hl * hl;
+        const float df[3] = {(float)d0, (float)d1, (float)d2};
+        const float ddf = (float)dd;
+        const float lim = (float)(dd - h2) - 1e-5f * ddf - 1e-30f;
+        const float neg = -1e-5f * sqrtf(ddf);
+        int ka, kb;
+        ray_ring_range(T.nside, d0, d1, d2, dd, h2, &ka, &kb);
+        uint64_t cand = 0ull;
+        for (int kq = max(ka - k0, 0); kq < min(kb - k0, kn); ++kq) {
+          const float pf = rnf[kq][0] * df[0] + rnf[kq][1] * df[1] + rnf[kq][2] * df[2];
+          if (pf > neg && pf * pf >= lim) cand |= 1ull << kq;
+        }
+        if (kdg >= 0) {
+          const float pf = rnf[kdg][0] * df[0] + rnf[kdg][1] * df[1] + rnf[kdg][2] * df[2];
+          if (pf > neg && pf * pf >= lim) cand |= 1ull << kdg;
+        }
+        if (cand == 0ull) continue;
+        const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+        const float iv = (float)(1.0 / hl);
+        float kap[NB];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (!kok[q]) continue;
-        float* o = tppb + ((int64_t)(ract + i) * nray + kb + q) * NB;
+        for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
+        while (cand) {
+          const int kq = __ffsll((long long)cand) - 1;
+          cand &= cand - 1ull;
+          const double proj = d0 * rn[kq][0] + d1 * rn[kq][1] + d2 * rn[kq][2];
+          const double b2 = dd - proj * proj;
+          if (!(proj > 0.0 && b2 < h2)) continue;
+          const float bb = sqrtf((float)fmax(b2, 0.0));
+          const float sg = sig * (1.0f - bb * iv);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) o[b] = tau[q][b];
+          for (int b = 0; b < NB; ++b) atomicAdd(&acc[i][kq][b], kap[b] * sg);
+        }
       }
+      __syncthreads();
+      for (int q = t; q < nrecv * kn; q += kNT) {
+        const int i = q / kn, kq = q % kn;
+        float* o = tppb + ((int64_t)(ract + i) * nray + k0 + kq) * NB;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) o[b] = acc[i][kq][b];
+      }
+      __syncthreads();
     }
     ract += (uint32_t)nrecv;
   }
@@ -1663,7 +1668,7 @@ static trevr_status pp_rays_nb(const Launch& L, const Scratch& S, const Items& I
   trevr_status rc;
   const void* fn = (const void*)&k_pp_rays<NB>;
   k_pp_rays<NB><<<persistent_grid(fn, kNT, count, L.cfg.grid_div), kNT, 0, L.st>>>(
-      L.TT, I, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, active, S.tpp, L.cfg.pp_sub);
+      L.TT, I, S.blist, S.bscene, S.ncnt, S.nidx, S.tcnt, active, S.tpp);
   TREVR_LAUNCH_CHECK("k_pp_rays");
   return rc;
 }

@@ -495,6 +495,11 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
     if (nrecv == 0) break;
     for (int k0 = 0; k0 < nray; k0 += 64) {
       const int kn = min(64, nray - k0);
+      // the directed ray, when it is in this group: its direction is not a
+      // HEALPix centre, so it is tested whatever the ring range
+      double ud[3];
+      const int kd = directed_ray(T, c, ud);
+      const int kdg = (kd >= k0 && kd < k0 + kn) ? kd - k0 : -1;
       if (t == 0) gz = 0;
       load_ray_group(T, c, k0, kn, RG);
       __syncthreads();
@@ -542,12 +547,19 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
           float ck[NB], gh = 0.0f;
 #pragma unroll
           for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
-          // the FP32 test over the whole ray group first, then the exact
-          // test for this lane's candidates only (in ray order as before)
+          // the FP32 test over the group's rays in the element's ring range
+          // (and the directed ray) first, then the exact test for this
+          // lane's candidates only (in ray order)
+          int ka, kb;
+          ray_ring_range(T.nside, d0, d1, d2, dd, h2, &ka, &kb);
           uint64_t cand = 0ull;
-          for (int kq = 0; kq < kn; ++kq) {
+          for (int kq = max(ka - k0, 0); kq < min(kb - k0, kn); ++kq) {
             const float pf = RG.nf[kq][0] * df[0] + RG.nf[kq][1] * df[1] + RG.nf[kq][2] * df[2];
             if (pf > neg && pf * pf >= lim) cand |= 1ull << kq;
+          }
+          if (kdg >= 0) {
+            const float pf = RG.nf[kdg][0] * df[0] + RG.nf[kdg][1] * df[1] + RG.nf[kdg][2] * df[2];
+            if (pf > neg && pf * pf >= lim) cand |= 1ull << kdg;
           }
           while (cand) {
             const int kq = __ffsll((long long)cand) - 1;

@@ -737,6 +737,51 @@ __device__ inline uint32_t block_compact(bool pred, uint32_t* wcnt, uint32_t* to
 
 // Directions of one group of up to 64 rays: FP64 (exact ray-box tests),
 // their reciprocals and an FP32 copy (conservative candidate filter).
+// The rays that can meet a p-p element from a receiver (d = the element's
+// offset from the receiver, dd = |d|^2, h2 = its size squared): a ray meets
+// it (ahead, b < h) only if its direction lies within asin(h/|d|) of d, so
+// its z (cos of the polar angle) lies within the z-range of that cone.  The
+// HEALPix ring order lists the rays by decreasing z, ring by ring (ring i of
+// 4N - 1 at z = 1 - i^2/(3N^2) in the north cap, 4/3 - 2i/(3N) in the belt),
+// so those rays are one index range [*ka, *kb): the rings inside the cone's
+// z-range, widened by 1e-4 in sin and z and 1e-3 of a ring for FP32
+// rounding.  The receiver inside the element (h near |d|): every ray.
+__device__ inline float ring_of_z(int N, float z) {
+  if (z > 2.0f / 3.0f) return (float)N * sqrtf(3.0f * fmaxf(1.0f - z, 0.0f));
+  if (z < -2.0f / 3.0f) return 4.0f * N - (float)N * sqrtf(3.0f * fmaxf(1.0f + z, 0.0f));
+  return 2.0f * N - 1.5f * N * z;
+}
+__device__ inline int ring_start(int N, int i) {
+  if (i <= N) return 2 * i * (i - 1);
+  if (i <= 3 * N) return 2 * N * (N - 1) + 4 * N * (i - N);
+  const int ii = 4 * N - i + 1;   // rings from i to the south pole: ii
+  return 12 * N * N - 2 * ii * (ii - 1);
+}
+__device__ inline void ray_ring_range(int N, double d0, double d1, double d2, double dd, double h2,
+                                      int* ka, int* kb) {
+  const float ddf = (float)dd;
+  const float s2 = (float)h2 / ddf;
+  if (!(s2 < 0.99f)) {
+    *ka = 0;
+    *kb = 12 * N * N;
+    return;
+  }
+  const float z = (float)d2 * rsqrtf(ddf);
+  const float sa = fminf(sqrtf(s2) * (1.0f + 1e-4f) + 1e-4f, 1.0f);
+  const float ca = sqrtf(fmaxf(1.0f - sa * sa, 0.0f));
+  const float st = sqrtf(fmaxf(1.0f - z * z, 0.0f));
+  const float zhi = (z >= ca) ? 1.0f : fminf(z * ca + st * sa + 1e-4f, 1.0f);
+  const float zlo = (-z >= ca) ? -1.0f : fmaxf(z * ca - st * sa - 1e-4f, -1.0f);
+  const int i0 = max(1, (int)ceilf(ring_of_z(N, zhi) - 1e-3f));
+  const int i1 = min(4 * N - 1, (int)floorf(ring_of_z(N, zlo) + 1e-3f));
+  if (i0 > i1) {
+    *ka = *kb = 0;
+    return;
+  }
+  *ka = ring_start(N, i0);
+  *kb = ring_start(N, i1 + 1);
+}
+
 struct RayGroup {
   double n[64][3], inv[64][3];
   float nf[64][3];
