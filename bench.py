@@ -324,9 +324,10 @@ def self_check(rec, samples):
 
 
 # ------------------------------------------------------- one-scene legs
-def single_tree(sc, dev, reps=3, active=None, label=""):
+def single_tree(sc, dev, reps=3, active=None, label="", extra_flags=0):
     """Forward and forward + adjoint on a resident tree (median of `reps`),
-    tree build time, per-phase kernel times, counters."""
+    tree build time, per-phase kernel times, counters; extra_flags (the
+    adjoint's depth cache) are or-ed into the scene's options."""
     import numpy as np
     import torch
     from paper_2310_15235_amd import api
@@ -336,7 +337,7 @@ def single_tree(sc, dev, reps=3, active=None, label=""):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
-    T = api.Tree.from_scene(sc, device=dev)
+    T = api.Tree.from_scene(sc, device=dev, extra_flags=extra_flags)
     ev1.record()
     torch.cuda.synchronize()
     ms_build = ev0.elapsed_time(ev1)
@@ -502,6 +503,10 @@ def main():
         rec["forest"].close()
         out["clumpy2e18"] = single_tree(scenes.config_clumpy(), dev, reps=3,
                                         label="clumpy 2^18")
+        from paper_2310_15235_amd import api
+        kd = single_tree(scenes.config_clumpy(), dev, reps=3, label="clumpy 2^18, depth cache",
+                         extra_flags=api.KEEP_DEPTHS)
+        out["clumpy2e18"]["keep_depths"] = {k: kd[k] for k in ("fwd", "fwd_adjoint")}
         sc3 = scenes.config_diffuse(active_frac=1.0)
         diffuse = {}
         for frac in (0.01, 0.1, 1.0):
