@@ -963,8 +963,19 @@ __device__ inline void far_counters_flush(unsigned long long* dst, unsigned long
 // thread (t mod P2, P2 the power of two >= the receiver count), so each
 // thread keeps one FP64 accumulator per band, reduced per receiver in a
 // fixed order at the end.
+//
+// Workgroups per CU to compile for: as many as the kernel's LDS lets reside
+// (up to 4; its LDS grows with the band count), the register budget capped
+// to match.  Latency-bound: four workgroups with some spilling beat two
+// without (2^21 diffuse, one band: 146 -> 93 ms; clumpy, three bands at
+// three: 5.8 -> 4.6 ms).
+template <int NB> struct FarCfg {
+  static constexpr int waves = NB <= 2 ? 4 : NB <= 4 ? 3 : NB == 5 ? 4 : NB == 6 ? 3
+                               : NB <= 12 ? 2 : 1;
+};
+
 template <int NB>
-__global__ void __launch_bounds__(kFT) k_far(const DevTree* __restrict__ TT, Items I,
+__global__ void __launch_bounds__(kFT, FarCfg<NB>::waves) k_far(const DevTree* __restrict__ TT, Items I,
                                              const uint32_t* blist, const uint32_t* bscene,
                                              const double* brad, const uint32_t* toff,
                                              const uint2* cut, uint32_t cut_cap,

@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
 template <int NB> struct BwdCfg {
   static constexpr int cap = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 5 ? 512 : NB == 6 ? 448
                             : NB == 7 ? 320 : 256;
-  static constexpr int waves = NB <= 4 ? 3 : 2;
+  static constexpr int waves = NB == 1 ? 4 : NB <= 4 ? 3 : 2;
 };
 
 // Adjoint of k_far (same workgroup layout).  Per window of sources the cell

@@ -118,6 +118,18 @@ def test_J_lognormal(nside, bands):
         assert cg["max_near"] >= 4096, cg["max_near"]
 
 
+@pytest.mark.parametrize("frac", [0.03, 0.4])
+def test_J_element_major_sparse_and_half_active(frac):
+    """The element-major p-p source sweep with few receivers per bucket (up
+    to 256 single-receiver source runs per pass of pairs, so several rounds
+    of sphere tests per element chunk) and with about half of them; counters
+    (pairs, triples, source-path hits) exact, J to the oracle."""
+    sc = scenes.lognormal_scene(n=2 ** 14, seed=11, grid=32, bands=(1.0, 10.0), nside=4)
+    act = scenes.active_subset(sc, frac, 5)
+    _, cg = compare_J(sc, active=act)
+    assert cg["max_near"] >= 4096, cg["max_near"]
+
+
 def test_J_diffuse_background_active_subset():
     sc = scenes.isothermal_scene(n=2 ** 14, seed=9, active_frac=0.25)
     compare_J(sc)
