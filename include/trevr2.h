@@ -104,7 +104,7 @@ enum {
 };
 
 typedef struct trevr_params {
-  int32_t nside;     /* HEALPix N_side, a power of two in [1, 8]; N_ray = 12 nside^2
+  int32_t nside;     /* HEALPix N_side, a power of two in [1, 16]; N_ray = 12 nside^2
                         (Sections 1.3, 2.5; paper default 2, i.e. 48 rays)          */
   int32_t leaf_size; /* bucket capacity, >= 1 (Section 2.3; paper default 12)       */
   int32_t n_bands;   /* B in [1, 16] (kernels are compiled per band count; the

@@ -37,7 +37,7 @@ static trevr_status check_params(const trevr_params* p, int64_t n) {
   if (n <= 0 || n >= (int64_t)1 << 31) return set_error(TREVR_E_INVALID, "n must be in [1, 2^31)");
   const int ns = p->nside;
   if (ns < 1 || ns > kMaxNside || (ns & (ns - 1)))
-    return set_error(TREVR_E_INVALID, "nside must be a power of two in [1, 8]");
+    return set_error(TREVR_E_INVALID, "nside must be a power of two in [1, 16]");
   if (p->leaf_size < 1) return set_error(TREVR_E_INVALID, "leaf_size must be >= 1");
   if (p->n_bands < 1 || p->n_bands > kMaxBands)
     return set_error(TREVR_E_INVALID, "n_bands must be in [1, 16]");

@@ -10,8 +10,7 @@
 namespace trevr {
 
 constexpr int kMaxBands = 16;
-constexpr int kMaxNside = 8;
-constexpr int kMaxRays = 12 * kMaxNside * kMaxNside;
+constexpr int kMaxNside = 16;   // 3072 rays (pixel ids keep 16 bits in cut entries)
 constexpr int kKeyBits = 21;           // bits per axis of the Morton key
 constexpr int kMaxLevels = 64;         // prefix lengths 0..63
 constexpr double kPi = 3.14159265358979323846;

@@ -33,7 +33,7 @@ def test_status_strings():
         assert len(L.trevr_status_string(s)) > 0
 
 
-@pytest.mark.parametrize("kw", [dict(nside=3), dict(nside=0), dict(nside=16), dict(leaf_size=0),
+@pytest.mark.parametrize("kw", [dict(nside=3), dict(nside=0), dict(nside=32), dict(leaf_size=0),
                                 dict(n_bands=0), dict(n_bands=17), dict(theta=-1.0),
                                 dict(theta=float("nan")), dict(rpp_min=-1.0), dict(flags=128),
                                 dict(flags=32, target=(float("nan"), 0.0, 0.0))])

@@ -195,6 +195,15 @@ def test_J_nside8():
     compare_J(sc)
 
 
+def test_J_nside16():
+    """3072 rays (the largest N_side the library takes): 48 ray groups of 64
+    per bucket, ring ranges spanning several groups."""
+    sc = scenes.uniform_scene(n=20000, seed=81, n_src=40, bands=(1.0, 3.0), nside=16)
+    act = scenes.active_subset(sc, 0.02, 3)
+    _, cg = compare_J(sc, active=act)
+    assert cg["cells"] > 0 and cg["source_entries"] > 0 and cg["max_near"] >= 4096
+
+
 def test_J_ragged_active_subset():
     sc = scenes.lognormal_scene(n=10000, seed=13, grid=32, bands=(1.0, 10.0), nside=2)
     act = scenes.active_subset(sc, 0.013, 5)
