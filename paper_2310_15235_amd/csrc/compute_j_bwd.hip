@@ -600,13 +600,16 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
 
 // ------------------------------------------------------------- far field
 // Sources per LDS window and workgroups per CU of the far-field adjoint:
-// up to four bands the window is sized so that three workgroups fit in
-// the 160 KiB of LDS (and the register budget is held to three wavefronts
-// per SIMD); with more bands, two (registers limit them anyway).
+// the window is sized so that that many workgroups fit in the 160 KiB of
+// LDS, and the register budget is held to match (with spilling).  Measured:
+// one, two and four bands at four workgroups (two bands with a window of
+// 448: 2^21 diffuse 284 -> 224 ms; four bands with 192: batched workload 79
+// -> 71 ms), three bands at three (at four, with a window of 320, the clumpy
+// scene ran 5% slower); more bands, two (registers limit them anyway).
 template <int NB> struct BwdCfg {
-  static constexpr int cap = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 5 ? 512 : NB == 6 ? 448
-                            : NB == 7 ? 320 : 256;
-  static constexpr int waves = NB == 1 ? 4 : NB <= 4 ? 3 : 2;
+  static constexpr int cap = NB == 1 ? 512 : NB == 2 ? 448 : NB == 3 ? 512 : NB == 4 ? 192
+                            : NB == 5 ? 512 : NB == 6 ? 448 : NB == 7 ? 320 : 256;
+  static constexpr int waves = NB == 3 ? 3 : NB <= 4 ? 4 : 2;
 };
 
 // Adjoint of k_far (same workgroup layout).  Per window of sources the cell

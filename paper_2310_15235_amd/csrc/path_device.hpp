@@ -708,7 +708,8 @@ constexpr int kFT = 256;   // threads of the far-field kernels
 // Sources of a (bucket, ray group) whose cell optical depths the forward
 // keeps for the adjoint when all of them fit one window of both kernels.
 template <int NB> struct KeptCap {
-  static constexpr int value = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 6 ? 224 : 256;
+  static constexpr int value = NB == 2 ? 448 : NB <= 3 ? 512 : NB == 4 ? 192 : NB == 6 ? 224
+                               : 256;
 };
 // Sources per LDS window of the forward far-field kernel: as many as let
 // three workgroups share a CU's 160 KiB of LDS (two from seven bands on,
