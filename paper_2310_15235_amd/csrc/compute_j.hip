@@ -965,13 +965,12 @@ __device__ inline void far_counters_flush(unsigned long long* dst, unsigned long
 // fixed order at the end.
 //
 // Workgroups per CU to compile for: as many as the kernel's LDS lets reside
-// (up to 4; its LDS grows with the band count), the register budget capped
-// to match.  Latency-bound: four workgroups with some spilling beat two
-// without (2^21 diffuse, one band: 146 -> 93 ms; clumpy, three bands at
-// three: 5.8 -> 4.6 ms).
+// (up to 4; its LDS grows with the band count, and the source window SrcCap
+// is sized for four up to five bands), the register budget capped to match.
+// Latency-bound: four workgroups with some spilling beat two without (2^21
+// diffuse, two bands: 146 -> 93 ms; clumpy, three bands: 5.8 -> 4.2 ms).
 template <int NB> struct FarCfg {
-  static constexpr int waves = NB <= 2 ? 4 : NB <= 4 ? 3 : NB == 5 ? 4 : NB == 6 ? 3
-                               : NB <= 12 ? 2 : 1;
+  static constexpr int waves = NB <= 5 ? 4 : NB == 6 ? 3 : NB <= 12 ? 2 : 1;
 };
 
 template <int NB>

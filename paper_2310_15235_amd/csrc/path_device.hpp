@@ -708,14 +708,14 @@ constexpr int kFT = 256;   // threads of the far-field kernels
 // Sources of a (bucket, ray group) whose cell optical depths the forward
 // keeps for the adjoint when all of them fit one window of both kernels.
 template <int NB> struct KeptCap {
-  static constexpr int value = NB == 2 ? 448 : NB <= 3 ? 512 : NB == 4 ? 192 : NB == 6 ? 224
+  static constexpr int value = NB == 1 ? 512 : NB <= 3 ? 448 : NB == 4 ? 192 : NB == 6 ? 224
                                : 256;
 };
 // Sources per LDS window of the forward far-field kernel: as many as let
-// three workgroups share a CU's 160 KiB of LDS (two from seven bands on,
-// where registers limit it anyway).
+// four workgroups share a CU's 160 KiB of LDS up to five bands (three at
+// six, two from seven bands on, where registers limit it anyway).
 template <int NB> struct SrcCap {
-  static constexpr int value = NB <= 3 ? 512 : NB == 4 ? 384 : NB == 6 ? 224 : 256;
+  static constexpr int value = NB <= 2 ? 512 : NB == 3 ? 448 : NB == 4 ? 320 : NB == 6 ? 224 : 256;
 };
 
 // Block-wide compaction: position of this thread's item among the set ones
