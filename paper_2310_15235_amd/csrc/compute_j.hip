@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     const RecvInfo& ri = recv[i];
     const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
     const uint32_t si = ri.slot;
-    const bool em = nnear >= kPpElementMajor;
+    const bool em = nnear >= kPpElementMajor || (uint32_t)nrecv * nl <= (uint32_t)kNT;
     float reach = 0.0f;   // largest receiver distance from the centre
     for (int k = 0; k < nrecv; ++k)
       reach = fmaxf(reach, sqrtf(recv[k].rel[0] * recv[k].rel[0] + recv[k].rel[1] * recv[k].rel[1] +

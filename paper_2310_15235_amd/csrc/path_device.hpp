@@ -377,9 +377,14 @@ constexpr int kNSub = kNChunk / kSub;
 // the largest enqueue (one per lane).
 constexpr uint32_t kJobQ = 128;
 // p-p sets from this size on are swept element-major by the p-p source kernel
-// (each element against the pass's source runs, exact tests queued); smaller
-// ones pair-major over culling boxes of staged elements.
-constexpr uint32_t kPpElementMajor = 4096;
+// (each element against the pass's source runs, exact tests queued), and so
+// are smaller ones whose pairs all fit one pass; the rest pair-major over
+// culling boxes of staged elements.  Measured (forward p-p sources): from
+// 4096 to 256 with the one-pass rule, clumpy 2^18 3.43 -> 2.66 ms, batched
+// 590 -> 573 ms, the 2^21 diffuse scene (every element emits, so many
+// passes over small sets) unchanged; below 256 the diffuse scene slows by
+// a third.
+constexpr uint32_t kPpElementMajor = 256;
 
 __device__ inline float wave_fmin(float v) {
 #pragma unroll

@@ -112,9 +112,8 @@ def test_J_lognormal(nside, bands):
     sc = scenes.lognormal_scene(n=2 ** 14, seed=7 + nside, grid=32, bands=bands, nside=nside)
     _, cg = compare_J(sc)
     if nside == 4:
-        # the p-p sets of this scene reach past 4096 elements, where the p-p
-        # source kernel sweeps element-major, so both of its sweeps meet the
-        # oracle here
+        # the p-p sets of this scene reach past 4096 elements, so the
+        # element-major p-p source sweep meets the oracle on large sets here
         assert cg["max_near"] >= 4096, cg["max_near"]
 
 
