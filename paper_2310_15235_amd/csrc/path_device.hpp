@@ -123,11 +123,6 @@ __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
-__device__ inline uint32_t wave_sum_u(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
-  return v;
-}
 // exclusive prefix sum over the wavefront
 __device__ inline uint32_t wave_excl(uint32_t v, int lane) {
   uint32_t incl = v;
@@ -386,16 +381,6 @@ constexpr uint32_t kJobQ = 128;
 // a third.
 constexpr uint32_t kPpElementMajor = 256;
 
-__device__ inline float wave_fmin(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ inline float wave_fmax(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
-}
 
 // Per source run of an element-major p-p sweep (LDS, one entry per pair,
 // read at the run's first pair): s = jr the source relative to the bucket
