@@ -15,7 +15,12 @@
 //                     pairs, each testing the rays of the element's HEALPix
 //                     ring range: per receiver and ray the p-p optical depth
 //                     (kept for the far field);
-//   k_pp_src          the attenuated p-p sources (J starts with these);
+//   k_pp_src          the attenuated p-p sources (J starts with these):
+//                     element-major for sets of 256 or more (or whose pairs
+//                     fit one pass), culled by spheres of 16 elements, the
+//                     cylinder and the round cone around each source run
+//                     before the exact tests; pair-major over culling boxes
+//                     otherwise;
 //   k_far             256 threads per bucket reduce the cut: sources are
 //                     staged per group of 64 rays and sorted along each ray;
 //                     every thread takes absorbing cut entries, finds the rays
