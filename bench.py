@@ -399,6 +399,41 @@ def bands_cost(dev):
     return out
 
 
+def complex_source_cost(dev, reps=3):
+    """Section 2.7 (the complex source model): its tree build costs about 40%
+    more wall clock in the paper's test problems.  The clumpy 2^18 scene
+    built and run forward with and without the model (medians of `reps`;
+    the build includes the inputs' upload, the same for both)."""
+    import numpy as np
+    import torch
+    from paper_2310_15235_amd import api, scenes
+    sc = scenes.config_clumpy()
+    act = torch.as_tensor(sc.active, device=dev)
+    out = {}
+    for name, flag in (("standard", 0), ("complex", api.COMPLEX_SOURCE)):
+        tb, tf = [], []
+        for _ in range(reps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            torch.cuda.synchronize()
+            e0.record()
+            T = api.Tree.from_scene(sc, device=dev, extra_flags=flag)
+            e1.record()
+            J = T.compute_J(act)
+            e2.record()
+            torch.cuda.synchronize()
+            T.check()
+            T.close()
+            tb.append(e0.elapsed_time(e1))
+            tf.append(e1.elapsed_time(e2))
+        out[name] = {"build_ms": float(np.median(tb)), "fwd_ms": float(np.median(tf))}
+    out["build_ratio"] = out["complex"]["build_ms"] / out["standard"]["build_ms"]
+    out["paper"] = "the complex source model's tree build: about +40% wall clock (Section 2.7)"
+    note(f"complex source model: build {out['standard']['build_ms']:.2f} -> "
+         f"{out['complex']['build_ms']:.2f} ms, forward {out['standard']['fwd_ms']:.2f} -> "
+         f"{out['complex']['fwd_ms']:.2f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +551,7 @@ def main():
                                                       "fwd_adjoint", "kernel_ms_per_step")}
         out["diffuse2e21"] = diffuse
         out["bands_cost"] = bands_cost(dev)
+        out["complex_source_cost"] = complex_source_cost(dev)
     else:
         rec["forest"].close()
     print(json.dumps(out), flush=True)
