@@ -12,7 +12,9 @@ time.
 
 Workload: 64 scenes of log-uniform size 2^12..2^17 elements (2.2M in all),
 each a uniform or a log-normal medium (C1 / C2 generators), 1-4 bands, N_side
-1, 2 or 4, theta 0.75, leaf 8, all elements active.
+1, 2 or 4, theta 0.75, leaf 8, all elements active.  The forest keeps the p-p
+job log (the forward's culled p-p source jobs, read by the adjoint), sized
+from the forward's own count of its entries.
 
 Beside it (extra keys): the batched forward alone, the same graph with mixed
 per-scene active fractions, the plain path (each scene's own tree called in
@@ -148,6 +150,12 @@ def batched(args, dev, extras: bool):
     F.check()
     per_scene = [F.counters(s) for s in range(F.S)]
     seg = sum(c["segments"] for c in per_scene)
+    # the p-p job log: room for every bucket's jobs (the forward's count) plus
+    # partly used blocks (32 KiB per persistent wavefront and band count)
+    log_entries = sum(c["pp_log_entries"] for c in per_scene)
+    F.set_job_log(2 * log_entries + (1 << 30))
+    note(f"p-p job log: {log_entries} entries, {F.job_log_bytes / 2 ** 30:.2f} GiB")
+    F.compute_J(a, out=J)
     F.compute_J_backward(gJ, a, out=outs)
     F.check()
 
@@ -220,6 +228,8 @@ def batched(args, dev, extras: bool):
         "fwd_ms": ms_f, "prof": prof, "kernel_ms": kms, "flops": flops,
         "dominant": dom, "achieved": achieved, "launches": d_launch, "dom_ms": d_ms,
         "traversal_bytes": tbytes, "build_and_plan_ms": (b1 - b0) * 1e3,
+        "job_log": {"entries": log_entries, "bytes": F.job_log_bytes,
+                    "scratch_bytes": int(F.scratch.numel())},
         "autotune": {"chosen": chosen, "candidate_fwd_ms": [float(t) for t in tune_ms],
                      "candidates": "bit 2: bucket order (cost / scene), bit 1: persistent "
                                    "grid (full / half), bit 0: p-p boxes (16 / 8)"},
@@ -513,9 +523,9 @@ def main():
         "config": {"workload": "batched forward + adjoint, HIP-graph replay: 64 scenes of "
                                "2^12..2^17 elements (log-uniform, 2.2M in all), uniform or "
                                "log-normal media, 1-4 bands, N_side 1/2/4, theta 0.75, leaf 8, "
-                               "all active",
+                               "all active; p-p job log on",
                    "scenes": len(rec["scenes"]), "elements": rec["n_total"],
-                   "segments_per_step": seg},
+                   "segments_per_step": seg, "pp_job_log_bytes": rec["job_log"]["bytes"]},
         "fwd_adjoint": {"value": seg / fa_s, "ms": rec["ms_step"],
                         "replay_ms": rec["per_replay_ms"]},
         "fwd": {"value": seg / (rec["fwd_ms"] * 1e-3), "ms": rec["fwd_ms"]},
@@ -525,6 +535,7 @@ def main():
         "self_check": check,
         "build_and_plan_ms": rec["build_and_plan_ms"],
         "autotune": rec["autotune"],
+        "job_log": rec["job_log"],
     }
     if extras:
         out["mixed_active"] = {"segments_per_step": rec["seg_mixed"],

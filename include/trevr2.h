@@ -139,6 +139,12 @@ typedef struct trevr_counters {
                                triples whose element absorbs on the path:
                                nearer the source than the receiver and within
                                its size of the segment                        */
+  int64_t pp_log_entries;   /* 16-bit entries a forest's p-p job log needs for
+                               the element-major p-p source sweep: one per
+                               (p-p element, source) job that passes its
+                               culling tests, one per pass and wavefront
+                               chunk of 64 p-p elements (see
+                               trevr_forest_job_log)                          */
 } trevr_counters;
 
 typedef struct trevr_tree trevr_tree; /* opaque host handle */
@@ -387,6 +393,22 @@ trevr_status trevr_forest_plan_bytes(const trevr_forest* f, size_t* bytes);
 trevr_status trevr_forest_plan(trevr_forest* f, void* scratch, size_t scratch_bytes,
                                void* stream);
 trevr_status trevr_forest_scratch_bytes(const trevr_forest* f, size_t* bytes);
+
+/* The p-p job log (memory for time, like TREVR_KEEP_DEPTHS for one tree):
+ * with bytes > 0 the batched forward keeps, for its adjoint, the
+ * (p-p element, source) jobs of its element-major p-p source sweep (Section
+ * 2.4's near-field paths) that passed the culling tests, in up to `bytes`
+ * of extra scratch; the adjoint that reuses that forward's state then runs
+ * only their exact tests.  The decisions are the forward's own, so results
+ * are unchanged (up to the order of FP32 atomic sums).  Buckets whose jobs
+ * do not fit, and those the sweep takes pair-major, are culled again by the
+ * adjoint.  The counter pp_log_entries (2 bytes each) of a forward gives
+ * the size that covers every bucket, plus up to 128 KiB per persistent
+ * wavefront and band count for partly used blocks.  0 (the default) turns
+ * the log off.  Afterwards trevr_forest_scratch_bytes includes the log; a
+ * forward before the change is not reused.  May be called before or after
+ * the plan; TREVR_E_STATE for an unknown forest. */
+trevr_status trevr_forest_job_log(trevr_forest* f, size_t bytes);
 
 /* J of the active elements of every scene (layouts above; active NULL = all
  * active; bg may be NULL unless a scene has TREVR_BACKGROUND).  Rows of

@@ -32,7 +32,7 @@ EXPORTED = ("trevr_workspace_bytes", "trevr_build_tree", "trevr_compute_J",
             "trevr_forest_get_counters", "trevr_forest_scene", "trevr_forest_destroy",
             "trevr_forest_autotune", "trevr_forest_set_config", "trevr_forest_get_config",
             "trevr_compute_J_noalloc", "trevr_forest_profile_enable",
-            "trevr_forest_profile_read")
+            "trevr_forest_profile_read", "trevr_forest_job_log")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # the fixed device array of trevr_compute_J_noalloc
 TUNE_STACK, TUNE_CUT, TUNE_STAGE = 0, 1, 2
 CONFIGS = 8          # launch configurations of the forest autotuner
@@ -58,7 +58,7 @@ class Counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("buckets", "cells", "absorber_entries", "source_entries", "segments",
                  "near_pairs", "max_near", "nodes", "src_pairs", "near_src_triples", "max_cut",
-                 "max_stack", "near_src_hits")]
+                 "max_stack", "near_src_hits", "pp_log_entries")]
 
 
 _lib = None
@@ -108,6 +108,7 @@ def lib():
         L.trevr_forest_profile_enable.argtypes = [vp, ctypes.c_int]
         L.trevr_forest_profile_read.argtypes = [vp, vp, vp]
         L.trevr_compute_J_noalloc.argtypes = [vp, vp, vp, vp, vp]
+        L.trevr_forest_job_log.argtypes = [vp, sz]
         L.trevr_status_string.restype = ctypes.c_char_p
         L.trevr_status_string.argtypes = [ctypes.c_int]
         L.trevr_last_error.restype = ctypes.c_char_p
@@ -433,11 +434,26 @@ class Forest:
         sb = ctypes.c_size_t()
         _check(lib().trevr_forest_scratch_bytes(h, ctypes.byref(sb)), "trevr_forest_scratch_bytes")
         self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        self.job_log_bytes = 0
         self.bg_default = None
         if any(s.background for s in scenes):
             self.bg_default = f32(np.concatenate([
                 np.asarray(s.bg if s.bg is not None else np.zeros(s.n_bands), np.float32)
                 for s in scenes]))
+
+    def set_job_log(self, nbytes):
+        """Size of the p-p job log the forward keeps for the adjoint
+        (trevr_forest_job_log; 0 turns it off).  Reallocates the scratch, so
+        the next backward recomputes the forward state unless a forward runs
+        first."""
+        torch = _torch()
+        _check(lib().trevr_forest_job_log(self.handle, int(nbytes)), "trevr_forest_job_log")
+        sb = ctypes.c_size_t()
+        _check(lib().trevr_forest_scratch_bytes(self.handle, ctypes.byref(sb)),
+               "trevr_forest_scratch_bytes")
+        self.scratch = None
+        self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        self.job_log_bytes = int(nbytes)
 
     def flat_active(self, actives):
         """uint8 device tensor [sum n] from per-scene flags (None = all)."""

@@ -393,6 +393,7 @@ trevr_status trevr_get_counters(trevr_tree* t, trevr_counters* o) {
   o->max_cut = (int64_t)c[CNT_MAX_CUT];
   o->max_stack = (int64_t)c[CNT_MAX_STACK];
   o->near_src_hits = (int64_t)c[CNT_NS_HITS];
+  o->pp_log_entries = (int64_t)c[CNT_PP_LOG];
   return TREVR_OK;
 }
 

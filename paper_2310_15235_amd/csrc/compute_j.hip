@@ -538,16 +538,17 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
 }
 
 // Adds (none when dst is null) and clears the p-p source kernel's counter
-// sums: near pairs, (receiver, source, element) triples, the largest set and
-// the triples whose element absorbs on the path.
+// sums: near pairs, (receiver, source, element) triples, the largest set,
+// the triples whose element absorbs on the path and the job-log entries.
 __device__ inline void pp_counters_flush(unsigned long long* dst, unsigned long long* s) {
   if (dst) {
     if (s[0]) atomicAdd(&dst[CNT_NEAR_PAIRS], s[0]);
     if (s[1]) atomicAdd(&dst[CNT_NS_TRIPLES], s[1]);
     if (s[2]) atomic_max_u64(&dst[CNT_MAX_NEAR], s[2]);
     if (s[3]) atomicAdd(&dst[CNT_NS_HITS], s[3]);
+    if (s[4]) atomicAdd(&dst[CNT_PP_LOG], s[4]);
   }
-  s[0] = s[1] = s[2] = s[3] = 0ull;
+  s[0] = s[1] = s[2] = s[3] = s[4] = 0ull;
 }
 
 // For each receiver i and luminous p-p element j (i itself included, at
@@ -564,7 +565,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
                                                const uint32_t* noff, const uint32_t* nlumc,
                                                const uint32_t* nidx, const uint32_t* poff,
                                                const uint8_t* active, double* Jall,
-                                               float* ptau, int sub) {
+                                               float* ptau, int sub, JobLog JL) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   // the staged elements (pair-major passes), the exact-test job queues
   // (element-major passes) and the receiver sums share their LDS
@@ -593,15 +594,20 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   __shared__ float egrp[kNT / 64][4][5];   // per wavefront: element spheres of its quarters
   // the workgroup's sums of the per-bucket counters (thread 0), added to a
   // scene's counters when it turns to another scene and after its last bucket
-  __shared__ unsigned long long csum[4];   // near pairs, triples, largest set, hits
+  __shared__ unsigned long long csum[5];   // near pairs, triples, largest set, hits, log
   __shared__ unsigned long long* cdst;
   __shared__ unsigned long long s_hits;    // this bucket's hits so far
+  __shared__ unsigned long long s_logn;    // this bucket's job-log entries so far
+  __shared__ uint32_t s_logbad;            // the log does not cover this bucket
   if (threadIdx.x == 0) {
     cdst = nullptr;
-    csum[0] = csum[1] = csum[2] = csum[3] = 0ull;
+    csum[0] = csum[1] = csum[2] = csum[3] = csum[4] = 0ull;
     s_hits = 0ull;
+    s_logn = 0ull;
   }
   uint32_t hits = 0;   // this thread's exact-test passes in the current bucket
+  uint32_t logn = 0;   // the wavefront's job-log entries in the current bucket
+  LogPos lp{kLogFresh, 0u};   // the wavefront's job-log stream
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -617,6 +623,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   const int64_t n = T.n;
   uint32_t member = lk.x;
   uint32_t nact = 0;
+  LogPos lbeg{kLogNone, 0u};   // where this bucket's stream starts
+  if (t == 0) s_logbad = 0u;
   for (;;) {
     const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
@@ -628,6 +636,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     const double xi0 = ri.x[0], xi1 = ri.x[1], xi2 = ri.x[2];
     const uint32_t si = ri.slot;
     const bool em = nnear >= kPpElementMajor || (uint32_t)nrecv * nl <= (uint32_t)kNT;
+    if (JL.log) {
+      if (!em && t == 0) s_logbad = 1u;
+      if (em && lbeg.blk == kLogNone && log_ready(JL, lp)) lbeg = lp;
+    }
     float reach = 0.0f;   // largest receiver distance from the centre
     for (int k = 0; k < nrecv; ++k)
       reach = fmaxf(reach, sqrtf(recv[k].rel[0] * recv[k].rel[0] + recv[k].rel[1] * recv[k].rel[1] +
@@ -746,6 +758,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
           const float hrad = (float)hl * (1.0f + 1e-5f) +
                              1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
           uint32_t ha = 0, ta = 0;   // wave-uniform cursors of the first queue
+          // the job log: this chunk's count first (written when known), then
+          // its jobs as they pass the round cone
+          uint32_t lcnt = 0;
+          const size_t lhead = JL.log ? log_put(JL, lp, 1u, lane == 0, 0u, 0) : ~(size_t)0;
           // the round-cone filter over up to 64 jobs of the first queue (job
           // ha + lane on this lane); the survivors go to the exact tests
           auto filter_jobs = [&](uint32_t cnt) {
@@ -764,6 +780,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               XQ[slot] = (uint8_t)q0;
             }
             tail += (uint32_t)__popcll(m);
+            lcnt += (uint32_t)__popcll(m);
+            if (JL.log && m != 0ull)
+              log_put(JL, lp, (uint32_t)__popcll(m), keep, (uint32_t)mbcnt(m), job);
             wave_lds_sync();
             while (tail - head >= 64u) {
               run_jobs(64u);
@@ -798,6 +817,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             }
           }
           if (ta > ha) filter_jobs(ta - ha);
+          if (lhead != ~(size_t)0 && lane == 0) JL.log[lhead] = (uint16_t)lcnt;
+          logn += 1u + lcnt;
           wave_lds_sync();
         }
         if (tail > head) run_jobs(tail - head);
@@ -917,7 +938,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     // receiver-wise sums in thread order (deterministic); red shares its LDS
     // with the last pass's tile or queues
     if (hits) atomicAdd(&s_hits, (unsigned long long)hits);
+    if (lane == 0 && logn) atomicAdd(&s_logn, (unsigned long long)logn);
     hits = 0;
+    logn = 0;
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < NB; ++b) red[t][b] = acc[b];
@@ -938,8 +961,18 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     csum[1] += (unsigned long long)nact * nl * nnear;
     csum[2] = max(csum[2], (unsigned long long)nnear);
     csum[3] += s_hits;
+    csum[4] += s_logn;
   }
-  if (t == 0) s_hits = 0ull;
+  if (t == 0) {
+    s_hits = 0ull;
+    s_logn = 0ull;
+  }
+  if (JL.log) {
+    // the bucket's stream starts, or none when the log does not cover it
+    if (lane == 0 && (lbeg.blk == kLogNone || lp.blk == kLogNone)) s_logbad = 1u;
+    __syncthreads();
+    if (lane == 0) JL.tab[4 * bucket + wv] = make_uint2(s_logbad ? kLogNone : lbeg.blk, lbeg.pos);
+  }
   }
   if (Jall && threadIdx.x == 0) pp_counters_flush(cdst, csum);
 }
@@ -1695,7 +1728,7 @@ static trevr_status pp_src_nb(const Launch& L, const Scratch& S, const Items& I,
   const void* fn = (const void*)&k_pp_src<NB>;
   k_pp_src<NB><<<persistent_grid(fn, kNT, count, L.cfg.grid_div), kNT, 0, L.st>>>(
       L.TT, I, S.blist, S.bscene, S.ncnt, S.nlumc, S.nidx, S.pcnt, active, J, S.ptau,
-      L.cfg.pp_sub);
+      L.cfg.pp_sub, S.jlog);
   TREVR_LAUNCH_CHECK("k_pp_src");
   return rc;
 }

@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
                                                    const uint32_t* nidx, const uint32_t* joff,
                                                    const uint32_t* poff, const float* ptau,
                                                    const uint8_t* active, const double* gJall,
-                                                   Grad Gall, double* jraw) {
+                                                   Grad Gall, double* jraw, JobLog JL) {
   const int t = threadIdx.x;
   __shared__ PairTile<NB> PT;
   __shared__ RecvInfo recv[kRMax];
@@ -179,6 +179,15 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
   const int64_t n = T.n;
   uint32_t member = lk.x;
   uint32_t nact = 0;
+  // the forward's job log of this bucket, where it covers it: the element-
+  // major sweep then reads its jobs instead of culling again
+  const bool logged = JL.log && JL.tab[4 * bucket].x != kLogNone;
+  LogPos lp{0u, 0u};
+  if (logged) {
+    const uint2 s = JL.tab[4 * bucket + wv];
+    lp.blk = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s.x < JL.blocks ? s.x : 0u));
+    lp.pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(s.y, kLogData));
+  }
   for (;;) {
     const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
@@ -289,6 +298,12 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
         // Passing (element, source run) jobs are queued per wavefront and
         // run 64 at a time, so the exact FP64 tests keep every lane busy.
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
+          // logged: the wavefront's jobs in this chunk (none: nothing to do)
+          uint32_t lcnt = 0;
+          if (logged) {
+            lcnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)log_get(JL, lp, 1u, 0u));
+            if (lcnt == 0u) continue;
+          }
           const uint32_t u = c0 + (uint32_t)t;
           const bool has = u < nnear;
           const uint32_t l = has ? near[u] : near[0];
@@ -311,15 +326,13 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
           for (int b = 0; b <= NB; ++b) A[lane][b] = 0.0f;
           uint32_t head = 0, tail = 0, ha = 0, ta = 0;   // wave-uniform queue cursors
 
-          // one batch of up to 64 queued jobs, job head + lane on this lane:
-          // a job is (element, source run); its lane runs the exact test of
-          // the element on each of the run's nrecv pairs (pair q0 + k has
+          // one batch of up to 64 jobs, one per lane (where mine): a job is
+          // (element, source run); its lane runs the exact test of the
+          // element on each of the run's nrecv pairs (pair q0 + k has
           // receiver k), the element and source read once, sums the
           // element's adjoints over the run and adds them to its LDS sums
-          auto run_jobs = [&](uint32_t cnt) {
-            const bool mine = (uint32_t)lane < cnt;
-            const uint32_t job = Q[(head + (uint32_t)lane) & (kJobQ - 1)];
-            const int L = mine ? (int)(job >> 8) : lane;
+          auto exact_jobs = [&](bool mine, uint32_t job) {
+            const int L = mine ? (int)((job >> 8) & 63u) : lane;
             const int q0 = (int)(job & 0xFFu);
             const double vx = (double)__shfl(ux, L), vy = (double)__shfl(uy, L),
                          vz = (double)__shfl(uz, L);
@@ -371,6 +384,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
               }
             }
           };
+          // the queued jobs head + lane
+          auto run_jobs = [&](uint32_t cnt) {
+            exact_jobs((uint32_t)lane < cnt, Q[(head + (uint32_t)lane) & (kJobQ - 1)]);
+          };
           // the round-cone filter over up to 64 jobs of the first queue (job
           // ha + lane on this lane); the survivors go to the exact tests
           auto filter_jobs = [&](uint32_t cnt) {
@@ -389,35 +406,45 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
               head += 64u;
             }
           };
-          // the wavefront's elements as one sphere first: only the source
-          // runs that may reach it go through the per-element tests
-          elem_group(pr, hrad, has, egrp[wv]);
-          const int nruns = qend / nrecv;
-          for (int k0 = 0; k0 < nruns; k0 += kElemGroup) {
-            uint64_t gm = group_runs(egrp[wv], RT, Rm, k0, nruns, nrecv);
-            while (gm != 0ull) {
-              // four (quarter, run) pairs at a time, 16 lanes each: lane
-              // 16 i + j tests element j of its pair's quarter
-              const int pq = take_quarter_pair(&gm);
-              const int eL = pq >= 0 ? (pq >> 4) * kElemGroup + (lane & (kElemGroup - 1)) : lane;
-              const int q0 = pq >= 0 ? (k0 + (pq & (kElemGroup - 1))) * nrecv : 0;
-              const float vp[3] = {__shfl(pr[0], eL), __shfl(pr[1], eL), __shfl(pr[2], eL)};
-              const float vh = __shfl(hrad, eL);
-              const bool vhas = __shfl((int)has, eL) != 0;
-              const bool pass = pq >= 0 && vhas && elem_run_test(vp, vh, RT, Rm, q0);
-              const uint64_t m = ballot64(pass);
-              if (m == 0ull) continue;
-              if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((eL << 8) | q0);
-              ta += (uint32_t)__popcll(m);
-              wave_lds_sync();
-              while (ta - ha >= 64u) {
-                filter_jobs(64u);
-                ha += 64u;
+          if (logged) {
+            // the forward's jobs of this chunk, 64 at a time
+            for (uint32_t d = 0; d < lcnt; d += 64u) {
+              const uint32_t cnt = min(64u, lcnt - d);
+              const uint32_t job = log_get(JL, lp, cnt, (uint32_t)lane);
+              exact_jobs((uint32_t)lane < cnt && (int)(job & 0xFFu) + nrecv <= qend, job);
+            }
+          } else {
+            // the wavefront's elements as one sphere first: only the source
+            // runs that may reach it go through the per-element tests
+            elem_group(pr, hrad, has, egrp[wv]);
+            const int nruns = qend / nrecv;
+            for (int k0 = 0; k0 < nruns; k0 += kElemGroup) {
+              uint64_t gm = group_runs(egrp[wv], RT, Rm, k0, nruns, nrecv);
+              while (gm != 0ull) {
+                // four (quarter, run) pairs at a time, 16 lanes each: lane
+                // 16 i + j tests element j of its pair's quarter
+                const int pq = take_quarter_pair(&gm);
+                const int eL =
+                    pq >= 0 ? (pq >> 4) * kElemGroup + (lane & (kElemGroup - 1)) : lane;
+                const int q0 = pq >= 0 ? (k0 + (pq & (kElemGroup - 1))) * nrecv : 0;
+                const float vp[3] = {__shfl(pr[0], eL), __shfl(pr[1], eL), __shfl(pr[2], eL)};
+                const float vh = __shfl(hrad, eL);
+                const bool vhas = __shfl((int)has, eL) != 0;
+                const bool pass = pq >= 0 && vhas && elem_run_test(vp, vh, RT, Rm, q0);
+                const uint64_t m = ballot64(pass);
+                if (m == 0ull) continue;
+                if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((eL << 8) | q0);
+                ta += (uint32_t)__popcll(m);
+                wave_lds_sync();
+                while (ta - ha >= 64u) {
+                  filter_jobs(64u);
+                  ha += 64u;
+                }
               }
             }
+            if (ta > ha) filter_jobs(ta - ha);
+            if (tail > head) run_jobs(tail - head);
           }
-          if (ta > ha) filter_jobs(ta - ha);
-          if (tail > head) run_jobs(tail - head);
           wave_lds_sync();
           if (has) {
 #pragma unroll
@@ -425,6 +452,13 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
             gadd(&G.gh[l], (double)A[lane][NB]);
           }
           wave_lds_sync();
+        }
+      } else if (logged) {
+        // no pair of this pass has an adjoint: step over its jobs
+        for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
+          const uint32_t cnt =
+              (uint32_t)__builtin_amdgcn_readfirstlane((int)log_get(JL, lp, 1u, 0u));
+          log_skip(JL, lp, cnt);
         }
       }
       __syncthreads();
@@ -1278,7 +1312,7 @@ static trevr_status bwd_items_nb(const Launch& L, const Scratch& S, const BwdArg
     const void* fn = (const void*)&k_pp_src_bwd<NB>;
     k_pp_src_bwd<NB><<<persistent_grid(fn, kNT, count, L.cfg.grid_div), kNT, 0, L.st>>>(
         L.TT, Ii, S.blist, S.bscene, S.ncnt, S.nlumc, S.nidx, S.jcnt, S.pcnt, S.ptau, a.active,
-        a.gJ, a.G, a.jraw);
+        a.gJ, a.G, a.jraw, S.jlog);
     TREVR_LAUNCH_CHECK("k_pp_src_bwd");
   }
   const size_t recorded = prof ? prof->pending.size() : 0;

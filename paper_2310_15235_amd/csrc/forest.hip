@@ -51,6 +51,7 @@ struct trevr_forest {
   uint32_t cut_cap;
   uint64_t tot[trevr::TOT_N];
   size_t scratch_run;
+  size_t job_log_bytes;                // p-p job log asked for (trevr_forest_job_log)
   // the scratch holding the last batched forward state of this forest
   const void* fwd_scratch;
   uint64_t fwd_epoch;
@@ -176,6 +177,16 @@ ForestScratch forest_carve(const trevr_forest* f, void* base) {
   fs.a.G = carve_grad(gcv, dims);
   fs.gbytes = align256(gcv.off);
   fs.bwd_end = fs.gbeg + fs.gbytes + 256;
+  // the p-p job log: stream starts per bucket, the block counter, the blocks
+  const uint64_t blocks = std::min<uint64_t>(f->job_log_bytes / (2ull * kLogBlock), 0xFFFFFF00ull);
+  if (blocks > 0) {
+    Carve lcv(base ? (char*)base + fs.bwd_end : nullptr);
+    fs.S.jlog.tab = lcv.take<uint2>((size_t)4 * std::max<int64_t>(f->leaves_total, 1));
+    fs.S.jlog.next = lcv.take<uint32_t>(64);
+    fs.S.jlog.log = lcv.take<uint16_t>((size_t)blocks * kLogBlock);
+    fs.S.jlog.blocks = (uint32_t)blocks;
+    fs.bwd_end += align256(lcv.off) + 256;
+  }
   return fs;
 }
 
@@ -199,6 +210,7 @@ trevr_status forward_body(trevr_forest* f, const Scratch& S, const uint8_t* acti
                         (uint64_t)f->leaves_total, f->cut_cap)) != TREVR_OK)
     return rc;
   prof_end(P, L.st, TREVR_PROF_WALK, e);
+  if (S.jlog.log && (rc = zero_words(L.st, S.jlog.next, 1)) != TREVR_OK) return rc;
   for (int B = 1; B <= kMaxBands; ++B) {
     const uint64_t cnt = (uint64_t)f->class_leaves[B - 1];
     if (cnt == 0) continue;
@@ -420,6 +432,7 @@ trevr_status trevr_build_forest(const trevr_params* params, int32_t S, const int
   f->stack_large = false;
   f->cut_cap = kCutCap;
   f->scratch_run = 0;
+  f->job_log_bytes = 0;
   f->fwd_scratch = nullptr;
   f->fwd_epoch = 0;
   f->cfg = LaunchCfg{};
@@ -514,6 +527,14 @@ trevr_status trevr_forest_scratch_bytes(const trevr_forest* f, size_t* bytes) {
   return TREVR_OK;
 }
 
+trevr_status trevr_forest_job_log(trevr_forest* f, size_t bytes) {
+  if (!forest_live(f)) return set_error(TREVR_E_STATE, "unknown or destroyed forest");
+  f->job_log_bytes = bytes;
+  if (f->planned) f->scratch_run = forest_carve(f, nullptr).bwd_end;
+  f->fwd_scratch = nullptr;
+  return TREVR_OK;
+}
+
 trevr_status trevr_compute_J_batched(trevr_forest* f, const uint8_t* active, const float* bg,
                                      double* J, void* scratch, size_t scratch_bytes,
                                      void* stream) {
@@ -594,6 +615,7 @@ trevr_status trevr_forest_get_counters(trevr_forest* f, int32_t scene, trevr_cou
     o->max_cut = std::max(o->max_cut, c.max_cut);
     o->max_stack = std::max(o->max_stack, c.max_stack);
     o->near_src_hits += c.near_src_hits;
+    o->pp_log_entries += c.pp_log_entries;
   }
   return TREVR_OK;
 }

@@ -381,6 +381,120 @@ constexpr uint32_t kJobQ = 128;
 // a third.
 constexpr uint32_t kPpElementMajor = 256;
 
+// ---------------------------------------------------------- p-p job log
+// The forward's element-major p-p source sweep can keep for the adjoint the
+// jobs that passed its culling tests, so that the adjoint runs only the
+// exact tests (the decisions are the same on both sides: the same tests on
+// the same values).  Each wavefront writes one stream of 16-bit entries:
+// per pass and chunk of kNT p-p elements, the number of the wavefront's jobs
+// in it, then the jobs (element lane << 8 | first pair of the source run).
+// A stream lives in blocks of kLogBlock entries taken from a device counter
+// as it grows; the last two entries of a block hold the index of the
+// stream's next block.  tab[4 bucket + wave] is where a bucket's stream
+// starts (block, entry); block kLogNone in tab[4 bucket] marks a bucket the
+// log does not cover (a pair-major receiver chunk, or no block left), which
+// the adjoint culls again itself.
+constexpr uint32_t kLogBlock = 1u << 14;
+constexpr uint32_t kLogData = kLogBlock - 2;   // entries per block before the link
+constexpr uint32_t kLogNone = 0xFFFFFFFFu;     // no block: the stream is dead
+constexpr uint32_t kLogFresh = 0xFFFFFFFEu;    // no block taken yet
+
+struct JobLog {
+  uint16_t* log;       // blocks * kLogBlock entries (null: no log)
+  uint2* tab;          // [bucket][4] stream starts
+  uint32_t* next;      // blocks taken (zeroed before the forward)
+  uint32_t blocks;
+};
+
+// A wavefront's place in its stream (wave-uniform).
+struct LogPos {
+  uint32_t blk, pos;
+};
+
+// A new block for the stream (kLogNone when none is left); the whole
+// wavefront calls it.
+__device__ inline uint32_t log_take_block(const JobLog& J) {
+  uint32_t b = 0;
+  if ((threadIdx.x & 63) == 0) b = atomicAdd(J.next, 1u);
+  b = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)b, 0));
+  return b < J.blocks ? b : kLogNone;
+}
+
+// Makes the stream writable at p (takes its first block); false if dead.
+__device__ inline bool log_ready(const JobLog& J, LogPos& p) {
+  if (p.blk == kLogFresh) {
+    p.blk = log_take_block(J);
+    p.pos = 0;
+  }
+  return p.blk != kLogNone;
+}
+
+// Appends cnt <= 64 entries (wave-uniform): entry k is v of the lane that
+// has it (mine).  Returns the index in the log of entry 0 (for a later
+// rewrite), or ~0 when the stream is dead.
+__device__ inline size_t log_put(const JobLog& J, LogPos& p, uint32_t cnt, bool mine, uint32_t k,
+                                 uint16_t v) {
+  if (!log_ready(J, p)) return ~(size_t)0;
+  uint32_t nb = p.blk;
+  if (p.pos + cnt > kLogData) {
+    nb = log_take_block(J);
+    if ((threadIdx.x & 63) == 0) {
+      J.log[(size_t)p.blk * kLogBlock + kLogData] = (uint16_t)(nb & 0xFFFFu);
+      J.log[(size_t)p.blk * kLogBlock + kLogData + 1] = (uint16_t)(nb >> 16);
+    }
+  }
+  const size_t first = p.pos < kLogData ? (size_t)p.blk * kLogBlock + p.pos
+                       : nb != kLogNone ? (size_t)nb * kLogBlock : ~(size_t)0;
+  if (mine) {
+    const uint32_t e = p.pos + k;
+    if (e < kLogData) J.log[(size_t)p.blk * kLogBlock + e] = v;
+    else if (nb != kLogNone) J.log[(size_t)nb * kLogBlock + (e - kLogData)] = v;
+  }
+  if (p.pos + cnt > kLogData) {
+    p.pos = p.pos + cnt - kLogData;
+    p.blk = nb;
+  } else {
+    p.pos += cnt;
+  }
+  return first;
+}
+
+// The stream's next block after p.blk (the link the writer left), kept in
+// range.
+__device__ inline uint32_t log_link(const JobLog& J, uint32_t blk) {
+  const uint32_t b = (uint32_t)J.log[(size_t)blk * kLogBlock + kLogData] |
+                     ((uint32_t)J.log[(size_t)blk * kLogBlock + kLogData + 1] << 16);
+  return b < J.blocks ? b : 0u;
+}
+
+// Reads cnt <= 64 entries (wave-uniform): lane k < cnt gets entry k.
+__device__ inline uint32_t log_get(const JobLog& J, LogPos& p, uint32_t cnt, uint32_t k) {
+  const uint32_t nb = p.pos + cnt > kLogData ? log_link(J, p.blk) : p.blk;
+  uint32_t v = 0;
+  if (k < cnt) {
+    const uint32_t e = p.pos + k;
+    v = e < kLogData ? J.log[(size_t)p.blk * kLogBlock + e]
+                     : J.log[(size_t)nb * kLogBlock + (e - kLogData)];
+  }
+  if (p.pos + cnt > kLogData) {
+    p.pos = p.pos + cnt - kLogData;
+    p.blk = nb;
+  } else {
+    p.pos += cnt;
+  }
+  return v;
+}
+
+// Skips cnt entries (wave-uniform).
+__device__ inline void log_skip(const JobLog& J, LogPos& p, uint32_t cnt) {
+  while (p.pos + cnt > kLogData) {
+    cnt -= kLogData - p.pos;
+    p.blk = log_link(J, p.blk);
+    p.pos = 0;
+  }
+  p.pos += cnt;
+}
+
 
 // Per source run of an element-major p-p sweep (LDS, one entry per pair,
 // read at the run's first pair): s = jr the source relative to the bucket

@@ -48,6 +48,7 @@ struct Scratch {
   float* tpp;
   float* ptau;                  // optical depth per (receiver, p-p source) pair and band
   float *kept_tau, *kept_tex;   // far-source optical depths kept for the adjoint (or null)
+  JobLog jlog;                  // p-p job log of a forest (log null: none)
   size_t fixed;                 // bytes of the fixed part
 };
 

@@ -43,7 +43,7 @@ enum : uint32_t {
 // Counter slots (uint64 on the device).
 enum { CNT_BUCKETS = 0, CNT_CELLS, CNT_ABS, CNT_SRC, CNT_SEG, CNT_NEAR_PAIRS, CNT_MAX_NEAR,
        CNT_NODES, CNT_SRC_PAIRS, CNT_NS_TRIPLES, CNT_MAX_CUT, CNT_MAX_STACK, CNT_NS_HITS,
-       CNT_N = 16 };
+       CNT_PP_LOG, CNT_N = 16 };
 
 // Device view of a tree (all pointers into the caller's tree workspace).
 struct DevTree {

@@ -83,6 +83,7 @@ int main() {
     size_t sz;
     expect(trevr_forest_check(fb) == TREVR_E_STATE, "check unknown forest");
     expect(trevr_forest_plan_bytes(fb, &sz) == TREVR_E_STATE, "plan bytes unknown forest");
+    expect(trevr_forest_job_log(fb, 1u << 20) == TREVR_E_STATE, "job log unknown forest");
     expect(trevr_forest_destroy(fb) == TREVR_E_STATE, "destroy unknown forest");
   }
   // forest sizing and validation

@@ -128,4 +128,5 @@ def test_unknown_forest_handle_rejected():
     assert L.trevr_forest_check(bogus) == api.E_STATE
     assert L.trevr_forest_destroy(bogus) == api.E_STATE
     assert L.trevr_forest_plan_bytes(bogus, ctypes.byref(sz)) == api.E_STATE
+    assert L.trevr_forest_job_log(bogus, 1 << 20) == api.E_STATE
     assert L.trevr_compute_J_batched(bogus, None, None, None, None, 0, None) == api.E_STATE

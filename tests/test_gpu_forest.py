@@ -289,6 +289,74 @@ def test_forest_graph_of_forward_and_adjoint():
     F.close()
 
 
+def _log_scenes():
+    """Small mixed scenes plus p-p sets of thousands (log-normal, N_side 4)
+    and two receiver chunks per bucket (leaf size 12)."""
+    return mixed_scenes()[:4] + [
+        scenes.lognormal_scene(n=2 ** 13, seed=21, grid=16, bands=(1.0, 10.0), nside=4),
+        scenes.lognormal_scene(n=3000, seed=22, grid=16, bands=(1.0,), nside=2, leaf_size=12),
+    ]
+
+
+def test_forest_job_log_gives_the_same_results():
+    """With the p-p job log the adjoint runs the forward's own jobs instead
+    of culling again: J, gL, gkappa and grho equal those without the log (to
+    FP32 rounding of atomic sums) -- with room for every bucket, with room
+    for a few (most buckets culled again), on the backward that recomputes
+    the forward state, and in a replayed HIP graph of both calls."""
+    api = _api()
+    import torch
+    scs = _log_scenes()
+    F = api.Forest(scs)
+    acts = _actives(scs, 0.6, seed=31)
+    a = F.flat_active(acts)
+    gJ = torch.as_tensor(np.random.default_rng(9).normal(size=int(F.boff[-1])), device="cuda")
+    J0 = F.compute_J(a).cpu().numpy()
+    g0 = [t.cpu().numpy() for t in F.compute_J_backward(gJ, a)]
+    F.check()
+    c0 = F.counters(-1)
+    need = c0["pp_log_entries"]
+    assert need > 0
+
+    def same(J, g):
+        assert np.max(_rel(J, J0)) <= SAME_TOL
+        for x, y in zip(g, g0):
+            _close(x, y, 1e-5)
+
+    for nbytes in (2 * need + (64 << 20), 6 * 32768):
+        F.set_job_log(nbytes)
+        J = F.compute_J(a).cpu().numpy()
+        g = [t.cpu().numpy() for t in F.compute_J_backward(gJ, a)]
+        F.check()
+        same(J, g)
+        assert F.counters(-1) == c0
+    # a backward with no forward state before it writes and reads the log itself
+    F.set_job_log(2 * need + (64 << 20))
+    same(J0, [t.cpu().numpy() for t in F.compute_J_backward(gJ, a)])
+    F.check()
+    # graph of forward and adjoint, replayed with other work between replays
+    Jd = F.new_J()
+    outs = (torch.empty_like(gJ), torch.empty_like(gJ),
+            torch.empty(int(F.offsets[-1]), dtype=torch.float64, device="cuda"))
+    F.compute_J(a, out=Jd)
+    F.compute_J_backward(gJ, a, out=outs)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        F.compute_J(a, out=Jd)
+        F.compute_J_backward(gJ, a, out=outs)
+    for rep in range(3):
+        Jd.zero_()
+        for t in outs:
+            t.zero_()
+        gr.replay()
+        torch.cuda.synchronize()
+        F.check()
+        same(Jd.cpu().numpy(), [t.cpu().numpy() for t in outs])
+        F.compute_J(F.flat_active(_actives(scs, 1.0, 0)))   # eager work between replays
+    F.close()
+
+
 def test_forest_launch_configurations_agree_and_autotune_picks_one():
     """Every launch configuration of the autotuner gives the same J (to FP32
     rounding of atomic sums) and the same gradients; the autotuner times all
