@@ -726,9 +726,13 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             const uint32_t qj = pd_j[q0];
             const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
             const double ff = f0 * f0 + f1 * f1 + f2 * f2;
+            // two receivers per step, every condition evaluated: their LDS
+            // reads issue together instead of one wait per condition
+            // (forward p-p sources 582 -> 568 ms on the batched workload;
+            // unrolled fully, the spills cost more than the waits)
+#pragma unroll 2
             for (int k = 0; k < nrecv; ++k) {
               const int q = q0 + k;
-              if (!pd_valid[q]) continue;
               const RecvInfo& rq = recv[k];
               const double pe0 = qx0 - rq.x[0], pe1 = qx1 - rq.x[1], pe2 = qx2 - rq.x[2];
               const double w0 = vx - rq.x[0], w1 = vy - rq.x[1], w2 = vz - rq.x[2];
@@ -736,7 +740,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               uu = fmin(1.0, fmax(0.0, uu));
               const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
               const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-              if (ff < pd_r2[q] && b2 < vh2 && vl != rq.slot && vl != qj) {
+              if ((pd_valid[q] != 0) & (ff < pd_r2[q]) & (b2 < vh2) & (vl != rq.slot) &
+                  (vl != qj)) {
                 ++hits;
                 const float bb = sqrtf((float)b2);
                 const float sg = vsig * (1.0f - bb * viv);
@@ -804,7 +809,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               const float vp[3] = {__shfl(pr[0], eL), __shfl(pr[1], eL), __shfl(pr[2], eL)};
               const float vh = __shfl(hrad, eL);
               const bool vhas = __shfl((int)has, eL) != 0;
-              const bool pass = pq >= 0 && vhas && elem_run_test(vp, vh, RT, Rm, q0);
+              const bool pass = (pq >= 0) & vhas & elem_run_test(vp, vh, RT, Rm, q0);
               const uint64_t m = ballot64(pass);
               if (m == 0ull) continue;
               if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((eL << 8) | q0);

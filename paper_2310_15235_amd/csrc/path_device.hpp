@@ -624,7 +624,7 @@ __device__ inline uint64_t group_runs(const float (*G)[5], const RunTab& RT, flo
                                fabsf(s[1]) + fabsf(s[2]));
     const float f0 = g[0] - s[0], f1 = g[1] - s[1], f2 = g[2] - s[2];
     const float r2 = (RT.lim[q] + rp) * (1.0f + 1e-4f) + tol;
-    pass = f0 * f0 + f1 * f1 + f2 * f2 <= r2 * r2 &&
+    pass = (f0 * f0 + f1 * f1 + f2 * f2 <= r2 * r2) &
            round_cone(g, s, RT.jinv[q], RT.k2[q], RT.m2[q], R, rr * (1.0f + 1e-4f) + R, tol);
   }
   return ballot64(pass);
@@ -659,8 +659,9 @@ __device__ inline bool elem_run_test(const float pr[3], float hrad, const RunTab
   tt = fminf(1.0f, fmaxf(0.0f, tt));
   const float d0 = pr[0] - tt * s0, d1 = pr[1] - tt * s1, d2 = pr[2] - tt * s2;
   const float rad = hrad + R, lim = RT.lim[q];
-  return f0 * f0 + f1 * f1 + f2 * f2 <= lim * lim * (1.0f + 1e-4f) &&
-         d0 * d0 + d1 * d1 + d2 * d2 <= rad * rad;
+  // both conditions evaluated (no branch between their LDS reads)
+  return (f0 * f0 + f1 * f1 + f2 * f2 <= lim * lim * (1.0f + 1e-4f)) &
+         (d0 * d0 + d1 * d1 + d2 * d2 <= rad * rad);
 }
 
 // The queued (element, source run) jobs that also pass the round cone
