@@ -425,23 +425,25 @@ __global__ void __launch_bounds__(64) k_walk(const DevTree* __restrict__ TT, Ite
 // Sigma -> 0 at b = h): kappa_l Sigma_l(b), Sigma_l(b) = 3 m_l/(pi h_l^2)
 // (1 - b/h_l).  Written to tpp[receiver][ray][band] for the far field.
 //
-// Element-major: per receiver chunk and group of 64 rays, threads take
-// (p-p element, receiver) pairs; a pair tests only the group's rays in the
-// element's ring range (and the directed ray), first with a conservative
-// FP32 test, then with the exact FP64 one, and adds each hit's kappa Sigma
-// to the (receiver, ray) sums in LDS, written out once per group.
+// Element-major: per receiver chunk and group of rays (all of them up to
+// N_side 4 and four bands, else 64), threads take (p-p element, receiver)
+// pairs; a pair tests only the group's rays in the element's ring range (and
+// the directed ray), 64 at a time first with a conservative FP32 test, then
+// with the exact FP64 one, and adds each hit's kappa Sigma to the (receiver,
+// ray) sums in LDS, written out once per group.
 template <int NB>
 __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT, Items I,
                                                 const uint32_t* blist, const uint32_t* bscene,
                                                 const uint32_t* noff, const uint32_t* nidx,
                                                 const uint32_t* toff, const uint8_t* active,
                                                 float* tpp) {
+  constexpr int RGN = PpRayGroup<NB>::value;
   const int t = threadIdx.x;
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s, s_item;
-  __shared__ double rn[64][3];
-  __shared__ float rnf[64][3];
-  __shared__ float acc[kRMax][64][NB];
+  __shared__ double rn[RGN][3];
+  __shared__ float rnf[RGN][3];
+  __shared__ float acc[kRMax][RGN][NB];
   for (;;) {
   const uint32_t bucket = next_item(I, &s_item);
   if (bucket == kNoItem) break;
@@ -463,8 +465,8 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
   for (;;) {
     const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
-    for (int k0 = 0; k0 < nray; k0 += 64) {
-      const int kn = min(64, nray - k0);
+    for (int k0 = 0; k0 < nray; k0 += RGN) {
+      const int kn = min(RGN, nray - k0);
       // the directed ray, when it is in this group: its direction is not a
       // HEALPix centre, so it is tested whatever the ring range
       const int kdg = (kd >= k0 && kd < k0 + kn) ? kd - k0 : -1;
@@ -477,7 +479,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
           rnf[t][a] = (float)na;
         }
       }
-      for (int q = t; q < kRMax * 64 * NB; q += kNT) (&acc[0][0][0])[q] = 0.0f;
+      for (int q = t; q < kRMax * RGN * NB; q += kNT) (&acc[0][0][0])[q] = 0.0f;
       __syncthreads();
       for (uint32_t pq = (uint32_t)t; pq < nnear * (uint32_t)nrecv; pq += kNT) {
         const uint32_t u = pq / (uint32_t)nrecv;
@@ -496,31 +498,39 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
         const float neg = -1e-5f * sqrtf(ddf);
         int ka, kb;
         ray_ring_range(T.nside, d0, d1, d2, dd, h2, &ka, &kb);
-        uint64_t cand = 0ull;
-        for (int kq = max(ka - k0, 0); kq < min(kb - k0, kn); ++kq) {
-          const float pf = rnf[kq][0] * df[0] + rnf[kq][1] * df[1] + rnf[kq][2] * df[2];
-          if (pf > neg && pf * pf >= lim) cand |= 1ull << kq;
-        }
-        if (kdg >= 0) {
-          const float pf = rnf[kdg][0] * df[0] + rnf[kdg][1] * df[1] + rnf[kdg][2] * df[2];
-          if (pf > neg && pf * pf >= lim) cand |= 1ull << kdg;
-        }
-        if (cand == 0ull) continue;
-        const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-        const float iv = (float)(1.0 / hl);
-        float kap[NB];
+        const int lo = max(ka - k0, 0), hi = min(kb - k0, kn);
+        bool loaded = false;
+        float sig = 0.0f, iv = 0.0f, kap[NB];
+        // candidates 64 rays at a time: the FP32 test, then the exact one
+        for (int s0 = 0; s0 < kn; s0 += 64) {
+          uint64_t cand = 0ull;
+          for (int kq = max(lo, s0); kq < min(hi, s0 + 64); ++kq) {
+            const float pf = rnf[kq][0] * df[0] + rnf[kq][1] * df[1] + rnf[kq][2] * df[2];
+            if (pf > neg && pf * pf >= lim) cand |= 1ull << (kq - s0);
+          }
+          if (kdg >= s0 && kdg < s0 + 64) {
+            const float pf = rnf[kdg][0] * df[0] + rnf[kdg][1] * df[1] + rnf[kdg][2] * df[2];
+            if (pf > neg && pf * pf >= lim) cand |= 1ull << (kdg - s0);
+          }
+          if (cand == 0ull) continue;
+          if (!loaded) {
+            sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
+            iv = (float)(1.0 / hl);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
-        while (cand) {
-          const int kq = __ffsll((long long)cand) - 1;
-          cand &= cand - 1ull;
-          const double proj = d0 * rn[kq][0] + d1 * rn[kq][1] + d2 * rn[kq][2];
-          const double b2 = dd - proj * proj;
-          if (!(proj > 0.0 && b2 < h2)) continue;
-          const float bb = sqrtf((float)fmax(b2, 0.0));
-          const float sg = sig * (1.0f - bb * iv);
+            for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
+            loaded = true;
+          }
+          while (cand) {
+            const int kq = s0 + __ffsll((long long)cand) - 1;
+            cand &= cand - 1ull;
+            const double proj = d0 * rn[kq][0] + d1 * rn[kq][1] + d2 * rn[kq][2];
+            const double b2 = dd - proj * proj;
+            if (!(proj > 0.0 && b2 < h2)) continue;
+            const float bb = sqrtf((float)fmax(b2, 0.0));
+            const float sg = sig * (1.0f - bb * iv);
 #pragma unroll
-          for (int b = 0; b < NB; ++b) atomicAdd(&acc[i][kq][b], kap[b] * sg);
+            for (int b = 0; b < NB; ++b) atomicAdd(&acc[i][kq][b], kap[b] * sg);
+          }
         }
       }
       __syncthreads();

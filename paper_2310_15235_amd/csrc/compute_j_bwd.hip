@@ -490,12 +490,12 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
 // Adjoint of k_pp_rays: tau_ikb = sum_l kappa_lb Sigma_l(b_ilk) with the
 // adjoint g_ikb of the far-field kernel: dkappa_lb += g Sigma, dh_l +=
 // g kappa_lb dSigma/dh.  Element-major: threads take (p-p element l,
-// receiver i) pairs and mark the rays of a group of 64 that a conservative
-// FP32 test cannot rule out (within h_l of l), then run the exact FP64 test
-// (the forward's operation sequence) over their own marked rays only; each thread
-// sums its pair's contributions in registers, one LDS atomic per pair
-// collects them per element, one FP64 atomic per element and group writes
-// them out.
+// receiver i) pairs and, per group of rays (as in the forward) 64 at a time,
+// mark the rays that a conservative FP32 test cannot rule out (within h_l of
+// l), then run the exact FP64 test (the forward's operation sequence) over
+// their own marked rays only; each thread sums its pair's contributions in
+// registers, one LDS atomic per pair collects them per element, one FP64
+// atomic per element and group writes them out.
 constexpr int kPRChunk = 256;   // p-p elements per LDS chunk
 
 template <int NB>
@@ -504,11 +504,13 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
                                                     const uint32_t* noff, const uint32_t* nidx,
                                                     const uint32_t* toff, const uint8_t* active,
                                                     const float* gtppg, Grad Gall) {
+  constexpr int RGN = PpRayGroup<NB>::value;
   const int t = threadIdx.x;
   __shared__ RecvInfo recv[kRMax];
   __shared__ uint32_t nrecv_s, s_item;
-  __shared__ RayGroup RG;
-  __shared__ float g[kRMax][64][NB];
+  __shared__ double rn[RGN][3];
+  __shared__ float rnf[RGN][3];
+  __shared__ float g[kRMax][RGN][NB];
   __shared__ float ek[kPRChunk][NB], eh[kPRChunk];
   __shared__ int gz;
   for (;;) {
@@ -526,20 +528,28 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
   const uint2 lk = T.nlink[leafb];
   const int nray = T.nray;
   const int64_t n = T.n;
+  double ud[3];
+  const int kd = directed_ray(T, c, ud);   // the bucket's directed ray, if any
   uint32_t ract = 0;
   uint32_t member = lk.x;
   for (;;) {
     const int nrecv = load_receivers(T, act, c, member, lk.x + lk.y, recv, &nrecv_s);
     if (nrecv == 0) break;
-    for (int k0 = 0; k0 < nray; k0 += 64) {
-      const int kn = min(64, nray - k0);
+    for (int k0 = 0; k0 < nray; k0 += RGN) {
+      const int kn = min(RGN, nray - k0);
       // the directed ray, when it is in this group: its direction is not a
       // HEALPix centre, so it is tested whatever the ring range
-      double ud[3];
-      const int kd = directed_ray(T, c, ud);
       const int kdg = (kd >= k0 && kd < k0 + kn) ? kd - k0 : -1;
       if (t == 0) gz = 0;
-      load_ray_group(T, c, k0, kn, RG);
+      if (t < kn) {
+        const int k = k0 + t;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double na = (k == kd) ? ud[a] : T.ray_n[3 * k + a];
+          rn[t][a] = na;
+          rnf[t][a] = (float)na;
+        }
+      }
       __syncthreads();
       int nz = 0;
       for (int q = t; q < nrecv * kn; q += kNT) {
@@ -582,39 +592,42 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
           float kap[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
+          int ka, kb;
+          ray_ring_range(T.nside, d0, d1, d2, dd, h2, &ka, &kb);
+          const int lo = max(ka - k0, 0), hi = min(kb - k0, kn);
           float ck[NB], gh = 0.0f;
 #pragma unroll
           for (int b = 0; b < NB; ++b) ck[b] = 0.0f;
           // the FP32 test over the group's rays in the element's ring range
-          // (and the directed ray) first, then the exact test for this
-          // lane's candidates only (in ray order)
-          int ka, kb;
-          ray_ring_range(T.nside, d0, d1, d2, dd, h2, &ka, &kb);
-          uint64_t cand = 0ull;
-          for (int kq = max(ka - k0, 0); kq < min(kb - k0, kn); ++kq) {
-            const float pf = RG.nf[kq][0] * df[0] + RG.nf[kq][1] * df[1] + RG.nf[kq][2] * df[2];
-            if (pf > neg && pf * pf >= lim) cand |= 1ull << kq;
-          }
-          if (kdg >= 0) {
-            const float pf = RG.nf[kdg][0] * df[0] + RG.nf[kdg][1] * df[1] + RG.nf[kdg][2] * df[2];
-            if (pf > neg && pf * pf >= lim) cand |= 1ull << kdg;
-          }
-          while (cand) {
-            const int kq = __ffsll((long long)cand) - 1;
-            cand &= cand - 1ull;
-            const double proj = d0 * RG.n[kq][0] + d1 * RG.n[kq][1] + d2 * RG.n[kq][2];
-            const double b2 = dd - proj * proj;
-            if (!(proj > 0.0 && b2 < h2)) continue;
-            const float bb = sqrtf((float)fmax(b2, 0.0));
-            const float sg = sig * (1.0f - bb * iv);
-            const float dsg = sig * iv * (3.0f * bb * iv - 2.0f);
-            float gq = 0.0f;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              ck[b] += g[i][kq][b] * sg;
-              gq += g[i][kq][b] * kap[b];
+          // (and the directed ray) first, 64 rays at a time, then the exact
+          // test for this lane's candidates only (in ray order)
+          for (int s0 = 0; s0 < kn; s0 += 64) {
+            uint64_t cand = 0ull;
+            for (int kq = max(lo, s0); kq < min(hi, s0 + 64); ++kq) {
+              const float pf = rnf[kq][0] * df[0] + rnf[kq][1] * df[1] + rnf[kq][2] * df[2];
+              if (pf > neg && pf * pf >= lim) cand |= 1ull << (kq - s0);
             }
-            gh += gq * dsg;
+            if (kdg >= s0 && kdg < s0 + 64) {
+              const float pf = rnf[kdg][0] * df[0] + rnf[kdg][1] * df[1] + rnf[kdg][2] * df[2];
+              if (pf > neg && pf * pf >= lim) cand |= 1ull << (kdg - s0);
+            }
+            while (cand) {
+              const int kq = s0 + __ffsll((long long)cand) - 1;
+              cand &= cand - 1ull;
+              const double proj = d0 * rn[kq][0] + d1 * rn[kq][1] + d2 * rn[kq][2];
+              const double b2 = dd - proj * proj;
+              if (!(proj > 0.0 && b2 < h2)) continue;
+              const float bb = sqrtf((float)fmax(b2, 0.0));
+              const float sg = sig * (1.0f - bb * iv);
+              const float dsg = sig * iv * (3.0f * bb * iv - 2.0f);
+              float gq = 0.0f;
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                ck[b] += g[i][kq][b] * sg;
+                gq += g[i][kq][b] * kap[b];
+              }
+              gh += gq * dsg;
+            }
           }
 #pragma unroll
           for (int b = 0; b < NB; ++b)

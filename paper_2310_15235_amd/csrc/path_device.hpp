@@ -888,6 +888,14 @@ __device__ inline void ray_ring_range(int N, double d0, double d1, double d2, do
   *kb = ring_start(N, i1 + 1);
 }
 
+// Rays per group of the p-p column kernels.  Their pair loop computes each
+// (p-p element, receiver) pair's ring range and loads its element once per
+// group, so a group holds every ray up to N_side 4 where the LDS sums of a
+// group allow it (up to four bands); the candidate masks stay 64 rays wide.
+template <int NB> struct PpRayGroup {
+  static constexpr int value = NB <= 4 ? 192 : 64;
+};
+
 struct RayGroup {
   double n[64][3], inv[64][3];
   float nf[64][3];
