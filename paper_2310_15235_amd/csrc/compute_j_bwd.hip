@@ -320,8 +320,10 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
           const float pr[3] = {(float)((double)ux - c[0]), (float)((double)uy - c[1]),
                                (float)((double)uz - c[2])};
-          const float hrad = (float)hl * (1.0f + 1e-5f) +
-                             1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]));
+          // no element: a NaN size, which fails every element test
+          const float hrad = has ? (float)hl * (1.0f + 1e-5f) +
+                                       1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]))
+                                 : __int_as_float(0x7fc00000);
 #pragma unroll
           for (int b = 0; b <= NB; ++b) A[lane][b] = 0.0f;
           uint32_t head = 0, tail = 0, ha = 0, ta = 0;   // wave-uniform queue cursors
@@ -433,8 +435,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
                 const int q0 = pq >= 0 ? (k0 + (pq & (kElemGroup - 1))) * nrecv : 0;
                 const float vp[3] = {__shfl(pr[0], eL), __shfl(pr[1], eL), __shfl(pr[2], eL)};
                 const float vh = __shfl(hrad, eL);
-                const bool vhas = __shfl((int)has, eL) != 0;
-                const bool pass = (pq >= 0) & vhas & elem_run_test(vp, vh, RT, Rm, q0);
+                const bool pass = (pq >= 0) & elem_run_test(vp, vh, RT, Rm, q0);
                 const uint64_t m = ballot64(pass);
                 if (m == 0ull) continue;
                 if (pass) QA[(ta + (uint32_t)mbcnt(m)) & (kJobQ - 1)] = (uint16_t)((eL << 8) | q0);

@@ -643,14 +643,15 @@ __device__ inline int take_quarter_pair(uint64_t* gm) {
   }
   *gm = m;
   const int i = (int)(threadIdx.x & 63) / kElemGroup;
-  return i == 0 ? b[0] : i == 1 ? b[1] : i == 2 ? b[2] : b[3];
+  const int r01 = (i & 1) ? b[1] : b[0], r23 = (i & 1) ? b[3] : b[2];
+  return (i & 2) ? r23 : r01;
 }
 
 // The per-element test of an element-major sweep against source run q (its
 // first pair): no farther from the source than lim, and within hrad
 // + R of the centre's segment to the source (the cylinder around the round
 // cone, cheaper to test); a superset of the elements the exact test finds
-// on any of the run's pairs.
+// on any of the run's pairs.  A NaN hrad (a lane without an element) fails.
 __device__ inline bool elem_run_test(const float pr[3], float hrad, const RunTab& RT, float R,
                                      int q) {
   const float s0 = RT.jr[q][0], s1 = RT.jr[q][1], s2 = RT.jr[q][2];
