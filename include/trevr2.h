@@ -142,9 +142,9 @@ typedef struct trevr_counters {
   int64_t pp_log_entries;   /* 16-bit entries a forest's p-p job log needs for
                                the element-major p-p source sweep: one per
                                (p-p element, source) job that passes its
-                               culling tests, one per pass and wavefront
-                               chunk of 64 p-p elements (see
-                               trevr_forest_job_log)                          */
+                               culling tests, three per wavefront chunk of 64
+                               p-p elements with such jobs, one per pass and
+                               wavefront (see trevr_forest_job_log)           */
 } trevr_counters;
 
 typedef struct trevr_tree trevr_tree; /* opaque host handle */

@@ -653,7 +653,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
     const uint32_t si = ri.slot;
     const bool em = nnear >= kPpElementMajor || (uint32_t)nrecv * nl <= (uint32_t)kNT;
     if (JL.log) {
-      if (!em && t == 0) s_logbad = 1u;
+      if ((!em || nnear >= kLogMaxNear) && t == 0) s_logbad = 1u;
       if (em && lbeg.blk == kLogNone && log_ready(JL, lp)) lbeg = lp;
     }
     float reach = 0.0f;   // largest receiver distance from the centre
@@ -718,6 +718,11 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
         uint32_t* XL = U.JQ.xl[wv];
         uint8_t* XQ = U.JQ.xq[wv];
         uint32_t head = 0, tail = 0;   // the exact-test queue, kept across chunks
+        // the job log: this pass's number of records (written at its end),
+        // then per chunk with jobs a record and the jobs as they pass the
+        // round cone
+        const size_t lpass = JL.log ? log_put(JL, lp, 1u, lane == 0, 0u, 0) : ~(size_t)0;
+        uint32_t nrec = 0, cnext = 0;
         // one batch of up to 64 queued exact-test jobs, job head + lane on
         // this lane: a job is (element, source run); its lane reads the
         // element and runs the exact test on each of the run's nrecv pairs
@@ -786,10 +791,8 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
           U.JQ.el[wv][lane] = l;
           wave_lds_sync();
           uint32_t ha = 0, ta = 0;   // wave-uniform cursors of the first queue
-          // the job log: this chunk's count first (written when known), then
-          // its jobs as they pass the round cone
-          uint32_t lcnt = 0;
-          const size_t lhead = JL.log ? log_put(JL, lp, 1u, lane == 0, 0u, 0) : ~(size_t)0;
+          uint32_t lcnt = 0;             // this chunk's jobs
+          size_t lrec = ~(size_t)0;      // its record
           // the round-cone filter over up to 64 jobs of the first queue (job
           // ha + lane on this lane); the survivors go to the exact tests
           auto filter_jobs = [&](uint32_t cnt) {
@@ -809,9 +812,11 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               XQ[slot] = (uint8_t)q0;
             }
             tail += (uint32_t)__popcll(m);
-            lcnt += (uint32_t)__popcll(m);
-            if (JL.log && m != 0ull)
+            if (JL.log && m != 0ull) {
+              if (lcnt == 0u) lrec = log_record(JL, lp);
               log_put(JL, lp, (uint32_t)__popcll(m), keep, (uint32_t)mbcnt(m), job);
+            }
+            lcnt += (uint32_t)__popcll(m);
             wave_lds_sync();
             while (tail - head >= 64u) {
               run_jobs(64u);
@@ -846,11 +851,21 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             }
           }
           if (ta > ha) filter_jobs(ta - ha);
-          if (lhead != ~(size_t)0 && lane == 0) JL.log[lhead] = (uint16_t)lcnt;
-          logn += 1u + lcnt;
+          if (lcnt != 0u) {
+            const uint32_t cc = c0 / (uint32_t)kNT;
+            if (lrec != ~(size_t)0 && lane == 0) {
+              JL.log[lrec] = (uint16_t)(cc - cnext);
+              JL.log[lrec + 1] = (uint16_t)lcnt;
+            }
+            cnext = cc + 1u;
+            ++nrec;
+            logn += 3u + lcnt;   // the record, a block end it may skip, the jobs
+          }
           wave_lds_sync();
         }
         if (tail > head) run_jobs(tail - head);
+        if (lpass != ~(size_t)0 && lane == 0) JL.log[lpass] = (uint16_t)nrec;
+        logn += 1u;
         wave_lds_sync();
         __syncthreads();
       } else

@@ -297,12 +297,28 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
         // (the reach at the centre, none at the source).
         // Passing (element, source run) jobs are queued per wavefront and
         // run 64 at a time, so the exact FP64 tests keep every lane busy.
+        // logged: the pass's records, one per chunk with jobs of this
+        // wavefront, in chunk order (rc: the next one's chunk, rcnt: its jobs)
+        uint32_t rleft = 0, rc = kLogNone, rcnt = 0, cnext = 0;
+        auto next_record = [&]() {
+          rc = kLogNone;
+          if (rleft == 0u) return;
+          --rleft;
+          const uint32_t e2 = log_get_record(JL, lp, (uint32_t)lane);
+          rc = cnext + (uint32_t)__builtin_amdgcn_readlane((int)e2, 0);
+          rcnt = (uint32_t)__builtin_amdgcn_readlane((int)e2, 1);
+          cnext = rc + 1u;
+        };
+        if (logged) {
+          rleft = (uint32_t)__builtin_amdgcn_readfirstlane((int)log_get(JL, lp, 1u, 0u));
+          next_record();
+        }
         for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
-          // logged: the wavefront's jobs in this chunk (none: nothing to do)
+          // logged: only the chunks with jobs of this wavefront
           uint32_t lcnt = 0;
           if (logged) {
-            lcnt = (uint32_t)__builtin_amdgcn_readfirstlane((int)log_get(JL, lp, 1u, 0u));
-            if (lcnt == 0u) continue;
+            if (c0 / (uint32_t)kNT != rc) continue;
+            lcnt = rcnt;
           }
           const uint32_t u = c0 + (uint32_t)t;
           const bool has = u < nnear;
@@ -457,13 +473,19 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
             gadd(&G.gh[l], (double)A[lane][NB]);
           }
           wave_lds_sync();
+          if (logged) next_record();
+        }
+        // records of chunks past the set (none in a log the forward wrote)
+        while (logged && rc != kLogNone) {
+          log_skip(JL, lp, rcnt);
+          next_record();
         }
       } else if (logged) {
-        // no pair of this pass has an adjoint: step over its jobs
-        for (uint32_t c0 = 0; c0 < nnear; c0 += kNT) {
-          const uint32_t cnt =
-              (uint32_t)__builtin_amdgcn_readfirstlane((int)log_get(JL, lp, 1u, 0u));
-          log_skip(JL, lp, cnt);
+        // no pair of this pass has an adjoint: step over its records and jobs
+        uint32_t rl = (uint32_t)__builtin_amdgcn_readfirstlane((int)log_get(JL, lp, 1u, 0u));
+        for (; rl > 0u; --rl) {
+          const uint32_t e2 = log_get_record(JL, lp, (uint32_t)lane);
+          log_skip(JL, lp, (uint32_t)__builtin_amdgcn_readlane((int)e2, 1));
         }
       }
       __syncthreads();

@@ -386,8 +386,10 @@ constexpr uint32_t kPpElementMajor = 256;
 // jobs that passed its culling tests, so that the adjoint runs only the
 // exact tests (the decisions are the same on both sides: the same tests on
 // the same values).  Each wavefront writes one stream of 16-bit entries:
-// per pass and chunk of kNT p-p elements, the number of the wavefront's jobs
-// in it, then the jobs (element lane << 8 | first pair of the source run).
+// per pass, the number of its chunks of kNT p-p elements that have jobs of
+// the wavefront, then per such chunk a record -- the chunks skipped since
+// the previous record and the number of jobs, two entries in one block --
+// followed by the jobs (element lane << 8 | first pair of the source run).
 // A stream lives in blocks of kLogBlock entries taken from a device counter
 // as it grows; the last two entries of a block hold the index of the
 // stream's next block.  tab[4 bucket + wave] is where a bucket's stream
@@ -398,6 +400,7 @@ constexpr uint32_t kLogBlock = 1u << 14;
 constexpr uint32_t kLogData = kLogBlock - 2;   // entries per block before the link
 constexpr uint32_t kLogNone = 0xFFFFFFFFu;     // no block: the stream is dead
 constexpr uint32_t kLogFresh = 0xFFFFFFFEu;    // no block taken yet
+constexpr uint32_t kLogMaxNear = 1u << 24;     // larger p-p sets are not logged
 
 struct JobLog {
   uint16_t* log;       // blocks * kLogBlock entries (null: no log)
@@ -459,6 +462,26 @@ __device__ inline size_t log_put(const JobLog& J, LogPos& p, uint32_t cnt, bool 
   return first;
 }
 
+// Reserves two entries of one block (a record, written later; writer and
+// reader skip the last data entry of a block when only it is left): the
+// index in the log of the first, or ~0 when the stream is dead.
+__device__ inline size_t log_record(const JobLog& J, LogPos& p) {
+  if (!log_ready(J, p)) return ~(size_t)0;
+  if (p.pos + 2 > kLogData) {
+    const uint32_t nb = log_take_block(J);
+    if ((threadIdx.x & 63) == 0) {
+      J.log[(size_t)p.blk * kLogBlock + kLogData] = (uint16_t)(nb & 0xFFFFu);
+      J.log[(size_t)p.blk * kLogBlock + kLogData + 1] = (uint16_t)(nb >> 16);
+    }
+    p.blk = nb;
+    p.pos = 0;
+    if (nb == kLogNone) return ~(size_t)0;
+  }
+  const size_t first = (size_t)p.blk * kLogBlock + p.pos;
+  p.pos += 2;
+  return first;
+}
+
 // The stream's next block after p.blk (the link the writer left), kept in
 // range.
 __device__ inline uint32_t log_link(const JobLog& J, uint32_t blk) {
@@ -482,6 +505,18 @@ __device__ inline uint32_t log_get(const JobLog& J, LogPos& p, uint32_t cnt, uin
   } else {
     p.pos += cnt;
   }
+  return v;
+}
+
+// Reads a record (see log_record): lane 0 gets its first entry, lane 1 its
+// second.
+__device__ inline uint32_t log_get_record(const JobLog& J, LogPos& p, uint32_t k) {
+  if (p.pos + 2 > kLogData) {
+    p.blk = log_link(J, p.blk);
+    p.pos = 0;
+  }
+  const uint32_t v = k < 2u ? J.log[(size_t)p.blk * kLogBlock + p.pos + k] : 0u;
+  p.pos += 2;
   return v;
 }
 
