@@ -604,7 +604,6 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
   __shared__ double pd_r2[kNT], pd_inv2[kNT];
   __shared__ uint32_t pd_j[kNT];
   __shared__ float pd_jr[kNT][3], pd_jinv[kNT], pd_jlim[kNT], pd_k2[kNT], pd_m2[kNT];
-  __shared__ uint8_t pd_valid[kNT];
   __shared__ float tacc[kNT][NB];
   __shared__ uint8_t nlist[kNT / 64][64];
   __shared__ float egrp[kNT / 64][4][5];   // per wavefront: element spheres of its quarters
@@ -694,7 +693,9 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
       pd_xj[t][0] = (float)xj0;   // exact: the positions are FP32
       pd_xj[t][1] = (float)xj1;
       pd_xj[t][2] = (float)xj2;
-      pd_r2[t] = rij2;
+      // a pair without a path (past the pairs, or the receiver itself) gets
+      // a negative squared length, which fails the exact test
+      pd_r2[t] = (ok && rij2 > 0.0) ? rij2 : -1.0;
       pd_inv2[t] = inv2;
       pd_j[t] = j;
       if (em) {
@@ -709,7 +710,6 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
         // the run, LDS atomics adding into tacc.  Both tests are supersets
         // of the exact test's passes
         run_tab_entry(jr, reach, pd_jr, pd_jinv, pd_jlim, pd_k2, pd_m2, t);
-        pd_valid[t] = (ok && rij2 > 0.0) ? 1u : 0u;
         const RunTab RT{pd_jr, pd_jinv, pd_jlim, pd_k2, pd_m2};
         const float Rm = reach * (1.0f + 1e-5f);
         __syncthreads();
@@ -761,7 +761,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
               uu = fmin(1.0, fmax(0.0, uu));
               const double g0 = w0 - uu * pe0, g1 = w1 - uu * pe1, g2 = w2 - uu * pe2;
               const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-              if ((pd_valid[q] != 0) & (ff < pd_r2[q]) & (b2 < vh2) & (vl != rq.slot) &
+              if ((ff < pd_r2[q]) & (b2 < vh2) & (vl != rq.slot) &
                   (vl != qj)) {
                 ++hits;
                 const float bb = sqrtf((float)b2);

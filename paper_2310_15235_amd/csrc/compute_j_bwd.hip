@@ -135,7 +135,6 @@ template <int NB> struct PairTile {
   double rij2[kNT], inv2[kNT];
   float gt[kNT][NB];
   uint32_t j[kNT];
-  uint8_t i[kNT], valid[kNT];
   // the source of each pair relative to the bucket centre and its run's
   // test values (RunTab): every receiver's segment to the source lies within
   // the round cone of the receivers' reach around the centre's segment
@@ -270,7 +269,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
       PT.xj[t][0] = (float)xj0;   // exact: the positions are FP32
       PT.xj[t][1] = (float)xj1;
       PT.xj[t][2] = (float)xj2;
-      PT.rij2[t] = rij2;
+      PT.rij2[t] = valid ? rij2 : -1.0;   // no adjoint or no path: fails the exact test
       PT.inv2[t] = rij2 > 0.0 ? 1.0 / rij2 : 0.0;
       {
         const float js[3] = {(float)(xj0 - c[0]), (float)(xj1 - c[1]), (float)(xj2 - c[2])};
@@ -279,8 +278,6 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
 #pragma unroll
       for (int b = 0; b < NB; ++b) PT.gt[t][b] = gt[b];
       PT.j[t] = j;
-      PT.i[t] = (uint8_t)i;
-      PT.valid[t] = valid ? 1u : 0u;
       __syncthreads();
       if (__syncthreads_or(valid)) {
         const int qend = (int)min((uint32_t)stride, P - pb);   // pairs of this pass
@@ -384,7 +381,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
                 uu = fmin(1.0, fmax(0.0, uu));
                 const double g0 = w0 - uu * e0q, g1 = w1 - uu * e1q, g2 = w2 - uu * e2q;
                 const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
-                if ((PT.valid[q] != 0) & (ff < PT.rij2[q]) & (b2 < vh2) & (vl != rq.slot) &
+                if ((ff < PT.rij2[q]) & (b2 < vh2) & (vl != rq.slot) &
                     (vl != qj)) {
                   const float bb = sqrtf((float)b2);
                   const float sg = vsig * (1.0f - bb * viv);
