@@ -747,11 +747,12 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src(const DevTree* __restrict__ T
             const uint32_t qj = pd_j[q0];
             const double f0 = vx - qx0, f1 = vy - qx1, f2 = vz - qx2;
             const double ff = f0 * f0 + f1 * f1 + f2 * f2;
-            // two receivers per step, every condition evaluated: their LDS
+            // four receivers per step, every condition evaluated: their LDS
             // reads issue together instead of one wait per condition
-            // (forward p-p sources 582 -> 568 ms on the batched workload;
-            // unrolled fully, the spills cost more than the waits)
-#pragma unroll 2
+            // (forward p-p sources 582 -> 568 ms at two per step on the
+            // batched workload, 512 -> 505 ms from two to four; unrolled
+            // fully, the spills cost more than the waits)
+#pragma unroll 4
             for (int k = 0; k < nrecv; ++k) {
               const int q = q0 + k;
               const RecvInfo& rq = recv[k];
