@@ -624,6 +624,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
           for (int s0 = 0; s0 < kn; s0 += 64) {
             uint64_t cand = 0ull;
             for (int kq = max(lo, s0); kq < min(hi, s0 + 64); ++kq) {
+#pragma clang fp contract(fast)   // FP32 test with margins: fused products are fine
               const float pf = rnf[kq][0] * df[0] + rnf[kq][1] * df[1] + rnf[kq][2] * df[2];
               if (pf > neg && pf * pf >= lim) cand |= 1ull << (kq - s0);
             }

@@ -567,6 +567,7 @@ __device__ inline void run_tab_entry(const float s[3], float reach, float (*jr)[
 // relative plus tol for FP32 rounding.
 __device__ inline bool round_cone(const float p[3], const float s[3], float jinv, float k2, float m2,
                                   float R, float A, float tol) {
+#pragma clang fp contract(fast)   // FP32 culling with margins: fused products are fine
   const float Ap = A * (1.0f + 1e-4f) + tol;
   const float pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
   const float f0 = p[0] - s[0], f1 = p[1] - s[1], f2 = p[2] - s[2];
@@ -645,6 +646,7 @@ __device__ inline void elem_group(const float pr[3], float hrad, bool has, float
 // sides.  Wave-uniform mask.
 __device__ inline uint64_t group_runs(const float (*G)[5], const RunTab& RT, float R, int k0,
                                       int nruns, int nrecv) {
+#pragma clang fp contract(fast)   // FP32 culling with margins: fused products are fine
   const int lane = (int)(threadIdx.x & 63);
   const float* Gq = G[lane / kElemGroup];
   const int k = k0 + (lane & (kElemGroup - 1));
@@ -689,6 +691,7 @@ __device__ inline int take_quarter_pair(uint64_t* gm) {
 // on any of the run's pairs.  A NaN hrad (a lane without an element) fails.
 __device__ inline bool elem_run_test(const float pr[3], float hrad, const RunTab& RT, float R,
                                      int q) {
+#pragma clang fp contract(fast)   // FP32 culling with margins: fused products are fine
   const float s0 = RT.jr[q][0], s1 = RT.jr[q][1], s2 = RT.jr[q][2];
   const float f0 = pr[0] - s0, f1 = pr[1] - s1, f2 = pr[2] - s2;
   float tt = (pr[0] * s0 + pr[1] * s1 + pr[2] * s2) * RT.jinv[q];
@@ -705,6 +708,7 @@ __device__ inline bool elem_run_test(const float pr[3], float hrad, const RunTab
 // between the per-element test and the exact tests.
 __device__ inline bool elem_run_cone(const float pr[3], float hrad, const RunTab& RT, float R,
                                      int q) {
+#pragma clang fp contract(fast)   // FP32 culling with margins: fused products are fine
   const float s[3] = {RT.jr[q][0], RT.jr[q][1], RT.jr[q][2]};
   const float tol = 1e-5f * (fabsf(pr[0]) + fabsf(pr[1]) + fabsf(pr[2]) + fabsf(s[0]) +
                              fabsf(s[1]) + fabsf(s[2]));
