@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kNT, 4) k_pp_src_bwd(const DevTree* __restrict
                 const double b2 = g0 * g0 + g1 * g1 + g2 * g2;
                 if ((ff < PT.rij2[q]) & (b2 < vh2) & (vl != rq.slot) &
                     (vl != qj)) {
-                  const float bb = sqrtf((float)b2);
+                  const float bb = __builtin_amdgcn_sqrtf((float)b2);
                   const float sg = vsig * (1.0f - bb * viv);
                   const float dsg = vsig * viv * (3.0f * bb * viv - 2.0f);
                   float gqk = 0.0f;
@@ -638,7 +638,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
               const double proj = d0 * rn[kq][0] + d1 * rn[kq][1] + d2 * rn[kq][2];
               const double b2 = dd - proj * proj;
               if (!(proj > 0.0 && b2 < h2)) continue;
-              const float bb = sqrtf((float)fmax(b2, 0.0));
+              const float bb = __builtin_amdgcn_sqrtf((float)fmax(b2, 0.0));
               const float sg = sig * (1.0f - bb * iv);
               const float dsg = sig * iv * (3.0f * bb * iv - 2.0f);
               float gq = 0.0f;
