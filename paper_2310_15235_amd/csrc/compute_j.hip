@@ -515,8 +515,10 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
           }
           if (cand == 0ull) continue;
           if (!loaded) {
-            sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-            iv = (float)(1.0 / hl);
+            // column density scale 3m/(pi h^2) and 1/h in FP32 (values,
+            // not decisions; no FP64 divisions in this VALU-bound loop)
+            iv = __builtin_amdgcn_rcpf((float)hl);
+            sig = (float)(3.0 / kPi) * T.m[l] * iv * iv;
 #pragma unroll
             for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];
             loaded = true;

@@ -607,8 +607,10 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
           const float ddf = (float)dd;
           const float lim = (float)(dd - h2) - 1e-5f * ddf - 1e-30f;
           const float neg = -1e-5f * sqrtf(ddf);
-          const float sig = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-          const float iv = (float)(1.0 / hl);
+          // column density scale 3m/(pi h^2) and 1/h in FP32 (values, not
+          // decisions; no FP64 divisions in this VALU-bound loop)
+          const float iv = __builtin_amdgcn_rcpf((float)hl);
+          const float sig = (float)(3.0 / kPi) * T.m[l] * iv * iv;
           float kap[NB];
 #pragma unroll
           for (int b = 0; b < NB; ++b) kap[b] = T.kappa[(int64_t)b * n + l];

@@ -755,8 +755,9 @@ __device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint3
     S.y[t] = (double)T.y[l];
     S.z[t] = (double)T.z[l];
     S.h2[t] = hl * hl;
-    S.sig[t] = (float)(3.0 * (double)T.m[l] / (kPi * hl * hl));
-    S.invh[t] = (float)(1.0 / hl);
+    const float iv = __builtin_amdgcn_rcpf((float)hl);   // values, not decisions: FP32
+    S.invh[t] = iv;
+    S.sig[t] = (float)(3.0 / kPi) * T.m[l] * iv * iv;
 #pragma unroll
     for (int b = 0; b < NB; ++b) S.kap[t][b] = T.kappa[(int64_t)b * T.n + l];
     S.slot[t] = l;
