@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays(const DevTree* __restrict__ TT,
         const float df[3] = {(float)d0, (float)d1, (float)d2};
         const float ddf = (float)dd;
         const float lim = (float)(dd - h2) - 1e-5f * ddf - 1e-30f;
-        const float neg = -1e-5f * sqrtf(ddf);
+        const float neg = -1e-5f * cull_sqrt(ddf);
         int ka, kb;
         ray_ring_range(T.nside, d0, d1, d2, dd, h2, &ka, &kb);
         const int lo = max(ka - k0, 0), hi = min(kb - k0, kn);

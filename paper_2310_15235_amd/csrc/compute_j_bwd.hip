@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(kNT) k_pp_rays_bwd(const DevTree* __restrict__
           const float df[3] = {(float)d0, (float)d1, (float)d2};
           const float ddf = (float)dd;
           const float lim = (float)(dd - h2) - 1e-5f * ddf - 1e-30f;
-          const float neg = -1e-5f * sqrtf(ddf);
+          const float neg = -1e-5f * cull_sqrt(ddf);
           // column density scale 3m/(pi h^2) and 1/h in FP32 (values, not
           // decisions; no FP64 divisions in this VALU-bound loop)
           const float iv = __builtin_amdgcn_rcpf((float)hl);

@@ -149,6 +149,11 @@ __device__ inline uint32_t wave_excl_bits(uint32_t v, uint32_t* total) {
   return e;
 }
 
+// Square root for the conservative FP32 culling tests: the hardware
+// instruction (within about an ulp), far inside their margins; the correctly
+// rounded sqrtf expands to a dozen instructions.
+__device__ inline float cull_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 constexpr int kLeafBatch = 8;   // leaf elements loaded together by one lane
 static_assert(kLeafBatch <= 16, "a run keeps 16 member bits of each kind");
 constexpr int kLeafBatchBits = 4;   // bits of a count in [0, kLeafBatch]
@@ -549,7 +554,7 @@ __device__ inline void run_tab_entry(const float s[3], float reach, float (*jr)[
   jr[t][1] = s[1];
   jr[t][2] = s[2];
   jinv[t] = L2 > 0.0f ? 1.0f / L2 : 0.0f;
-  lim[t] = (sqrtf(L2) + reach) * (1.0f + 1e-5f);
+  lim[t] = (cull_sqrt(L2) + reach) * (1.0f + 1e-5f);
   k2[t] = L2 > R2 ? (L2 - R2) / L2 : 0.0f;
   m2[t] = L2 > R2 ? R2 / (L2 * (L2 - R2)) : -1.0f;
 }
@@ -622,7 +627,7 @@ __device__ inline void elem_group(const float pr[3], float hrad, bool has, float
   for (int a = 0; a < 3; ++a)
     g[a] = 0.5f * (quarter_fmin(has ? pr[a] : INFINITY) + quarter_fmax(has ? pr[a] : -INFINITY));
   const float d0 = pr[0] - g[0], d1 = pr[1] - g[1], d2 = pr[2] - g[2];
-  const float dl = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+  const float dl = cull_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   const float rp = quarter_fmax(has ? dl : -1.0f);
   const float rr = quarter_fmax(has ? dl + hrad : -1.0f);
   const int lane = (int)(threadIdx.x & 63);
@@ -768,7 +773,7 @@ __device__ inline void stage_near(NearTile<NB>& S, const DevTree& T, const uint3
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     const int u1 = min((int)cl, (t + 1) * kHalf);
     for (int u = t * kHalf; u < u1; ++u) {
-      const float h = sqrtf((float)S.h2[u]);
+      const float h = cull_sqrt((float)S.h2[u]);
       const float p[3] = {(float)(S.x[u] - c[0]), (float)(S.y[u] - c[1]), (float)(S.z[u] - c[2])};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -894,8 +899,8 @@ __device__ inline uint32_t block_compact(bool pred, uint32_t* wcnt, uint32_t* to
 // z-range, widened by 1e-4 in sin and z and 1e-3 of a ring for FP32
 // rounding.  The receiver inside the element (h near |d|): every ray.
 __device__ inline float ring_of_z(int N, float z) {
-  if (z > 2.0f / 3.0f) return (float)N * sqrtf(3.0f * fmaxf(1.0f - z, 0.0f));
-  if (z < -2.0f / 3.0f) return 4.0f * N - (float)N * sqrtf(3.0f * fmaxf(1.0f + z, 0.0f));
+  if (z > 2.0f / 3.0f) return (float)N * cull_sqrt(3.0f * fmaxf(1.0f - z, 0.0f));
+  if (z < -2.0f / 3.0f) return 4.0f * N - (float)N * cull_sqrt(3.0f * fmaxf(1.0f + z, 0.0f));
   return 2.0f * N - 1.5f * N * z;
 }
 __device__ inline int ring_start(int N, int i) {
@@ -914,9 +919,9 @@ __device__ inline void ray_ring_range(int N, double d0, double d1, double d2, do
     return;
   }
   const float z = (float)d2 * rsqrtf(ddf);
-  const float sa = fminf(sqrtf(s2) * (1.0f + 1e-4f) + 1e-4f, 1.0f);
-  const float ca = sqrtf(fmaxf(1.0f - sa * sa, 0.0f));
-  const float st = sqrtf(fmaxf(1.0f - z * z, 0.0f));
+  const float sa = fminf(cull_sqrt(s2) * (1.0f + 1e-4f) + 1e-4f, 1.0f);
+  const float ca = cull_sqrt(fmaxf(1.0f - sa * sa, 0.0f));
+  const float st = cull_sqrt(fmaxf(1.0f - z * z, 0.0f));
   const float zhi = (z >= ca) ? 1.0f : fminf(z * ca + st * sa + 1e-4f, 1.0f);
   const float zlo = (-z >= ca) ? -1.0f : fmaxf(z * ca - st * sa - 1e-4f, -1.0f);
   const int i0 = max(1, (int)ceilf(ring_of_z(N, zhi) - 1e-3f));
